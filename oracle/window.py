@@ -1,0 +1,168 @@
+"""FP64 window forward and reverse of the short-horizon actor loss (oracle; tests only).
+
+Forward, per frame t (Sec. 3.3; App. A.3):
+    o_t = obs(s_t);  a_t = tanh(MLP_theta(o_t))  (deterministic policy; or given actions)
+    r_t = R(s_t, a_t)
+    S substeps of the simulator with a_t held;  s_{t+1} = (q, qd[, a_t])
+Loss (Sec. 3.3, Eq. "policy_loss"):
+    L = -1/(N h) * sum_i [ sum_t gamma^t r_t + gamma^h V(o_h) ]
+Reverse (App. A.1): dL/da_t is the adjoint of the action node (the partial of the
+appendix's action equation, including the path through the last-action entry of
+s_{t+1}), dL/ds_0 is the total derivative through the closed-loop policy, and
+dL/dtheta sums (dL/da_t)(d pi / d theta) over envs and frames; all three are
+obtained here by reverse-mode differentiation of the forward.
+"""
+import numpy as np
+import torch
+
+from .dynamics import F64, OracleModel, quat_to_rot, substep
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x), dtype=F64)
+
+
+def mlp_forward(layers, x):
+    """ELU hidden layers, linear output (App. A.2 network description, LayerNorm off)."""
+    h = x
+    n = len(layers)
+    for i, (W, b) in enumerate(layers):
+        h = h @ W.T + b
+        if i < n - 1:
+            h = torch.where(h > 0, h, torch.expm1(torch.clamp(h, max=0.0)))
+    return h
+
+
+def obs_fn(m, s):
+    """Observation vector of the task (App. A.3 observation tables)."""
+    task = m.md["task"]
+    nq, nv = m.nq, m.nv
+    q, qd = s[:, :nq], s[:, nq:nq + nv]
+    if task == "cartpole":
+        x, th, xd, thd = q[:, 0], q[:, 1], qd[:, 0], qd[:, 1]
+        return torch.stack([x, xd, torch.sin(th), torch.cos(th), thd], 1)
+    R = quat_to_rot(q[:, 3:7])
+    up = R[:, 2, 2]
+    heading = R[:, 0, 0]
+    parts = [q[:, 2:3], q[:, 3:7], qd[:, 0:3], qd[:, 3:6], q[:, 7:], qd[:, 6:],
+             up[:, None], heading[:, None]]
+    if m.md["has_last_action"]:
+        parts.append(s[:, nq + nv:])
+    return torch.cat(parts, 1)
+
+
+def reward_fn(m, s, a):
+    """Single-step reward R(s_t, a_t) (App. A.3 reward definitions)."""
+    task = m.md["task"]
+    nq, nv = m.nq, m.nv
+    q, qd = s[:, :nq], s[:, nq:nq + nv]
+    if task == "cartpole":
+        th = torch.atan2(torch.sin(q[:, 1]), torch.cos(q[:, 1]))
+        return -th ** 2 - 0.1 * qd[:, 1] ** 2 - 0.05 * q[:, 0] ** 2 - 0.1 * qd[:, 0] ** 2
+    R = quat_to_rot(q[:, 3:7])
+    up, heading, hgt, vx = R[:, 2, 2], R[:, 0, 0], q[:, 2], qd[:, 0]
+    if task == "ant":
+        return vx + 0.1 * up + heading + (hgt - 0.27)
+    if task == "humanoid":
+        dh = torch.clamp(hgt - 0.84, -1.0, 0.1)
+        rh = torch.where(dh < 0, -200.0 * dh * dh, 10.0 * dh)
+        return vx + 0.1 * up + heading + rh - 0.002 * (a * a).sum(1)
+    raise ValueError(task)
+
+
+def _layers(params):
+    return [(_t(W), _t(b)) for (W, b) in params]
+
+
+def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
+                  keep_graph=False, layers=None, action_offset=None):
+    """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
+
+    s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
+    n_total: the N of the 1/(N h) loss scale (defaults to B).
+    action_offset: optional [h, B, na] added to each action (used by finite-difference
+    checks of dL/da_t).
+    """
+    m = md if isinstance(md, OracleModel) else OracleModel(md)
+    s = s0 if torch.is_tensor(s0) else _t(s0)
+    B = s.shape[0]
+    N = B if n_total is None else n_total
+    if layers is None:
+        layers = (_layers(actor) if actor is not None else None,
+                  _layers(critic) if critic is not None else None)
+    act_l, crit_l = layers
+    nq, nv = m.nq, m.nv
+    dt = m.dt / m.substeps
+    states, obs, acts, rews = [s], [], [], []
+    for t in range(h):
+        o = obs_fn(m, s)
+        if actions is None:
+            a = torch.tanh(mlp_forward(act_l, o))
+        else:
+            a = actions[t] if torch.is_tensor(actions) else _t(actions[t])
+        if action_offset is not None:
+            a = a + _t(action_offset[t])
+        if keep_graph and not a.requires_grad:
+            a.requires_grad_(True)
+        r = reward_fn(m, s, a)
+        q, qd = s[:, :nq], s[:, nq:nq + nv]
+        for _ in range(m.substeps):
+            q, qd = substep(m, q, qd, a, dt)
+        s = torch.cat([q, qd, a], 1) if m.md["has_last_action"] else torch.cat([q, qd], 1)
+        states.append(s)
+        obs.append(o)
+        acts.append(a)
+        rews.append(r)
+    o_h = obs_fn(m, s)
+    obs.append(o_h)
+    value = mlp_forward(crit_l, o_h)[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
+    disc = sum(gamma ** t * rews[t] for t in range(h))
+    loss = -(disc + gamma ** h * value).sum() / (N * h)
+    return dict(states=states, obs=obs, actions=acts, rewards=rews, value=value, loss=loss,
+                layers=layers)
+
+
+def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
+                        n_total=None, want_theta=False):
+    """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
+
+    Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
+    value [B], loss, dL/da [h,B,na], dL/ds0 [B,n_s] and, if asked, dL/dtheta as a
+    list of (dW, db) per actor layer.
+    """
+    s0t = _t(s0).clone().requires_grad_(True)
+    layers = None
+    if actor is not None:
+        layers = ([(W.clone().requires_grad_(want_theta), b.clone().requires_grad_(want_theta))
+                   for (W, b) in _layers(actor)],
+                  _layers(critic) if critic is not None else None)
+    act_in = None
+    if actions is not None:
+        act_in = [_t(actions[t]).clone().requires_grad_(True) for t in range(h)]
+    out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
+                        layers=layers)
+    wrt = [s0t] + list(out["actions"])
+    theta = []
+    if want_theta and actor is not None:
+        for (W, b) in layers[0]:
+            theta += [W, b]
+    g = torch.autograd.grad(out["loss"], wrt + theta, allow_unused=True)
+    gs0 = g[0]
+    ga = torch.stack([x if x is not None else torch.zeros_like(out["actions"][0])
+                      for x in g[1:1 + h]])
+    res = dict(
+        s_h=out["states"][-1].detach().numpy(),
+        states=torch.stack(out["states"]).detach().numpy(),
+        obs=torch.stack(out["obs"]).detach().numpy(),
+        actions=torch.stack(out["actions"]).detach().numpy(),
+        rewards=torch.stack(out["rewards"]).detach().numpy(),
+        value=out["value"].detach().numpy(),
+        loss=float(out["loss"].detach()),
+        dL_da=ga.detach().numpy(),
+        dL_ds0=gs0.detach().numpy(),
+    )
+    if want_theta and actor is not None:
+        gt = g[1 + h:]
+        res["dL_dtheta"] = [(gt[2 * i].numpy(), gt[2 * i + 1].numpy())
+                            for i in range(len(gt) // 2)]
+    return res

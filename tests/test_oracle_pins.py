@@ -1,0 +1,546 @@
+"""Pins of the FP64 oracle against closed forms, invariants and brute force.
+
+Each test checks the oracle against something it does not itself define: the
+closed-form semi-implicit Euler solution, textbook pendulum frequencies, energy and
+momentum behaviour of a symplectic integrator, the mass matrix and bias rebuilt
+from finite differences of the kinematics and of the Lagrangian, static contact
+equilibria, Coulomb sliding, the exact linearisation of the discrete map, and
+central finite differences of the window loss.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import dynamics as D
+from oracle.dynamics import F64, OracleModel
+from oracle.window import mlp_forward, obs_fn, oracle_window, oracle_window_grads, reward_fn
+
+torch.set_num_threads(4)
+
+
+def T(x):
+    return torch.as_tensor(np.asarray(x), dtype=F64)
+
+
+def run_substeps(m, q, qd, a, dt, n):
+    for _ in range(n):
+        q, qd = D.substep(m, q, qd, a, dt)
+    return q, qd
+
+
+# ------------------------------------------------------------------ integrator, gravity
+
+def test_free_fall_closed_form():
+    """Semi-implicit Euler free fall: z_n = z0 + n dt v0 - g dt^2 n (n+1) / 2."""
+    m = OracleModel(wl.free_body())
+    q = T([[0.0, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0]])
+    qd = torch.zeros(1, 6, dtype=F64)
+    dt, n = 1.0 / 240.0, 128
+    q, qd = run_substeps(m, q, qd, torch.zeros(1, 0, dtype=F64), dt, n)
+    z_ref = 1.0 - 9.81 * dt * dt * n * (n + 1) / 2.0
+    assert abs(z_ref - (-0.40610)) < 1e-5
+    assert abs(float(q[0, 2]) - z_ref) <= 1e-12 * abs(z_ref)
+    assert abs(float(qd[0, 2]) + 9.81 * dt * n) < 1e-12
+
+
+def _period(theta, dt):
+    """Mean period from upward zero crossings with linear interpolation."""
+    th = np.asarray(theta)
+    idx = np.where((th[:-1] < 0) & (th[1:] >= 0))[0]
+    tc = (idx + (-th[idx]) / (th[idx + 1] - th[idx])) * dt
+    return (tc[-1] - tc[0]) / (len(tc) - 1), len(tc)
+
+
+def test_pendulum_period_locked_cart():
+    """Rod on a hinge: T = 2 pi sqrt(2L / 3g); discrete T_d = 2 pi dt / acos(1 - w^2 dt^2 / 2)."""
+    m = OracleModel(wl.pendulum(mass=0.1, length=1.0))
+    dt = 1.0 / 240.0
+    w2 = 3.0 * 9.81 / 2.0
+    assert abs(2 * np.pi / np.sqrt(w2) - 1.637947) < 1e-6
+    Td = 2 * np.pi * dt / np.arccos(1 - w2 * dt * dt / 2)
+    assert abs(Td - 1.637929) < 1e-6
+    q, qd = T([[1e-4]]), T([[0.0]])
+    a = torch.zeros(1, 1, dtype=F64)
+    th = []
+    for _ in range(int(12 * 1.64 / dt)):
+        q, qd = D.substep(m, q, qd, a, dt)
+        th.append(float(q[0, 0]))
+    Tm, nc = _period(th, dt)
+    assert nc >= 10
+    assert abs(Tm - Td) / Td < 1e-6
+
+
+def test_pendulum_period_free_cart():
+    """CartPole hanging (angle pi): w^2 = m g l / (I_c + m l^2 - m^2 l^2 / (M + m))."""
+    m = OracleModel(wl.cartpole())
+    dt = 1.0 / 240.0
+    M_, mp, l, Ic = 1.0, 0.1, 0.5, 0.1 / 12
+    w2 = mp * 9.81 * l / (Ic + mp * l * l - mp * mp * l * l / (M_ + mp))
+    assert abs(2 * np.pi / np.sqrt(w2) - 1.581122) < 1e-6
+    Td = 2 * np.pi * dt / np.arccos(1 - w2 * dt * dt / 2)
+    assert abs(Td - 1.581104) < 1e-6
+    q, qd = T([[0.0, np.pi + 1e-4]]), T([[0.0, 0.0]])
+    a = torch.zeros(1, 1, dtype=F64)
+    th = []
+    for _ in range(int(12 * 1.6 / dt)):
+        q, qd = D.substep(m, q, qd, a, dt)
+        th.append(float(q[0, 1]) - np.pi)
+    Tm, nc = _period(th, dt)
+    assert nc >= 10
+    assert abs(Tm - Td) / Td < 1e-6
+
+
+# ------------------------------------------------------------------ energy, momentum
+
+def _energy_error(md, q0, qd0, dt, t_end):
+    m = OracleModel(md)
+    q, qd = T(q0), T(qd0)
+    a = torch.zeros(q.shape[0], m.na, dtype=F64)
+    e0 = float(D.kinetic_energy(m, q, qd)[0] + D.potential_energy(m, q))
+    err = 0.0
+    for _ in range(int(round(t_end / dt))):
+        q, qd = D.substep(m, q, qd, a, dt)
+        e = float(D.kinetic_energy(m, q, qd)[0] + D.potential_energy(m, q))
+        err = max(err, abs(e - e0) / abs(e0))
+    return err
+
+
+def test_energy_error_is_first_order_cartpole():
+    md = wl.cartpole()
+    q0, qd0 = [[0.0, 2.0]], [[0.3, -0.5]]
+    e1 = _energy_error(md, q0, qd0, 1.0 / 120, 5.0)
+    e2 = _energy_error(md, q0, qd0, 1.0 / 240, 5.0)
+    assert e1 < 0.1
+    assert 1.6 < e1 / e2 < 2.4
+
+
+def test_energy_error_is_first_order_floating_chain_zero_g():
+    md = wl.chain(n=4, free_root=True, gravity=0.0)
+    m = OracleModel(md)
+    rng = np.random.default_rng(3)
+    q0 = np.zeros((1, m.nq))
+    q0[0, 3] = 1.0
+    q0[0, 7:] = rng.normal(size=m.nq - 7) * 0.3
+    qd0 = rng.normal(size=(1, m.nv))
+    e1 = _energy_error(md, q0, qd0, 1.0 / 400, 1.0)
+    e2 = _energy_error(md, q0, qd0, 1.0 / 800, 1.0)
+    assert e1 < 0.05
+    assert 1.6 < e1 / e2 < 2.4
+
+
+def _momentum(m, q, qd):
+    """Total spatial momentum about the world origin from body COM velocities (FK finite differences free)."""
+    T_ = D.dynamics_terms(m, q, qd)
+    h = torch.zeros(q.shape[0], 6, dtype=F64)
+    for i, j in enumerate(T_["bodies"]):
+        h = h + (T_["I6"][:, i] @ T_["V"][j][..., None])[..., 0]
+    return h
+
+
+def test_momentum_drift_in_flight_is_first_order():
+    md = wl.chain(n=4, free_root=True, gravity=0.0)
+    m = OracleModel(md)
+    rng = np.random.default_rng(5)
+    q0 = np.zeros((1, m.nq))
+    q0[0, 3] = 1.0
+    q0[0, 7:] = rng.normal(size=m.nq - 7) * 0.3
+    qd0 = rng.normal(size=(1, m.nv))
+    a = T(rng.normal(size=(1, m.na)))
+
+    def drift(dt, t_end=0.5):
+        q, qd = T(q0), T(qd0)
+        h0 = _momentum(m, q, qd)
+        worst = 0.0
+        for _ in range(int(round(t_end / dt))):
+            q, qd = D.substep(m, q, qd, a, dt)
+            worst = max(worst, float((_momentum(m, q, qd) - h0).abs().max()))
+        return worst, float(h0.abs().max())
+
+    d1, scale = drift(1.0 / 400)
+    d2, _ = drift(1.0 / 800)
+    assert d1 / scale < 0.3
+    assert 1.6 < d1 / d2 < 2.4
+
+
+# ------------------------------------------------------------------ M and bias in other forms
+
+def _fd_point_and_rotation(m, q, dq, eps):
+    """Central differences of every body's COM and rotation along the velocity dq."""
+    def advance(qv, s):
+        out = qv.clone()
+        for j in range(m.J):
+            a, v = m.qadr[j], m.vadr[j]
+            if m.jtype[j] == D.FREE:
+                out[:, a:a + 3] = qv[:, a:a + 3] + s * dq[:, v:v + 3]
+                out[:, a + 3:a + 7] = D.quat_exp_update(qv[:, a + 3:a + 7], dq[:, v + 3:v + 6], s)
+            else:
+                out[:, a] = qv[:, a] + s * dq[:, v]
+        return out
+    Rp, pp = D.forward_kinematics(m, advance(q, eps))
+    Rm, pm = D.forward_kinematics(m, advance(q, -eps))
+    R0, _ = D.forward_kinematics(m, q)
+    res = {}
+    for j in m.bodies:
+        cp = pp[j] + Rp[j] @ m.com[j]
+        cm = pm[j] + Rm[j] @ m.com[j]
+        vc = (cp - cm) / (2 * eps)
+        W = (Rp[j] - Rm[j]) / (2 * eps) @ R0[j].transpose(-1, -2)
+        w = torch.stack([W[:, 2, 1], W[:, 0, 2], W[:, 1, 0]], -1)
+        res[j] = (vc, w, R0[j])
+    return res
+
+
+@pytest.mark.parametrize("name", ["chain_free", "chain_fixed", "ant", "humanoid"])
+def test_mass_matrix_from_kinematics(name):
+    md = {"chain_free": lambda: wl.chain(4, True), "chain_fixed": lambda: wl.chain(4, False),
+          "ant": wl.ant, "humanoid": wl.humanoid}[name]()
+    m = OracleModel(md)
+    rng = np.random.default_rng(11)
+    s0 = wl.initial_states(md, 1, seed=2) if md["task"] != "none" else None
+    q = T(s0[:, :m.nq]) if s0 is not None else T(rng.normal(size=(1, m.nq)) * 0.5)
+    if m.jtype[0] == D.FREE:
+        q[:, 3:7] = T(rng.normal(size=(1, 4)))
+        q[:, 3:7] /= q[:, 3:7].norm()
+    T_ = D.dynamics_terms(m, q, torch.zeros(1, m.nv, dtype=F64))
+    M = T_["M"][0]
+    assert torch.allclose(M, M.T, atol=1e-12)
+    assert float(torch.linalg.eigvalsh(M).min()) > 0
+    # M = sum_b m J_c^T J_c + J_w^T I_w J_w with Jacobian columns from FK differences
+    cols = []
+    for k in range(m.nv):
+        e = torch.zeros(1, m.nv, dtype=F64)
+        e[0, k] = 1.0
+        cols.append(_fd_point_and_rotation(m, q, e, 1e-6))
+    Mfd = torch.diag(m.armature).clone()
+    for j in m.bodies:
+        Jc = torch.stack([cols[k][j][0][0] for k in range(m.nv)], 1)
+        Jw = torch.stack([cols[k][j][1][0] for k in range(m.nv)], 1)
+        R0 = cols[0][j][2][0]
+        Iw = R0 @ m.inertia[j] @ R0.T
+        Mfd = Mfd + m.mass[j] * Jc.T @ Jc + Jw.T @ Iw @ Jw
+    assert torch.allclose(M, Mfd, atol=1e-7 * float(M.abs().max()))
+    # kinetic energy identity for a random velocity
+    qd = T(rng.normal(size=(1, m.nv)))
+    ke, _ = D.kinetic_energy(m, q, qd)
+    fd = _fd_point_and_rotation(m, q, qd, 1e-6)
+    ke_fd = 0.5 * float((qd[0] * T(m.armature) * qd[0]).sum())
+    for j in m.bodies:
+        vc, w, R0 = fd[j]
+        Iw = R0[0] @ m.inertia[j] @ R0[0].T
+        ke_fd += 0.5 * float(m.mass[j] * (vc[0] ** 2).sum() + w[0] @ Iw @ w[0])
+    assert abs(float(ke[0]) - ke_fd) < 1e-7 * abs(ke_fd)
+
+
+def test_bias_from_lagrangian_fixed_base():
+    """b = Mdot qd - d/dq (qd^T M qd / 2) + dV/dq, all by central differences."""
+    md = wl.chain(5, free_root=False, seed=13)
+    m = OracleModel(md)
+    rng = np.random.default_rng(4)
+    q = T(rng.normal(size=(1, m.nq)) * 0.7)
+    qd = T(rng.normal(size=(1, m.nv)))
+    b = D.dynamics_terms(m, q, qd)["bias"][0]
+    eps = 1e-5
+
+    def Mof(qq):
+        return D.dynamics_terms(m, qq, torch.zeros_like(qd))["M"][0]
+
+    Mdot_qd = (Mof(q + eps * qd) - Mof(q - eps * qd)) / (2 * eps) @ qd[0]
+    grad_T = torch.zeros(m.nv, dtype=F64)
+    grad_V = torch.zeros(m.nv, dtype=F64)
+    for k in range(m.nv):
+        e = torch.zeros_like(q)
+        e[0, k] = eps
+        grad_T[k] = 0.5 * (qd[0] @ (Mof(q + e) - Mof(q - e)) @ qd[0]) / (2 * eps)
+        grad_V[k] = (D.potential_energy(m, q + e) - D.potential_energy(m, q - e))[0] / (2 * eps)
+    b_lag = Mdot_qd - grad_T + grad_V
+    assert torch.allclose(b, b_lag, atol=1e-7 * float(b_lag.abs().max()) + 1e-9)
+
+
+def test_free_body_com_acceleration_and_euler_equations():
+    """Torque-free body with offset COM: COM accelerates at g; I w' + w x I w = 0."""
+    md = wl.free_body(mass=2.0, inertia=(0.1, 0.2, 0.3))
+    md["com"][0] = np.array([0.1, -0.2, 0.05])
+    m = OracleModel(md)
+    rng = np.random.default_rng(9)
+    qu = rng.normal(size=4)
+    q = T(np.concatenate([[0.3, 0.1, 1.0], qu / np.linalg.norm(qu)])[None])
+    qd = T(rng.normal(size=(1, 6)))
+    T_ = D.dynamics_terms(m, q, qd)
+    qdd = torch.linalg.solve(T_["M"], (-T_["bias"])[..., None])[..., 0][0]
+    R = T_["R"][0][0]
+    c_rel = R @ m.com[0]
+    w, vp = qd[0, 3:], qd[0, :3]
+    ap, alpha = qdd[:3], qdd[3:]
+    a_com = ap + torch.linalg.cross(alpha, c_rel) + torch.linalg.cross(w, torch.linalg.cross(w, c_rel))
+    assert torch.allclose(a_com, T([0, 0, -9.81]), atol=1e-10)
+    Iw = R @ m.inertia[0] @ R.T
+    assert torch.allclose(Iw @ alpha + torch.linalg.cross(w, Iw @ w), torch.zeros(3, dtype=F64),
+                          atol=1e-10)
+
+
+def test_solve_matches_numpy():
+    W = wl.workload("humanoid", 2)
+    m = OracleModel(W["model"])
+    s = T(W["s0"])
+    q, qd = s[:, :m.nq], T(np.random.default_rng(1).normal(size=(2, m.nv)))
+    T_ = D.dynamics_terms(m, q, qd)
+    rhs = np.random.default_rng(2).normal(size=(2, m.nv))
+    L = torch.linalg.cholesky(T_["M"])
+    x = torch.cholesky_solve(T(rhs)[..., None], L)[..., 0].numpy()
+    for i in range(2):
+        x_np = np.linalg.solve(T_["M"][i].numpy(), rhs[i])
+        assert np.allclose(x[i], x_np, rtol=1e-12, atol=1e-12)
+        assert np.allclose(L[i].numpy(), np.linalg.cholesky(T_["M"][i].numpy()), atol=1e-12)
+
+
+# ------------------------------------------------------------------ contact
+
+def test_sphere_rests_at_static_penetration():
+    md = wl.free_body(mass=2.0, inertia=(0.1, 0.1, 0.1), radius=0.1, contact=True,
+                      kn=4e4, kd=1e4, kt=1e3, mu=0.75)
+    m = OracleModel(md)
+    q = T([[0.0, 0.0, 0.1, 1.0, 0.0, 0.0, 0.0]])
+    qd = torch.zeros(1, 6, dtype=F64)
+    q, qd = run_substeps(m, q, qd, torch.zeros(1, 0, dtype=F64), 1.0 / 2000, 20000)
+    d = float(q[0, 2]) - 0.1
+    assert abs(d - (-2.0 * 9.81 / 4e4)) < 1e-5 * 2.0 * 9.81 / 4e4
+
+
+def test_block_normal_forces_sum_to_weight():
+    md = wl.sliding_block(mass=1.5, radius=0.05, kn=4e4, kd=1e4, kt=1e3, mu=0.75)
+    m = OracleModel(md)
+    q = T([[0.0, 0.0, 0.05, 1.0, 0.0, 0.0, 0.0]])
+    qd = torch.zeros(1, 6, dtype=F64)
+    q, qd = run_substeps(m, q, qd, torch.zeros(1, 0, dtype=F64), 1.0 / 2000, 20000)
+    T_ = D.dynamics_terms(m, q, qd)
+    fz = float(T_["contact_f"][0, :, 2].sum())
+    assert abs(fz - 1.5 * 9.81) < 1e-5 * 1.5 * 9.81
+
+
+def test_coulomb_sliding_decelerates_at_mu_g():
+    """All contacts in the Coulomb branch: friction totals mu * sum|f_n| = mu m g."""
+    mass, mu, kn = 1.0, 0.75, 4e4
+    md = wl.sliding_block(mass=mass, radius=0.05, kn=kn, kd=1e4, kt=1e3, mu=mu)
+    m = OracleModel(md)
+    d_eq = -mass * 9.81 / (4 * kn)
+    q = T([[0.0, 0.0, 0.05 + d_eq, 1.0, 0.0, 0.0, 0.0]])
+    qd = T([[1.0, 0.0, 0.0, 0.0, 0.0, 0.0]])
+    dt, n = 1.0 / 4000, 400
+    T_ = D.dynamics_terms(m, q, qd)
+    assert float(T_["contact_f"][0, :, 2].sum()) == pytest.approx(mass * 9.81, rel=1e-9)
+    q, qd = run_substeps(m, q, qd, torch.zeros(1, 0, dtype=F64), dt, n)
+    decel = (1.0 - float(qd[0, 0])) / (n * dt)
+    assert decel == pytest.approx(mu * 9.81, rel=2e-3)
+
+
+def test_viscous_friction_decays_at_kt_over_m():
+    mass, kt = 2.0, 1e3
+    md = wl.free_body(mass=mass, inertia=(100.0, 100.0, 100.0), radius=0.1, contact=True,
+                      kn=4e4, kd=1e4, kt=kt, mu=0.75)
+    m = OracleModel(md)
+    d_eq = -mass * 9.81 / 4e4
+    v0 = 1e-4
+    q = T([[0.0, 0.0, 0.1 + d_eq, 1.0, 0.0, 0.0, 0.0]])
+    qd = T([[v0, 0.0, 0.0, 0.0, 0.0, 0.0]])
+    dt, n = 1e-4, 20
+    T_ = D.dynamics_terms(m, q, qd)
+    assert kt * v0 < 0.75 * abs(float(T_["contact_f"][0, 0, 2]))
+    q, qd = run_substeps(m, q, qd, torch.zeros(1, 0, dtype=F64), dt, n)
+    assert float(qd[0, 0]) / v0 == pytest.approx((1 - kt * dt / mass) ** n, rel=1e-3)
+
+
+def test_contact_force_law_values():
+    """Single sphere: hand-evaluated normal force and both friction branches."""
+    md = wl.free_body(mass=1.0, radius=0.1, contact=True, kn=4e4, kd=1e4, kt=1e3, mu=0.75)
+    m = OracleModel(md)
+    q = T([[0.0, 0.0, 0.099, 1.0, 0.0, 0.0, 0.0]])        # d = -1e-3
+    for vx, branch in ((1e-3, "viscous"), (1.0, "coulomb")):
+        qd = T([[vx, 0.0, -0.2, 0.0, 0.0, 0.0]])
+        f = D.dynamics_terms(m, q, qd)["contact_f"][0, 0]
+        fn = (-4e4 + 1e4 * -0.2) * -1e-3
+        assert float(f[2]) == pytest.approx(fn, rel=1e-12)
+        ft = -1e3 * vx if branch == "viscous" else -0.75 * fn
+        assert float(f[0]) == pytest.approx(ft, rel=1e-12)
+    qd = T([[1.0, 0.0, 0.0, 0.0, 0.0, 0.0]])
+    q_air = T([[0.0, 0.0, 0.2, 1.0, 0.0, 0.0, 0.0]])
+    assert float(D.dynamics_terms(m, q_air, qd)["contact_f"].abs().max()) == 0.0
+
+
+def test_joint_limit_penalty_values():
+    md = wl.ant()
+    m = OracleModel(md)
+    q = torch.zeros(1, m.nq, dtype=F64)
+    q[0, 3] = 1.0
+    j = 2                                             # first knee, limits 30..70 deg
+    q[0, m.qadr[j]] = np.deg2rad(20)
+    tau = D.joint_torques(m, q, torch.zeros(1, m.na, dtype=F64))[0]
+    assert float(tau[m.vadr[j]]) == pytest.approx(1e4 * np.deg2rad(10), rel=1e-12)
+    q[0, m.qadr[j]] = np.deg2rad(80)
+    tau = D.joint_torques(m, q, torch.zeros(1, m.na, dtype=F64))[0]
+    assert float(tau[m.vadr[j]]) == pytest.approx(-1e4 * np.deg2rad(10), rel=1e-12)
+    q[0, m.qadr[j]] = np.deg2rad(50)
+    tau = D.joint_torques(m, q, torch.ones(1, m.na, dtype=F64))[0]
+    assert float(tau[m.vadr[j]]) == pytest.approx(50.0, rel=1e-12)
+
+
+# ------------------------------------------------------------------ rewards, obs, MLP
+
+def test_humanoid_standing_reward_and_obs():
+    W = wl.workload("humanoid", 1)
+    m = OracleModel(W["model"])
+    s = torch.zeros(1, 76, dtype=F64)
+    s[0, 2] = 1.348
+    s[0, 3] = 1.0
+    a = torch.zeros(1, 21, dtype=F64)
+    # v = 0, up = heading = 1, height term 10 * clip(1.348 - 0.84, -1, 0.1) = 1
+    assert float(reward_fn(m, s, a)[0]) == pytest.approx(0.1 + 1.0 + 1.0, abs=1e-14)
+    a[0, :] = 0.5
+    s[0, 2] = 0.74
+    assert float(reward_fn(m, s, a)[0]) == pytest.approx(0.1 + 1.0 - 200 * 0.01 - 0.002 * 21 * 0.25)
+    o = obs_fn(m, s)
+    assert o.shape == (1, 76)
+    assert float(o[0, 53]) == 1.0 and float(o[0, 54]) == 1.0
+
+
+def test_cartpole_reward_wraps_angle():
+    m = OracleModel(wl.cartpole())
+    s = T([[0.5, 2 * np.pi + 0.1, 0.2, -0.3]])
+    r = float(reward_fn(m, s, torch.zeros(1, 1, dtype=F64))[0])
+    assert r == pytest.approx(-0.01 - 0.1 * 0.09 - 0.05 * 0.25 - 0.1 * 0.04, abs=1e-12)
+
+
+def test_mlp_elu_tanh_small_case():
+    W1, b1 = T([[1.0, -2.0], [0.5, 0.5]]), T([0.0, -1.0])
+    W2, b2 = T([[1.0, 1.0]]), T([0.25])
+    y = mlp_forward([(W1, b1), (W2, b2)], T([[1.0, 1.0]]))
+    # hidden: [-1 -> e^-1 - 1, 0 -> 0] ; out = e^-1 - 1 + 0 + 0.25
+    assert float(y[0, 0]) == pytest.approx(np.exp(-1) - 1 + 0.25, abs=1e-15)
+
+
+# ------------------------------------------------------------------ exact linearisation
+
+@pytest.mark.parametrize("upright", [False, True])
+def test_linearisation_is_matrix_power(upright):
+    """At an equilibrium with zero action, d s_n / d s_0 = Phi^n of the linear scheme."""
+    m = OracleModel(wl.pendulum())
+    dt, n = 1.0 / 240, 200
+    w2 = 3.0 * 9.81 / 2.0 * (-1.0 if upright else 1.0)
+    Phi = np.array([[1 - dt * dt * w2, dt], [-dt * w2, 1.0]])
+    th0 = np.pi if upright else 0.0
+
+    def f(x):
+        q, qd = x[:, :1], x[:, 1:]
+        q, qd = run_substeps(m, q, qd, torch.zeros(1, 1, dtype=F64), dt, n)
+        return torch.cat([q, qd], 1)
+
+    J = torch.autograd.functional.jacobian(f, T([[th0, 0.0]]))[0, :, 0, :].numpy()
+    P = np.linalg.matrix_power(Phi, n)
+    assert np.allclose(J, P, rtol=1e-10, atol=1e-10 * np.abs(P).max())
+
+
+def test_linearisation_free_cart_blocks():
+    m = OracleModel(wl.cartpole())
+    dt, n = 1.0 / 240, 100
+    T_ = D.dynamics_terms(m, T([[0.0, np.pi]]), torch.zeros(1, 2, dtype=F64))
+    M = T_["M"][0].numpy()
+    # gravity torque m g l sin(theta) linearises to -m g l (theta - pi): qdd = -M^{-1} K q
+    A = np.linalg.solve(M, np.diag([0.0, 0.1 * 9.81 * 0.5]))
+    I2 = np.eye(2)
+    Phi = np.block([[I2 - dt * dt * A, dt * I2], [-dt * A, I2]])
+
+    def f(x):
+        q, qd = x[:, :2], x[:, 2:]
+        q, qd = run_substeps(m, q, qd, torch.zeros(1, 1, dtype=F64), dt, n)
+        return torch.cat([q, qd], 1)
+
+    J = torch.autograd.functional.jacobian(f, T([[0.0, np.pi, 0.0, 0.0]]))[0, :, 0, :].numpy()
+    P = np.linalg.matrix_power(Phi, n)
+    assert np.allclose(J, P, rtol=1e-9, atol=1e-9 * np.abs(P).max())
+
+
+# ------------------------------------------------------------------ window adjoint vs FD
+
+def _fd_check(W, h, envs, coords_a, coords_s, eps, tol, closed_loop=True):
+    md = W["model"]
+    s0 = W["s0"][envs]
+    N = W["n_envs"]
+    actor = W["actor"] if closed_loop else None
+    acts = None
+    if not closed_loop:
+        rng = np.random.default_rng(7)
+        acts = np.tanh(rng.normal(size=(h, len(envs), md["na"])))
+    g = oracle_window_grads(md, s0, h, actor, W["critic"], actions=acts, n_total=N)
+    m = OracleModel(md)
+    lay = ([(T(Wt), T(b)) for Wt, b in W["actor"]], [(T(Wt), T(b)) for Wt, b in W["critic"]])
+
+    def loss(ds=None, da=None):
+        s = T(s0).clone()
+        if ds is not None:
+            s = s + T(ds)
+        return float(oracle_window(m, s, h, actions=acts, n_total=N, layers=lay,
+                                   action_offset=da)["loss"])
+    L0 = abs(loss())
+    floor = 50 * 2.2e-16 * L0 / eps        # roundoff of a central difference of L
+    worst = 0.0
+    for (t, e, k) in coords_a:
+        da = np.zeros((h, len(envs), md["na"]))
+        da[t, e, k] = eps
+        fd = (loss(da=da) - loss(da=-da)) / (2 * eps)
+        an = g["dL_da"][t, e, k]
+        worst = max(worst, abs(fd - an) / (abs(fd) + 1e-12 * (1 + abs(an))))
+        assert abs(fd - an) <= tol * abs(fd) + floor, (t, e, k, fd, an)
+    for (e, k) in coords_s:
+        ds = np.zeros_like(s0)
+        ds[e, k] = eps
+        fd = (loss(ds=ds) - loss(ds=-ds)) / (2 * eps)
+        an = g["dL_ds0"][e, k]
+        assert abs(fd - an) <= tol * abs(fd) + floor, (e, k, fd, an)
+    return worst
+
+
+def test_window_adjoint_fd_cartpole_every_coordinate():
+    W = wl.workload("cartpole")
+    h = 32
+    envs = [0, 5]
+    coords_a = [(t, e, 0) for t in range(h) for e in range(len(envs))]
+    coords_s = [(e, k) for e in range(len(envs)) for k in range(4)]
+    _fd_check(W, h, envs, coords_a, coords_s, 1e-6, 1e-6)
+
+
+def test_window_adjoint_fd_ant_short():
+    W = wl.workload("ant", 64)
+    h = 2
+    rng = np.random.default_rng(0)
+    coords_a = [(t, 0, int(k)) for t in range(h) for k in rng.choice(8, 3, replace=False)]
+    coords_s = [(0, int(k)) for k in rng.choice(37, 8, replace=False)]
+    _fd_check(W, h, [3], coords_a, coords_s, 1e-6, 1e-5)
+
+
+def test_policy_weight_fd_like_paper_check():
+    """FD of the loss along single actor weights vs the reverse-mode dL/dtheta (App. A.5)."""
+    W = wl.workload("cartpole")
+    h = 16
+    s0 = W["s0"][:4]
+    g = oracle_window_grads(W["model"], s0, h, W["actor"], W["critic"], n_total=16,
+                            want_theta=True)
+    for (li, idx) in ((0, (3, 1)), (1, (10, 20)), (2, (0, 5))):
+        eps = 1e-6
+        Wp = [(x.copy(), y.copy()) for x, y in W["actor"]]
+        Wm = [(x.copy(), y.copy()) for x, y in W["actor"]]
+        Wp[li][0][idx] += eps
+        Wm[li][0][idx] -= eps
+        lp = float(oracle_window(W["model"], s0, h, Wp, W["critic"], n_total=16)["loss"])
+        lm = float(oracle_window(W["model"], s0, h, Wm, W["critic"], n_total=16)["loss"])
+        fd = (lp - lm) / (2 * eps)
+        an = g["dL_dtheta"][li][0][idx]
+        floor = 50 * 2.2e-16 * abs(lp) / eps
+        assert abs(fd - an) <= 1e-6 * abs(fd) + floor, (li, idx, fd, an)
+
+
+def test_window_adjoint_fd_humanoid_short():
+    W = wl.workload("humanoid", 1024)
+    h = 1
+    coords_a = [(0, 0, 0), (0, 0, 7), (0, 0, 20)]
+    coords_s = [(0, 2), (0, 9), (0, 40), (0, 60)]
+    _fd_check(W, h, [5], coords_a, coords_s, 1e-6, 1e-5)
