@@ -1,0 +1,186 @@
+/*
+ * shacsim — batched differentiable articulated-body windows on one AMD Instinct GPU.
+ *
+ * C ABI of the hot path of Short-Horizon Actor-Critic (Xu et al., ICLR 2022): N
+ * independent environments are simulated forward over a window of h frames by the
+ * simulator map s_{t+1} = F(s_t, a_t) (Sec. 3.1), with the actions produced in the
+ * loop by a deterministic MLP policy (Sec. 3.3) or given open loop, and the window is
+ * then differentiated backward (Sec. 3.1 Eq. "backward"; App. A.1) to give the
+ * gradients of the short-horizon actor loss (Sec. 3.3 Eq. "policy_loss")
+ *     L = -1/(N h) sum_i [ sum_t gamma^t R(s_t, a_t) + gamma^h V(s_h) ]
+ * with respect to the actions and the window's initial states.  Gradients stop at the
+ * window start (Sec. 3.3: gradients are cut between learning episodes).
+ *
+ * Dynamics (Sec. 3.1 Eq. "fwd_dynamics"): generalized coordinates, RNEA bias forces,
+ * CRBA mass matrix, a per-environment dense Cholesky solve, penalty ground contact with
+ * the linear-step Coulomb friction law (Sec. 3.1 contact equation), joint-limit
+ * penalties (Sec. 3.1 limit equation) and semi-implicit Euler with S substeps per frame.
+ *
+ * Conventions
+ *   - Every array passed to sim_forward_window / sim_adjoint_window is a DEVICE pointer
+ *     owned by the caller, row-major and env-major:  X[t][env][component].  Real arrays
+ *     are float32 when the handle's precision is SIM_PREC_FP32 (the production path:
+ *     dynamics, policy and critic in FP32) and float64 when it is SIM_PREC_FP64 (the
+ *     same kernels instantiated in double precision, for verification at scale).
+ *   - State  s = [q (nq) | qd (nv) | a_prev (na, tasks whose observation holds the last
+ *     action)].  A free root has q = (x, y, z, qw, qx, qy, qz) and qd = (world velocity of
+ *     the root origin, world angular velocity).
+ *   - MLP weights are W[out][in] and b[out] per linear layer (ELU hidden layers, linear
+ *     output; the policy output is squashed by tanh).
+ *   - The calls enqueue work on the given HIP stream and return; they allocate nothing
+ *     (the caller passes a workspace of sim_workspace_bytes()) and may be captured in a
+ *     HIP graph.  The forward and the adjoint of one window must use the same handle,
+ *     workspace and stream order.
+ * Errors
+ *   - Functions return a SimStatus.  Argument errors are detected before anything is
+ *     enqueued and leave the outputs untouched; sim_last_error() then describes the
+ *     problem (per calling thread).  Numerical failure of one environment is data, not an
+ *     error: its nonfinite flag is set and the other environments are unaffected.
+ */
+#ifndef SHACSIM_H
+#define SHACSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_E_ARG = -1,         /* bad argument: null pointer, size, shape or option */
+  SIM_E_HANDLE = -2,      /* null or destroyed handle */
+  SIM_E_HIP = -3,         /* a HIP runtime call failed */
+  SIM_E_MODEL = -4,       /* model description invalid or beyond the compiled limits */
+  SIM_E_WORKSPACE = -5,   /* workspace missing or smaller than sim_workspace_bytes() */
+  SIM_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} SimStatus;
+
+enum { SIM_JOINT_FREE = 0, SIM_JOINT_HINGE = 1, SIM_JOINT_SLIDE = 2 };
+enum { SIM_TASK_NONE = 0, SIM_TASK_CARTPOLE = 1, SIM_TASK_ANT = 2, SIM_TASK_HUMANOID = 3 };
+enum { SIM_PATH_PERSISTENT = 0, SIM_PATH_PLAIN = 1 };
+enum { SIM_PREC_FP32 = 0, SIM_PREC_FP64 = 1 };
+
+/* Compiled limits. */
+#define SIM_MAX_JOINTS 32
+#define SIM_MAX_DOFS 32
+#define SIM_MAX_CONTACTS 32
+#define SIM_MAX_ACTIONS 32
+#define SIM_MAX_OBS 128
+#define SIM_MAX_HIDDEN 512
+#define SIM_MAX_LAYERS 4
+
+/* Articulated model (host memory, read during sim_create only).  Frame j hangs from frame
+ * parent[j] (-1 = world, parents listed first) at offset[j] (parent frame, no fixed
+ * rotation), then moves through its joint (FREE root, HINGE about axis[j], SLIDE along
+ * axis[j]).  mass/com/inertia describe the body rigidly attached to frame j (inertia about
+ * the COM in frame axes, 3x3 row-major; mass 0 = massless frame).  Actuator i drives
+ * joint act_joint[i] with torque/force gear[i] * a_i.  Contact spheres (body, centre in
+ * the body frame, radius) touch the ground plane z = 0. */
+typedef struct SimModelDesc {
+  int n_joints;
+  const int* parent;
+  const int* jtype;
+  const double* offset;          /* [J][3] */
+  const double* axis;            /* [J][3], unit */
+  const double* mass;            /* [J] */
+  const double* com;             /* [J][3] */
+  const double* inertia;         /* [J][3][3] */
+  const int* limited;            /* [J] */
+  const double* lower;           /* [J] */
+  const double* upper;           /* [J] */
+  int n_act;
+  const int* act_joint;          /* [n_act] */
+  const double* gear;            /* [n_act] */
+  const double* armature;        /* [nv] added to the mass-matrix diagonal */
+  int n_contacts;
+  const int* contact_body;       /* [C] */
+  const double* contact_pos;     /* [C][3] */
+  const double* contact_radius;  /* [C] */
+  double gravity;                /* m/s^2, along -z */
+  double kn, kd, kt, mu;         /* contact stiffness, damping, friction stiffness, Coulomb mu */
+  double klim;                   /* joint-limit stiffness */
+  double dt;                     /* frame duration (s) */
+  int substeps;                  /* S: semi-implicit Euler substeps per frame */
+  int task;                      /* SIM_TASK_*: observation and reward definition */
+  int has_last_action;           /* state carries the previous action */
+} SimModelDesc;
+
+typedef struct SimOptions {
+  int n_envs;                    /* N */
+  int horizon;                   /* h frames per window */
+  int ckpt_interval;             /* k: the forward stores the state every k substeps (k | S) */
+  int path;                      /* SIM_PATH_PERSISTENT (one launch per window) or SIM_PATH_PLAIN */
+  int closed_loop;               /* 1: actions from the actor MLP; 0: actions given */
+  int actor_layers;              /* linear layers of the actor (closed loop) */
+  int actor_dims[SIM_MAX_LAYERS + 1];
+  int critic_layers;             /* linear layers of the critic (terminal value) */
+  int critic_dims[SIM_MAX_LAYERS + 1];
+  double gamma;                  /* discount */
+  int precision;                 /* SIM_PREC_FP32 or SIM_PREC_FP64 (arithmetic and I/O type) */
+} SimOptions;
+
+typedef struct SimHandle SimHandle;
+
+typedef struct SimForwardIO {
+  const void* s0;                           /* [N][ns] */
+  const void* actions_in;                   /* [h][N][na], open loop only */
+  const void* actor_w[SIM_MAX_LAYERS];      /* closed loop only: W [out][in] */
+  const void* actor_b[SIM_MAX_LAYERS];      /* b [out] */
+  const void* critic_w[SIM_MAX_LAYERS];
+  const void* critic_b[SIM_MAX_LAYERS];
+  void* workspace;                          /* sim_workspace_bytes() bytes, 256-byte aligned */
+  size_t workspace_bytes;
+  void* s_h;                                /* [N][ns] out: state after h frames */
+  void* obs;                                /* [h+1][N][obs_dim] out */
+  void* actions;                            /* [h][N][na] out */
+  void* rewards;                            /* [h][N] out */
+  void* value;                              /* [N] out: critic value of s_h */
+  uint8_t* nonfinite;                       /* [N] out, optional: 1 if s_h is not finite */
+} SimForwardIO;
+
+typedef struct SimAdjointIO {
+  const void* s0;                           /* as given to the forward */
+  const void* actions;                      /* forward output */
+  const void* obs;                          /* forward output */
+  const void* s_h;                          /* forward output */
+  const void* actor_w[SIM_MAX_LAYERS];
+  const void* actor_b[SIM_MAX_LAYERS];
+  const void* critic_w[SIM_MAX_LAYERS];
+  const void* critic_b[SIM_MAX_LAYERS];
+  void* workspace;                          /* written by the matching forward */
+  size_t workspace_bytes;
+  const void* grad_s_h;                     /* [N][ns] optional extra upstream dL/ds_h */
+  double loss_scale;                        /* factor on the loss seeds: 1/(N h) for the actor loss
+                                               of Sec. 3.3 (times dOut/dL when chained); 0 = only
+                                               grad_s_h is propagated */
+  void* dL_da;                              /* [h][N][na] out: partial dL/da_t (App. A.1) */
+  void* dL_ds0;                             /* [N][ns] out: total dL/ds_0 (App. A.1) */
+} SimAdjointIO;
+
+/* Validates the model and options and uploads the constant tables to the current device.
+ * Returns SIM_E_MODEL for a model beyond the compiled limits. */
+int sim_create(const SimModelDesc* model, const SimOptions* opt, SimHandle** out);
+
+/* Bytes of device workspace the caller must provide (checkpoint arena + MLP copies). */
+size_t sim_workspace_bytes(const SimHandle* h);
+
+/* Sizes derived from the model: state width, observation width, actions, nq, nv. */
+int sim_dims(const SimHandle* h, int* n_state, int* n_obs, int* n_act, int* nq, int* nv);
+
+/* Forward window: h frames of (observation, policy, reward, S substeps). */
+int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hip_stream);
+
+/* Reverse of the forward window: dL/da_t and dL/ds_0 of the actor loss. */
+int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream);
+
+void sim_destroy(SimHandle* h);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHACSIM_H */

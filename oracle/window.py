@@ -99,7 +99,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         if actions is None:
             a = torch.tanh(mlp_forward(act_l, o))
         else:
-            a = actions[t] if torch.is_tensor(actions) else _t(actions[t])
+            a = actions[t] if torch.is_tensor(actions[t]) else _t(actions[t])
         if action_offset is not None:
             a = a + _t(action_offset[t])
         if keep_graph and not a.requires_grad:

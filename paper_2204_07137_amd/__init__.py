@@ -1,0 +1,311 @@
+"""Python binding of libshacsim (argument marshalling only).
+
+Every step of the window runs in the HIP kernels of ``libshacsim.so``; PyTorch is used
+for device memory and streams.  Importing this package does not load the library;
+``lib()`` does, and raises if the library is missing (there is no fallback).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshacsim.so")
+
+MAXL = 4
+PATH_PERSISTENT, PATH_PLAIN = 0, 1
+PREC = {"fp32": 0, "fp64": 1}
+TASKS = {"none": 0, "cartpole": 1, "ant": 2, "humanoid": 3}
+STATUS = {0: "SIM_OK", -1: "SIM_E_ARG", -2: "SIM_E_HANDLE", -3: "SIM_E_HIP", -4: "SIM_E_MODEL",
+          -5: "SIM_E_WORKSPACE", -6: "SIM_E_UNSUPPORTED"}
+
+_p = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_f = ctypes.c_float
+
+
+class SimModelDesc(ctypes.Structure):
+    _fields_ = [("n_joints", _i), ("parent", _p), ("jtype", _p), ("offset", _p), ("axis", _p),
+                ("mass", _p), ("com", _p), ("inertia", _p), ("limited", _p), ("lower", _p),
+                ("upper", _p), ("n_act", _i), ("act_joint", _p), ("gear", _p), ("armature", _p),
+                ("n_contacts", _i), ("contact_body", _p), ("contact_pos", _p),
+                ("contact_radius", _p), ("gravity", _d), ("kn", _d), ("kd", _d), ("kt", _d),
+                ("mu", _d), ("klim", _d), ("dt", _d), ("substeps", _i), ("task", _i),
+                ("has_last_action", _i)]
+
+
+class SimOptions(ctypes.Structure):
+    _fields_ = [("n_envs", _i), ("horizon", _i), ("ckpt_interval", _i), ("path", _i),
+                ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
+                ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
+                ("precision", _i)]
+
+
+class SimForwardIO(ctypes.Structure):
+    _fields_ = [("s0", _p), ("actions_in", _p), ("actor_w", _p * MAXL), ("actor_b", _p * MAXL),
+                ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("workspace", _p),
+                ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
+                ("rewards", _p), ("value", _p), ("nonfinite", _p)]
+
+
+class SimAdjointIO(ctypes.Structure):
+    _fields_ = [("s0", _p), ("actions", _p), ("obs", _p), ("s_h", _p),
+                ("actor_w", _p * MAXL), ("actor_b", _p * MAXL), ("critic_w", _p * MAXL),
+                ("critic_b", _p * MAXL), ("workspace", _p), ("workspace_bytes", ctypes.c_size_t),
+                ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p)]
+
+
+EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
+           "sim_adjoint_window", "sim_destroy", "sim_last_error"]
+
+_LIB = None
+
+
+def lib():
+    """Load libshacsim.so (built in-tree by build()).  Raises if it is absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2204_07137_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.sim_create.argtypes = [ctypes.POINTER(SimModelDesc), ctypes.POINTER(SimOptions), ctypes.POINTER(_p)]
+        L.sim_create.restype = _i
+        L.sim_workspace_bytes.argtypes = [_p]
+        L.sim_workspace_bytes.restype = ctypes.c_size_t
+        L.sim_dims.argtypes = [_p] + [ctypes.POINTER(_i)] * 5
+        L.sim_dims.restype = _i
+        L.sim_forward_window.argtypes = [_p, ctypes.POINTER(SimForwardIO), _p]
+        L.sim_forward_window.restype = _i
+        L.sim_adjoint_window.argtypes = [_p, ctypes.POINTER(SimAdjointIO), _p]
+        L.sim_adjoint_window.restype = _i
+        L.sim_destroy.argtypes = [_p]
+        L.sim_destroy.restype = None
+        L.sim_last_error.argtypes = []
+        L.sim_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise SimError(code, lib().sim_last_error().decode())
+
+
+def _arr(x, dtype):
+    return np.ascontiguousarray(np.asarray(x), dtype=dtype)
+
+
+def model_desc(md):
+    """Build a SimModelDesc (and keep its host arrays alive) from a workload model dict."""
+    keep = {}
+
+    def ptr(name, arr, dtype):
+        a = _arr(arr, dtype)
+        keep[name] = a
+        return a.ctypes.data_as(_p)
+
+    d = SimModelDesc()
+    d.n_joints = int(md["n_joints"])
+    d.parent = ptr("parent", md["parent"], np.int32)
+    d.jtype = ptr("jtype", md["jtype"], np.int32)
+    d.offset = ptr("offset", md["offset"], np.float64)
+    d.axis = ptr("axis", md["axis"], np.float64)
+    d.mass = ptr("mass", md["mass"], np.float64)
+    d.com = ptr("com", md["com"], np.float64)
+    d.inertia = ptr("inertia", md["inertia"], np.float64)
+    d.limited = ptr("limited", md["limited"], np.int32)
+    d.lower = ptr("lower", md["lower"], np.float64)
+    d.upper = ptr("upper", md["upper"], np.float64)
+    d.n_act = int(md["na"])
+    d.act_joint = ptr("act_joint", md["act_joint"], np.int32)
+    d.gear = ptr("gear", md["gear"], np.float64)
+    d.armature = ptr("armature", md["armature"], np.float64)
+    d.n_contacts = int(len(md["contact_body"]))
+    d.contact_body = ptr("contact_body", md["contact_body"], np.int32)
+    d.contact_pos = ptr("contact_pos", np.reshape(md["contact_pos"], (-1, 3)), np.float64)
+    d.contact_radius = ptr("contact_radius", md["contact_radius"], np.float64)
+    for k in ("gravity", "kn", "kd", "kt", "mu", "klim", "dt"):
+        setattr(d, k, float(md[k]))
+    d.substeps = int(md["substeps"])
+    d.task = TASKS[md["task"]]
+    d.has_last_action = int(md["has_last_action"])
+    return d, keep
+
+
+class Sim:
+    """One handle: a model, a batch size N, a horizon h and the MLP shapes."""
+
+    def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
+                 path=PATH_PERSISTENT, gamma=0.99, precision="fp32"):
+        import torch
+        self.torch = torch
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        L = lib()
+        self.md = md
+        d, self._keep = model_desc(md)
+        o = SimOptions()
+        o.n_envs = int(n_envs)
+        o.horizon = int(horizon)
+        o.ckpt_interval = int(ckpt_interval if ckpt_interval is not None else
+                              (1 if path == PATH_PLAIN else md["substeps"]))
+        o.path = int(path)
+        o.closed_loop = 1 if actor_dims is not None else 0
+        if actor_dims is not None:
+            o.actor_layers = len(actor_dims) - 1
+            for i, v in enumerate(actor_dims):
+                o.actor_dims[i] = int(v)
+        o.critic_layers = len(critic_dims) - 1
+        for i, v in enumerate(critic_dims):
+            o.critic_dims[i] = int(v)
+        o.gamma = float(gamma)
+        o.precision = PREC[precision]
+        h = _p()
+        _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self.opt = o
+        dims = [_i() for _ in range(5)]
+        _check(L.sim_dims(h, *[ctypes.byref(x) for x in dims]))
+        self.ns, self.od, self.na, self.nq, self.nv = (x.value for x in dims)
+        self.N, self.H = int(n_envs), int(horizon)
+        self.ws_bytes = int(L.sim_workspace_bytes(h))
+        self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def _dev(self, x):
+        t = self.torch
+        if isinstance(x, t.Tensor):
+            return x.to(device="cuda", dtype=self.dtype).contiguous()
+        return t.as_tensor(np.asarray(x), dtype=self.dtype, device="cuda").contiguous()
+
+    def weights(self, layers):
+        """[(W [out,in], b [out])] -> device float32 tensors."""
+        return [(self._dev(W), self._dev(b)) for (W, b) in layers]
+
+    @staticmethod
+    def _ptr(t):
+        return _p(t.data_ptr()) if t is not None else _p(0)
+
+    def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None):
+        """Run sim_forward_window.  Returns a dict of device tensors."""
+        t = self.torch
+        N, H = self.N, self.H
+        s0 = self._dev(s0)
+        assert s0.shape == (N, self.ns), (s0.shape, (N, self.ns))
+        dt = self.dtype
+        out = dict(
+            s0=s0,
+            s_h=t.empty(N, self.ns, device="cuda", dtype=dt),
+            obs=t.empty(H + 1, N, self.od, device="cuda", dtype=dt),
+            actions=t.empty(H, N, self.na, device="cuda", dtype=dt),
+            rewards=t.empty(H, N, device="cuda", dtype=dt),
+            value=t.empty(N, device="cuda", dtype=dt),
+            nonfinite=t.zeros(N, dtype=t.uint8, device="cuda"),
+        )
+        io = SimForwardIO()
+        io.s0 = self._ptr(s0)
+        if actions_in is not None:
+            actions_in = self._dev(actions_in)
+            assert actions_in.shape == (H, N, self.na)
+            out["actions_in"] = actions_in
+            io.actions_in = self._ptr(actions_in)
+        self._set_weights(io, actor, critic, out)
+        io.workspace = self._ptr(self.workspace)
+        io.workspace_bytes = self.workspace.numel()
+        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite"):
+            setattr(io, k, self._ptr(out[k]))
+        st = stream if stream is not None else t.cuda.current_stream()
+        _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
+        return out
+
+    def _set_weights(self, io, actor, critic, keep):
+        if actor is not None:
+            aw = self.weights(actor)
+            keep["actor"] = aw
+            for i, (W, b) in enumerate(aw):
+                io.actor_w[i] = W.data_ptr()
+                io.actor_b[i] = b.data_ptr()
+        cw = self.weights(critic)
+        keep["critic"] = cw
+        for i, (W, b) in enumerate(cw):
+            io.critic_w[i] = W.data_ptr()
+            io.critic_b[i] = b.data_ptr()
+
+    def adjoint(self, fw, actor=None, critic=None, grad_s_h=None, loss_scale=None, stream=None):
+        """Run sim_adjoint_window after forward() on the same handle and stream.
+
+        loss_scale defaults to 1/(N h), the gradient of the actor loss itself."""
+        t = self.torch
+        N, H = self.N, self.H
+        dt = self.dtype
+        out = dict(dL_da=t.empty(H, N, self.na, device="cuda", dtype=dt),
+                   dL_ds0=t.empty(N, self.ns, device="cuda", dtype=dt))
+        io = SimAdjointIO()
+        io.s0 = self._ptr(fw["s0"])
+        io.actions = self._ptr(fw["actions"])
+        io.obs = self._ptr(fw["obs"])
+        io.s_h = self._ptr(fw["s_h"])
+        self._set_weights(io, actor if actor is not None else fw.get("actor"),
+                          critic if critic is not None else fw["critic"], out)
+        io.workspace = self._ptr(self.workspace)
+        io.workspace_bytes = self.workspace.numel()
+        if grad_s_h is not None:
+            grad_s_h = self._dev(grad_s_h)
+            out["grad_s_h"] = grad_s_h
+            io.grad_s_h = self._ptr(grad_s_h)
+        io.loss_scale = float(1.0 / (N * H) if loss_scale is None else loss_scale)
+        io.dL_da = self._ptr(out["dL_da"])
+        io.dL_ds0 = self._ptr(out["dL_ds0"])
+        st = stream if stream is not None else t.cuda.current_stream()
+        _check(lib().sim_adjoint_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
+        return out
+
+
+def window_function():
+    """torch.autograd.Function over one window: forward -> sim_forward_window, backward ->
+    sim_adjoint_window.  ``ShacWindow.apply(sim, s0, actor, critic, actions_in)`` returns
+    (loss, s_h, obs, actions, rewards, value); gradients flow to s0 (total, through the
+    closed-loop policy) and, in open loop, to actions_in.  The loss is the short-horizon
+    actor loss; a gradient arriving on s_h is propagated through the window as well."""
+    import torch
+
+    class ShacWindow(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sim, s0, actor, critic, actions_in):
+            fw = sim.forward(s0.detach(), actor, critic,
+                             actions_in.detach() if actions_in is not None else None)
+            g = sim.opt.gamma
+            H, N = sim.H, sim.N
+            disc = torch.stack([g ** t * fw["rewards"][t] for t in range(H)]).sum(0)
+            loss = -(disc + g ** H * fw["value"]).sum() / (N * H)
+            ctx.sim, ctx.fw, ctx.open_loop = sim, fw, actions_in is not None
+            ctx.mark_non_differentiable(fw["obs"], fw["actions"], fw["rewards"], fw["value"])
+            return loss, fw["s_h"], fw["obs"], fw["actions"], fw["rewards"], fw["value"]
+
+        @staticmethod
+        def backward(ctx, g_loss, g_sh, *unused):
+            sim, fw = ctx.sim, ctx.fw
+            scale = float(g_loss) / (sim.N * sim.H) if g_loss is not None else 0.0
+            ad = sim.adjoint(fw, grad_s_h=g_sh, loss_scale=scale)
+            gs0 = ad["dL_ds0"]
+            ga = ad["dL_da"] if ctx.open_loop else None
+            return None, gs0, None, None, ga
+
+    return ShacWindow

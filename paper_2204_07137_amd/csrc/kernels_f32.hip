@@ -1,0 +1,12 @@
+// FP32 instantiation of the window kernels (the production path).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "sim_types.h"
+
+namespace sim_f32 {
+typedef float real;
+#include "sim_math.h"
+#include "sim_dynamics.h"
+#include "sim_task.h"
+#include "sim_kernels.h"
+}  // namespace sim_f32

@@ -1,0 +1,12 @@
+// FP64 instantiation of the window kernels (reference-precision path on the GPU).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "sim_types.h"
+
+namespace sim_f64 {
+typedef double real;
+#include "sim_math.h"
+#include "sim_dynamics.h"
+#include "sim_task.h"
+#include "sim_kernels.h"
+}  // namespace sim_f64

@@ -1,0 +1,399 @@
+// Host side of the C ABI: model validation and upload, workspace layout, argument
+// checks and dispatch to the FP32 or FP64 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "../../include/shacsim.h"
+#include "sim_types.h"
+
+static_assert(SIM_MAX_JOINTS == SIM_MAXJ, "limit mismatch");
+static_assert(SIM_MAX_DOFS == SIM_MAXV, "limit mismatch");
+static_assert(SIM_MAX_CONTACTS == SIM_MAXC, "limit mismatch");
+static_assert(SIM_MAX_ACTIONS == SIM_MAXA, "limit mismatch");
+static_assert(SIM_MAX_HIDDEN == SIM_MAXHID, "limit mismatch");
+static_assert(SIM_MAX_OBS == SIM_MAXOBS, "limit mismatch");
+static_assert(SIM_MAX_LAYERS == SIM_MAXL, "limit mismatch");
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+static const uint32_t kMagic = 0x53484143u;
+
+struct SimHandle {
+  DevModelT<float> m32;
+  DevModelT<double> m64;
+  void* dev_model = nullptr;
+  SimOptions opt;
+  int ns = 0, od = 0, nq = 0, nv = 0, na = 0, substeps = 0;
+  size_t elem = 4;
+  size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL];
+  size_t off_ckpt = 0, off_seg = 0, off_adj = 0, ws_bytes = 0;
+  int n_ckpt = 0;
+  int device = -1;
+  uint32_t magic = kMagic;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" const char* sim_last_error(void) { return g_err.c_str(); }
+
+template <typename T>
+static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
+  std::memcpy(&d, &s, offsetof(DevModelT<double>, dt_sub));   // leading ints
+  d.dt_sub = (T)s.dt_sub; d.g = (T)s.g; d.kn = (T)s.kn; d.kd = (T)s.kd; d.kt = (T)s.kt; d.mu = (T)s.mu;
+  d.klim = (T)s.klim;
+  for (int j = 0; j < SIM_MAXJ; ++j) {
+    d.parent[j] = s.parent[j]; d.jtype[j] = s.jtype[j]; d.qadr[j] = s.qadr[j]; d.vadr[j] = s.vadr[j];
+    d.depth[j] = s.depth[j]; d.first_child[j] = s.first_child[j]; d.next_sib[j] = s.next_sib[j];
+    d.act_of_joint[j] = s.act_of_joint[j]; d.limited[j] = s.limited[j];
+    d.mass[j] = (T)s.mass[j]; d.lower[j] = (T)s.lower[j]; d.upper[j] = (T)s.upper[j]; d.gear[j] = (T)s.gear[j];
+    for (int k = 0; k < 3; ++k) {
+      d.offset[3 * j + k] = (T)s.offset[3 * j + k];
+      d.axis[3 * j + k] = (T)s.axis[3 * j + k];
+      d.com[3 * j + k] = (T)s.com[3 * j + k];
+    }
+    for (int k = 0; k < 6; ++k) d.inertia[6 * j + k] = (T)s.inertia[6 * j + k];
+  }
+  for (int i = 0; i < SIM_MAXV; ++i) d.armature[i] = (T)s.armature[i];
+  for (int c = 0; c < SIM_MAXC; ++c) {
+    d.cbody[c] = s.cbody[c];
+    d.crad[c] = (T)s.crad[c];
+    for (int k = 0; k < 3; ++k) d.cpos[3 * c + k] = (T)s.cpos[3 * c + k];
+  }
+}
+
+static int obs_dim_for(const DevModelT<double>& m) {
+  if (m.task == TASK_CARTPOLE) return 5;
+  if (m.task == TASK_ANT || m.task == TASK_HUMANOID) return 13 + 2 * (m.nq - 7) + (m.has_last_action ? m.na : 0);
+  return 0;
+}
+
+static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
+  std::memset(&m, 0, sizeof(m));
+  int J = md->n_joints;
+  if (J < 1 || J > SIM_MAXJ) return fail(SIM_E_MODEL, "n_joints out of range [1, 32]");
+  if (!md->parent || !md->jtype || !md->offset || !md->axis || !md->mass || !md->com || !md->inertia ||
+      !md->limited || !md->lower || !md->upper || !md->armature)
+    return fail(SIM_E_ARG, "sim_create: null model array");
+  for (int j = 0; j < SIM_MAXJ; ++j) {
+    m.first_child[j] = -1; m.next_sib[j] = -1; m.act_of_joint[j] = -1; m.parent[j] = -1; m.depth[j] = -1;
+  }
+  int nq = 0, nv = 0, maxd = 0;
+  for (int j = 0; j < J; ++j) {
+    int p = md->parent[j], t = md->jtype[j];
+    if (p >= j || p < -1) return fail(SIM_E_MODEL, "parents must precede children");
+    if (t != J_FREE && t != J_HINGE && t != J_SLIDE) return fail(SIM_E_MODEL, "unknown joint type");
+    if (t == J_FREE && (p != -1 || j != 0)) return fail(SIM_E_MODEL, "a FREE joint must be frame 0 with no parent");
+    m.parent[j] = p;
+    m.jtype[j] = t;
+    m.qadr[j] = nq;
+    m.vadr[j] = nv;
+    nq += (t == J_FREE) ? 7 : 1;
+    nv += (t == J_FREE) ? 6 : 1;
+    m.depth[j] = (p < 0) ? 0 : m.depth[p] + 1;
+    maxd = std::max(maxd, m.depth[j]);
+    for (int k = 0; k < 3; ++k) {
+      m.offset[3 * j + k] = md->offset[3 * j + k];
+      m.axis[3 * j + k] = md->axis[3 * j + k];
+      m.com[3 * j + k] = md->com[3 * j + k];
+    }
+    const double* I = md->inertia + 9 * j;
+    m.inertia[6 * j + 0] = I[0];
+    m.inertia[6 * j + 1] = I[4];
+    m.inertia[6 * j + 2] = I[8];
+    m.inertia[6 * j + 3] = I[1];
+    m.inertia[6 * j + 4] = I[2];
+    m.inertia[6 * j + 5] = I[5];
+    if (!(md->mass[j] >= 0.0)) return fail(SIM_E_MODEL, "negative mass");
+    m.mass[j] = md->mass[j];
+    m.limited[j] = md->limited[j] ? 1 : 0;
+    m.lower[j] = md->lower[j];
+    m.upper[j] = md->upper[j];
+  }
+  if (nv > SIM_MAXV || nq > SIM_MAXQ) return fail(SIM_E_MODEL, "more than 32 velocity DOFs");
+  for (int j = J - 1; j >= 1; --j) {
+    int p = m.parent[j];
+    if (p >= 0) {
+      m.next_sib[j] = m.first_child[p];
+      m.first_child[p] = j;
+    }
+  }
+  if (md->n_act < 0 || md->n_act > SIM_MAXA) return fail(SIM_E_MODEL, "n_act out of range [0, 32]");
+  if (md->n_act > 0 && (!md->act_joint || !md->gear)) return fail(SIM_E_ARG, "null actuator arrays");
+  for (int i = 0; i < md->n_act; ++i) {
+    int j = md->act_joint[i];
+    if (j < 0 || j >= J || m.jtype[j] == J_FREE || m.act_of_joint[j] >= 0)
+      return fail(SIM_E_MODEL, "actuator must drive a distinct hinge or slide joint");
+    m.act_of_joint[j] = i;
+    m.gear[j] = md->gear[i];
+  }
+  for (int i = 0; i < nv; ++i) m.armature[i] = md->armature[i];
+  if (md->n_contacts < 0 || md->n_contacts > SIM_MAXC) return fail(SIM_E_MODEL, "n_contacts out of range [0, 32]");
+  if (md->n_contacts > 0 && (!md->contact_body || !md->contact_pos || !md->contact_radius))
+    return fail(SIM_E_ARG, "null contact arrays");
+  for (int c = 0; c < md->n_contacts; ++c) {
+    int b = md->contact_body[c];
+    if (b < 0 || b >= J) return fail(SIM_E_MODEL, "contact body out of range");
+    m.cbody[c] = b;
+    for (int k = 0; k < 3; ++k) m.cpos[3 * c + k] = md->contact_pos[3 * c + k];
+    m.crad[c] = md->contact_radius[c];
+  }
+  if (md->substeps < 1 || !(md->dt > 0)) return fail(SIM_E_MODEL, "substeps >= 1 and dt > 0 required");
+  m.J = J; m.nq = nq; m.nv = nv; m.na = md->n_act; m.nc = md->n_contacts;
+  m.task = md->task; m.floating = (m.jtype[0] == J_FREE) ? 1 : 0;
+  m.has_last_action = md->has_last_action ? 1 : 0;
+  m.substeps = md->substeps; m.max_depth = maxd;
+  m.dt_sub = md->dt / md->substeps;
+  m.g = md->gravity; m.kn = md->kn; m.kd = md->kd; m.kt = md->kt; m.mu = md->mu; m.klim = md->klim;
+  m.ns = nq + nv + (m.has_last_action ? m.na : 0);
+  if (m.task == TASK_ANT || m.task == TASK_HUMANOID) {
+    if (!m.floating) return fail(SIM_E_MODEL, "locomotion tasks need a FREE root");
+  } else if (m.task == TASK_CARTPOLE) {
+    if (nq != 2 || nv != 2) return fail(SIM_E_MODEL, "cartpole task needs a 2-DOF model");
+  } else if (m.task != TASK_NONE) {
+    return fail(SIM_E_MODEL, "unknown task");
+  }
+  m.od = obs_dim_for(m);
+  if (m.od > SIM_MAXOBS) return fail(SIM_E_MODEL, "observation wider than 128");
+  return SIM_OK;
+}
+
+static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
+  if (opt->n_envs < 1 || opt->horizon < 1) return fail(SIM_E_ARG, "n_envs and horizon must be >= 1");
+  if (opt->ckpt_interval < 1 || m.substeps % opt->ckpt_interval != 0)
+    return fail(SIM_E_ARG, "ckpt_interval must divide the substep count");
+  if (opt->path != SIM_PATH_PERSISTENT && opt->path != SIM_PATH_PLAIN) return fail(SIM_E_ARG, "unknown path");
+  if (opt->path == SIM_PATH_PLAIN && opt->ckpt_interval != 1)
+    return fail(SIM_E_ARG, "the plain path stores every substep: ckpt_interval must be 1");
+  if (opt->precision != SIM_PREC_FP32 && opt->precision != SIM_PREC_FP64) return fail(SIM_E_ARG, "unknown precision");
+  if (opt->critic_layers < 1 || opt->critic_layers > SIM_MAXL) return fail(SIM_E_ARG, "critic_layers out of range");
+  if (opt->critic_dims[0] != m.od || opt->critic_dims[opt->critic_layers] != 1)
+    return fail(SIM_E_ARG, "critic dims must map obs_dim to 1");
+  for (int l = 0; l <= opt->critic_layers; ++l)
+    if (opt->critic_dims[l] < 1 || opt->critic_dims[l] > SIM_MAXHID) return fail(SIM_E_ARG, "critic width out of range");
+  if (opt->closed_loop) {
+    if (opt->actor_layers < 1 || opt->actor_layers > SIM_MAXL) return fail(SIM_E_ARG, "actor_layers out of range");
+    if (opt->actor_dims[0] != m.od || opt->actor_dims[opt->actor_layers] != m.na)
+      return fail(SIM_E_ARG, "actor dims must map obs_dim to n_act");
+    for (int l = 0; l <= opt->actor_layers; ++l)
+      if (opt->actor_dims[l] < 1 || opt->actor_dims[l] > SIM_MAXHID) return fail(SIM_E_ARG, "actor width out of range");
+  }
+  if (opt->critic_layers > 3 || (opt->closed_loop && opt->actor_layers > 3))
+    return fail(SIM_E_UNSUPPORTED, "at most two hidden layers per MLP");
+  return SIM_OK;
+}
+
+extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHandle** out) {
+  if (!md || !opt || !out) return fail(SIM_E_ARG, "sim_create: null argument");
+  *out = nullptr;
+  DevModelT<double> m;
+  int rc = build_model(md, m);
+  if (rc) return rc;
+  rc = check_options(opt, m);
+  if (rc) return rc;
+  SimHandle* h = new SimHandle();
+  h->m64 = m;
+  convert_model(m, h->m32);
+  h->opt = *opt;
+  h->ns = m.ns; h->od = m.od; h->nq = m.nq; h->nv = m.nv; h->na = m.na; h->substeps = m.substeps;
+  h->elem = (opt->precision == SIM_PREC_FP64) ? 8 : 4;
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(SIM_E_HIP, "hipGetDevice failed"); }
+  size_t msz = (opt->precision == SIM_PREC_FP64) ? sizeof(DevModelT<double>) : sizeof(DevModelT<float>);
+  const void* src = (opt->precision == SIM_PREC_FP64) ? (const void*)&h->m64 : (const void*)&h->m32;
+  if (hipMalloc(&h->dev_model, msz) != hipSuccess) { delete h; return fail(SIM_E_HIP, "hipMalloc failed"); }
+  if (hipMemcpy(h->dev_model, src, msz, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(h->dev_model); delete h; return fail(SIM_E_HIP, "hipMemcpy failed");
+  }
+  // workspace: transposed MLP weights, checkpoint arena, segment pre-states, plain-path adjoint
+  const size_t e = h->elem;
+  size_t off = 0;
+  for (int l = 0; l < SIM_MAXL; ++l) { h->wt_actor_off[l] = 0; h->wt_critic_off[l] = 0; }
+  if (opt->closed_loop)
+    for (int l = 0; l < opt->actor_layers; ++l) {
+      h->wt_actor_off[l] = off;
+      off = align256(off + e * (size_t)opt->actor_dims[l] * opt->actor_dims[l + 1]);
+    }
+  for (int l = 0; l < opt->critic_layers; ++l) {
+    h->wt_critic_off[l] = off;
+    off = align256(off + e * (size_t)opt->critic_dims[l] * opt->critic_dims[l + 1]);
+  }
+  const size_t N = opt->n_envs, nqv = m.nq + m.nv;
+  h->n_ckpt = (opt->path == SIM_PATH_PLAIN) ? opt->horizon * m.substeps + 1
+                                             : opt->horizon * m.substeps / opt->ckpt_interval;
+  h->off_ckpt = off;
+  off = align256(off + e * (size_t)h->n_ckpt * N * nqv);
+  h->off_seg = off;
+  off = align256(off + e * N * (size_t)opt->ckpt_interval * nqv);
+  h->off_adj = off;
+  off = align256(off + e * N * (nqv + m.na));
+  h->ws_bytes = off;
+  *out = h;
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" size_t sim_workspace_bytes(const SimHandle* h) {
+  if (!h || h->magic != kMagic) return 0;
+  return h->ws_bytes;
+}
+
+extern "C" int sim_dims(const SimHandle* h, int* n_state, int* n_obs, int* n_act, int* nq, int* nv) {
+  if (!h || h->magic != kMagic) return fail(SIM_E_HANDLE, "invalid handle");
+  if (n_state) *n_state = h->ns;
+  if (n_obs) *n_obs = h->od;
+  if (n_act) *n_act = h->na;
+  if (nq) *nq = h->nq;
+  if (nv) *nv = h->nv;
+  return SIM_OK;
+}
+
+extern "C" void sim_destroy(SimHandle* h) {
+  if (!h || h->magic != kMagic) return;
+  h->magic = 0;
+  if (h->dev_model) hipFree(h->dev_model);
+  delete h;
+}
+
+static int check_handle(SimHandle* h) {
+  if (!h || h->magic != kMagic) return fail(SIM_E_HANDLE, "invalid handle");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_E_HIP, "hipGetDevice failed");
+  if (dev != h->device) return fail(SIM_E_ARG, "handle was created on another device");
+  return SIM_OK;
+}
+
+template <typename T>
+static int fill_mlp(MlpArgsT<T>& P, int nl, const int* dims, const void* const* W, const void* const* b,
+                    char* ws, const size_t* wt_off, const char* what) {
+  P.nl = nl;
+  for (int l = 0; l <= SIM_MAXL; ++l) P.dims[l] = (l <= nl) ? dims[l] : 0;
+  for (int l = 0; l < SIM_MAXL; ++l) { P.W[l] = nullptr; P.WT[l] = nullptr; P.b[l] = nullptr; }
+  for (int l = 0; l < nl; ++l) {
+    if (!W[l] || !b[l]) return fail(SIM_E_ARG, std::string(what) + ": null weight or bias pointer");
+    P.W[l] = static_cast<const T*>(W[l]);
+    P.b[l] = static_cast<const T*>(b[l]);
+    P.WT[l] = reinterpret_cast<const T*>(ws + wt_off[l]);
+  }
+  return SIM_OK;
+}
+
+template <typename T>
+static int launch_transposes(const MlpArgsT<T>& P, void* s);
+template <>
+int launch_transposes<float>(const MlpArgsT<float>& P, void* s) {
+  for (int l = 0; l < P.nl; ++l)
+    if (sim_f32::launch_transpose(P.W[l], const_cast<float*>(P.WT[l]), P.dims[l + 1], P.dims[l], s)) return -1;
+  return 0;
+}
+template <>
+int launch_transposes<double>(const MlpArgsT<double>& P, void* s) {
+  for (int l = 0; l < P.nl; ++l)
+    if (sim_f64::launch_transpose(P.W[l], const_cast<double*>(P.WT[l]), P.dims[l + 1], P.dims[l], s)) return -1;
+  return 0;
+}
+
+template <typename T>
+static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
+  const SimOptions& o = h->opt;
+  char* ws = static_cast<char*>(io->workspace);
+  WinArgsT<T> A;
+  std::memset(&A, 0, sizeof(A));
+  A.model = static_cast<const DevModelT<T>*>(h->dev_model);
+  A.N = o.n_envs; A.h = o.horizon; A.k = o.ckpt_interval; A.closed_loop = o.closed_loop;
+  A.gamma = (T)o.gamma;
+  A.scale = (T)(1.0 / ((double)o.n_envs * o.horizon));
+  A.s0 = static_cast<const T*>(io->s0);
+  A.actions_in = static_cast<const T*>(io->actions_in);
+  int rc;
+  if (o.closed_loop) {
+    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, "actor");
+    if (rc) return rc;
+  }
+  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, "critic");
+  if (rc) return rc;
+  A.s_h = static_cast<T*>(io->s_h); A.obs = static_cast<T*>(io->obs); A.actions = static_cast<T*>(io->actions);
+  A.rewards = static_cast<T*>(io->rewards); A.value = static_cast<T*>(io->value);
+  A.nonfinite = io->nonfinite;
+  A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
+  A.seg = reinterpret_cast<T*>(ws + h->off_seg);
+  A.adj = reinterpret_cast<T*>(ws + h->off_adj);
+  int bad = 0;
+  if (o.closed_loop) bad |= launch_transposes(A.actor, stream);
+  bad |= launch_transposes(A.critic, stream);
+  int plain = (o.path == SIM_PATH_PLAIN);
+  if (sizeof(T) == 4)
+    bad |= sim_f32::launch_forward(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, stream);
+  else
+    bad |= sim_f64::launch_forward(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, stream);
+  if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return SIM_OK;
+}
+
+template <typename T>
+static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
+  const SimOptions& o = h->opt;
+  char* ws = static_cast<char*>(io->workspace);
+  WinArgsT<T> A;
+  std::memset(&A, 0, sizeof(A));
+  A.model = static_cast<const DevModelT<T>*>(h->dev_model);
+  A.N = o.n_envs; A.h = o.horizon; A.k = o.ckpt_interval; A.closed_loop = o.closed_loop;
+  A.gamma = (T)o.gamma;
+  A.scale = (T)io->loss_scale;
+  A.s0 = static_cast<const T*>(io->s0);
+  int rc;
+  if (o.closed_loop) {
+    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, "actor");
+    if (rc) return rc;
+  }
+  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, "critic");
+  if (rc) return rc;
+  A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
+  A.seg = reinterpret_cast<T*>(ws + h->off_seg);
+  A.adj = reinterpret_cast<T*>(ws + h->off_adj);
+  A.obs_in = static_cast<const T*>(io->obs);
+  A.actions_fw = static_cast<const T*>(io->actions);
+  A.s_h_in = static_cast<const T*>(io->s_h);
+  A.grad_s_h = static_cast<const T*>(io->grad_s_h);
+  A.dL_da = static_cast<T*>(io->dL_da);
+  A.dL_ds0 = static_cast<T*>(io->dL_ds0);
+  int plain = (o.path == SIM_PATH_PLAIN);
+  int bad;
+  if (sizeof(T) == 4)
+    bad = sim_f32::launch_adjoint(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, stream);
+  else
+    bad = sim_f64::launch_adjoint(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, stream);
+  if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return SIM_OK;
+}
+
+extern "C" int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hip_stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!io) return fail(SIM_E_ARG, "null io");
+  const SimOptions& o = h->opt;
+  if (!io->s0 || !io->s_h || !io->obs || !io->actions || !io->rewards || !io->value)
+    return fail(SIM_E_ARG, "sim_forward_window: null input/output pointer");
+  if (!o.closed_loop && !io->actions_in) return fail(SIM_E_ARG, "open loop needs actions_in");
+  if (!io->workspace || io->workspace_bytes < h->ws_bytes)
+    return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
+  return (o.precision == SIM_PREC_FP64) ? run_forward<double>(h, io, hip_stream) : run_forward<float>(h, io, hip_stream);
+}
+
+extern "C" int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!io) return fail(SIM_E_ARG, "null io");
+  const SimOptions& o = h->opt;
+  if (!io->s0 || !io->actions || !io->obs || !io->s_h || !io->dL_da || !io->dL_ds0)
+    return fail(SIM_E_ARG, "sim_adjoint_window: null input/output pointer");
+  if (!io->workspace || io->workspace_bytes < h->ws_bytes)
+    return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
+  return (o.precision == SIM_PREC_FP64) ? run_adjoint<double>(h, io, hip_stream) : run_adjoint<float>(h, io, hip_stream);
+}

@@ -1,0 +1,688 @@
+// One substep of the articulated-body dynamics and its adjoint, for one environment
+// per wavefront.
+//
+// Forward (Sec. 3.1, Eq. "fwd_dynamics"): forward kinematics and velocities over the
+// tree levels, penalty contact and friction (Sec. 3.1 contact equation), joint limit
+// penalty (Sec. 3.1 limit equation), RNEA bias b(q, qd) with gravity and contact
+// wrenches, CRBA mass matrix, dense Cholesky M = L L^T, qdd = M^{-1}(tau - b) and a
+// semi-implicit Euler step.
+//
+// Adjoint (Sec. 3.1, Eq. "backward"): the integrator is reversed explicitly; the
+// solve is reversed with the cached factor (lambda = M^{-1} qdd_bar, the reuse of the
+// factorisation that Sec. 3.1 describes); the dependence of qdd on (q, qd, a) is taken
+// from the implicit function theorem on ID(q, qd, qdd, a) = M qdd + b - tau = 0, so that
+// x_bar -= d/dx [lambda^T ID] at the solved qdd.  That scalar is sum_b w_b . f_b^net
+// (w_b = virtual body velocities of lambda, f_b^net = Newton-Euler force minus contact
+// wrench) minus the limit and actuation work; its derivatives are evaluated in closed
+// form from subtree sums of spatial vectors (no derivative of M or of the factor).
+
+struct JointRegs {
+  int par, type, qa, va, depth, fc, act, lim;
+  real lo, hi, gear, mass;
+  f3 off, ax, com;
+  real I6[6];
+};
+struct ContactRegs {
+  int body;
+  f3 pos;
+  real rad;
+};
+
+struct EnvLDS {
+  real q[SIM_MAXQ], qd[SIM_MAXV], a[SIM_MAXA];
+  real qn[SIM_MAXQ], qdn[SIM_MAXV];
+  real R[SIM_MAXJ][9], p[SIM_MAXJ][3], S[SIM_MAXJ][6], v[SIM_MAXJ][6], ab[SIM_MAXJ][6];
+  real F[SIM_MAXJ][6];
+  real Ib[SIM_MAXJ][10], Ic[SIM_MAXJ][10];
+  real M[SIM_MAXV][SIM_MAXV + 1];
+  real vec[SIM_MAXV], qdd[SIM_MAXV];
+  real cf[SIM_MAXC][3], cx[SIM_MAXC][3], cvel[SIM_MAXC][3], cdep[SIM_MAXC];
+  real O[4];
+  // adjoint
+  real W[SIM_MAXJ][6], A[SIM_MAXJ][6];
+  real acc[SIM_MAXJ][42];
+  real cAb[SIM_MAXC][6], cVb[SIM_MAXC][6];
+  real qb[SIM_MAXQ], qdb[SIM_MAXV], abar[SIM_MAXA];
+  real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
+  // topology copies for arbitrary-index lookups
+  int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ];
+  // policy / critic
+  real obs[SIM_MAXOBS];
+  real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
+  real red[4];
+};
+
+__device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, EnvLDS& E, int ln,
+                                          JointRegs& jr, ContactRegs& cr) {
+  int j = ln < m->J ? ln : 0;
+  jr.par = m->parent[j]; jr.type = m->jtype[j]; jr.qa = m->qadr[j]; jr.va = m->vadr[j];
+  jr.depth = ln < m->J ? m->depth[j] : -1;
+  jr.fc = m->first_child[j]; jr.act = m->act_of_joint[j]; jr.lim = m->limited[j];
+  jr.lo = m->lower[j]; jr.hi = m->upper[j]; jr.gear = m->gear[j]; jr.mass = m->mass[j];
+  jr.off = ld3(&m->offset[3 * j]); jr.ax = ld3(&m->axis[3 * j]); jr.com = ld3(&m->com[3 * j]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) jr.I6[k] = m->inertia[6 * j + k];
+  int c = ln < m->nc ? ln : 0;
+  cr.body = m->cbody[c]; cr.pos = ld3(&m->cpos[3 * c]); cr.rad = m->crad[c];
+  if (ln < SIM_MAXJ) {
+    E.t_next_sib[ln] = m->next_sib[ln]; E.t_type[ln] = m->jtype[ln];
+    E.t_va[ln] = m->vadr[ln]; E.t_parent[ln] = m->parent[ln];
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------- contact law
+// Normal f_n = (-kn + kd ddot) min(d, 0) (active for d < 0), friction only while d < 0:
+// viscous -kt v_t when kt |v_t| <= mu |f_n| (ties included), else -mu |f_n| v_t / |v_t|.
+// Returns the world force and, if wanted, df/dd (3) and df/dv (3x3 row-major).
+__device__ __forceinline__ f3 contact_force(const DevModel* __restrict__ m, real d, f3 v,
+                                            bool want_d, f3* dfdd, real* dfdv) {
+  f3 f = mk3(RL(0.0), RL(0.0), RL(0.0));
+  if (want_d) {
+    *dfdd = mk3(RL(0.0), RL(0.0), RL(0.0));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dfdv[k] = RL(0.0);
+  }
+  if (!(d < RL(0.0))) return f;
+  real kn = m->kn, kd = m->kd, kt = m->kt, mu = m->mu;
+  real stiff = -kn + kd * v.z;
+  real fn = stiff * d;
+  real vt2 = v.x * v.x + v.y * v.y;
+  real afn = m_fabs(fn);
+  real lim = mu * afn;
+  f.z = fn;
+  bool viscous = kt * kt * vt2 <= lim * lim;
+  if (viscous) {
+    f.x = -kt * v.x;
+    f.y = -kt * v.y;
+  } else {
+    real vn = m_sqrt(vt2);
+    real s = lim / vn;
+    f.x = -s * v.x;
+    f.y = -s * v.y;
+  }
+  if (want_d) {
+    // d fn / d d = stiff, d fn / d vz = kd d
+    dfdd->z = stiff;
+    dfdv[8] = kd * d;
+    if (viscous) {
+      dfdv[0] = -kt;
+      dfdv[4] = -kt;
+    } else {
+      real vn = m_sqrt(vt2);
+      real tx = v.x / vn, ty = v.y / vn;
+      real sg = fn > RL(0.0) ? RL(1.0) : (fn < RL(0.0) ? -RL(1.0) : RL(0.0));
+      real dft_dfn_x = -mu * sg * tx, dft_dfn_y = -mu * sg * ty;
+      dfdd->x = dft_dfn_x * stiff;
+      dfdd->y = dft_dfn_y * stiff;
+      dfdv[2] = dft_dfn_x * kd * d;
+      dfdv[5] = dft_dfn_y * kd * d;
+      real c = -lim / vn;
+      dfdv[0] = c * (RL(1.0) - tx * tx);
+      dfdv[1] = c * (-tx * ty);
+      dfdv[3] = c * (-ty * tx);
+      dfdv[4] = c * (RL(1.0) - ty * ty);
+    }
+  }
+  return f;
+}
+
+// rotation matrix of the normalised quaternion (w, x, y, z)
+__device__ __forceinline__ void quat_rot(real w, real x, real y, real z, real* R) {
+  real n2 = w * w + x * x + y * y + z * z;
+  real s = RL(2.0) / n2;
+  R[0] = RL(1.0) - s * (y * y + z * z); R[1] = s * (x * y - w * z);       R[2] = s * (x * z + w * y);
+  R[3] = s * (x * y + w * z);       R[4] = RL(1.0) - s * (x * x + z * z); R[5] = s * (y * z - w * x);
+  R[6] = s * (x * z - w * y);       R[7] = s * (y * z + w * x);       R[8] = RL(1.0) - s * (x * x + y * y);
+}
+
+// coefficients of the half-angle exponential exp((dt/2) w): c(u), s(u) with u = |w|^2,
+// and their derivatives in u
+__device__ __forceinline__ void dq_coeffs(real u, real hh, real& c, real& s, real& dc, real& ds) {
+  real x2 = u * hh * hh;
+  if (x2 < RL(1e-2)) {
+    c = RL(1.0) - x2 * (RL(0.5) - x2 * (RL(1.0) / RL(24.0) - x2 * (RL(1.0) / RL(720.0))));
+    s = hh * (RL(1.0) - x2 * (RL(1.0) / RL(6.0) - x2 * (RL(1.0) / RL(120.0) - x2 * (RL(1.0) / RL(5040.0)))));
+    ds = hh * hh * hh * (-RL(1.0) / RL(6.0) + x2 * (RL(2.0) / RL(120.0) - x2 * (RL(3.0) / RL(5040.0))));
+  } else {
+    real n = m_sqrt(u);
+    real sn, cs;
+    m_sincos(n * hh, &sn, &cs);
+    c = cs;
+    s = sn / n;
+    ds = (hh * c - s) / (RL(2.0) * u);
+  }
+  dc = -RL(0.5) * hh * s;
+}
+
+// --------------------------------------------------------------- dense Cholesky (row per lane)
+// On entry Lrow[k] = M[ln][k].  On exit Lrow[k] = L[ln][k] for k <= ln.
+template <int NV>
+__device__ __forceinline__ void chol_factor(real (&Lrow)[SIM_MAXV], int nv, int ln, real& minpiv) {
+  minpiv = RL(3.0e38);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nv) {
+      real piv = rdl(Lrow[k], k);
+      minpiv = m_fmin(minpiv, piv);
+      real d = m_sqrt(piv);
+      real inv = RL(1.0) / d;
+      real lk = (ln == k) ? d : Lrow[k] * inv;
+      Lrow[k] = lk;
+#pragma unroll
+      for (int j = k + 1; j < NV; ++j) {
+        if (j < nv) {
+          real ljk = rdl(lk, j);
+          Lrow[j] = m_fma(-lk, ljk, Lrow[j]);
+        }
+      }
+    }
+  }
+}
+
+// solve L L^T x = b for b given in lane ln (row ln); Lcol[k] = L[k][ln]
+template <int NV>
+__device__ __forceinline__ real chol_solve(const real (&Lrow)[SIM_MAXV], const real (&Lcol)[SIM_MAXV],
+                                            int nv, int ln, real b) {
+  real y = b;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nv) {
+      real yk = rdl(y, k) / rdl(Lrow[k], k);
+      y = (ln == k) ? yk : (ln > k ? m_fma(-Lrow[k], yk, y) : y);
+    }
+  }
+#pragma unroll
+  for (int k = NV - 1; k >= 0; --k) {
+    if (k < nv) {
+      real xk = rdl(y, k) / rdl(Lrow[k], k);
+      y = (ln == k) ? xk : (ln < k ? m_fma(-Lcol[k], xk, y) : y);
+    }
+  }
+  return y;
+}
+
+// --------------------------------------------------------------- forward substep
+// Uses E.q, E.qd, E.a.  Writes all intermediates to E and the new state to E.qn/E.qdn
+// (and back to E.q/E.qd when inplace).  Lrow/Lcol keep the Cholesky factor.
+__device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, EnvLDS& E,
+                                                const JointRegs& jr, const ContactRegs& cr, int ln,
+                                                real (&Lrow)[SIM_MAXV], real (&Lcol)[SIM_MAXV],
+                                                bool inplace, real& minpiv) {
+  const int J = m->J, nv = m->nv, nc = m->nc;
+  const real g = m->g;
+  const real dt = m->dt_sub;
+  // reference point O = root position (floating) or world origin
+  if (ln < 3) E.O[ln] = m->floating ? E.q[ln] : RL(0.0);
+  // clear M
+  for (int i = ln; i < SIM_MAXV * (SIM_MAXV + 1); i += SIM_WAVE) (&E.M[0][0])[i] = RL(0.0);
+  __syncthreads();
+  // ---- kinematics, velocities, bias accelerations, level by level
+  for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
+    if (jr.depth == lvl) {
+      real Rp[9];
+      f3 pp;
+      sv vp, ap;
+      if (jr.par >= 0) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rp[k] = E.R[jr.par][k];
+        pp = ld3(E.p[jr.par]);
+        vp = ldsv(E.v[jr.par]);
+        ap = ldsv(E.ab[jr.par]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? RL(1.0) : RL(0.0);
+        pp = mk3(RL(0.0), RL(0.0), RL(0.0));
+        vp = zsv();
+        ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+      }
+      real R[9];
+      f3 p;
+      sv S = zsv(), v, ab;
+      if (jr.type == J_FREE) {
+        quat_rot(E.q[jr.qa + 3], E.q[jr.qa + 4], E.q[jr.qa + 5], E.q[jr.qa + 6], R);
+        p = mk3(RL(0.0), RL(0.0), RL(0.0));
+        f3 vl = mk3(E.qd[jr.va], E.qd[jr.va + 1], E.qd[jr.va + 2]);
+        f3 w = mk3(E.qd[jr.va + 3], E.qd[jr.va + 4], E.qd[jr.va + 5]);
+        v = mksv(w, vl);
+        ab = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), add3(mk3(RL(0.0), RL(0.0), g), cross3(vl, w)));
+      } else {
+        real qj = E.q[jr.qa];
+        f3 sh = mv3(Rp, jr.ax);
+        if (jr.type == J_HINGE) {
+          real sn, cs;
+          m_sincos(qj, &sn, &cs);
+          real omc = RL(1.0) - cs;
+          f3 a = jr.ax;
+          // Rodrigues: Rot = I + sn K + (1 - cs) K^2 with K = [a]x, K^2 = a a^T - I
+          real Rot[9];
+          Rot[0] = RL(1.0) + omc * (a.x * a.x - RL(1.0)); Rot[1] = -sn * a.z + omc * a.x * a.y; Rot[2] = sn * a.y + omc * a.x * a.z;
+          Rot[3] = sn * a.z + omc * a.y * a.x; Rot[4] = RL(1.0) + omc * (a.y * a.y - RL(1.0)); Rot[5] = -sn * a.x + omc * a.y * a.z;
+          Rot[6] = -sn * a.y + omc * a.z * a.x; Rot[7] = sn * a.x + omc * a.z * a.y; Rot[8] = RL(1.0) + omc * (a.z * a.z - RL(1.0));
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              R[3 * r + c] = Rp[3 * r] * Rot[c] + Rp[3 * r + 1] * Rot[3 + c] + Rp[3 * r + 2] * Rot[6 + c];
+          p = add3(pp, mv3(Rp, jr.off));
+          S = mksv(sh, cross3(p, sh));
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) R[k] = Rp[k];
+          p = add3(add3(pp, mv3(Rp, jr.off)), scl3(sh, qj));
+          S = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
+        }
+        real qdj = E.qd[jr.va];
+        sv u = sclsv(S, qdj);
+        v = addsv(vp, u);
+        ab = addsv(ap, crm(v, u));
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) E.R[ln][k] = R[k];
+      st3(E.p[ln], p);
+      stsv(E.S[ln], S);
+      stsv(E.v[ln], v);
+      stsv(E.ab[ln], ab);
+    }
+    __syncthreads();
+  }
+  // ---- contacts (lane = contact)
+  if (ln < nc) {
+    int b = cr.body;
+    f3 xc = add3(ld3(E.p[b]), mv3(E.R[b], cr.pos));
+    f3 xp = mk3(xc.x, xc.y, xc.z - cr.rad);
+    real d = xc.z + E.O[2] - cr.rad;
+    f3 vpt = ptv(ldsv(E.v[b]), xp);
+    f3 dd;
+    real dv[9];
+    f3 f = contact_force(m, d, vpt, false, &dd, dv);
+    st3(E.cf[ln], f);
+    st3(E.cx[ln], xp);
+    st3(E.cvel[ln], vpt);
+    E.cdep[ln] = d;
+  }
+  __syncthreads();
+  // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
+  if (ln < J) {
+    real* R = E.R[ln];
+    f3 p = ld3(E.p[ln]);
+    real mass = jr.mass;
+    f3 c = add3(p, mv3(R, jr.com));
+    // Ic_w = R I R^T
+    const real* I6 = jr.I6;
+    real Il[9] = {I6[0], I6[3], I6[4], I6[3], I6[1], I6[5], I6[4], I6[5], I6[2]};
+    real T[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) T[3 * r + k] = R[3 * r] * Il[k] + R[3 * r + 1] * Il[3 + k] + R[3 * r + 2] * Il[6 + k];
+    real Iw[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Iw[3 * r + k] = T[3 * r] * R[3 * k] + T[3 * r + 1] * R[3 * k + 1] + T[3 * r + 2] * R[3 * k + 2];
+    real cc = dot3(c, c);
+    real Ib[10];
+    Ib[0] = mass;
+    Ib[1] = mass * c.x; Ib[2] = mass * c.y; Ib[3] = mass * c.z;
+    Ib[4] = Iw[0] + mass * (cc - c.x * c.x);
+    Ib[5] = Iw[4] + mass * (cc - c.y * c.y);
+    Ib[6] = Iw[8] + mass * (cc - c.z * c.z);
+    Ib[7] = Iw[1] - mass * c.x * c.y;
+    Ib[8] = Iw[2] - mass * c.x * c.z;
+    Ib[9] = Iw[5] - mass * c.y * c.z;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) { E.Ib[ln][k] = Ib[k]; E.Ic[ln][k] = Ib[k]; }
+    sv v = ldsv(E.v[ln]);
+    sv hv = iapply(Ib, v);
+    sv f = addsv(iapply(Ib, ldsv(E.ab[ln])), crf(v, hv));
+    for (int ci = 0; ci < nc; ++ci) {
+      if (m->cbody[ci] == ln) f = subsv(f, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
+    }
+    stsv(E.F[ln], f);
+    // joint torques: actuation + limit penalty
+    if (jr.type != J_FREE) {
+      real tau = RL(0.0);
+      if (jr.act >= 0) tau = jr.gear * E.a[jr.act];
+      if (jr.lim) {
+        real qj = E.q[jr.qa];
+        if (qj < jr.lo) tau += m->klim * (jr.lo - qj);
+        else if (qj > jr.hi) tau += m->klim * (jr.hi - qj);
+      }
+      E.vec[jr.va] = tau;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) E.vec[jr.va + k] = RL(0.0);
+    }
+  }
+  __syncthreads();
+  // ---- subtree sums of forces and composite inertias, deepest level first
+  for (int lvl = m->max_depth - 1; lvl >= 0; --lvl) {
+    if (jr.depth == lvl && jr.fc >= 0) {
+      sv f = ldsv(E.F[ln]);
+      real Ic[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Ic[k] = E.Ic[ln][k];
+      for (int ch = jr.fc; ch >= 0; ch = E.t_next_sib[ch]) {
+        f = addsv(f, ldsv(E.F[ch]));
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Ic[k] += E.Ic[ch][k];
+      }
+      stsv(E.F[ln], f);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) E.Ic[ln][k] = Ic[k];
+    }
+    __syncthreads();
+  }
+  // ---- bias into rhs, CRBA entries (lane = joint)
+  if (ln < J) {
+    sv F = ldsv(E.F[ln]);
+    const real* Ic = E.Ic[ln];
+    if (jr.type == J_FREE) {
+      int va = jr.va;
+      E.vec[va + 0] -= F.l.x; E.vec[va + 1] -= F.l.y; E.vec[va + 2] -= F.l.z;
+      E.vec[va + 3] -= F.a.x; E.vec[va + 4] -= F.a.y; E.vec[va + 5] -= F.a.z;
+      real m0 = Ic[0];
+      f3 h = mk3(Ic[1], Ic[2], Ic[3]);
+      real Ibar[9] = {Ic[4], Ic[7], Ic[8], Ic[7], Ic[5], Ic[9], Ic[8], Ic[9], Ic[6]};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+#pragma unroll
+        for (int f2 = 0; f2 < 3; ++f2) {
+          E.M[va + e][va + f2] = (e == f2) ? m0 : RL(0.0);
+          E.M[va + 3 + e][va + 3 + f2] = Ibar[3 * e + f2];
+        }
+      }
+      // M[v_e][w_f] = (e_f x h)_e
+      f3 ex = cross3(mk3(1, 0, 0), h), ey = cross3(mk3(0, 1, 0), h), ez = cross3(mk3(0, 0, 1), h);
+      real C[9] = {ex.x, ey.x, ez.x, ex.y, ey.y, ez.y, ex.z, ey.z, ez.z};
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int f2 = 0; f2 < 3; ++f2) {
+          E.M[va + e][va + 3 + f2] = C[3 * e + f2];
+          E.M[va + 3 + f2][va + e] = C[3 * e + f2];
+        }
+    } else {
+      sv S = ldsv(E.S[ln]);
+      E.vec[jr.va] -= dotsv(S, F);
+      sv Fi = iapply(Ic, S);
+      int i = jr.va;
+      E.M[i][i] = dotsv(S, Fi) + m->armature[i];
+      int k = jr.par;
+      while (k >= 0) {
+        int tk = E.t_type[k], vk = E.t_va[k];
+        if (tk == J_FREE) {
+          E.M[vk + 0][i] = Fi.l.x; E.M[vk + 1][i] = Fi.l.y; E.M[vk + 2][i] = Fi.l.z;
+          E.M[vk + 3][i] = Fi.a.x; E.M[vk + 4][i] = Fi.a.y; E.M[vk + 5][i] = Fi.a.z;
+          E.M[i][vk + 0] = Fi.l.x; E.M[i][vk + 1] = Fi.l.y; E.M[i][vk + 2] = Fi.l.z;
+          E.M[i][vk + 3] = Fi.a.x; E.M[i][vk + 4] = Fi.a.y; E.M[i][vk + 5] = Fi.a.z;
+        } else {
+          real mk = dotsv(ldsv(E.S[k]), Fi);
+          E.M[vk][i] = mk;
+          E.M[i][vk] = mk;
+        }
+        k = E.t_parent[k];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- Cholesky and solve (lane = DOF)
+#pragma unroll
+  for (int k = 0; k < SIM_MAXV; ++k) Lrow[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : RL(0.0);
+  if (ln >= nv) Lrow[0] = RL(0.0);
+  chol_factor<SIM_MAXV>(Lrow, nv, ln, minpiv);
+  __syncthreads();
+  if (ln < nv) {
+#pragma unroll
+    for (int k = 0; k < SIM_MAXV; ++k) E.M[ln][k] = Lrow[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SIM_MAXV; ++k) Lcol[k] = (ln < nv && k < nv) ? E.M[k][ln < nv ? ln : 0] : RL(0.0);
+  real b = ln < nv ? E.vec[ln] : RL(0.0);
+  real x = chol_solve<SIM_MAXV>(Lrow, Lcol, nv, ln, b);
+  if (ln < nv) {
+    E.qdd[ln] = x;
+    real qdn = E.qd[ln] + dt * x;
+    E.qdn[ln] = qdn;
+  }
+  __syncthreads();
+  // ---- positions with the new velocities (lane = joint)
+  if (ln < J) {
+    if (jr.type == J_FREE) {
+      int qa = jr.qa, va = jr.va;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) E.qn[qa + k] = E.q[qa + k] + dt * E.qdn[va + k];
+      f3 w = mk3(E.qdn[va + 3], E.qdn[va + 4], E.qdn[va + 5]);
+      real c, s, dc, ds;
+      dq_coeffs(dot3(w, w), RL(0.5) * dt, c, s, dc, ds);
+      real a0 = c, a1 = s * w.x, a2 = s * w.y, a3 = s * w.z;
+      real b0 = E.q[qa + 3], b1 = E.q[qa + 4], b2 = E.q[qa + 5], b3 = E.q[qa + 6];
+      E.qn[qa + 3] = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
+      E.qn[qa + 4] = a0 * b1 + a1 * b0 + a2 * b3 - a3 * b2;
+      E.qn[qa + 5] = a0 * b2 - a1 * b3 + a2 * b0 + a3 * b1;
+      E.qn[qa + 6] = a0 * b3 + a1 * b2 - a2 * b1 + a3 * b0;
+    } else {
+      E.qn[jr.qa] = E.q[jr.qa] + dt * E.qdn[jr.va];
+    }
+  }
+  __syncthreads();
+  if (inplace) {
+    if (ln < m->nq) E.q[ln] = E.qn[ln];
+    if (ln < nv) E.qd[ln] = E.qdn[ln];
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- adjoint of one substep
+// On entry E.q/E.qd/E.a hold the pre-substep state, E.qb/E.qdb the adjoint of the
+// post-substep state.  On exit E.qb/E.qdb hold the adjoint of the pre-substep state and
+// E.abar has gained this substep's contribution.
+__device__ __forceinline__ void substep_adjoint(const DevModel* __restrict__ m, EnvLDS& E,
+                                                const JointRegs& jr, const ContactRegs& cr, int ln) {
+  real Lrow[SIM_MAXV], Lcol[SIM_MAXV];
+  real minpiv;
+  substep_forward(m, E, jr, cr, ln, Lrow, Lcol, false, minpiv);
+  const int J = m->J, nv = m->nv, nc = m->nc;
+  const real dt = m->dt_sub;
+  const real g = m->g;
+  // ---- integrator reverse (lane = joint)
+  if (ln < J) {
+    if (jr.type == J_FREE) {
+      int qa = jr.qa, va = jr.va;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) E.qdb[va + k] += dt * E.qb[qa + k];
+      f3 w = mk3(E.qdn[va + 3], E.qdn[va + 4], E.qdn[va + 5]);
+      real c, s, dc, ds;
+      dq_coeffs(dot3(w, w), RL(0.5) * dt, c, s, dc, ds);
+      real d0 = c, d1 = s * w.x, d2 = s * w.y, d3 = s * w.z;
+      real b0 = E.q[qa + 3], b1 = E.q[qa + 4], b2 = E.q[qa + 5], b3 = E.q[qa + 6];
+      real g0 = E.qb[qa + 3], g1 = E.qb[qa + 4], g2 = E.qb[qa + 5], g3 = E.qb[qa + 6];
+      // quat' = L(dq) quat  ->  quat_bar = L(dq)^T quat'_bar
+      real q0 = d0 * g0 + d1 * g1 + d2 * g2 + d3 * g3;
+      real q1 = -d1 * g0 + d0 * g1 + d3 * g2 - d2 * g3;
+      real q2 = -d2 * g0 - d3 * g1 + d0 * g2 + d1 * g3;
+      real q3 = -d3 * g0 + d2 * g1 - d1 * g2 + d0 * g3;
+      // quat' = Rm(quat) dq  ->  dq_bar = Rm(quat)^T quat'_bar
+      real e0 = b0 * g0 + b1 * g1 + b2 * g2 + b3 * g3;
+      real e1 = -b1 * g0 + b0 * g1 - b3 * g2 + b2 * g3;
+      real e2 = -b2 * g0 + b3 * g1 + b0 * g2 - b1 * g3;
+      real e3 = -b3 * g0 - b2 * g1 + b1 * g2 + b0 * g3;
+      f3 ev = mk3(e1, e2, e3);
+      f3 wbar = add3(add3(scl3(w, RL(2.0) * dc * e0), scl3(ev, s)), scl3(w, RL(2.0) * ds * dot3(w, ev)));
+      E.qdb[va + 3] += wbar.x; E.qdb[va + 4] += wbar.y; E.qdb[va + 5] += wbar.z;
+      E.qb[qa + 3] = q0; E.qb[qa + 4] = q1; E.qb[qa + 5] = q2; E.qb[qa + 6] = q3;
+    } else {
+      E.qdb[jr.va] += dt * E.qb[jr.qa];
+    }
+  }
+  __syncthreads();
+  // ---- lambda = M^{-1} qdd_bar with the cached factor (lane = DOF)
+  {
+    real rb = ln < nv ? dt * E.qdb[ln] : RL(0.0);
+    real lam = chol_solve<SIM_MAXV>(Lrow, Lcol, nv, ln, rb);
+    if (ln < nv) E.lam[ln] = lam;
+  }
+  __syncthreads();
+  // actuation adjoint and full accelerations / virtual velocities, level by level
+  if (ln < J && jr.act >= 0) E.abar[jr.act] += jr.gear * E.lam[jr.va];
+  for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
+    if (jr.depth == lvl) {
+      sv Ap, Wp;
+      if (jr.par >= 0) {
+        Ap = ldsv(E.A[jr.par]);
+        Wp = ldsv(E.W[jr.par]);
+      } else {
+        Ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+        Wp = zsv();
+      }
+      sv A, W;
+      if (jr.type == J_FREE) {
+        int va = jr.va;
+        sv ab = ldsv(E.ab[ln]);
+        A = addsv(ab, mksv(mk3(E.qdd[va + 3], E.qdd[va + 4], E.qdd[va + 5]),
+                           mk3(E.qdd[va], E.qdd[va + 1], E.qdd[va + 2])));
+        W = mksv(mk3(E.lam[va + 3], E.lam[va + 4], E.lam[va + 5]), mk3(E.lam[va], E.lam[va + 1], E.lam[va + 2]));
+      } else {
+        sv S = ldsv(E.S[ln]);
+        sv v = ldsv(E.v[ln]);
+        sv u = sclsv(S, E.qd[jr.va]);
+        A = addsv(addsv(Ap, sclsv(S, E.qdd[jr.va])), crm(v, u));
+        W = addsv(Wp, sclsv(S, E.lam[jr.va]));
+      }
+      stsv(E.A[ln], A);
+      stsv(E.W[ln], W);
+    }
+    __syncthreads();
+  }
+  // ---- contact adjoints (lane = contact)
+  if (ln < nc) {
+    int b = cr.body;
+    f3 x = ld3(E.cx[ln]);
+    f3 vpt = ld3(E.cvel[ln]);
+    f3 f = ld3(E.cf[ln]);
+    sv Wb = ldsv(E.W[b]);
+    sv vb = ldsv(E.v[b]);
+    f3 nu = ptv(Wb, x);
+    f3 dfdd;
+    real dfdv[9];
+    contact_force(m, E.cdep[ln], vpt, true, &dfdd, dfdv);
+    f3 fbar = scl3(nu, -RL(1.0));
+    f3 xbar = mk3(RL(0.0), RL(0.0), dot3(dfdd, fbar));
+    f3 vbar = mk3(dfdv[0] * fbar.x + dfdv[3] * fbar.y + dfdv[6] * fbar.z,
+                  dfdv[1] * fbar.x + dfdv[4] * fbar.y + dfdv[7] * fbar.z,
+                  dfdv[2] * fbar.x + dfdv[5] * fbar.y + dfdv[8] * fbar.z);
+    f3 r = mk3(RL(0.0), RL(0.0), cr.rad);
+    f3 extra = cross3(r, sub3(add3(xbar, cross3(vbar, vb.a)), cross3(f, Wb.a)));
+    sv ab = addsv(spf(x, xbar), mksv(add3(add3(scl3(cross3(nu, f), -RL(1.0)), cross3(vpt, vbar)), extra),
+                                    mk3(RL(0.0), RL(0.0), RL(0.0))));
+    stsv(E.cAb[ln], ab);
+    stsv(E.cVb[ln], spf(x, vbar));
+  }
+  __syncthreads();
+  // ---- per-body terms (lane = joint): P Q R T Fn Ab Vb
+  if (ln < J) {
+    const real* Ib = E.Ib[ln];
+    sv v = ldsv(E.v[ln]), W = ldsv(E.W[ln]), A = ldsv(E.A[ln]);
+    sv Iw = iapply(Ib, W);
+    sv hv = iapply(Ib, v);
+    sv Q = crf(v, Iw);
+    sv Rr = crf(W, hv);
+    sv T = iapply(Ib, crm(v, W));
+    sv Fn = addsv(iapply(Ib, A), crf(v, hv));
+    sv Ab = zsv(), Vb = zsv();
+    for (int ci = 0; ci < nc; ++ci) {
+      if (m->cbody[ci] == ln) {
+        Fn = subsv(Fn, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
+        Ab = addsv(Ab, ldsv(E.cAb[ci]));
+        Vb = addsv(Vb, ldsv(E.cVb[ci]));
+      }
+    }
+    real* o = E.acc[ln];
+    stsv(o + 0, Iw); stsv(o + 6, Q); stsv(o + 12, Rr); stsv(o + 18, T);
+    stsv(o + 24, Fn); stsv(o + 30, Ab); stsv(o + 36, Vb);
+  }
+  __syncthreads();
+  for (int lvl = m->max_depth - 1; lvl >= 0; --lvl) {
+    if (jr.depth == lvl && jr.fc >= 0) {
+      real s[42];
+#pragma unroll
+      for (int k = 0; k < 42; ++k) s[k] = E.acc[ln][k];
+      for (int ch = jr.fc; ch >= 0; ch = E.t_next_sib[ch]) {
+#pragma unroll
+        for (int k = 0; k < 42; ++k) s[k] += E.acc[ch][k];
+      }
+#pragma unroll
+      for (int k = 0; k < 42; ++k) E.acc[ln][k] = s[k];
+    }
+    __syncthreads();
+  }
+  // ---- derivatives of lambda^T ID per joint (lane = joint)
+  if (ln < J) {
+    const real* o = E.acc[ln];
+    sv P = ldsv(o + 0), Q = ldsv(o + 6), Rr = ldsv(o + 12), T = ldsv(o + 18);
+    sv Fn = ldsv(o + 24), Ab = ldsv(o + 30), Vb = ldsv(o + 36);
+    sv QRT = subsv(subsv(Q, Rr), T);
+    if (jr.type == J_FREE) {
+      int va = jr.va;
+      sv vA = ldsv(E.v[ln]), wA = ldsv(E.W[ln]), aA = ldsv(E.A[ln]);
+      f3 vl = mk3(E.qd[va], E.qd[va + 1], E.qd[va + 2]);
+      f3 w = mk3(E.qd[va + 3], E.qd[va + 4], E.qd[va + 5]);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        f3 ue = mk3(e == 0 ? RL(1.0) : RL(0.0), e == 1 ? RL(1.0) : RL(0.0), e == 2 ? RL(1.0) : RL(0.0));
+        sv Te = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), ue);
+        sv Se = mksv(ue, mk3(RL(0.0), RL(0.0), RL(0.0)));
+        E.dPq[va + e] = dotsv(Te, Ab);
+        sv ee = crm(Se, vA);
+        E.dPq[va + 3 + e] = -dotsv(crm(Se, wA), Fn) - dotsv(crm(Se, aA), P) - dotsv(ee, Q) +
+                            dotsv(crm(ee, vA), P) + dotsv(ee, Rr) + dotsv(ee, T) + dotsv(Se, Ab) - dotsv(ee, Vb);
+        sv daT = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), cross3(ue, w));
+        sv daS = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), cross3(vl, ue));
+        E.dPqd[va + e] = dotsv(Te, QRT) - dotsv(crm(Te, vA), P) + dotsv(daT, P) + dotsv(Te, Vb);
+        E.dPqd[va + 3 + e] = dotsv(Se, QRT) - dotsv(crm(Se, vA), P) + dotsv(daS, P) + dotsv(Se, Vb);
+      }
+    } else {
+      sv S = ldsv(E.S[ln]);
+      sv vA, wA, aA;
+      if (jr.par >= 0) {
+        vA = ldsv(E.v[jr.par]); wA = ldsv(E.W[jr.par]); aA = ldsv(E.A[jr.par]);
+      } else {
+        vA = zsv(); wA = zsv(); aA = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+      }
+      sv ee = crm(S, vA);
+      real val = -dotsv(crm(S, wA), Fn) - dotsv(crm(S, aA), P) - dotsv(ee, Q) + dotsv(crm(ee, vA), P) +
+                  dotsv(ee, Rr) + dotsv(ee, T) + dotsv(S, Ab) - dotsv(ee, Vb);
+      if (jr.lim) {
+        real qj = E.q[jr.qa];
+        if (qj < jr.lo || qj > jr.hi) val += E.lam[jr.va] * m->klim;
+      }
+      E.dPq[jr.va] = val;
+      E.dPqd[jr.va] = dotsv(S, QRT) - RL(2.0) * dotsv(ee, P) + dotsv(S, Vb);
+    }
+  }
+  __syncthreads();
+  // ---- adjoint of the pre-substep state
+  if (ln < nv) E.qdb[ln] -= E.dPqd[ln];
+  if (ln < J) {
+    if (jr.type == J_FREE) {
+      int qa = jr.qa, va = jr.va;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) E.qb[qa + k] -= E.dPq[va + k];
+      f3 tr = mk3(E.dPq[va + 3], E.dPq[va + 4], E.dPq[va + 5]);
+      real q0 = E.q[qa + 3], q1 = E.q[qa + 4], q2 = E.q[qa + 5], q3 = E.q[qa + 6];
+      real nrm = m_sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+      real in = RL(1.0) / nrm;
+      real w0 = q0 * in;
+      f3 vv = mk3(q1 * in, q2 * in, q3 * in);
+      // d/dquat = (1/|q|) J(qhat)^T tau,  J = 2 [-v | w I + [v]x]
+      E.qb[qa + 3] -= in * (-RL(2.0) * dot3(vv, tr));
+      f3 gv = scl3(sub3(scl3(tr, w0), cross3(vv, tr)), RL(2.0) * in);
+      E.qb[qa + 4] -= gv.x; E.qb[qa + 5] -= gv.y; E.qb[qa + 6] -= gv.z;
+    } else {
+      E.qb[jr.qa] -= E.dPq[jr.va];
+    }
+  }
+  __syncthreads();
+}

@@ -1,0 +1,371 @@
+// Window kernels (persistent and plain per-step paths) and their launchers, for one
+// arithmetic type.  Included inside the namespace of kernels_f32.hip / kernels_f64.hip.
+
+// ======================================================================= device helpers
+__device__ __forceinline__ bool all_finite_wave(bool ok) {
+  return __all(ok);
+}
+
+__device__ __forceinline__ void load_state(const DevModel* __restrict__ m, EnvLDS& E, const real* s, int ln) {
+  int nq = m->nq, nv = m->nv;
+  for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = s[i];
+  for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = s[nq + i];
+  if (m->has_last_action)
+    for (int i = ln; i < m->na; i += SIM_WAVE) E.a[i] = s[nq + nv + i];
+  else
+    for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.a[i] = RL(0.0);
+  __syncthreads();
+}
+
+__device__ __forceinline__ void store_qqd(const DevModel* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
+  int nq = m->nq, nv = m->nv;
+  for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.q[i];
+  for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qd[i];
+}
+
+__device__ __forceinline__ void load_qqd(const DevModel* __restrict__ m, EnvLDS& E, const real* src, int ln) {
+  int nq = m->nq, nv = m->nv;
+  for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = src[i];
+  for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = src[nq + i];
+  __syncthreads();
+}
+
+// observation, action and reward at the start of frame t (state in E.q/E.qd, previous
+// action in E.a); leaves a_t in E.a.
+__device__ __forceinline__ void frame_begin(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+                                            int env, int t, int ln) {
+  const int N = A.N, od = m->od, na = m->na;
+  task_obs(m, E.q, E.qd, E.a, E.obs, ln);
+  real* ob = A.obs + ((size_t)t * N + env) * od;
+  for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
+  if (A.closed_loop) {
+    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, ln);
+    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = m_tanh(E.y[i]);
+  } else {
+    const real* ai = A.actions_in + ((size_t)t * N + env) * na;
+    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = ai[i];
+  }
+  __syncthreads();
+  real r = task_reward(m, E.q, E.qd, E.a, ln);
+  if (ln == 0) A.rewards[(size_t)t * N + env] = r;
+  real* ao = A.actions + ((size_t)t * N + env) * na;
+  for (int i = ln; i < na; i += SIM_WAVE) ao[i] = E.a[i];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void window_end(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+                                           int env, int ln) {
+  const int N = A.N, od = m->od, ns = m->ns, nq = m->nq, nv = m->nv, na = m->na;
+  task_obs(m, E.q, E.qd, E.a, E.obs, ln);
+  real* ob = A.obs + ((size_t)A.h * N + env) * od;
+  for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
+  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, ln);
+  if (ln == 0) A.value[env] = E.y[0];
+  real* so = A.s_h + (size_t)env * ns;
+  bool ok = true;
+  for (int i = ln; i < nq; i += SIM_WAVE) { so[i] = E.q[i]; ok = ok && m_isfinite(E.q[i]); }
+  for (int i = ln; i < nv; i += SIM_WAVE) { so[nq + i] = E.qd[i]; ok = ok && m_isfinite(E.qd[i]); }
+  if (m->has_last_action)
+    for (int i = ln; i < na; i += SIM_WAVE) so[nq + nv + i] = E.a[i];
+  bool all = all_finite_wave(ok);
+  if (ln == 0 && A.nonfinite) A.nonfinite[env] = all ? 0 : 1;
+}
+
+// ======================================================================= persistent forward
+__global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int S = m->substeps, nqv = m->nq + m->nv, N = A.N;
+  load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
+  real Lrow[SIM_MAXV], Lcol[SIM_MAXV];
+  for (int t = 0; t < A.h; ++t) {
+    frame_begin(A, m, E, env, t, ln);
+    for (int sub = 0; sub < S; ++sub) {
+      int gi = t * S + sub;
+      if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
+      real minpiv;
+      substep_forward(m, E, jr, cr, ln, Lrow, Lcol, true, minpiv);
+    }
+  }
+  window_end(A, m, E, env, ln);
+}
+
+// ======================================================================= persistent adjoint
+// terminal seed: s_bar(h) = -gamma^h scale (d obs/d s)^T dV/d obs  (+ optional upstream)
+__device__ __forceinline__ void adjoint_seed(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+                                             int env, int ln) {
+  const int ns = m->ns, nq = m->nq, nv = m->nv, na = m->na, od = m->od;
+  const real* sh = A.s_h_in + (size_t)env * ns;
+  load_state(m, E, sh, ln);
+  for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = RL(0.0);
+  for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = RL(0.0);
+  for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+  for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
+  __syncthreads();
+  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, ln);
+  real c = -m_pow(A.gamma, (real)A.h) * A.scale;
+  if (ln == 0) E.y[0] = c;
+  __syncthreads();
+  mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, ln);
+  // E.obs now holds obs_bar; E.a holds a_prev of s_h
+  task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, ln);
+  if (A.grad_s_h) {
+    const real* gs = A.grad_s_h + (size_t)env * ns;
+    for (int i = ln; i < nq; i += SIM_WAVE) E.qb[i] += gs[i];
+    for (int i = ln; i < nv; i += SIM_WAVE) E.qdb[i] += gs[nq + i];
+    if (m->has_last_action)
+      for (int i = ln; i < na; i += SIM_WAVE) E.abar[i] += gs[nq + nv + i];
+  }
+  __syncthreads();
+}
+
+// frame-level reverse at frame t: E.qb/E.qdb hold the adjoint of the frame-start (q, qd)
+// through the dynamics; E.abar holds dL/da_t except the reward term.
+__device__ __forceinline__ void adjoint_frame(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+                                              int env, int t, int ln) {
+  const int N = A.N, nq = m->nq, nv = m->nv, na = m->na, od = m->od, ns = m->ns, S = m->substeps;
+  const int nqv = nq + nv;
+  // frame-start state and a_t
+  load_qqd(m, E, A.ckpt + ((size_t)(t * S / A.k) * N + env) * nqv, ln);
+  const real* at = A.actions_fw + ((size_t)t * N + env) * na;
+  for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+  __syncthreads();
+  real c = -m_pow(A.gamma, (real)t) * A.scale;
+  task_reward_vjp(m, E.q, E.qd, E.a, c, E.qb, E.qdb, E.abar, ln);
+  real* da = A.dL_da + ((size_t)t * N + env) * na;
+  for (int i = ln; i < na; i += SIM_WAVE) da[i] = E.abar[i];
+  // a_prev of s_t is a_{t-1} (or the a_prev of s_0); its adjoint starts at zero
+  __syncthreads();
+  if (A.closed_loop) {
+    for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)t * N + env) * od + i];
+    __syncthreads();
+    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, ln);
+    for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * (RL(1.0) - E.a[i] * E.a[i]);
+    __syncthreads();
+    mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, ln);
+    for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+    __syncthreads();
+    task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, ln);
+  } else {
+    for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+    __syncthreads();
+  }
+  (void)ns;
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int S = m->substeps, nq = m->nq, nv = m->nv, na = m->na, ns = m->ns, N = A.N, k = A.k;
+  const int nqv = nq + nv;
+  adjoint_seed(A, m, E, env, ln);
+  // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
+  real* seg = A.seg + (size_t)env * k * nqv;
+  real Lrow[SIM_MAXV], Lcol[SIM_MAXV];
+  for (int t = A.h - 1; t >= 0; --t) {
+    const real* at = A.actions_fw + ((size_t)t * N + env) * na;
+    for (int sg = S / k - 1; sg >= 0; --sg) {
+      int c = (t * S + sg * k) / k;
+      const real* ck = A.ckpt + ((size_t)c * N + env) * nqv;
+      if (k > 1) {
+        load_qqd(m, E, ck, ln);
+        for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+        __syncthreads();
+        for (int i = 0; i < k - 1; ++i) {
+          store_qqd(m, E, seg + (size_t)i * nqv, ln);
+          real minpiv;
+          substep_forward(m, E, jr, cr, ln, Lrow, Lcol, true, minpiv);
+        }
+        store_qqd(m, E, seg + (size_t)(k - 1) * nqv, ln);
+        __syncthreads();
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        load_qqd(m, E, k > 1 ? seg + (size_t)i * nqv : ck, ln);
+        for (int j = ln; j < na; j += SIM_WAVE) E.a[j] = at[j];
+        __syncthreads();
+        substep_adjoint(m, E, jr, cr, ln);
+      }
+    }
+    adjoint_frame(A, m, E, env, t, ln);
+  }
+  real* d0 = A.dL_ds0 + (size_t)env * ns;
+  for (int i = ln; i < nq; i += SIM_WAVE) d0[i] = E.qb[i];
+  for (int i = ln; i < nv; i += SIM_WAVE) d0[nq + i] = E.qdb[i];
+  if (m->has_last_action)
+    for (int i = ln; i < na; i += SIM_WAVE) d0[nq + nv + i] = E.abar[i];
+}
+
+// ======================================================================= plain path kernels
+// One launch per frame start and one per substep; the state goes through HBM between
+// launches (ckpt holds every substep's state, k = 1).
+__global__ __launch_bounds__(SIM_WAVE) void k_plain_frame(WinArgs A, int t) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
+  if (t == 0) {
+    load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
+    store_qqd(m, E, A.ckpt + (size_t)env * nqv, ln);
+  } else {
+    load_qqd(m, E, A.ckpt + ((size_t)(t * S) * N + env) * nqv, ln);
+    const real* ap = A.actions + ((size_t)(t - 1) * N + env) * na;
+    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = ap[i];
+    __syncthreads();
+  }
+  frame_begin(A, m, E, env, t, ln);
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_plain_substep(WinArgs A, int t, int sub) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
+  int gi = t * S + sub;
+  load_qqd(m, E, A.ckpt + ((size_t)gi * N + env) * nqv, ln);
+  const real* at = A.actions + ((size_t)t * N + env) * na;
+  for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+  __syncthreads();
+  real Lrow[SIM_MAXV], Lcol[SIM_MAXV], minpiv;
+  substep_forward(m, E, jr, cr, ln, Lrow, Lcol, true, minpiv);
+  store_qqd(m, E, A.ckpt + ((size_t)(gi + 1) * N + env) * nqv, ln);
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_plain_end(WinArgs A) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
+  load_qqd(m, E, A.ckpt + ((size_t)(A.h * S) * N + env) * nqv, ln);
+  const real* ap = A.actions + ((size_t)(A.h - 1) * N + env) * na;
+  for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = ap[i];
+  __syncthreads();
+  window_end(A, m, E, env, ln);
+}
+
+__device__ __forceinline__ void adj_load(const DevModel* __restrict__ m, EnvLDS& E, const real* src, int ln) {
+  int nq = m->nq, nv = m->nv, na = m->na;
+  for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = i < nq ? src[i] : RL(0.0);
+  for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = i < nv ? src[nq + i] : RL(0.0);
+  for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = i < na ? src[nq + nv + i] : RL(0.0);
+  __syncthreads();
+}
+__device__ __forceinline__ void adj_store(const DevModel* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
+  int nq = m->nq, nv = m->nv, na = m->na;
+  for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.qb[i];
+  for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qdb[i];
+  for (int i = ln; i < na; i += SIM_WAVE) dst[nq + nv + i] = E.abar[i];
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_seed(WinArgs A) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  adjoint_seed(A, m, E, env, ln);
+  adj_store(m, E, A.adj + (size_t)env * (m->nq + m->nv + m->na), ln);
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_substep(WinArgs A, int t, int sub) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
+  real* adj = A.adj + (size_t)env * (nqv + na);
+  adj_load(m, E, adj, ln);
+  load_qqd(m, E, A.ckpt + ((size_t)(t * S + sub) * N + env) * nqv, ln);
+  const real* at = A.actions_fw + ((size_t)t * N + env) * na;
+  for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+  __syncthreads();
+  substep_adjoint(m, E, jr, cr, ln);
+  adj_store(m, E, adj, ln);
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_frame(WinArgs A, int t) {
+  __shared__ EnvLDS E;
+  const DevModel* __restrict__ m = A.model;
+  const int env = blockIdx.x, ln = threadIdx.x;
+  JointRegs jr;
+  ContactRegs cr;
+  load_regs(m, E, ln, jr, cr);
+  const int nqv = m->nq + m->nv, na = m->na, ns = m->ns, nq = m->nq, nv = m->nv;
+  real* adj = A.adj + (size_t)env * (nqv + na);
+  adj_load(m, E, adj, ln);
+  adjoint_frame(A, m, E, env, t, ln);
+  adj_store(m, E, adj, ln);
+  if (t == 0) {
+    real* d0 = A.dL_ds0 + (size_t)env * ns;
+    for (int i = ln; i < nq; i += SIM_WAVE) d0[i] = E.qb[i];
+    for (int i = ln; i < nv; i += SIM_WAVE) d0[nq + i] = E.qdb[i];
+    if (m->has_last_action)
+      for (int i = ln; i < na; i += SIM_WAVE) d0[nq + nv + i] = E.abar[i];
+  }
+}
+
+// weights [out][in] -> [in][out]
+__global__ void k_transpose(const real* __restrict__ W, real* __restrict__ WT, int no, int ni) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < no * ni) {
+    int o = idx / ni, i = idx % ni;
+    WT[(size_t)i * no + o] = W[idx];
+  }
+}
+
+
+// ======================================================================= launchers
+int launch_transpose(const real* W, real* WT, int n_out, int n_in, void* stream) {
+  int n = n_out * n_in;
+  hipLaunchKernelGGL(k_transpose, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, W, WT, n_out, n_in);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_forward(const WinArgs& A, int plain, int substeps, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  dim3 grid(A.N), block(SIM_WAVE);
+  if (!plain) {
+    hipLaunchKernelGGL(k_window_fwd, grid, block, 0, s, A);
+  } else {
+    for (int t = 0; t < A.h; ++t) {
+      hipLaunchKernelGGL(k_plain_frame, grid, block, 0, s, A, t);
+      for (int sub = 0; sub < substeps; ++sub) hipLaunchKernelGGL(k_plain_substep, grid, block, 0, s, A, t, sub);
+    }
+    hipLaunchKernelGGL(k_plain_end, grid, block, 0, s, A);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_adjoint(const WinArgs& A, int plain, int substeps, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  dim3 grid(A.N), block(SIM_WAVE);
+  if (!plain) {
+    hipLaunchKernelGGL(k_window_adj, grid, block, 0, s, A);
+  } else {
+    hipLaunchKernelGGL(k_plain_adj_seed, grid, block, 0, s, A);
+    for (int t = A.h - 1; t >= 0; --t) {
+      for (int sub = substeps - 1; sub >= 0; --sub) hipLaunchKernelGGL(k_plain_adj_substep, grid, block, 0, s, A, t, sub);
+      hipLaunchKernelGGL(k_plain_adj_frame, grid, block, 0, s, A, t);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}

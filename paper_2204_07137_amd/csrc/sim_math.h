@@ -1,0 +1,111 @@
+// Device math for one arithmetic type.  Included inside a namespace with `real` defined
+// as float or double (kernels_f32.hip, kernels_f64.hip).
+//
+// Spatial vectors are 6-vectors in world-aligned Plücker coordinates whose reference
+// point O is the root position of the current substep (the world origin for fixed-base
+// models): motion (w, v_O), force (n_O, f).
+
+#define RL(x) static_cast<real>(x)
+
+typedef DevModelT<real> DevModel;
+typedef MlpArgsT<real> MlpArgs;
+typedef WinArgsT<real> WinArgs;
+
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ void m_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double m_fma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float m_tanh(float x) { return tanhf(x); }
+__device__ __forceinline__ double m_tanh(double x) { return tanh(x); }
+__device__ __forceinline__ float m_atan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double m_atan2(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float m_fabs(float x) { return fabsf(x); }
+__device__ __forceinline__ double m_fabs(double x) { return fabs(x); }
+__device__ __forceinline__ float m_pow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float m_fmin(float x, float y) { return fminf(x, y); }
+__device__ __forceinline__ double m_fmin(double x, double y) { return fmin(x, y); }
+__device__ __forceinline__ float m_fmax(float x, float y) { return fmaxf(x, y); }
+__device__ __forceinline__ double m_fmax(double x, double y) { return fmax(x, y); }
+__device__ __forceinline__ bool m_isfinite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool m_isfinite(double x) { return isfinite(x); }
+
+// broadcast lane l's value (l uniform)
+__device__ __forceinline__ float rdl(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+__device__ __forceinline__ double rdl(double x, int l) {
+  long long v = __builtin_bit_cast(long long, x);
+  int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+  int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// ------------------------------------------------------------------ small vector math
+struct f3 { real x, y, z; };
+__device__ __forceinline__ f3 mk3(real a, real b, real c) { f3 r; r.x = a; r.y = b; r.z = c; return r; }
+__device__ __forceinline__ f3 add3(f3 a, f3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ f3 sub3(f3 a, f3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ f3 scl3(f3 a, real s) { return mk3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ real dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross3(f3 a, f3 b) {
+  return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ f3 ld3(const real* p) { return mk3(p[0], p[1], p[2]); }
+__device__ __forceinline__ void st3(real* p, f3 a) { p[0] = a.x; p[1] = a.y; p[2] = a.z; }
+
+// 3x3 row-major matrix times vector
+__device__ __forceinline__ f3 mv3(const real* R, f3 v) {
+  return mk3(R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z,
+             R[6] * v.x + R[7] * v.y + R[8] * v.z);
+}
+__device__ __forceinline__ f3 mtv3(const real* R, f3 v) {
+  return mk3(R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z,
+             R[2] * v.x + R[5] * v.y + R[8] * v.z);
+}
+
+// spatial 6-vectors as (angular, linear) pairs
+struct sv { f3 a, l; };
+__device__ __forceinline__ sv mksv(f3 a, f3 l) { sv r; r.a = a; r.l = l; return r; }
+__device__ __forceinline__ sv zsv() { return mksv(mk3(0, 0, 0), mk3(0, 0, 0)); }
+__device__ __forceinline__ sv addsv(sv a, sv b) { return mksv(add3(a.a, b.a), add3(a.l, b.l)); }
+__device__ __forceinline__ sv subsv(sv a, sv b) { return mksv(sub3(a.a, b.a), sub3(a.l, b.l)); }
+__device__ __forceinline__ sv sclsv(sv a, real s) { return mksv(scl3(a.a, s), scl3(a.l, s)); }
+__device__ __forceinline__ real dotsv(sv m, sv f) { return dot3(m.a, f.a) + dot3(m.l, f.l); }
+__device__ __forceinline__ sv ldsv(const real* p) { return mksv(mk3(p[0], p[1], p[2]), mk3(p[3], p[4], p[5])); }
+__device__ __forceinline__ void stsv(real* p, sv a) {
+  p[0] = a.a.x; p[1] = a.a.y; p[2] = a.a.z; p[3] = a.l.x; p[4] = a.l.y; p[5] = a.l.z;
+}
+// motion x motion
+__device__ __forceinline__ sv crm(sv a, sv b) {
+  return mksv(cross3(a.a, b.a), add3(cross3(a.a, b.l), cross3(a.l, b.a)));
+}
+// motion x* force
+__device__ __forceinline__ sv crf(sv a, sv f) {
+  return mksv(add3(cross3(a.a, f.a), cross3(a.l, f.l)), cross3(a.a, f.l));
+}
+// spatial force of the 3-force g applied at point x
+__device__ __forceinline__ sv spf(f3 x, f3 g) { return mksv(cross3(x, g), g); }
+// velocity of the point x under the motion m
+__device__ __forceinline__ f3 ptv(sv m, f3 x) { return add3(m.l, cross3(m.a, x)); }
+
+// spatial inertia in 10 numbers: m, h = m c (3), Ibar = rotational inertia about O (xx yy zz xy xz yz)
+__device__ __forceinline__ sv iapply(const real* I, sv v) {
+  real m = I[0];
+  f3 h = mk3(I[1], I[2], I[3]);
+  f3 w = v.a;
+  f3 Iw = mk3(I[4] * w.x + I[7] * w.y + I[8] * w.z, I[7] * w.x + I[5] * w.y + I[9] * w.z,
+              I[8] * w.x + I[9] * w.y + I[6] * w.z);
+  return mksv(add3(Iw, cross3(h, v.l)), add3(scl3(v.l, m), cross3(w, h)));
+}
+
+// wave-wide sum (deterministic butterfly over 64 lanes)
+__device__ __forceinline__ real wave_sum(real x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, SIM_WAVE);
+  return x;
+}

@@ -1,0 +1,222 @@
+// Observations, rewards, the deterministic MLP policy / critic and their adjoints, one
+// environment per wavefront.
+//
+// Observations and rewards follow the task definitions of App. A.3 (CartPole Swing Up,
+// Ant, Humanoid); "up" and "heading" are the z-z and x-x entries of the root rotation.
+// The MLP has ELU hidden layers and a linear output (App. A.2); the policy squashes its
+// output with tanh.
+
+
+// x (LDS, dims[0]) -> out (LDS, dims[nl]); hidden activations kept in h0 / h1 (<= 2 hidden)
+__device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, real* h0, real* h1,
+                                            real* out, int ln) {
+  const real* in = x;
+  for (int l = 0; l < P.nl; ++l) {
+    int ni = P.dims[l], no = P.dims[l + 1];
+    real* dst = (l == P.nl - 1) ? out : ((l & 1) ? h1 : h0);
+    const real* __restrict__ WT = P.WT[l];
+    const real* __restrict__ bb = P.b[l];
+    real acc[SIM_MAXHID / SIM_WAVE];
+#pragma unroll
+    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
+      int o = c * SIM_WAVE + ln;
+      acc[c] = (o < no) ? bb[o] : RL(0.0);
+    }
+    for (int i = 0; i < ni; ++i) {
+      real xi = in[i];
+      const real* row = WT + (size_t)i * no;
+#pragma unroll
+      for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
+        int o = c * SIM_WAVE + ln;
+        if (c * SIM_WAVE < no && o < no) acc[c] = m_fma(row[o], xi, acc[c]);
+      }
+    }
+    bool hidden = l < P.nl - 1;
+#pragma unroll
+    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
+      int o = c * SIM_WAVE + ln;
+      if (o < no) {
+        real z = acc[c];
+        dst[o] = (hidden && z <= RL(0.0)) ? m_expm1(z) : z;
+      }
+    }
+    __syncthreads();
+    in = dst;
+  }
+}
+
+// Given the output adjoint gout (LDS, dims[nl]) and the forward activations kept by
+// mlp_forward, writes the input adjoint to xbar (LDS, dims[0]).  Scratch: gbuf (>= max width).
+__device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, const real* h1,
+                                              real* gout, real* gbuf, real* xbar, int ln) {
+  real* g = gout;
+  for (int l = P.nl - 1; l >= 0; --l) {
+    int ni = P.dims[l], no = P.dims[l + 1];
+    const real* __restrict__ W = P.W[l];
+    real* dst = (l == 0) ? xbar : gbuf;
+    real acc[SIM_MAXHID / SIM_WAVE];
+#pragma unroll
+    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) acc[c] = RL(0.0);
+    for (int o = 0; o < no; ++o) {
+      real go = g[o];
+      const real* row = W + (size_t)o * ni;
+#pragma unroll
+      for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
+        int i = c * SIM_WAVE + ln;
+        if (c * SIM_WAVE < ni && i < ni) acc[c] = m_fma(row[i], go, acc[c]);
+      }
+    }
+    __syncthreads();   // every lane has read g before dst (which may alias g) is written
+    const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
+#pragma unroll
+    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
+      int i = c * SIM_WAVE + ln;
+      if (i < ni) {
+        real v = acc[c];
+        if (hin) {
+          real hv = hin[i];
+          v *= (hv > RL(0.0)) ? RL(1.0) : (hv + RL(1.0));    // ELU'(z) = 1 (z > 0) or exp(z) = h + 1
+        }
+        dst[i] = v;
+      }
+    }
+    __syncthreads();
+    g = dst;
+  }
+}
+
+// --------------------------------------------------------------- observations
+// s = [q | qd | a_prev];  obs written to o (LDS)
+__device__ __forceinline__ void task_obs(const DevModel* __restrict__ m, const real* q, const real* qd,
+                                         const real* aprev, real* o, int ln) {
+  if (m->task == TASK_CARTPOLE) {
+    if (ln == 0) {
+      real sn, cs;
+      m_sincos(q[1], &sn, &cs);
+      o[0] = q[0]; o[1] = qd[0]; o[2] = sn; o[3] = cs; o[4] = qd[1];
+    }
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+    int nh = m->nq - 7;
+    if (ln == 0) {
+      real w = q[3], x = q[4], y = q[5], z = q[6];
+      real n2 = w * w + x * x + y * y + z * z;
+      o[0] = q[2];
+      o[1] = w; o[2] = x; o[3] = y; o[4] = z;
+      o[5] = qd[0]; o[6] = qd[1]; o[7] = qd[2]; o[8] = qd[3]; o[9] = qd[4]; o[10] = qd[5];
+      o[11 + 2 * nh] = RL(1.0) - RL(2.0) * (x * x + y * y) / n2;       // up
+      o[12 + 2 * nh] = RL(1.0) - RL(2.0) * (y * y + z * z) / n2;       // heading
+    }
+    for (int i = ln; i < nh; i += SIM_WAVE) {
+      o[11 + i] = q[7 + i];
+      o[11 + nh + i] = qd[6 + i];
+    }
+    if (m->has_last_action)
+      for (int i = ln; i < m->na; i += SIM_WAVE) o[13 + 2 * nh + i] = aprev[i];
+  }
+  __syncthreads();
+}
+
+// adjoint of task_obs: adds (d obs / d s)^T obar to (qb, qdb, abar_prev)
+__device__ __forceinline__ void task_obs_vjp(const DevModel* __restrict__ m, const real* q, const real* ob,
+                                             real* qb, real* qdb, real* apb, int ln) {
+  if (m->task == TASK_CARTPOLE) {
+    if (ln == 0) {
+      real sn, cs;
+      m_sincos(q[1], &sn, &cs);
+      qb[0] += ob[0]; qdb[0] += ob[1]; qb[1] += cs * ob[2] - sn * ob[3]; qdb[1] += ob[4];
+    }
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+    int nh = m->nq - 7;
+    if (ln == 0) {
+      real w = q[3], x = q[4], y = q[5], z = q[6];
+      real n2 = w * w + x * x + y * y + z * z;
+      real i2 = RL(1.0) / n2, i4 = i2 * i2;
+      real gu = ob[11 + 2 * nh], gh = ob[12 + 2 * nh];
+      real u = x * x + y * y, hh = y * y + z * z;
+      // up = 1 - 2u/n2 ; heading = 1 - 2hh/n2
+      qb[2] += ob[0];
+      qb[3] += ob[1] + gu * (RL(4.0) * u * w * i4) + gh * (RL(4.0) * hh * w * i4);
+      qb[4] += ob[2] + gu * (-RL(4.0) * x * i2 + RL(4.0) * u * x * i4) + gh * (RL(4.0) * hh * x * i4);
+      qb[5] += ob[3] + gu * (-RL(4.0) * y * i2 + RL(4.0) * u * y * i4) + gh * (-RL(4.0) * y * i2 + RL(4.0) * hh * y * i4);
+      qb[6] += ob[4] + gu * (RL(4.0) * u * z * i4) + gh * (-RL(4.0) * z * i2 + RL(4.0) * hh * z * i4);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) qdb[k] += ob[5 + k];
+    }
+    for (int i = ln; i < nh; i += SIM_WAVE) {
+      qb[7 + i] += ob[11 + i];
+      qdb[6 + i] += ob[11 + nh + i];
+    }
+    if (m->has_last_action)
+      for (int i = ln; i < m->na; i += SIM_WAVE) apb[i] += ob[13 + 2 * nh + i];
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------- rewards
+__device__ __forceinline__ real task_reward(const DevModel* __restrict__ m, const real* q, const real* qd,
+                                             const real* a, int ln) {
+  real r = RL(0.0);
+  if (m->task == TASK_CARTPOLE) {
+    real sn, cs;
+    m_sincos(q[1], &sn, &cs);
+    real th = m_atan2(sn, cs);
+    r = -th * th - RL(0.1) * qd[1] * qd[1] - RL(0.05) * q[0] * q[0] - RL(0.1) * qd[0] * qd[0];
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+    real w = q[3], x = q[4], y = q[5], z = q[6];
+    real n2 = w * w + x * x + y * y + z * z;
+    real up = RL(1.0) - RL(2.0) * (x * x + y * y) / n2;
+    real hd = RL(1.0) - RL(2.0) * (y * y + z * z) / n2;
+    real hgt = q[2];
+    r = qd[0] + RL(0.1) * up + hd;
+    if (m->task == TASK_ANT) {
+      r += hgt - RL(0.27);
+    } else {
+      real dh = m_fmin(m_fmax(hgt - RL(0.84), -RL(1.0)), RL(0.1));
+      r += (dh < RL(0.0)) ? -RL(200.0) * dh * dh : RL(10.0) * dh;
+      real aa = RL(0.0);
+      for (int i = 0; i < m->na; ++i) aa += a[i] * a[i];
+      r -= RL(0.002) * aa;
+    }
+  }
+  return r;
+}
+
+// adds c * dR/ds to (qb, qdb) and c * dR/da to abar
+__device__ __forceinline__ void task_reward_vjp(const DevModel* __restrict__ m, const real* q, const real* qd,
+                                                const real* a, real c, real* qb, real* qdb, real* abar,
+                                                int ln) {
+  if (m->task == TASK_CARTPOLE) {
+    if (ln == 0) {
+      real sn, cs;
+      m_sincos(q[1], &sn, &cs);
+      real th = m_atan2(sn, cs);
+      qb[1] += c * (-RL(2.0) * th);
+      qdb[1] += c * (-RL(0.2) * qd[1]);
+      qb[0] += c * (-RL(0.1) * q[0]);
+      qdb[0] += c * (-RL(0.2) * qd[0]);
+    }
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+    if (ln == 0) {
+      real w = q[3], x = q[4], y = q[5], z = q[6];
+      real n2 = w * w + x * x + y * y + z * z;
+      real i2 = RL(1.0) / n2, i4 = i2 * i2;
+      real u = x * x + y * y, hh = y * y + z * z;
+      real gu = RL(0.1) * c, gh = c;
+      qb[3] += gu * (RL(4.0) * u * w * i4) + gh * (RL(4.0) * hh * w * i4);
+      qb[4] += gu * (-RL(4.0) * x * i2 + RL(4.0) * u * x * i4) + gh * (RL(4.0) * hh * x * i4);
+      qb[5] += gu * (-RL(4.0) * y * i2 + RL(4.0) * u * y * i4) + gh * (-RL(4.0) * y * i2 + RL(4.0) * hh * y * i4);
+      qb[6] += gu * (RL(4.0) * u * z * i4) + gh * (-RL(4.0) * z * i2 + RL(4.0) * hh * z * i4);
+      qdb[0] += c;
+      real hgt = q[2];
+      if (m->task == TASK_ANT) {
+        qb[2] += c;
+      } else {
+        real xh = hgt - RL(0.84);
+        if (xh >= -RL(1.0) && xh <= RL(0.1)) qb[2] += c * ((xh < RL(0.0)) ? -RL(400.0) * xh : RL(10.0));
+      }
+    }
+    if (m->task == TASK_HUMANOID)
+      for (int i = ln; i < m->na; i += SIM_WAVE) abar[i] += c * (-RL(0.004) * a[i]);
+  }
+  __syncthreads();
+}

@@ -1,0 +1,76 @@
+// Types shared by the host ABI code and the device code: model tables, MLP and window
+// kernel arguments, each templated on the arithmetic type of the path (float or double).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#define SIM_WAVE 64
+#define SIM_MAXJ 32      // joint frames
+#define SIM_MAXV 32      // velocity DOFs (one row of M per lane)
+#define SIM_MAXQ 33      // position coordinates
+#define SIM_MAXC 32      // contact spheres
+#define SIM_MAXA 32      // actuators
+#define SIM_MAXOBS 128   // observation width
+#define SIM_MAXHID 512   // MLP width
+#define SIM_MAXL 4       // MLP linear layers
+
+enum { J_FREE = 0, J_HINGE = 1, J_SLIDE = 2 };
+enum { TASK_NONE = 0, TASK_CARTPOLE = 1, TASK_ANT = 2, TASK_HUMANOID = 3 };
+
+template <typename T>
+struct DevModelT {
+  int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
+  T dt_sub, g, kn, kd, kt, mu, klim;
+  int parent[SIM_MAXJ], jtype[SIM_MAXJ], qadr[SIM_MAXJ], vadr[SIM_MAXJ], depth[SIM_MAXJ];
+  int first_child[SIM_MAXJ], next_sib[SIM_MAXJ], act_of_joint[SIM_MAXJ], limited[SIM_MAXJ];
+  T offset[SIM_MAXJ * 3], axis[SIM_MAXJ * 3], mass[SIM_MAXJ], com[SIM_MAXJ * 3];
+  T inertia[SIM_MAXJ * 6];   // xx yy zz xy xz yz about the COM, frame axes
+  T lower[SIM_MAXJ], upper[SIM_MAXJ], gear[SIM_MAXJ];
+  T armature[SIM_MAXV];
+  int cbody[SIM_MAXC];
+  T cpos[SIM_MAXC * 3], crad[SIM_MAXC];
+};
+
+template <typename T>
+struct MlpArgsT {
+  int nl;                      // linear layers
+  int dims[SIM_MAXL + 1];
+  const T* W[SIM_MAXL];        // [out][in] row-major (caller layout)
+  const T* WT[SIM_MAXL];       // [in][out] (library copy in the workspace)
+  const T* b[SIM_MAXL];
+};
+
+template <typename T>
+struct WinArgsT {
+  const DevModelT<T>* model;
+  int N, h, k, closed_loop;
+  T gamma, scale;
+  const T* s0;
+  const T* actions_in;
+  MlpArgsT<T> actor, critic;
+  T* s_h;
+  T* obs;
+  T* actions;
+  T* rewards;
+  T* value;
+  uint8_t* nonfinite;
+  T* ckpt;          // [n_ckpt][N][nq+nv]
+  T* seg;           // [N][k][nq+nv] segment pre-states (recompute)
+  T* adj;           // [N][nq+nv+na] adjoint carried between plain launches
+  const T* obs_in;
+  const T* actions_fw;
+  const T* s_h_in;
+  const T* grad_s_h;
+  T* dL_da;
+  T* dL_ds0;
+};
+
+// Launchers implemented once per arithmetic type (kernels_f32.hip, kernels_f64.hip).
+#define SIM_DECLARE_LAUNCHERS(NS, T)                                                        \
+  namespace NS {                                                                            \
+  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, void* stream);         \
+  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, void* stream);         \
+  int launch_transpose(const T* W, T* WT, int n_out, int n_in, void* stream);              \
+  }
+SIM_DECLARE_LAUNCHERS(sim_f32, float)
+SIM_DECLARE_LAUNCHERS(sim_f64, double)

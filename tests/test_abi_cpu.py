@@ -1,0 +1,78 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry point, and
+rejects bad models and options before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2204_07137_amd as P
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "shacsim.h")).read()
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = _declared()
+    assert set(names) == set(P.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(md, **kw):
+    d, keep = P.model_desc(md)
+    o = P.SimOptions()
+    o.n_envs = kw.get("n_envs", 4)
+    o.horizon = kw.get("horizon", 2)
+    o.ckpt_interval = kw.get("k", md["substeps"])
+    o.path = kw.get("path", 0)
+    o.closed_loop = 0
+    od = {"cartpole": 5, "ant": 37, "humanoid": 76}.get(md["task"], 1)
+    dims = kw.get("critic", [od, 8, 1])
+    o.critic_layers = len(dims) - 1
+    for i, v in enumerate(dims):
+        o.critic_dims[i] = v
+    o.gamma = 0.99
+    h = ctypes.c_void_p()
+    rc = P.lib().sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h))
+    return rc, P.lib().sim_last_error().decode()
+
+
+def test_null_arguments_rejected():
+    L = P.lib()
+    assert L.sim_create(None, None, None) == -1
+    assert L.sim_workspace_bytes(None) == 0
+    assert L.sim_forward_window(None, None, None) == -2
+    assert L.sim_adjoint_window(None, None, None) == -2
+    L.sim_destroy(None)
+
+
+def test_model_limits_rejected():
+    md = wl.humanoid()
+    bad = dict(md)
+    bad["parent"] = md["parent"].copy()
+    bad["parent"][3] = 5
+    rc, msg = _create(bad)
+    assert rc == -4 and "parents" in msg
+    rc, msg = _create(md, k=5)
+    assert rc == -1 and "ckpt_interval" in msg
+    rc, msg = _create(md, k=1, path=1)
+    assert rc != -1 or "ckpt" not in msg
+    rc, msg = _create(md, k=16, path=1)
+    assert rc == -1 and "plain" in msg
+    rc, msg = _create(md, critic=[75, 8, 1])
+    assert rc == -1 and "critic" in msg
+
+
+def test_too_many_joints_rejected():
+    md = wl.chain(40, free_root=True)
+    md["task"] = "none"
+    rc, msg = _create(md, critic=[1, 1])
+    assert rc == -4 and "n_joints" in msg

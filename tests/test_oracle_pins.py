@@ -544,3 +544,11 @@ def test_window_adjoint_fd_humanoid_short():
     coords_a = [(0, 0, 0), (0, 0, 7), (0, 0, 20)]
     coords_s = [(0, 2), (0, 9), (0, 40), (0, 60)]
     _fd_check(W, h, [5], coords_a, coords_s, 1e-6, 1e-5)
+
+
+def test_window_adjoint_fd_open_loop_ant():
+    W = wl.workload("ant", 64)
+    h = 2
+    coords_a = [(0, 0, 1), (1, 0, 6), (0, 0, 3)]
+    coords_s = [(0, 2), (0, 20), (0, 33)]
+    _fd_check(W, h, [11], coords_a, coords_s, 1e-6, 1e-5, closed_loop=False)
