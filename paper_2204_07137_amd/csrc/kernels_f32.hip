@@ -3,6 +3,9 @@
 #include <math.h>
 #include "sim_types.h"
 
+// DOF counts compiled as kernels of their own (CartPole, Ant, Humanoid)
+#define SIM_NV_LIST(X) X(2) X(14) X(27)
+
 namespace sim_f32 {
 typedef float real;
 #include "sim_math.h"

@@ -3,6 +3,9 @@
 #include <math.h>
 #include "sim_types.h"
 
+// FP64 path: every model runs the padded 32-DOF kernel
+#define SIM_NV_LIST(X)
+
 namespace sim_f64 {
 typedef double real;
 #include "sim_math.h"

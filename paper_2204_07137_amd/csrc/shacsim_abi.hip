@@ -33,7 +33,7 @@ struct SimHandle {
   SimOptions opt;
   int ns = 0, od = 0, nq = 0, nv = 0, na = 0, substeps = 0;
   size_t elem = 4;
-  size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL];
+  size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL], wp_actor_off[SIM_MAXL], wp_critic_off[SIM_MAXL];
   size_t off_ckpt = 0, off_seg = 0, off_adj = 0, ws_bytes = 0;
   int n_ckpt = 0;
   int device = -1;
@@ -62,6 +62,9 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
     for (int k = 0; k < 6; ++k) d.inertia[6 * j + k] = (T)s.inertia[6 * j + k];
   }
   for (int i = 0; i < SIM_MAXV; ++i) d.armature[i] = (T)s.armature[i];
+  for (int j = 0; j < SIM_MAXJ; ++j) d.cmask[j] = s.cmask[j];
+  d.npair = s.npair;
+  for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
   for (int c = 0; c < SIM_MAXC; ++c) {
     d.cbody[c] = s.cbody[c];
     d.crad[c] = (T)s.crad[c];
@@ -142,6 +145,7 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
     int b = md->contact_body[c];
     if (b < 0 || b >= J) return fail(SIM_E_MODEL, "contact body out of range");
     m.cbody[c] = b;
+    m.cmask[b] |= 1u << c;
     for (int k = 0; k < 3; ++k) m.cpos[3 * c + k] = md->contact_pos[3 * c + k];
     m.crad[c] = md->contact_radius[c];
   }
@@ -162,6 +166,15 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
   }
   m.od = obs_dim_for(m);
   if (m.od > SIM_MAXOBS) return fail(SIM_E_MODEL, "observation wider than 128");
+  m.npair = 0;
+  for (int i = 0; i < J; ++i) {
+    if (m.jtype[i] == J_FREE) continue;
+    for (int k = i; k >= 0; k = m.parent[k]) {
+      if (m.npair >= SIM_MAXPAIR) return fail(SIM_E_MODEL, "too many mass-matrix pairs");
+      m.pair[m.npair++] = i | (k << 5) | (m.vadr[i] << 10) | (m.vadr[k] << 15) |
+                          ((m.jtype[k] == J_FREE ? 1 : 0) << 20) | (1 << 21);
+    }
+  }
   return SIM_OK;
 }
 
@@ -214,15 +227,24 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   // workspace: transposed MLP weights, checkpoint arena, segment pre-states, plain-path adjoint
   const size_t e = h->elem;
   size_t off = 0;
-  for (int l = 0; l < SIM_MAXL; ++l) { h->wt_actor_off[l] = 0; h->wt_critic_off[l] = 0; }
+  for (int l = 0; l < SIM_MAXL; ++l) {
+    h->wt_actor_off[l] = h->wt_critic_off[l] = h->wp_actor_off[l] = h->wp_critic_off[l] = 0;
+  }
+  auto pad64 = [](int n) { return (size_t)((n + SIM_WAVE - 1) / SIM_WAVE * SIM_WAVE); };
   if (opt->closed_loop)
     for (int l = 0; l < opt->actor_layers; ++l) {
+      int ni = opt->actor_dims[l], no = opt->actor_dims[l + 1];
       h->wt_actor_off[l] = off;
-      off = align256(off + e * (size_t)opt->actor_dims[l] * opt->actor_dims[l + 1]);
+      off = align256(off + e * ni * pad64(no));
+      h->wp_actor_off[l] = off;
+      off = align256(off + e * no * pad64(ni));
     }
   for (int l = 0; l < opt->critic_layers; ++l) {
+    int ni = opt->critic_dims[l], no = opt->critic_dims[l + 1];
     h->wt_critic_off[l] = off;
-    off = align256(off + e * (size_t)opt->critic_dims[l] * opt->critic_dims[l + 1]);
+    off = align256(off + e * ni * pad64(no));
+    h->wp_critic_off[l] = off;
+    off = align256(off + e * no * pad64(ni));
   }
   const size_t N = opt->n_envs, nqv = m.nq + m.nv;
   h->n_ckpt = (opt->path == SIM_PATH_PLAIN) ? opt->horizon * m.substeps + 1
@@ -271,15 +293,16 @@ static int check_handle(SimHandle* h) {
 
 template <typename T>
 static int fill_mlp(MlpArgsT<T>& P, int nl, const int* dims, const void* const* W, const void* const* b,
-                    char* ws, const size_t* wt_off, const char* what) {
+                    char* ws, const size_t* wt_off, const size_t* wp_off, const char* what) {
   P.nl = nl;
   for (int l = 0; l <= SIM_MAXL; ++l) P.dims[l] = (l <= nl) ? dims[l] : 0;
-  for (int l = 0; l < SIM_MAXL; ++l) { P.W[l] = nullptr; P.WT[l] = nullptr; P.b[l] = nullptr; }
+  for (int l = 0; l < SIM_MAXL; ++l) { P.W[l] = nullptr; P.WT[l] = nullptr; P.b[l] = nullptr; P.src[l] = nullptr; }
   for (int l = 0; l < nl; ++l) {
     if (!W[l] || !b[l]) return fail(SIM_E_ARG, std::string(what) + ": null weight or bias pointer");
-    P.W[l] = static_cast<const T*>(W[l]);
+    P.src[l] = static_cast<const T*>(W[l]);
     P.b[l] = static_cast<const T*>(b[l]);
     P.WT[l] = reinterpret_cast<const T*>(ws + wt_off[l]);
+    P.W[l] = reinterpret_cast<const T*>(ws + wp_off[l]);
   }
   return SIM_OK;
 }
@@ -289,13 +312,17 @@ static int launch_transposes(const MlpArgsT<T>& P, void* s);
 template <>
 int launch_transposes<float>(const MlpArgsT<float>& P, void* s) {
   for (int l = 0; l < P.nl; ++l)
-    if (sim_f32::launch_transpose(P.W[l], const_cast<float*>(P.WT[l]), P.dims[l + 1], P.dims[l], s)) return -1;
+    if (sim_f32::launch_prep_weights(P.src[l], const_cast<float*>(P.WT[l]), const_cast<float*>(P.W[l]),
+                                     P.dims[l + 1], P.dims[l], s))
+      return -1;
   return 0;
 }
 template <>
 int launch_transposes<double>(const MlpArgsT<double>& P, void* s) {
   for (int l = 0; l < P.nl; ++l)
-    if (sim_f64::launch_transpose(P.W[l], const_cast<double*>(P.WT[l]), P.dims[l + 1], P.dims[l], s)) return -1;
+    if (sim_f64::launch_prep_weights(P.src[l], const_cast<double*>(P.WT[l]), const_cast<double*>(P.W[l]),
+                                     P.dims[l + 1], P.dims[l], s))
+      return -1;
   return 0;
 }
 
@@ -313,10 +340,10 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   A.actions_in = static_cast<const T*>(io->actions_in);
   int rc;
   if (o.closed_loop) {
-    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, "actor");
+    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off, "actor");
     if (rc) return rc;
   }
-  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, "critic");
+  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, h->wp_critic_off, "critic");
   if (rc) return rc;
   A.s_h = static_cast<T*>(io->s_h); A.obs = static_cast<T*>(io->obs); A.actions = static_cast<T*>(io->actions);
   A.rewards = static_cast<T*>(io->rewards); A.value = static_cast<T*>(io->value);
@@ -329,9 +356,9 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   bad |= launch_transposes(A.critic, stream);
   int plain = (o.path == SIM_PATH_PLAIN);
   if (sizeof(T) == 4)
-    bad |= sim_f32::launch_forward(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, stream);
+    bad |= sim_f32::launch_forward(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, h->nv, stream);
   else
-    bad |= sim_f64::launch_forward(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, stream);
+    bad |= sim_f64::launch_forward(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, h->nv, stream);
   if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
   return SIM_OK;
 }
@@ -349,10 +376,10 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   A.s0 = static_cast<const T*>(io->s0);
   int rc;
   if (o.closed_loop) {
-    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, "actor");
+    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off, "actor");
     if (rc) return rc;
   }
-  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, "critic");
+  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, h->wp_critic_off, "critic");
   if (rc) return rc;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.seg = reinterpret_cast<T*>(ws + h->off_seg);
@@ -366,9 +393,9 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   int plain = (o.path == SIM_PATH_PLAIN);
   int bad;
   if (sizeof(T) == 4)
-    bad = sim_f32::launch_adjoint(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, stream);
+    bad = sim_f32::launch_adjoint(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, h->nv, stream);
   else
-    bad = sim_f64::launch_adjoint(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, stream);
+    bad = sim_f64::launch_adjoint(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, h->nv, stream);
   if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
   return SIM_OK;
 }

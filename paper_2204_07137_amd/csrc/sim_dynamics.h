@@ -16,9 +16,12 @@
 // wrench) minus the limit and actuation work; its derivatives are evaluated in closed
 // form from subtree sums of spatial vectors (no derivative of M or of the factor).
 
+#define SIM_PAIR_ROUNDS (SIM_MAXPAIR / SIM_WAVE)
 struct JointRegs {
   int par, type, qa, va, depth, fc, act, lim;
-  real lo, hi, gear, mass;
+  int pair[SIM_PAIR_ROUNDS];   // this lane's mass-matrix pairs, one per round (0 = none)
+  unsigned int cmask;
+  real lo, hi, gear, mass, arm;
   f3 off, ax, com;
   real I6[6];
 };
@@ -32,7 +35,7 @@ struct EnvLDS {
   real q[SIM_MAXQ], qd[SIM_MAXV], a[SIM_MAXA];
   real qn[SIM_MAXQ], qdn[SIM_MAXV];
   real R[SIM_MAXJ][9], p[SIM_MAXJ][3], S[SIM_MAXJ][6], v[SIM_MAXJ][6], ab[SIM_MAXJ][6];
-  real F[SIM_MAXJ][6];
+  real F[SIM_MAXJ][6], Fi[SIM_MAXJ][6];
   real Ib[SIM_MAXJ][10], Ic[SIM_MAXJ][10];
   real M[SIM_MAXV][SIM_MAXV + 1];
   real vec[SIM_MAXV], qdd[SIM_MAXV];
@@ -46,6 +49,7 @@ struct EnvLDS {
   real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
   // topology copies for arbitrary-index lookups
   int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ];
+  real arm[SIM_MAXV];
   // policy / critic
   real obs[SIM_MAXOBS];
   real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
@@ -59,6 +63,13 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, EnvLDS
   jr.depth = ln < m->J ? m->depth[j] : -1;
   jr.fc = m->first_child[j]; jr.act = m->act_of_joint[j]; jr.lim = m->limited[j];
   jr.lo = m->lower[j]; jr.hi = m->upper[j]; jr.gear = m->gear[j]; jr.mass = m->mass[j];
+  jr.cmask = ln < m->J ? m->cmask[j] : 0u;
+#pragma unroll
+  for (int r = 0; r < SIM_PAIR_ROUNDS; ++r) {
+    int pi = r * SIM_WAVE + ln;
+    jr.pair[r] = pi < m->npair ? m->pair[pi] : 0;
+  }
+  jr.arm = m->armature[m->vadr[j]];
   jr.off = ld3(&m->offset[3 * j]); jr.ax = ld3(&m->axis[3 * j]); jr.com = ld3(&m->com[3 * j]);
 #pragma unroll
   for (int k = 0; k < 6; ++k) jr.I6[k] = m->inertia[6 * j + k];
@@ -67,6 +78,7 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, EnvLDS
   if (ln < SIM_MAXJ) {
     E.t_next_sib[ln] = m->next_sib[ln]; E.t_type[ln] = m->jtype[ln];
     E.t_va[ln] = m->vadr[ln]; E.t_parent[ln] = m->parent[ln];
+    E.arm[ln] = m->armature[ln];
   }
   __syncthreads();
 }
@@ -75,7 +87,7 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, EnvLDS
 // Normal f_n = (-kn + kd ddot) min(d, 0) (active for d < 0), friction only while d < 0:
 // viscous -kt v_t when kt |v_t| <= mu |f_n| (ties included), else -mu |f_n| v_t / |v_t|.
 // Returns the world force and, if wanted, df/dd (3) and df/dv (3x3 row-major).
-__device__ __forceinline__ f3 contact_force(const DevModel* __restrict__ m, real d, f3 v,
+__device__ __forceinline__ f3 contact_force(const Scal* __restrict__ m, real d, f3 v,
                                             bool want_d, f3* dfdd, real* dfdv) {
   f3 f = mk3(RL(0.0), RL(0.0), RL(0.0));
   if (want_d) {
@@ -156,59 +168,73 @@ __device__ __forceinline__ void dq_coeffs(real u, real hh, real& c, real& s, rea
 }
 
 // --------------------------------------------------------------- dense Cholesky (row per lane)
-// On entry Lrow[k] = M[ln][k].  On exit Lrow[k] = L[ln][k] for k <= ln.
+// The factor of one environment lives in the registers of its wavefront: lane i holds row i
+// (row[k] = L[i][k], k <= i) and column i (col[k] = L[k][i], k >= i); dinv[k] = 1 / L[k][k]
+// is held by every lane.  NV is the compile-time DOF count: rows beyond the model's nv are
+// padded with the identity, which leaves the factor and the solution of the real block
+// unchanged, so no per-step guards are needed.
+struct Chol {
+  real row[SIM_MAXV], col[SIM_MAXV], dinv[SIM_MAXV];
+};
+
+// On entry C.row[k] = M[ln][k].  Right-looking factorisation; the column-k entries of the
+// other rows are broadcast with readlane.
 template <int NV>
-__device__ __forceinline__ void chol_factor(real (&Lrow)[SIM_MAXV], int nv, int ln, real& minpiv) {
+__device__ __forceinline__ void chol_factor(Chol& C, int ln, real& minpiv) {
   minpiv = RL(3.0e38);
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    if (k < nv) {
-      real piv = rdl(Lrow[k], k);
-      minpiv = m_fmin(minpiv, piv);
-      real d = m_sqrt(piv);
-      real inv = RL(1.0) / d;
-      real lk = (ln == k) ? d : Lrow[k] * inv;
-      Lrow[k] = lk;
+    real piv = rdl(C.row[k], k);
+    minpiv = m_fmin(minpiv, piv);
+    real inv = m_rsqrt(piv);
+    real d = piv * inv;
+    C.dinv[k] = inv;
+    real lk = (ln == k) ? d : C.row[k] * inv;
+    C.row[k] = lk;
+    real ljk[NV];
 #pragma unroll
-      for (int j = k + 1; j < NV; ++j) {
-        if (j < nv) {
-          real ljk = rdl(lk, j);
-          Lrow[j] = m_fma(-lk, ljk, Lrow[j]);
-        }
-      }
-    }
+    for (int j = k + 1; j < NV; ++j) ljk[j] = rdl(lk, j);
+#pragma unroll
+    for (int j = k + 1; j < NV; ++j) C.row[j] = m_fma(-lk, ljk[j], C.row[j]);
   }
 }
 
-// solve L L^T x = b for b given in lane ln (row ln); Lcol[k] = L[k][ln]
+// solve L L^T x = b for b given in lane ln (row ln)
 template <int NV>
-__device__ __forceinline__ real chol_solve(const real (&Lrow)[SIM_MAXV], const real (&Lcol)[SIM_MAXV],
-                                            int nv, int ln, real b) {
+__device__ __forceinline__ real chol_solve(const Chol& C, int ln, real b) {
   real y = b;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    if (k < nv) {
-      real yk = rdl(y, k) / rdl(Lrow[k], k);
-      y = (ln == k) ? yk : (ln > k ? m_fma(-Lrow[k], yk, y) : y);
-    }
+    real yk = rdl(y, k) * C.dinv[k];
+    y = (ln == k) ? yk : (ln > k ? m_fma(-C.row[k], yk, y) : y);
   }
 #pragma unroll
   for (int k = NV - 1; k >= 0; --k) {
-    if (k < nv) {
-      real xk = rdl(y, k) / rdl(Lrow[k], k);
-      y = (ln == k) ? xk : (ln < k ? m_fma(-Lcol[k], xk, y) : y);
-    }
+    real xk = rdl(y, k) * C.dinv[k];
+    y = (ln == k) ? xk : (ln < k ? m_fma(-C.col[k], xk, y) : y);
   }
   return y;
+}
+
+// --------------------------------------------------------------- subtree sums
+// Adds every frame's row of a table into its parent's row, children before parents
+// (frames are listed parents first); each active lane owns one column.  The parent index
+// is broadcast from the lane that holds it; the LDS executes one wavefront's accesses in
+// order, so a parent updated by an earlier edge is read back correctly without a wait.
+__device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active, int J, int par_reg) {
+  for (int j = J - 1; j >= 1; --j) {
+    int p = __builtin_amdgcn_readlane(par_reg, j);
+    if (active && p >= 0) col[p * stride] += col[j * stride];
+  }
 }
 
 // --------------------------------------------------------------- forward substep
 // Uses E.q, E.qd, E.a.  Writes all intermediates to E and the new state to E.qn/E.qdn
 // (and back to E.q/E.qd when inplace).  Lrow/Lcol keep the Cholesky factor.
-__device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, EnvLDS& E,
+template <int NV>
+__device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvLDS& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln,
-                                                real (&Lrow)[SIM_MAXV], real (&Lcol)[SIM_MAXV],
-                                                bool inplace, real& minpiv) {
+                                                Chol& C, bool inplace, real& minpiv) {
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real g = m->g;
   const real dt = m->dt_sub;
@@ -217,48 +243,62 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
   // clear M
   for (int i = ln; i < SIM_MAXV * (SIM_MAXV + 1); i += SIM_WAVE) (&E.M[0][0])[i] = RL(0.0);
   __syncthreads();
-  // ---- kinematics, velocities, bias accelerations, level by level
-  for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
-    if (jr.depth == lvl) {
-      real Rp[9];
-      f3 pp;
-      sv vp, ap;
-      if (jr.par >= 0) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Rp[k] = E.R[jr.par][k];
-        pp = ld3(E.p[jr.par]);
-        vp = ldsv(E.v[jr.par]);
-        ap = ldsv(E.ab[jr.par]);
+  // ---- local joint rotations (all lanes at once), then kinematics, velocities and bias
+  // accelerations level by level; each lane keeps its own frame's results in registers
+  real Rot[9];
+  real qj = RL(0.0), qdj = RL(0.0);
+  if (ln < J) {
+    if (jr.type == J_FREE) {
+      quat_rot(E.q[jr.qa + 3], E.q[jr.qa + 4], E.q[jr.qa + 5], E.q[jr.qa + 6], Rot);
+    } else {
+      qj = E.q[jr.qa];
+      qdj = E.qd[jr.va];
+      if (jr.type == J_HINGE) {
+        real sn, cs;
+        m_sincos(qj, &sn, &cs);
+        real omc = RL(1.0) - cs;
+        f3 a = jr.ax;
+        // Rodrigues: Rot = I + sn K + (1 - cs) K^2 with K = [a]x, K^2 = a a^T - I
+        Rot[0] = RL(1.0) + omc * (a.x * a.x - RL(1.0)); Rot[1] = -sn * a.z + omc * a.x * a.y; Rot[2] = sn * a.y + omc * a.x * a.z;
+        Rot[3] = sn * a.z + omc * a.y * a.x; Rot[4] = RL(1.0) + omc * (a.y * a.y - RL(1.0)); Rot[5] = -sn * a.x + omc * a.y * a.z;
+        Rot[6] = -sn * a.y + omc * a.z * a.x; Rot[7] = sn * a.x + omc * a.z * a.y; Rot[8] = RL(1.0) + omc * (a.z * a.z - RL(1.0));
       } else {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? RL(1.0) : RL(0.0);
-        pp = mk3(RL(0.0), RL(0.0), RL(0.0));
-        vp = zsv();
-        ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+        for (int k = 0; k < 9; ++k) Rot[k] = (k % 4 == 0) ? RL(1.0) : RL(0.0);
       }
-      real R[9];
-      f3 p;
-      sv S = zsv(), v, ab;
+    }
+  }
+  real R[9];
+  f3 p = mk3(RL(0.0), RL(0.0), RL(0.0));
+  sv S = zsv(), v = zsv(), ab = zsv();
+  for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
+    if (jr.depth == lvl) {
       if (jr.type == J_FREE) {
-        quat_rot(E.q[jr.qa + 3], E.q[jr.qa + 4], E.q[jr.qa + 5], E.q[jr.qa + 6], R);
-        p = mk3(RL(0.0), RL(0.0), RL(0.0));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = Rot[k];
         f3 vl = mk3(E.qd[jr.va], E.qd[jr.va + 1], E.qd[jr.va + 2]);
         f3 w = mk3(E.qd[jr.va + 3], E.qd[jr.va + 4], E.qd[jr.va + 5]);
         v = mksv(w, vl);
         ab = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), add3(mk3(RL(0.0), RL(0.0), g), cross3(vl, w)));
       } else {
-        real qj = E.q[jr.qa];
+        real Rp[9];
+        f3 pp;
+        sv vp, ap;
+        if (jr.par >= 0) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Rp[k] = E.R[jr.par][k];
+          pp = ld3(E.p[jr.par]);
+          vp = ldsv(E.v[jr.par]);
+          ap = ldsv(E.ab[jr.par]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? RL(1.0) : RL(0.0);
+          pp = mk3(RL(0.0), RL(0.0), RL(0.0));
+          vp = zsv();
+          ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+        }
         f3 sh = mv3(Rp, jr.ax);
         if (jr.type == J_HINGE) {
-          real sn, cs;
-          m_sincos(qj, &sn, &cs);
-          real omc = RL(1.0) - cs;
-          f3 a = jr.ax;
-          // Rodrigues: Rot = I + sn K + (1 - cs) K^2 with K = [a]x, K^2 = a a^T - I
-          real Rot[9];
-          Rot[0] = RL(1.0) + omc * (a.x * a.x - RL(1.0)); Rot[1] = -sn * a.z + omc * a.x * a.y; Rot[2] = sn * a.y + omc * a.x * a.z;
-          Rot[3] = sn * a.z + omc * a.y * a.x; Rot[4] = RL(1.0) + omc * (a.y * a.y - RL(1.0)); Rot[5] = -sn * a.x + omc * a.y * a.z;
-          Rot[6] = -sn * a.y + omc * a.z * a.x; Rot[7] = sn * a.x + omc * a.z * a.y; Rot[8] = RL(1.0) + omc * (a.z * a.z - RL(1.0));
 #pragma unroll
           for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -272,7 +312,6 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
           p = add3(add3(pp, mv3(Rp, jr.off)), scl3(sh, qj));
           S = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
         }
-        real qdj = E.qd[jr.va];
         sv u = sclsv(S, qdj);
         v = addsv(vp, u);
         ab = addsv(ap, crm(v, u));
@@ -304,8 +343,6 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
   __syncthreads();
   // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
   if (ln < J) {
-    real* R = E.R[ln];
-    f3 p = ld3(E.p[ln]);
     real mass = jr.mass;
     f3 c = add3(p, mv3(R, jr.com));
     // Ic_w = R I R^T
@@ -333,11 +370,11 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
     Ib[9] = Iw[5] - mass * c.y * c.z;
 #pragma unroll
     for (int k = 0; k < 10; ++k) { E.Ib[ln][k] = Ib[k]; E.Ic[ln][k] = Ib[k]; }
-    sv v = ldsv(E.v[ln]);
     sv hv = iapply(Ib, v);
-    sv f = addsv(iapply(Ib, ldsv(E.ab[ln])), crf(v, hv));
-    for (int ci = 0; ci < nc; ++ci) {
-      if (m->cbody[ci] == ln) f = subsv(f, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
+    sv f = addsv(iapply(Ib, ab), crf(v, hv));
+    for (unsigned int cm = jr.cmask; cm; cm &= cm - 1) {
+      int ci = __builtin_ctz(cm);
+      f = subsv(f, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
     }
     stsv(E.F[ln], f);
     // joint torques: actuation + limit penalty
@@ -356,25 +393,13 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
     }
   }
   __syncthreads();
-  // ---- subtree sums of forces and composite inertias, deepest level first
-  for (int lvl = m->max_depth - 1; lvl >= 0; --lvl) {
-    if (jr.depth == lvl && jr.fc >= 0) {
-      sv f = ldsv(E.F[ln]);
-      real Ic[10];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) Ic[k] = E.Ic[ln][k];
-      for (int ch = jr.fc; ch >= 0; ch = E.t_next_sib[ch]) {
-        f = addsv(f, ldsv(E.F[ch]));
-#pragma unroll
-        for (int k = 0; k < 10; ++k) Ic[k] += E.Ic[ch][k];
-      }
-      stsv(E.F[ln], f);
-#pragma unroll
-      for (int k = 0; k < 10; ++k) E.Ic[ln][k] = Ic[k];
-    }
-    __syncthreads();
+  // ---- subtree sums of forces (6 columns) and composite inertias (10 columns)
+  {
+    real* col = (ln < 6) ? &E.F[0][ln] : &E.Ic[0][ln < 16 ? ln - 6 : 0];
+    tree_sum_cols(col, (ln < 6) ? 6 : 10, ln < 16, J, jr.par);
   }
-  // ---- bias into rhs, CRBA entries (lane = joint)
+  __syncthreads();
+  // ---- bias into rhs; composite-inertia columns F_i = Ic_i S_i; root block of M
   if (ln < J) {
     sv F = ldsv(E.F[ln]);
     const real* Ic = E.Ic[ln];
@@ -404,44 +429,49 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
           E.M[va + 3 + f2][va + e] = C[3 * e + f2];
         }
     } else {
-      sv S = ldsv(E.S[ln]);
       E.vec[jr.va] -= dotsv(S, F);
-      sv Fi = iapply(Ic, S);
-      int i = jr.va;
-      E.M[i][i] = dotsv(S, Fi) + m->armature[i];
-      int k = jr.par;
-      while (k >= 0) {
-        int tk = E.t_type[k], vk = E.t_va[k];
-        if (tk == J_FREE) {
-          E.M[vk + 0][i] = Fi.l.x; E.M[vk + 1][i] = Fi.l.y; E.M[vk + 2][i] = Fi.l.z;
-          E.M[vk + 3][i] = Fi.a.x; E.M[vk + 4][i] = Fi.a.y; E.M[vk + 5][i] = Fi.a.z;
-          E.M[i][vk + 0] = Fi.l.x; E.M[i][vk + 1] = Fi.l.y; E.M[i][vk + 2] = Fi.l.z;
-          E.M[i][vk + 3] = Fi.a.x; E.M[i][vk + 4] = Fi.a.y; E.M[i][vk + 5] = Fi.a.z;
-        } else {
-          real mk = dotsv(ldsv(E.S[k]), Fi);
-          E.M[vk][i] = mk;
-          E.M[i][vk] = mk;
-        }
-        k = E.t_parent[k];
+      stsv(E.Fi[ln], iapply(Ic, S));
+    }
+  }
+  __syncthreads();
+  // ---- CRBA entries M[va_k][va_i] = S_k . F_i, one (frame, ancestor) pair per lane and round
+#pragma unroll
+  for (int r = 0; r < SIM_PAIR_ROUNDS; ++r) {
+    int pk = jr.pair[r];
+    if (pk) {
+      int i = pk & 31, k = (pk >> 5) & 31, vi = (pk >> 10) & 31, vk = (pk >> 15) & 31;
+      sv Fi = ldsv(E.Fi[i]);
+      if (pk & (1 << 20)) {
+        E.M[vk + 0][vi] = Fi.l.x; E.M[vk + 1][vi] = Fi.l.y; E.M[vk + 2][vi] = Fi.l.z;
+        E.M[vk + 3][vi] = Fi.a.x; E.M[vk + 4][vi] = Fi.a.y; E.M[vk + 5][vi] = Fi.a.z;
+        E.M[vi][vk + 0] = Fi.l.x; E.M[vi][vk + 1] = Fi.l.y; E.M[vi][vk + 2] = Fi.l.z;
+        E.M[vi][vk + 3] = Fi.a.x; E.M[vi][vk + 4] = Fi.a.y; E.M[vi][vk + 5] = Fi.a.z;
+      } else {
+        real mk = dotsv(ldsv(E.S[k]), Fi);
+        if (k == i) mk += E.arm[vi];
+        E.M[vk][vi] = mk;
+        E.M[vi][vk] = mk;
       }
     }
   }
   __syncthreads();
-  // ---- Cholesky and solve (lane = DOF)
+  // ---- Cholesky and solve (lane = DOF); rows >= nv padded with the identity
 #pragma unroll
-  for (int k = 0; k < SIM_MAXV; ++k) Lrow[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : RL(0.0);
-  if (ln >= nv) Lrow[0] = RL(0.0);
-  chol_factor<SIM_MAXV>(Lrow, nv, ln, minpiv);
+  for (int k = 0; k < NV; ++k)
+    C.row[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : ((ln == k) ? RL(1.0) : RL(0.0));
+  chol_factor<NV>(C, ln, minpiv);
   __syncthreads();
   if (ln < nv) {
 #pragma unroll
-    for (int k = 0; k < SIM_MAXV; ++k) E.M[ln][k] = Lrow[k];
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) E.M[ln][k] = C.row[k];
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < SIM_MAXV; ++k) Lcol[k] = (ln < nv && k < nv) ? E.M[k][ln < nv ? ln : 0] : RL(0.0);
+  for (int k = 0; k < NV; ++k)
+    C.col[k] = (ln < nv && k < nv) ? E.M[k][ln < nv ? ln : 0] : ((ln == k) ? RL(1.0) : RL(0.0));
   real b = ln < nv ? E.vec[ln] : RL(0.0);
-  real x = chol_solve<SIM_MAXV>(Lrow, Lcol, nv, ln, b);
+  real x = chol_solve<NV>(C, ln, b);
   if (ln < nv) {
     E.qdd[ln] = x;
     real qdn = E.qd[ln] + dt * x;
@@ -479,11 +509,12 @@ __device__ __forceinline__ void substep_forward(const DevModel* __restrict__ m, 
 // On entry E.q/E.qd/E.a hold the pre-substep state, E.qb/E.qdb the adjoint of the
 // post-substep state.  On exit E.qb/E.qdb hold the adjoint of the pre-substep state and
 // E.abar has gained this substep's contribution.
-__device__ __forceinline__ void substep_adjoint(const DevModel* __restrict__ m, EnvLDS& E,
+template <int NV>
+__device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvLDS& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln) {
-  real Lrow[SIM_MAXV], Lcol[SIM_MAXV];
+  Chol C;
   real minpiv;
-  substep_forward(m, E, jr, cr, ln, Lrow, Lcol, false, minpiv);
+  substep_forward<NV>(m, E, jr, cr, ln, C, false, minpiv);
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real dt = m->dt_sub;
   const real g = m->g;
@@ -521,41 +552,41 @@ __device__ __forceinline__ void substep_adjoint(const DevModel* __restrict__ m, 
   // ---- lambda = M^{-1} qdd_bar with the cached factor (lane = DOF)
   {
     real rb = ln < nv ? dt * E.qdb[ln] : RL(0.0);
-    real lam = chol_solve<SIM_MAXV>(Lrow, Lcol, nv, ln, rb);
+    real lam = chol_solve<NV>(C, ln, rb);
     if (ln < nv) E.lam[ln] = lam;
   }
   __syncthreads();
   // actuation adjoint and full accelerations / virtual velocities, level by level
   if (ln < J && jr.act >= 0) E.abar[jr.act] += jr.gear * E.lam[jr.va];
-  for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
-    if (jr.depth == lvl) {
-      sv Ap, Wp;
-      if (jr.par >= 0) {
-        Ap = ldsv(E.A[jr.par]);
-        Wp = ldsv(E.W[jr.par]);
-      } else {
-        Ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
-        Wp = zsv();
-      }
-      sv A, W;
-      if (jr.type == J_FREE) {
-        int va = jr.va;
-        sv ab = ldsv(E.ab[ln]);
-        A = addsv(ab, mksv(mk3(E.qdd[va + 3], E.qdd[va + 4], E.qdd[va + 5]),
-                           mk3(E.qdd[va], E.qdd[va + 1], E.qdd[va + 2])));
-        W = mksv(mk3(E.lam[va + 3], E.lam[va + 4], E.lam[va + 5]), mk3(E.lam[va], E.lam[va + 1], E.lam[va + 2]));
-      } else {
-        sv S = ldsv(E.S[ln]);
-        sv v = ldsv(E.v[ln]);
-        sv u = sclsv(S, E.qd[jr.va]);
-        A = addsv(addsv(Ap, sclsv(S, E.qdd[jr.va])), crm(v, u));
-        W = addsv(Wp, sclsv(S, E.lam[jr.va]));
-      }
-      stsv(E.A[ln], A);
-      stsv(E.W[ln], W);
+  // local terms (lane = joint), then top-down prefix sums over the tree edges
+  if (ln < J) {
+    sv A, W;
+    if (jr.type == J_FREE) {
+      int va = jr.va;
+      sv ab = ldsv(E.ab[ln]);
+      A = addsv(ab, mksv(mk3(E.qdd[va + 3], E.qdd[va + 4], E.qdd[va + 5]),
+                         mk3(E.qdd[va], E.qdd[va + 1], E.qdd[va + 2])));
+      W = mksv(mk3(E.lam[va + 3], E.lam[va + 4], E.lam[va + 5]), mk3(E.lam[va], E.lam[va + 1], E.lam[va + 2]));
+    } else {
+      sv S = ldsv(E.S[ln]);
+      sv v = ldsv(E.v[ln]);
+      sv u = sclsv(S, E.qd[jr.va]);
+      A = addsv(sclsv(S, E.qdd[jr.va]), crm(v, u));
+      W = sclsv(S, E.lam[jr.va]);
+      if (jr.par < 0) A = addsv(A, mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g)));
     }
-    __syncthreads();
+    stsv(E.A[ln], A);
+    stsv(E.W[ln], W);
   }
+  __syncthreads();
+  {
+    real* col = (ln < 6) ? &E.A[0][ln] : &E.W[0][ln < 12 ? ln - 6 : 0];
+    for (int j = 1; j < J; ++j) {
+      int p = __builtin_amdgcn_readlane(jr.par, j);
+      if (ln < 12 && p >= 0) col[j * 6] += col[p * 6];
+    }
+  }
+  __syncthreads();
   // ---- contact adjoints (lane = contact)
   if (ln < nc) {
     int b = cr.body;
@@ -592,32 +623,19 @@ __device__ __forceinline__ void substep_adjoint(const DevModel* __restrict__ m, 
     sv T = iapply(Ib, crm(v, W));
     sv Fn = addsv(iapply(Ib, A), crf(v, hv));
     sv Ab = zsv(), Vb = zsv();
-    for (int ci = 0; ci < nc; ++ci) {
-      if (m->cbody[ci] == ln) {
-        Fn = subsv(Fn, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
-        Ab = addsv(Ab, ldsv(E.cAb[ci]));
-        Vb = addsv(Vb, ldsv(E.cVb[ci]));
-      }
+    for (unsigned int cm = jr.cmask; cm; cm &= cm - 1) {
+      int ci = __builtin_ctz(cm);
+      Fn = subsv(Fn, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
+      Ab = addsv(Ab, ldsv(E.cAb[ci]));
+      Vb = addsv(Vb, ldsv(E.cVb[ci]));
     }
     real* o = E.acc[ln];
     stsv(o + 0, Iw); stsv(o + 6, Q); stsv(o + 12, Rr); stsv(o + 18, T);
     stsv(o + 24, Fn); stsv(o + 30, Ab); stsv(o + 36, Vb);
   }
   __syncthreads();
-  for (int lvl = m->max_depth - 1; lvl >= 0; --lvl) {
-    if (jr.depth == lvl && jr.fc >= 0) {
-      real s[42];
-#pragma unroll
-      for (int k = 0; k < 42; ++k) s[k] = E.acc[ln][k];
-      for (int ch = jr.fc; ch >= 0; ch = E.t_next_sib[ch]) {
-#pragma unroll
-        for (int k = 0; k < 42; ++k) s[k] += E.acc[ch][k];
-      }
-#pragma unroll
-      for (int k = 0; k < 42; ++k) E.acc[ln][k] = s[k];
-    }
-    __syncthreads();
-  }
+  tree_sum_cols(&E.acc[0][ln < 42 ? ln : 0], 42, ln < 42, J, jr.par);
+  __syncthreads();
   // ---- derivatives of lambda^T ID per joint (lane = joint)
   if (ln < J) {
     const real* o = E.acc[ln];

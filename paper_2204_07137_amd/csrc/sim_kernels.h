@@ -6,7 +6,7 @@ __device__ __forceinline__ bool all_finite_wave(bool ok) {
   return __all(ok);
 }
 
-__device__ __forceinline__ void load_state(const DevModel* __restrict__ m, EnvLDS& E, const real* s, int ln) {
+__device__ __forceinline__ void load_state(const Scal* __restrict__ m, EnvLDS& E, const real* s, int ln) {
   int nq = m->nq, nv = m->nv;
   for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = s[i];
   for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = s[nq + i];
@@ -17,13 +17,13 @@ __device__ __forceinline__ void load_state(const DevModel* __restrict__ m, EnvLD
   __syncthreads();
 }
 
-__device__ __forceinline__ void store_qqd(const DevModel* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
+__device__ __forceinline__ void store_qqd(const Scal* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
   int nq = m->nq, nv = m->nv;
   for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.q[i];
   for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qd[i];
 }
 
-__device__ __forceinline__ void load_qqd(const DevModel* __restrict__ m, EnvLDS& E, const real* src, int ln) {
+__device__ __forceinline__ void load_qqd(const Scal* __restrict__ m, EnvLDS& E, const real* src, int ln) {
   int nq = m->nq, nv = m->nv;
   for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = src[i];
   for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = src[nq + i];
@@ -32,7 +32,7 @@ __device__ __forceinline__ void load_qqd(const DevModel* __restrict__ m, EnvLDS&
 
 // observation, action and reward at the start of frame t (state in E.q/E.qd, previous
 // action in E.a); leaves a_t in E.a.
-__device__ __forceinline__ void frame_begin(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+__device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
                                             int env, int t, int ln) {
   const int N = A.N, od = m->od, na = m->na;
   task_obs(m, E.q, E.qd, E.a, E.obs, ln);
@@ -53,7 +53,7 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const DevModel* __
   __syncthreads();
 }
 
-__device__ __forceinline__ void window_end(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+__device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
                                            int env, int ln) {
   const int N = A.N, od = m->od, ns = m->ns, nq = m->nq, nv = m->nv, na = m->na;
   task_obs(m, E.q, E.qd, E.a, E.obs, ln);
@@ -72,23 +72,25 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const DevModel* __r
 }
 
 // ======================================================================= persistent forward
+template <int NV>
 __global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nqv = m->nq + m->nv, N = A.N;
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
-  real Lrow[SIM_MAXV], Lcol[SIM_MAXV];
+  Chol C;
   for (int t = 0; t < A.h; ++t) {
     frame_begin(A, m, E, env, t, ln);
     for (int sub = 0; sub < S; ++sub) {
       int gi = t * S + sub;
       if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
       real minpiv;
-      substep_forward(m, E, jr, cr, ln, Lrow, Lcol, true, minpiv);
+      substep_forward<NV>(m, E, jr, cr, ln, C, true, minpiv);
     }
   }
   window_end(A, m, E, env, ln);
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
 
 // ======================================================================= persistent adjoint
 // terminal seed: s_bar(h) = -gamma^h scale (d obs/d s)^T dV/d obs  (+ optional upstream)
-__device__ __forceinline__ void adjoint_seed(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+__device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
                                              int env, int ln) {
   const int ns = m->ns, nq = m->nq, nv = m->nv, na = m->na, od = m->od;
   const real* sh = A.s_h_in + (size_t)env * ns;
@@ -125,7 +127,7 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const DevModel* _
 
 // frame-level reverse at frame t: E.qb/E.qdb hold the adjoint of the frame-start (q, qd)
 // through the dynamics; E.abar holds dL/da_t except the reward term.
-__device__ __forceinline__ void adjoint_frame(const WinArgs& A, const DevModel* __restrict__ m, EnvLDS& E,
+__device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
                                               int env, int t, int ln) {
   const int N = A.N, nq = m->nq, nv = m->nv, na = m->na, od = m->od, ns = m->ns, S = m->substeps;
   const int nqv = nq + nv;
@@ -157,19 +159,21 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const DevModel* 
   (void)ns;
 }
 
+template <int NV>
 __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nq = m->nq, nv = m->nv, na = m->na, ns = m->ns, N = A.N, k = A.k;
   const int nqv = nq + nv;
   adjoint_seed(A, m, E, env, ln);
   // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
   real* seg = A.seg + (size_t)env * k * nqv;
-  real Lrow[SIM_MAXV], Lcol[SIM_MAXV];
+  Chol C;
   for (int t = A.h - 1; t >= 0; --t) {
     const real* at = A.actions_fw + ((size_t)t * N + env) * na;
     for (int sg = S / k - 1; sg >= 0; --sg) {
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
         for (int i = 0; i < k - 1; ++i) {
           store_qqd(m, E, seg + (size_t)i * nqv, ln);
           real minpiv;
-          substep_forward(m, E, jr, cr, ln, Lrow, Lcol, true, minpiv);
+          substep_forward<NV>(m, E, jr, cr, ln, C, true, minpiv);
         }
         store_qqd(m, E, seg + (size_t)(k - 1) * nqv, ln);
         __syncthreads();
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
         load_qqd(m, E, k > 1 ? seg + (size_t)i * nqv : ck, ln);
         for (int j = ln; j < na; j += SIM_WAVE) E.a[j] = at[j];
         __syncthreads();
-        substep_adjoint(m, E, jr, cr, ln);
+        substep_adjoint<NV>(m, E, jr, cr, ln);
       }
     }
     adjoint_frame(A, m, E, env, t, ln);
@@ -208,11 +212,12 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
 // launches (ckpt holds every substep's state, k = 1).
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_frame(WinArgs A, int t) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
   if (t == 0) {
     load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
@@ -226,31 +231,35 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_frame(WinArgs A, int t) {
   frame_begin(A, m, E, env, t, ln);
 }
 
+template <int NV>
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_substep(WinArgs A, int t, int sub) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
   int gi = t * S + sub;
   load_qqd(m, E, A.ckpt + ((size_t)gi * N + env) * nqv, ln);
   const real* at = A.actions + ((size_t)t * N + env) * na;
   for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
   __syncthreads();
-  real Lrow[SIM_MAXV], Lcol[SIM_MAXV], minpiv;
-  substep_forward(m, E, jr, cr, ln, Lrow, Lcol, true, minpiv);
+  Chol C;
+  real minpiv;
+  substep_forward<NV>(m, E, jr, cr, ln, C, true, minpiv);
   store_qqd(m, E, A.ckpt + ((size_t)(gi + 1) * N + env) * nqv, ln);
 }
 
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_end(WinArgs A) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
   load_qqd(m, E, A.ckpt + ((size_t)(A.h * S) * N + env) * nqv, ln);
   const real* ap = A.actions + ((size_t)(A.h - 1) * N + env) * na;
@@ -259,14 +268,14 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_end(WinArgs A) {
   window_end(A, m, E, env, ln);
 }
 
-__device__ __forceinline__ void adj_load(const DevModel* __restrict__ m, EnvLDS& E, const real* src, int ln) {
+__device__ __forceinline__ void adj_load(const Scal* __restrict__ m, EnvLDS& E, const real* src, int ln) {
   int nq = m->nq, nv = m->nv, na = m->na;
   for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = i < nq ? src[i] : RL(0.0);
   for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = i < nv ? src[nq + i] : RL(0.0);
   for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = i < na ? src[nq + nv + i] : RL(0.0);
   __syncthreads();
 }
-__device__ __forceinline__ void adj_store(const DevModel* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
+__device__ __forceinline__ void adj_store(const Scal* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
   int nq = m->nq, nv = m->nv, na = m->na;
   for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.qb[i];
   for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qdb[i];
@@ -275,22 +284,25 @@ __device__ __forceinline__ void adj_store(const DevModel* __restrict__ m, const 
 
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_seed(WinArgs A) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   adjoint_seed(A, m, E, env, ln);
   adj_store(m, E, A.adj + (size_t)env * (m->nq + m->nv + m->na), ln);
 }
 
+template <int NV>
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_substep(WinArgs A, int t, int sub) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nqv = m->nq + m->nv, N = A.N, na = m->na;
   real* adj = A.adj + (size_t)env * (nqv + na);
   adj_load(m, E, adj, ln);
@@ -298,17 +310,18 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_substep(WinArgs A, int t
   const real* at = A.actions_fw + ((size_t)t * N + env) * na;
   for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
   __syncthreads();
-  substep_adjoint(m, E, jr, cr, ln);
+  substep_adjoint<NV>(m, E, jr, cr, ln);
   adj_store(m, E, adj, ln);
 }
 
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_frame(WinArgs A, int t) {
   __shared__ EnvLDS E;
-  const DevModel* __restrict__ m = A.model;
+  const Scal scl = load_scal(A.model);
+  const Scal* m = &scl;
   const int env = blockIdx.x, ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
-  load_regs(m, E, ln, jr, cr);
+  load_regs(A.model, E, ln, jr, cr);
   const int nqv = m->nq + m->nv, na = m->na, ns = m->ns, nq = m->nq, nv = m->nv;
   real* adj = A.adj + (size_t)env * (nqv + na);
   adj_load(m, E, adj, ln);
@@ -323,49 +336,76 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_frame(WinArgs A, int t) 
   }
 }
 
-// weights [out][in] -> [in][out]
-__global__ void k_transpose(const real* __restrict__ W, real* __restrict__ WT, int no, int ni) {
+// zero-padded weight copies: WT [in][pad64(out)] and Wp [out][pad64(in)] from W [out][in]
+__global__ void k_prep_weights(const real* __restrict__ W, real* __restrict__ WT, real* __restrict__ Wp,
+                               int no, int ni) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < no * ni) {
-    int o = idx / ni, i = idx % ni;
-    WT[(size_t)i * no + o] = W[idx];
+  int nop = pad64(no), nip = pad64(ni);
+  if (idx < ni * nop) {
+    int i = idx / nop, o = idx % nop;
+    WT[idx] = (o < no) ? W[(size_t)o * ni + i] : RL(0.0);
+  }
+  if (idx < no * nip) {
+    int o = idx / nip, i = idx % nip;
+    Wp[idx] = (i < ni) ? W[(size_t)o * ni + i] : RL(0.0);
   }
 }
 
-
 // ======================================================================= launchers
-int launch_transpose(const real* W, real* WT, int n_out, int n_in, void* stream) {
-  int n = n_out * n_in;
-  hipLaunchKernelGGL(k_transpose, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, W, WT, n_out, n_in);
+int launch_prep_weights(const real* W, real* WT, real* Wp, int n_out, int n_in, void* stream) {
+  int n = n_in * pad64(n_out) > n_out * pad64(n_in) ? n_in * pad64(n_out) : n_out * pad64(n_in);
+  hipLaunchKernelGGL(k_prep_weights, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, W, WT, Wp, n_out, n_in);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_forward(const WinArgs& A, int plain, int substeps, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
+template <int NV>
+static void launch_forward_nv(const WinArgs& A, int plain, int substeps, hipStream_t s) {
   dim3 grid(A.N), block(SIM_WAVE);
   if (!plain) {
-    hipLaunchKernelGGL(k_window_fwd, grid, block, 0, s, A);
+    hipLaunchKernelGGL(k_window_fwd<NV>, grid, block, 0, s, A);
   } else {
     for (int t = 0; t < A.h; ++t) {
       hipLaunchKernelGGL(k_plain_frame, grid, block, 0, s, A, t);
-      for (int sub = 0; sub < substeps; ++sub) hipLaunchKernelGGL(k_plain_substep, grid, block, 0, s, A, t, sub);
+      for (int sub = 0; sub < substeps; ++sub) hipLaunchKernelGGL(k_plain_substep<NV>, grid, block, 0, s, A, t, sub);
     }
     hipLaunchKernelGGL(k_plain_end, grid, block, 0, s, A);
+  }
+}
+
+template <int NV>
+static void launch_adjoint_nv(const WinArgs& A, int plain, int substeps, hipStream_t s) {
+  dim3 grid(A.N), block(SIM_WAVE);
+  if (!plain) {
+    hipLaunchKernelGGL(k_window_adj<NV>, grid, block, 0, s, A);
+  } else {
+    hipLaunchKernelGGL(k_plain_adj_seed, grid, block, 0, s, A);
+    for (int t = A.h - 1; t >= 0; --t) {
+      for (int sub = substeps - 1; sub >= 0; --sub)
+        hipLaunchKernelGGL(k_plain_adj_substep<NV>, grid, block, 0, s, A, t, sub);
+      hipLaunchKernelGGL(k_plain_adj_frame, grid, block, 0, s, A, t);
+    }
+  }
+}
+
+// DOF counts with a kernel of their own (SIM_NV_LIST, set per arithmetic type); every
+// other model runs the padded 32-DOF kernel
+#define SIM_NV_CASE_F(n) case n: launch_forward_nv<n>(A, plain, substeps, s); break;
+#define SIM_NV_CASE_A(n) case n: launch_adjoint_nv<n>(A, plain, substeps, s); break;
+
+int launch_forward(const WinArgs& A, int plain, int substeps, int nv, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (nv) {
+    SIM_NV_LIST(SIM_NV_CASE_F)
+    default: launch_forward_nv<SIM_MAXV>(A, plain, substeps, s);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_adjoint(const WinArgs& A, int plain, int substeps, void* stream) {
+int launch_adjoint(const WinArgs& A, int plain, int substeps, int nv, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  dim3 grid(A.N), block(SIM_WAVE);
-  if (!plain) {
-    hipLaunchKernelGGL(k_window_adj, grid, block, 0, s, A);
-  } else {
-    hipLaunchKernelGGL(k_plain_adj_seed, grid, block, 0, s, A);
-    for (int t = A.h - 1; t >= 0; --t) {
-      for (int sub = substeps - 1; sub >= 0; --sub) hipLaunchKernelGGL(k_plain_adj_substep, grid, block, 0, s, A, t, sub);
-      hipLaunchKernelGGL(k_plain_adj_frame, grid, block, 0, s, A, t);
-    }
+  switch (nv) {
+    SIM_NV_LIST(SIM_NV_CASE_A)
+    default: launch_adjoint_nv<SIM_MAXV>(A, plain, substeps, s);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -11,7 +11,25 @@ typedef DevModelT<real> DevModel;
 typedef MlpArgsT<real> MlpArgs;
 typedef WinArgsT<real> WinArgs;
 
+// Uniform model scalars, copied once per kernel into registers (the tables in global
+// memory are read only at kernel start).
+struct Scal {
+  int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
+  real dt_sub, g, kn, kd, kt, mu, klim;
+};
+__device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
+  Scal s;
+  s.J = m->J; s.nq = m->nq; s.nv = m->nv; s.na = m->na; s.nc = m->nc; s.ns = m->ns; s.od = m->od;
+  s.task = m->task; s.floating = m->floating; s.has_last_action = m->has_last_action;
+  s.substeps = m->substeps; s.max_depth = m->max_depth;
+  s.dt_sub = m->dt_sub; s.g = m->g; s.kn = m->kn; s.kd = m->kd; s.kt = m->kt; s.mu = m->mu; s.klim = m->klim;
+  return s;
+}
+
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+// reciprocal square root: hardware v_rsq in FP32 (about 1 ulp), exact division in FP64
+__device__ __forceinline__ float m_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double m_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ void m_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sincos(x, s, c); }

@@ -7,6 +7,57 @@
 // output with tanh.
 
 
+// The library keeps two zero-padded copies of every weight matrix in its workspace:
+// WT [in][out_pad] for the forward (lane = output) and W [out][in_pad] for the input
+// adjoint (lane = input), pad = next multiple of 64, so that the inner loops have a
+// compile-time chunk count and unconditional, coalesced loads.
+__host__ __device__ __forceinline__ int pad64(int n) { return (n + SIM_WAVE - 1) / SIM_WAVE * SIM_WAVE; }
+
+template <int NCH>
+__device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const real* __restrict__ bb,
+                                              const real* in, real* dst, int ni, int no, bool hidden, int ln) {
+  const int nop = NCH * SIM_WAVE;
+  real acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    int o = c * SIM_WAVE + ln;
+    acc[c] = (o < no) ? bb[o] : RL(0.0);
+  }
+#pragma unroll 8
+  for (int i = 0; i < ni; ++i) {
+    real xi = in[i];
+    const real* row = WT + (size_t)i * nop + ln;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = m_fma(row[c * SIM_WAVE], xi, acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    int o = c * SIM_WAVE + ln;
+    if (o < no) {
+      real z = acc[c];
+      dst[o] = (hidden && z <= RL(0.0)) ? m_expm1(z) : z;
+    }
+  }
+}
+
+template <int NCH>
+__device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const real* g, real* acc_out,
+                                              int ni, int no, int ln) {
+  const int nip = NCH * SIM_WAVE;
+  real acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = RL(0.0);
+#pragma unroll 8
+  for (int o = 0; o < no; ++o) {
+    real go = g[o];
+    const real* row = W + (size_t)o * nip + ln;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = m_fma(row[c * SIM_WAVE], go, acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc_out[c] = acc[c];
+}
+
 // x (LDS, dims[0]) -> out (LDS, dims[nl]); hidden activations kept in h0 / h1 (<= 2 hidden)
 __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, real* h0, real* h1,
                                             real* out, int ln) {
@@ -14,31 +65,16 @@ __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, rea
   for (int l = 0; l < P.nl; ++l) {
     int ni = P.dims[l], no = P.dims[l + 1];
     real* dst = (l == P.nl - 1) ? out : ((l & 1) ? h1 : h0);
-    const real* __restrict__ WT = P.WT[l];
-    const real* __restrict__ bb = P.b[l];
-    real acc[SIM_MAXHID / SIM_WAVE];
-#pragma unroll
-    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
-      int o = c * SIM_WAVE + ln;
-      acc[c] = (o < no) ? bb[o] : RL(0.0);
-    }
-    for (int i = 0; i < ni; ++i) {
-      real xi = in[i];
-      const real* row = WT + (size_t)i * no;
-#pragma unroll
-      for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
-        int o = c * SIM_WAVE + ln;
-        if (c * SIM_WAVE < no && o < no) acc[c] = m_fma(row[o], xi, acc[c]);
-      }
-    }
     bool hidden = l < P.nl - 1;
-#pragma unroll
-    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
-      int o = c * SIM_WAVE + ln;
-      if (o < no) {
-        real z = acc[c];
-        dst[o] = (hidden && z <= RL(0.0)) ? m_expm1(z) : z;
-      }
+    switch (pad64(no) / SIM_WAVE) {
+      case 1: mlp_layer_fwd<1>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 2: mlp_layer_fwd<2>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 3: mlp_layer_fwd<3>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 4: mlp_layer_fwd<4>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 5: mlp_layer_fwd<5>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 6: mlp_layer_fwd<6>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 7: mlp_layer_fwd<7>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      default: mlp_layer_fwd<8>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
     }
     __syncthreads();
     in = dst;
@@ -52,19 +88,17 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
   real* g = gout;
   for (int l = P.nl - 1; l >= 0; --l) {
     int ni = P.dims[l], no = P.dims[l + 1];
-    const real* __restrict__ W = P.W[l];
     real* dst = (l == 0) ? xbar : gbuf;
     real acc[SIM_MAXHID / SIM_WAVE];
-#pragma unroll
-    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) acc[c] = RL(0.0);
-    for (int o = 0; o < no; ++o) {
-      real go = g[o];
-      const real* row = W + (size_t)o * ni;
-#pragma unroll
-      for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
-        int i = c * SIM_WAVE + ln;
-        if (c * SIM_WAVE < ni && i < ni) acc[c] = m_fma(row[i], go, acc[c]);
-      }
+    switch (pad64(ni) / SIM_WAVE) {
+      case 1: mlp_layer_vjp<1>(P.W[l], g, acc, ni, no, ln); break;
+      case 2: mlp_layer_vjp<2>(P.W[l], g, acc, ni, no, ln); break;
+      case 3: mlp_layer_vjp<3>(P.W[l], g, acc, ni, no, ln); break;
+      case 4: mlp_layer_vjp<4>(P.W[l], g, acc, ni, no, ln); break;
+      case 5: mlp_layer_vjp<5>(P.W[l], g, acc, ni, no, ln); break;
+      case 6: mlp_layer_vjp<6>(P.W[l], g, acc, ni, no, ln); break;
+      case 7: mlp_layer_vjp<7>(P.W[l], g, acc, ni, no, ln); break;
+      default: mlp_layer_vjp<8>(P.W[l], g, acc, ni, no, ln); break;
     }
     __syncthreads();   // every lane has read g before dst (which may alias g) is written
     const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
@@ -87,7 +121,7 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
 
 // --------------------------------------------------------------- observations
 // s = [q | qd | a_prev];  obs written to o (LDS)
-__device__ __forceinline__ void task_obs(const DevModel* __restrict__ m, const real* q, const real* qd,
+__device__ __forceinline__ void task_obs(const Scal* __restrict__ m, const real* q, const real* qd,
                                          const real* aprev, real* o, int ln) {
   if (m->task == TASK_CARTPOLE) {
     if (ln == 0) {
@@ -117,7 +151,7 @@ __device__ __forceinline__ void task_obs(const DevModel* __restrict__ m, const r
 }
 
 // adjoint of task_obs: adds (d obs / d s)^T obar to (qb, qdb, abar_prev)
-__device__ __forceinline__ void task_obs_vjp(const DevModel* __restrict__ m, const real* q, const real* ob,
+__device__ __forceinline__ void task_obs_vjp(const Scal* __restrict__ m, const real* q, const real* ob,
                                              real* qb, real* qdb, real* apb, int ln) {
   if (m->task == TASK_CARTPOLE) {
     if (ln == 0) {
@@ -153,7 +187,7 @@ __device__ __forceinline__ void task_obs_vjp(const DevModel* __restrict__ m, con
 }
 
 // --------------------------------------------------------------- rewards
-__device__ __forceinline__ real task_reward(const DevModel* __restrict__ m, const real* q, const real* qd,
+__device__ __forceinline__ real task_reward(const Scal* __restrict__ m, const real* q, const real* qd,
                                              const real* a, int ln) {
   real r = RL(0.0);
   if (m->task == TASK_CARTPOLE) {
@@ -182,7 +216,7 @@ __device__ __forceinline__ real task_reward(const DevModel* __restrict__ m, cons
 }
 
 // adds c * dR/ds to (qb, qdb) and c * dR/da to abar
-__device__ __forceinline__ void task_reward_vjp(const DevModel* __restrict__ m, const real* q, const real* qd,
+__device__ __forceinline__ void task_reward_vjp(const Scal* __restrict__ m, const real* q, const real* qd,
                                                 const real* a, real c, real* qb, real* qdb, real* abar,
                                                 int ln) {
   if (m->task == TASK_CARTPOLE) {

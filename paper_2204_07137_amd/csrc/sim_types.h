@@ -13,6 +13,7 @@
 #define SIM_MAXOBS 128   // observation width
 #define SIM_MAXHID 512   // MLP width
 #define SIM_MAXL 4       // MLP linear layers
+#define SIM_MAXPAIR 576  // (frame, ancestor-or-self) pairs of the mass matrix, 9 rounds of 64 lanes
 
 enum { J_FREE = 0, J_HINGE = 1, J_SLIDE = 2 };
 enum { TASK_NONE = 0, TASK_CARTPOLE = 1, TASK_ANT = 2, TASK_HUMANOID = 3 };
@@ -29,15 +30,21 @@ struct DevModelT {
   T armature[SIM_MAXV];
   int cbody[SIM_MAXC];
   T cpos[SIM_MAXC * 3], crad[SIM_MAXC];
+  unsigned int cmask[SIM_MAXJ];   // bit c set when contact c belongs to frame j
+  // mass-matrix entries M[va_k][va_i] for every non-root frame i and every k in its
+  // ancestors-or-self: packed i | k << 5 | va_i << 10 | va_k << 15 | (k is FREE) << 20 | 1 << 21
+  int npair;
+  int pair[SIM_MAXPAIR];
 };
 
 template <typename T>
 struct MlpArgsT {
   int nl;                      // linear layers
   int dims[SIM_MAXL + 1];
-  const T* W[SIM_MAXL];        // [out][in] row-major (caller layout)
-  const T* WT[SIM_MAXL];       // [in][out] (library copy in the workspace)
-  const T* b[SIM_MAXL];
+  const T* W[SIM_MAXL];        // [out][pad64(in)] zero-padded copy (workspace)
+  const T* WT[SIM_MAXL];       // [in][pad64(out)] zero-padded copy (workspace)
+  const T* b[SIM_MAXL];        // [out] (caller)
+  const T* src[SIM_MAXL];      // [out][in] caller weights, copied by the prep kernel
 };
 
 template <typename T>
@@ -68,9 +75,9 @@ struct WinArgsT {
 // Launchers implemented once per arithmetic type (kernels_f32.hip, kernels_f64.hip).
 #define SIM_DECLARE_LAUNCHERS(NS, T)                                                        \
   namespace NS {                                                                            \
-  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, void* stream);         \
-  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, void* stream);         \
-  int launch_transpose(const T* W, T* WT, int n_out, int n_in, void* stream);              \
+  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
+  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
+  int launch_prep_weights(const T* W, T* WT, T* Wp, int n_out, int n_in, void* stream);   \
   }
 SIM_DECLARE_LAUNCHERS(sim_f32, float)
 SIM_DECLARE_LAUNCHERS(sim_f64, double)
