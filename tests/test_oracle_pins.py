@@ -552,3 +552,75 @@ def test_window_adjoint_fd_open_loop_ant():
     coords_a = [(0, 0, 1), (1, 0, 6), (0, 0, 3)]
     coords_s = [(0, 2), (0, 20), (0, 33)]
     _fd_check(W, h, [11], coords_a, coords_s, 1e-6, 1e-5, closed_loop=False)
+
+
+# ------------------------------------------------------------------ the paper's printed constants
+
+def _golden():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def test_reward_coefficients_match_the_paper():
+    G = _golden()
+    m = OracleModel(wl.cartpole())
+    c = G["cartpole_reward"]
+    base = T([[0.0, 0.0, 0.0, 0.0]])
+    for idx, key in ((1, "theta2"), (3, "thetadot2"), (0, "x2"), (2, "xdot2")):
+        s = base.clone()
+        s[0, idx] = 0.5
+        assert float(reward_fn(m, s, torch.zeros(1, 1, dtype=F64))[0]) == pytest.approx(c[key] * 0.25)
+    for name in ("ant", "humanoid"):
+        W = wl.workload(name, 1)
+        m = OracleModel(W["model"])
+        g = G[f"{name}_reward"]
+        ns = W["s0"].shape[1]
+        s = torch.zeros(1, ns, dtype=F64)
+        s[0, 3] = 1.0
+        a = torch.zeros(1, m.na, dtype=F64)
+        if name == "ant":
+            s[0, 2] = 1.0
+            r0 = float(reward_fn(m, s, a)[0])
+            assert r0 == pytest.approx(g["up"] + g["heading"] + 1.0 - g["height_offset"])
+        else:
+            s[0, 2] = g["height_target"] + 0.05
+            r0 = float(reward_fn(m, s, a)[0])
+            assert r0 == pytest.approx(g["up"] + g["heading"] + g["above"] * 0.05)
+            s2 = s.clone()
+            s2[0, 2] = g["height_target"] - 0.3
+            assert float(reward_fn(m, s2, a)[0]) == pytest.approx(g["up"] + g["heading"] + g["below"] * 0.09)
+            s3 = s.clone()
+            s3[0, 2] = g["height_target"] + 5.0
+            assert float(reward_fn(m, s3, a)[0]) == pytest.approx(g["up"] + g["heading"] + g["above"] * g["clip_hi"])
+            a2 = torch.full((1, m.na), 0.5, dtype=F64)
+            assert float(reward_fn(m, s, a2)[0]) == pytest.approx(r0 + g["action"] * 0.25 * m.na)
+        s4 = s.clone()
+        s4[0, m.nq] = 0.7
+        assert float(reward_fn(m, s4, a)[0]) == pytest.approx(r0 + g["vx"] * 0.7)
+
+
+def test_obs_and_action_dimensions_match_the_paper():
+    G = _golden()
+    for name in ("cartpole", "ant", "humanoid"):
+        W = wl.workload(name, 2)
+        m = OracleModel(W["model"])
+        o = obs_fn(m, T(W["s0"]))
+        assert o.shape[1] == G["obs_dims"][name]
+        assert m.na == G["action_dims"][name]
+
+
+def test_discounted_loss_closed_form():
+    """CartPole hanging at rest with zero actions and a constant critic c0:
+    L = pi^2 (1 - g^h) / ((1 - g) h) - g^h c0 / h."""
+    G = _golden()
+    gamma, h = G["gamma"]["value"], G["horizon"]["value"]
+    md = wl.cartpole()
+    N = 3
+    s0 = np.tile([[0.0, np.pi, 0.0, 0.0]], (N, 1))
+    c0 = 0.37
+    critic = [(np.zeros((4, 5)), np.zeros(4)), (np.zeros((1, 4)), np.array([c0]))]
+    acts = np.zeros((h, N, 1))
+    out = oracle_window(md, s0, h, None, critic, actions=acts, gamma=gamma)
+    ref = np.pi ** 2 * (1 - gamma ** h) / ((1 - gamma) * h) - gamma ** h * c0 / h
+    assert float(out["loss"]) == pytest.approx(ref, rel=1e-12)
