@@ -119,6 +119,10 @@ typedef struct SimOptions {
   int critic_dims[SIM_MAX_LAYERS + 1];
   double gamma;                  /* discount */
   int precision;                 /* SIM_PREC_FP32 or SIM_PREC_FP64 (arithmetic and I/O type) */
+  double chol_fp64_threshold;    /* FP32 path: an environment's mass matrix is refactorised in
+                                    FP64 for a substep whose smallest Cholesky pivot is <= this
+                                    times its largest diagonal entry, or not finite (1e-6 is the
+                                    documented default; a value > 1 forces FP64 every substep) */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;
@@ -138,6 +142,7 @@ typedef struct SimForwardIO {
   void* rewards;                            /* [h][N] out */
   void* value;                              /* [N] out: critic value of s_h */
   uint8_t* nonfinite;                       /* [N] out, optional: 1 if s_h is not finite */
+  int32_t* fp64_refactor_count;             /* [N] out, optional: substeps refactorised in FP64 */
 } SimForwardIO;
 
 typedef struct SimAdjointIO {

@@ -39,14 +39,14 @@ class SimOptions(ctypes.Structure):
     _fields_ = [("n_envs", _i), ("horizon", _i), ("ckpt_interval", _i), ("path", _i),
                 ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
                 ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
-                ("precision", _i)]
+                ("precision", _i), ("chol_fp64_threshold", _d)]
 
 
 class SimForwardIO(ctypes.Structure):
     _fields_ = [("s0", _p), ("actions_in", _p), ("actor_w", _p * MAXL), ("actor_b", _p * MAXL),
                 ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("workspace", _p),
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
-                ("rewards", _p), ("value", _p), ("nonfinite", _p)]
+                ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p)]
 
 
 class SimAdjointIO(ctypes.Structure):
@@ -143,7 +143,7 @@ class Sim:
     """One handle: a model, a batch size N, a horizon h and the MLP shapes."""
 
     def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
-                 path=PATH_PERSISTENT, gamma=0.99, precision="fp32"):
+                 path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6):
         import torch
         self.torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -166,6 +166,7 @@ class Sim:
             o.critic_dims[i] = int(v)
         o.gamma = float(gamma)
         o.precision = PREC[precision]
+        o.chol_fp64_threshold = float(chol_fp64_threshold)
         h = _p()
         _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
         self.h = h
@@ -218,6 +219,7 @@ class Sim:
             rewards=t.empty(H, N, device="cuda", dtype=dt),
             value=t.empty(N, device="cuda", dtype=dt),
             nonfinite=t.zeros(N, dtype=t.uint8, device="cuda"),
+            fp64_refactor_count=t.zeros(N, dtype=t.int32, device="cuda"),
         )
         io = SimForwardIO()
         io.s0 = self._ptr(s0)
@@ -229,7 +231,7 @@ class Sim:
         self._set_weights(io, actor, critic, out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
-        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite"):
+        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count"):
             setattr(io, k, self._ptr(out[k]))
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))

@@ -49,6 +49,7 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   std::memcpy(&d, &s, offsetof(DevModelT<double>, dt_sub));   // leading ints
   d.dt_sub = (T)s.dt_sub; d.g = (T)s.g; d.kn = (T)s.kn; d.kd = (T)s.kd; d.kt = (T)s.kt; d.mu = (T)s.mu;
   d.klim = (T)s.klim;
+  d.chol_thr = (T)s.chol_thr;
   for (int j = 0; j < SIM_MAXJ; ++j) {
     d.parent[j] = s.parent[j]; d.jtype[j] = s.jtype[j]; d.qadr[j] = s.qadr[j]; d.vadr[j] = s.vadr[j];
     d.depth[j] = s.depth[j]; d.first_child[j] = s.first_child[j]; d.next_sib[j] = s.next_sib[j];
@@ -212,6 +213,7 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   rc = check_options(opt, m);
   if (rc) return rc;
   SimHandle* h = new SimHandle();
+  m.chol_thr = opt->chol_fp64_threshold;
   h->m64 = m;
   convert_model(m, h->m32);
   h->opt = *opt;
@@ -348,6 +350,7 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   A.s_h = static_cast<T*>(io->s_h); A.obs = static_cast<T*>(io->obs); A.actions = static_cast<T*>(io->actions);
   A.rewards = static_cast<T*>(io->rewards); A.value = static_cast<T*>(io->value);
   A.nonfinite = io->nonfinite;
+  A.fallback = io->fp64_refactor_count;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.seg = reinterpret_cast<T*>(ws + h->off_seg);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);

@@ -17,13 +17,12 @@
 // form from subtree sums of spatial vectors (no derivative of M or of the factor).
 
 #define SIM_PAIR_ROUNDS (SIM_MAXPAIR / SIM_WAVE)
+// per-lane joint constants kept in registers; the larger per-joint tables (offsets, axes,
+// centres of mass, inertias, mass-matrix pairs) are copied to LDS once per kernel
 struct JointRegs {
-  int par, type, qa, va, depth, fc, act, lim;
-  int pair[SIM_PAIR_ROUNDS];   // this lane's mass-matrix pairs, one per round (0 = none)
+  int par, type, qa, va, depth, act, lim, npair;
   unsigned int cmask;
   real lo, hi, gear, mass, arm;
-  f3 off, ax, com;
-  real I6[6];
 };
 struct ContactRegs {
   int body;
@@ -50,9 +49,16 @@ struct EnvLDS {
   // topology copies for arbitrary-index lookups
   int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ];
   real arm[SIM_MAXV];
+  real j_off[SIM_MAXJ][3], j_ax[SIM_MAXJ][3], j_com[SIM_MAXJ][3], j_I6[SIM_MAXJ][6];
+  int pairs[SIM_MAXPAIR];
   // policy / critic
   real obs[SIM_MAXOBS];
-  real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
+  union {
+    struct {
+      real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
+    };
+    double M64[SIM_MAXV][SIM_MAXV];   // FP64 refactorisation (never live at the same time as the MLP)
+  };
   real red[4];
 };
 
@@ -61,18 +67,22 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, EnvLDS
   int j = ln < m->J ? ln : 0;
   jr.par = m->parent[j]; jr.type = m->jtype[j]; jr.qa = m->qadr[j]; jr.va = m->vadr[j];
   jr.depth = ln < m->J ? m->depth[j] : -1;
-  jr.fc = m->first_child[j]; jr.act = m->act_of_joint[j]; jr.lim = m->limited[j];
+  jr.act = m->act_of_joint[j]; jr.lim = m->limited[j];
   jr.lo = m->lower[j]; jr.hi = m->upper[j]; jr.gear = m->gear[j]; jr.mass = m->mass[j];
   jr.cmask = ln < m->J ? m->cmask[j] : 0u;
-#pragma unroll
-  for (int r = 0; r < SIM_PAIR_ROUNDS; ++r) {
-    int pi = r * SIM_WAVE + ln;
-    jr.pair[r] = pi < m->npair ? m->pair[pi] : 0;
-  }
   jr.arm = m->armature[m->vadr[j]];
-  jr.off = ld3(&m->offset[3 * j]); jr.ax = ld3(&m->axis[3 * j]); jr.com = ld3(&m->com[3 * j]);
+  jr.npair = m->npair;
+  for (int p = ln; p < m->npair; p += SIM_WAVE) E.pairs[p] = m->pair[p];
+  if (ln < SIM_MAXJ) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) jr.I6[k] = m->inertia[6 * j + k];
+    for (int k = 0; k < 3; ++k) {
+      E.j_off[ln][k] = m->offset[3 * ln + k];
+      E.j_ax[ln][k] = m->axis[3 * ln + k];
+      E.j_com[ln][k] = m->com[3 * ln + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) E.j_I6[ln][k] = m->inertia[6 * ln + k];
+  }
   int c = ln < m->nc ? ln : 0;
   cr.body = m->cbody[c]; cr.pos = ld3(&m->cpos[3 * c]); cr.rad = m->crad[c];
   if (ln < SIM_MAXJ) {
@@ -216,6 +226,52 @@ __device__ __forceinline__ real chol_solve(const Chol& C, int ln, real b) {
   return y;
 }
 
+// --------------------------------------------------------------- FP64 fallback factorisation
+// When the FP32 factorisation meets a pivot below chol_thr times the largest diagonal (or
+// a non-finite pivot), the environment's mass matrix is refactorised in double precision
+// in LDS (lane = row) and both solves of the substep use that factor.
+template <int NV>
+__device__ __forceinline__ void chol64_factor(EnvLDS& E, int nv, int ln) {
+  if (ln < NV) {
+#pragma unroll 1
+    for (int k = 0; k < NV; ++k)
+      E.M64[ln][k] = (ln < nv && k < nv) ? (double)E.M[ln][k] : (ln == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int k = 0; k < NV; ++k) {
+    double piv = E.M64[k][k];
+    double d = sqrt(piv);
+    double lk = (ln > k && ln < NV) ? E.M64[ln][k] / d : 0.0;
+    __syncthreads();
+    if (ln == k) E.M64[k][k] = d;
+    if (ln > k && ln < NV) E.M64[ln][k] = lk;
+    __syncthreads();
+    if (ln > k && ln < NV)
+#pragma unroll 1
+      for (int j = k + 1; j <= ln; ++j) E.M64[ln][j] -= lk * E.M64[j][k];
+    __syncthreads();
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double chol64_solve(EnvLDS& E, int ln, double b) {
+  double y = b;
+#pragma unroll 1
+  for (int k = 0; k < NV; ++k) {
+    double yk = rdl(y, k) / E.M64[k][k];
+    if (ln == k) y = yk;
+    else if (ln > k && ln < NV) y -= E.M64[ln][k] * yk;
+  }
+#pragma unroll 1
+  for (int k = NV - 1; k >= 0; --k) {
+    double xk = rdl(y, k) / E.M64[k][k];
+    if (ln == k) y = xk;
+    else if (ln < k) y -= E.M64[k][ln] * xk;
+  }
+  return y;
+}
+
 // --------------------------------------------------------------- subtree sums
 // Adds every frame's row of a table into its parent's row, children before parents
 // (frames are listed parents first); each active lane owns one column.  The parent index
@@ -234,7 +290,7 @@ __device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active
 template <int NV>
 __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvLDS& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln,
-                                                Chol& C, bool inplace, real& minpiv) {
+                                                Chol& C, bool inplace, int& fb) {
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real g = m->g;
   const real dt = m->dt_sub;
@@ -257,7 +313,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
         real sn, cs;
         m_sincos(qj, &sn, &cs);
         real omc = RL(1.0) - cs;
-        f3 a = jr.ax;
+        f3 a = ld3(E.j_ax[ln]);
         // Rodrigues: Rot = I + sn K + (1 - cs) K^2 with K = [a]x, K^2 = a a^T - I
         Rot[0] = RL(1.0) + omc * (a.x * a.x - RL(1.0)); Rot[1] = -sn * a.z + omc * a.x * a.y; Rot[2] = sn * a.y + omc * a.x * a.z;
         Rot[3] = sn * a.z + omc * a.y * a.x; Rot[4] = RL(1.0) + omc * (a.y * a.y - RL(1.0)); Rot[5] = -sn * a.x + omc * a.y * a.z;
@@ -297,19 +353,19 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
           vp = zsv();
           ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
         }
-        f3 sh = mv3(Rp, jr.ax);
+        f3 sh = mv3(Rp, ld3(E.j_ax[ln]));
         if (jr.type == J_HINGE) {
 #pragma unroll
           for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
               R[3 * r + c] = Rp[3 * r] * Rot[c] + Rp[3 * r + 1] * Rot[3 + c] + Rp[3 * r + 2] * Rot[6 + c];
-          p = add3(pp, mv3(Rp, jr.off));
+          p = add3(pp, mv3(Rp, ld3(E.j_off[ln])));
           S = mksv(sh, cross3(p, sh));
         } else {
 #pragma unroll
           for (int k = 0; k < 9; ++k) R[k] = Rp[k];
-          p = add3(add3(pp, mv3(Rp, jr.off)), scl3(sh, qj));
+          p = add3(add3(pp, mv3(Rp, ld3(E.j_off[ln]))), scl3(sh, qj));
           S = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
         }
         sv u = sclsv(S, qdj);
@@ -344,9 +400,9 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
   // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
   if (ln < J) {
     real mass = jr.mass;
-    f3 c = add3(p, mv3(R, jr.com));
+    f3 c = add3(p, mv3(R, ld3(E.j_com[ln])));
     // Ic_w = R I R^T
-    const real* I6 = jr.I6;
+    const real* I6 = E.j_I6[ln];
     real Il[9] = {I6[0], I6[3], I6[4], I6[3], I6[1], I6[5], I6[4], I6[5], I6[2]};
     real T[9];
 #pragma unroll
@@ -435,9 +491,9 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
   }
   __syncthreads();
   // ---- CRBA entries M[va_k][va_i] = S_k . F_i, one (frame, ancestor) pair per lane and round
-#pragma unroll
-  for (int r = 0; r < SIM_PAIR_ROUNDS; ++r) {
-    int pk = jr.pair[r];
+  for (int r = 0; r * SIM_WAVE < jr.npair; ++r) {
+    int pi = r * SIM_WAVE + ln;
+    int pk = pi < jr.npair ? E.pairs[pi] : 0;
     if (pk) {
       int i = pk & 31, k = (pk >> 5) & 31, vi = (pk >> 10) & 31, vk = (pk >> 15) & 31;
       sv Fi = ldsv(E.Fi[i]);
@@ -459,19 +515,28 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
 #pragma unroll
   for (int k = 0; k < NV; ++k)
     C.row[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : ((ln == k) ? RL(1.0) : RL(0.0));
+  real minpiv;
+  real dmax = wave_max(ln < nv ? E.M[ln < nv ? ln : 0][ln < nv ? ln : 0] : RL(0.0));
   chol_factor<NV>(C, ln, minpiv);
-  __syncthreads();
-  if (ln < nv) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-      if (k < nv) E.M[ln][k] = C.row[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k)
-    C.col[k] = (ln < nv && k < nv) ? E.M[k][ln < nv ? ln : 0] : ((ln == k) ? RL(1.0) : RL(0.0));
+  fb = 0;
+  if (sizeof(real) == 4 && !(minpiv > m->chol_thr * dmax)) fb = 1;
   real b = ln < nv ? E.vec[ln] : RL(0.0);
-  real x = chol_solve<NV>(C, ln, b);
+  real x;
+  if (fb) {
+    chol64_factor<NV>(E, nv, ln);
+    x = (real)chol64_solve<NV>(E, ln, (double)b);
+  } else {
+    __syncthreads();
+    if (ln < NV) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) E.M[ln][k] = C.row[k];   // padded rows hold the identity
+    }
+    __syncthreads();
+    const int lc = ln < NV ? ln : 0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) C.col[k] = (ln < NV) ? E.M[k][lc] : RL(0.0);
+    x = chol_solve<NV>(C, ln, b);
+  }
   if (ln < nv) {
     E.qdd[ln] = x;
     real qdn = E.qd[ln] + dt * x;
@@ -513,8 +578,8 @@ template <int NV>
 __device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvLDS& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln) {
   Chol C;
-  real minpiv;
-  substep_forward<NV>(m, E, jr, cr, ln, C, false, minpiv);
+  int fb;
+  substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real dt = m->dt_sub;
   const real g = m->g;
@@ -552,7 +617,7 @@ __device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvL
   // ---- lambda = M^{-1} qdd_bar with the cached factor (lane = DOF)
   {
     real rb = ln < nv ? dt * E.qdb[ln] : RL(0.0);
-    real lam = chol_solve<NV>(C, ln, rb);
+    real lam = fb ? (real)chol64_solve<NV>(E, ln, (double)rb) : chol_solve<NV>(C, ln, rb);
     if (ln < nv) E.lam[ln] = lam;
   }
   __syncthreads();

@@ -84,16 +84,19 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
   const int S = m->substeps, nqv = m->nq + m->nv, N = A.N;
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
   Chol C;
+  int nfb = 0;
   for (int t = 0; t < A.h; ++t) {
     frame_begin(A, m, E, env, t, ln);
     for (int sub = 0; sub < S; ++sub) {
       int gi = t * S + sub;
       if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
-      real minpiv;
-      substep_forward<NV>(m, E, jr, cr, ln, C, true, minpiv);
+      int fb;
+      substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
+      nfb += fb;
     }
   }
   window_end(A, m, E, env, ln);
+  if (ln == 0 && A.fallback) A.fallback[env] = nfb;
 }
 
 // ======================================================================= persistent adjoint
@@ -185,8 +188,8 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
         __syncthreads();
         for (int i = 0; i < k - 1; ++i) {
           store_qqd(m, E, seg + (size_t)i * nqv, ln);
-          real minpiv;
-          substep_forward<NV>(m, E, jr, cr, ln, C, true, minpiv);
+          int fb;
+          substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
         }
         store_qqd(m, E, seg + (size_t)(k - 1) * nqv, ln);
         __syncthreads();
@@ -222,6 +225,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_frame(WinArgs A, int t) {
   if (t == 0) {
     load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
     store_qqd(m, E, A.ckpt + (size_t)env * nqv, ln);
+    if (ln == 0 && A.fallback) A.fallback[env] = 0;
   } else {
     load_qqd(m, E, A.ckpt + ((size_t)(t * S) * N + env) * nqv, ln);
     const real* ap = A.actions + ((size_t)(t - 1) * N + env) * na;
@@ -247,9 +251,10 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_substep(WinArgs A, int t, in
   for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
   __syncthreads();
   Chol C;
-  real minpiv;
-  substep_forward<NV>(m, E, jr, cr, ln, C, true, minpiv);
+  int fb;
+  substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
   store_qqd(m, E, A.ckpt + ((size_t)(gi + 1) * N + env) * nqv, ln);
+  if (ln == 0 && A.fallback) A.fallback[env] += fb;
 }
 
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_end(WinArgs A) {

@@ -15,7 +15,7 @@ typedef WinArgsT<real> WinArgs;
 // memory are read only at kernel start).
 struct Scal {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
-  real dt_sub, g, kn, kd, kt, mu, klim;
+  real dt_sub, g, kn, kd, kt, mu, klim, chol_thr;
 };
 __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   Scal s;
@@ -23,6 +23,7 @@ __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   s.task = m->task; s.floating = m->floating; s.has_last_action = m->has_last_action;
   s.substeps = m->substeps; s.max_depth = m->max_depth;
   s.dt_sub = m->dt_sub; s.g = m->g; s.kn = m->kn; s.kd = m->kd; s.kt = m->kt; s.mu = m->mu; s.klim = m->klim;
+  s.chol_thr = m->chol_thr;
   return s;
 }
 
@@ -119,6 +120,13 @@ __device__ __forceinline__ sv iapply(const real* I, sv v) {
   f3 Iw = mk3(I[4] * w.x + I[7] * w.y + I[8] * w.z, I[7] * w.x + I[5] * w.y + I[9] * w.z,
               I[8] * w.x + I[9] * w.y + I[6] * w.z);
   return mksv(add3(Iw, cross3(h, v.l)), add3(scl3(v.l, m), cross3(w, h)));
+}
+
+// wave-wide max (butterfly over 64 lanes)
+__device__ __forceinline__ real wave_max(real x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = m_fmax(x, __shfl_xor(x, off, SIM_WAVE));
+  return x;
 }
 
 // wave-wide sum (deterministic butterfly over 64 lanes)

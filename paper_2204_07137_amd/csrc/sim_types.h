@@ -22,6 +22,7 @@ template <typename T>
 struct DevModelT {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
   T dt_sub, g, kn, kd, kt, mu, klim;
+  T chol_thr;   // FP64 refactorisation when the smallest pivot <= chol_thr * largest diagonal
   int parent[SIM_MAXJ], jtype[SIM_MAXJ], qadr[SIM_MAXJ], vadr[SIM_MAXJ], depth[SIM_MAXJ];
   int first_child[SIM_MAXJ], next_sib[SIM_MAXJ], act_of_joint[SIM_MAXJ], limited[SIM_MAXJ];
   T offset[SIM_MAXJ * 3], axis[SIM_MAXJ * 3], mass[SIM_MAXJ], com[SIM_MAXJ * 3];
@@ -61,6 +62,7 @@ struct WinArgsT {
   T* rewards;
   T* value;
   uint8_t* nonfinite;
+  int* fallback;    // [N] substeps whose factorisation fell back to FP64 (optional)
   T* ckpt;          // [n_ckpt][N][nq+nv]
   T* seg;           // [N][k][nq+nv] segment pre-states (recompute)
   T* adj;           // [N][nq+nv+na] adjoint carried between plain launches

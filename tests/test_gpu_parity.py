@@ -231,3 +231,28 @@ def test_workspace_and_pointer_errors():
     sim.workspace = ws
     io = P.SimForwardIO()
     assert P.lib().sim_forward_window(sim.h, io, None) == -1
+
+
+def test_fp64_fallback_factorisation():
+    """The FP32 path refactorises in FP64 when the pivot test fails; a threshold above 1
+    forces it on every substep.  The forced path must still match the oracle, count every
+    substep, and leave the default path (no stiff configuration here) untouched."""
+    W = wl.workload("humanoid", 64)
+    h = 4
+    print("[fp64 fallback] humanoid", flush=True)
+    sim = P.Sim(W["model"], 64, h, [76, 256, 128, 21], [76, 128, 128, 1], ckpt_interval=16,
+                chol_fp64_threshold=2.0)
+    fw = sim.forward(W["s0"], W["actor"], W["critic"])
+    ad = sim.adjoint(fw)
+    torch.cuda.synchronize()
+    assert (fw["fp64_refactor_count"].cpu().numpy() == h * 48).all()
+    envs = [3]
+    ref = oracle_window_grads(W["model"], W["s0"][envs], h, W["actor"], W["critic"], n_total=64)
+    assert state_rel(fw["s_h"].double().cpu().numpy()[envs], ref["s_h"]) < 1e-4
+    for got, want in ((ad["dL_da"].double().cpu().numpy()[:, envs], ref["dL_da"]),
+                      (ad["dL_ds0"].double().cpu().numpy()[envs], ref["dL_ds0"])):
+        assert relnorm(got, want) <= 1e-3
+    sim2 = P.Sim(W["model"], 64, h, [76, 256, 128, 21], [76, 128, 128, 1], ckpt_interval=16)
+    fw2 = sim2.forward(W["s0"], W["actor"], W["critic"])
+    torch.cuda.synchronize()
+    assert int(fw2["fp64_refactor_count"].sum()) == 0
