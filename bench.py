@@ -1,10 +1,16 @@
 """Throughput of the SHAC hot path on one GPU: forward + adjoint window of the 21-hinge
 humanoid, 1024 envs, h = 32 frames, 48 substeps per frame (checkpoint every k substeps).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--k 16] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--k 4] [--no-cpu-baseline]
+                    [--no-parity] [--no-plain] [--no-theta] [--copy-probe]
 
 Prints one JSON line.  A step is one sim_forward_window + sim_adjoint_window pair over
-one batch of synthetic inputs already resident in HBM.
+one batch of synthetic inputs already resident in HBM.  Beside the headline number the
+line carries: the plain per-substep launch path on the same batch and its speedup, the
+policy-parameter gradient pass (timed apart, not part of the step), the FP32 gradient
+error against the FP64 kernels together with the FP32 sensitivity floor of the window,
+and the FP64 oracle timed on the host.  --copy-probe only runs a device copy of known
+size (the calibration of the HBM byte counters).
 """
 import argparse
 import json
@@ -65,7 +71,65 @@ def parse():
     ap.add_argument("--envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the tape / k-sweep / plain comparisons")
+    ap.add_argument("--no-theta", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A 256 MiB device-to-device copy, five times: the reference kernel for scaling the
+    profiler's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 64 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}),
+          flush=True)
+
+
+def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False):
+    """Forward + adjoint windows; per-launch HIP-event times on torch's current stream
+    (the stream the window kernels are launched on) and the wall time of the timed loop."""
+    import torch
+    for _ in range(warmup):
+        fw = sim.forward(s0, actor, critic)
+        sim.adjoint(fw, want_theta=want_theta)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record()
+        fw = sim.forward(s0, actor, critic)
+        ev[i][1].record()
+        ad = sim.adjoint(fw, want_theta=want_theta)
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+    adj_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+    return wall, fwd_ms, adj_ms, fw, ad
+
+
+def grad_err(a, b, per_env_axis=None):
+    """Relative-norm error and cosine of a against b (flattened), plus the median and
+    worst per-env cosine when per_env_axis names the env axis."""
+    a64 = a.double()
+    b64 = b.double()
+    fa, fb = a64.flatten(), b64.flatten()
+    out = {"relnorm": float((fa - fb).norm() / fb.norm()),
+           "cos": float((fa @ fb) / (fa.norm() * fb.norm()))}
+    if per_env_axis is not None:
+        A = a64.movedim(per_env_axis, 0).reshape(a64.shape[per_env_axis], -1)
+        B = b64.movedim(per_env_axis, 0).reshape(b64.shape[per_env_axis], -1)
+        c = (A * B).sum(1) / (A.norm(dim=1) * B.norm(dim=1)).clamp_min(1e-300)
+        out["cos_env_median"] = float(c.median())
+        out["cos_env_min"] = float(c.min())
+    return out
 
 
 def cpu_baseline(W, h, n_envs_sample=2):
@@ -93,6 +157,9 @@ def main():
     import paper_2204_07137_amd as P
 
     torch.manual_seed(0)
+    if args.copy_probe:
+        copy_probe()
+        return
     W = wl.workload("humanoid", args.envs)
     md = W["model"]
     od = W["obs_dim"]
@@ -101,28 +168,11 @@ def main():
     actor_dims = [od] + [w.shape[0] for w, _ in W["actor"]]
     critic_dims = [od] + [w.shape[0] for w, _ in W["critic"]]
     N = args.envs
-    sim = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=args.k)
+    sim = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=args.k, policy_grad=not args.no_theta)
     s0 = sim._dev(W["s0"])
     actor = sim.weights(W["actor"])
     critic = sim.weights(W["critic"])
-    for _ in range(args.warmup):
-        fw = sim.forward(s0, actor, critic)
-        sim.adjoint(fw)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record()
-        fw = sim.forward(s0, actor, critic)
-        ev[i][1].record()
-        ad = sim.adjoint(fw)
-        ev[i][2].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    fwd_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
-    adj_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+    wall, fwd_ms, adj_ms, fw, ad = time_windows(sim, s0, actor, critic, args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     value = N * h / (wall / args.steps)
 
@@ -151,22 +201,72 @@ def main():
                       "ckpt_interval": args.k, "path": "persistent"},
            "roofline": roof}
 
+    if not args.no_theta:
+        # policy-parameter gradient pass: adjoint with and without it, the difference
+        _, _, adj_th_ms, _, _ = time_windows(sim, s0, actor, critic, max(3, args.steps // 4), 1,
+                                             want_theta=True)
+        th_ms = max(float(np.median(adj_th_ms)) - float(np.median(adj_ms)), 0.0)
+        rows = N * h
+        th_flops = 3 * 2 * rows * sum(a * b for a, b in zip(actor_dims[:-1], actor_dims[1:]))
+        out["policy_grad"] = {"ms": round(th_ms, 3), "rows": rows,
+                              "mfma_tflops": round(th_flops / max(th_ms, 1e-6) / 1e9, 3),
+                              "mfma_peak_fp32_tflops": 157.3}
+
+    if not args.no_plain:
+        # the same window on the other launch forms: the tape path (the forward records
+        # every substep's linearisation, the adjoint recomputes nothing), the other
+        # checkpoint intervals, and the plain per-substep launch path
+        tape = P.Sim(md, N, h, actor_dims, critic_dims, path=P.PATH_TAPE)
+        tw, tf, ta, _, _ = time_windows(tape, s0, actor, critic, max(3, args.steps // 4), 1)
+        tval = N * h / (tw / max(3, args.steps // 4))
+        out["tape_path"] = {"value": round(tval, 1), "unit": "env-steps/s",
+                            "fwd_ms": round(float(np.mean(tf)), 3), "adj_ms": round(float(np.mean(ta)), 3),
+                            "workspace_gb": round(tape.ws_bytes / 1e9, 2),
+                            "vs_persistent": round(tval / value, 3)}
+        del tape
+        sweep = {}
+        for kk in (4, 8, 16):
+            if kk == args.k:
+                sweep[str(kk)] = round(value, 1)
+                continue
+            sk = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=kk)
+            kw, _, _, _, _ = time_windows(sk, s0, actor, critic, 3, 1)
+            sweep[str(kk)] = round(N * h / (kw / 3), 1)
+            del sk
+        out["ckpt_sweep"] = sweep
+        plain = P.Sim(md, N, h, actor_dims, critic_dims, path=P.PATH_PLAIN)
+        pw, pf, pa, _, _ = time_windows(plain, s0, actor, critic, args.plain_steps, 1)
+        pval = N * h / (pw / args.plain_steps)
+        out["plain_path"] = {"value": round(pval, 1), "unit": "env-steps/s",
+                             "ms_per_step": round(pw * 1e3 / args.plain_steps, 3),
+                             "fwd_ms": round(float(np.mean(pf)), 3), "adj_ms": round(float(np.mean(pa)), 3),
+                             "launches_per_step": 2 * (h * (S + 1) + 1),
+                             "persistent_speedup": round(value / pval, 3),
+                             "tape_speedup": round(tval / pval, 3)}
+        del plain
+
     if not args.no_parity:
-        # error of the FP32 gradients against the FP64 instantiation of the same kernels
+        # FP32 error against the FP64 instantiation of the same kernels, beside the
+        # sensitivity floor: the FP64 window from s0 moved by one FP32 ulp
         sim64 = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=args.k, precision="fp64")
         fw64 = sim64.forward(W["s0"], W["actor"], W["critic"])
         ad64 = sim64.adjoint(fw64)
+        s0_32 = np.asarray(W["s0"], np.float32)
+        rng = np.random.default_rng(5)
+        bump = np.where(rng.random(s0_32.shape) < 0.5, np.float32(np.inf), np.float32(-np.inf))
+        s0_ulp = np.nextafter(s0_32, bump).astype(np.float64)
+        fwp = sim64.forward(s0_ulp, W["actor"], W["critic"])
+        adp = sim64.adjoint(fwp)
         torch.cuda.synchronize()
-
-        def err(a, b):
-            a = a.double().flatten()
-            b = b.double().flatten()
-            return {"relnorm": float((a - b).norm() / b.norm()),
-                    "cos": float((a @ b) / (a.norm() * b.norm()))}
-        out["grad_err_vs_fp64"] = {"dL_da": err(ad["dL_da"], ad64["dL_da"]),
-                                   "dL_ds0": err(ad["dL_ds0"], ad64["dL_ds0"]),
+        out["grad_err_vs_fp64"] = {"dL_da": grad_err(ad["dL_da"], ad64["dL_da"], 1),
+                                   "dL_ds0": grad_err(ad["dL_ds0"], ad64["dL_ds0"], 0),
                                    "s_h_relmax": float(((fw["s_h"].double() - fw64["s_h"]).abs().max()
                                                         / fw64["s_h"].abs().max()))}
+        out["fp32_sensitivity_floor"] = {"what": "FP64 kernels, s0 moved by one FP32 ulp per component",
+                                         "dL_da": grad_err(adp["dL_da"], ad64["dL_da"], 1),
+                                         "dL_ds0": grad_err(adp["dL_ds0"], ad64["dL_ds0"], 0),
+                                         "s_h_relmax": float(((fwp["s_h"] - fw64["s_h"]).abs().max()
+                                                              / fw64["s_h"].abs().max()))}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, h)
     print(json.dumps(out), flush=True)

@@ -59,7 +59,7 @@ typedef enum {
 
 enum { SIM_JOINT_FREE = 0, SIM_JOINT_HINGE = 1, SIM_JOINT_SLIDE = 2 };
 enum { SIM_TASK_NONE = 0, SIM_TASK_CARTPOLE = 1, SIM_TASK_ANT = 2, SIM_TASK_HUMANOID = 3 };
-enum { SIM_PATH_PERSISTENT = 0, SIM_PATH_PLAIN = 1 };
+enum { SIM_PATH_PERSISTENT = 0, SIM_PATH_PLAIN = 1, SIM_PATH_TAPE = 2 };
 enum { SIM_PREC_FP32 = 0, SIM_PREC_FP64 = 1 };
 
 /* Compiled limits. */
@@ -110,8 +110,16 @@ typedef struct SimModelDesc {
 typedef struct SimOptions {
   int n_envs;                    /* N */
   int horizon;                   /* h frames per window */
-  int ckpt_interval;             /* k: the forward stores the state every k substeps (k | S) */
-  int path;                      /* SIM_PATH_PERSISTENT (one launch per window) or SIM_PATH_PLAIN */
+  int ckpt_interval;             /* k: the forward stores the state every k substeps (k | S);
+                                    1 for the tape and plain paths */
+  int path;                      /* SIM_PATH_PERSISTENT: one launch per window, the adjoint
+                                      recomputes each k-substep segment from its checkpoint;
+                                    SIM_PATH_TAPE: one launch per window, the forward also
+                                      records every substep's linearisation (Cholesky factor,
+                                      frame screws, inertias, contacts; about 9.5 KB per substep
+                                      and env in FP32) and the adjoint recomputes nothing (k = 1);
+                                    SIM_PATH_PLAIN: one launch per frame start and per substep,
+                                      the state of every substep goes through HBM (k = 1) */
   int closed_loop;               /* 1: actions from the actor MLP; 0: actions given */
   int actor_layers;              /* linear layers of the actor (closed loop) */
   int actor_dims[SIM_MAX_LAYERS + 1];
@@ -123,6 +131,9 @@ typedef struct SimOptions {
                                     FP64 for a substep whose smallest Cholesky pivot is <= this
                                     times its largest diagonal entry, or not finite (1e-6 is the
                                     documented default; a value > 1 forces FP64 every substep) */
+  int policy_grad;               /* closed loop: 1 = the workspace also holds the scratch of the
+                                    policy-parameter gradient, and sim_adjoint_window accepts
+                                    dL_dtheta */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;
@@ -162,6 +173,11 @@ typedef struct SimAdjointIO {
                                                grad_s_h is propagated */
   void* dL_da;                              /* [h][N][na] out: partial dL/da_t (App. A.1) */
   void* dL_ds0;                             /* [N][ns] out: total dL/ds_0 (App. A.1) */
+  void* dL_dtheta;                          /* optional out (needs opt.policy_grad): dL/dtheta of the
+                                               actor (App. A.1), the sum over frames and envs of
+                                               (d pi / d theta)^T dL/da_t, flat in layer order
+                                               W_0 [out][in], b_0, W_1, b_1, ...; bitwise
+                                               reproducible for a given handle */
 } SimAdjointIO;
 
 /* Validates the model and options and uploads the constant tables to the current device.
@@ -177,7 +193,10 @@ int sim_dims(const SimHandle* h, int* n_state, int* n_obs, int* n_act, int* nq, 
 /* Forward window: h frames of (observation, policy, reward, S substeps). */
 int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hip_stream);
 
-/* Reverse of the forward window: dL/da_t and dL/ds_0 of the actor loss. */
+/* Reverse of the forward window: dL/da_t and dL/ds_0 of the actor loss and, when
+ * dL_dtheta is given, the actor's parameter gradient (App. A.1).  The parameter gradient
+ * re-evaluates the actor on the stored observations and contracts the layer adjoints with
+ * the layer inputs over all h*N rows on the matrix cores. */
 int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream);
 
 void sim_destroy(SimHandle* h);

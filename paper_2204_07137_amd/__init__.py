@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshacsim.so")
 
 MAXL = 4
-PATH_PERSISTENT, PATH_PLAIN = 0, 1
+PATH_PERSISTENT, PATH_PLAIN, PATH_TAPE = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1}
 TASKS = {"none": 0, "cartpole": 1, "ant": 2, "humanoid": 3}
 STATUS = {0: "SIM_OK", -1: "SIM_E_ARG", -2: "SIM_E_HANDLE", -3: "SIM_E_HIP", -4: "SIM_E_MODEL",
@@ -39,7 +39,7 @@ class SimOptions(ctypes.Structure):
     _fields_ = [("n_envs", _i), ("horizon", _i), ("ckpt_interval", _i), ("path", _i),
                 ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
                 ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
-                ("precision", _i), ("chol_fp64_threshold", _d)]
+                ("precision", _i), ("chol_fp64_threshold", _d), ("policy_grad", _i)]
 
 
 class SimForwardIO(ctypes.Structure):
@@ -53,7 +53,8 @@ class SimAdjointIO(ctypes.Structure):
     _fields_ = [("s0", _p), ("actions", _p), ("obs", _p), ("s_h", _p),
                 ("actor_w", _p * MAXL), ("actor_b", _p * MAXL), ("critic_w", _p * MAXL),
                 ("critic_b", _p * MAXL), ("workspace", _p), ("workspace_bytes", ctypes.c_size_t),
-                ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p)]
+                ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p),
+                ("dL_dtheta", _p)]
 
 
 EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
@@ -143,7 +144,8 @@ class Sim:
     """One handle: a model, a batch size N, a horizon h and the MLP shapes."""
 
     def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
-                 path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6):
+                 path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6,
+                 policy_grad=False):
         import torch
         self.torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -154,7 +156,7 @@ class Sim:
         o.n_envs = int(n_envs)
         o.horizon = int(horizon)
         o.ckpt_interval = int(ckpt_interval if ckpt_interval is not None else
-                              (1 if path == PATH_PLAIN else md["substeps"]))
+                              (1 if path in (PATH_PLAIN, PATH_TAPE) else md["substeps"]))
         o.path = int(path)
         o.closed_loop = 1 if actor_dims is not None else 0
         if actor_dims is not None:
@@ -167,6 +169,8 @@ class Sim:
         o.gamma = float(gamma)
         o.precision = PREC[precision]
         o.chol_fp64_threshold = float(chol_fp64_threshold)
+        o.policy_grad = 1 if policy_grad else 0
+        self.actor_dims = list(actor_dims) if actor_dims is not None else None
         h = _p()
         _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
         self.h = h
@@ -250,10 +254,13 @@ class Sim:
             io.critic_w[i] = W.data_ptr()
             io.critic_b[i] = b.data_ptr()
 
-    def adjoint(self, fw, actor=None, critic=None, grad_s_h=None, loss_scale=None, stream=None):
+    def adjoint(self, fw, actor=None, critic=None, grad_s_h=None, loss_scale=None, stream=None,
+                want_theta=False):
         """Run sim_adjoint_window after forward() on the same handle and stream.
 
-        loss_scale defaults to 1/(N h), the gradient of the actor loss itself."""
+        loss_scale defaults to 1/(N h), the gradient of the actor loss itself.  With
+        want_theta (handle created with policy_grad=True) the result also holds
+        dL_dtheta, a list of (dW [out, in], db [out]) views of one flat buffer."""
         t = self.torch
         N, H = self.N, self.H
         dt = self.dtype
@@ -275,6 +282,19 @@ class Sim:
         io.loss_scale = float(1.0 / (N * H) if loss_scale is None else loss_scale)
         io.dL_da = self._ptr(out["dL_da"])
         io.dL_ds0 = self._ptr(out["dL_ds0"])
+        if want_theta:
+            dims = self.actor_dims
+            n = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+            flat = t.empty(n, device="cuda", dtype=dt)
+            out["dL_dtheta_flat"] = flat
+            io.dL_dtheta = self._ptr(flat)
+            views, off = [], 0
+            for i in range(len(dims) - 1):
+                nw = dims[i] * dims[i + 1]
+                views.append((flat[off:off + nw].view(dims[i + 1], dims[i]),
+                              flat[off + nw:off + nw + dims[i + 1]]))
+                off += nw + dims[i + 1]
+            out["dL_dtheta"] = views
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_adjoint_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
         return out
@@ -282,15 +302,21 @@ class Sim:
 
 def window_function():
     """torch.autograd.Function over one window: forward -> sim_forward_window, backward ->
-    sim_adjoint_window.  ``ShacWindow.apply(sim, s0, actor, critic, actions_in)`` returns
-    (loss, s_h, obs, actions, rewards, value); gradients flow to s0 (total, through the
-    closed-loop policy) and, in open loop, to actions_in.  The loss is the short-horizon
-    actor loss; a gradient arriving on s_h is propagated through the window as well."""
+    sim_adjoint_window.
+
+    ``ShacWindow.apply(sim, s0, actions_in, critic, *actor_params)`` with actor_params the
+    flat sequence W_0, b_0, W_1, b_1, ... returns (loss, s_h, obs, actions, rewards,
+    value).  Gradients flow to s0 (total, through the closed-loop policy), to actions_in
+    in open loop, and to the actor parameters when the handle was created with
+    policy_grad=True.  The loss is the short-horizon actor loss; a gradient arriving on
+    s_h is propagated through the window as well."""
     import torch
 
     class ShacWindow(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, sim, s0, actor, critic, actions_in):
+        def forward(ctx, sim, s0, actions_in, critic, *actor_params):
+            actor = ([(actor_params[2 * i].detach(), actor_params[2 * i + 1].detach())
+                      for i in range(len(actor_params) // 2)] if actor_params else None)
             fw = sim.forward(s0.detach(), actor, critic,
                              actions_in.detach() if actions_in is not None else None)
             g = sim.opt.gamma
@@ -298,6 +324,7 @@ def window_function():
             disc = torch.stack([g ** t * fw["rewards"][t] for t in range(H)]).sum(0)
             loss = -(disc + g ** H * fw["value"]).sum() / (N * H)
             ctx.sim, ctx.fw, ctx.open_loop = sim, fw, actions_in is not None
+            ctx.n_actor = len(actor_params)
             ctx.mark_non_differentiable(fw["obs"], fw["actions"], fw["rewards"], fw["value"])
             return loss, fw["s_h"], fw["obs"], fw["actions"], fw["rewards"], fw["value"]
 
@@ -305,9 +332,13 @@ def window_function():
         def backward(ctx, g_loss, g_sh, *unused):
             sim, fw = ctx.sim, ctx.fw
             scale = float(g_loss) / (sim.N * sim.H) if g_loss is not None else 0.0
-            ad = sim.adjoint(fw, grad_s_h=g_sh, loss_scale=scale)
+            want = bool(ctx.n_actor) and bool(sim.opt.policy_grad) and any(ctx.needs_input_grad[4:])
+            ad = sim.adjoint(fw, grad_s_h=g_sh, loss_scale=scale, want_theta=want)
             gs0 = ad["dL_ds0"]
             ga = ad["dL_da"] if ctx.open_loop else None
-            return None, gs0, None, None, ga
+            gth = [None] * ctx.n_actor
+            if want:
+                gth = [x for pair in ad["dL_dtheta"] for x in pair]
+            return (None, gs0, ga, None, *gth)
 
     return ShacWindow

@@ -12,4 +12,5 @@ typedef float real;
 #include "sim_dynamics.h"
 #include "sim_task.h"
 #include "sim_kernels.h"
+#include "sim_gemm.h"
 }  // namespace sim_f32

@@ -34,7 +34,10 @@ struct SimHandle {
   int ns = 0, od = 0, nq = 0, nv = 0, na = 0, substeps = 0;
   size_t elem = 4;
   size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL], wp_actor_off[SIM_MAXL], wp_critic_off[SIM_MAXL];
-  size_t off_ckpt = 0, off_seg = 0, off_adj = 0, ws_bytes = 0;
+  size_t off_ckpt = 0, off_adj = 0, off_tape = 0, ws_bytes = 0;
+  // policy-gradient scratch: hidden activations, two layer-adjoint buffers, split partials
+  size_t off_th_h[SIM_MAXL], off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
+  int th_splits = 0;
   int n_ckpt = 0;
   int device = -1;
   uint32_t magic = kMagic;
@@ -183,9 +186,12 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
   if (opt->n_envs < 1 || opt->horizon < 1) return fail(SIM_E_ARG, "n_envs and horizon must be >= 1");
   if (opt->ckpt_interval < 1 || m.substeps % opt->ckpt_interval != 0)
     return fail(SIM_E_ARG, "ckpt_interval must divide the substep count");
-  if (opt->path != SIM_PATH_PERSISTENT && opt->path != SIM_PATH_PLAIN) return fail(SIM_E_ARG, "unknown path");
+  if (opt->path != SIM_PATH_PERSISTENT && opt->path != SIM_PATH_PLAIN && opt->path != SIM_PATH_TAPE)
+    return fail(SIM_E_ARG, "unknown path");
   if (opt->path == SIM_PATH_PLAIN && opt->ckpt_interval != 1)
     return fail(SIM_E_ARG, "the plain path stores every substep: ckpt_interval must be 1");
+  if (opt->path == SIM_PATH_TAPE && opt->ckpt_interval != 1)
+    return fail(SIM_E_ARG, "the tape path stores every substep: ckpt_interval must be 1");
   if (opt->precision != SIM_PREC_FP32 && opt->precision != SIM_PREC_FP64) return fail(SIM_E_ARG, "unknown precision");
   if (opt->critic_layers < 1 || opt->critic_layers > SIM_MAXL) return fail(SIM_E_ARG, "critic_layers out of range");
   if (opt->critic_dims[0] != m.od || opt->critic_dims[opt->critic_layers] != 1)
@@ -201,6 +207,8 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
   }
   if (opt->critic_layers > 3 || (opt->closed_loop && opt->actor_layers > 3))
     return fail(SIM_E_UNSUPPORTED, "at most two hidden layers per MLP");
+  if (opt->policy_grad != 0 && opt->policy_grad != 1) return fail(SIM_E_ARG, "policy_grad must be 0 or 1");
+  if (opt->policy_grad && !opt->closed_loop) return fail(SIM_E_ARG, "policy_grad needs the closed-loop policy");
   return SIM_OK;
 }
 
@@ -226,7 +234,8 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   if (hipMemcpy(h->dev_model, src, msz, hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(h->dev_model); delete h; return fail(SIM_E_HIP, "hipMemcpy failed");
   }
-  // workspace: transposed MLP weights, checkpoint arena, segment pre-states, plain-path adjoint
+  // workspace: transposed MLP weights, checkpoint arena, plain-path adjoint, linearisation tape,
+  // policy-gradient scratch
   const size_t e = h->elem;
   size_t off = 0;
   for (int l = 0; l < SIM_MAXL; ++l) {
@@ -249,14 +258,40 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
     off = align256(off + e * no * pad64(ni));
   }
   const size_t N = opt->n_envs, nqv = m.nq + m.nv;
-  h->n_ckpt = (opt->path == SIM_PATH_PLAIN) ? opt->horizon * m.substeps + 1
+  h->n_ckpt = (opt->path == SIM_PATH_TAPE) ? 0
+              : (opt->path == SIM_PATH_PLAIN) ? opt->horizon * m.substeps + 1
                                              : opt->horizon * m.substeps / opt->ckpt_interval;
   h->off_ckpt = off;
   off = align256(off + e * (size_t)h->n_ckpt * N * nqv);
-  h->off_seg = off;
-  off = align256(off + e * N * (size_t)opt->ckpt_interval * nqv);
   h->off_adj = off;
   off = align256(off + e * N * (nqv + m.na));
+  // linearisation tape: every substep of the window (tape path) or one recomputed
+  // segment but its last substep per env (persistent path)
+  const size_t tape_entries = (opt->path == SIM_PATH_TAPE) ? (size_t)opt->horizon * m.substeps * N
+                              : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
+  h->off_tape = off;
+  off = align256(off + tape_entries * sim_tape_bytes(e));
+  for (int l = 0; l < SIM_MAXL; ++l) h->off_th_h[l] = 0;
+  if (opt->policy_grad) {
+    const size_t rows = N * (size_t)opt->horizon;
+    size_t maxw = 0, maxpart = 0;
+    for (int l = 1; l < opt->actor_layers; ++l) {
+      h->off_th_h[l] = off;
+      off = align256(off + e * rows * opt->actor_dims[l]);
+    }
+    for (int l = 0; l < opt->actor_layers; ++l) {
+      maxw = std::max(maxw, (size_t)opt->actor_dims[l + 1]);
+      maxpart = std::max(maxpart, (size_t)opt->actor_dims[l + 1] * (opt->actor_dims[l] + 1));
+    }
+    // row chunks of at least 512 rows, at most 64 of them
+    h->th_splits = (int)std::min<size_t>(64, std::max<size_t>(1, rows / 512));
+    h->off_th_d0 = off;
+    off = align256(off + e * rows * maxw);
+    h->off_th_d1 = off;
+    off = align256(off + e * rows * maxw);
+    h->off_th_part = off;
+    off = align256(off + e * (size_t)h->th_splits * maxpart);
+  }
   h->ws_bytes = off;
   *out = h;
   g_err.clear();
@@ -352,8 +387,9 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   A.nonfinite = io->nonfinite;
   A.fallback = io->fp64_refactor_count;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
-  A.seg = reinterpret_cast<T*>(ws + h->off_seg);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
+  A.tape = reinterpret_cast<T*>(ws + h->off_tape);
+  A.tape_full = (o.path == SIM_PATH_TAPE);
   int bad = 0;
   if (o.closed_loop) bad |= launch_transposes(A.actor, stream);
   bad |= launch_transposes(A.critic, stream);
@@ -385,8 +421,9 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, h->wp_critic_off, "critic");
   if (rc) return rc;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
-  A.seg = reinterpret_cast<T*>(ws + h->off_seg);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
+  A.tape = reinterpret_cast<T*>(ws + h->off_tape);
+  A.tape_full = (o.path == SIM_PATH_TAPE);
   A.obs_in = static_cast<const T*>(io->obs);
   A.actions_fw = static_cast<const T*>(io->actions);
   A.s_h_in = static_cast<const T*>(io->s_h);
@@ -400,6 +437,36 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   else
     bad = sim_f64::launch_adjoint(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, h->nv, stream);
   if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  if (io->dL_dtheta) {
+    ThetaArgsT<T> P;
+    std::memset(&P, 0, sizeof(P));
+    P.M = o.n_envs * o.horizon;
+    P.nl = o.actor_layers;
+    for (int l = 0; l <= o.actor_layers; ++l) P.dims[l] = o.actor_dims[l];
+    P.splits = h->th_splits;
+    long off = 0;
+    for (int l = 0; l < o.actor_layers; ++l) {
+      P.W[l] = static_cast<const T*>(io->actor_w[l]);
+      P.b[l] = static_cast<const T*>(io->actor_b[l]);
+      P.off_w[l] = off;
+      off += (long)o.actor_dims[l] * o.actor_dims[l + 1];
+      P.off_b[l] = off;
+      off += o.actor_dims[l + 1];
+      if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + h->off_th_h[l]);
+    }
+    P.x0 = static_cast<const T*>(io->obs);
+    P.act = static_cast<const T*>(io->actions);
+    P.da = static_cast<const T*>(io->dL_da);
+    P.d0 = reinterpret_cast<T*>(ws + h->off_th_d0);
+    P.d1 = reinterpret_cast<T*>(ws + h->off_th_d1);
+    P.part = reinterpret_cast<T*>(ws + h->off_th_part);
+    P.out = static_cast<T*>(io->dL_dtheta);
+    if (sizeof(T) == 4)
+      bad = sim_f32::launch_theta(*reinterpret_cast<const ThetaArgsT<float>*>(&P), stream);
+    else
+      bad = sim_f64::launch_theta(*reinterpret_cast<const ThetaArgsT<double>*>(&P), stream);
+    if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  }
   return SIM_OK;
 }
 
@@ -423,6 +490,12 @@ extern "C" int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hi
   const SimOptions& o = h->opt;
   if (!io->s0 || !io->actions || !io->obs || !io->s_h || !io->dL_da || !io->dL_ds0)
     return fail(SIM_E_ARG, "sim_adjoint_window: null input/output pointer");
+  if (io->dL_dtheta && !o.policy_grad)
+    return fail(SIM_E_ARG, "dL_dtheta needs a handle created with policy_grad = 1");
+  if (io->dL_dtheta) {
+    for (int l = 0; l < o.actor_layers; ++l)
+      if (!io->actor_w[l] || !io->actor_b[l]) return fail(SIM_E_ARG, "dL_dtheta needs the actor weights");
+  }
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
   return (o.precision == SIM_PREC_FP64) ? run_adjoint<double>(h, io, hip_stream) : run_adjoint<float>(h, io, hip_stream);

@@ -30,15 +30,28 @@ struct ContactRegs {
   real rad;
 };
 
+constexpr int kTapeBytes = (SIM_TAPE_REALS * (int)sizeof(real) + 1023) / 1024 * 1024;
+constexpr int kTapePad = (kTapeBytes - SIM_TAPE_REALS * (int)sizeof(real)) / (int)sizeof(real);
+constexpr int kTapeReals = kTapeBytes / (int)sizeof(real);   // stride of one tape entry
+
 struct EnvLDS {
-  real q[SIM_MAXQ], qd[SIM_MAXV], a[SIM_MAXA];
-  real qn[SIM_MAXQ], qdn[SIM_MAXV];
-  real R[SIM_MAXJ][9], p[SIM_MAXJ][3], S[SIM_MAXJ][6], v[SIM_MAXJ][6], ab[SIM_MAXJ][6];
+  // The linearisation of the current substep, one contiguous 1 KB-padded block so that it
+  // moves to and from HBM as whole 64-lane x 16-byte transfers (the linearisation tape).
+  struct __attribute__((aligned(16))) {
+    real q[SIM_MAXQ], qd[SIM_MAXV];   // state before the substep
+    real S[SIM_MAXJ][6], v[SIM_MAXJ][6], ab[SIM_MAXJ][6], Ib[SIM_MAXJ][10];
+    real cf[SIM_MAXC][3], cx[SIM_MAXC][3], cvel[SIM_MAXC][3], cdep[SIM_MAXC];
+    real qdd[SIM_MAXV], qdn[SIM_MAXV];
+    real M[SIM_MAXV][SIM_MAXV + 1];    // mass matrix, then the Cholesky rows
+    real tdinv[SIM_MAXV], tfb[SIM_MAXV];
+    real tpad[kTapePad];
+  };
+  real a[SIM_MAXA];
+  real qn[SIM_MAXQ];
+  real R[SIM_MAXJ][9], p[SIM_MAXJ][3];
   real F[SIM_MAXJ][6], Fi[SIM_MAXJ][6];
-  real Ib[SIM_MAXJ][10], Ic[SIM_MAXJ][10];
-  real M[SIM_MAXV][SIM_MAXV + 1];
-  real vec[SIM_MAXV], qdd[SIM_MAXV];
-  real cf[SIM_MAXC][3], cx[SIM_MAXC][3], cvel[SIM_MAXC][3], cdep[SIM_MAXC];
+  real Ic[SIM_MAXJ][10];
+  real vec[SIM_MAXV];
   real O[4];
   // adjoint
   real W[SIM_MAXJ][6], A[SIM_MAXJ][6];
@@ -575,11 +588,9 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
 // post-substep state.  On exit E.qb/E.qdb hold the adjoint of the pre-substep state and
 // E.abar has gained this substep's contribution.
 template <int NV>
-__device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvLDS& E,
-                                                const JointRegs& jr, const ContactRegs& cr, int ln) {
-  Chol C;
-  int fb;
-  substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+__device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m, EnvLDS& E,
+                                                     const JointRegs& jr, const ContactRegs& cr, int ln,
+                                                     const Chol& C, int fb) {
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real dt = m->dt_sub;
   const real g = m->g;
@@ -768,4 +779,75 @@ __device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvL
     }
   }
   __syncthreads();
+}
+
+// Adjoint of one substep from its pre-state alone: the forward linearisation is
+// recomputed first (plain path, and the last substep of a recomputed segment).
+template <int NV>
+__device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvLDS& E,
+                                                const JointRegs& jr, const ContactRegs& cr, int ln) {
+  Chol C;
+  int fb;
+  substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+  substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
+}
+
+// --------------------------------------------------------------- linearisation tape
+// Everything the adjoint of a substep reads from its forward pass, kept so that the
+// reverse sweep does not recompute it: the pre-substep state, per frame the world screw S, velocity v, bias
+// acceleration and spatial inertia, per contact sphere the force, contact point, its
+// velocity and the depth, qdd, the post-substep velocities, the Cholesky rows, the
+// reciprocal pivots and the FP64-fallback flag (the FP64 factor itself is not kept: a
+// flagged substep is recomputed).  These fields are one contiguous block of EnvLDS, so
+// a tape entry is a byte copy of it: 16 bytes per lane and instruction.
+static_assert(offsetof(EnvLDS, tpad) + sizeof(real) * kTapePad - offsetof(EnvLDS, q) == (size_t)kTapeBytes,
+              "tape block layout");
+static_assert(offsetof(EnvLDS, q) == 0, "tape block first");
+
+// make the post-substep state current (the in-place end of substep_forward)
+__device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, EnvLDS& E, int ln) {
+  if (ln < m->nq) E.q[ln] = E.qn[ln];
+  if (ln < m->nv) E.qd[ln] = E.qdn[ln];
+  __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void tape_store(EnvLDS& E, const Chol& C, int fb, int ln, real* __restrict__ tp) {
+  real dv = RL(0.0);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) dv = (ln == k) ? C.dinv[k] : dv;
+  if (ln < SIM_MAXV) {
+    E.tdinv[ln] = dv;
+    E.tfb[ln] = fb ? RL(1.0) : RL(0.0);
+  }
+  __syncthreads();
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4* src = reinterpret_cast<const u32x4*>(&E.q[0]);
+  u32x4* dst = reinterpret_cast<u32x4*>(tp);
+  // streaming (non-temporal) stores: the tape must not displace the policy weights in L2
+#pragma unroll
+  for (int i = 0; i < kTapeBytes / 1024; ++i) __builtin_nontemporal_store(src[i * SIM_WAVE + ln], &dst[i * SIM_WAVE + ln]);
+}
+
+// Restores the block with direct global-to-LDS transfers (no registers in flight,
+// non-temporal), then the factor's rows and columns and the pivots into registers.
+template <int NV>
+__device__ __forceinline__ void tape_load(EnvLDS& E, Chol& C, int& fb, int ln, const real* __restrict__ tp) {
+  const char* g = reinterpret_cast<const char*>(tp);
+  char* l = reinterpret_cast<char*>(&E.q[0]);
+#pragma unroll
+  for (int i = 0; i < kTapeBytes / 1024; ++i)
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + i * 1024 + ln * 16),
+                                     (__attribute__((address_space(3))) void*)(l + i * 1024), 16, 0,
+                                     /* non-temporal */ 2);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const int lr = ln < NV ? ln : 0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    C.row[k] = (ln < NV) ? E.M[lr][k] : RL(0.0);
+    C.col[k] = (ln < NV) ? E.M[k][lr] : RL(0.0);
+    C.dinv[k] = E.tdinv[k];
+  }
+  fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
 }

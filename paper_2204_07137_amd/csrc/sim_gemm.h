@@ -1,0 +1,205 @@
+// Policy-parameter gradient of the short-horizon actor loss (App. A.1, the dL/dtheta
+// term): given dL/da_t of every environment and frame, the gradient is the sum over all
+// h*N (frame, env) rows of (d pi(o_t) / d theta)^T dL/da_t.  The actor is re-evaluated on
+// the observations the forward window stored, the action adjoint is carried back through
+// tanh and every ELU layer, and the weight gradient of a layer is the contraction of its
+// output adjoint with its input over all rows.
+//
+// Every contraction runs on the matrix cores: 64x64 output tiles staged through LDS in
+// K-slices of 16, four wavefronts per tile, each wavefront a 2x2 block of 16x16x4 MFMA
+// accumulators.  Row reductions (K = h*N) are split into fixed chunks whose partial tiles
+// are summed in a fixed order, so the gradient is bitwise reproducible.
+//
+// Included inside a namespace with `real` defined as float or double.
+
+#define GT_M 64
+#define GT_N 64
+#define GT_K 16
+#define GT_THREADS 256
+
+enum { EPI_STORE = 0, EPI_BIAS_ELU = 1, EPI_DELU = 2 };
+
+typedef float mfma_v4f __attribute__((__vector_size__(4 * sizeof(float))));
+typedef double mfma_v4d __attribute__((__vector_size__(4 * sizeof(double))));
+typedef real mfma_v4 __attribute__((__vector_size__(4 * sizeof(real))));
+
+__device__ __forceinline__ mfma_v4f mfma_16x16x4(float a, float b, mfma_v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma_v4d mfma_16x16x4(double a, double b, mfma_v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Row of a 16x16 accumulator block held by lane l in element r (the column is l % 16).
+// The two instructions lay their results out differently: FP32 keeps four consecutive
+// rows per 16-lane group, FP64 interleaves the groups.
+__device__ __forceinline__ int mfma_row(float, int l, int r) { return 4 * (l >> 4) + r; }
+__device__ __forceinline__ int mfma_row(double, int l, int r) { return (l >> 4) + 4 * r; }
+
+// C(m, n) = sum_k A(m, k) B(k, n) over k in this split's chunk, with element strides
+// A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn].
+struct GemmArgs {
+  const real* A;
+  long sam, sak;
+  const real* B;
+  long sbk, sbn;
+  int M, N, K;
+  int ones_col;      // column N-1 of B is all ones (bias gradient); B holds N-1 columns
+  int k_chunk;       // K rows per split (multiple of GT_K); split z = blockIdx.z
+  real* C;
+  long ldc, split_stride;
+  int epi;
+  const real* bias;  // EPI_BIAS_ELU: C = elu(acc + bias[n])
+  const real* Hm;    // EPI_DELU: C = acc * elu'(z), z > 0 <=> Hm > 0, else elu'(z) = Hm + 1
+  long ldh;
+};
+
+__global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
+  __shared__ real As[GT_K][GT_M + 4];
+  __shared__ real Bs[GT_K][GT_N + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.x * GT_M, n0 = blockIdx.y * GT_N;
+  const int kb = blockIdx.z * g.k_chunk;
+  const int ke = min(g.K, kb + g.k_chunk);
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  const int bcols = g.ones_col ? g.N - 1 : g.N;
+  mfma_v4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = mfma_v4{RL(0.0), RL(0.0), RL(0.0), RL(0.0)};
+
+  const bool a_kfast = (g.sak == 1), b_kfast = (g.sbk == 1);
+  for (int k0 = kb; k0 < ke; k0 += GT_K) {
+#pragma unroll
+    for (int r = 0; r < GT_M * GT_K / GT_THREADS; ++r) {
+      const int e = tid + r * GT_THREADS;
+      const int mm = a_kfast ? e / GT_K : e % GT_M;
+      const int kk = a_kfast ? e % GT_K : e / GT_M;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < ke) ? g.A[(long)m * g.sam + (long)k * g.sak] : RL(0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < GT_N * GT_K / GT_THREADS; ++r) {
+      const int e = tid + r * GT_THREADS;
+      const int nn = b_kfast ? e / GT_K : e % GT_N;
+      const int kk = b_kfast ? e % GT_K : e / GT_N;
+      const int n = n0 + nn, k = k0 + kk;
+      real v = RL(0.0);
+      if (k < ke) {
+        if (n < bcols) v = g.B[(long)k * g.sbk + (long)n * g.sbn];
+        else if (g.ones_col && n == g.N - 1) v = RL(1.0);
+      }
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < GT_K; k4 += 4) {
+      const int kr = k4 + (lane >> 4);
+      real a0 = As[kr][wm + (lane & 15)], a1 = As[kr][wm + 16 + (lane & 15)];
+      real b0 = Bs[kr][wn + (lane & 15)], b1 = Bs[kr][wn + 16 + (lane & 15)];
+      acc[0][0] = mfma_16x16x4(a0, b0, acc[0][0]);
+      acc[0][1] = mfma_16x16x4(a0, b1, acc[0][1]);
+      acc[1][0] = mfma_16x16x4(a1, b0, acc[1][0]);
+      acc[1][1] = mfma_16x16x4(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  real* C = g.C + (long)blockIdx.z * g.split_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + mfma_row(RL(0.0), lane, r);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          real v = acc[i][j][r];
+          if (g.epi == EPI_BIAS_ELU) {
+            v += g.bias[n];
+            v = v > RL(0.0) ? v : m_expm1(v);
+          } else if (g.epi == EPI_DELU) {
+            const real hv = g.Hm[(long)m * g.ldh + n];
+            v *= hv > RL(0.0) ? RL(1.0) : hv + RL(1.0);
+          }
+          C[(long)m * g.ldc + n] = v;
+        }
+      }
+}
+
+// adjoint of the pre-squash policy output: dL/dy = dL/da (1 - a^2)
+__global__ void k_theta_seed(const real* __restrict__ da, const real* __restrict__ a, real* __restrict__ d, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const real av = a[i];
+    d[i] = da[i] * (RL(1.0) - av * av);
+  }
+}
+
+// sum of the split partials in split order; column `in` of each row is the bias gradient
+__global__ void k_split_reduce(const real* __restrict__ part, int splits, long stride, int rows, int cols,
+                               real* __restrict__ gW, real* __restrict__ gb) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  real s = RL(0.0);
+  for (int z = 0; z < splits; ++z) s += part[z * stride + idx];
+  const int o = (int)(idx / cols), i = (int)(idx % cols);
+  if (i < cols - 1) gW[(long)o * (cols - 1) + i] = s;
+  else gb[o] = s;
+}
+
+static void launch_gemm(const GemmArgs& g, int splits, hipStream_t s) {
+  dim3 grid((g.M + GT_M - 1) / GT_M, (g.N + GT_N - 1) / GT_N, splits);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(GT_THREADS), 0, s, g);
+}
+
+int launch_theta(const ThetaArgsT<real>& T, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int M = T.M, L = T.nl;
+  // re-evaluate the hidden layers on the stored observations
+  for (int l = 0; l + 1 < L; ++l) {
+    const int ni = T.dims[l], no = T.dims[l + 1];
+    GemmArgs g = {};
+    g.A = (l == 0) ? T.x0 : T.H[l];
+    g.sam = ni; g.sak = 1;
+    g.B = T.W[l]; g.sbk = 1; g.sbn = ni;
+    g.M = M; g.N = no; g.K = ni;
+    g.k_chunk = (ni + GT_K - 1) / GT_K * GT_K;
+    g.C = T.H[l + 1]; g.ldc = no;
+    g.epi = EPI_BIAS_ELU; g.bias = T.b[l];
+    launch_gemm(g, 1, s);
+  }
+  const int na = T.dims[L];
+  const long nseed = (long)M * na;
+  hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed);
+  real* dcur = T.d0;
+  real* dnext = T.d1;
+  const int chunk = ((M + T.splits - 1) / T.splits + GT_K - 1) / GT_K * GT_K;
+  const int splits = (M + chunk - 1) / chunk;
+  for (int l = L - 1; l >= 0; --l) {
+    const int ni = T.dims[l], no = T.dims[l + 1];
+    const real* xin = (l == 0) ? T.x0 : T.H[l];
+    GemmArgs g = {};
+    g.A = dcur; g.sam = 1; g.sak = no;
+    g.B = xin; g.sbk = ni; g.sbn = 1; g.ones_col = 1;
+    g.M = no; g.N = ni + 1; g.K = M; g.k_chunk = chunk;
+    g.C = T.part; g.ldc = ni + 1; g.split_stride = (long)no * (ni + 1);
+    g.epi = EPI_STORE;
+    launch_gemm(g, splits, s);
+    const long nr = (long)no * (ni + 1);
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, T.part, splits,
+                       (long)no * (ni + 1), no, ni + 1, T.out + T.off_w[l], T.out + T.off_b[l]);
+    if (l > 0) {
+      GemmArgs g2 = {};
+      g2.A = dcur; g2.sam = no; g2.sak = 1;
+      g2.B = T.W[l]; g2.sbk = ni; g2.sbn = 1;
+      g2.M = M; g2.N = ni; g2.K = no;
+      g2.k_chunk = (no + GT_K - 1) / GT_K * GT_K;
+      g2.C = dnext; g2.ldc = ni;
+      g2.epi = EPI_DELU; g2.Hm = T.H[l]; g2.ldh = ni;
+      launch_gemm(g2, 1, s);
+      real* t = dcur; dcur = dnext; dnext = t;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}

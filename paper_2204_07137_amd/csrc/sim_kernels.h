@@ -89,9 +89,16 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
     frame_begin(A, m, E, env, t, ln);
     for (int sub = 0; sub < S; ++sub) {
       int gi = t * S + sub;
-      if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
       int fb;
-      substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
+      if (A.tape_full) {
+        // the tape entry holds the pre-substep state and the linearisation
+        substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+        tape_store<NV>(E, C, fb, ln, A.tape + ((size_t)gi * N + env) * kTapeReals);
+        commit_substep(m, E, ln);
+      } else {
+        if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
+        substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
+      }
       nfb += fb;
     }
   }
@@ -129,13 +136,14 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
 }
 
 // frame-level reverse at frame t: E.qb/E.qdb hold the adjoint of the frame-start (q, qd)
-// through the dynamics; E.abar holds dL/da_t except the reward term.
+// through the dynamics; E.abar holds dL/da_t except the reward term.  E.q/E.qd hold the
+// frame-start state unless load_start (then it is read from the checkpoint arena).
 __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
-                                              int env, int t, int ln) {
+                                              int env, int t, int ln, bool load_start) {
   const int N = A.N, nq = m->nq, nv = m->nv, na = m->na, od = m->od, ns = m->ns, S = m->substeps;
   const int nqv = nq + nv;
   // frame-start state and a_t
-  load_qqd(m, E, A.ckpt + ((size_t)(t * S / A.k) * N + env) * nqv, ln);
+  if (load_start) load_qqd(m, E, A.ckpt + ((size_t)(t * S / A.k) * N + env) * nqv, ln);
   const real* at = A.actions_fw + ((size_t)t * N + env) * na;
   for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
   __syncthreads();
@@ -175,33 +183,48 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
   const int nqv = nq + nv;
   adjoint_seed(A, m, E, env, ln);
   // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
-  real* seg = A.seg + (size_t)env * k * nqv;
   Chol C;
   for (int t = A.h - 1; t >= 0; --t) {
     const real* at = A.actions_fw + ((size_t)t * N + env) * na;
-    for (int sg = S / k - 1; sg >= 0; --sg) {
-      int c = (t * S + sg * k) / k;
-      const real* ck = A.ckpt + ((size_t)c * N + env) * nqv;
-      if (k > 1) {
-        load_qqd(m, E, ck, ln);
-        for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
-        __syncthreads();
-        for (int i = 0; i < k - 1; ++i) {
-          store_qqd(m, E, seg + (size_t)i * nqv, ln);
-          int fb;
-          substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
-        }
-        store_qqd(m, E, seg + (size_t)(k - 1) * nqv, ln);
-        __syncthreads();
+    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+    if (A.tape_full) {
+      // the forward stored every substep's pre-state and linearisation
+      for (int sub = S - 1; sub >= 0; --sub) {
+        const size_t c = (size_t)t * S + sub;
+        int fb;
+        tape_load<NV>(E, C, fb, ln, A.tape + (c * N + env) * kTapeReals);
+        if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+        substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
       }
-      for (int i = k - 1; i >= 0; --i) {
-        load_qqd(m, E, k > 1 ? seg + (size_t)i * nqv : ck, ln);
-        for (int j = ln; j < na; j += SIM_WAVE) E.a[j] = at[j];
-        __syncthreads();
-        substep_adjoint<NV>(m, E, jr, cr, ln);
+    } else {
+      real* tseg = A.tape + (size_t)env * (k - 1) * kTapeReals;
+      for (int sg = S / k - 1; sg >= 0; --sg) {
+        int c = (t * S + sg * k) / k;
+        const real* ck = A.ckpt + ((size_t)c * N + env) * nqv;
+        load_qqd(m, E, ck, ln);
+        // recompute the segment from its checkpoint, recording pre-states and
+        // linearisations; the last substep's linearisation stays on chip
+        for (int i = 0; i < k - 1; ++i) {
+          int fb;
+          substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+          tape_store<NV>(E, C, fb, ln, tseg + (size_t)i * kTapeReals);
+          commit_substep(m, E, ln);
+        }
+        {
+          int fb;
+          substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+          substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
+        }
+        for (int i = k - 2; i >= 0; --i) {
+          int fb;
+          tape_load<NV>(E, C, fb, ln, tseg + (size_t)i * kTapeReals);
+          if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+          substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
+        }
       }
     }
-    adjoint_frame(A, m, E, env, t, ln);
+    // the reverse sweep ends on the frame's first substep: E.q/E.qd = s_t
+    adjoint_frame(A, m, E, env, t, ln, false);
   }
   real* d0 = A.dL_ds0 + (size_t)env * ns;
   for (int i = ln; i < nq; i += SIM_WAVE) d0[i] = E.qb[i];
@@ -330,7 +353,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_adj_frame(WinArgs A, int t) 
   const int nqv = m->nq + m->nv, na = m->na, ns = m->ns, nq = m->nq, nv = m->nv;
   real* adj = A.adj + (size_t)env * (nqv + na);
   adj_load(m, E, adj, ln);
-  adjoint_frame(A, m, E, env, t, ln);
+  adjoint_frame(A, m, E, env, t, ln, true);
   adj_store(m, E, adj, ln);
   if (t == 0) {
     real* d0 = A.dL_ds0 + (size_t)env * ns;

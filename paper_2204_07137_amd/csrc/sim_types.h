@@ -14,6 +14,11 @@
 #define SIM_MAXHID 512   // MLP width
 #define SIM_MAXL 4       // MLP linear layers
 #define SIM_MAXPAIR 576  // (frame, ancestor-or-self) pairs of the mass matrix, 9 rounds of 64 lanes
+// linearisation tape of one substep: SIM_TAPE_REALS values (pre-substep state, frame
+// screws, velocities, bias accelerations and inertias, contact data, accelerations, new
+// velocities, the Cholesky rows, pivots and flag), padded to whole 1 KB blocks
+#define SIM_TAPE_REALS 2465
+static inline size_t sim_tape_bytes(size_t elem) { return (SIM_TAPE_REALS * elem + 1023) / 1024 * 1024; }
 
 enum { J_FREE = 0, J_HINGE = 1, J_SLIDE = 2 };
 enum { TASK_NONE = 0, TASK_CARTPOLE = 1, TASK_ANT = 2, TASK_HUMANOID = 3 };
@@ -63,9 +68,11 @@ struct WinArgsT {
   T* value;
   uint8_t* nonfinite;
   int* fallback;    // [N] substeps whose factorisation fell back to FP64 (optional)
-  T* ckpt;          // [n_ckpt][N][nq+nv]
-  T* seg;           // [N][k][nq+nv] segment pre-states (recompute)
+  T* ckpt;          // [n_ckpt][N][nq+nv] (persistent and plain paths)
   T* adj;           // [N][nq+nv+na] adjoint carried between plain launches
+  T* tape;          // tape_full: [h*S][N] tape entries written by the forward; else the
+                    // adjoint's segment tape [N][k-1] entries (sim_tape_bytes each)
+  int tape_full;
   const T* obs_in;
   const T* actions_fw;
   const T* s_h_in;
@@ -74,12 +81,33 @@ struct WinArgsT {
   T* dL_ds0;
 };
 
+// Policy-parameter gradient pass over the rows (frame, env) of one window.
+template <typename T>
+struct ThetaArgsT {
+  int M;                      // rows: h * N
+  int nl;                     // linear layers of the actor
+  int dims[SIM_MAXL + 1];
+  int splits;                 // row chunks of the weight-gradient reductions
+  const T* W[SIM_MAXL];       // [out][in] caller weights
+  const T* b[SIM_MAXL];
+  const T* x0;                // [M][dims[0]] observations o_0 .. o_{h-1}
+  const T* act;               // [M][na] actions
+  const T* da;                // [M][na] dL/da
+  T* H[SIM_MAXL];             // H[l] (l >= 1): [M][dims[l]] hidden activations
+  T* d0;                      // [M][max dim] layer adjoints (ping-pong)
+  T* d1;
+  T* part;                    // [splits][max out*(in+1)] partial weight gradients
+  T* out;                     // flat dL/dtheta: W_0, b_0, W_1, b_1, ...
+  long off_w[SIM_MAXL], off_b[SIM_MAXL];
+};
+
 // Launchers implemented once per arithmetic type (kernels_f32.hip, kernels_f64.hip).
 #define SIM_DECLARE_LAUNCHERS(NS, T)                                                        \
   namespace NS {                                                                            \
   int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
   int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
   int launch_prep_weights(const T* W, T* WT, T* Wp, int n_out, int n_in, void* stream);   \
+  int launch_theta(const ThetaArgsT<T>& A, void* stream);                                  \
   }
 SIM_DECLARE_LAUNCHERS(sim_f32, float)
 SIM_DECLARE_LAUNCHERS(sim_f64, double)

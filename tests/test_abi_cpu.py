@@ -40,6 +40,7 @@ def _create(md, **kw):
     for i, v in enumerate(dims):
         o.critic_dims[i] = v
     o.gamma = 0.99
+    o.policy_grad = kw.get("policy_grad", 0)
     h = ctypes.c_void_p()
     rc = P.lib().sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h))
     return rc, P.lib().sim_last_error().decode()
@@ -69,6 +70,10 @@ def test_model_limits_rejected():
     assert rc == -1 and "plain" in msg
     rc, msg = _create(md, critic=[75, 8, 1])
     assert rc == -1 and "critic" in msg
+    rc, msg = _create(md, policy_grad=1)
+    assert rc == -1 and "policy_grad" in msg
+    rc, msg = _create(md, policy_grad=2)
+    assert rc == -1 and "policy_grad" in msg
 
 
 def test_too_many_joints_rejected():

@@ -128,15 +128,34 @@ def test_checkpoint_interval_gradients_bitwise_identical(name, ks):
             assert np.array_equal(a, b)
 
 
-def test_plain_path_bitwise_equals_persistent():
-    W = wl.workload("ant", 64)
-    print("[plain vs persistent] ant", flush=True)
-    _, fa, aa = run(W, 4, k=1)
-    _, fb, ab = run(W, 4, k=1, path=P.PATH_PLAIN)
-    for key in ("s_h", "obs", "actions", "rewards", "value"):
-        assert np.array_equal(fa[key], fb[key]), key
-    assert np.array_equal(aa["dL_da"], ab["dL_da"])
-    assert np.array_equal(aa["dL_ds0"], ab["dL_ds0"])
+@pytest.mark.parametrize("name,k", [("ant", 4), ("humanoid", 16)])
+def test_paths_bitwise_identical(name, k):
+    """The plain per-substep path, the tape path (forward records every linearisation) and
+    the persistent path (segments recomputed from checkpoints through the segment tape)
+    run the same arithmetic in the same order: outputs and gradients agree bitwise."""
+    W = wl.workload(name, 64)
+    h = 3
+    print(f"[paths] {name} persistent k={k} / k=1 / tape / plain", flush=True)
+    _, f0, a0 = run(W, h, k=k)
+    for kw in (dict(k=1), dict(path=P.PATH_TAPE), dict(path=P.PATH_PLAIN)):
+        _, f1, a1 = run(W, h, **kw)
+        for key in ("s_h", "obs", "actions", "rewards", "value"):
+            assert np.array_equal(f0[key], f1[key]), (kw, key)
+        assert np.array_equal(a0["dL_da"], a1["dL_da"]), kw
+        assert np.array_equal(a0["dL_ds0"], a1["dL_ds0"]), kw
+
+
+def test_tape_path_fp64_full_window_matches_oracle():
+    """The tape path over the full Ant window in FP64 against the oracle (sampled envs)."""
+    W = wl.workload("ant", 256)
+    h = W["h"]
+    print("[tape fp64] ant 256 full window", flush=True)
+    _, fw, ad = run(W, h, path=P.PATH_TAPE, precision="fp64")
+    envs = [7, 200]
+    ref = oracle_window_grads(W["model"], W["s0"][envs], h, W["actor"], W["critic"], n_total=256)
+    assert relnorm(fw["s_h"][envs], ref["s_h"]) < 1e-9
+    assert relnorm(ad["dL_da"][:, envs], ref["dL_da"]) < 1e-9
+    assert relnorm(ad["dL_ds0"][envs], ref["dL_ds0"]) < 1e-9
 
 
 def test_envs_are_independent_bitwise():
@@ -209,15 +228,75 @@ def test_upstream_gradient_on_final_state_fp64():
 def test_autograd_function_backward_matches_adjoint():
     W = wl.workload("cartpole")
     h = 16
-    sim = make_sim(W, h)
+    od = W["obs_dim"]
+    sim = P.Sim(W["model"], W["n_envs"], h, [od] + [w.shape[0] for w, _ in W["actor"]],
+                [od] + [w.shape[0] for w, _ in W["critic"]], policy_grad=True)
     Fn = P.window_function()
     s0 = torch.tensor(W["s0"], dtype=torch.float32, device="cuda", requires_grad=True)
+    params = [torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True)
+              for pair in W["actor"] for x in pair]
     print("[autograd] cartpole", flush=True)
-    loss, s_h, *_ = Fn.apply(sim, s0, W["actor"], W["critic"], None)
+    loss, s_h, *_ = Fn.apply(sim, s0, None, W["critic"], *params)
     (2.0 * loss).backward()
-    ref = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], n_total=16)
-    assert abs(float(loss) - ref["loss"]) < 1e-5 * abs(ref["loss"])
+    ref = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], n_total=16,
+                              want_theta=True)
+    assert abs(float(loss.detach()) - ref["loss"]) < 1e-5 * abs(ref["loss"])
     assert relnorm(s0.grad.double().cpu().numpy(), 2.0 * ref["dL_ds0"]) < 1e-5
+    got = np.concatenate([p.grad.double().cpu().numpy().ravel() for p in params])
+    want = np.concatenate([2.0 * x.ravel() for pair in ref["dL_dtheta"] for x in pair])
+    assert relnorm(got, want) < 1e-4
+
+
+THETA = [("cartpole", 16, 32, None), ("ant", 24, 4, 16), ("humanoid", 4, 2, 16)]
+
+
+def _theta_run(W, h, k, precision, n_envs=None, loss_scale=None):
+    od = W["obs_dim"]
+    N = n_envs or W["n_envs"]
+    sim = P.Sim(W["model"], N, h, [od] + [w.shape[0] for w, _ in W["actor"]],
+                [od] + [w.shape[0] for w, _ in W["critic"]], ckpt_interval=k,
+                precision=precision, policy_grad=True)
+    fw = sim.forward(W["s0"][:N], W["actor"], W["critic"])
+    ad = sim.adjoint(fw, want_theta=True, loss_scale=loss_scale)
+    torch.cuda.synchronize()
+    return ad["dL_dtheta_flat"].double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name,N,h,k", THETA, ids=[c[0] for c in THETA])
+def test_policy_gradient_matches_oracle(name, N, h, k):
+    """dL/dtheta of the actor (App. A.1) from the MFMA row-contraction pass against the
+    oracle's reverse-mode gradient: FP64 to rounding, FP32 to the gradient bar."""
+    W = wl.workload(name, N)
+    print(f"[theta] {name} N={N} h={h}", flush=True)
+    ref = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], n_total=N,
+                              want_theta=True)
+    want = np.concatenate([x.ravel() for pair in ref["dL_dtheta"] for x in pair])
+    g64 = _theta_run(W, h, k, "fp64")
+    assert relnorm(g64, want) < 1e-9
+    g32 = _theta_run(W, h, k, "fp32")
+    assert cosine(g32, want) >= 0.999
+    assert relnorm(g32, want) <= 1e-3
+
+
+def test_policy_gradient_full_size_additive_and_reproducible():
+    """At a full-size batch (1000 Ant envs, h = 32: 32000 rows, 61 ragged row chunks) the
+    parameter gradient is the sum of the gradients of two halves of the batch (envs are
+    independent; the reductions differ only in order), and repeated calls agree bitwise."""
+    W = wl.workload("ant", 1000)
+    h = W["h"]
+    scale = 1.0 / (1000 * h)
+    print("[theta] ant 1000 fp64 additivity", flush=True)
+    g = _theta_run(W, h, 16, "fp64", 1000)
+    W_a = dict(W, s0=W["s0"][:500])
+    W_b = dict(W, s0=W["s0"][500:])
+    ga = _theta_run(W_a, h, 16, "fp64", 500, loss_scale=scale)
+    gb = _theta_run(W_b, h, 16, "fp64", 500, loss_scale=scale)
+    assert relnorm(ga + gb, g) < 1e-12
+    print("[theta] ant 1000 fp32 reproducibility", flush=True)
+    g1 = _theta_run(W, h, 16, "fp32", 1000)
+    g2 = _theta_run(W, h, 16, "fp32", 1000)
+    assert np.array_equal(g1, g2)
+    assert np.isfinite(g1).all()
 
 
 def test_workspace_and_pointer_errors():
@@ -252,6 +331,15 @@ def test_fp64_fallback_factorisation():
     for got, want in ((ad["dL_da"].double().cpu().numpy()[:, envs], ref["dL_da"]),
                       (ad["dL_ds0"].double().cpu().numpy()[envs], ref["dL_ds0"])):
         assert relnorm(got, want) <= 1e-3
+    # the tape does not hold the FP64 factor: flagged substeps are recomputed, bitwise
+    for path in (P.PATH_TAPE,):
+        simt = P.Sim(W["model"], 64, h, [76, 256, 128, 21], [76, 128, 128, 1], path=path,
+                     chol_fp64_threshold=2.0)
+        fwt = simt.forward(W["s0"], W["actor"], W["critic"])
+        adt = simt.adjoint(fwt)
+        torch.cuda.synchronize()
+        assert torch.equal(fwt["s_h"], fw["s_h"])
+        assert torch.equal(adt["dL_da"], ad["dL_da"]) and torch.equal(adt["dL_ds0"], ad["dL_ds0"])
     sim2 = P.Sim(W["model"], 64, h, [76, 256, 128, 21], [76, 128, 128, 1], ckpt_interval=16)
     fw2 = sim2.forward(W["s0"], W["actor"], W["critic"])
     torch.cuda.synchronize()
