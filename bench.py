@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-theta", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-morphology batch")
     return ap.parse_args()
 
 
@@ -113,6 +114,69 @@ def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False):
     fwd_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
     adj_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
     return wall, fwd_ms, adj_ms, fw, ad
+
+
+def mixed_batch(P, wl, torch, budget_gb=48.0, steps=3):
+    """Mixed-morphology batch: 4096 CartPole + 2048 Ant + 1024 Humanoid envs, h = 32.  Each
+    model's launch configuration is picked by the autotuner within a shared workspace
+    budget, then all three go out as one graph-captured group launch; compared with the
+    per-model plain per-substep launch path on the same inputs."""
+    members = [("humanoid", 1024), ("ant", 2048), ("cartpole", 4096)]
+    Ws, dims = [], []
+    for name, n in members:
+        W = wl.workload(name, n)
+        od = W["obs_dim"]
+        Ws.append(W)
+        dims.append(([od] + [w.shape[0] for w, _ in W["actor"]], [od] + [w.shape[0] for w, _ in W["critic"]]))
+    h = Ws[0]["h"]
+    left = budget_gb * 1e9
+    tuned, sims, args, costs = [], [], [], []
+    for (name, n), W, (ad_, cd_) in zip(members, Ws, dims):
+        r = P.tune(W["model"], n, h, ad_, cd_, W["s0"], W["actor"], W["critic"], budget_bytes=int(left), reps=1)
+        left -= r["workspace_bytes"]
+        kw = dict(path=P.PATH_TAPE) if r["path"] == P.PATH_TAPE else dict(ckpt_interval=r["ckpt_interval"])
+        sim = P.Sim(W["model"], n, h, ad_, cd_, **kw)
+        tuned.append({"model": name, "envs": n, "path": "tape" if r["path"] == P.PATH_TAPE else "persistent",
+                      "k": r["ckpt_interval"], "ms_window": round(r["ms_window"], 3),
+                      "workspace_gb": round(r["workspace_bytes"] / 1e9, 2)})
+        sims.append(sim)
+        args.append((sim._dev(W["s0"]), sim.weights(W["actor"]), sim.weights(W["critic"])))
+        costs.append(r["ms_window"] / n)
+    G = P.Group(sims, cost_hint=costs)
+    total_envs = sum(n for _, n in members)
+
+    def run_group():
+        fws = G.forward(args)
+        G.adjoint(fws)
+
+    def run_plain(plains):
+        for sim, a in zip(plains, args):
+            fw = sim.forward(*a)
+            sim.adjoint(fw)
+
+    run_group()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_group()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / steps
+    plains = [P.Sim(W["model"], n, h, ad_, cd_, path=P.PATH_PLAIN)
+              for (name, n), W, (ad_, cd_) in zip(members, Ws, dims)]
+    run_plain(plains)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_plain(plains)
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / steps
+    order = [members[i][0] for i in G.order()]
+    return {"workload": "4096 cartpole + 2048 ant + 1024 humanoid envs, h=32, one graph-captured group "
+                        "launch per direction (autotuned path / k per model, 48 GB workspace budget)",
+            "value": round(total_envs * h / tg, 1), "unit": "env-steps/s", "ms_per_step": round(tg * 1e3, 3),
+            "dispatch_order": order, "tuned": tuned, "graph_captures": G.captures(),
+            "plain_per_model": {"value": round(total_envs * h / tp, 1), "ms_per_step": round(tp * 1e3, 3)},
+            "speedup_vs_plain": round(tp / tg, 3)}
 
 
 def grad_err(a, b, per_env_axis=None):
@@ -244,6 +308,9 @@ def main():
                              "persistent_speedup": round(value / pval, 3),
                              "tape_speedup": round(tval / pval, 3)}
         del plain
+
+    if not args.no_mixed:
+        out["mixed"] = mixed_batch(P, wl, torch)
 
     if not args.no_parity:
         # FP32 error against the FP64 instantiation of the same kernels, beside the

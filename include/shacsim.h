@@ -201,6 +201,49 @@ int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream);
 
 void sim_destroy(SimHandle* h);
 
+/* ---- Mixed-morphology batches.  A group runs the windows of several handles (models
+ * with different DOF, contact and action counts, each with its own N, weights and
+ * workspace) as ONE kernel launch: a work table maps every block to (model, env), the
+ * models ordered by decreasing per-env cost so that the longest windows start first (the
+ * environments of all models are independent, Sec. 3.1).  The launch (with the weight
+ * preparation and, in the adjoint, the parameter-gradient passes) is captured once into a
+ * HIP graph on a stream the group owns and replayed with hipGraphLaunch on the caller's
+ * stream; it is captured again when the arguments change.  Results are bitwise those of
+ * the members' own sim_forward_window / sim_adjoint_window calls. */
+#define SIM_MAX_GROUP 6
+typedef struct SimGroup SimGroup;
+
+/* members: n (1..SIM_MAX_GROUP) distinct handles of one precision on the current device,
+ * persistent or tape path.  cost_hint: optional per-env cost of each member (e.g. the
+ * us_per_env of sim_tune) for the dispatch order; NULL = estimate from the model.  The
+ * handles must outlive the group. */
+int sim_group_create(SimHandle* const* members, int n, const double* cost_hint, SimGroup** out);
+/* ios[i] is member i's argument block, as for its own call. */
+int sim_group_forward(SimGroup* g, const SimForwardIO* ios, void* hip_stream);
+int sim_group_adjoint(SimGroup* g, const SimAdjointIO* ios, void* hip_stream);
+/* order[s] (optional) = member index dispatched in work-table slot s; n_captures
+ * (optional) = graphs captured so far (a call with the same arguments as the previous
+ * one of its kind replays its graph). */
+int sim_group_info(const SimGroup* g, int* order, int* n_captures);
+void sim_group_destroy(SimGroup* g);
+
+/* ---- Autotuner.  Times forward + adjoint windows of one model on the caller's inputs
+ * for every launch configuration whose workspace fits workspace_budget: the tape path and
+ * the persistent path at every checkpoint interval k dividing S; returns the fastest
+ * (median of reps windows after a warm-up).  opt supplies everything else (N, h, MLP
+ * shapes, precision).  io supplies s0, the weights (or actions_in) and the forward output
+ * buffers, which the tuner overwrites; its workspace fields are ignored.  A set-up call:
+ * it allocates and frees its own workspaces and synchronizes the stream. */
+typedef struct SimTuneResult {
+  int path;                      /* SIM_PATH_TAPE or SIM_PATH_PERSISTENT */
+  int ckpt_interval;             /* k for the chosen path */
+  size_t workspace_bytes;        /* workspace of the chosen configuration */
+  double ms_window;              /* its forward + adjoint time per window */
+  int n_candidates;              /* configurations timed */
+} SimTuneResult;
+int sim_tune(const SimModelDesc* model, const SimOptions* opt, const SimForwardIO* io,
+             size_t workspace_budget, int reps, void* hip_stream, SimTuneResult* out);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* sim_last_error(void);
 

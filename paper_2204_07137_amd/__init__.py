@@ -57,8 +57,16 @@ class SimAdjointIO(ctypes.Structure):
                 ("dL_dtheta", _p)]
 
 
+class SimTuneResult(ctypes.Structure):
+    _fields_ = [("path", _i), ("ckpt_interval", _i), ("workspace_bytes", ctypes.c_size_t),
+                ("ms_window", _d), ("n_candidates", _i)]
+
+
 EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
-           "sim_adjoint_window", "sim_destroy", "sim_last_error"]
+           "sim_adjoint_window", "sim_destroy", "sim_last_error", "sim_group_create",
+           "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
+           "sim_tune"]
+MAX_GROUP = 6
 
 _LIB = None
 
@@ -84,6 +92,20 @@ def lib():
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = []
         L.sim_last_error.restype = ctypes.c_char_p
+        L.sim_group_create.argtypes = [ctypes.POINTER(_p), _i, ctypes.POINTER(_d), ctypes.POINTER(_p)]
+        L.sim_group_create.restype = _i
+        L.sim_group_forward.argtypes = [_p, ctypes.POINTER(SimForwardIO), _p]
+        L.sim_group_forward.restype = _i
+        L.sim_group_adjoint.argtypes = [_p, ctypes.POINTER(SimAdjointIO), _p]
+        L.sim_group_adjoint.restype = _i
+        L.sim_group_info.argtypes = [_p, ctypes.POINTER(_i), ctypes.POINTER(_i)]
+        L.sim_group_info.restype = _i
+        L.sim_group_destroy.argtypes = [_p]
+        L.sim_group_destroy.restype = None
+        L.sim_tune.argtypes = [ctypes.POINTER(SimModelDesc), ctypes.POINTER(SimOptions),
+                               ctypes.POINTER(SimForwardIO), ctypes.c_size_t, _i, _p,
+                               ctypes.POINTER(SimTuneResult)]
+        L.sim_tune.restype = _i
         _LIB = L
     return _LIB
 
@@ -152,6 +174,7 @@ class Sim:
         L = lib()
         self.md = md
         d, self._keep = model_desc(md)
+        self._desc = d
         o = SimOptions()
         o.n_envs = int(n_envs)
         o.horizon = int(horizon)
@@ -210,21 +233,35 @@ class Sim:
 
     def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None):
         """Run sim_forward_window.  Returns a dict of device tensors."""
+        out, io = self.forward_io(s0, actor, critic, actions_in)
+        t = self.torch
+        st = stream if stream is not None else t.cuda.current_stream()
+        _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
+        return out
+
+    def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None):
+        """Allocate the forward outputs (or reuse those of `out`, a previous result) and
+        fill a SimForwardIO (no launch)."""
         t = self.torch
         N, H = self.N, self.H
         s0 = self._dev(s0)
         assert s0.shape == (N, self.ns), (s0.shape, (N, self.ns))
         dt = self.dtype
-        out = dict(
-            s0=s0,
-            s_h=t.empty(N, self.ns, device="cuda", dtype=dt),
-            obs=t.empty(H + 1, N, self.od, device="cuda", dtype=dt),
-            actions=t.empty(H, N, self.na, device="cuda", dtype=dt),
-            rewards=t.empty(H, N, device="cuda", dtype=dt),
-            value=t.empty(N, device="cuda", dtype=dt),
-            nonfinite=t.zeros(N, dtype=t.uint8, device="cuda"),
-            fp64_refactor_count=t.zeros(N, dtype=t.int32, device="cuda"),
-        )
+        keys = ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count")
+        if out is not None:
+            out = {k: out[k] for k in keys}
+            out["s0"] = s0
+        else:
+            out = dict(
+                s0=s0,
+                s_h=t.empty(N, self.ns, device="cuda", dtype=dt),
+                obs=t.empty(H + 1, N, self.od, device="cuda", dtype=dt),
+                actions=t.empty(H, N, self.na, device="cuda", dtype=dt),
+                rewards=t.empty(H, N, device="cuda", dtype=dt),
+                value=t.empty(N, device="cuda", dtype=dt),
+                nonfinite=t.zeros(N, dtype=t.uint8, device="cuda"),
+                fp64_refactor_count=t.zeros(N, dtype=t.int32, device="cuda"),
+            )
         io = SimForwardIO()
         io.s0 = self._ptr(s0)
         if actions_in is not None:
@@ -237,9 +274,8 @@ class Sim:
         io.workspace_bytes = self.workspace.numel()
         for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count"):
             setattr(io, k, self._ptr(out[k]))
-        st = stream if stream is not None else t.cuda.current_stream()
-        _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
-        return out
+        out["_io"] = io
+        return out, io
 
     def _set_weights(self, io, actor, critic, keep):
         if actor is not None:
@@ -261,11 +297,24 @@ class Sim:
         loss_scale defaults to 1/(N h), the gradient of the actor loss itself.  With
         want_theta (handle created with policy_grad=True) the result also holds
         dL_dtheta, a list of (dW [out, in], db [out]) views of one flat buffer."""
+        out, io = self.adjoint_io(fw, actor, critic, grad_s_h, loss_scale, want_theta)
+        t = self.torch
+        st = stream if stream is not None else t.cuda.current_stream()
+        _check(lib().sim_adjoint_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
+        return out
+
+    def adjoint_io(self, fw, actor=None, critic=None, grad_s_h=None, loss_scale=None, want_theta=False,
+                   out=None):
+        """Allocate the adjoint outputs (or reuse those of `out`) and fill a SimAdjointIO."""
         t = self.torch
         N, H = self.N, self.H
         dt = self.dtype
-        out = dict(dL_da=t.empty(H, N, self.na, device="cuda", dtype=dt),
-                   dL_ds0=t.empty(N, self.ns, device="cuda", dtype=dt))
+        prev = out
+        if prev is not None:
+            out = dict(dL_da=prev["dL_da"], dL_ds0=prev["dL_ds0"])
+        else:
+            out = dict(dL_da=t.empty(H, N, self.na, device="cuda", dtype=dt),
+                       dL_ds0=t.empty(N, self.ns, device="cuda", dtype=dt))
         io = SimAdjointIO()
         io.s0 = self._ptr(fw["s0"])
         io.actions = self._ptr(fw["actions"])
@@ -285,7 +334,8 @@ class Sim:
         if want_theta:
             dims = self.actor_dims
             n = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
-            flat = t.empty(n, device="cuda", dtype=dt)
+            flat = (prev["dL_dtheta_flat"] if prev is not None and "dL_dtheta_flat" in prev
+                    else t.empty(n, device="cuda", dtype=dt))
             out["dL_dtheta_flat"] = flat
             io.dL_dtheta = self._ptr(flat)
             views, off = [], 0
@@ -295,9 +345,93 @@ class Sim:
                               flat[off + nw:off + nw + dims[i + 1]]))
                 off += nw + dims[i + 1]
             out["dL_dtheta"] = views
-        st = stream if stream is not None else t.cuda.current_stream()
-        _check(lib().sim_adjoint_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
-        return out
+        out["_io"] = io
+        return out, io
+
+
+class Group:
+    """A mixed-morphology batch: the windows of several Sim handles in one graph-captured
+    kernel launch (sim_group_*).  cost_hint: optional per-env costs for the dispatch order."""
+
+    def __init__(self, sims, cost_hint=None):
+        import torch
+        self.torch = torch
+        self.sims = list(sims)
+        n = len(self.sims)
+        arr = (_p * n)(*[s.h for s in self.sims])
+        hint = (_d * n)(*cost_hint) if cost_hint is not None else None
+        g = _p()
+        _check(lib().sim_group_create(arr, n, hint, ctypes.byref(g)))
+        self.g = g
+
+    def order(self):
+        o = (_i * len(self.sims))()
+        _check(lib().sim_group_info(self.g, o, None))
+        return list(o)
+
+    def captures(self):
+        c = _i()
+        _check(lib().sim_group_info(self.g, None, ctypes.byref(c)))
+        return c.value
+
+    def close(self):
+        if getattr(self, "g", None):
+            lib().sim_group_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, args, stream=None):
+        """args: per member (s0, actor, critic[, actions_in]).  Returns per-member dicts.
+        The output tensors are kept and reused by the next call, so repeated calls with the
+        same inputs replay one captured graph (copy results out before calling again)."""
+        outs, ios = [], []
+        prev = getattr(self, "_fw", None) or [None] * len(self.sims)
+        for sim, a, pv in zip(self.sims, args, prev):
+            o, io = sim.forward_io(*a, out=pv)
+            outs.append(o)
+            ios.append(io)
+        arr = (SimForwardIO * len(ios))(*ios)
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        _check(lib().sim_group_forward(self.g, arr, _p(st.cuda_stream)))
+        self._fw = outs
+        return outs
+
+    def adjoint(self, fws, want_theta=False, stream=None):
+        outs, ios = [], []
+        prev = getattr(self, "_ad", None) or [None] * len(self.sims)
+        for sim, fw, pv in zip(self.sims, fws, prev):
+            o, io = sim.adjoint_io(fw, want_theta=want_theta, out=pv)
+            outs.append(o)
+            ios.append(io)
+        arr = (SimAdjointIO * len(ios))(*ios)
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        _check(lib().sim_group_adjoint(self.g, arr, _p(st.cuda_stream)))
+        self._ad = outs
+        return outs
+
+
+def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget_bytes,
+         reps=3, precision="fp32", gamma=0.99):
+    """Run sim_tune: the fastest launch configuration (path, k) of this model within a
+    workspace budget.  Returns a dict with path, ckpt_interval, workspace_bytes,
+    ms_window and n_candidates."""
+    import torch
+    probe = Sim(md, n_envs, horizon, actor_dims, critic_dims, ckpt_interval=md["substeps"],
+                precision=precision, gamma=gamma)
+    out, io = probe.forward_io(s0, actor, critic)
+    r = SimTuneResult()
+    st = torch.cuda.current_stream()
+    _check(lib().sim_tune(ctypes.byref(probe._desc), ctypes.byref(probe.opt), ctypes.byref(io),
+                          int(budget_bytes), int(reps),
+                          _p(st.cuda_stream), ctypes.byref(r)))
+    probe.close()
+    return {"path": r.path, "ckpt_interval": r.ckpt_interval, "workspace_bytes": r.workspace_bytes,
+            "ms_window": r.ms_window, "n_candidates": r.n_candidates, "keep": out}
 
 
 def window_function():

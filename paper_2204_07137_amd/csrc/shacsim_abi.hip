@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/shacsim.h"
 #include "sim_types.h"
@@ -363,11 +364,11 @@ int launch_transposes<double>(const MlpArgsT<double>& P, void* s) {
   return 0;
 }
 
+// ---------------------------------------------------------------- argument building
 template <typename T>
-static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
+static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>& A) {
   const SimOptions& o = h->opt;
   char* ws = static_cast<char*>(io->workspace);
-  WinArgsT<T> A;
   std::memset(&A, 0, sizeof(A));
   A.model = static_cast<const DevModelT<T>*>(h->dev_model);
   A.N = o.n_envs; A.h = o.horizon; A.k = o.ckpt_interval; A.closed_loop = o.closed_loop;
@@ -389,24 +390,14 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
-  A.tape_full = (o.path == SIM_PATH_TAPE);
-  int bad = 0;
-  if (o.closed_loop) bad |= launch_transposes(A.actor, stream);
-  bad |= launch_transposes(A.critic, stream);
-  int plain = (o.path == SIM_PATH_PLAIN);
-  if (sizeof(T) == 4)
-    bad |= sim_f32::launch_forward(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, h->nv, stream);
-  else
-    bad |= sim_f64::launch_forward(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, h->nv, stream);
-  if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  A.tape_full = (h->opt.path == SIM_PATH_TAPE);
   return SIM_OK;
 }
 
 template <typename T>
-static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
+static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>& A) {
   const SimOptions& o = h->opt;
   char* ws = static_cast<char*>(io->workspace);
-  WinArgsT<T> A;
   std::memset(&A, 0, sizeof(A));
   A.model = static_cast<const DevModelT<T>*>(h->dev_model);
   A.N = o.n_envs; A.h = o.horizon; A.k = o.ckpt_interval; A.closed_loop = o.closed_loop;
@@ -430,47 +421,87 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   A.grad_s_h = static_cast<const T*>(io->grad_s_h);
   A.dL_da = static_cast<T*>(io->dL_da);
   A.dL_ds0 = static_cast<T*>(io->dL_ds0);
-  int plain = (o.path == SIM_PATH_PLAIN);
-  int bad;
-  if (sizeof(T) == 4)
-    bad = sim_f32::launch_adjoint(*reinterpret_cast<const WinArgsT<float>*>(&A), plain, h->substeps, h->nv, stream);
-  else
-    bad = sim_f64::launch_adjoint(*reinterpret_cast<const WinArgsT<double>*>(&A), plain, h->substeps, h->nv, stream);
-  if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return SIM_OK;
+}
+
+template <typename T>
+static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>& P) {
+  const SimOptions& o = h->opt;
+  char* ws = static_cast<char*>(io->workspace);
+  std::memset(&P, 0, sizeof(P));
+  P.M = o.n_envs * o.horizon;
+  P.nl = o.actor_layers;
+  for (int l = 0; l <= o.actor_layers; ++l) P.dims[l] = o.actor_dims[l];
+  P.splits = h->th_splits;
+  long off = 0;
+  for (int l = 0; l < o.actor_layers; ++l) {
+    P.W[l] = static_cast<const T*>(io->actor_w[l]);
+    P.b[l] = static_cast<const T*>(io->actor_b[l]);
+    P.off_w[l] = off;
+    off += (long)o.actor_dims[l] * o.actor_dims[l + 1];
+    P.off_b[l] = off;
+    off += o.actor_dims[l + 1];
+    if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + h->off_th_h[l]);
+  }
+  P.x0 = static_cast<const T*>(io->obs);
+  P.act = static_cast<const T*>(io->actions);
+  P.da = static_cast<const T*>(io->dL_da);
+  P.d0 = reinterpret_cast<T*>(ws + h->off_th_d0);
+  P.d1 = reinterpret_cast<T*>(ws + h->off_th_d1);
+  P.part = reinterpret_cast<T*>(ws + h->off_th_part);
+  P.out = static_cast<T*>(io->dL_dtheta);
+}
+
+// ---------------------------------------------------------------- launches (FP32 / FP64)
+static int do_prep(const WinArgsT<float>& A, void* s) {
+  int bad = A.closed_loop ? launch_transposes(A.actor, s) : 0;
+  return bad | launch_transposes(A.critic, s);
+}
+static int do_prep(const WinArgsT<double>& A, void* s) {
+  int bad = A.closed_loop ? launch_transposes(A.actor, s) : 0;
+  return bad | launch_transposes(A.critic, s);
+}
+static int do_window(const WinArgsT<float>& A, int adjoint, int plain, int S, int nv, void* s) {
+  return adjoint ? sim_f32::launch_adjoint(A, plain, S, nv, s) : sim_f32::launch_forward(A, plain, S, nv, s);
+}
+static int do_window(const WinArgsT<double>& A, int adjoint, int plain, int S, int nv, void* s) {
+  return adjoint ? sim_f64::launch_adjoint(A, plain, S, nv, s) : sim_f64::launch_forward(A, plain, S, nv, s);
+}
+static int do_theta(const ThetaArgsT<float>& P, void* s) { return sim_f32::launch_theta(P, s); }
+static int do_theta(const ThetaArgsT<double>& P, void* s) { return sim_f64::launch_theta(P, s); }
+static int do_group(const GroupArgsT<float>& G, int adjoint, void* s) { return sim_f32::launch_group(G, adjoint, s); }
+static int do_group(const GroupArgsT<double>& G, int adjoint, void* s) { return sim_f64::launch_group(G, adjoint, s); }
+
+static int launch_failed() {
+  return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+}
+
+template <typename T>
+static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
+  WinArgsT<T> A;
+  int rc = build_forward_args<T>(h, io, A);
+  if (rc) return rc;
+  int bad = do_prep(A, stream);
+  bad |= do_window(A, 0, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, stream);
+  return bad ? launch_failed() : SIM_OK;
+}
+
+template <typename T>
+static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
+  WinArgsT<T> A;
+  int rc = build_adjoint_args<T>(h, io, A);
+  if (rc) return rc;
+  if (do_window(A, 1, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, stream)) return launch_failed();
   if (io->dL_dtheta) {
     ThetaArgsT<T> P;
-    std::memset(&P, 0, sizeof(P));
-    P.M = o.n_envs * o.horizon;
-    P.nl = o.actor_layers;
-    for (int l = 0; l <= o.actor_layers; ++l) P.dims[l] = o.actor_dims[l];
-    P.splits = h->th_splits;
-    long off = 0;
-    for (int l = 0; l < o.actor_layers; ++l) {
-      P.W[l] = static_cast<const T*>(io->actor_w[l]);
-      P.b[l] = static_cast<const T*>(io->actor_b[l]);
-      P.off_w[l] = off;
-      off += (long)o.actor_dims[l] * o.actor_dims[l + 1];
-      P.off_b[l] = off;
-      off += o.actor_dims[l + 1];
-      if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + h->off_th_h[l]);
-    }
-    P.x0 = static_cast<const T*>(io->obs);
-    P.act = static_cast<const T*>(io->actions);
-    P.da = static_cast<const T*>(io->dL_da);
-    P.d0 = reinterpret_cast<T*>(ws + h->off_th_d0);
-    P.d1 = reinterpret_cast<T*>(ws + h->off_th_d1);
-    P.part = reinterpret_cast<T*>(ws + h->off_th_part);
-    P.out = static_cast<T*>(io->dL_dtheta);
-    if (sizeof(T) == 4)
-      bad = sim_f32::launch_theta(*reinterpret_cast<const ThetaArgsT<float>*>(&P), stream);
-    else
-      bad = sim_f64::launch_theta(*reinterpret_cast<const ThetaArgsT<double>*>(&P), stream);
-    if (bad) return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+    build_theta_args<T>(h, io, P);
+    if (do_theta(P, stream)) return launch_failed();
   }
   return SIM_OK;
 }
 
-extern "C" int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hip_stream) {
+// ---------------------------------------------------------------- argument checks
+static int check_forward_io(SimHandle* h, const SimForwardIO* io) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!io) return fail(SIM_E_ARG, "null io");
@@ -480,10 +511,10 @@ extern "C" int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hi
   if (!o.closed_loop && !io->actions_in) return fail(SIM_E_ARG, "open loop needs actions_in");
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
-  return (o.precision == SIM_PREC_FP64) ? run_forward<double>(h, io, hip_stream) : run_forward<float>(h, io, hip_stream);
+  return SIM_OK;
 }
 
-extern "C" int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream) {
+static int check_adjoint_io(SimHandle* h, const SimAdjointIO* io) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!io) return fail(SIM_E_ARG, "null io");
@@ -498,5 +529,304 @@ extern "C" int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hi
   }
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
-  return (o.precision == SIM_PREC_FP64) ? run_adjoint<double>(h, io, hip_stream) : run_adjoint<float>(h, io, hip_stream);
+  return SIM_OK;
+}
+
+extern "C" int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hip_stream) {
+  int rc = check_forward_io(h, io);
+  if (rc) return rc;
+  return (h->opt.precision == SIM_PREC_FP64) ? run_forward<double>(h, io, hip_stream)
+                                             : run_forward<float>(h, io, hip_stream);
+}
+
+extern "C" int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream) {
+  int rc = check_adjoint_io(h, io);
+  if (rc) return rc;
+  return (h->opt.precision == SIM_PREC_FP64) ? run_adjoint<double>(h, io, hip_stream)
+                                             : run_adjoint<float>(h, io, hip_stream);
+}
+
+// ---------------------------------------------------------------- mixed-morphology groups
+static const uint32_t kGroupMagic = 0x47525053u;
+
+struct SimGroup {
+  int n = 0, precision = 0, device = -1;
+  SimHandle* h[SIM_MAXGROUP];
+  int order[SIM_MAXGROUP];            // member in each work-table slot, decreasing per-env cost
+  double cost[SIM_MAXGROUP];
+  hipStream_t cap = nullptr;          // capture stream (default priority)
+  hipGraphExec_t exec[2] = {nullptr, nullptr};   // forward, adjoint
+  std::string key[2];                 // launch arguments the graph was captured with
+  int captures = 0;
+  uint32_t magic = kGroupMagic;
+};
+
+// Per-env cost estimate of one window: substeps times a per-substep operation count
+// (factorisation, tree passes, contacts) plus the policy MLP per frame.
+static double member_cost(const SimHandle* h) {
+  const double nv = h->nv, J = h->m64.J, nc = h->m64.nc;
+  double mlp = 0;
+  for (int l = 0; l < h->opt.actor_layers; ++l) mlp += (double)h->opt.actor_dims[l] * h->opt.actor_dims[l + 1];
+  return h->opt.horizon * (h->substeps * (nv * nv * nv / 3.0 + 2.0 * nv * nv + 900.0 * J + 120.0 * nc) + 3.0 * mlp);
+}
+
+static int check_group(SimGroup* g) {
+  if (!g || g->magic != kGroupMagic) return fail(SIM_E_HANDLE, "invalid group");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_E_HIP, "hipGetDevice failed");
+  if (dev != g->device) return fail(SIM_E_ARG, "group was created on another device");
+  return SIM_OK;
+}
+
+extern "C" int sim_group_create(SimHandle* const* members, int n, const double* cost_hint, SimGroup** out) {
+  if (!members || !out) return fail(SIM_E_ARG, "sim_group_create: null argument");
+  *out = nullptr;
+  if (n < 1 || n > SIM_MAXGROUP) return fail(SIM_E_ARG, "a group holds 1 to SIM_MAX_GROUP models");
+  for (int i = 0; i < n; ++i) {
+    int rc = check_handle(members[i]);
+    if (rc) return rc;
+    if (members[i]->opt.path == SIM_PATH_PLAIN)
+      return fail(SIM_E_UNSUPPORTED, "group members must use the persistent or tape path");
+    if (members[i]->opt.precision != members[0]->opt.precision)
+      return fail(SIM_E_ARG, "group members must share one precision");
+    for (int j = 0; j < i; ++j)
+      if (members[j] == members[i]) return fail(SIM_E_ARG, "a handle appears twice in the group");
+  }
+  SimGroup* g = new SimGroup();
+  g->n = n;
+  g->precision = members[0]->opt.precision;
+  g->device = members[0]->device;
+  for (int i = 0; i < n; ++i) {
+    g->h[i] = members[i];
+    g->cost[i] = (cost_hint && cost_hint[i] > 0) ? cost_hint[i] : member_cost(members[i]);
+    g->order[i] = i;
+  }
+  std::stable_sort(g->order, g->order + n, [g](int a, int b) { return g->cost[a] > g->cost[b]; });
+  if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return fail(SIM_E_HIP, "hipStreamCreate failed");
+  }
+  *out = g;
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" void sim_group_destroy(SimGroup* g) {
+  if (!g || g->magic != kGroupMagic) return;
+  g->magic = 0;
+  for (int i = 0; i < 2; ++i)
+    if (g->exec[i]) hipGraphExecDestroy(g->exec[i]);
+  if (g->cap) hipStreamDestroy(g->cap);
+  delete g;
+}
+
+extern "C" int sim_group_info(const SimGroup* g, int* order, int* n_captures) {
+  if (!g || g->magic != kGroupMagic) return fail(SIM_E_HANDLE, "invalid group");
+  if (order)
+    for (int i = 0; i < g->n; ++i) order[i] = g->order[i];
+  if (n_captures) *n_captures = g->captures;
+  return SIM_OK;
+}
+
+// Captures `enqueue` on the group's stream into a graph (once per distinct argument set)
+// and launches it on the caller's stream.
+template <typename F>
+static int group_launch(SimGroup* g, int which, const std::string& key, void* stream, F&& enqueue) {
+  if (!g->exec[which] || g->key[which] != key) {
+    if (g->exec[which]) {
+      hipGraphExecDestroy(g->exec[which]);
+      g->exec[which] = nullptr;
+    }
+    if (hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(SIM_E_HIP, "hipStreamBeginCapture failed");
+    int bad = enqueue(static_cast<void*>(g->cap));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g->cap, &graph);
+    if (bad || e != hipSuccess || !graph) {
+      if (graph) hipGraphDestroy(graph);
+      return fail(SIM_E_HIP, "graph capture of the group launch failed");
+    }
+    e = hipGraphInstantiate(&g->exec[which], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g->exec[which] = nullptr;
+      return fail(SIM_E_HIP, "hipGraphInstantiate failed");
+    }
+    g->key[which] = key;
+    g->captures++;
+  }
+  if (hipGraphLaunch(g->exec[which], (hipStream_t)stream) != hipSuccess) return fail(SIM_E_HIP, "hipGraphLaunch failed");
+  return SIM_OK;
+}
+
+template <typename T>
+static int run_group_forward(SimGroup* g, const SimForwardIO* ios, void* stream) {
+  GroupArgsT<T> G;
+  std::memset(&G, 0, sizeof(G));
+  G.n = g->n;
+  int start = 0;
+  for (int s = 0; s < g->n; ++s) {
+    SimHandle* h = g->h[g->order[s]];
+    int rc = build_forward_args<T>(h, &ios[g->order[s]], G.A[s]);
+    if (rc) return rc;
+    G.start[s] = start;
+    G.nv[s] = h->nv;
+    start += h->opt.n_envs;
+  }
+  G.start[g->n] = start;
+  std::string key(reinterpret_cast<const char*>(&G), sizeof(G));
+  return group_launch(g, 0, key, stream, [&](void* cs) {
+    int bad = 0;
+    for (int s = 0; s < G.n; ++s) bad |= do_prep(G.A[s], cs);
+    return bad | do_group(G, 0, cs);
+  });
+}
+
+template <typename T>
+static int run_group_adjoint(SimGroup* g, const SimAdjointIO* ios, void* stream) {
+  GroupArgsT<T> G;
+  std::memset(&G, 0, sizeof(G));
+  G.n = g->n;
+  ThetaArgsT<T> P[SIM_MAXGROUP];
+  int has_theta[SIM_MAXGROUP];
+  int start = 0;
+  std::string key;
+  for (int s = 0; s < g->n; ++s) {
+    const int mi = g->order[s];
+    SimHandle* h = g->h[mi];
+    int rc = build_adjoint_args<T>(h, &ios[mi], G.A[s]);
+    if (rc) return rc;
+    G.start[s] = start;
+    G.nv[s] = h->nv;
+    start += h->opt.n_envs;
+    has_theta[s] = ios[mi].dL_dtheta != nullptr;
+    if (has_theta[s]) {
+      build_theta_args<T>(h, &ios[mi], P[s]);
+      key.append(reinterpret_cast<const char*>(&P[s]), sizeof(P[s]));
+    }
+  }
+  G.start[g->n] = start;
+  key.append(reinterpret_cast<const char*>(&G), sizeof(G));
+  return group_launch(g, 1, key, stream, [&](void* cs) {
+    int bad = do_group(G, 1, cs);
+    for (int s = 0; s < G.n; ++s)
+      if (has_theta[s]) bad |= do_theta(P[s], cs);
+    return bad;
+  });
+}
+
+extern "C" int sim_group_forward(SimGroup* g, const SimForwardIO* ios, void* hip_stream) {
+  int rc = check_group(g);
+  if (rc) return rc;
+  if (!ios) return fail(SIM_E_ARG, "null io array");
+  for (int i = 0; i < g->n; ++i) {
+    rc = check_forward_io(g->h[i], &ios[i]);
+    if (rc) return rc;
+  }
+  return g->precision == SIM_PREC_FP64 ? run_group_forward<double>(g, ios, hip_stream)
+                                       : run_group_forward<float>(g, ios, hip_stream);
+}
+
+extern "C" int sim_group_adjoint(SimGroup* g, const SimAdjointIO* ios, void* hip_stream) {
+  int rc = check_group(g);
+  if (rc) return rc;
+  if (!ios) return fail(SIM_E_ARG, "null io array");
+  for (int i = 0; i < g->n; ++i) {
+    rc = check_adjoint_io(g->h[i], &ios[i]);
+    if (rc) return rc;
+  }
+  return g->precision == SIM_PREC_FP64 ? run_group_adjoint<double>(g, ios, hip_stream)
+                                       : run_group_adjoint<float>(g, ios, hip_stream);
+}
+
+// ---------------------------------------------------------------- autotuner
+// Times forward + adjoint windows for every launch configuration of one model whose
+// workspace fits the budget (the tape path, then every checkpoint interval k dividing S)
+// and reports the fastest.  A set-up call: it allocates and frees its own workspaces.
+extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const SimForwardIO* io,
+                        size_t workspace_budget, int reps, void* hip_stream, SimTuneResult* out) {
+  if (!model || !opt || !io || !out) return fail(SIM_E_ARG, "sim_tune: null argument");
+  if (reps < 1) return fail(SIM_E_ARG, "sim_tune: reps must be >= 1");
+  std::memset(out, 0, sizeof(*out));
+  hipStream_t st = (hipStream_t)hip_stream;
+  struct Cand { int path, k; };
+  std::vector<Cand> cands;
+  cands.push_back({SIM_PATH_TAPE, 1});
+  for (int k = 1; k <= model->substeps; ++k)
+    if (model->substeps % k == 0) cands.push_back({SIM_PATH_PERSISTENT, k});
+  double best = -1.0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SIM_E_HIP, "hipEventCreate failed");
+  int rc = SIM_OK;
+  for (const Cand& c : cands) {
+    SimOptions o = *opt;
+    o.path = c.path;
+    o.ckpt_interval = c.k;
+    SimHandle* h = nullptr;
+    rc = sim_create(model, &o, &h);
+    if (rc) break;
+    const size_t ws = h->ws_bytes;
+    if (ws > workspace_budget) {
+      sim_destroy(h);
+      continue;
+    }
+    const size_t e = h->elem;
+    void *wsp = nullptr, *da = nullptr, *ds0 = nullptr;
+    if (hipMalloc(&wsp, ws > 0 ? ws : 256) != hipSuccess ||
+        hipMalloc(&da, e * (size_t)o.horizon * o.n_envs * std::max(h->na, 1)) != hipSuccess ||
+        hipMalloc(&ds0, e * (size_t)o.n_envs * h->ns) != hipSuccess) {
+      if (wsp) hipFree(wsp);
+      if (da) hipFree(da);
+      sim_destroy(h);
+      rc = fail(SIM_E_HIP, "sim_tune: hipMalloc failed");
+      break;
+    }
+    SimForwardIO fio = *io;
+    fio.workspace = wsp;
+    fio.workspace_bytes = ws;
+    SimAdjointIO aio;
+    std::memset(&aio, 0, sizeof(aio));
+    aio.s0 = io->s0; aio.actions = io->actions; aio.obs = io->obs; aio.s_h = io->s_h;
+    for (int l = 0; l < SIM_MAXL; ++l) {
+      aio.actor_w[l] = io->actor_w[l]; aio.actor_b[l] = io->actor_b[l];
+      aio.critic_w[l] = io->critic_w[l]; aio.critic_b[l] = io->critic_b[l];
+    }
+    aio.workspace = wsp;
+    aio.workspace_bytes = ws;
+    aio.loss_scale = 1.0 / ((double)o.n_envs * o.horizon);
+    aio.dL_da = da;
+    aio.dL_ds0 = ds0;
+    std::vector<float> t;
+    for (int r = 0; r <= reps && rc == SIM_OK; ++r) {   // the first window is a warm-up
+      hipEventRecord(e0, st);
+      rc = sim_forward_window(h, &fio, st);
+      if (!rc) rc = sim_adjoint_window(h, &aio, st);
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = fail(SIM_E_HIP, "sim_tune: window failed");
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) t.push_back(ms);
+    }
+    hipFree(wsp);
+    hipFree(da);
+    hipFree(ds0);
+    sim_destroy(h);
+    if (rc) break;
+    std::sort(t.begin(), t.end());
+    const double med = t[t.size() / 2];
+    out->n_candidates++;
+    if (best < 0 || med < best) {
+      best = med;
+      out->path = c.path;
+      out->ckpt_interval = c.k;
+      out->workspace_bytes = ws;
+      out->ms_window = med;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (best < 0) return fail(SIM_E_WORKSPACE, "sim_tune: no configuration fits the workspace budget");
+  g_err.clear();
+  return SIM_OK;
 }

@@ -72,12 +72,12 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restr
 }
 
 // ======================================================================= persistent forward
+// One environment's forward window (the wavefront owns env; E is its LDS).
 template <int NV>
-__global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
-  __shared__ EnvLDS E;
+__device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, EnvLDS& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
-  const int env = blockIdx.x, ln = threadIdx.x;
+  const int ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
   load_regs(A.model, E, ln, jr, cr);
@@ -170,12 +170,12 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   (void)ns;
 }
 
+// One environment's reverse window.
 template <int NV>
-__global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
-  __shared__ EnvLDS E;
+__device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLDS& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
-  const int env = blockIdx.x, ln = threadIdx.x;
+  const int ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
   load_regs(A.model, E, ln, jr, cr);
@@ -231,6 +231,51 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
   for (int i = ln; i < nv; i += SIM_WAVE) d0[nq + i] = E.qdb[i];
   if (m->has_last_action)
     for (int i = ln; i < na; i += SIM_WAVE) d0[nq + nv + i] = E.abar[i];
+}
+
+template <int NV>
+__global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
+  __shared__ EnvLDS E;
+  window_fwd_body<NV>(A, blockIdx.x, E);
+}
+
+template <int NV>
+__global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
+  __shared__ EnvLDS E;
+  window_adj_body<NV>(A, blockIdx.x, E);
+}
+
+// ======================================================================= mixed-morphology group
+// One launch over the envs of several models: block b runs env b - start[s] of the model in
+// work-table slot s (slots ordered by decreasing per-env cost, so the longest windows are
+// dispatched first).  Each slot's model runs the DOF-specialised body of its own kernel.
+__device__ __forceinline__ int group_slot(const GroupArgs& G, int b) {
+  int s = 0;
+  for (int i = 1; i < G.n; ++i) s = (b >= G.start[i]) ? i : s;
+  return s;
+}
+
+#define SIM_GROUP_CASE_F(n) case n: window_fwd_body<n>(G.A[s], env, E); break;
+#define SIM_GROUP_CASE_A(n) case n: window_adj_body<n>(G.A[s], env, E); break;
+
+__global__ __launch_bounds__(SIM_WAVE) void k_group_fwd(GroupArgs G) {
+  __shared__ EnvLDS E;
+  const int s = group_slot(G, blockIdx.x);
+  const int env = blockIdx.x - G.start[s];
+  switch (G.nv[s]) {
+    SIM_NV_LIST(SIM_GROUP_CASE_F)
+    default: window_fwd_body<SIM_MAXV>(G.A[s], env, E);
+  }
+}
+
+__global__ __launch_bounds__(SIM_WAVE) void k_group_adj(GroupArgs G) {
+  __shared__ EnvLDS E;
+  const int s = group_slot(G, blockIdx.x);
+  const int env = blockIdx.x - G.start[s];
+  switch (G.nv[s]) {
+    SIM_NV_LIST(SIM_GROUP_CASE_A)
+    default: window_adj_body<SIM_MAXV>(G.A[s], env, E);
+  }
 }
 
 // ======================================================================= plain path kernels
@@ -435,5 +480,13 @@ int launch_adjoint(const WinArgs& A, int plain, int substeps, int nv, void* stre
     SIM_NV_LIST(SIM_NV_CASE_A)
     default: launch_adjoint_nv<SIM_MAXV>(A, plain, substeps, s);
   }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_group(const GroupArgs& G, int adjoint, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  dim3 grid(G.start[G.n]), block(SIM_WAVE);
+  if (adjoint) hipLaunchKernelGGL(k_group_adj, grid, block, 0, st, G);
+  else hipLaunchKernelGGL(k_group_fwd, grid, block, 0, st, G);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

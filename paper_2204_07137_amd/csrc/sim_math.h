@@ -10,6 +10,7 @@
 typedef DevModelT<real> DevModel;
 typedef MlpArgsT<real> MlpArgs;
 typedef WinArgsT<real> WinArgs;
+typedef GroupArgsT<real> GroupArgs;
 
 // Uniform model scalars, copied once per kernel into registers (the tables in global
 // memory are read only at kernel start).

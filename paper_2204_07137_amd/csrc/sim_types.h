@@ -81,6 +81,17 @@ struct WinArgsT {
   T* dL_ds0;
 };
 
+// Several models' windows in one launch (mixed-morphology batch): work-table slot s covers
+// blocks [start[s], start[s+1]) with the window arguments A[s] of a model with nv[s] DOFs.
+#define SIM_MAXGROUP 6
+template <typename T>
+struct GroupArgsT {
+  int n;
+  int start[SIM_MAXGROUP + 1];
+  int nv[SIM_MAXGROUP];
+  WinArgsT<T> A[SIM_MAXGROUP];
+};
+
 // Policy-parameter gradient pass over the rows (frame, env) of one window.
 template <typename T>
 struct ThetaArgsT {
@@ -108,6 +119,7 @@ struct ThetaArgsT {
   int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
   int launch_prep_weights(const T* W, T* WT, T* Wp, int n_out, int n_in, void* stream);   \
   int launch_theta(const ThetaArgsT<T>& A, void* stream);                                  \
+  int launch_group(const GroupArgsT<T>& G, int adjoint, void* stream);                     \
   }
 SIM_DECLARE_LAUNCHERS(sim_f32, float)
 SIM_DECLARE_LAUNCHERS(sim_f64, double)

@@ -53,6 +53,16 @@ def test_null_arguments_rejected():
     assert L.sim_forward_window(None, None, None) == -2
     assert L.sim_adjoint_window(None, None, None) == -2
     L.sim_destroy(None)
+    g = ctypes.c_void_p()
+    assert L.sim_group_create(None, 2, None, ctypes.byref(g)) == -1
+    bogus = (ctypes.c_void_p * 1)(None)
+    assert L.sim_group_create(bogus, 1, None, ctypes.byref(g)) == -2
+    assert L.sim_group_create(bogus, 0, None, ctypes.byref(g)) == -1
+    assert L.sim_group_forward(None, None, None) == -2
+    assert L.sim_group_adjoint(None, None, None) == -2
+    assert L.sim_group_info(None, None, None) == -2
+    L.sim_group_destroy(None)
+    assert L.sim_tune(None, None, None, 0, 1, None, None) == -1
 
 
 def test_model_limits_rejected():
