@@ -58,7 +58,7 @@ typedef enum {
 } SimStatus;
 
 enum { SIM_JOINT_FREE = 0, SIM_JOINT_HINGE = 1, SIM_JOINT_SLIDE = 2 };
-enum { SIM_TASK_NONE = 0, SIM_TASK_CARTPOLE = 1, SIM_TASK_ANT = 2, SIM_TASK_HUMANOID = 3 };
+enum { SIM_TASK_NONE = 0, SIM_TASK_CARTPOLE = 1, SIM_TASK_ANT = 2, SIM_TASK_HUMANOID = 3, SIM_TASK_MTU = 4 };
 enum { SIM_PATH_PERSISTENT = 0, SIM_PATH_PLAIN = 1, SIM_PATH_TAPE = 2 };
 enum { SIM_PREC_FP32 = 0, SIM_PREC_FP64 = 1 };
 
@@ -66,8 +66,11 @@ enum { SIM_PREC_FP32 = 0, SIM_PREC_FP64 = 1 };
 #define SIM_MAX_JOINTS 32
 #define SIM_MAX_DOFS 32
 #define SIM_MAX_CONTACTS 32
-#define SIM_MAX_ACTIONS 32
-#define SIM_MAX_OBS 128
+#define SIM_MAX_ACTIONS 32             /* motors */
+#define SIM_MAX_MTU 160                /* muscle-tendon units */
+#define SIM_MAX_MTU_POINTS 6           /* path points per unit */
+#define SIM_MAX_MUSCLE_ACTIONS 160     /* motors + muscles of a muscle model */
+#define SIM_MAX_OBS 288
 #define SIM_MAX_HIDDEN 512
 #define SIM_MAX_LAYERS 4
 
@@ -105,6 +108,25 @@ typedef struct SimModelDesc {
   int substeps;                  /* S: semi-implicit Euler substeps per frame */
   int task;                      /* SIM_TASK_*: observation and reward definition */
   int has_last_action;           /* state carries the previous action */
+  /* Muscle-tendon units (Sec. 3.1: muscle actuation through attachment sites on several
+   * bodies; Hill-type reading).  Unit i is a polyline through mtu_npt[i] points, point k
+   * fixed at mtu_pos[i][k] in frame mtu_body[i][k].  With path length L and rate Ldot,
+   * rigid tendon l_m = L - l_slack, the tension is
+   *   F = max(0, F_max act exp(-((l_m/l_opt - 1)/fl_width)^2) (1 + Ldot/(vmax l_opt)))
+   * pulling every path point towards its neighbours; the activation follows
+   * act' = act + dt (u - act)/tau_act per substep with the excitation u.  The actions
+   * are [motor actions (n_act) | excitations (n_mtu)], the state gains the n_mtu
+   * activations after q, qd (and a_prev). */
+  int n_mtu;                     /* 0 = torque-driven model */
+  const int* mtu_npt;            /* [n_mtu], 2..SIM_MAX_MTU_POINTS */
+  const int* mtu_body;           /* [n_mtu][SIM_MAX_MTU_POINTS] */
+  const double* mtu_pos;         /* [n_mtu][SIM_MAX_MTU_POINTS][3] */
+  const double* mtu_fmax;        /* [n_mtu] N */
+  const double* mtu_lopt;        /* [n_mtu] m */
+  const double* mtu_lslack;      /* [n_mtu] m */
+  double tau_act;                /* s */
+  double fl_width;
+  double vmax;                   /* optimal fibre lengths per second */
 } SimModelDesc;
 
 typedef struct SimOptions {

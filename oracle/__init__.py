@@ -19,8 +19,10 @@ computes, written from the paper's method section and appendix:
 Only the test-suite, the package smoke check and the benchmark's CPU-baseline leg
 may import this package.  The product path never calls it.
 """
-from .dynamics import OracleModel, substep, dynamics_terms, kinetic_energy, potential_energy
-from .window import oracle_window, oracle_window_grads, obs_fn, reward_fn, mlp_forward
+from .dynamics import (OracleModel, substep, dynamics_terms, kinetic_energy, potential_energy,
+                       muscle_terms, activation_step)
+from .window import (oracle_window, oracle_window_grads, obs_fn, reward_fn, mlp_forward,
+                     mlp_forward_bf16, bf16_round, squash)
 
 __all__ = ["OracleModel", "substep", "dynamics_terms", "kinetic_energy", "potential_energy",
            "oracle_window", "oracle_window_grads", "obs_fn", "reward_fn", "mlp_forward"]

@@ -24,6 +24,14 @@ Conventions (the readings of the paper's Sec. 3.1 that the whole project uses):
   branch, ties included), else -mu |f_n| v_t / |v_t|.
 * Joint limits (Sec. 3.1, limit equation): k_lim (lo - q) if q < lo, k_lim (hi - q)
   if q > hi, else 0.
+* Muscle-tendon units (Sec. 3.1, muscle actuation; the Hill-type reading of this
+  project): a polyline path through points fixed in body frames, length L and rate Ldot;
+  rigid tendon l_m = L - l_slack; force-length exp(-((l_m/l_opt - 1)/w)^2);
+  force-velocity 1 + Ldot/(v_max l_opt); F = max(0, F_max act f_l f_v), pulling every
+  path point towards its neighbours (purely contractive); at a raw tension of exactly 0
+  (zero activation, the initial state) the derivative is that of the active branch, the
+  side a non-negative activation lies on; the activation follows
+  act' = act + dt (u - act)/tau with the excitation u, explicit per substep.
 """
 import torch
 
@@ -126,6 +134,20 @@ class OracleModel:
         self.dt = float(md["dt"])
         self.substeps = int(md["substeps"])
         self.bodies = [j for j in range(self.J) if float(md["mass"][j]) > 0.0]
+        self.n_mtu = int(md.get("n_mtu", 0))
+        self.n_motor = int(md.get("n_motor", self.na))
+        if self.n_mtu:
+            self.mtu_npt = [int(x) for x in md["mtu_npt"]]
+            self.mtu_body = torch.as_tensor(md["mtu_body"], dtype=torch.long)
+            self.mtu_pos = _t(md["mtu_pos"])
+            self.mtu_fmax = _t(md["mtu_fmax"])
+            self.mtu_lopt = _t(md["mtu_lopt"])
+            self.mtu_lslack = _t(md["mtu_lslack"])
+            self.tau_act = float(md["tau_act"])
+            self.fl_width = float(md["fl_width"])
+            self.vmax = float(md["vmax"])
+            P = self.mtu_pos.shape[1]
+            self.mtu_valid = torch.tensor([[k < n for k in range(P)] for n in self.mtu_npt])
 
     def ndof(self, j):
         return 6 if self.jtype[j] == FREE else 1
@@ -244,11 +266,50 @@ def dynamics_terms(m, q, qd):
     return out
 
 
+def muscle_terms(m, T, qd, act):
+    """Generalized forces of the muscle-tendon units at activation ``act`` [B, n_mtu],
+    with the path lengths, rates and tensions (point Jacobians as for the contacts)."""
+    B = qd.shape[0]
+    Rall = torch.stack(T["R"], 1)                                     # [B,J,3,3]
+    pall = torch.stack(T["p"], 1)
+    Jall = torch.stack(T["Jb"], 1)                                    # [B,J,6,nv]
+    bi = m.mtu_body                                                   # [n,P]
+    x = pall[:, bi] + (Rall[:, bi] @ m.mtu_pos[None, :, :, :, None])[..., 0]      # [B,n,P,3]
+    Jp = Jall[:, bi]                                                  # [B,n,P,6,nv]
+    Jpt = Jp[..., 3:, :] - skew(x) @ Jp[..., :3, :]                   # point Jacobians
+    v = (Jpt @ qd[:, None, None, :, None])[..., 0]                    # [B,n,P,3]
+    seg_ok = (m.mtu_valid[:, 1:] & m.mtu_valid[:, :-1]).to(F64)       # [n,P-1]
+    # segments past a path's last point get a unit dummy vector (masked out below), so
+    # that no square root is taken at zero length
+    dummy = torch.tensor([1.0, 0.0, 0.0], dtype=F64)
+    d = (x[:, :, 1:] - x[:, :, :-1]) * seg_ok[..., None] + (1.0 - seg_ok)[..., None] * dummy
+    ell = torch.sqrt((d * d).sum(-1))
+    u = d / ell[..., None] * seg_ok[..., None]                        # unit segment vectors
+    L = (ell * seg_ok).sum(-1)                                         # [B,n]
+    Ldot = (u * (v[:, :, 1:] - v[:, :, :-1])).sum(-1).sum(-1)
+    lm = L - m.mtu_lslack
+    fl = torch.exp(-(((lm / m.mtu_lopt) - 1.0) / m.fl_width) ** 2)
+    fv = 1.0 + Ldot / (m.vmax * m.mtu_lopt)
+    F = torch.clamp(m.mtu_fmax * act * fl * fv, min=0.0)
+    # point forces F (u_k - u_{k-1}), u_{-1} = u_last = 0 (masked)
+    z = torch.zeros_like(u[:, :, :1])
+    uf = torch.cat([u, z], 2)
+    ub = torch.cat([z, u], 2)
+    fpt = F[..., None, None] * (uf - ub)                               # [B,n,P,3]
+    tau = (Jpt.transpose(-1, -2) @ fpt[..., None])[..., 0].sum((1, 2))
+    return dict(tau=tau, L=L, Ldot=Ldot, F=F, x=x, fpt=fpt)
+
+
+def activation_step(m, act, u, dt):
+    """First-order activation lag, explicit over one substep."""
+    return act + dt * (u - act) / m.tau_act
+
+
 def joint_torques(m, q, a):
     """Actuation gear * a plus the joint-limit penalty, in velocity coordinates."""
     B = q.shape[0]
     cols = [torch.zeros(B, dtype=F64) for _ in range(m.nv)]
-    for i, j in enumerate(m.act_joint):
+    for i, j in enumerate(m.act_joint):                 # motors are the first actions
         cols[m.vadr[j]] = cols[m.vadr[j]] + m.gear[i] * a[:, i]
     for j in range(m.J):
         if m.limited[j] and m.jtype[j] != FREE:
@@ -273,13 +334,19 @@ def integrate(m, q, qd_new, dt):
     return torch.cat(parts, 1)
 
 
-def substep(m, q, qd, a, dt):
-    """One semi-implicit Euler substep of M qdd = J^T f + c + tau (Sec. 3.1)."""
+def substep(m, q, qd, a, dt, act=None):
+    """One semi-implicit Euler substep of M qdd = J^T f + c + tau (Sec. 3.1).  Muscle
+    models also take the activations ``act`` and return the updated ones."""
     T = dynamics_terms(m, q, qd)
     tau = joint_torques(m, q, a) + T["tau_contact"] - T["bias"]
+    if m.n_mtu:
+        tau = tau + muscle_terms(m, T, qd, act)["tau"]
     L = torch.linalg.cholesky(T["M"])
     qdd = torch.cholesky_solve(tau[..., None], L)[..., 0]
     qd_new = qd + dt * qdd
+    if m.n_mtu:
+        act_new = activation_step(m, act, a[:, m.n_motor:], dt)
+        return integrate(m, q, qd_new, dt), qd_new, act_new
     return integrate(m, q, qd_new, dt), qd_new
 
 

@@ -22,6 +22,29 @@ def _t(x):
     return torch.as_tensor(np.asarray(x), dtype=F64)
 
 
+def bf16_round(x):
+    """Round float64 values to the nearest bfloat16 the way an FP32 pipeline does: to
+    float32 (round to nearest even), then the float32 bit pattern to its top 16 bits
+    with round to nearest even (IEEE 754 bfloat16, finite values)."""
+    f = x.to(torch.float32).contiguous()
+    bits = f.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    lsb = (bits >> 16) & 1
+    r = ((bits + 0x7FFF + lsb) >> 16) << 16
+    r = torch.where(r >= 2 ** 31, r - 2 ** 32, r).to(torch.int32)
+    return r.view(torch.float32).to(F64)
+
+
+def mlp_forward_bf16(layers, x):
+    """The MLP with BF16 weights and BF16 layer inputs and exact (float64) accumulation
+    of their products: the reference of the BF16 matrix-core MLPs."""
+    h = x
+    for i, (W, b) in enumerate(layers):
+        h = bf16_round(h) @ bf16_round(W).T + b
+        if i < len(layers) - 1:
+            h = torch.nn.functional.elu(h)
+    return h
+
+
 def mlp_forward(layers, x):
     """ELU hidden layers, linear output (App. A.2 network description, LayerNorm off)."""
     h = x
@@ -38,6 +61,8 @@ def obs_fn(m, s):
     task = m.md["task"]
     nq, nv = m.nq, m.nv
     q, qd = s[:, :nq], s[:, nq:nq + nv]
+    if task == "none":
+        return s                              # no task: the state itself
     if task == "cartpole":
         x, th, xd, thd = q[:, 0], q[:, 1], qd[:, 0], qd[:, 1]
         return torch.stack([x, xd, torch.sin(th), torch.cos(th), thd], 1)
@@ -47,7 +72,12 @@ def obs_fn(m, s):
     parts = [q[:, 2:3], q[:, 3:7], qd[:, 0:3], qd[:, 3:6], q[:, 7:], qd[:, 6:],
              up[:, None], heading[:, None]]
     if m.md["has_last_action"]:
-        parts.append(s[:, nq + nv:])
+        parts.append(s[:, nq + nv:nq + nv + m.na])
+    if task == "mtu":
+        # skeleton observation, zero padding to 128 entries, then the activations
+        sk = torch.cat(parts, 1)
+        pad = torch.zeros(s.shape[0], 128 - sk.shape[1], dtype=F64)
+        return torch.cat([sk, pad, s[:, nq + nv:nq + nv + m.n_mtu]], 1)
     return torch.cat(parts, 1)
 
 
@@ -56,6 +86,8 @@ def reward_fn(m, s, a):
     task = m.md["task"]
     nq, nv = m.nq, m.nv
     q, qd = s[:, :nq], s[:, nq:nq + nv]
+    if task == "none":
+        return torch.zeros(s.shape[0], dtype=F64)
     if task == "cartpole":
         th = torch.atan2(torch.sin(q[:, 1]), torch.cos(q[:, 1]))
         return -th ** 2 - 0.1 * qd[:, 1] ** 2 - 0.05 * q[:, 0] ** 2 - 0.1 * qd[:, 0] ** 2
@@ -67,7 +99,19 @@ def reward_fn(m, s, a):
         dh = torch.clamp(hgt - 0.84, -1.0, 0.1)
         rh = torch.where(dh < 0, -200.0 * dh * dh, 10.0 * dh)
         return vx + 0.1 * up + heading + rh - 0.002 * (a * a).sum(1)
+    if task == "mtu":
+        # App. A.3 muscle-task reward, at the humanoid skeleton's torso height reference
+        dh = torch.clamp(hgt - 0.84, -1.0, 0.05)
+        rh = torch.where(dh < 0, -200.0 * dh * dh, 4.0 * dh)
+        return vx + 0.1 * up + heading + rh - 0.001 * (a * a).sum(1)
     raise ValueError(task)
+
+
+def squash(m, y):
+    """Policy output to action: tanh for torques, (tanh + 1)/2 for muscle excitations."""
+    if m.md["task"] == "mtu":
+        return 0.5 * (torch.tanh(y) + 1.0)
+    return torch.tanh(y)
 
 
 def _layers(params):
@@ -75,13 +119,14 @@ def _layers(params):
 
 
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
-                  keep_graph=False, layers=None, action_offset=None):
+                  keep_graph=False, layers=None, action_offset=None, bf16=False):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
     n_total: the N of the 1/(N h) loss scale (defaults to B).
     action_offset: optional [h, B, na] added to each action (used by finite-difference
     checks of dL/da_t).
+    bf16: evaluate actor and critic with BF16 weights and layer inputs (mlp_forward_bf16).
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
     s = s0 if torch.is_tensor(s0) else _t(s0)
@@ -93,11 +138,12 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     act_l, crit_l = layers
     nq, nv = m.nq, m.nv
     dt = m.dt / m.substeps
+    mlp = mlp_forward_bf16 if bf16 else mlp_forward
     states, obs, acts, rews = [s], [], [], []
     for t in range(h):
         o = obs_fn(m, s)
         if actions is None:
-            a = torch.tanh(mlp_forward(act_l, o))
+            a = squash(m, mlp(act_l, o))
         else:
             a = actions[t] if torch.is_tensor(actions[t]) else _t(actions[t])
         if action_offset is not None:
@@ -106,16 +152,22 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
             a.requires_grad_(True)
         r = reward_fn(m, s, a)
         q, qd = s[:, :nq], s[:, nq:nq + nv]
-        for _ in range(m.substeps):
-            q, qd = substep(m, q, qd, a, dt)
-        s = torch.cat([q, qd, a], 1) if m.md["has_last_action"] else torch.cat([q, qd], 1)
+        if m.n_mtu:
+            act = s[:, nq + nv:nq + nv + m.n_mtu]
+            for _ in range(m.substeps):
+                q, qd, act = substep(m, q, qd, a, dt, act)
+            s = torch.cat([q, qd, act], 1)
+        else:
+            for _ in range(m.substeps):
+                q, qd = substep(m, q, qd, a, dt)
+            s = torch.cat([q, qd, a], 1) if m.md["has_last_action"] else torch.cat([q, qd], 1)
         states.append(s)
         obs.append(o)
         acts.append(a)
         rews.append(r)
     o_h = obs_fn(m, s)
     obs.append(o_h)
-    value = mlp_forward(crit_l, o_h)[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
+    value = mlp(crit_l, o_h)[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
     disc = sum(gamma ** t * rews[t] for t in range(h))
     loss = -(disc + gamma ** h * value).sum() / (N * h)
     return dict(states=states, obs=obs, actions=acts, rewards=rews, value=value, loss=loss,
@@ -123,7 +175,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
-                        n_total=None, want_theta=False):
+                        n_total=None, want_theta=False, bf16=False):
     """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
 
     Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
@@ -140,7 +192,7 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
     if actions is not None:
         act_in = [_t(actions[t]).clone().requires_grad_(True) for t in range(h)]
     out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
-                        layers=layers)
+                        layers=layers, bf16=bf16)
     wrt = [s0t] + list(out["actions"])
     theta = []
     if want_theta and actor is not None:

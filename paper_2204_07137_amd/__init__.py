@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libshacsim.so")
 MAXL = 4
 PATH_PERSISTENT, PATH_PLAIN, PATH_TAPE = 0, 1, 2
 PREC = {"fp32": 0, "fp64": 1}
-TASKS = {"none": 0, "cartpole": 1, "ant": 2, "humanoid": 3}
+TASKS = {"none": 0, "cartpole": 1, "ant": 2, "humanoid": 3, "mtu": 4}
 STATUS = {0: "SIM_OK", -1: "SIM_E_ARG", -2: "SIM_E_HANDLE", -3: "SIM_E_HIP", -4: "SIM_E_MODEL",
           -5: "SIM_E_WORKSPACE", -6: "SIM_E_UNSUPPORTED"}
 
@@ -32,7 +32,9 @@ class SimModelDesc(ctypes.Structure):
                 ("n_contacts", _i), ("contact_body", _p), ("contact_pos", _p),
                 ("contact_radius", _p), ("gravity", _d), ("kn", _d), ("kd", _d), ("kt", _d),
                 ("mu", _d), ("klim", _d), ("dt", _d), ("substeps", _i), ("task", _i),
-                ("has_last_action", _i)]
+                ("has_last_action", _i), ("n_mtu", _i), ("mtu_npt", _p), ("mtu_body", _p),
+                ("mtu_pos", _p), ("mtu_fmax", _p), ("mtu_lopt", _p), ("mtu_lslack", _p),
+                ("tau_act", _d), ("fl_width", _d), ("vmax", _d)]
 
 
 class SimOptions(ctypes.Structure):
@@ -146,7 +148,7 @@ def model_desc(md):
     d.limited = ptr("limited", md["limited"], np.int32)
     d.lower = ptr("lower", md["lower"], np.float64)
     d.upper = ptr("upper", md["upper"], np.float64)
-    d.n_act = int(md["na"])
+    d.n_act = int(md.get("n_motor", md["na"]))
     d.act_joint = ptr("act_joint", md["act_joint"], np.int32)
     d.gear = ptr("gear", md["gear"], np.float64)
     d.armature = ptr("armature", md["armature"], np.float64)
@@ -159,6 +161,17 @@ def model_desc(md):
     d.substeps = int(md["substeps"])
     d.task = TASKS[md["task"]]
     d.has_last_action = int(md["has_last_action"])
+    d.n_mtu = int(md.get("n_mtu", 0))
+    if d.n_mtu:
+        d.mtu_npt = ptr("mtu_npt", md["mtu_npt"], np.int32)
+        d.mtu_body = ptr("mtu_body", md["mtu_body"], np.int32)
+        d.mtu_pos = ptr("mtu_pos", md["mtu_pos"], np.float64)
+        d.mtu_fmax = ptr("mtu_fmax", md["mtu_fmax"], np.float64)
+        d.mtu_lopt = ptr("mtu_lopt", md["mtu_lopt"], np.float64)
+        d.mtu_lslack = ptr("mtu_lslack", md["mtu_lslack"], np.float64)
+        d.tau_act = float(md["tau_act"])
+        d.fl_width = float(md["fl_width"])
+        d.vmax = float(md["vmax"])
     return d, keep
 
 

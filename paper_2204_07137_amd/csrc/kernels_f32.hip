@@ -4,6 +4,8 @@
 #include "sim_types.h"
 
 // DOF counts compiled as kernels of their own (CartPole, Ant, Humanoid)
+// DOF counts of muscle-driven models with a kernel of their own (the humanoid skeleton)
+#define SIM_NV_LIST_MTU(X) X(27)
 #define SIM_NV_LIST(X) X(2) X(14) X(27)
 
 namespace sim_f32 {

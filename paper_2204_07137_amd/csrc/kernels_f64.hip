@@ -4,6 +4,8 @@
 #include "sim_types.h"
 
 // FP64 path: every model runs the padded 32-DOF kernel
+// DOF counts of muscle-driven models with a kernel of their own (the humanoid skeleton)
+#define SIM_NV_LIST_MTU(X)
 #define SIM_NV_LIST(X)
 
 namespace sim_f64 {

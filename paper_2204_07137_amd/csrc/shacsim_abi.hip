@@ -70,6 +70,13 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   for (int j = 0; j < SIM_MAXJ; ++j) d.cmask[j] = s.cmask[j];
   d.npair = s.npair;
   for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
+  d.tau_act = (T)s.tau_act; d.fl_w = (T)s.fl_w; d.vmax = (T)s.vmax;
+  for (int i = 0; i < SIM_MAXMTU; ++i) {
+    d.mtu_npt[i] = s.mtu_npt[i];
+    d.mtu_fmax[i] = (T)s.mtu_fmax[i]; d.mtu_lopt[i] = (T)s.mtu_lopt[i]; d.mtu_lslack[i] = (T)s.mtu_lslack[i];
+  }
+  for (int i = 0; i < SIM_MAXMPT * SIM_MAXMTU; ++i) d.mtu_body[i] = s.mtu_body[i];
+  for (int i = 0; i < SIM_MAXMPT * 3 * SIM_MAXMTU; ++i) d.mtu_pos[i] = (T)s.mtu_pos[i];
   for (int c = 0; c < SIM_MAXC; ++c) {
     d.cbody[c] = s.cbody[c];
     d.crad[c] = (T)s.crad[c];
@@ -80,7 +87,8 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
 static int obs_dim_for(const DevModelT<double>& m) {
   if (m.task == TASK_CARTPOLE) return 5;
   if (m.task == TASK_ANT || m.task == TASK_HUMANOID) return 13 + 2 * (m.nq - 7) + (m.has_last_action ? m.na : 0);
-  return 0;
+  if (m.task == TASK_MTU) return 128 + m.n_mtu;
+  return m.ns;   // no task: the observation is the state
 }
 
 static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
@@ -155,22 +163,52 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
     m.crad[c] = md->contact_radius[c];
   }
   if (md->substeps < 1 || !(md->dt > 0)) return fail(SIM_E_MODEL, "substeps >= 1 and dt > 0 required");
-  m.J = J; m.nq = nq; m.nv = nv; m.na = md->n_act; m.nc = md->n_contacts;
+  if (md->n_mtu < 0 || md->n_mtu > SIM_MAXMTU) return fail(SIM_E_MODEL, "n_mtu out of range [0, 160]");
+  if (md->n_mtu > 0) {
+    if (!md->mtu_npt || !md->mtu_body || !md->mtu_pos || !md->mtu_fmax || !md->mtu_lopt || !md->mtu_lslack)
+      return fail(SIM_E_ARG, "null muscle arrays");
+    if (!(md->tau_act > 0) || !(md->fl_width > 0) || !(md->vmax > 0))
+      return fail(SIM_E_MODEL, "tau_act, fl_width and vmax must be > 0");
+    if (md->n_act + md->n_mtu > SIM_MAXAM) return fail(SIM_E_MODEL, "n_act + n_mtu above 160");
+    if (md->has_last_action) return fail(SIM_E_UNSUPPORTED, "muscle models carry activations, not the last action");
+    for (int i = 0; i < md->n_mtu; ++i) {
+      const int np = md->mtu_npt[i];
+      if (np < 2 || np > SIM_MAXMPT) return fail(SIM_E_MODEL, "a muscle path has 2..6 points");
+      if (!(md->mtu_fmax[i] >= 0) || !(md->mtu_lopt[i] > 0) || !(md->mtu_lslack[i] >= 0))
+        return fail(SIM_E_MODEL, "muscle F_max >= 0, l_opt > 0, l_slack >= 0 required");
+      m.mtu_npt[i] = np;
+      m.mtu_fmax[i] = md->mtu_fmax[i]; m.mtu_lopt[i] = md->mtu_lopt[i]; m.mtu_lslack[i] = md->mtu_lslack[i];
+      for (int k = 0; k < SIM_MAXMPT; ++k) {
+        int b = (k < np) ? md->mtu_body[i * SIM_MAXMPT + k] : 0;
+        if (b < 0 || b >= J) return fail(SIM_E_MODEL, "muscle point body out of range");
+        m.mtu_body[k * SIM_MAXMTU + i] = b;
+        for (int c = 0; c < 3; ++c)
+          m.mtu_pos[(k * 3 + c) * SIM_MAXMTU + i] = (k < np) ? md->mtu_pos[(i * SIM_MAXMPT + k) * 3 + c] : 0.0;
+      }
+    }
+    m.tau_act = md->tau_act; m.fl_w = md->fl_width; m.vmax = md->vmax;
+  }
+  if (md->task == TASK_MTU && md->n_mtu < 1) return fail(SIM_E_MODEL, "the muscle task needs muscles");
+  m.J = J; m.nq = nq; m.nv = nv; m.na = md->n_act + md->n_mtu; m.nc = md->n_contacts;
+  m.n_mtu = md->n_mtu; m.n_motor = md->n_act; m.nck = nq + nv + md->n_mtu;
   m.task = md->task; m.floating = (m.jtype[0] == J_FREE) ? 1 : 0;
   m.has_last_action = md->has_last_action ? 1 : 0;
   m.substeps = md->substeps; m.max_depth = maxd;
   m.dt_sub = md->dt / md->substeps;
   m.g = md->gravity; m.kn = md->kn; m.kd = md->kd; m.kt = md->kt; m.mu = md->mu; m.klim = md->klim;
-  m.ns = nq + nv + (m.has_last_action ? m.na : 0);
+  m.ns = nq + nv + (m.has_last_action ? m.na : 0) + m.n_mtu;
   if (m.task == TASK_ANT || m.task == TASK_HUMANOID) {
     if (!m.floating) return fail(SIM_E_MODEL, "locomotion tasks need a FREE root");
+  } else if (m.task == TASK_MTU) {
+    if (!m.floating) return fail(SIM_E_MODEL, "locomotion tasks need a FREE root");
+    if (13 + 2 * (nq - 7) > 128) return fail(SIM_E_MODEL, "muscle task: skeleton observation wider than 128");
   } else if (m.task == TASK_CARTPOLE) {
     if (nq != 2 || nv != 2) return fail(SIM_E_MODEL, "cartpole task needs a 2-DOF model");
   } else if (m.task != TASK_NONE) {
     return fail(SIM_E_MODEL, "unknown task");
   }
   m.od = obs_dim_for(m);
-  if (m.od > SIM_MAXOBS) return fail(SIM_E_MODEL, "observation wider than 128");
+  if (m.od > SIM_MAXOBS) return fail(SIM_E_MODEL, "observation wider than 288");
   m.npair = 0;
   for (int i = 0; i < J; ++i) {
     if (m.jtype[i] == J_FREE) continue;
@@ -210,6 +248,8 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
     return fail(SIM_E_UNSUPPORTED, "at most two hidden layers per MLP");
   if (opt->policy_grad != 0 && opt->policy_grad != 1) return fail(SIM_E_ARG, "policy_grad must be 0 or 1");
   if (opt->policy_grad && !opt->closed_loop) return fail(SIM_E_ARG, "policy_grad needs the closed-loop policy");
+  if (m.n_mtu > 0 && opt->path == SIM_PATH_PLAIN)
+    return fail(SIM_E_UNSUPPORTED, "muscle models run on the persistent and tape paths");
   return SIM_OK;
 }
 
@@ -258,7 +298,7 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
     h->wp_critic_off[l] = off;
     off = align256(off + e * no * pad64(ni));
   }
-  const size_t N = opt->n_envs, nqv = m.nq + m.nv;
+  const size_t N = opt->n_envs, nqv = m.nck;
   h->n_ckpt = (opt->path == SIM_PATH_TAPE) ? 0
               : (opt->path == SIM_PATH_PLAIN) ? opt->horizon * m.substeps + 1
                                              : opt->horizon * m.substeps / opt->ckpt_interval;
@@ -271,7 +311,7 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   const size_t tape_entries = (opt->path == SIM_PATH_TAPE) ? (size_t)opt->horizon * m.substeps * N
                               : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
   h->off_tape = off;
-  off = align256(off + tape_entries * sim_tape_bytes(e));
+  off = align256(off + tape_entries * sim_tape_bytes(e, m.n_mtu > 0));
   for (int l = 0; l < SIM_MAXL; ++l) h->off_th_h[l] = 0;
   if (opt->policy_grad) {
     const size_t rows = N * (size_t)opt->horizon;
@@ -461,16 +501,25 @@ static int do_prep(const WinArgsT<double>& A, void* s) {
   int bad = A.closed_loop ? launch_transposes(A.actor, s) : 0;
   return bad | launch_transposes(A.critic, s);
 }
-static int do_window(const WinArgsT<float>& A, int adjoint, int plain, int S, int nv, void* s) {
-  return adjoint ? sim_f32::launch_adjoint(A, plain, S, nv, s) : sim_f32::launch_forward(A, plain, S, nv, s);
+static int do_window(const WinArgsT<float>& A, int adjoint, int plain, int S, int nv, int mtu, void* s) {
+  return adjoint ? sim_f32::launch_adjoint(A, plain, S, nv, mtu, s) : sim_f32::launch_forward(A, plain, S, nv, mtu, s);
 }
-static int do_window(const WinArgsT<double>& A, int adjoint, int plain, int S, int nv, void* s) {
-  return adjoint ? sim_f64::launch_adjoint(A, plain, S, nv, s) : sim_f64::launch_forward(A, plain, S, nv, s);
+static int do_window(const WinArgsT<double>& A, int adjoint, int plain, int S, int nv, int mtu, void* s) {
+  return adjoint ? sim_f64::launch_adjoint(A, plain, S, nv, mtu, s) : sim_f64::launch_forward(A, plain, S, nv, mtu, s);
 }
 static int do_theta(const ThetaArgsT<float>& P, void* s) { return sim_f32::launch_theta(P, s); }
 static int do_theta(const ThetaArgsT<double>& P, void* s) { return sim_f64::launch_theta(P, s); }
-static int do_group(const GroupArgsT<float>& G, int adjoint, void* s) { return sim_f32::launch_group(G, adjoint, s); }
-static int do_group(const GroupArgsT<double>& G, int adjoint, void* s) { return sim_f64::launch_group(G, adjoint, s); }
+static int group_has_mtu(const int* mtu, int n) {
+  for (int i = 0; i < n; ++i)
+    if (mtu[i]) return 1;
+  return 0;
+}
+static int do_group(const GroupArgsT<float>& G, int adjoint, void* s) {
+  return sim_f32::launch_group(G, adjoint, group_has_mtu(G.mtu, G.n), s);
+}
+static int do_group(const GroupArgsT<double>& G, int adjoint, void* s) {
+  return sim_f64::launch_group(G, adjoint, group_has_mtu(G.mtu, G.n), s);
+}
 
 static int launch_failed() {
   return fail(SIM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
@@ -482,7 +531,7 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   int rc = build_forward_args<T>(h, io, A);
   if (rc) return rc;
   int bad = do_prep(A, stream);
-  bad |= do_window(A, 0, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, stream);
+  bad |= do_window(A, 0, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, h->m64.n_mtu > 0, stream);
   return bad ? launch_failed() : SIM_OK;
 }
 
@@ -491,7 +540,8 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   WinArgsT<T> A;
   int rc = build_adjoint_args<T>(h, io, A);
   if (rc) return rc;
-  if (do_window(A, 1, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, stream)) return launch_failed();
+  if (do_window(A, 1, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, h->m64.n_mtu > 0, stream))
+    return launch_failed();
   if (io->dL_dtheta) {
     ThetaArgsT<T> P;
     build_theta_args<T>(h, io, P);
@@ -671,6 +721,7 @@ static int run_group_forward(SimGroup* g, const SimForwardIO* ios, void* stream)
     if (rc) return rc;
     G.start[s] = start;
     G.nv[s] = h->nv;
+    G.mtu[s] = h->m64.n_mtu > 0;
     start += h->opt.n_envs;
   }
   G.start[g->n] = start;
@@ -698,6 +749,7 @@ static int run_group_adjoint(SimGroup* g, const SimAdjointIO* ios, void* stream)
     if (rc) return rc;
     G.start[s] = start;
     G.nv[s] = h->nv;
+    G.mtu[s] = h->m64.n_mtu > 0;
     start += h->opt.n_envs;
     has_theta[s] = ios[mi].dL_dtheta != nullptr;
     if (has_theta[s]) {

@@ -30,13 +30,23 @@ struct ContactRegs {
   real rad;
 };
 
-constexpr int kTapeBytes = (SIM_TAPE_REALS * (int)sizeof(real) + 1023) / 1024 * 1024;
-constexpr int kTapePad = (kTapeBytes - SIM_TAPE_REALS * (int)sizeof(real)) / (int)sizeof(real);
-constexpr int kTapeReals = kTapeBytes / (int)sizeof(real);   // stride of one tape entry
-
-struct EnvLDS {
+// Per-environment LDS of one wavefront.  MAXA: action capacity; NMTU: muscle capacity
+// (0 for torque-driven models, whose layout then carries no muscle fields).
+template <int MAXA, int NMTU>
+struct EnvLDST {
+  static constexpr int kMtu = NMTU;
+  static constexpr int kMaxA = MAXA;
+  // reals of the tape entry: the block below up to and including tfb, plus the frame
+  // transforms and activations for muscle models
+  static constexpr int kTapeUsed = SIM_TAPE_REALS + (NMTU > 0 ? 12 * SIM_MAXJ + NMTU : 0);
+  static constexpr int kTapeBytes = (kTapeUsed * (int)sizeof(real) + 1023) / 1024 * 1024;
+  static constexpr int kTapeReals = kTapeBytes / (int)sizeof(real);   // stride of one tape entry
+  static constexpr int kBlockReals = SIM_TAPE_REALS + 12 * SIM_MAXJ + NMTU;
+  static constexpr int kPad = kTapeReals > kBlockReals ? kTapeReals - kBlockReals : 0;
   // The linearisation of the current substep, one contiguous 1 KB-padded block so that it
   // moves to and from HBM as whole 64-lane x 16-byte transfers (the linearisation tape).
+  // For torque-driven models the entry ends inside R (R and p are then rebuilt by any
+  // recomputation and never read by the adjoint).
   struct __attribute__((aligned(16))) {
     real q[SIM_MAXQ], qd[SIM_MAXV];   // state before the substep
     real S[SIM_MAXJ][6], v[SIM_MAXJ][6], ab[SIM_MAXJ][6], Ib[SIM_MAXJ][10];
@@ -44,11 +54,14 @@ struct EnvLDS {
     real qdd[SIM_MAXV], qdn[SIM_MAXV];
     real M[SIM_MAXV][SIM_MAXV + 1];    // mass matrix, then the Cholesky rows
     real tdinv[SIM_MAXV], tfb[SIM_MAXV];
-    real tpad[kTapePad];
+    real R[SIM_MAXJ][9], p[SIM_MAXJ][3];
+    real act[NMTU];                    // muscle activations before the substep
+    real tpad[kPad];
   };
-  real a[SIM_MAXA];
+  real a[MAXA];
   real qn[SIM_MAXQ];
-  real R[SIM_MAXJ][9], p[SIM_MAXJ][3];
+  real actn[NMTU];                     // activations after the substep
+  real act_bar[NMTU];
   real F[SIM_MAXJ][6], Fi[SIM_MAXJ][6];
   real Ic[SIM_MAXJ][10];
   real vec[SIM_MAXV];
@@ -57,7 +70,7 @@ struct EnvLDS {
   real W[SIM_MAXJ][6], A[SIM_MAXJ][6];
   real acc[SIM_MAXJ][42];
   real cAb[SIM_MAXC][6], cVb[SIM_MAXC][6];
-  real qb[SIM_MAXQ], qdb[SIM_MAXV], abar[SIM_MAXA];
+  real qb[SIM_MAXQ], qdb[SIM_MAXV], abar[MAXA];
   real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
   // topology copies for arbitrary-index lookups
   int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ];
@@ -71,11 +84,17 @@ struct EnvLDS {
       real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
     };
     double M64[SIM_MAXV][SIM_MAXV];   // FP64 refactorisation (never live at the same time as the MLP)
+    struct {                          // per-body muscle wrenches and their adjoint terms (substep-local)
+      real Fm[SIM_MAXJ][6], mAb[SIM_MAXJ][6], mVb[SIM_MAXJ][6];
+    };
   };
   real red[4];
 };
+typedef EnvLDST<SIM_MAXA, 0> EnvLDS;             // torque-driven models
+typedef EnvLDST<SIM_MAXAM, SIM_MAXMTU> EnvLDSM;  // muscle-driven models
 
-__device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, EnvLDS& E, int ln,
+template <class L>
+__device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, int ln,
                                           JointRegs& jr, ContactRegs& cr) {
   int j = ln < m->J ? ln : 0;
   jr.par = m->parent[j]; jr.type = m->jtype[j]; jr.qa = m->qadr[j]; jr.va = m->vadr[j];
@@ -243,8 +262,8 @@ __device__ __forceinline__ real chol_solve(const Chol& C, int ln, real b) {
 // When the FP32 factorisation meets a pivot below chol_thr times the largest diagonal (or
 // a non-finite pivot), the environment's mass matrix is refactorised in double precision
 // in LDS (lane = row) and both solves of the substep use that factor.
-template <int NV>
-__device__ __forceinline__ void chol64_factor(EnvLDS& E, int nv, int ln) {
+template <int NV, class L>
+__device__ __forceinline__ void chol64_factor(L& E, int nv, int ln) {
   if (ln < NV) {
 #pragma unroll 1
     for (int k = 0; k < NV; ++k)
@@ -267,8 +286,8 @@ __device__ __forceinline__ void chol64_factor(EnvLDS& E, int nv, int ln) {
   }
 }
 
-template <int NV>
-__device__ __forceinline__ double chol64_solve(EnvLDS& E, int ln, double b) {
+template <int NV, class L>
+__device__ __forceinline__ double chol64_solve(L& E, int ln, double b) {
   double y = b;
 #pragma unroll 1
   for (int k = 0; k < NV; ++k) {
@@ -300,8 +319,168 @@ __device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active
 // --------------------------------------------------------------- forward substep
 // Uses E.q, E.qd, E.a.  Writes all intermediates to E and the new state to E.qn/E.qdn
 // (and back to E.q/E.qd when inplace).  Lrow/Lcol keep the Cholesky factor.
-template <int NV>
-__device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvLDS& E,
+// --------------------------------------------------------------- muscle-tendon units
+// Unit i's path: points x_k (relative to O) fixed in body frames, segments u_k (unit) of
+// length l_k, L = sum l_k, Ldot = sum u_k . (v_{k+1} - v_k).  Rigid tendon l_m = L - l_slack;
+// tension F = max(0, F_max act f_l f_v) with f_l = exp(-((l_m/l_opt - 1)/w)^2) and
+// f_v = 1 + Ldot/(v_max l_opt); point k receives F (u_k - u_{k-1}) (u_{-1} = u_{n-1} = 0).
+struct MtuPath {
+  f3 x[SIM_MAXMPT], v[SIM_MAXMPT], u[SIM_MAXMPT - 1];
+  real il[SIM_MAXMPT - 1];   // 1 / segment length
+  int b[SIM_MAXMPT];
+  int np;
+  real F, Fr, fl, fv, lt, L, Ld;
+};
+
+template <class L>
+__device__ __forceinline__ void mtu_path(const Scal* __restrict__ m, const L& E, int i, MtuPath& P,
+                                         real act) {
+  const DevModel* __restrict__ T = m->tab;
+  P.np = T->mtu_npt[i];
+#pragma unroll
+  for (int k = 0; k < SIM_MAXMPT; ++k) {
+    const int kk = k < P.np ? k : P.np - 1;     // points past the end repeat the last one
+    const int b = T->mtu_body[kk * SIM_MAXMTU + i];
+    f3 r = mk3(T->mtu_pos[(kk * 3 + 0) * SIM_MAXMTU + i], T->mtu_pos[(kk * 3 + 1) * SIM_MAXMTU + i],
+               T->mtu_pos[(kk * 3 + 2) * SIM_MAXMTU + i]);
+    P.b[k] = b;
+    P.x[k] = add3(ld3(E.p[b]), mv3(E.R[b], r));
+    P.v[k] = ptv(ldsv(E.v[b]), P.x[k]);
+  }
+  real Lp = RL(0.0), Ld = RL(0.0);
+#pragma unroll
+  for (int k = 0; k < SIM_MAXMPT - 1; ++k) {
+    if (k + 1 < P.np) {
+      f3 d = sub3(P.x[k + 1], P.x[k]);
+      real l = m_sqrt(dot3(d, d));
+      real il = RL(1.0) / l;
+      P.u[k] = scl3(d, il);
+      P.il[k] = il;
+      Lp += l;
+      Ld += dot3(P.u[k], sub3(P.v[k + 1], P.v[k]));
+    } else {
+      P.u[k] = mk3(RL(0.0), RL(0.0), RL(0.0));
+      P.il[k] = RL(0.0);
+    }
+  }
+  const real lopt = T->mtu_lopt[i];
+  P.L = Lp;
+  P.Ld = Ld;
+  P.lt = (Lp - T->mtu_lslack[i]) / lopt;
+  const real z = (P.lt - RL(1.0)) / m->fl_w;
+  P.fl = m_exp(-z * z);
+  P.fv = RL(1.0) + Ld / (m->vmax * lopt);
+  P.Fr = T->mtu_fmax[i] * act * P.fl * P.fv;
+  P.F = P.Fr > RL(0.0) ? P.Fr : RL(0.0);
+}
+
+__device__ __forceinline__ f3 mtu_udiff(const MtuPath& P, int k) {
+  f3 uf = (k < SIM_MAXMPT - 1) ? P.u[k] : mk3(RL(0.0), RL(0.0), RL(0.0));
+  f3 ub = (k > 0) ? P.u[k - 1] : mk3(RL(0.0), RL(0.0), RL(0.0));
+  return sub3(uf, ub);
+}
+
+__device__ __forceinline__ void lds_add6(real* dst, sv w) {
+  atomicAdd(dst + 0, w.a.x); atomicAdd(dst + 1, w.a.y); atomicAdd(dst + 2, w.a.z);
+  atomicAdd(dst + 3, w.l.x); atomicAdd(dst + 4, w.l.y); atomicAdd(dst + 5, w.l.z);
+}
+
+// Per-body wrench of all muscle tensions (about O) into E.Fm.  One lane per unit; the LDS
+// additions of one wavefront are ordered, so the sums are reproducible.
+template <class L>
+__device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E, int ln) {
+  for (int i = ln; i < SIM_MAXJ * 6; i += SIM_WAVE) (&E.Fm[0][0])[i] = RL(0.0);
+  __syncthreads();
+  for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
+    const int i = i0 + ln;
+    if (i < m->n_mtu) {
+      MtuPath P;
+      mtu_path(m, E, i, P, E.act[i]);
+#pragma unroll
+      for (int k = 0; k < SIM_MAXMPT; ++k) {
+        if (k < P.np) {
+          f3 f = scl3(mtu_udiff(P, k), P.F);
+          lds_add6(E.Fm[P.b[k]], spf(P.x[k], f));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Adjoint of the muscle forces in lambda^T ID = ... - sum_p nu_p . f_p (nu_p the virtual
+// velocity of point p under lambda): recomputes the tensions and E.Fm, adds to E.act_bar
+// the activation term, and collects per body the terms of the point-force adjoint that the
+// contacts use (E.mAb: Sp(x, xbar) + (-nu x f + v x vbar, 0); E.mVb: Sp(x, vbar)), where
+// xbar, vbar are the derivatives of F delta (delta = sum u_k . (nu_{k+1} - nu_k)) through
+// the tension and the segment directions.
+template <class L>
+__device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E, int ln) {
+  for (int i = ln; i < SIM_MAXJ * 6; i += SIM_WAVE) {
+    (&E.Fm[0][0])[i] = RL(0.0);
+    (&E.mAb[0][0])[i] = RL(0.0);
+    (&E.mVb[0][0])[i] = RL(0.0);
+  }
+  __syncthreads();
+  const DevModel* __restrict__ T = m->tab;
+  for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
+    const int i = i0 + ln;
+    if (i < m->n_mtu) {
+      const real act = E.act[i];
+      MtuPath P;
+      mtu_path(m, E, i, P, act);
+      f3 nu[SIM_MAXMPT];
+#pragma unroll
+      for (int k = 0; k < SIM_MAXMPT; ++k) nu[k] = ptv(ldsv(E.W[P.b[k]]), P.x[k]);
+      real delta = RL(0.0);
+#pragma unroll
+      for (int k = 0; k < SIM_MAXMPT - 1; ++k)
+        if (k + 1 < P.np) delta += dot3(P.u[k], sub3(nu[k + 1], nu[k]));
+      // at zero raw tension (e.g. zero activation) the derivative is the active branch's
+      const bool on = P.Fr >= RL(0.0);
+      const real lopt = T->mtu_lopt[i], fmax = T->mtu_fmax[i];
+      const real z = (P.lt - RL(1.0)) / m->fl_w;
+      const real dFdL = on ? fmax * act * P.fv * P.fl * (-RL(2.0) * z / m->fl_w) / lopt : RL(0.0);
+      const real dFdLd = on ? fmax * act * P.fl / (m->vmax * lopt) : RL(0.0);
+      const real dFda = on ? fmax * P.fl * P.fv : RL(0.0);
+      E.act_bar[i] -= delta * dFda;
+      const real cL = dFdL * delta, cV = dFdLd * delta;
+      f3 xb[SIM_MAXMPT];
+#pragma unroll
+      for (int k = 0; k < SIM_MAXMPT; ++k) xb[k] = scl3(mtu_udiff(P, k), -cL);
+#pragma unroll
+      for (int k = 0; k < SIM_MAXMPT - 1; ++k) {
+        if (k + 1 < P.np) {
+          // d(u_k . a)/dx_{k+1} = (a - u_k (u_k . a)) / l_k
+          f3 dv = sub3(P.v[k + 1], P.v[k]), dn = sub3(nu[k + 1], nu[k]);
+          f3 pv = sub3(dv, scl3(P.u[k], dot3(P.u[k], dv)));
+          f3 pn = sub3(dn, scl3(P.u[k], dot3(P.u[k], dn)));
+          f3 g = scl3(add3(scl3(pv, cV), scl3(pn, P.F)), P.il[k]);
+          xb[k + 1] = add3(xb[k + 1], g);
+          xb[k] = sub3(xb[k], g);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < SIM_MAXMPT; ++k) {
+        if (k < P.np) {
+          const f3 ud = mtu_udiff(P, k);
+          const f3 f = scl3(ud, P.F);
+          const f3 vb = scl3(ud, -cV);
+          const int b = P.b[k];
+          lds_add6(E.Fm[b], spf(P.x[k], f));
+          lds_add6(E.mAb[b], addsv(spf(P.x[k], xb[k]),
+                                   mksv(add3(scl3(cross3(nu[k], f), -RL(1.0)), cross3(P.v[k], vb)),
+                                        mk3(RL(0.0), RL(0.0), RL(0.0)))));
+          lds_add6(E.mVb[b], spf(P.x[k], vb));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int NV, class L>
+__device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln,
                                                 Chol& C, bool inplace, int& fb) {
   const int J = m->J, nv = m->nv, nc = m->nc;
@@ -410,6 +589,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
     E.cdep[ln] = d;
   }
   __syncthreads();
+  if constexpr (L::kMtu > 0) muscle_wrenches(m, E, ln);
   // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
   if (ln < J) {
     real mass = jr.mass;
@@ -445,6 +625,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
       int ci = __builtin_ctz(cm);
       f = subsv(f, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
     }
+    if constexpr (L::kMtu > 0) f = subsv(f, ldsv(E.Fm[ln]));
     stsv(E.F[ln], f);
     // joint torques: actuation + limit penalty
     if (jr.type != J_FREE) {
@@ -575,10 +756,17 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
       E.qn[jr.qa] = E.q[jr.qa] + dt * E.qdn[jr.va];
     }
   }
+  if constexpr (L::kMtu > 0) {
+    // activation lag, explicit with the pre-substep activation
+    const real ka = dt / m->tau_act;
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.actn[i] = E.act[i] + ka * (E.a[m->n_motor + i] - E.act[i]);
+  }
   __syncthreads();
   if (inplace) {
     if (ln < m->nq) E.q[ln] = E.qn[ln];
     if (ln < nv) E.qd[ln] = E.qdn[ln];
+    if constexpr (L::kMtu > 0)
+      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = E.actn[i];
     __syncthreads();
   }
 }
@@ -587,13 +775,22 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, EnvL
 // On entry E.q/E.qd/E.a hold the pre-substep state, E.qb/E.qdb the adjoint of the
 // post-substep state.  On exit E.qb/E.qdb hold the adjoint of the pre-substep state and
 // E.abar has gained this substep's contribution.
-template <int NV>
-__device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m, EnvLDS& E,
+template <int NV, class L>
+__device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m, L& E,
                                                      const JointRegs& jr, const ContactRegs& cr, int ln,
                                                      const Chol& C, int fb) {
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real dt = m->dt_sub;
   const real g = m->g;
+  if constexpr (L::kMtu > 0) {
+    // activation lag reverse: act' = act + (dt/tau)(u - act)
+    const real ka = dt / m->tau_act;
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) {
+      const real gb = E.act_bar[i];
+      E.abar[m->n_motor + i] += ka * gb;
+      E.act_bar[i] = gb - ka * gb;
+    }
+  }
   // ---- integrator reverse (lane = joint)
   if (ln < J) {
     if (jr.type == J_FREE) {
@@ -688,6 +885,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(E.cVb[ln], spf(x, vbar));
   }
   __syncthreads();
+  if constexpr (L::kMtu > 0) muscle_adjoint(m, E, ln);
   // ---- per-body terms (lane = joint): P Q R T Fn Ab Vb
   if (ln < J) {
     const real* Ib = E.Ib[ln];
@@ -704,6 +902,11 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
       Fn = subsv(Fn, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
       Ab = addsv(Ab, ldsv(E.cAb[ci]));
       Vb = addsv(Vb, ldsv(E.cVb[ci]));
+    }
+    if constexpr (L::kMtu > 0) {
+      Fn = subsv(Fn, ldsv(E.Fm[ln]));
+      Ab = addsv(Ab, ldsv(E.mAb[ln]));
+      Vb = addsv(Vb, ldsv(E.mVb[ln]));
     }
     real* o = E.acc[ln];
     stsv(o + 0, Iw); stsv(o + 6, Q); stsv(o + 12, Rr); stsv(o + 18, T);
@@ -783,8 +986,8 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
 
 // Adjoint of one substep from its pre-state alone: the forward linearisation is
 // recomputed first (plain path, and the last substep of a recomputed segment).
-template <int NV>
-__device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvLDS& E,
+template <int NV, class L>
+__device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, L& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln) {
   Chol C;
   int fb;
@@ -800,19 +1003,22 @@ __device__ __forceinline__ void substep_adjoint(const Scal* __restrict__ m, EnvL
 // reciprocal pivots and the FP64-fallback flag (the FP64 factor itself is not kept: a
 // flagged substep is recomputed).  These fields are one contiguous block of EnvLDS, so
 // a tape entry is a byte copy of it: 16 bytes per lane and instruction.
-static_assert(offsetof(EnvLDS, tpad) + sizeof(real) * kTapePad - offsetof(EnvLDS, q) == (size_t)kTapeBytes,
-              "tape block layout");
-static_assert(offsetof(EnvLDS, q) == 0, "tape block first");
 
 // make the post-substep state current (the in-place end of substep_forward)
-__device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, EnvLDS& E, int ln) {
+template <class L>
+__device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, L& E, int ln) {
   if (ln < m->nq) E.q[ln] = E.qn[ln];
   if (ln < m->nv) E.qd[ln] = E.qdn[ln];
+  if constexpr (L::kMtu > 0)
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = E.actn[i];
   __syncthreads();
 }
 
-template <int NV>
-__device__ __forceinline__ void tape_store(EnvLDS& E, const Chol& C, int fb, int ln, real* __restrict__ tp) {
+template <int NV, class L>
+__device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, real* __restrict__ tp) {
+  static_assert(offsetof(L, q) == 0, "tape block first");
+  static_assert(offsetof(L, tpad) + sizeof(real) * L::kPad - offsetof(L, q) >= (size_t)L::kTapeBytes,
+                "tape entry inside the LDS block");
   real dv = RL(0.0);
 #pragma unroll
   for (int k = 0; k < NV; ++k) dv = (ln == k) ? C.dinv[k] : dv;
@@ -826,17 +1032,17 @@ __device__ __forceinline__ void tape_store(EnvLDS& E, const Chol& C, int fb, int
   u32x4* dst = reinterpret_cast<u32x4*>(tp);
   // streaming (non-temporal) stores: the tape must not displace the policy weights in L2
 #pragma unroll
-  for (int i = 0; i < kTapeBytes / 1024; ++i) __builtin_nontemporal_store(src[i * SIM_WAVE + ln], &dst[i * SIM_WAVE + ln]);
+  for (int i = 0; i < L::kTapeBytes / 1024; ++i) __builtin_nontemporal_store(src[i * SIM_WAVE + ln], &dst[i * SIM_WAVE + ln]);
 }
 
 // Restores the block with direct global-to-LDS transfers (no registers in flight,
 // non-temporal), then the factor's rows and columns and the pivots into registers.
-template <int NV>
-__device__ __forceinline__ void tape_load(EnvLDS& E, Chol& C, int& fb, int ln, const real* __restrict__ tp) {
+template <int NV, class L>
+__device__ __forceinline__ void tape_load(L& E, Chol& C, int& fb, int ln, const real* __restrict__ tp) {
   const char* g = reinterpret_cast<const char*>(tp);
   char* l = reinterpret_cast<char*>(&E.q[0]);
 #pragma unroll
-  for (int i = 0; i < kTapeBytes / 1024; ++i)
+  for (int i = 0; i < L::kTapeBytes / 1024; ++i)
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + i * 1024 + ln * 16),
                                      (__attribute__((address_space(3))) void*)(l + i * 1024), 16, 0,
                                      /* non-temporal */ 2);

@@ -6,41 +6,54 @@ __device__ __forceinline__ bool all_finite_wave(bool ok) {
   return __all(ok);
 }
 
-__device__ __forceinline__ void load_state(const Scal* __restrict__ m, EnvLDS& E, const real* s, int ln) {
+template <class L>
+__device__ __forceinline__ void load_state(const Scal* __restrict__ m, L& E, const real* s, int ln) {
   int nq = m->nq, nv = m->nv;
   for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = s[i];
   for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = s[nq + i];
   if (m->has_last_action)
     for (int i = ln; i < m->na; i += SIM_WAVE) E.a[i] = s[nq + nv + i];
   else
-    for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.a[i] = RL(0.0);
+    for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.a[i] = RL(0.0);
+  if constexpr (L::kMtu > 0) {
+    const int o = nq + nv + (m->has_last_action ? m->na : 0);
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = s[o + i];
+  }
   __syncthreads();
 }
 
-__device__ __forceinline__ void store_qqd(const Scal* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
+// checkpoint of the dynamic state: [q | qd | act] (nck values)
+template <class L>
+__device__ __forceinline__ void store_qqd(const Scal* __restrict__ m, const L& E, real* dst, int ln) {
   int nq = m->nq, nv = m->nv;
   for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.q[i];
   for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qd[i];
+  if constexpr (L::kMtu > 0)
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) dst[nq + nv + i] = E.act[i];
 }
 
-__device__ __forceinline__ void load_qqd(const Scal* __restrict__ m, EnvLDS& E, const real* src, int ln) {
+template <class L>
+__device__ __forceinline__ void load_qqd(const Scal* __restrict__ m, L& E, const real* src, int ln) {
   int nq = m->nq, nv = m->nv;
   for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = src[i];
   for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = src[nq + i];
+  if constexpr (L::kMtu > 0)
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = src[nq + nv + i];
   __syncthreads();
 }
 
 // observation, action and reward at the start of frame t (state in E.q/E.qd, previous
 // action in E.a); leaves a_t in E.a.
-__device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
+template <class L>
+__device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __restrict__ m, L& E,
                                             int env, int t, int ln) {
   const int N = A.N, od = m->od, na = m->na;
-  task_obs(m, E.q, E.qd, E.a, E.obs, ln);
+  task_obs(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)t * N + env) * od;
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
   if (A.closed_loop) {
     mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, ln);
-    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = m_tanh(E.y[i]);
+    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, E.y[i]);
   } else {
     const real* ai = A.actions_in + ((size_t)t * N + env) * na;
     for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = ai[i];
@@ -53,10 +66,11 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   __syncthreads();
 }
 
-__device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
+template <class L>
+__device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restrict__ m, L& E,
                                            int env, int ln) {
   const int N = A.N, od = m->od, ns = m->ns, nq = m->nq, nv = m->nv, na = m->na;
-  task_obs(m, E.q, E.qd, E.a, E.obs, ln);
+  task_obs(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)A.h * N + env) * od;
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
   mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, ln);
@@ -67,21 +81,25 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restr
   for (int i = ln; i < nv; i += SIM_WAVE) { so[nq + i] = E.qd[i]; ok = ok && m_isfinite(E.qd[i]); }
   if (m->has_last_action)
     for (int i = ln; i < na; i += SIM_WAVE) so[nq + nv + i] = E.a[i];
+  if constexpr (L::kMtu > 0) {
+    const int o = nq + nv + (m->has_last_action ? na : 0);
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) { so[o + i] = E.act[i]; ok = ok && m_isfinite(E.act[i]); }
+  }
   bool all = all_finite_wave(ok);
   if (ln == 0 && A.nonfinite) A.nonfinite[env] = all ? 0 : 1;
 }
 
 // ======================================================================= persistent forward
 // One environment's forward window (the wavefront owns env; E is its LDS).
-template <int NV>
-__device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, EnvLDS& E) {
+template <int NV, class L>
+__device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
   const int ln = threadIdx.x;
   JointRegs jr;
   ContactRegs cr;
   load_regs(A.model, E, ln, jr, cr);
-  const int S = m->substeps, nqv = m->nq + m->nv, N = A.N;
+  const int S = m->substeps, nqv = m->nck, N = A.N;
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
   Chol C;
   int nfb = 0;
@@ -93,7 +111,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, EnvLD
       if (A.tape_full) {
         // the tape entry holds the pre-substep state and the linearisation
         substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-        tape_store<NV>(E, C, fb, ln, A.tape + ((size_t)gi * N + env) * kTapeReals);
+        tape_store<NV>(E, C, fb, ln, A.tape + ((size_t)gi * N + env) * L::kTapeReals);
         commit_substep(m, E, ln);
       } else {
         if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
@@ -108,14 +126,17 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, EnvLD
 
 // ======================================================================= persistent adjoint
 // terminal seed: s_bar(h) = -gamma^h scale (d obs/d s)^T dV/d obs  (+ optional upstream)
-__device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
+template <class L>
+__device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __restrict__ m, L& E,
                                              int env, int ln) {
   const int ns = m->ns, nq = m->nq, nv = m->nv, na = m->na, od = m->od;
   const real* sh = A.s_h_in + (size_t)env * ns;
   load_state(m, E, sh, ln);
   for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = RL(0.0);
   for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = RL(0.0);
-  for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+  for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+  if constexpr (L::kMtu > 0)
+    for (int i = ln; i < L::kMtu; i += SIM_WAVE) E.act_bar[i] = RL(0.0);
   for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
   __syncthreads();
   mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, ln);
@@ -124,13 +145,17 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
   __syncthreads();
   mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, ln);
   // E.obs now holds obs_bar; E.a holds a_prev of s_h
-  task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, ln);
+  task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   if (A.grad_s_h) {
     const real* gs = A.grad_s_h + (size_t)env * ns;
     for (int i = ln; i < nq; i += SIM_WAVE) E.qb[i] += gs[i];
     for (int i = ln; i < nv; i += SIM_WAVE) E.qdb[i] += gs[nq + i];
     if (m->has_last_action)
       for (int i = ln; i < na; i += SIM_WAVE) E.abar[i] += gs[nq + nv + i];
+    if constexpr (L::kMtu > 0) {
+      const int o = nq + nv + (m->has_last_action ? na : 0);
+      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act_bar[i] += gs[o + i];
+    }
   }
   __syncthreads();
 }
@@ -138,12 +163,13 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
 // frame-level reverse at frame t: E.qb/E.qdb hold the adjoint of the frame-start (q, qd)
 // through the dynamics; E.abar holds dL/da_t except the reward term.  E.q/E.qd hold the
 // frame-start state unless load_start (then it is read from the checkpoint arena).
-__device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __restrict__ m, EnvLDS& E,
+template <class L>
+__device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __restrict__ m, L& E,
                                               int env, int t, int ln, bool load_start) {
   const int N = A.N, nq = m->nq, nv = m->nv, na = m->na, od = m->od, ns = m->ns, S = m->substeps;
-  const int nqv = nq + nv;
+  const int nck = m->nck;
   // frame-start state and a_t
-  if (load_start) load_qqd(m, E, A.ckpt + ((size_t)(t * S / A.k) * N + env) * nqv, ln);
+  if (load_start) load_qqd(m, E, A.ckpt + ((size_t)(t * S / A.k) * N + env) * nck, ln);
   const real* at = A.actions_fw + ((size_t)t * N + env) * na;
   for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
   __syncthreads();
@@ -157,22 +183,22 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
     for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)t * N + env) * od + i];
     __syncthreads();
     mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, ln);
-    for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * (RL(1.0) - E.a[i] * E.a[i]);
+    for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
     mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, ln);
-    for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+    for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
     __syncthreads();
-    task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, ln);
+    task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   } else {
-    for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+    for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
     __syncthreads();
   }
   (void)ns;
 }
 
 // One environment's reverse window.
-template <int NV>
-__device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLDS& E) {
+template <int NV, class L>
+__device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
   const int ln = threadIdx.x;
@@ -180,7 +206,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLD
   ContactRegs cr;
   load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nq = m->nq, nv = m->nv, na = m->na, ns = m->ns, N = A.N, k = A.k;
-  const int nqv = nq + nv;
+  const int nqv = m->nck;
   adjoint_seed(A, m, E, env, ln);
   // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
   Chol C;
@@ -192,12 +218,12 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLD
       for (int sub = S - 1; sub >= 0; --sub) {
         const size_t c = (size_t)t * S + sub;
         int fb;
-        tape_load<NV>(E, C, fb, ln, A.tape + (c * N + env) * kTapeReals);
+        tape_load<NV>(E, C, fb, ln, A.tape + (c * N + env) * L::kTapeReals);
         if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
       }
     } else {
-      real* tseg = A.tape + (size_t)env * (k - 1) * kTapeReals;
+      real* tseg = A.tape + (size_t)env * (k - 1) * L::kTapeReals;
       for (int sg = S / k - 1; sg >= 0; --sg) {
         int c = (t * S + sg * k) / k;
         const real* ck = A.ckpt + ((size_t)c * N + env) * nqv;
@@ -207,7 +233,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLD
         for (int i = 0; i < k - 1; ++i) {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          tape_store<NV>(E, C, fb, ln, tseg + (size_t)i * kTapeReals);
+          tape_store<NV>(E, C, fb, ln, tseg + (size_t)i * L::kTapeReals);
           commit_substep(m, E, ln);
         }
         {
@@ -217,7 +243,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLD
         }
         for (int i = k - 2; i >= 0; --i) {
           int fb;
-          tape_load<NV>(E, C, fb, ln, tseg + (size_t)i * kTapeReals);
+          tape_load<NV>(E, C, fb, ln, tseg + (size_t)i * L::kTapeReals);
           if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
@@ -231,6 +257,10 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, EnvLD
   for (int i = ln; i < nv; i += SIM_WAVE) d0[nq + i] = E.qdb[i];
   if (m->has_last_action)
     for (int i = ln; i < na; i += SIM_WAVE) d0[nq + nv + i] = E.abar[i];
+  if constexpr (L::kMtu > 0) {
+    const int o = nq + nv + (m->has_last_action ? na : 0);
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) d0[o + i] = E.act_bar[i];
+  }
 }
 
 template <int NV>
@@ -245,37 +275,71 @@ __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
   window_adj_body<NV>(A, blockIdx.x, E);
 }
 
+// muscle-driven models: the larger LDS layout with activations and muscle terms
+template <int NV>
+__global__ __launch_bounds__(SIM_WAVE) void k_window_fwd_m(WinArgs A) {
+  __shared__ EnvLDSM E;
+  window_fwd_body<NV>(A, blockIdx.x, E);
+}
+
+template <int NV>
+__global__ __launch_bounds__(SIM_WAVE) void k_window_adj_m(WinArgs A) {
+  __shared__ EnvLDSM E;
+  window_adj_body<NV>(A, blockIdx.x, E);
+}
+
 // ======================================================================= mixed-morphology group
 // One launch over the envs of several models: block b runs env b - start[s] of the model in
 // work-table slot s (slots ordered by decreasing per-env cost, so the longest windows are
 // dispatched first).  Each slot's model runs the DOF-specialised body of its own kernel.
+// A group with a muscle model reserves the muscle LDS layout for every block; the other
+// slots view the same storage with the torque-model layout.
 __device__ __forceinline__ int group_slot(const GroupArgs& G, int b) {
   int s = 0;
   for (int i = 1; i < G.n; ++i) s = (b >= G.start[i]) ? i : s;
   return s;
 }
 
-#define SIM_GROUP_CASE_F(n) case n: window_fwd_body<n>(G.A[s], env, E); break;
-#define SIM_GROUP_CASE_A(n) case n: window_adj_body<n>(G.A[s], env, E); break;
+template <bool ADJ, int NV, class L>
+__device__ __forceinline__ void group_body(const WinArgs& A, int env, L& E) {
+  if (ADJ) window_adj_body<NV>(A, env, E);
+  else window_fwd_body<NV>(A, env, E);
+}
 
-__global__ __launch_bounds__(SIM_WAVE) void k_group_fwd(GroupArgs G) {
-  __shared__ EnvLDS E;
-  const int s = group_slot(G, blockIdx.x);
-  const int env = blockIdx.x - G.start[s];
+template <bool ADJ>
+__device__ __forceinline__ void group_torque(const GroupArgs& G, int s, int env, EnvLDS& E) {
   switch (G.nv[s]) {
-    SIM_NV_LIST(SIM_GROUP_CASE_F)
-    default: window_fwd_body<SIM_MAXV>(G.A[s], env, E);
+#define SIM_GROUP_T(n) case n: group_body<ADJ, n>(G.A[s], env, E); break;
+    SIM_NV_LIST(SIM_GROUP_T)
+#undef SIM_GROUP_T
+    default: group_body<ADJ, SIM_MAXV>(G.A[s], env, E);
   }
 }
 
-__global__ __launch_bounds__(SIM_WAVE) void k_group_adj(GroupArgs G) {
+template <bool ADJ>
+__device__ __forceinline__ void group_muscle(const GroupArgs& G, int s, int env, EnvLDSM& E) {
+  switch (G.nv[s]) {
+#define SIM_GROUP_M(n) case n: group_body<ADJ, n>(G.A[s], env, E); break;
+    SIM_NV_LIST_MTU(SIM_GROUP_M)
+#undef SIM_GROUP_M
+    default: group_body<ADJ, SIM_MAXV>(G.A[s], env, E);
+  }
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(SIM_WAVE) void k_group(GroupArgs G) {
   __shared__ EnvLDS E;
   const int s = group_slot(G, blockIdx.x);
+  group_torque<ADJ>(G, s, blockIdx.x - G.start[s], E);
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(SIM_WAVE) void k_group_m(GroupArgs G) {
+  __shared__ __attribute__((aligned(16))) char buf[sizeof(EnvLDSM) > sizeof(EnvLDS) ? sizeof(EnvLDSM) : sizeof(EnvLDS)];
+  const int s = group_slot(G, blockIdx.x);
   const int env = blockIdx.x - G.start[s];
-  switch (G.nv[s]) {
-    SIM_NV_LIST(SIM_GROUP_CASE_A)
-    default: window_adj_body<SIM_MAXV>(G.A[s], env, E);
-  }
+  if (G.mtu[s]) group_muscle<ADJ>(G, s, env, *reinterpret_cast<EnvLDSM*>(buf));
+  else group_torque<ADJ>(G, s, env, *reinterpret_cast<EnvLDS*>(buf));
 }
 
 // ======================================================================= plain path kernels
@@ -341,14 +405,16 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_end(WinArgs A) {
   window_end(A, m, E, env, ln);
 }
 
-__device__ __forceinline__ void adj_load(const Scal* __restrict__ m, EnvLDS& E, const real* src, int ln) {
+template <class L>
+__device__ __forceinline__ void adj_load(const Scal* __restrict__ m, L& E, const real* src, int ln) {
   int nq = m->nq, nv = m->nv, na = m->na;
   for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = i < nq ? src[i] : RL(0.0);
   for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = i < nv ? src[nq + i] : RL(0.0);
-  for (int i = ln; i < SIM_MAXA; i += SIM_WAVE) E.abar[i] = i < na ? src[nq + nv + i] : RL(0.0);
+  for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = i < na ? src[nq + nv + i] : RL(0.0);
   __syncthreads();
 }
-__device__ __forceinline__ void adj_store(const Scal* __restrict__ m, const EnvLDS& E, real* dst, int ln) {
+template <class L>
+__device__ __forceinline__ void adj_store(const Scal* __restrict__ m, const L& E, real* dst, int ln) {
   int nq = m->nq, nv = m->nv, na = m->na;
   for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.qb[i];
   for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qdb[i];
@@ -432,9 +498,11 @@ int launch_prep_weights(const real* W, real* WT, real* Wp, int n_out, int n_in, 
 }
 
 template <int NV>
-static void launch_forward_nv(const WinArgs& A, int plain, int substeps, hipStream_t s) {
+static void launch_forward_nv(const WinArgs& A, int plain, int substeps, int mtu, hipStream_t s) {
   dim3 grid(A.N), block(SIM_WAVE);
-  if (!plain) {
+  if (mtu) {
+    hipLaunchKernelGGL(k_window_fwd_m<NV>, grid, block, 0, s, A);
+  } else if (!plain) {
     hipLaunchKernelGGL(k_window_fwd<NV>, grid, block, 0, s, A);
   } else {
     for (int t = 0; t < A.h; ++t) {
@@ -446,9 +514,11 @@ static void launch_forward_nv(const WinArgs& A, int plain, int substeps, hipStre
 }
 
 template <int NV>
-static void launch_adjoint_nv(const WinArgs& A, int plain, int substeps, hipStream_t s) {
+static void launch_adjoint_nv(const WinArgs& A, int plain, int substeps, int mtu, hipStream_t s) {
   dim3 grid(A.N), block(SIM_WAVE);
-  if (!plain) {
+  if (mtu) {
+    hipLaunchKernelGGL(k_window_adj_m<NV>, grid, block, 0, s, A);
+  } else if (!plain) {
     hipLaunchKernelGGL(k_window_adj<NV>, grid, block, 0, s, A);
   } else {
     hipLaunchKernelGGL(k_plain_adj_seed, grid, block, 0, s, A);
@@ -460,33 +530,58 @@ static void launch_adjoint_nv(const WinArgs& A, int plain, int substeps, hipStre
   }
 }
 
-// DOF counts with a kernel of their own (SIM_NV_LIST, set per arithmetic type); every
-// other model runs the padded 32-DOF kernel
-#define SIM_NV_CASE_F(n) case n: launch_forward_nv<n>(A, plain, substeps, s); break;
-#define SIM_NV_CASE_A(n) case n: launch_adjoint_nv<n>(A, plain, substeps, s); break;
-
-int launch_forward(const WinArgs& A, int plain, int substeps, int nv, void* stream) {
+// Torque-driven models have a kernel per DOF count in SIM_NV_LIST, muscle-driven ones per
+// DOF count in SIM_NV_LIST_MTU; every other model runs the padded 32-DOF kernel.  The
+// plain path exists for torque-driven models only (the host rejects the other case).
+int launch_forward(const WinArgs& A, int plain, int substeps, int nv, int mtu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  switch (nv) {
-    SIM_NV_LIST(SIM_NV_CASE_F)
-    default: launch_forward_nv<SIM_MAXV>(A, plain, substeps, s);
+  if (mtu) {
+    switch (nv) {
+#define SIM_CASE_FM(n) case n: launch_forward_nv<n>(A, 0, substeps, 1, s); break;
+      SIM_NV_LIST_MTU(SIM_CASE_FM)
+#undef SIM_CASE_FM
+      default: launch_forward_nv<SIM_MAXV>(A, 0, substeps, 1, s);
+    }
+  } else {
+    switch (nv) {
+#define SIM_CASE_F(n) case n: launch_forward_nv<n>(A, plain, substeps, 0, s); break;
+      SIM_NV_LIST(SIM_CASE_F)
+#undef SIM_CASE_F
+      default: launch_forward_nv<SIM_MAXV>(A, plain, substeps, 0, s);
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_adjoint(const WinArgs& A, int plain, int substeps, int nv, void* stream) {
+int launch_adjoint(const WinArgs& A, int plain, int substeps, int nv, int mtu, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  switch (nv) {
-    SIM_NV_LIST(SIM_NV_CASE_A)
-    default: launch_adjoint_nv<SIM_MAXV>(A, plain, substeps, s);
+  if (mtu) {
+    switch (nv) {
+#define SIM_CASE_AM(n) case n: launch_adjoint_nv<n>(A, 0, substeps, 1, s); break;
+      SIM_NV_LIST_MTU(SIM_CASE_AM)
+#undef SIM_CASE_AM
+      default: launch_adjoint_nv<SIM_MAXV>(A, 0, substeps, 1, s);
+    }
+  } else {
+    switch (nv) {
+#define SIM_CASE_A(n) case n: launch_adjoint_nv<n>(A, plain, substeps, 0, s); break;
+      SIM_NV_LIST(SIM_CASE_A)
+#undef SIM_CASE_A
+      default: launch_adjoint_nv<SIM_MAXV>(A, plain, substeps, 0, s);
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_group(const GroupArgs& G, int adjoint, void* stream) {
+int launch_group(const GroupArgs& G, int adjoint, int mtu, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   dim3 grid(G.start[G.n]), block(SIM_WAVE);
-  if (adjoint) hipLaunchKernelGGL(k_group_adj, grid, block, 0, st, G);
-  else hipLaunchKernelGGL(k_group_fwd, grid, block, 0, st, G);
+  if (mtu) {
+    if (adjoint) hipLaunchKernelGGL(k_group_m<true>, grid, block, 0, st, G);
+    else hipLaunchKernelGGL(k_group_m<false>, grid, block, 0, st, G);
+  } else {
+    if (adjoint) hipLaunchKernelGGL(k_group<true>, grid, block, 0, st, G);
+    else hipLaunchKernelGGL(k_group<false>, grid, block, 0, st, G);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -16,7 +16,10 @@ typedef GroupArgsT<real> GroupArgs;
 // memory are read only at kernel start).
 struct Scal {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
+  int n_mtu, n_motor, nck;
   real dt_sub, g, kn, kd, kt, mu, klim, chol_thr;
+  real tau_act, fl_w, vmax;
+  const DevModel* tab;   // the model's tables (muscle paths) in global memory
 };
 __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   Scal s;
@@ -25,6 +28,9 @@ __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   s.substeps = m->substeps; s.max_depth = m->max_depth;
   s.dt_sub = m->dt_sub; s.g = m->g; s.kn = m->kn; s.kd = m->kd; s.kt = m->kt; s.mu = m->mu; s.klim = m->klim;
   s.chol_thr = m->chol_thr;
+  s.n_mtu = m->n_mtu; s.n_motor = m->n_motor; s.nck = m->nck;
+  s.tau_act = m->tau_act; s.fl_w = m->fl_w; s.vmax = m->vmax;
+  s.tab = m;
   return s;
 }
 
@@ -38,6 +44,8 @@ __device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sinco
 __device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double m_fma(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
 __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float m_tanh(float x) { return tanhf(x); }
 __device__ __forceinline__ double m_tanh(double x) { return tanh(x); }

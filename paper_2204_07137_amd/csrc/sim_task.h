@@ -119,17 +119,37 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
   }
 }
 
+// --------------------------------------------------------------- policy squashing
+// torques: a = tanh(y); muscle excitations: u = (tanh(y) + 1) / 2
+__device__ __forceinline__ real squash(const Scal* __restrict__ m, real y) {
+  real t = m_tanh(y);
+  return (m->task == TASK_MTU) ? RL(0.5) * (t + RL(1.0)) : t;
+}
+// d(action)/dy expressed through the action value
+__device__ __forceinline__ real squash_grad(const Scal* __restrict__ m, real a) {
+  return (m->task == TASK_MTU) ? RL(2.0) * a * (RL(1.0) - a) : RL(1.0) - a * a;
+}
+
 // --------------------------------------------------------------- observations
-// s = [q | qd | a_prev];  obs written to o (LDS)
+// s = [q | qd | a_prev | act];  obs written to o (LDS).  The muscle task observes the
+// humanoid skeleton entries (no last action), zero padding up to entry 128 and the
+// muscle activations.
 __device__ __forceinline__ void task_obs(const Scal* __restrict__ m, const real* q, const real* qd,
-                                         const real* aprev, real* o, int ln) {
-  if (m->task == TASK_CARTPOLE) {
+                                         const real* aprev, const real* act, real* o, int ln) {
+  if (m->task == TASK_NONE) {
+    // no task: the observation is the state [q | qd | a_prev | act]
+    const int nq = m->nq, nv = m->nv, na = m->has_last_action ? m->na : 0;
+    for (int i = ln; i < nq; i += SIM_WAVE) o[i] = q[i];
+    for (int i = ln; i < nv; i += SIM_WAVE) o[nq + i] = qd[i];
+    for (int i = ln; i < na; i += SIM_WAVE) o[nq + nv + i] = aprev[i];
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) o[nq + nv + na + i] = act[i];
+  } else if (m->task == TASK_CARTPOLE) {
     if (ln == 0) {
       real sn, cs;
       m_sincos(q[1], &sn, &cs);
       o[0] = q[0]; o[1] = qd[0]; o[2] = sn; o[3] = cs; o[4] = qd[1];
     }
-  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID || m->task == TASK_MTU) {
     int nh = m->nq - 7;
     if (ln == 0) {
       real w = q[3], x = q[4], y = q[5], z = q[6];
@@ -146,20 +166,30 @@ __device__ __forceinline__ void task_obs(const Scal* __restrict__ m, const real*
     }
     if (m->has_last_action)
       for (int i = ln; i < m->na; i += SIM_WAVE) o[13 + 2 * nh + i] = aprev[i];
+    if (m->task == TASK_MTU) {
+      for (int i = 13 + 2 * nh + ln; i < 128; i += SIM_WAVE) o[i] = RL(0.0);
+      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) o[128 + i] = act[i];
+    }
   }
   __syncthreads();
 }
 
-// adjoint of task_obs: adds (d obs / d s)^T obar to (qb, qdb, abar_prev)
+// adjoint of task_obs: adds (d obs / d s)^T obar to (qb, qdb, abar_prev, act_bar)
 __device__ __forceinline__ void task_obs_vjp(const Scal* __restrict__ m, const real* q, const real* ob,
-                                             real* qb, real* qdb, real* apb, int ln) {
-  if (m->task == TASK_CARTPOLE) {
+                                             real* qb, real* qdb, real* apb, real* actb, int ln) {
+  if (m->task == TASK_NONE) {
+    const int nq = m->nq, nv = m->nv, na = m->has_last_action ? m->na : 0;
+    for (int i = ln; i < nq; i += SIM_WAVE) qb[i] += ob[i];
+    for (int i = ln; i < nv; i += SIM_WAVE) qdb[i] += ob[nq + i];
+    for (int i = ln; i < na; i += SIM_WAVE) apb[i] += ob[nq + nv + i];
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) actb[i] += ob[nq + nv + na + i];
+  } else if (m->task == TASK_CARTPOLE) {
     if (ln == 0) {
       real sn, cs;
       m_sincos(q[1], &sn, &cs);
       qb[0] += ob[0]; qdb[0] += ob[1]; qb[1] += cs * ob[2] - sn * ob[3]; qdb[1] += ob[4];
     }
-  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID || m->task == TASK_MTU) {
     int nh = m->nq - 7;
     if (ln == 0) {
       real w = q[3], x = q[4], y = q[5], z = q[6];
@@ -182,6 +212,8 @@ __device__ __forceinline__ void task_obs_vjp(const Scal* __restrict__ m, const r
     }
     if (m->has_last_action)
       for (int i = ln; i < m->na; i += SIM_WAVE) apb[i] += ob[13 + 2 * nh + i];
+    if (m->task == TASK_MTU)
+      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) actb[i] += ob[128 + i];
   }
   __syncthreads();
 }
@@ -195,7 +227,7 @@ __device__ __forceinline__ real task_reward(const Scal* __restrict__ m, const re
     m_sincos(q[1], &sn, &cs);
     real th = m_atan2(sn, cs);
     r = -th * th - RL(0.1) * qd[1] * qd[1] - RL(0.05) * q[0] * q[0] - RL(0.1) * qd[0] * qd[0];
-  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID || m->task == TASK_MTU) {
     real w = q[3], x = q[4], y = q[5], z = q[6];
     real n2 = w * w + x * x + y * y + z * z;
     real up = RL(1.0) - RL(2.0) * (x * x + y * y) / n2;
@@ -204,12 +236,18 @@ __device__ __forceinline__ real task_reward(const Scal* __restrict__ m, const re
     r = qd[0] + RL(0.1) * up + hd;
     if (m->task == TASK_ANT) {
       r += hgt - RL(0.27);
-    } else {
+    } else if (m->task == TASK_HUMANOID) {
       real dh = m_fmin(m_fmax(hgt - RL(0.84), -RL(1.0)), RL(0.1));
       r += (dh < RL(0.0)) ? -RL(200.0) * dh * dh : RL(10.0) * dh;
       real aa = RL(0.0);
       for (int i = 0; i < m->na; ++i) aa += a[i] * a[i];
       r -= RL(0.002) * aa;
+    } else {
+      real dh = m_fmin(m_fmax(hgt - RL(0.84), -RL(1.0)), RL(0.05));
+      r += (dh < RL(0.0)) ? -RL(200.0) * dh * dh : RL(4.0) * dh;
+      real aa = RL(0.0);
+      for (int i = 0; i < m->na; ++i) aa += a[i] * a[i];
+      r -= RL(0.001) * aa;
     }
   }
   return r;
@@ -229,7 +267,7 @@ __device__ __forceinline__ void task_reward_vjp(const Scal* __restrict__ m, cons
       qb[0] += c * (-RL(0.1) * q[0]);
       qdb[0] += c * (-RL(0.2) * qd[0]);
     }
-  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID) {
+  } else if (m->task == TASK_ANT || m->task == TASK_HUMANOID || m->task == TASK_MTU) {
     if (ln == 0) {
       real w = q[3], x = q[4], y = q[5], z = q[6];
       real n2 = w * w + x * x + y * y + z * z;
@@ -244,13 +282,18 @@ __device__ __forceinline__ void task_reward_vjp(const Scal* __restrict__ m, cons
       real hgt = q[2];
       if (m->task == TASK_ANT) {
         qb[2] += c;
-      } else {
+      } else if (m->task == TASK_HUMANOID) {
         real xh = hgt - RL(0.84);
         if (xh >= -RL(1.0) && xh <= RL(0.1)) qb[2] += c * ((xh < RL(0.0)) ? -RL(400.0) * xh : RL(10.0));
+      } else {
+        real xh = hgt - RL(0.84);
+        if (xh >= -RL(1.0) && xh <= RL(0.05)) qb[2] += c * ((xh < RL(0.0)) ? -RL(400.0) * xh : RL(4.0));
       }
     }
     if (m->task == TASK_HUMANOID)
       for (int i = ln; i < m->na; i += SIM_WAVE) abar[i] += c * (-RL(0.004) * a[i]);
+    if (m->task == TASK_MTU)
+      for (int i = ln; i < m->na; i += SIM_WAVE) abar[i] += c * (-RL(0.002) * a[i]);
   }
   __syncthreads();
 }

@@ -9,25 +9,34 @@
 #define SIM_MAXV 32      // velocity DOFs (one row of M per lane)
 #define SIM_MAXQ 33      // position coordinates
 #define SIM_MAXC 32      // contact spheres
-#define SIM_MAXA 32      // actuators
-#define SIM_MAXOBS 128   // observation width
+#define SIM_MAXA 32      // actions of torque-driven models
+#define SIM_MAXAM 160    // actions of muscle-driven models (motors + muscle excitations)
+#define SIM_MAXMTU 160   // muscle-tendon units
+#define SIM_MAXMPT 6     // path points per muscle-tendon unit
+#define SIM_MAXOBS 288   // observation width
 #define SIM_MAXHID 512   // MLP width
 #define SIM_MAXL 4       // MLP linear layers
 #define SIM_MAXPAIR 576  // (frame, ancestor-or-self) pairs of the mass matrix, 9 rounds of 64 lanes
 // linearisation tape of one substep: SIM_TAPE_REALS values (pre-substep state, frame
 // screws, velocities, bias accelerations and inertias, contact data, accelerations, new
-// velocities, the Cholesky rows, pivots and flag), padded to whole 1 KB blocks
+// velocities, the Cholesky rows, pivots and flag), plus the frame transforms and the
+// activations for muscle models, padded to whole 1 KB blocks
 #define SIM_TAPE_REALS 2465
-static inline size_t sim_tape_bytes(size_t elem) { return (SIM_TAPE_REALS * elem + 1023) / 1024 * 1024; }
+static inline size_t sim_tape_bytes(size_t elem, int muscles) {
+  size_t n = SIM_TAPE_REALS + (muscles ? 12 * SIM_MAXJ + SIM_MAXMTU : 0);
+  return (n * elem + 1023) / 1024 * 1024;
+}
 
 enum { J_FREE = 0, J_HINGE = 1, J_SLIDE = 2 };
-enum { TASK_NONE = 0, TASK_CARTPOLE = 1, TASK_ANT = 2, TASK_HUMANOID = 3 };
+enum { TASK_NONE = 0, TASK_CARTPOLE = 1, TASK_ANT = 2, TASK_HUMANOID = 3, TASK_MTU = 4 };
 
 template <typename T>
 struct DevModelT {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
+  int n_mtu, n_motor, nck;   // muscles; motors (the first n_motor actions); nq + nv + n_mtu
   T dt_sub, g, kn, kd, kt, mu, klim;
   T chol_thr;   // FP64 refactorisation when the smallest pivot <= chol_thr * largest diagonal
+  T tau_act, fl_w, vmax;     // activation time constant, force-length width, max fibre speed (l_opt/s)
   int parent[SIM_MAXJ], jtype[SIM_MAXJ], qadr[SIM_MAXJ], vadr[SIM_MAXJ], depth[SIM_MAXJ];
   int first_child[SIM_MAXJ], next_sib[SIM_MAXJ], act_of_joint[SIM_MAXJ], limited[SIM_MAXJ];
   T offset[SIM_MAXJ * 3], axis[SIM_MAXJ * 3], mass[SIM_MAXJ], com[SIM_MAXJ * 3];
@@ -41,6 +50,11 @@ struct DevModelT {
   // ancestors-or-self: packed i | k << 5 | va_i << 10 | va_k << 15 | (k is FREE) << 20 | 1 << 21
   int npair;
   int pair[SIM_MAXPAIR];
+  // muscle-tendon units, point-major so that lanes (one unit each) read contiguously
+  int mtu_npt[SIM_MAXMTU];
+  int mtu_body[SIM_MAXMPT * SIM_MAXMTU];     // [point][unit]
+  T mtu_pos[SIM_MAXMPT * 3 * SIM_MAXMTU];    // [point][xyz][unit], in the body frame
+  T mtu_fmax[SIM_MAXMTU], mtu_lopt[SIM_MAXMTU], mtu_lslack[SIM_MAXMTU];
 };
 
 template <typename T>
@@ -89,6 +103,7 @@ struct GroupArgsT {
   int n;
   int start[SIM_MAXGROUP + 1];
   int nv[SIM_MAXGROUP];
+  int mtu[SIM_MAXGROUP];      // slot's model has muscles
   WinArgsT<T> A[SIM_MAXGROUP];
 };
 
@@ -115,11 +130,11 @@ struct ThetaArgsT {
 // Launchers implemented once per arithmetic type (kernels_f32.hip, kernels_f64.hip).
 #define SIM_DECLARE_LAUNCHERS(NS, T)                                                        \
   namespace NS {                                                                            \
-  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
-  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, void* stream); \
+  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, void* stream); \
+  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, void* stream); \
   int launch_prep_weights(const T* W, T* WT, T* Wp, int n_out, int n_in, void* stream);   \
   int launch_theta(const ThetaArgsT<T>& A, void* stream);                                  \
-  int launch_group(const GroupArgsT<T>& G, int adjoint, void* stream);                     \
+  int launch_group(const GroupArgsT<T>& G, int adjoint, int mtu, void* stream);            \
   }
 SIM_DECLARE_LAUNCHERS(sim_f32, float)
 SIM_DECLARE_LAUNCHERS(sim_f64, double)

@@ -624,3 +624,196 @@ def test_discounted_loss_closed_form():
     out = oracle_window(md, s0, h, None, critic, actions=acts, gamma=gamma)
     ref = np.pi ** 2 * (1 - gamma ** h) / ((1 - gamma) * h) - gamma ** h * c0 / h
     assert float(out["loss"]) == pytest.approx(ref, rel=1e-12)
+
+
+# ------------------------------------------------------------------ muscle-tendon units
+
+def _arm_state(md, theta, x=0.1, xd=0.0, thd=0.0, act=0.5):
+    return T([[x, theta, xd, thd, act]])
+
+
+@pytest.mark.parametrize("via", [None, 0.45])
+def test_muscle_path_length_rate_and_torque_closed_form(via):
+    """Cart + pole with one muscle (origin on the cart, insertion on the pole, optionally a
+    via point on the pole): L(theta) = sqrt(b^2+d^2-2bd sin th) [+ via form], the cart force
+    vanishes (the tension is internal to the chain) and the hinge torque is -F dL/dtheta."""
+    d, b = 0.3, 0.8
+    md = wl.muscle_arm(d=d, b=b, c=via)
+    m = OracleModel(md)
+    for th, thd in ((0.3, 1.7), (-0.8, -0.4), (1.2, 0.9)):
+        s = _arm_state(md, th, thd=thd)
+        q, qd, act = s[:, :2], s[:, 2:4], s[:, 4:5]
+        Tm = D.dynamics_terms(m, q, qd)
+        mt = D.muscle_terms(m, Tm, qd, act)
+        if via is None:
+            L = np.sqrt(b * b + d * d - 2 * b * d * np.sin(th))
+            dL = -b * d * np.cos(th) / L
+        else:
+            c = via
+            Lc = np.sqrt(c * c + d * d - 2 * c * d * np.sin(th))
+            L = Lc + (b - c)
+            dL = -c * d * np.cos(th) / Lc
+        assert float(mt["L"][0, 0]) == pytest.approx(L, rel=1e-13)
+        assert float(mt["Ldot"][0, 0]) == pytest.approx(dL * thd, rel=1e-12)
+        F = float(mt["F"][0, 0])
+        assert F > 0
+        tau = mt["tau"][0].numpy()
+        assert abs(tau[0]) < 1e-12 * F
+        assert tau[1] == pytest.approx(-F * dL, rel=1e-12)
+
+
+def test_muscle_force_length_velocity_special_cases():
+    """At l_m = l_opt and zero lengthening rate the tension is F_max * act; it falls to
+    F_max act exp(-1) one width away, and vanishes at the maximum shortening speed."""
+    d, b = 0.3, 0.8
+    th = 0.4
+    L = np.sqrt(b * b + d * d - 2 * b * d * np.sin(th))
+    lslack = 0.2
+    for lt, fl in ((1.0, 1.0), (1.45, np.exp(-1.0)), (0.55, np.exp(-1.0))):
+        lopt = (L - lslack) / lt
+        md = wl.muscle_arm(d=d, b=b, fmax=80.0, lopt=lopt, lslack=lslack)
+        m = OracleModel(md)
+        s = _arm_state(md, th, act=0.25)
+        Tm = D.dynamics_terms(m, s[:, :2], s[:, 2:4])
+        F = float(D.muscle_terms(m, Tm, s[:, 2:4], s[:, 4:5])["F"][0, 0])
+        assert F == pytest.approx(80.0 * 0.25 * fl, rel=1e-12)
+    # shortening at v_max * l_opt: f_v = 0
+    lopt = L - lslack
+    md = wl.muscle_arm(d=d, b=b, lopt=lopt, lslack=lslack)
+    m = OracleModel(md)
+    dL = -b * d * np.cos(th) / L
+    thd = -10.0 * lopt / dL        # Ldot = -v_max l_opt
+    s = _arm_state(md, th, thd=thd)
+    Tm = D.dynamics_terms(m, s[:, :2], s[:, 2:4])
+    mt = D.muscle_terms(m, Tm, s[:, 2:4], s[:, 4:5])
+    assert abs(float(mt["F"][0, 0])) < 1e-9
+
+
+def test_muscle_power_balance_humanoid():
+    """For the 152-unit humanoid at a random state: the power of the generalized muscle
+    forces equals minus the sum of tension times lengthening rate (virtual work), and the
+    lengthening rate equals the central difference of the path length along qd."""
+    md = wl.mtu_humanoid()
+    m = OracleModel(md)
+    W = wl.workload("mtu", 3)
+    rng = np.random.default_rng(11)
+    s = T(W["s0"])
+    nq, nv = m.nq, m.nv
+    q = s[:, :nq]
+    qd = T(rng.normal(0.0, 0.5, (3, nv)))
+    act = T(rng.uniform(0.1, 0.9, (3, m.n_mtu)))
+    Tm = D.dynamics_terms(m, q, qd)
+    mt = D.muscle_terms(m, Tm, qd, act)
+    power = (mt["tau"] * qd).sum(1)
+    assert torch.allclose(power, -(mt["F"] * mt["Ldot"]).sum(1), rtol=1e-12, atol=1e-9)
+    eps = 1e-6
+    qp = D.integrate(m, q, qd, eps)
+    qm = D.integrate(m, q, qd, -eps)
+    Lp = D.muscle_terms(m, D.dynamics_terms(m, qp, qd), qd, act)["L"]
+    Lm = D.muscle_terms(m, D.dynamics_terms(m, qm, qd), qd, act)["L"]
+    fd = (Lp - Lm) / (2 * eps)
+    assert torch.allclose(fd, mt["Ldot"], rtol=1e-6, atol=1e-8)
+
+
+def test_activation_lag_closed_form():
+    """Explicit activation recursion with constant excitation u:
+    a_n = u + (a_0 - u) (1 - dt/tau)^n."""
+    md = wl.muscle_arm()
+    m = OracleModel(md)
+    dt = 1.0 / 240.0
+    a = T([[0.1]])
+    u = T([[0.8]])
+    for n in range(1, 40):
+        a = D.activation_step(m, a, u, dt)
+        want = 0.8 + (0.1 - 0.8) * (1.0 - dt / m.tau_act) ** n
+        assert float(a[0, 0]) == pytest.approx(want, rel=1e-13)
+
+
+def test_muscle_arm_window_adjoint_fd():
+    """Open-loop excitations on the muscle arm over 6 frames: every dL/du_t and dL/ds0
+    coordinate against central differences."""
+    md = wl.muscle_arm()
+    m = OracleModel(md)
+    h = 6
+    rng = np.random.default_rng(3)
+    s0 = np.array([[0.05, 0.3, 0.2, -0.5, 0.3], [0.0, -0.6, 0.0, 0.4, 0.7]])
+    u = rng.uniform(0.1, 0.9, (h, 2, 1))
+    critic = [(rng.normal(size=(1, 5)), np.zeros(1))]      # linear value of the observed state
+    g = oracle_window_grads(md, s0, h, None, critic, actions=u, n_total=2)
+    lay = (None, [(T(Wc), T(bc)) for Wc, bc in critic])
+
+    def loss(ds=None, du=None):
+        s = T(s0) + (T(ds) if ds is not None else 0.0)
+        return float(oracle_window(m, s, h, actions=u, n_total=2, action_offset=du, layers=lay)["loss"])
+    eps = 1e-6
+    for t in range(h):
+        for e in range(2):
+            du = np.zeros_like(u)
+            du[t, e, 0] = eps
+            fd = (loss(du=du) - loss(du=-du)) / (2 * eps)
+            assert fd == pytest.approx(g["dL_da"][t, e, 0], rel=1e-6, abs=1e-11)
+    for e in range(2):
+        for k in range(5):
+            ds = np.zeros_like(s0)
+            ds[e, k] = eps
+            fd = (loss(ds=ds) - loss(ds=-ds)) / (2 * eps)
+            assert fd == pytest.approx(g["dL_ds0"][e, k], rel=1e-6, abs=1e-11)
+
+
+def test_mtu_reward_coefficients_match_the_paper():
+    G = _golden()["mtu_reward"]
+    W = wl.workload("mtu", 1)
+    m = OracleModel(W["model"])
+    s = torch.zeros(1, W["s0"].shape[1], dtype=F64)
+    s[0, 3] = 1.0
+    a = torch.zeros(1, m.na, dtype=F64)
+    s[0, 2] = 0.84 + 0.02
+    r0 = float(reward_fn(m, s, a)[0])
+    assert r0 == pytest.approx(G["up"] + G["heading"] + G["above"] * 0.02)
+    s2 = s.clone()
+    s2[0, 2] = 0.84 + 3.0
+    assert float(reward_fn(m, s2, a)[0]) == pytest.approx(G["up"] + G["heading"] + G["above"] * G["clip_hi"])
+    s3 = s.clone()
+    s3[0, 2] = 0.84 - 0.3
+    assert float(reward_fn(m, s3, a)[0]) == pytest.approx(G["up"] + G["heading"] + G["below"] * 0.09)
+    a2 = torch.full((1, m.na), 0.5, dtype=F64)
+    assert float(reward_fn(m, s, a2)[0]) == pytest.approx(r0 + G["action"] * 0.25 * m.na)
+    assert m.n_mtu == _golden()["mtu_dims"]["muscles"] and m.na == _golden()["mtu_dims"]["actions"]
+
+
+def test_mtu_observation_layout_and_squash():
+    """Skeleton entries as in the humanoid observation (without the last action), zeros up
+    to entry 128, then the activations; excitations are (tanh + 1)/2 in (0, 1)."""
+    from oracle import squash
+    Wm = wl.workload("mtu", 2)
+    Wh = wl.workload("humanoid", 2)
+    m = OracleModel(Wm["model"])
+    mh = OracleModel(Wh["model"])
+    s = T(Wm["s0"]).clone()
+    s[:, 55:] = T(np.linspace(0.0, 1.0, 152))[None]
+    o = obs_fn(m, s)
+    sh = torch.cat([s[:, :55], torch.zeros(2, 21, dtype=F64)], 1)
+    oh = obs_fn(mh, sh)
+    assert o.shape == (2, 280)
+    assert torch.equal(o[:, :55], oh[:, :55])
+    assert torch.equal(o[:, 55:128], torch.zeros(2, 73, dtype=F64))
+    assert torch.equal(o[:, 128:], s[:, 55:])
+    y = T([[-30.0, 0.0, 30.0]])
+    u = squash(m, y)
+    assert float(u[0, 1]) == 0.5 and 0.0 <= float(u[0, 0]) < 1e-12 and 1 - 1e-12 < float(u[0, 2]) <= 1.0
+
+
+def test_bf16_rounding_matches_library_conversion_and_ties():
+    """bf16_round agrees with torch's float32 -> bfloat16 conversion (round to nearest
+    even) on random values, keeps bfloat16 values, and sends exact ties to the even
+    neighbour."""
+    from oracle import bf16_round
+    x = torch.randn(20000, dtype=F64) * 10.0 ** torch.randint(-6, 6, (20000,)).to(F64)
+    want = x.to(torch.float32).to(torch.bfloat16).to(F64)
+    assert torch.equal(bf16_round(x), want)
+    exact = want
+    assert torch.equal(bf16_round(exact), exact)
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: the even neighbour is 1
+    assert float(bf16_round(T([1.0 + 2.0 ** -8]))[0]) == 1.0
+    # 1 + 3 * 2^-8 lies halfway between 1 + 2^-7 and 1 + 2^-6: even is 1 + 2^-6
+    assert float(bf16_round(T([1.0 + 3 * 2.0 ** -8]))[0]) == 1.0 + 2.0 ** -6

@@ -1,7 +1,8 @@
 """Seeded initial states, MLP weights and named workload configurations (data only).
 
 State layout (one row per env, env-major):  s = [q (nq) | qd (nv) | a_prev (na, only
-for tasks whose observation holds the last action)].
+for tasks whose observation holds the last action) | muscle activations (n_mtu, muscle
+models only)].
 """
 import numpy as np
 
@@ -13,12 +14,16 @@ NETS = {
     "cartpole": ([64, 64], [64, 64]),
     "ant": ([128, 64], [64, 64]),
     "humanoid": ([256, 128], [128, 128]),
+    "mtu": ([400, 200], [400, 200]),
 }
-OBS_DIM = {"cartpole": 5, "ant": 37, "humanoid": 76}
+# the muscle task's observation: 55 skeleton entries, zero padding to 128, then the 152
+# activations (280)
+OBS_DIM = {"cartpole": 5, "ant": 37, "humanoid": 76, "mtu": 280}
+MTU_OBS_PAD = 128
 
 
 def state_dim(m):
-    return m["nq"] + m["nv"] + (m["na"] if m["has_last_action"] else 0)
+    return m["nq"] + m["nv"] + (m["na"] if m["has_last_action"] else 0) + m.get("n_mtu", 0)
 
 
 def initial_states(m, n_envs, seed=1):
@@ -26,7 +31,7 @@ def initial_states(m, n_envs, seed=1):
 
     CartPole: cart at 0, pole angle U(-pi, pi), velocities N(0, 0.1) (std).
     Floating-base tasks: root upright at the model's standing height, hinge angles
-    q_mean + N(0, 0.1), zero velocities, zero last action.
+    q_mean + N(0, 0.1), zero velocities, zero last action, zero muscle activations.
     """
     rng = np.random.default_rng(seed)
     n_s = state_dim(m)
@@ -63,6 +68,7 @@ WORKLOADS = {
     "cartpole": dict(model="cartpole", n_envs=16, h=32),
     "ant": dict(model="ant", n_envs=1024, h=32),
     "humanoid": dict(model="humanoid", n_envs=1024, h=32),
+    "mtu": dict(model="mtu_humanoid", n_envs=2048, h=32),
 }
 
 
