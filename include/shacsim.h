@@ -61,6 +61,7 @@ enum { SIM_JOINT_FREE = 0, SIM_JOINT_HINGE = 1, SIM_JOINT_SLIDE = 2 };
 enum { SIM_TASK_NONE = 0, SIM_TASK_CARTPOLE = 1, SIM_TASK_ANT = 2, SIM_TASK_HUMANOID = 3, SIM_TASK_MTU = 4 };
 enum { SIM_PATH_PERSISTENT = 0, SIM_PATH_PLAIN = 1, SIM_PATH_TAPE = 2 };
 enum { SIM_PREC_FP32 = 0, SIM_PREC_FP64 = 1 };
+enum { SIM_MLP_FP32 = 0, SIM_MLP_BF16 = 1 };
 
 /* Compiled limits. */
 #define SIM_MAX_JOINTS 32
@@ -156,6 +157,11 @@ typedef struct SimOptions {
   int policy_grad;               /* closed loop: 1 = the workspace also holds the scratch of the
                                     policy-parameter gradient, and sim_adjoint_window accepts
                                     dL_dtheta */
+  int mlp_precision;             /* SIM_MLP_FP32, or SIM_MLP_BF16 (FP32 path only): actor and
+                                    critic layers on the BF16 matrix cores with BF16 weights and
+                                    layer inputs and FP32 accumulation, biases and activations;
+                                    their input adjoints likewise (the output adjoint in BF16).
+                                    The dynamics stay FP32. */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;

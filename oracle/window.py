@@ -34,12 +34,30 @@ def bf16_round(x):
     return r.view(torch.float32).to(F64)
 
 
+class _BF16Linear(torch.autograd.Function):
+    """y = bf16(x) bf16(W)^T + b with exact accumulation; its input adjoint is
+    bf16(dy) bf16(W) (the output adjoint enters the transposed product in BF16 as
+    well), the weight adjoint dy^T bf16(x)."""
+
+    @staticmethod
+    def forward(ctx, x, W, b):
+        xr, Wr = bf16_round(x), bf16_round(W)
+        ctx.save_for_backward(xr, Wr)
+        return xr @ Wr.T + b
+
+    @staticmethod
+    def backward(ctx, gy):
+        xr, Wr = ctx.saved_tensors
+        return bf16_round(gy) @ Wr, gy.T @ xr, gy.sum(0)
+
+
 def mlp_forward_bf16(layers, x):
     """The MLP with BF16 weights and BF16 layer inputs and exact (float64) accumulation
-    of their products: the reference of the BF16 matrix-core MLPs."""
+    of their products: the reference of the BF16 matrix-core MLPs (FP32 biases and
+    activations)."""
     h = x
     for i, (W, b) in enumerate(layers):
-        h = bf16_round(h) @ bf16_round(W).T + b
+        h = _BF16Linear.apply(h, W, b)
         if i < len(layers) - 1:
             h = torch.nn.functional.elu(h)
     return h

@@ -41,7 +41,8 @@ class SimOptions(ctypes.Structure):
     _fields_ = [("n_envs", _i), ("horizon", _i), ("ckpt_interval", _i), ("path", _i),
                 ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
                 ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
-                ("precision", _i), ("chol_fp64_threshold", _d), ("policy_grad", _i)]
+                ("precision", _i), ("chol_fp64_threshold", _d), ("policy_grad", _i),
+                ("mlp_precision", _i)]
 
 
 class SimForwardIO(ctypes.Structure):
@@ -180,7 +181,7 @@ class Sim:
 
     def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
                  path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6,
-                 policy_grad=False):
+                 policy_grad=False, mlp_precision="fp32"):
         import torch
         self.torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -206,6 +207,7 @@ class Sim:
         o.precision = PREC[precision]
         o.chol_fp64_threshold = float(chol_fp64_threshold)
         o.policy_grad = 1 if policy_grad else 0
+        o.mlp_precision = {"fp32": 0, "bf16": 1}[mlp_precision]
         self.actor_dims = list(actor_dims) if actor_dims is not None else None
         h = _p()
         _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))

@@ -35,6 +35,7 @@ struct SimHandle {
   int ns = 0, od = 0, nq = 0, nv = 0, na = 0, substeps = 0;
   size_t elem = 4;
   size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL], wp_actor_off[SIM_MAXL], wp_critic_off[SIM_MAXL];
+  size_t bf_actor_off[SIM_MAXL][2], bf_critic_off[SIM_MAXL][2];   // BF16 forward / adjoint tiles
   size_t off_ckpt = 0, off_adj = 0, off_tape = 0, ws_bytes = 0;
   // policy-gradient scratch: hidden activations, two layer-adjoint buffers, split partials
   size_t off_th_h[SIM_MAXL], off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
@@ -250,6 +251,12 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
   if (opt->policy_grad && !opt->closed_loop) return fail(SIM_E_ARG, "policy_grad needs the closed-loop policy");
   if (m.n_mtu > 0 && opt->path == SIM_PATH_PLAIN)
     return fail(SIM_E_UNSUPPORTED, "muscle models run on the persistent and tape paths");
+  if (opt->mlp_precision != SIM_MLP_FP32 && opt->mlp_precision != SIM_MLP_BF16)
+    return fail(SIM_E_ARG, "unknown mlp_precision");
+  if (opt->mlp_precision == SIM_MLP_BF16 && opt->precision != SIM_PREC_FP32)
+    return fail(SIM_E_ARG, "BF16 MLPs run in the FP32 path");
+  if (opt->mlp_precision == SIM_MLP_BF16 && opt->policy_grad)
+    return fail(SIM_E_UNSUPPORTED, "the policy-parameter gradient runs with FP32 MLPs");
   return SIM_OK;
 }
 
@@ -281,6 +288,23 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   size_t off = 0;
   for (int l = 0; l < SIM_MAXL; ++l) {
     h->wt_actor_off[l] = h->wt_critic_off[l] = h->wp_actor_off[l] = h->wp_critic_off[l] = 0;
+    h->bf_actor_off[l][0] = h->bf_actor_off[l][1] = h->bf_critic_off[l][0] = h->bf_critic_off[l][1] = 0;
+  }
+  if (opt->mlp_precision == SIM_MLP_BF16) {
+    for (int l = 0; l < (opt->closed_loop ? opt->actor_layers : 0); ++l) {
+      int ni = opt->actor_dims[l], no = opt->actor_dims[l + 1];
+      h->bf_actor_off[l][0] = off;
+      off = align256(off + sim_bf16_tiles_bytes(no, ni));
+      h->bf_actor_off[l][1] = off;
+      off = align256(off + sim_bf16_tiles_bytes(ni, no));
+    }
+    for (int l = 0; l < opt->critic_layers; ++l) {
+      int ni = opt->critic_dims[l], no = opt->critic_dims[l + 1];
+      h->bf_critic_off[l][0] = off;
+      off = align256(off + sim_bf16_tiles_bytes(no, ni));
+      h->bf_critic_off[l][1] = off;
+      off = align256(off + sim_bf16_tiles_bytes(ni, no));
+    }
   }
   auto pad64 = [](int n) { return (size_t)((n + SIM_WAVE - 1) / SIM_WAVE * SIM_WAVE); };
   if (opt->closed_loop)
@@ -371,8 +395,14 @@ static int check_handle(SimHandle* h) {
 
 template <typename T>
 static int fill_mlp(MlpArgsT<T>& P, int nl, const int* dims, const void* const* W, const void* const* b,
-                    char* ws, const size_t* wt_off, const size_t* wp_off, const char* what) {
+                    char* ws, const size_t* wt_off, const size_t* wp_off, const size_t (*bf_off)[2], int bf16,
+                    const char* what) {
   P.nl = nl;
+  P.bf16 = bf16;
+  for (int l = 0; l < SIM_MAXL; ++l) {
+    P.Pf[l] = (bf16 && l < nl) ? reinterpret_cast<const uint16_t*>(ws + bf_off[l][0]) : nullptr;
+    P.Pb[l] = (bf16 && l < nl) ? reinterpret_cast<const uint16_t*>(ws + bf_off[l][1]) : nullptr;
+  }
   for (int l = 0; l <= SIM_MAXL; ++l) P.dims[l] = (l <= nl) ? dims[l] : 0;
   for (int l = 0; l < SIM_MAXL; ++l) { P.W[l] = nullptr; P.WT[l] = nullptr; P.b[l] = nullptr; P.src[l] = nullptr; }
   for (int l = 0; l < nl; ++l) {
@@ -389,10 +419,13 @@ template <typename T>
 static int launch_transposes(const MlpArgsT<T>& P, void* s);
 template <>
 int launch_transposes<float>(const MlpArgsT<float>& P, void* s) {
-  for (int l = 0; l < P.nl; ++l)
-    if (sim_f32::launch_prep_weights(P.src[l], const_cast<float*>(P.WT[l]), const_cast<float*>(P.W[l]),
-                                     P.dims[l + 1], P.dims[l], s))
-      return -1;
+  for (int l = 0; l < P.nl; ++l) {
+    int bad = P.bf16 ? sim_f32::launch_prep_bf16(P.src[l], const_cast<uint16_t*>(P.Pf[l]), const_cast<uint16_t*>(P.Pb[l]),
+                                                 P.dims[l + 1], P.dims[l], s)
+                     : sim_f32::launch_prep_weights(P.src[l], const_cast<float*>(P.WT[l]), const_cast<float*>(P.W[l]),
+                                                    P.dims[l + 1], P.dims[l], s);
+    if (bad) return -1;
+  }
   return 0;
 }
 template <>
@@ -418,10 +451,12 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.actions_in = static_cast<const T*>(io->actions_in);
   int rc;
   if (o.closed_loop) {
-    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off, "actor");
+    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off,
+                  h->bf_actor_off, o.mlp_precision == SIM_MLP_BF16, "actor");
     if (rc) return rc;
   }
-  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, h->wp_critic_off, "critic");
+  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off,
+                h->wp_critic_off, h->bf_critic_off, o.mlp_precision == SIM_MLP_BF16, "critic");
   if (rc) return rc;
   A.s_h = static_cast<T*>(io->s_h); A.obs = static_cast<T*>(io->obs); A.actions = static_cast<T*>(io->actions);
   A.rewards = static_cast<T*>(io->rewards); A.value = static_cast<T*>(io->value);
@@ -446,10 +481,12 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.s0 = static_cast<const T*>(io->s0);
   int rc;
   if (o.closed_loop) {
-    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off, "actor");
+    rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off,
+                  h->bf_actor_off, o.mlp_precision == SIM_MLP_BF16, "actor");
     if (rc) return rc;
   }
-  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off, h->wp_critic_off, "critic");
+  rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off,
+                h->wp_critic_off, h->bf_critic_off, o.mlp_precision == SIM_MLP_BF16, "critic");
   if (rc) return rc;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);

@@ -82,6 +82,7 @@ struct EnvLDST {
   union {
     struct {
       real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
+      uint16_t xb16[SIM_MAXHID] __attribute__((aligned(16)));   // BF16 layer operand
     };
     double M64[SIM_MAXV][SIM_MAXV];   // FP64 refactorisation (never live at the same time as the MLP)
     struct {                          // per-body muscle wrenches and their adjoint terms (substep-local)

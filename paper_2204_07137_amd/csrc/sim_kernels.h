@@ -52,7 +52,7 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   real* ob = A.obs + ((size_t)t * N + env) * od;
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
   if (A.closed_loop) {
-    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, ln);
+    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
     for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, E.y[i]);
   } else {
     const real* ai = A.actions_in + ((size_t)t * N + env) * na;
@@ -73,7 +73,7 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restr
   task_obs(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)A.h * N + env) * od;
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
-  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, ln);
+  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
   if (ln == 0) A.value[env] = E.y[0];
   real* so = A.s_h + (size_t)env * ns;
   bool ok = true;
@@ -139,11 +139,11 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
     for (int i = ln; i < L::kMtu; i += SIM_WAVE) E.act_bar[i] = RL(0.0);
   for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
   __syncthreads();
-  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, ln);
+  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
   real c = -m_pow(A.gamma, (real)A.h) * A.scale;
   if (ln == 0) E.y[0] = c;
   __syncthreads();
-  mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, ln);
+  mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
   // E.obs now holds obs_bar; E.a holds a_prev of s_h
   task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   if (A.grad_s_h) {
@@ -182,10 +182,10 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   if (A.closed_loop) {
     for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)t * N + env) * od + i];
     __syncthreads();
-    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, ln);
+    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
     for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
-    mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, ln);
+    mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
     for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
     __syncthreads();
     task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
@@ -490,7 +490,37 @@ __global__ void k_prep_weights(const real* __restrict__ W, real* __restrict__ WT
   }
 }
 
+// BF16 operand tiles of one layer (see mlp_tiles_bf16): forward tiles of W and
+// input-adjoint tiles of W^T, zero outside the matrix.
+__global__ void k_prep_bf16(const real* __restrict__ W, uint16_t* __restrict__ Pf, uint16_t* __restrict__ Pb,
+                            int no, int ni) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nf = (long)((no + 15) / 16) * ((ni + 31) / 32) * 512;
+  const long nb = (long)((ni + 15) / 16) * ((no + 31) / 32) * 512;
+  if (e < nf) {
+    const int tile = (int)(e / 512), lane = (int)(e % 512) / 8, j = (int)(e % 8);
+    const int nkt = (ni + 31) / 32;
+    const int r = (tile / nkt) * 16 + lane % 16, k = (tile % nkt) * 32 + (lane / 16) * 8 + j;
+    Pf[e] = (r < no && k < ni) ? f2bf((float)W[(size_t)r * ni + k]) : (uint16_t)0;
+  }
+  if (e < nb) {
+    const int tile = (int)(e / 512), lane = (int)(e % 512) / 8, j = (int)(e % 8);
+    const int nkt = (no + 31) / 32;
+    const int r = (tile / nkt) * 16 + lane % 16, k = (tile % nkt) * 32 + (lane / 16) * 8 + j;
+    Pb[e] = (r < ni && k < no) ? f2bf((float)W[(size_t)k * ni + r]) : (uint16_t)0;
+  }
+}
+
 // ======================================================================= launchers
+int launch_prep_bf16(const real* W, uint16_t* Pf, uint16_t* Pb, int n_out, int n_in, void* stream) {
+  const long nf = (long)((n_out + 15) / 16) * ((n_in + 31) / 32) * 512;
+  const long nb = (long)((n_in + 15) / 16) * ((n_out + 31) / 32) * 512;
+  const long n = nf > nb ? nf : nb;
+  hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, W, Pf, Pb,
+                     n_out, n_in);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prep_weights(const real* W, real* WT, real* Wp, int n_out, int n_in, void* stream) {
   int n = n_in * pad64(n_out) > n_out * pad64(n_in) ? n_in * pad64(n_out) : n_out * pad64(n_in);
   hipLaunchKernelGGL(k_prep_weights, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, W, WT, Wp, n_out, n_in);

@@ -13,6 +13,96 @@
 // compile-time chunk count and unconditional, coalesced loads.
 __host__ __device__ __forceinline__ int pad64(int n) { return (n + SIM_WAVE - 1) / SIM_WAVE * SIM_WAVE; }
 
+// ---------------------------------------------------------------- BF16 matrix-core layers
+// One environment's layer is a matrix-vector product.  It runs on the 16x16x32 BF16
+// matrix instruction with the layer input as row 0 of the A operand (the other rows are
+// zero) and 16 outputs as the columns of B, accumulating in FP32; lanes 0..15 then hold
+// the 16 outputs of the tile.  Weights are pre-packed so that every B operand is one
+// coalesced 1 KB load: lane l of a tile holds W[o0 + l % 16][k0 + 8 (l / 16) + j], j < 8.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite values)
+__host__ __device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// LDS x (n values) -> LDS BF16 operand, zero-padded to a multiple of 32
+__device__ __forceinline__ void to_bf16(const real* x, uint16_t* xb, int n, int ln) {
+  const int np = (n + 31) / 32 * 32;
+  for (int i = ln; i < np; i += SIM_WAVE) xb[i] = (i < n) ? f2bf((float)x[i]) : (uint16_t)0;
+  __syncthreads();
+}
+
+// out[r] (r < nr) = sum_k Wt[r][k] xb[k] over nk inputs, Wt in tiles of P; with the bias,
+// the ELU for hidden forward layers, or the ELU' factor from hin for the input adjoint.
+__device__ __forceinline__ void mlp_tiles_bf16(const uint16_t* __restrict__ P, const uint16_t* xb, int nk,
+                                               int nr, int ln, const real* bias, bool elu,
+                                               const real* hin, real* dst) {
+  const int nkt = (nk + 31) / 32, nrt = (nr + 15) / 16;
+  const int lk = ln >> 4;
+  for (int t0 = 0; t0 < nrt; t0 += 4) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < nkt; ++kt) {
+      bf16x8 a = *reinterpret_cast<const bf16x8*>(xb + kt * 32 + lk * 8);
+      if (ln & 15) a = bf16x8{};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (t0 + u < nrt) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(P + ((size_t)((t0 + u) * nkt + kt) * SIM_WAVE + ln) * 8);
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[u], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = (t0 + u) * 16 + ln;
+      if (ln < 16 && r < nr) {
+        real z = (real)acc[u][0];
+        if (bias) {
+          z += bias[r];
+          if (elu && z <= RL(0.0)) z = m_expm1(z);
+        } else if (hin) {
+          const real hv = hin[r];
+          z *= (hv > RL(0.0)) ? RL(1.0) : (hv + RL(1.0));
+        }
+        dst[r] = z;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void mlp_forward_bf16(const MlpArgs& P, const real* x, real* h0, real* h1,
+                                                 real* out, uint16_t* xb, int ln) {
+  const real* in = x;
+  for (int l = 0; l < P.nl; ++l) {
+    const int ni = P.dims[l], no = P.dims[l + 1];
+    real* dst = (l == P.nl - 1) ? out : ((l & 1) ? h1 : h0);
+    to_bf16(in, xb, ni, ln);
+    mlp_tiles_bf16(P.Pf[l], xb, ni, no, ln, P.b[l], l < P.nl - 1, nullptr, dst);
+    __syncthreads();
+    in = dst;
+  }
+}
+
+__device__ __forceinline__ void mlp_vjp_input_bf16(const MlpArgs& P, const real* h0, const real* h1,
+                                                   real* gout, real* gbuf, real* xbar, uint16_t* xb, int ln) {
+  const real* g = gout;
+  for (int l = P.nl - 1; l >= 0; --l) {
+    const int ni = P.dims[l], no = P.dims[l + 1];
+    real* dst = (l == 0) ? xbar : gbuf;
+    to_bf16(g, xb, no, ln);          // g is not read again: dst may alias it
+    const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
+    mlp_tiles_bf16(P.Pb[l], xb, no, ni, ln, nullptr, false, hin, dst);
+    __syncthreads();
+    g = dst;
+  }
+}
+
 template <int NCH>
 __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const real* __restrict__ bb,
                                               const real* in, real* dst, int ni, int no, bool hidden, int ln) {
@@ -60,7 +150,11 @@ __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const 
 
 // x (LDS, dims[0]) -> out (LDS, dims[nl]); hidden activations kept in h0 / h1 (<= 2 hidden)
 __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, real* h0, real* h1,
-                                            real* out, int ln) {
+                                            real* out, uint16_t* xb, int ln) {
+  if (P.bf16) {
+    mlp_forward_bf16(P, x, h0, h1, out, xb, ln);
+    return;
+  }
   const real* in = x;
   for (int l = 0; l < P.nl; ++l) {
     int ni = P.dims[l], no = P.dims[l + 1];
@@ -84,7 +178,11 @@ __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, rea
 // Given the output adjoint gout (LDS, dims[nl]) and the forward activations kept by
 // mlp_forward, writes the input adjoint to xbar (LDS, dims[0]).  Scratch: gbuf (>= max width).
 __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, const real* h1,
-                                              real* gout, real* gbuf, real* xbar, int ln) {
+                                              real* gout, real* gbuf, real* xbar, uint16_t* xb, int ln) {
+  if (P.bf16) {
+    mlp_vjp_input_bf16(P, h0, h1, gout, gbuf, xbar, xb, ln);
+    return;
+  }
   real* g = gout;
   for (int l = P.nl - 1; l >= 0; --l) {
     int ni = P.dims[l], no = P.dims[l + 1];

@@ -22,6 +22,10 @@
 // velocities, the Cholesky rows, pivots and flag), plus the frame transforms and the
 // activations for muscle models, padded to whole 1 KB blocks
 #define SIM_TAPE_REALS 2465
+// BF16 tile bytes of one layer's forward or input-adjoint operand set
+static inline size_t sim_bf16_tiles_bytes(int n_rows, int n_k) {
+  return (size_t)((n_rows + 15) / 16) * ((n_k + 31) / 32) * 64 * 8 * 2;
+}
 static inline size_t sim_tape_bytes(size_t elem, int muscles) {
   size_t n = SIM_TAPE_REALS + (muscles ? 12 * SIM_MAXJ + SIM_MAXMTU : 0);
   return (n * elem + 1023) / 1024 * 1024;
@@ -60,7 +64,11 @@ struct DevModelT {
 template <typename T>
 struct MlpArgsT {
   int nl;                      // linear layers
+  int bf16;                    // layers on the BF16 matrix cores (FP32 accumulation)
   int dims[SIM_MAXL + 1];
+  // BF16 tiles of 64 lanes x 8 values, one matrix-core operand each (workspace):
+  const uint16_t* Pf[SIM_MAXL];   // forward: [ceil(out/16)][ceil(in/32)] tiles of W
+  const uint16_t* Pb[SIM_MAXL];   // input adjoint: [ceil(in/16)][ceil(out/32)] tiles of W^T
   const T* W[SIM_MAXL];        // [out][pad64(in)] zero-padded copy (workspace)
   const T* WT[SIM_MAXL];       // [in][pad64(out)] zero-padded copy (workspace)
   const T* b[SIM_MAXL];        // [out] (caller)
@@ -133,6 +141,7 @@ struct ThetaArgsT {
   int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, void* stream); \
   int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, void* stream); \
   int launch_prep_weights(const T* W, T* WT, T* Wp, int n_out, int n_in, void* stream);   \
+  int launch_prep_bf16(const T* W, uint16_t* Pf, uint16_t* Pb, int n_out, int n_in, void* stream); \
   int launch_theta(const ThetaArgsT<T>& A, void* stream);                                  \
   int launch_group(const GroupArgsT<T>& G, int adjoint, int mtu, void* stream);            \
   }

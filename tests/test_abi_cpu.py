@@ -41,6 +41,8 @@ def _create(md, **kw):
         o.critic_dims[i] = v
     o.gamma = 0.99
     o.policy_grad = kw.get("policy_grad", 0)
+    o.mlp_precision = kw.get("mlp_precision", 0)
+    o.precision = kw.get("precision", 0)
     h = ctypes.c_void_p()
     rc = P.lib().sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h))
     return rc, P.lib().sim_last_error().decode()
@@ -84,6 +86,13 @@ def test_model_limits_rejected():
     assert rc == -1 and "policy_grad" in msg
     rc, msg = _create(md, policy_grad=2)
     assert rc == -1 and "policy_grad" in msg
+    rc, msg = _create(md, mlp_precision=1, precision=1)
+    assert rc == -1 and "BF16" in msg
+    rc, msg = _create(md, mlp_precision=3)
+    assert rc == -1 and "mlp_precision" in msg
+    mm = wl.mtu_humanoid()
+    rc, msg = _create(mm, path=1, k=1, critic=[280, 8, 1])
+    assert rc == -6 and "muscle" in msg
 
 
 def test_too_many_joints_rejected():

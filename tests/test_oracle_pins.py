@@ -817,3 +817,20 @@ def test_bf16_rounding_matches_library_conversion_and_ties():
     assert float(bf16_round(T([1.0 + 2.0 ** -8]))[0]) == 1.0
     # 1 + 3 * 2^-8 lies halfway between 1 + 2^-7 and 1 + 2^-6: even is 1 + 2^-6
     assert float(bf16_round(T([1.0 + 3 * 2.0 ** -8]))[0]) == 1.0 + 2.0 ** -6
+
+
+def test_bf16_linear_backward_is_rounded_transpose_product():
+    """The BF16 MLP's reverse: input adjoint bf16(dy) bf16(W), weight adjoint
+    dy^T bf16(x), checked on one layer against the explicit products."""
+    from oracle import bf16_round, mlp_forward_bf16
+    rng = np.random.default_rng(5)
+    W = T(rng.normal(size=(7, 5)))
+    b = T(rng.normal(size=7))
+    x = T(rng.normal(size=(3, 5))).requires_grad_(True)
+    Wg = W.clone().requires_grad_(True)
+    y = mlp_forward_bf16([(Wg, b)], x)
+    gy = T(rng.normal(size=(3, 7)))
+    y.backward(gy)
+    assert torch.equal(y.detach(), bf16_round(x.detach()) @ bf16_round(W).T + b)
+    assert torch.equal(x.grad, bf16_round(gy) @ bf16_round(W))
+    assert torch.allclose(Wg.grad, gy.T @ bf16_round(x.detach()), rtol=1e-15, atol=0)
