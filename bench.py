@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-morphology batch")
+    ap.add_argument("--no-mtu", action="store_true", help="skip the muscle-driven humanoid")
     return ap.parse_args()
 
 
@@ -116,12 +117,40 @@ def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False):
     return wall, fwd_ms, adj_ms, fw, ad
 
 
-def mixed_batch(P, wl, torch, budget_gb=48.0, steps=3):
-    """Mixed-morphology batch: 4096 CartPole + 2048 Ant + 1024 Humanoid envs, h = 32.  Each
-    model's launch configuration is picked by the autotuner within a shared workspace
-    budget, then all three go out as one graph-captured group launch; compared with the
-    per-model plain per-substep launch path on the same inputs."""
-    members = [("humanoid", 1024), ("ant", 2048), ("cartpole", 4096)]
+def mtu_window(P, wl, torch, steps=3):
+    """Muscle-driven humanoid: 2048 envs, 152 muscle-tendon units, h = 32, S = 48, FP32
+    dynamics with the actor (280-400-200-152) and critic (280-400-200-1) on the BF16
+    matrix cores, persistent path with k = 16; gradient error against the FP64 kernels
+    (FP64 dynamics and MLPs) reported, not gated."""
+    W = wl.workload("mtu")
+    N, h = W["n_envs"], W["h"]
+    od = W["obs_dim"]
+    ad_ = [od] + [w.shape[0] for w, _ in W["actor"]]
+    cd_ = [od] + [w.shape[0] for w, _ in W["critic"]]
+    sim = P.Sim(W["model"], N, h, ad_, cd_, ckpt_interval=16, mlp_precision="bf16")
+    s0 = sim._dev(W["s0"])
+    actor, critic = sim.weights(W["actor"]), sim.weights(W["critic"])
+    wall, fwd_ms, adj_ms, fw, ad = time_windows(sim, s0, actor, critic, steps, 1)
+    sim64 = P.Sim(W["model"], N, h, ad_, cd_, ckpt_interval=16, precision="fp64")
+    fw64 = sim64.forward(W["s0"], W["actor"], W["critic"])
+    ad64 = sim64.adjoint(fw64)
+    torch.cuda.synchronize()
+    return {"workload": f"muscle humanoid, 152 MTUs, {N} envs, h={h}, S=48, k=16, BF16 MFMA actor/critic",
+            "value": round(N * h / (wall / steps), 1), "unit": "env-steps/s",
+            "fwd_ms": round(float(np.mean(fwd_ms)), 3), "adj_ms": round(float(np.mean(adj_ms)), 3),
+            "err_vs_fp64": {"dL_da": grad_err(ad["dL_da"], ad64["dL_da"], 1),
+                            "dL_ds0": grad_err(ad["dL_ds0"], ad64["dL_ds0"], 0),
+                            "actions_t0_relmax": float(((fw["actions"][0].double() - fw64["actions"][0]).abs().max()
+                                                        / fw64["actions"][0].abs().max()))}}
+
+
+def mixed_batch(P, wl, torch, budget_gb=64.0, steps=3):
+    """Mixed-morphology batch: 4096 CartPole + 2048 Ant + 1024 Humanoid + 512 muscle
+    humanoid envs, h = 32.  Each model's launch configuration is picked by the autotuner
+    within a shared workspace budget, then all four go out as one graph-captured group
+    launch; compared with per-model launches of the plain per-substep path (the muscle
+    model, which has no plain path, with its own persistent launch)."""
+    members = [("humanoid", 1024), ("mtu", 512), ("ant", 2048), ("cartpole", 4096)]
     Ws, dims = [], []
     for name, n in members:
         W = wl.workload(name, n)
@@ -161,7 +190,8 @@ def mixed_batch(P, wl, torch, budget_gb=48.0, steps=3):
         run_group()
     torch.cuda.synchronize()
     tg = (time.perf_counter() - t0) / steps
-    plains = [P.Sim(W["model"], n, h, ad_, cd_, path=P.PATH_PLAIN)
+    plains = [P.Sim(W["model"], n, h, ad_, cd_,
+                    **(dict(ckpt_interval=16) if name == "mtu" else dict(path=P.PATH_PLAIN)))
               for (name, n), W, (ad_, cd_) in zip(members, Ws, dims)]
     run_plain(plains)
     torch.cuda.synchronize()
@@ -171,8 +201,9 @@ def mixed_batch(P, wl, torch, budget_gb=48.0, steps=3):
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t0) / steps
     order = [members[i][0] for i in G.order()]
-    return {"workload": "4096 cartpole + 2048 ant + 1024 humanoid envs, h=32, one graph-captured group "
-                        "launch per direction (autotuned path / k per model, 48 GB workspace budget)",
+    return {"workload": "4096 cartpole + 2048 ant + 1024 humanoid + 512 muscle-humanoid envs, h=32, one "
+                        "graph-captured group launch per direction (autotuned path / k per model, 64 GB "
+                        "workspace budget)",
             "value": round(total_envs * h / tg, 1), "unit": "env-steps/s", "ms_per_step": round(tg * 1e3, 3),
             "dispatch_order": order, "tuned": tuned, "graph_captures": G.captures(),
             "plain_per_model": {"value": round(total_envs * h / tp, 1), "ms_per_step": round(tp * 1e3, 3)},
@@ -309,6 +340,8 @@ def main():
                              "tape_speedup": round(tval / pval, 3)}
         del plain
 
+    if not args.no_mtu:
+        out["mtu"] = mtu_window(P, wl, torch)
     if not args.no_mixed:
         out["mixed"] = mixed_batch(P, wl, torch)
 
