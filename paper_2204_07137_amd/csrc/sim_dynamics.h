@@ -22,6 +22,7 @@
 struct JointRegs {
   int par, type, qa, va, depth, act, lim, npair;
   unsigned int cmask;
+  unsigned int anc0, anc1;   // root-to-frame path (see DevModelT::anc)
   real lo, hi, gear, mass, arm;
 };
 struct ContactRegs {
@@ -73,7 +74,7 @@ struct EnvLDST {
   real qb[SIM_MAXQ], qdb[SIM_MAXV], abar[MAXA];
   real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
   // topology copies for arbitrary-index lookups
-  int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ];
+  int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ], t_qa[SIM_MAXJ];
   real arm[SIM_MAXV];
   real j_off[SIM_MAXJ][3], j_ax[SIM_MAXJ][3], j_com[SIM_MAXJ][3], j_I6[SIM_MAXJ][6];
   int pairs[SIM_MAXPAIR];
@@ -103,6 +104,8 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, 
   jr.act = m->act_of_joint[j]; jr.lim = m->limited[j];
   jr.lo = m->lower[j]; jr.hi = m->upper[j]; jr.gear = m->gear[j]; jr.mass = m->mass[j];
   jr.cmask = ln < m->J ? m->cmask[j] : 0u;
+  jr.anc0 = m->anc[j][0];
+  jr.anc1 = m->anc[j][1];
   jr.arm = m->armature[m->vadr[j]];
   jr.npair = m->npair;
   for (int p = ln; p < m->npair; p += SIM_WAVE) E.pairs[p] = m->pair[p];
@@ -120,7 +123,7 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, 
   cr.body = m->cbody[c]; cr.pos = ld3(&m->cpos[3 * c]); cr.rad = m->crad[c];
   if (ln < SIM_MAXJ) {
     E.t_next_sib[ln] = m->next_sib[ln]; E.t_type[ln] = m->jtype[ln];
-    E.t_va[ln] = m->vadr[ln]; E.t_parent[ln] = m->parent[ln];
+    E.t_va[ln] = m->vadr[ln]; E.t_parent[ln] = m->parent[ln]; E.t_qa[ln] = m->qadr[ln];
     E.arm[ln] = m->armature[ln];
   }
   __syncthreads();
@@ -520,6 +523,84 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   real R[9];
   f3 p = mk3(RL(0.0), RL(0.0), RL(0.0));
   sv S = zsv(), v = zsv(), ab = zsv();
+  if (m->max_depth < SIM_WALK_DEPTH) {
+    // Every frame's lane composes its own root path with the local rotations of its
+    // ancestors (written to LDS first), so no level waits for the one above; the
+    // operations per frame are those of the level-by-level form below.
+    if (ln < J) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) E.R[ln][k] = Rot[k];
+    }
+    __syncthreads();
+    if (ln < J) {
+#pragma unroll
+      for (int d = 0; d < SIM_WALK_DEPTH; ++d) {
+        if (d > m->max_depth) break;
+        if (d <= jr.depth) {
+          const unsigned int wd = (d < 6) ? jr.anc0 : jr.anc1;
+          const int k = (int)((wd >> (5 * (d % 6))) & 31u);
+          const int tk = E.t_type[k];
+          const int vk = E.t_va[k];
+          if (tk == J_FREE) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) R[i] = E.R[k][i];
+            f3 vl = mk3(E.qd[vk], E.qd[vk + 1], E.qd[vk + 2]);
+            f3 w = mk3(E.qd[vk + 3], E.qd[vk + 4], E.qd[vk + 5]);
+            v = mksv(w, vl);
+            ab = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), add3(mk3(RL(0.0), RL(0.0), g), cross3(vl, w)));
+          } else {
+            real Rp[9];
+            f3 pp;
+            sv vp, ap;
+            if (d > 0) {
+#pragma unroll
+              for (int i = 0; i < 9; ++i) Rp[i] = R[i];
+              pp = p;
+              vp = v;
+              ap = ab;
+            } else {
+#pragma unroll
+              for (int i = 0; i < 9; ++i) Rp[i] = (i % 4 == 0) ? RL(1.0) : RL(0.0);
+              pp = mk3(RL(0.0), RL(0.0), RL(0.0));
+              vp = zsv();
+              ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+            }
+            f3 sh = mv3(Rp, ld3(E.j_ax[k]));
+            if (tk == J_HINGE) {
+              real Rl[9];
+#pragma unroll
+              for (int i = 0; i < 9; ++i) Rl[i] = E.R[k][i];
+#pragma unroll
+              for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                  R[3 * r + c] = Rp[3 * r] * Rl[c] + Rp[3 * r + 1] * Rl[3 + c] + Rp[3 * r + 2] * Rl[6 + c];
+              p = add3(pp, mv3(Rp, ld3(E.j_off[k])));
+              S = mksv(sh, cross3(p, sh));
+            } else {
+#pragma unroll
+              for (int i = 0; i < 9; ++i) R[i] = Rp[i];
+              p = add3(add3(pp, mv3(Rp, ld3(E.j_off[k]))), scl3(sh, E.q[E.t_qa[k]]));
+              S = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
+            }
+            sv u = sclsv(S, E.qd[vk]);
+            v = addsv(vp, u);
+            ab = addsv(ap, crm(v, u));
+          }
+        }
+      }
+    }
+    __syncthreads();   // every lane has read the local rotations
+    if (ln < J) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) E.R[ln][k] = R[k];
+      st3(E.p[ln], p);
+      stsv(E.S[ln], S);
+      stsv(E.v[ln], v);
+      stsv(E.ab[ln], ab);
+    }
+    __syncthreads();
+  } else {
   for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
     if (jr.depth == lvl) {
       if (jr.type == J_FREE) {
@@ -573,6 +654,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       stsv(E.ab[ln], ab);
     }
     __syncthreads();
+  }
   }
   // ---- contacts (lane = contact)
   if (ln < nc) {
@@ -853,7 +935,33 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(E.W[ln], W);
   }
   __syncthreads();
-  {
+  if (m->max_depth < SIM_WALK_DEPTH) {
+    // each frame sums the local terms along its root path, root first (the additions of
+    // the edge-by-edge form, in the same order)
+    sv As = zsv(), Ws = zsv();
+    if (ln < J) {
+#pragma unroll
+      for (int d = 0; d < SIM_WALK_DEPTH; ++d) {
+        if (d > m->max_depth) break;
+        if (d <= jr.depth) {
+          const unsigned int wd = (d < 6) ? jr.anc0 : jr.anc1;
+          const int k = (int)((wd >> (5 * (d % 6))) & 31u);
+          if (d == 0) {
+            As = ldsv(E.A[k]);
+            Ws = ldsv(E.W[k]);
+          } else {
+            As = addsv(ldsv(E.A[k]), As);
+            Ws = addsv(ldsv(E.W[k]), Ws);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (ln < J) {
+      stsv(E.A[ln], As);
+      stsv(E.W[ln], Ws);
+    }
+  } else {
     real* col = (ln < 6) ? &E.A[0][ln] : &E.W[0][ln < 12 ? ln - 6 : 0];
     for (int j = 1; j < J; ++j) {
       int p = __builtin_amdgcn_readlane(jr.par, j);

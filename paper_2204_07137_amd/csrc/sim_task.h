@@ -8,9 +8,10 @@
 
 
 // The library keeps two zero-padded copies of every weight matrix in its workspace:
-// WT [in][out_pad] for the forward (lane = output) and W [out][in_pad] for the input
-// adjoint (lane = input), pad = next multiple of 64, so that the inner loops have a
-// compile-time chunk count and unconditional, coalesced loads.
+// WT [in][out_pad] for the forward (each lane owns out_pad/64 consecutive outputs) and
+// W [out][in_pad] for the input adjoint (each lane owns in_pad/64 consecutive inputs),
+// pad = next multiple of 64, so that the inner loops have a compile-time block size and
+// unconditional, coalesced vector loads.
 __host__ __device__ __forceinline__ int pad64(int n) { return (n + SIM_WAVE - 1) / SIM_WAVE * SIM_WAVE; }
 
 // ---------------------------------------------------------------- BF16 matrix-core layers
@@ -103,6 +104,26 @@ __device__ __forceinline__ void mlp_vjp_input_bf16(const MlpArgs& P, const real*
   }
 }
 
+// NCH consecutive weights of one lane as one vector load where the width allows
+// (16 or 8 bytes, aligned because rows are padded to 64 * NCH values).
+template <int NCH>
+__device__ __forceinline__ void load_lane_block(const real* __restrict__ p, real* w) {
+  if constexpr (NCH == 4 && sizeof(real) == 4) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const v4*>(p);
+    w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
+  } else if constexpr (NCH == 2) {
+    typedef real v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *reinterpret_cast<const v2*>(p);
+    w[0] = v[0]; w[1] = v[1];
+  } else {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) w[c] = p[c];
+  }
+}
+
+// Each lane owns NCH consecutive outputs (rows padded to 64 * NCH), so a weight row is one
+// coalesced vector load per lane; 16 input rows are kept in flight.
 template <int NCH>
 __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const real* __restrict__ bb,
                                               const real* in, real* dst, int ni, int no, bool hidden, int ln) {
@@ -110,19 +131,21 @@ __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const
   real acc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    int o = c * SIM_WAVE + ln;
+    const int o = ln * NCH + c;
     acc[c] = (o < no) ? bb[o] : RL(0.0);
   }
-#pragma unroll 8
+  const real* base = WT + ln * NCH;
+#pragma unroll 16
   for (int i = 0; i < ni; ++i) {
-    real xi = in[i];
-    const real* row = WT + (size_t)i * nop + ln;
+    const real xi = in[i];
+    real w[NCH];
+    load_lane_block<NCH>(base + (size_t)i * nop, w);
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) acc[c] = m_fma(row[c * SIM_WAVE], xi, acc[c]);
+    for (int c = 0; c < NCH; ++c) acc[c] = m_fma(w[c], xi, acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    int o = c * SIM_WAVE + ln;
+    const int o = ln * NCH + c;
     if (o < no) {
       real z = acc[c];
       dst[o] = (hidden && z <= RL(0.0)) ? m_expm1(z) : z;
@@ -130,6 +153,7 @@ __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const
   }
 }
 
+// input adjoint of one layer: lane owns NCH consecutive inputs
 template <int NCH>
 __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const real* g, real* acc_out,
                                               int ni, int no, int ln) {
@@ -137,12 +161,14 @@ __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const 
   real acc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc[c] = RL(0.0);
-#pragma unroll 8
+  const real* base = W + ln * NCH;
+#pragma unroll 16
   for (int o = 0; o < no; ++o) {
-    real go = g[o];
-    const real* row = W + (size_t)o * nip + ln;
+    const real go = g[o];
+    real w[NCH];
+    load_lane_block<NCH>(base + (size_t)o * nip, w);
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) acc[c] = m_fma(row[c * SIM_WAVE], go, acc[c]);
+    for (int c = 0; c < NCH; ++c) acc[c] = m_fma(w[c], go, acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc_out[c] = acc[c];
@@ -200,10 +226,11 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
     }
     __syncthreads();   // every lane has read g before dst (which may alias g) is written
     const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
+    const int nch = pad64(ni) / SIM_WAVE;
 #pragma unroll
     for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
-      int i = c * SIM_WAVE + ln;
-      if (i < ni) {
+      const int i = ln * nch + c;
+      if (c < nch && i < ni) {
         real v = acc[c];
         if (hin) {
           real hv = hin[i];
