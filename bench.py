@@ -29,6 +29,36 @@ METRIC = "env-steps/s fwd+adjoint (h=32), 21-DOF humanoid ×1024 envs; grad err 
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 FP32_VALU_PEAK_TFLOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_GHZ / 1e3   # non-packed FMA
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_window_kernels_humanoid1024_k4.json")
+
+
+def kernel_source_hash():
+    """SHA-256 over the kernel sources and the C-ABI header (relative path + bytes, sorted)."""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2204_07137_amd", "csrc", "*.h"))
+                   + glob.glob(os.path.join(ROOT, "paper_2204_07137_amd", "csrc", "*.hip"))
+                   + glob.glob(os.path.join(ROOT, "include", "*.h")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def adjoint_traffic(n_envs, k):
+    """HBM bytes per k_window_adj launch from the profiler's FETCH_SIZE / WRITE_SIZE passes
+    (scaled by the copy-kernel calibration), or None when the record is for another
+    workload or the kernel sources have changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if n_envs != 1024 or k != 4 or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(rec["bytes_per_launch"])
 
 
 def substep_flops(md):
@@ -281,7 +311,8 @@ def main():
     achieved = adj_launch_flops / adj_avg_s / 1e12
     roof = {"bound": "alu", "kernel": "k_window_adj", "achieved": round(achieved, 4),
             "peak": round(FP32_VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 5), "traffic": None,
+            "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 5), "traffic": adjoint_traffic(N, args.k),
+            "traffic_unit": "bytes per launch, profiler FETCH_SIZE + WRITE_SIZE scaled by a copy of known size",
             "flops_per_env_step": {"adjoint_kernel": adj_flops_env_step, "forward_kernel": fwd_flops_env_step},
             "avg_ms": {"k_window_adj": round(float(np.mean(adj_ms)), 3),
                        "k_window_fwd": round(float(np.mean(fwd_ms)), 3)}}
