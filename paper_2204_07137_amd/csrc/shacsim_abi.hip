@@ -70,8 +70,6 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   for (int i = 0; i < SIM_MAXV; ++i) d.armature[i] = (T)s.armature[i];
   for (int j = 0; j < SIM_MAXJ; ++j) {
     d.cmask[j] = s.cmask[j];
-    d.anc[j][0] = s.anc[j][0];
-    d.anc[j][1] = s.anc[j][1];
   }
   d.npair = s.npair;
   for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
@@ -199,14 +197,6 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
   m.task = md->task; m.floating = (m.jtype[0] == J_FREE) ? 1 : 0;
   m.has_last_action = md->has_last_action ? 1 : 0;
   m.substeps = md->substeps; m.max_depth = maxd;
-  for (int j = 0; j < J; ++j) {
-    m.anc[j][0] = m.anc[j][1] = 0u;
-    if (maxd < SIM_WALK_DEPTH)
-      for (int k = j; k >= 0; k = m.parent[k]) {
-        const int d = m.depth[k];
-        m.anc[j][d / 6] |= (unsigned int)k << (5 * (d % 6));
-      }
-  }
   m.dt_sub = md->dt / md->substeps;
   m.g = md->gravity; m.kn = md->kn; m.kd = md->kd; m.kt = md->kt; m.mu = md->mu; m.klim = md->klim;
   m.ns = nq + nv + (m.has_last_action ? m.na : 0) + m.n_mtu;

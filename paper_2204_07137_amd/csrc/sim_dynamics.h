@@ -22,7 +22,6 @@
 struct JointRegs {
   int par, type, qa, va, depth, act, lim, npair;
   unsigned int cmask;
-  unsigned int anc0, anc1;   // root-to-frame path (see DevModelT::anc)
   real lo, hi, gear, mass, arm;
 };
 struct ContactRegs {
@@ -104,8 +103,6 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, 
   jr.act = m->act_of_joint[j]; jr.lim = m->limited[j];
   jr.lo = m->lower[j]; jr.hi = m->upper[j]; jr.gear = m->gear[j]; jr.mass = m->mass[j];
   jr.cmask = ln < m->J ? m->cmask[j] : 0u;
-  jr.anc0 = m->anc[j][0];
-  jr.anc1 = m->anc[j][1];
   jr.arm = m->armature[m->vadr[j]];
   jr.npair = m->npair;
   for (int p = ln; p < m->npair; p += SIM_WAVE) E.pairs[p] = m->pair[p];
@@ -310,13 +307,62 @@ __device__ __forceinline__ double chol64_solve(L& E, int ln, double b) {
 
 // --------------------------------------------------------------- subtree sums
 // Adds every frame's row of a table into its parent's row, children before parents
-// (frames are listed parents first); each active lane owns one column.  The parent index
-// is broadcast from the lane that holds it; the LDS executes one wavefront's accesses in
-// order, so a parent updated by an earlier edge is read back correctly without a wait.
+// (frames are listed parents first); each active lane owns one column.  The column is held
+// in registers during the walk: the parent index is the same on every lane (broadcast
+// from the lane that holds it), so the indexed register access moves no memory and the
+// walk carries no LDS round trip per edge.  The additions and their order are those of
+// the edge list, so the sums do not depend on how they are stored.
 __device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active, int J, int par_reg) {
-  for (int j = J - 1; j >= 1; --j) {
-    int p = __builtin_amdgcn_readlane(par_reg, j);
-    if (active && p >= 0) col[p * stride] += col[j * stride];
+  real r[SIM_MAXJ];
+  if (active) {
+    // every table has SIM_MAXJ rows; rows >= J are carried through untouched
+#pragma unroll
+    for (int j = 0; j < SIM_MAXJ; ++j) r[j] = col[j * stride];
+  }
+#pragma unroll
+  for (int j = SIM_MAXJ - 1; j >= 1; --j) {
+    if (j < J) {
+      const int p = __builtin_amdgcn_readlane(par_reg, j);
+      if (p >= 0) r[p] += r[j];
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < SIM_MAXJ; ++j) col[j * stride] = r[j];
+  }
+}
+
+// Sum of a spatial vector over each frame's root path by pointer jumping: a round adds the
+// partial sum of the frame the link names and takes over its link (ceil(log2(depth + 1))
+// rounds).  Values move between lanes by wavefront permutes, so every lane must be active.
+__device__ __forceinline__ sv pull_sv(sv x, int src) {
+  return mksv(mk3(pull(x.a.x, src), pull(x.a.y, src), pull(x.a.z, src)),
+              mk3(pull(x.l.x, src), pull(x.l.y, src), pull(x.l.z, src)));
+}
+__device__ __forceinline__ sv path_sum(sv x, int link, int rounds) {
+  for (int r = 0; r < rounds; ++r) {
+    const int src = link >= 0 ? link : (int)threadIdx.x;
+    const sv y = pull_sv(x, src);
+    const int nl = pull(link, src);
+    if (link >= 0) {
+      x = addsv(y, x);
+      link = nl;
+    }
+  }
+  return x;
+}
+// the same for two vectors over the same links
+__device__ __forceinline__ void path_sum2(sv& x, sv& z, int link, int rounds) {
+  for (int r = 0; r < rounds; ++r) {
+    const int src = link >= 0 ? link : (int)threadIdx.x;
+    const sv yx = pull_sv(x, src);
+    const sv yz = pull_sv(z, src);
+    const int nl = pull(link, src);
+    if (link >= 0) {
+      x = addsv(yx, x);
+      z = addsv(yz, z);
+      link = nl;
+    }
   }
 }
 
@@ -521,141 +567,80 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     }
   }
   real R[9];
-  f3 p = mk3(RL(0.0), RL(0.0), RL(0.0));
-  sv S = zsv(), v = zsv(), ab = zsv();
-  if (m->max_depth < SIM_WALK_DEPTH) {
-    // Every frame's lane composes its own root path with the local rotations of its
-    // ancestors (written to LDS first), so no level waits for the one above; the
-    // operations per frame are those of the level-by-level form below.
-    if (ln < J) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) E.R[ln][k] = Rot[k];
+  f3 p;
+  sv S = zsv(), v, ab;
+  int rounds = 0;
+  while ((1 << rounds) <= m->max_depth) ++rounds;
+  {
+    // Frame transforms by pointer jumping.  Each frame starts from its transform relative
+    // to its parent (rotation Rot, translation t) and a link to the parent; a round
+    // composes the frame's partial path with the partial path of the frame its link names
+    // and takes over that frame's link, so after ceil(log2(max_depth + 1)) rounds every
+    // frame holds its whole root path.  A round's values come from the other lanes'
+    // registers before the round (wavefront permutes).
+    f3 t = mk3(RL(0.0), RL(0.0), RL(0.0));
+    if (ln < J && jr.type != J_FREE) {
+      t = ld3(E.j_off[ln]);
+      if (jr.type == J_SLIDE) t = add3(t, scl3(ld3(E.j_ax[ln]), qj));
     }
-    __syncthreads();
-    if (ln < J) {
 #pragma unroll
-      for (int d = 0; d < SIM_WALK_DEPTH; ++d) {
-        if (d > m->max_depth) break;
-        if (d <= jr.depth) {
-          const unsigned int wd = (d < 6) ? jr.anc0 : jr.anc1;
-          const int k = (int)((wd >> (5 * (d % 6))) & 31u);
-          const int tk = E.t_type[k];
-          const int vk = E.t_va[k];
-          if (tk == J_FREE) {
+    for (int k = 0; k < 9; ++k) R[k] = (ln < J) ? Rot[k] : ((k % 4 == 0) ? RL(1.0) : RL(0.0));
+    p = t;
+    int link = (ln < J) ? jr.par : -1;
+    for (int r = 0; r < rounds; ++r) {
+      const int src = link >= 0 ? link : ln;
+      real Ra[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) R[i] = E.R[k][i];
-            f3 vl = mk3(E.qd[vk], E.qd[vk + 1], E.qd[vk + 2]);
-            f3 w = mk3(E.qd[vk + 3], E.qd[vk + 4], E.qd[vk + 5]);
-            v = mksv(w, vl);
-            ab = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), add3(mk3(RL(0.0), RL(0.0), g), cross3(vl, w)));
-          } else {
-            real Rp[9];
-            f3 pp;
-            sv vp, ap;
-            if (d > 0) {
+      for (int k = 0; k < 9; ++k) Ra[k] = pull(R[k], src);
+      const f3 pa = mk3(pull(p.x, src), pull(p.y, src), pull(p.z, src));
+      const int nl = pull(link, src);
+      if (link >= 0) {
+        real Rn[9];
 #pragma unroll
-              for (int i = 0; i < 9; ++i) Rp[i] = R[i];
-              pp = p;
-              vp = v;
-              ap = ab;
-            } else {
+        for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-              for (int i = 0; i < 9; ++i) Rp[i] = (i % 4 == 0) ? RL(1.0) : RL(0.0);
-              pp = mk3(RL(0.0), RL(0.0), RL(0.0));
-              vp = zsv();
-              ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
-            }
-            f3 sh = mv3(Rp, ld3(E.j_ax[k]));
-            if (tk == J_HINGE) {
-              real Rl[9];
+          for (int c = 0; c < 3; ++c)
+            Rn[3 * rr + c] = Ra[3 * rr] * R[c] + Ra[3 * rr + 1] * R[3 + c] + Ra[3 * rr + 2] * R[6 + c];
+        p = add3(pa, mv3(Ra, p));
 #pragma unroll
-              for (int i = 0; i < 9; ++i) Rl[i] = E.R[k][i];
-#pragma unroll
-              for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                  R[3 * r + c] = Rp[3 * r] * Rl[c] + Rp[3 * r + 1] * Rl[3 + c] + Rp[3 * r + 2] * Rl[6 + c];
-              p = add3(pp, mv3(Rp, ld3(E.j_off[k])));
-              S = mksv(sh, cross3(p, sh));
-            } else {
-#pragma unroll
-              for (int i = 0; i < 9; ++i) R[i] = Rp[i];
-              p = add3(add3(pp, mv3(Rp, ld3(E.j_off[k]))), scl3(sh, E.q[E.t_qa[k]]));
-              S = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
-            }
-            sv u = sclsv(S, E.qd[vk]);
-            v = addsv(vp, u);
-            ab = addsv(ap, crm(v, u));
-          }
-        }
+        for (int k = 0; k < 9; ++k) R[k] = Rn[k];
+        link = nl;
       }
     }
-    __syncthreads();   // every lane has read the local rotations
-    if (ln < J) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) E.R[ln][k] = R[k];
-      st3(E.p[ln], p);
-      stsv(E.S[ln], S);
-      stsv(E.v[ln], v);
-      stsv(E.ab[ln], ab);
-    }
-    __syncthreads();
-  } else {
-  for (int lvl = 0; lvl <= m->max_depth; ++lvl) {
-    if (jr.depth == lvl) {
-      if (jr.type == J_FREE) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) R[k] = Rot[k];
-        f3 vl = mk3(E.qd[jr.va], E.qd[jr.va + 1], E.qd[jr.va + 2]);
-        f3 w = mk3(E.qd[jr.va + 3], E.qd[jr.va + 4], E.qd[jr.va + 5]);
-        v = mksv(w, vl);
-        ab = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), add3(mk3(RL(0.0), RL(0.0), g), cross3(vl, w)));
-      } else {
-        real Rp[9];
-        f3 pp;
-        sv vp, ap;
-        if (jr.par >= 0) {
-#pragma unroll
-          for (int k = 0; k < 9; ++k) Rp[k] = E.R[jr.par][k];
-          pp = ld3(E.p[jr.par]);
-          vp = ldsv(E.v[jr.par]);
-          ap = ldsv(E.ab[jr.par]);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? RL(1.0) : RL(0.0);
-          pp = mk3(RL(0.0), RL(0.0), RL(0.0));
-          vp = zsv();
-          ap = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
-        }
-        f3 sh = mv3(Rp, ld3(E.j_ax[ln]));
-        if (jr.type == J_HINGE) {
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-              R[3 * r + c] = Rp[3 * r] * Rot[c] + Rp[3 * r + 1] * Rot[3 + c] + Rp[3 * r + 2] * Rot[6 + c];
-          p = add3(pp, mv3(Rp, ld3(E.j_off[ln])));
-          S = mksv(sh, cross3(p, sh));
-        } else {
-#pragma unroll
-          for (int k = 0; k < 9; ++k) R[k] = Rp[k];
-          p = add3(add3(pp, mv3(Rp, ld3(E.j_off[ln]))), scl3(sh, qj));
-          S = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
-        }
-        sv u = sclsv(S, qdj);
-        v = addsv(vp, u);
-        ab = addsv(ap, crm(v, u));
-      }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) E.R[ln][k] = R[k];
-      st3(E.p[ln], p);
-      stsv(E.S[ln], S);
-      stsv(E.v[ln], v);
-      stsv(E.ab[ln], ab);
-    }
-    __syncthreads();
   }
+  // motion subspaces: a hinge turns about its own axis, so its world axis is R ax either
+  // side of the joint rotation; a slide keeps the parent's rotation
+  sv u = zsv(), c = zsv();
+  if (ln < J) {
+    if (jr.type == J_FREE) {
+      f3 vl = mk3(E.qd[jr.va], E.qd[jr.va + 1], E.qd[jr.va + 2]);
+      f3 w = mk3(E.qd[jr.va + 3], E.qd[jr.va + 4], E.qd[jr.va + 5]);
+      u = mksv(w, vl);
+      c = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), add3(mk3(RL(0.0), RL(0.0), g), cross3(vl, w)));
+    } else {
+      f3 sh = mv3(R, ld3(E.j_ax[ln]));
+      S = (jr.type == J_HINGE) ? mksv(sh, cross3(p, sh)) : mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), sh);
+      u = sclsv(S, qdj);
+    }
   }
+  // velocities v = sum of S qd along the root path, then bias accelerations
+  // ab = sum of v x (S qd) along the path (plus gravity at the root), both by pointer
+  // jumping over the same links
+  v = path_sum(u, (ln < J) ? jr.par : -1, rounds);
+  if (ln < J && jr.type != J_FREE) {
+    c = crm(v, u);
+    if (jr.par < 0) c = addsv(c, mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g)));
+  }
+  ab = path_sum(c, (ln < J) ? jr.par : -1, rounds);
+  if (ln < J) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) E.R[ln][k] = R[k];
+    st3(E.p[ln], p);
+    stsv(E.S[ln], S);
+    stsv(E.v[ln], v);
+    stsv(E.ab[ln], ab);
+  }
+  __syncthreads();
   // ---- contacts (lane = contact)
   if (ln < nc) {
     int b = cr.body;
@@ -914,9 +899,9 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
   __syncthreads();
   // actuation adjoint and full accelerations / virtual velocities, level by level
   if (ln < J && jr.act >= 0) E.abar[jr.act] += jr.gear * E.lam[jr.va];
-  // local terms (lane = joint), then top-down prefix sums over the tree edges
+  // local terms (lane = joint), then their sums along each root path by pointer jumping
+  sv A = zsv(), W = zsv();
   if (ln < J) {
-    sv A, W;
     if (jr.type == J_FREE) {
       int va = jr.va;
       sv ab = ldsv(E.ab[ln]);
@@ -931,42 +916,15 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
       W = sclsv(S, E.lam[jr.va]);
       if (jr.par < 0) A = addsv(A, mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g)));
     }
+  }
+  {
+    int rounds = 0;
+    while ((1 << rounds) <= m->max_depth) ++rounds;
+    path_sum2(A, W, (ln < J) ? jr.par : -1, rounds);
+  }
+  if (ln < J) {
     stsv(E.A[ln], A);
     stsv(E.W[ln], W);
-  }
-  __syncthreads();
-  if (m->max_depth < SIM_WALK_DEPTH) {
-    // each frame sums the local terms along its root path, root first (the additions of
-    // the edge-by-edge form, in the same order)
-    sv As = zsv(), Ws = zsv();
-    if (ln < J) {
-#pragma unroll
-      for (int d = 0; d < SIM_WALK_DEPTH; ++d) {
-        if (d > m->max_depth) break;
-        if (d <= jr.depth) {
-          const unsigned int wd = (d < 6) ? jr.anc0 : jr.anc1;
-          const int k = (int)((wd >> (5 * (d % 6))) & 31u);
-          if (d == 0) {
-            As = ldsv(E.A[k]);
-            Ws = ldsv(E.W[k]);
-          } else {
-            As = addsv(ldsv(E.A[k]), As);
-            Ws = addsv(ldsv(E.W[k]), Ws);
-          }
-        }
-      }
-    }
-    __syncthreads();
-    if (ln < J) {
-      stsv(E.A[ln], As);
-      stsv(E.W[ln], Ws);
-    }
-  } else {
-    real* col = (ln < 6) ? &E.A[0][ln] : &E.W[0][ln < 12 ? ln - 6 : 0];
-    for (int j = 1; j < J; ++j) {
-      int p = __builtin_amdgcn_readlane(jr.par, j);
-      if (ln < 12 && p >= 0) col[j * 6] += col[p * 6];
-    }
   }
   __syncthreads();
   // ---- contact adjoints (lane = contact)

@@ -73,6 +73,19 @@ __device__ __forceinline__ double rdl(double x, int l) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// lane src's value, src chosen per lane (a wavefront-wide permute through the LDS
+// crossbar: no LDS memory, no barrier); every lane of the wavefront must be active
+__device__ __forceinline__ int pull(int x, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, x); }
+__device__ __forceinline__ float pull(float x, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double pull(double x, int src) {
+  long long v = __builtin_bit_cast(long long, x);
+  int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(v & 0xffffffffll));
+  int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(v >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // ------------------------------------------------------------------ small vector math
 struct f3 { real x, y, z; };
 __device__ __forceinline__ f3 mk3(real a, real b, real c) { f3 r; r.x = a; r.y = b; r.z = c; return r; }

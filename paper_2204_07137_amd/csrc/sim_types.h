@@ -17,7 +17,6 @@
 #define SIM_MAXHID 512   // MLP width
 #define SIM_MAXL 4       // MLP linear layers
 #define SIM_MAXPAIR 576  // (frame, ancestor-or-self) pairs of the mass matrix, 9 rounds of 64 lanes
-#define SIM_WALK_DEPTH 12  // trees at most this deep (levels) are traversed frame by frame along root paths
 // linearisation tape of one substep: SIM_TAPE_REALS values (pre-substep state, frame
 // screws, velocities, bias accelerations and inertias, contact data, accelerations, new
 // velocities, the Cholesky rows, pivots and flag), plus the frame transforms and the
@@ -51,9 +50,6 @@ struct DevModelT {
   int cbody[SIM_MAXC];
   T cpos[SIM_MAXC * 3], crad[SIM_MAXC];
   unsigned int cmask[SIM_MAXJ];   // bit c set when contact c belongs to frame j
-  // root-to-frame path of frame j (depth[j] + 1 frames, root first), 5 bits per frame,
-  // six per word (trees of at most SIM_WALK_DEPTH levels)
-  unsigned int anc[SIM_MAXJ][2];
   // mass-matrix entries M[va_k][va_i] for every non-root frame i and every k in its
   // ancestors-or-self: packed i | k << 5 | va_i << 10 | va_k << 15 | (k is FREE) << 20 | 1 << 21
   int npair;
