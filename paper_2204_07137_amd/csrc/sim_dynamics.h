@@ -123,7 +123,7 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, 
     E.t_va[ln] = m->vadr[ln]; E.t_parent[ln] = m->parent[ln]; E.t_qa[ln] = m->qadr[ln];
     E.arm[ln] = m->armature[ln];
   }
-  __syncthreads();
+  wsync();
 }
 
 // --------------------------------------------------------------- contact law
@@ -270,20 +270,20 @@ __device__ __forceinline__ void chol64_factor(L& E, int nv, int ln) {
     for (int k = 0; k < NV; ++k)
       E.M64[ln][k] = (ln < nv && k < nv) ? (double)E.M[ln][k] : (ln == k ? 1.0 : 0.0);
   }
-  __syncthreads();
+  wsync();
 #pragma unroll 1
   for (int k = 0; k < NV; ++k) {
     double piv = E.M64[k][k];
     double d = sqrt(piv);
     double lk = (ln > k && ln < NV) ? E.M64[ln][k] / d : 0.0;
-    __syncthreads();
+    wsync();
     if (ln == k) E.M64[k][k] = d;
     if (ln > k && ln < NV) E.M64[ln][k] = lk;
-    __syncthreads();
+    wsync();
     if (ln > k && ln < NV)
 #pragma unroll 1
       for (int j = k + 1; j <= ln; ++j) E.M64[ln][j] -= lk * E.M64[j][k];
-    __syncthreads();
+    wsync();
   }
 }
 
@@ -440,7 +440,7 @@ __device__ __forceinline__ void lds_add6(real* dst, sv w) {
 template <class L>
 __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E, int ln) {
   for (int i = ln; i < SIM_MAXJ * 6; i += SIM_WAVE) (&E.Fm[0][0])[i] = RL(0.0);
-  __syncthreads();
+  wsync();
   for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
     const int i = i0 + ln;
     if (i < m->n_mtu) {
@@ -455,7 +455,7 @@ __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E
       }
     }
   }
-  __syncthreads();
+  wsync();
 }
 
 // Adjoint of the muscle forces in lambda^T ID = ... - sum_p nu_p . f_p (nu_p the virtual
@@ -471,7 +471,7 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
     (&E.mAb[0][0])[i] = RL(0.0);
     (&E.mVb[0][0])[i] = RL(0.0);
   }
-  __syncthreads();
+  wsync();
   const DevModel* __restrict__ T = m->tab;
   for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
     const int i = i0 + ln;
@@ -526,7 +526,7 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
       }
     }
   }
-  __syncthreads();
+  wsync();
 }
 
 template <int NV, class L>
@@ -540,7 +540,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   if (ln < 3) E.O[ln] = m->floating ? E.q[ln] : RL(0.0);
   // clear M
   for (int i = ln; i < SIM_MAXV * (SIM_MAXV + 1); i += SIM_WAVE) (&E.M[0][0])[i] = RL(0.0);
-  __syncthreads();
+  wsync();
   // ---- local joint rotations (all lanes at once), then kinematics, velocities and bias
   // accelerations level by level; each lane keeps its own frame's results in registers
   real Rot[9];
@@ -640,7 +640,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     stsv(E.v[ln], v);
     stsv(E.ab[ln], ab);
   }
-  __syncthreads();
+  wsync();
   // ---- contacts (lane = contact)
   if (ln < nc) {
     int b = cr.body;
@@ -656,7 +656,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     st3(E.cvel[ln], vpt);
     E.cdep[ln] = d;
   }
-  __syncthreads();
+  wsync();
   if constexpr (L::kMtu > 0) muscle_wrenches(m, E, ln);
   // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
   if (ln < J) {
@@ -710,13 +710,13 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       for (int k = 0; k < 6; ++k) E.vec[jr.va + k] = RL(0.0);
     }
   }
-  __syncthreads();
+  wsync();
   // ---- subtree sums of forces (6 columns) and composite inertias (10 columns)
   {
     real* col = (ln < 6) ? &E.F[0][ln] : &E.Ic[0][ln < 16 ? ln - 6 : 0];
     tree_sum_cols(col, (ln < 6) ? 6 : 10, ln < 16, J, jr.par);
   }
-  __syncthreads();
+  wsync();
   // ---- bias into rhs; composite-inertia columns F_i = Ic_i S_i; root block of M
   if (ln < J) {
     sv F = ldsv(E.F[ln]);
@@ -751,7 +751,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       stsv(E.Fi[ln], iapply(Ic, S));
     }
   }
-  __syncthreads();
+  wsync();
   // ---- CRBA entries M[va_k][va_i] = S_k . F_i, one (frame, ancestor) pair per lane and round
   for (int r = 0; r * SIM_WAVE < jr.npair; ++r) {
     int pi = r * SIM_WAVE + ln;
@@ -772,7 +772,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       }
     }
   }
-  __syncthreads();
+  wsync();
   // ---- Cholesky and solve (lane = DOF); rows >= nv padded with the identity
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -788,12 +788,12 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     chol64_factor<NV>(E, nv, ln);
     x = (real)chol64_solve<NV>(E, ln, (double)b);
   } else {
-    __syncthreads();
+    wsync();
     if (ln < NV) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) E.M[ln][k] = C.row[k];   // padded rows hold the identity
     }
-    __syncthreads();
+    wsync();
     const int lc = ln < NV ? ln : 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) C.col[k] = (ln < NV) ? E.M[k][lc] : RL(0.0);
@@ -804,7 +804,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     real qdn = E.qd[ln] + dt * x;
     E.qdn[ln] = qdn;
   }
-  __syncthreads();
+  wsync();
   // ---- positions with the new velocities (lane = joint)
   if (ln < J) {
     if (jr.type == J_FREE) {
@@ -829,13 +829,13 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     const real ka = dt / m->tau_act;
     for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.actn[i] = E.act[i] + ka * (E.a[m->n_motor + i] - E.act[i]);
   }
-  __syncthreads();
+  wsync();
   if (inplace) {
     if (ln < m->nq) E.q[ln] = E.qn[ln];
     if (ln < nv) E.qd[ln] = E.qdn[ln];
     if constexpr (L::kMtu > 0)
       for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = E.actn[i];
-    __syncthreads();
+    wsync();
   }
 }
 
@@ -889,14 +889,14 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
       E.qdb[jr.va] += dt * E.qb[jr.qa];
     }
   }
-  __syncthreads();
+  wsync();
   // ---- lambda = M^{-1} qdd_bar with the cached factor (lane = DOF)
   {
     real rb = ln < nv ? dt * E.qdb[ln] : RL(0.0);
     real lam = fb ? (real)chol64_solve<NV>(E, ln, (double)rb) : chol_solve<NV>(C, ln, rb);
     if (ln < nv) E.lam[ln] = lam;
   }
-  __syncthreads();
+  wsync();
   // actuation adjoint and full accelerations / virtual velocities, level by level
   if (ln < J && jr.act >= 0) E.abar[jr.act] += jr.gear * E.lam[jr.va];
   // local terms (lane = joint), then their sums along each root path by pointer jumping
@@ -926,7 +926,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(E.A[ln], A);
     stsv(E.W[ln], W);
   }
-  __syncthreads();
+  wsync();
   // ---- contact adjoints (lane = contact)
   if (ln < nc) {
     int b = cr.body;
@@ -951,7 +951,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(E.cAb[ln], ab);
     stsv(E.cVb[ln], spf(x, vbar));
   }
-  __syncthreads();
+  wsync();
   if constexpr (L::kMtu > 0) muscle_adjoint(m, E, ln);
   // ---- per-body terms (lane = joint): P Q R T Fn Ab Vb
   if (ln < J) {
@@ -979,9 +979,9 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(o + 0, Iw); stsv(o + 6, Q); stsv(o + 12, Rr); stsv(o + 18, T);
     stsv(o + 24, Fn); stsv(o + 30, Ab); stsv(o + 36, Vb);
   }
-  __syncthreads();
+  wsync();
   tree_sum_cols(&E.acc[0][ln < 42 ? ln : 0], 42, ln < 42, J, jr.par);
-  __syncthreads();
+  wsync();
   // ---- derivatives of lambda^T ID per joint (lane = joint)
   if (ln < J) {
     const real* o = E.acc[ln];
@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
       E.dPqd[jr.va] = dotsv(S, QRT) - RL(2.0) * dotsv(ee, P) + dotsv(S, Vb);
     }
   }
-  __syncthreads();
+  wsync();
   // ---- adjoint of the pre-substep state
   if (ln < nv) E.qdb[ln] -= E.dPqd[ln];
   if (ln < J) {
@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
       E.qb[jr.qa] -= E.dPq[jr.va];
     }
   }
-  __syncthreads();
+  wsync();
 }
 
 // Adjoint of one substep from its pre-state alone: the forward linearisation is
@@ -1078,7 +1078,7 @@ __device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, L& E,
   if (ln < m->nv) E.qd[ln] = E.qdn[ln];
   if constexpr (L::kMtu > 0)
     for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = E.actn[i];
-  __syncthreads();
+  wsync();
 }
 
 template <int NV, class L>
@@ -1093,7 +1093,7 @@ __device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, 
     E.tdinv[ln] = dv;
     E.tfb[ln] = fb ? RL(1.0) : RL(0.0);
   }
-  __syncthreads();
+  wsync();
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const u32x4* src = reinterpret_cast<const u32x4*>(&E.q[0]);
   u32x4* dst = reinterpret_cast<u32x4*>(tp);
@@ -1108,6 +1108,7 @@ template <int NV, class L>
 __device__ __forceinline__ void tape_load(L& E, Chol& C, int& fb, int ln, const real* __restrict__ tp) {
   const char* g = reinterpret_cast<const char*>(tp);
   char* l = reinterpret_cast<char*>(&E.q[0]);
+  __syncthreads();   // earlier LDS reads of the block complete before the transfer overwrites it
 #pragma unroll
   for (int i = 0; i < L::kTapeBytes / 1024; ++i)
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + i * 1024 + ln * 16),

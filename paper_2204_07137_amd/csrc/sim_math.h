@@ -73,6 +73,17 @@ __device__ __forceinline__ double rdl(double x, int l) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Orders the LDS accesses of the environment's lanes.  A workgroup here is one wavefront,
+// and one wavefront's LDS operations are performed in program order, so a value written
+// by one lane is seen by a later read of another lane without waiting for the write; the
+// fences only keep the compiler from moving memory accesses across this point.  (Direct
+// global-to-LDS transfers are not LDS operations in this sense and keep a full barrier.)
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // lane src's value, src chosen per lane (a wavefront-wide permute through the LDS
 // crossbar: no LDS memory, no barrier); every lane of the wavefront must be active
 __device__ __forceinline__ int pull(int x, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, x); }

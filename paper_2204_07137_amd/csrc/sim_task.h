@@ -34,7 +34,7 @@ __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ void to_bf16(const real* x, uint16_t* xb, int n, int ln) {
   const int np = (n + 31) / 32 * 32;
   for (int i = ln; i < np; i += SIM_WAVE) xb[i] = (i < n) ? f2bf((float)x[i]) : (uint16_t)0;
-  __syncthreads();
+  wsync();
 }
 
 // out[r] (r < nr) = sum_k Wt[r][k] xb[k] over nk inputs, Wt in tiles of P; with the bias,
@@ -85,7 +85,7 @@ __device__ __forceinline__ void mlp_forward_bf16(const MlpArgs& P, const real* x
     real* dst = (l == P.nl - 1) ? out : ((l & 1) ? h1 : h0);
     to_bf16(in, xb, ni, ln);
     mlp_tiles_bf16(P.Pf[l], xb, ni, no, ln, P.b[l], l < P.nl - 1, nullptr, dst);
-    __syncthreads();
+    wsync();
     in = dst;
   }
 }
@@ -99,7 +99,7 @@ __device__ __forceinline__ void mlp_vjp_input_bf16(const MlpArgs& P, const real*
     to_bf16(g, xb, no, ln);          // g is not read again: dst may alias it
     const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
     mlp_tiles_bf16(P.Pb[l], xb, no, ni, ln, nullptr, false, hin, dst);
-    __syncthreads();
+    wsync();
     g = dst;
   }
 }
@@ -196,7 +196,7 @@ __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, rea
       case 7: mlp_layer_fwd<7>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
       default: mlp_layer_fwd<8>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
     }
-    __syncthreads();
+    wsync();
     in = dst;
   }
 }
@@ -224,7 +224,7 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
       case 7: mlp_layer_vjp<7>(P.W[l], g, acc, ni, no, ln); break;
       default: mlp_layer_vjp<8>(P.W[l], g, acc, ni, no, ln); break;
     }
-    __syncthreads();   // every lane has read g before dst (which may alias g) is written
+    wsync();   // every lane has read g before dst (which may alias g) is written
     const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
     const int nch = pad64(ni) / SIM_WAVE;
 #pragma unroll
@@ -239,7 +239,7 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
         dst[i] = v;
       }
     }
-    __syncthreads();
+    wsync();
     g = dst;
   }
 }
@@ -296,7 +296,7 @@ __device__ __forceinline__ void task_obs(const Scal* __restrict__ m, const real*
       for (int i = ln; i < m->n_mtu; i += SIM_WAVE) o[128 + i] = act[i];
     }
   }
-  __syncthreads();
+  wsync();
 }
 
 // adjoint of task_obs: adds (d obs / d s)^T obar to (qb, qdb, abar_prev, act_bar)
@@ -340,7 +340,7 @@ __device__ __forceinline__ void task_obs_vjp(const Scal* __restrict__ m, const r
     if (m->task == TASK_MTU)
       for (int i = ln; i < m->n_mtu; i += SIM_WAVE) actb[i] += ob[128 + i];
   }
-  __syncthreads();
+  wsync();
 }
 
 // --------------------------------------------------------------- rewards
@@ -420,5 +420,5 @@ __device__ __forceinline__ void task_reward_vjp(const Scal* __restrict__ m, cons
     if (m->task == TASK_MTU)
       for (int i = ln; i < m->na; i += SIM_WAVE) abar[i] += c * (-RL(0.002) * a[i]);
   }
-  __syncthreads();
+  wsync();
 }
