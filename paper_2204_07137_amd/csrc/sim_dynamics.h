@@ -307,51 +307,24 @@ __device__ __forceinline__ double chol64_solve(L& E, int ln, double b) {
 
 // --------------------------------------------------------------- subtree sums
 // Adds every frame's row of a table into its parent's row, children before parents
-// (frames are listed parents first); each active lane owns one column.  The column is held
-// in registers during the walk: the parent index is the same on every lane (broadcast
-// from the lane that holds it), so the indexed register access moves no memory and the
-// walk carries no LDS round trip per edge.  The additions and their order are those of
-// the edge list, so the sums do not depend on how they are stored.
+// (frames are listed parents first); each active lane owns one column.  The parent index
+// is broadcast from the lane that holds it; the LDS executes one wavefront's accesses in
+// order, so a parent updated by an earlier edge is read back correctly without a wait.
 __device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active, int J, int par_reg) {
-  real r[SIM_MAXJ];
-  if (active) {
-    // every table has SIM_MAXJ rows; rows >= J are carried through untouched
-#pragma unroll
-    for (int j = 0; j < SIM_MAXJ; ++j) r[j] = col[j * stride];
-  }
-#pragma unroll
-  for (int j = SIM_MAXJ - 1; j >= 1; --j) {
-    if (j < J) {
-      const int p = __builtin_amdgcn_readlane(par_reg, j);
-      if (p >= 0) r[p] += r[j];
-    }
-  }
-  if (active) {
-#pragma unroll
-    for (int j = 0; j < SIM_MAXJ; ++j) col[j * stride] = r[j];
+  for (int j = J - 1; j >= 1; --j) {
+    int p = __builtin_amdgcn_readlane(par_reg, j);
+    if (active && p >= 0) col[p * stride] += col[j * stride];
   }
 }
 
-// Sum of a spatial vector over each frame's root path by pointer jumping: a round adds the
-// partial sum of the frame the link names and takes over its link (ceil(log2(depth + 1))
-// rounds).  Values move between lanes by wavefront permutes, so every lane must be active.
+// Sums of two spatial vectors over each frame's root path by pointer jumping: a round adds
+// the partial sums of the frame the link names and takes over its link (ceil(log2(depth +
+// 1)) rounds).  Values move between lanes by wavefront permutes, so every lane must be
+// active.
 __device__ __forceinline__ sv pull_sv(sv x, int src) {
   return mksv(mk3(pull(x.a.x, src), pull(x.a.y, src), pull(x.a.z, src)),
               mk3(pull(x.l.x, src), pull(x.l.y, src), pull(x.l.z, src)));
 }
-__device__ __forceinline__ sv path_sum(sv x, int link, int rounds) {
-  for (int r = 0; r < rounds; ++r) {
-    const int src = link >= 0 ? link : (int)threadIdx.x;
-    const sv y = pull_sv(x, src);
-    const int nl = pull(link, src);
-    if (link >= 0) {
-      x = addsv(y, x);
-      link = nl;
-    }
-  }
-  return x;
-}
-// the same for two vectors over the same links
 __device__ __forceinline__ void path_sum2(sv& x, sv& z, int link, int rounds) {
   for (int r = 0; r < rounds; ++r) {
     const int src = link >= 0 ? link : (int)threadIdx.x;
@@ -623,15 +596,32 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       u = sclsv(S, qdj);
     }
   }
-  // velocities v = sum of S qd along the root path, then bias accelerations
-  // ab = sum of v x (S qd) along the path (plus gravity at the root), both by pointer
-  // jumping over the same links
-  v = path_sum(u, (ln < J) ? jr.par : -1, rounds);
-  if (ln < J && jr.type != J_FREE) {
-    c = crm(v, u);
-    if (jr.par < 0) c = addsv(c, mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g)));
+  // velocities v_j = sum of u_k = S_k qd_k over the root path and bias accelerations
+  // ab_j = sum of v_k x u_k over the path (plus gravity at the root), in one pointer-jumping
+  // pass: for a path segment (V, C) = (sum u, sum of v x u with v measured from the
+  // segment's top), appending the segment below gives V = Va + Vb, C = Ca + Cb + Va x Vb
+  // (u x u = 0, so a single frame starts from C = 0)
+  {
+    sv V = u, Cs = zsv();
+    if (ln < J) {
+      if (jr.type == J_FREE) Cs = c;
+      else if (jr.par < 0) Cs = mksv(mk3(RL(0.0), RL(0.0), RL(0.0)), mk3(RL(0.0), RL(0.0), g));
+    }
+    int link = (ln < J) ? jr.par : -1;
+    for (int r = 0; r < rounds; ++r) {
+      const int src = link >= 0 ? link : ln;
+      const sv Va = pull_sv(V, src);
+      const sv Ca = pull_sv(Cs, src);
+      const int nl = pull(link, src);
+      if (link >= 0) {
+        Cs = addsv(addsv(Ca, Cs), crm(Va, V));
+        V = addsv(Va, V);
+        link = nl;
+      }
+    }
+    v = V;
+    ab = Cs;
   }
-  ab = path_sum(c, (ln < J) ? jr.par : -1, rounds);
   if (ln < J) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) E.R[ln][k] = R[k];
