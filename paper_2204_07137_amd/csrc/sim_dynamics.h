@@ -62,13 +62,19 @@ struct EnvLDST {
   real qn[SIM_MAXQ];
   real actn[NMTU];                     // activations after the substep
   real act_bar[NMTU];
-  real F[SIM_MAXJ][6], Fi[SIM_MAXJ][6];
-  real Ic[SIM_MAXJ][10];
+  // substep scratch: the forward's Newton-Euler forces, CRBA columns and composite
+  // inertias, and the adjoint's per-body terms with their subtree sums (never live together)
+  union {
+    struct {
+      real F[SIM_MAXJ][6], Fi[SIM_MAXJ][6];
+      real Ic[SIM_MAXJ][10];
+    };
+    real acc[SIM_MAXJ][42];
+  };
   real vec[SIM_MAXV];
   real O[4];
   // adjoint
   real W[SIM_MAXJ][6], A[SIM_MAXJ][6];
-  real acc[SIM_MAXJ][42];
   real cAb[SIM_MAXC][6], cVb[SIM_MAXC][6];
   real qb[SIM_MAXQ], qdb[SIM_MAXV], abar[MAXA];
   real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
@@ -93,6 +99,8 @@ struct EnvLDST {
 };
 typedef EnvLDST<SIM_MAXA, 0> EnvLDS;             // torque-driven models
 typedef EnvLDST<SIM_MAXAM, SIM_MAXMTU> EnvLDSM;  // muscle-driven models
+// four environments per CU (160 KB of LDS) in FP32, for both layouts
+static_assert(sizeof(real) != 4 || sizeof(EnvLDSM) <= 40960, "muscle LDS layout exceeds a quarter of the CU's LDS");
 
 template <class L>
 __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, int ln,
