@@ -181,12 +181,14 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
         return fail(SIM_E_MODEL, "muscle F_max >= 0, l_opt > 0, l_slack >= 0 required");
       m.mtu_npt[i] = np;
       m.mtu_fmax[i] = md->mtu_fmax[i]; m.mtu_lopt[i] = md->mtu_lopt[i]; m.mtu_lslack[i] = md->mtu_lslack[i];
+      // slots past the last point repeat it, so the kernels load every slot unconditionally
       for (int k = 0; k < SIM_MAXMPT; ++k) {
-        int b = (k < np) ? md->mtu_body[i * SIM_MAXMPT + k] : 0;
+        const int kk = k < np ? k : np - 1;
+        int b = md->mtu_body[i * SIM_MAXMPT + kk];
         if (b < 0 || b >= J) return fail(SIM_E_MODEL, "muscle point body out of range");
         m.mtu_body[k * SIM_MAXMTU + i] = b;
         for (int c = 0; c < 3; ++c)
-          m.mtu_pos[(k * 3 + c) * SIM_MAXMTU + i] = (k < np) ? md->mtu_pos[(i * SIM_MAXMPT + k) * 3 + c] : 0.0;
+          m.mtu_pos[(k * 3 + c) * SIM_MAXMTU + i] = md->mtu_pos[(i * SIM_MAXMPT + kk) * 3 + c];
       }
     }
     m.tau_act = md->tau_act; m.fl_w = md->fl_width; m.vmax = md->vmax;

@@ -30,6 +30,14 @@ struct ContactRegs {
   real rad;
 };
 
+// Muscle accumulators: a table of SIM_MAXJ x 6 values padded to an odd stride (so the copies
+// of one entry sit in different banks); the forward keeps SIM_MUS_CF copies of the wrench
+// table, the adjoint SIM_MUS_CA copies of each of its three tables.
+#define SIM_MUS_STRIDE (SIM_MAXJ * 6 + 1)
+#define SIM_MUS_CF 11
+#define SIM_MUS_CA 3
+static_assert(3 * SIM_MUS_CA <= SIM_MUS_CF, "adjoint muscle tables fit the forward's space");
+
 // Per-environment LDS of one wavefront.  MAXA: action capacity; NMTU: muscle capacity
 // (0 for torque-driven models, whose layout then carries no muscle fields).
 template <int MAXA, int NMTU>
@@ -91,9 +99,9 @@ struct EnvLDST {
       uint16_t xb16[SIM_MAXHID] __attribute__((aligned(16)));   // BF16 layer operand
     };
     double M64[SIM_MAXV][SIM_MAXV];   // FP64 refactorisation (never live at the same time as the MLP)
-    struct {                          // per-body muscle wrenches and their adjoint terms (substep-local)
-      real Fm[SIM_MAXJ][6], mAb[SIM_MAXJ][6], mVb[SIM_MAXJ][6];
-    };
+    // per-body muscle wrenches and their adjoint terms (substep-local), accumulated in
+    // several copies (see muscle_wrenches); copy 0 of each table holds the sums
+    real mus[SIM_MUS_CF * SIM_MUS_STRIDE];
   };
   real red[4];
 };
@@ -370,10 +378,10 @@ __device__ __forceinline__ void mtu_path(const Scal* __restrict__ m, const L& E,
   P.np = T->mtu_npt[i];
 #pragma unroll
   for (int k = 0; k < SIM_MAXMPT; ++k) {
-    const int kk = k < P.np ? k : P.np - 1;     // points past the end repeat the last one
-    const int b = T->mtu_body[kk * SIM_MAXMTU + i];
-    f3 r = mk3(T->mtu_pos[(kk * 3 + 0) * SIM_MAXMTU + i], T->mtu_pos[(kk * 3 + 1) * SIM_MAXMTU + i],
-               T->mtu_pos[(kk * 3 + 2) * SIM_MAXMTU + i]);
+    // the model tables repeat the last point in the slots past it
+    const int b = T->mtu_body[k * SIM_MAXMTU + i];
+    f3 r = mk3(T->mtu_pos[(k * 3 + 0) * SIM_MAXMTU + i], T->mtu_pos[(k * 3 + 1) * SIM_MAXMTU + i],
+               T->mtu_pos[(k * 3 + 2) * SIM_MAXMTU + i]);
     P.b[k] = b;
     P.x[k] = add3(ld3(E.p[b]), mv3(E.R[b], r));
     P.v[k] = ptv(ldsv(E.v[b]), P.x[k]);
@@ -416,12 +424,34 @@ __device__ __forceinline__ void lds_add6(real* dst, sv w) {
   atomicAdd(dst + 3, w.l.x); atomicAdd(dst + 4, w.l.y); atomicAdd(dst + 5, w.l.z);
 }
 
-// Per-body wrench of all muscle tensions (about O) into E.Fm.  One lane per unit; the LDS
-// additions of one wavefront are ordered, so the sums are reproducible.
+// Per-body wrench of all muscle tensions (about O), left in copy 0 of the wrench table
+// (mus_fm).  One lane per unit.  Many units share a body, and LDS atomics to one address
+// are serialised, so lane l adds into copy l % SIM_MUS_CF and the copies are summed
+// afterwards in copy order; an instruction's additions to one address are performed in
+// lane order, so the sums are reproducible.
+template <class L>
+__device__ __forceinline__ real* mus_fm(L& E, int b) { return &E.mus[b * 6]; }
+template <class L>
+__device__ __forceinline__ real* mus_ab(L& E, int b) { return &E.mus[SIM_MUS_CA * SIM_MUS_STRIDE + b * 6]; }
+template <class L>
+__device__ __forceinline__ real* mus_vb(L& E, int b) { return &E.mus[2 * SIM_MUS_CA * SIM_MUS_STRIDE + b * 6]; }
+
+// sum copies 1..nc-1 of table t (tables of nc copies each) into its copy 0
+template <class L>
+__device__ __forceinline__ void mus_fold(L& E, int t, int nc, int ln) {
+  real* base = &E.mus[t * nc * SIM_MUS_STRIDE];
+  for (int e = ln; e < SIM_MAXJ * 6; e += SIM_WAVE) {
+    real s = base[e];
+    for (int c = 1; c < nc; ++c) s += base[c * SIM_MUS_STRIDE + e];
+    base[e] = s;
+  }
+}
+
 template <class L>
 __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E, int ln) {
-  for (int i = ln; i < SIM_MAXJ * 6; i += SIM_WAVE) (&E.Fm[0][0])[i] = RL(0.0);
+  for (int i = ln; i < SIM_MUS_CF * SIM_MUS_STRIDE; i += SIM_WAVE) E.mus[i] = RL(0.0);
   wsync();
+  real* fm = &E.mus[(ln % SIM_MUS_CF) * SIM_MUS_STRIDE];
   for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
     const int i = i0 + ln;
     if (i < m->n_mtu) {
@@ -431,28 +461,31 @@ __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E
       for (int k = 0; k < SIM_MAXMPT; ++k) {
         if (k < P.np) {
           f3 f = scl3(mtu_udiff(P, k), P.F);
-          lds_add6(E.Fm[P.b[k]], spf(P.x[k], f));
+          lds_add6(fm + P.b[k] * 6, spf(P.x[k], f));
         }
       }
     }
   }
   wsync();
+  mus_fold(E, 0, SIM_MUS_CF, ln);
+  wsync();
 }
 
 // Adjoint of the muscle forces in lambda^T ID = ... - sum_p nu_p . f_p (nu_p the virtual
-// velocity of point p under lambda): recomputes the tensions and E.Fm, adds to E.act_bar
+// velocity of point p under lambda): recomputes the tensions and the wrench table, adds to E.act_bar
 // the activation term, and collects per body the terms of the point-force adjoint that the
-// contacts use (E.mAb: Sp(x, xbar) + (-nu x f + v x vbar, 0); E.mVb: Sp(x, vbar)), where
+// contacts use (mus_ab: Sp(x, xbar) + (-nu x f + v x vbar, 0); mus_vb: Sp(x, vbar)), where
 // xbar, vbar are the derivatives of F delta (delta = sum u_k . (nu_{k+1} - nu_k)) through
 // the tension and the segment directions.
 template <class L>
 __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E, int ln) {
-  for (int i = ln; i < SIM_MAXJ * 6; i += SIM_WAVE) {
-    (&E.Fm[0][0])[i] = RL(0.0);
-    (&E.mAb[0][0])[i] = RL(0.0);
-    (&E.mVb[0][0])[i] = RL(0.0);
-  }
+  for (int i = ln; i < 3 * SIM_MUS_CA * SIM_MUS_STRIDE; i += SIM_WAVE) E.mus[i] = RL(0.0);
   wsync();
+  // lane l adds into copy l % SIM_MUS_CA of each table (see muscle_wrenches)
+  const int cp = ln % SIM_MUS_CA;
+  real* fm = &E.mus[cp * SIM_MUS_STRIDE];
+  real* mab = &E.mus[(SIM_MUS_CA + cp) * SIM_MUS_STRIDE];
+  real* mvb = &E.mus[(2 * SIM_MUS_CA + cp) * SIM_MUS_STRIDE];
   const DevModel* __restrict__ T = m->tab;
   for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
     const int i = i0 + ln;
@@ -498,15 +531,17 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
           const f3 f = scl3(ud, P.F);
           const f3 vb = scl3(ud, -cV);
           const int b = P.b[k];
-          lds_add6(E.Fm[b], spf(P.x[k], f));
-          lds_add6(E.mAb[b], addsv(spf(P.x[k], xb[k]),
+          lds_add6(fm + b * 6, spf(P.x[k], f));
+          lds_add6(mab + b * 6, addsv(spf(P.x[k], xb[k]),
                                    mksv(add3(scl3(cross3(nu[k], f), -RL(1.0)), cross3(P.v[k], vb)),
                                         mk3(RL(0.0), RL(0.0), RL(0.0)))));
-          lds_add6(E.mVb[b], spf(P.x[k], vb));
+          lds_add6(mvb + b * 6, spf(P.x[k], vb));
         }
       }
     }
   }
+  wsync();
+  for (int t = 0; t < 3; ++t) mus_fold(E, t, SIM_MUS_CA, ln);
   wsync();
 }
 
@@ -691,7 +726,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       int ci = __builtin_ctz(cm);
       f = subsv(f, spf(ld3(E.cx[ci]), ld3(E.cf[ci])));
     }
-    if constexpr (L::kMtu > 0) f = subsv(f, ldsv(E.Fm[ln]));
+    if constexpr (L::kMtu > 0) f = subsv(f, ldsv(mus_fm(E, ln)));
     stsv(E.F[ln], f);
     // joint torques: actuation + limit penalty
     if (jr.type != J_FREE) {
@@ -969,9 +1004,9 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
       Vb = addsv(Vb, ldsv(E.cVb[ci]));
     }
     if constexpr (L::kMtu > 0) {
-      Fn = subsv(Fn, ldsv(E.Fm[ln]));
-      Ab = addsv(Ab, ldsv(E.mAb[ln]));
-      Vb = addsv(Vb, ldsv(E.mVb[ln]));
+      Fn = subsv(Fn, ldsv(mus_fm(E, ln)));
+      Ab = addsv(Ab, ldsv(mus_ab(E, ln)));
+      Vb = addsv(Vb, ldsv(mus_vb(E, ln)));
     }
     real* o = E.acc[ln];
     stsv(o + 0, Iw); stsv(o + 6, Q); stsv(o + 12, Rr); stsv(o + 18, T);
