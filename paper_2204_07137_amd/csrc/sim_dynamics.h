@@ -457,13 +457,23 @@ __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E
     if (i < m->n_mtu) {
       MtuPath P;
       mtu_path(m, E, i, P, E.act[i]);
+      // consecutive points on one body are summed first: one addition per run of points
+      sv acc = zsv();
+      int cur = P.b[0];
 #pragma unroll
       for (int k = 0; k < SIM_MAXMPT; ++k) {
         if (k < P.np) {
-          f3 f = scl3(mtu_udiff(P, k), P.F);
-          lds_add6(fm + P.b[k] * 6, spf(P.x[k], f));
+          const sv w = spf(P.x[k], scl3(mtu_udiff(P, k), P.F));
+          if (P.b[k] != cur) {
+            lds_add6(fm + cur * 6, acc);
+            acc = w;
+            cur = P.b[k];
+          } else {
+            acc = addsv(acc, w);
+          }
         }
       }
+      lds_add6(fm + cur * 6, acc);
     }
   }
   wsync();
@@ -524,20 +534,34 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
           xb[k] = sub3(xb[k], g);
         }
       }
+      // consecutive points on one body are summed first (see muscle_wrenches)
+      sv af = zsv(), aa = zsv(), av = zsv();
+      int cur = P.b[0];
 #pragma unroll
       for (int k = 0; k < SIM_MAXMPT; ++k) {
         if (k < P.np) {
           const f3 ud = mtu_udiff(P, k);
           const f3 f = scl3(ud, P.F);
           const f3 vb = scl3(ud, -cV);
-          const int b = P.b[k];
-          lds_add6(fm + b * 6, spf(P.x[k], f));
-          lds_add6(mab + b * 6, addsv(spf(P.x[k], xb[k]),
-                                   mksv(add3(scl3(cross3(nu[k], f), -RL(1.0)), cross3(P.v[k], vb)),
-                                        mk3(RL(0.0), RL(0.0), RL(0.0)))));
-          lds_add6(mvb + b * 6, spf(P.x[k], vb));
+          const sv wf = spf(P.x[k], f);
+          const sv wa = addsv(spf(P.x[k], xb[k]),
+                              mksv(add3(scl3(cross3(nu[k], f), -RL(1.0)), cross3(P.v[k], vb)),
+                                   mk3(RL(0.0), RL(0.0), RL(0.0))));
+          const sv wv = spf(P.x[k], vb);
+          if (P.b[k] != cur) {
+            lds_add6(fm + cur * 6, af);
+            lds_add6(mab + cur * 6, aa);
+            lds_add6(mvb + cur * 6, av);
+            af = wf; aa = wa; av = wv;
+            cur = P.b[k];
+          } else {
+            af = addsv(af, wf); aa = addsv(aa, wa); av = addsv(av, wv);
+          }
         }
       }
+      lds_add6(fm + cur * 6, af);
+      lds_add6(mab + cur * 6, aa);
+      lds_add6(mvb + cur * 6, av);
     }
   }
   wsync();
