@@ -30,6 +30,7 @@ CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 FP32_VALU_PEAK_TFLOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_GHZ / 1e3   # non-packed FMA
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_window_kernels_humanoid1024_k4.json")
+PLAIN_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_plain_kernels_humanoid1024.json")
 
 
 def kernel_source_hash():
@@ -47,16 +48,22 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def adjoint_traffic(n_envs, k):
-    """HBM bytes per k_window_adj launch from the profiler's FETCH_SIZE / WRITE_SIZE passes
-    (scaled by the copy-kernel calibration), or None when the record is for another
-    workload or the kernel sources have changed since the counters were taken."""
+def traffic_record(path):
+    """A profiler traffic record (FETCH_SIZE / WRITE_SIZE passes scaled by the copy-kernel
+    calibration), or None when it is missing or the kernel sources have changed since the
+    counters were taken."""
     try:
-        with open(TRAFFIC_RECORD) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except OSError:
         return None
-    if n_envs != 1024 or k != 4 or rec.get("source_sha256") != kernel_source_hash():
+    return rec if rec.get("source_sha256") == kernel_source_hash() else None
+
+
+def adjoint_traffic(n_envs, k):
+    """HBM bytes per k_window_adj launch at the headline workload, or None."""
+    rec = traffic_record(TRAFFIC_RECORD)
+    if rec is None or n_envs != 1024 or k != 4:
         return None
     return float(rec["bytes_per_launch"])
 
@@ -265,8 +272,14 @@ def cpu_baseline(W, h, n_envs_sample=2):
     oracle_window_grads(W["model"], W["s0"][:n_envs_sample], h, W["actor"], W["critic"],
                         n_total=W["n_envs"])
     dt = time.time() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n_envs_sample * h / dt, "unit": "env-steps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu, "nproc": os.cpu_count(),
             "sample": f"{n_envs_sample} humanoid envs x h={h} frames (48 substeps each), fwd+reverse, "
                       f"{dt:.1f} s wall"}
 
@@ -369,7 +382,26 @@ def main():
                              "launches_per_step": 2 * (h * (S + 1) + 1),
                              "persistent_speedup": round(value / pval, 3),
                              "tape_speedup": round(tval / pval, 3)}
+        # the plain adjoint re-linearises each substep from its stored pre-state, like the
+        # persistent one: the same work per window
+        plain_flops = (fwd_flops_env_step + adj_flops_env_step) * N * h
+        plain_s = pw / args.plain_steps
+        out["plain_path"]["achieved_tflops"] = round(plain_flops / plain_s / 1e12, 4)
+        out["plain_path"]["frac_fp32_valu"] = round(plain_flops / plain_s / 1e12 / FP32_VALU_PEAK_TFLOPS, 5)
+        prec = traffic_record(PLAIN_TRAFFIC_RECORD)
+        if prec is not None:
+            out["plain_path"]["traffic_bytes_per_step"] = prec["bytes_per_step"]
+            out["plain_path"]["hbm_gbs"] = round(prec["bytes_per_step"] / plain_s / 1e9, 1)
+            out["plain_path"]["hbm_frac"] = round(prec["bytes_per_step"] / plain_s / 1e9 / HBM_PEAK_GBS, 4)
         del plain
+
+    # measured device ceilings beside the published ones
+    ceil = P.probe_ceilings()
+    out["ceilings"] = {"measured_fp32_valu_tflops": round(ceil["fp32_valu_tflops"], 2),
+                       "published_fp32_valu_tflops_nonpacked": round(FP32_VALU_PEAK_TFLOPS, 1),
+                       "measured_copy_gbs": round(ceil["copy_gbs"], 1),
+                       "published_hbm_gbs": HBM_PEAK_GBS}
+    roof["frac_of_measured"] = round(achieved / ceil["fp32_valu_tflops"], 5)
 
     if not args.no_mtu:
         out["mtu"] = mtu_window(P, wl, torch)

@@ -272,6 +272,21 @@ typedef struct SimTuneResult {
 int sim_tune(const SimModelDesc* model, const SimOptions* opt, const SimForwardIO* io,
              size_t workspace_budget, int reps, void* hip_stream, SimTuneResult* out);
 
+/* ---- Device ceilings (measurement probes, not part of a window).  The roofline of the
+ * window kernels is quoted against AMD's published MI355X figures and against these
+ * measured ones.
+ * sim_probe_fma: times an FP32 FMA loop (eight independent chains per lane, no packed
+ * instructions, 4096 x 256 threads) on the stream and returns the achieved FP32 VALU
+ * TFLOP/s.  scratch: caller-owned device buffer of at least sim_probe_fma_bytes() bytes
+ * (the loop's results are written there).  Synchronizes the stream.
+ * sim_probe_copy: times a device-to-device copy of `bytes` (a multiple of 16; both device
+ * pointers 16-byte aligned, caller-owned, not overlapping) and returns GB/s counting
+ * bytes read plus bytes written.  Synchronizes the stream.  Both return SIM_E_ARG on bad
+ * arguments before any launch and SIM_E_HIP on a failed launch. */
+size_t sim_probe_fma_bytes(void);
+int sim_probe_fma(void* scratch, size_t scratch_bytes, void* hip_stream, double* tflops);
+int sim_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stream, double* gbs);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* sim_last_error(void);
 

@@ -68,7 +68,7 @@ class SimTuneResult(ctypes.Structure):
 EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
            "sim_adjoint_window", "sim_destroy", "sim_last_error", "sim_group_create",
            "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
-           "sim_tune"]
+           "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy"]
 MAX_GROUP = 6
 
 _LIB = None
@@ -109,6 +109,12 @@ def lib():
                                ctypes.POINTER(SimForwardIO), ctypes.c_size_t, _i, _p,
                                ctypes.POINTER(SimTuneResult)]
         L.sim_tune.restype = _i
+        L.sim_probe_fma_bytes.argtypes = []
+        L.sim_probe_fma_bytes.restype = ctypes.c_size_t
+        L.sim_probe_fma.argtypes = [_p, ctypes.c_size_t, _p, ctypes.POINTER(_d)]
+        L.sim_probe_fma.restype = _i
+        L.sim_probe_copy.argtypes = [_p, _p, ctypes.c_size_t, _p, ctypes.POINTER(_d)]
+        L.sim_probe_copy.restype = _i
         _LIB = L
     return _LIB
 
@@ -447,6 +453,24 @@ def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget
     probe.close()
     return {"path": r.path, "ckpt_interval": r.ckpt_interval, "workspace_bytes": r.workspace_bytes,
             "ms_window": r.ms_window, "n_candidates": r.n_candidates, "keep": out}
+
+
+def probe_ceilings(copy_bytes=1 << 30):
+    """Measured device ceilings: FP32 VALU TFLOP/s of an FMA loop and GB/s (read + write)
+    of a device copy of copy_bytes, both from the library's own probe kernels."""
+    import torch
+    st = torch.cuda.current_stream()
+    L = lib()
+    nb = int(L.sim_probe_fma_bytes())
+    scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    tf = ctypes.c_double()
+    _check(L.sim_probe_fma(_p(scratch.data_ptr()), nb, _p(st.cuda_stream), ctypes.byref(tf)))
+    src = torch.ones(copy_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    gb = ctypes.c_double()
+    _check(L.sim_probe_copy(_p(src.data_ptr()), _p(dst.data_ptr()), copy_bytes, _p(st.cuda_stream),
+                            ctypes.byref(gb)))
+    return {"fp32_valu_tflops": tf.value, "copy_gbs": gb.value, "copy_bytes": copy_bytes}
 
 
 def window_function():

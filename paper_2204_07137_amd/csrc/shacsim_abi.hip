@@ -923,3 +923,80 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
   g_err.clear();
   return SIM_OK;
 }
+
+// ======================================================================= device ceilings
+// FP32 FMA loop: eight independent dependency chains per lane, no packed instructions
+// (the build disables them), enough waves to fill every SIMD several times over.
+#define PROBE_FMA_BLOCKS 4096
+#define PROBE_FMA_THREADS 256
+#define PROBE_FMA_ITERS 2048
+__global__ __launch_bounds__(PROBE_FMA_THREADS) void k_probe_fma(float* out, float m, float c) {
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = (float)(threadIdx.x + j) * 1e-3f;
+  for (int i = 0; i < PROBE_FMA_ITERS; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = __builtin_fmaf(a[j], m, c);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += a[j];
+  out[(size_t)blockIdx.x * PROBE_FMA_THREADS + threadIdx.x] = s;
+}
+
+// device-to-device copy, 16 bytes per lane and step, grid-stride
+__global__ __launch_bounds__(256) void k_probe_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+// time fn(stream) (already warmed up once) with events on the stream; ms of one call
+template <class F>
+static int probe_time(F fn, hipStream_t s, float* ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(SIM_E_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return fail(SIM_E_HIP, "hipEventCreate failed"); }
+  fn();
+  hipEventRecord(e0, s);
+  fn();
+  hipEventRecord(e1, s);
+  const hipError_t err = hipEventSynchronize(e1);
+  hipEventElapsedTime(ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess || hipGetLastError() != hipSuccess) return fail(SIM_E_HIP, "probe launch failed");
+  return SIM_OK;
+}
+
+int sim_probe_fma(void* scratch, size_t scratch_bytes, void* hip_stream, double* tflops) {
+  const size_t need = (size_t)PROBE_FMA_BLOCKS * PROBE_FMA_THREADS * sizeof(float);
+  if (!scratch || !tflops) return fail(SIM_E_ARG, "sim_probe_fma: null argument");
+  if (scratch_bytes < need) return fail(SIM_E_ARG, "sim_probe_fma: scratch smaller than sim_probe_fma_bytes()");
+  hipStream_t s = (hipStream_t)hip_stream;
+  float ms = 0.f;
+  const int rc = probe_time([&] {
+    hipLaunchKernelGGL(k_probe_fma, dim3(PROBE_FMA_BLOCKS), dim3(PROBE_FMA_THREADS), 0, s, (float*)scratch, 0.999999f, 1e-7f);
+  }, s, &ms);
+  if (rc) return rc;
+  const double flops = 2.0 * 8.0 * PROBE_FMA_ITERS * (double)PROBE_FMA_BLOCKS * PROBE_FMA_THREADS;
+  *tflops = flops / (ms * 1e-3) / 1e12;
+  g_err.clear();
+  return SIM_OK;
+}
+
+size_t sim_probe_fma_bytes(void) { return (size_t)PROBE_FMA_BLOCKS * PROBE_FMA_THREADS * sizeof(float); }
+
+int sim_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stream, double* gbs) {
+  if (!src || !dst || !gbs) return fail(SIM_E_ARG, "sim_probe_copy: null argument");
+  if (bytes < 16 || bytes % 16 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+    return fail(SIM_E_ARG, "sim_probe_copy: bytes and both pointers must be multiples of 16");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t n = bytes / 16;
+  float ms = 0.f;
+  const int rc = probe_time([&] {
+    hipLaunchKernelGGL(k_probe_copy, dim3(4096), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n);
+  }, s, &ms);
+  if (rc) return rc;
+  *gbs = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
+  g_err.clear();
+  return SIM_OK;
+}

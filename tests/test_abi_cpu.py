@@ -65,6 +65,14 @@ def test_null_arguments_rejected():
     assert L.sim_group_info(None, None, None) == -2
     L.sim_group_destroy(None)
     assert L.sim_tune(None, None, None, 0, 1, None, None) == -1
+    # ceiling probes: argument errors before any launch
+    d = ctypes.c_double()
+    assert L.sim_probe_fma_bytes() > 0
+    assert L.sim_probe_fma(None, 0, None, ctypes.byref(d)) == -1
+    assert L.sim_probe_fma(ctypes.c_void_p(16), 16, None, ctypes.byref(d)) == -1     # scratch too small
+    assert L.sim_probe_copy(None, None, 64, None, ctypes.byref(d)) == -1
+    assert L.sim_probe_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), 24, None, ctypes.byref(d)) == -1
+    assert L.sim_probe_copy(ctypes.c_void_p(8), ctypes.c_void_p(32), 64, None, ctypes.byref(d)) == -1
 
 
 def test_model_limits_rejected():
