@@ -29,6 +29,11 @@ METRIC = "env-steps/s fwd+adjoint (h=32), 21-DOF humanoid ×1024 envs; grad err 
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 FP32_VALU_PEAK_TFLOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_GHZ / 1e3   # non-packed FMA
 HBM_PEAK_GBS = 8000.0
+# Operations of the FP64 oracle per humanoid env-step (forward window, reverse-mode pass),
+# counted at the dispatcher by oracle/count_ops.py (re-derived by tests/test_oracle_count.py).
+# The oracle builds the mass matrix and bias in their dense defining form, so these exceed
+# the recursive algorithm's count below; they are reported as context, not as the roofline.
+ORACLE_OPS_PER_ENV_STEP = {"forward": 9205415, "reverse": 23383710}
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_window_kernels_humanoid1024_k4.json")
 PLAIN_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_plain_kernels_humanoid1024.json")
 
@@ -327,6 +332,7 @@ def main():
             "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 5), "traffic": adjoint_traffic(N, args.k),
             "traffic_unit": "bytes per launch, profiler FETCH_SIZE + WRITE_SIZE scaled by a copy of known size",
             "flops_per_env_step": {"adjoint_kernel": adj_flops_env_step, "forward_kernel": fwd_flops_env_step},
+            "oracle_ops_per_env_step": ORACLE_OPS_PER_ENV_STEP,
             "avg_ms": {"k_window_adj": round(float(np.mean(adj_ms)), 3),
                        "k_window_fwd": round(float(np.mean(fwd_ms)), 3)}}
 
