@@ -39,17 +39,21 @@ PLAIN_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_plain_kernels_hum
 
 
 def kernel_source_hash():
-    """SHA-256 over the kernel sources and the C-ABI header (relative path + bytes, sorted)."""
+    """SHA-256 over the kernel sources and the C-ABI header (relative path + code, sorted),
+    with comments and blank lines removed, so that only code changes invalidate a record."""
     import glob
     import hashlib
+    import re
     files = sorted(glob.glob(os.path.join(ROOT, "paper_2204_07137_amd", "csrc", "*.h"))
                    + glob.glob(os.path.join(ROOT, "paper_2204_07137_amd", "csrc", "*.hip"))
                    + glob.glob(os.path.join(ROOT, "include", "*.h")))
     h = hashlib.sha256()
     for f in files:
+        with open(f) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        code = [re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines()]
         h.update(os.path.relpath(f, ROOT).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        h.update("\n".join(line for line in code if line.strip()).encode())
     return h.hexdigest()
 
 

@@ -1,8 +1,8 @@
 // One substep of the articulated-body dynamics and its adjoint, for one environment
 // per wavefront.
 //
-// Forward (Sec. 3.1, Eq. "fwd_dynamics"): forward kinematics and velocities over the
-// tree levels, penalty contact and friction (Sec. 3.1 contact equation), joint limit
+// Forward (Sec. 3.1, Eq. "fwd_dynamics"): forward kinematics and velocities by pointer
+// jumping over the tree's parent links, penalty contact and friction (Sec. 3.1 contact equation), joint limit
 // penalty (Sec. 3.1 limit equation), RNEA bias b(q, qd) with gravity and contact
 // wrenches, CRBA mass matrix, dense Cholesky M = L L^T, qdd = M^{-1}(tau - b) and a
 // semi-implicit Euler step.
@@ -582,7 +582,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   for (int i = ln; i < SIM_MAXV * (SIM_MAXV + 1); i += SIM_WAVE) (&E.M[0][0])[i] = RL(0.0);
   wsync();
   // ---- local joint rotations (all lanes at once), then kinematics, velocities and bias
-  // accelerations level by level; each lane keeps its own frame's results in registers
+  // accelerations along the root paths; each lane keeps its own frame's results in registers
   real Rot[9];
   real qj = RL(0.0), qdj = RL(0.0);
   if (ln < J) {
@@ -954,7 +954,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     if (ln < nv) E.lam[ln] = lam;
   }
   wsync();
-  // actuation adjoint and full accelerations / virtual velocities, level by level
+  // actuation adjoint and full accelerations / virtual velocities
   if (ln < J && jr.act >= 0) E.abar[jr.act] += jr.gear * E.lam[jr.va];
   // local terms (lane = joint), then their sums along each root path by pointer jumping
   sv A = zsv(), W = zsv();
