@@ -71,6 +71,9 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   for (int j = 0; j < SIM_MAXJ; ++j) {
     d.cmask[j] = s.cmask[j];
   }
+  for (int g = 0; g < 4; ++g)
+    for (int t = 0; t < SIM_MAXTS; ++t) d.ts_edge[g][t] = s.ts_edge[g][t];
+  d.ts_steps = s.ts_steps;
   d.npair = s.npair;
   for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
   d.tau_act = (T)s.tau_act; d.fl_w = (T)s.fl_w; d.vmax = (T)s.vmax;
@@ -199,6 +202,42 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
   m.task = md->task; m.floating = (m.jtype[0] == J_FREE) ? 1 : 0;
   m.has_last_action = md->has_last_action ? 1 : 0;
   m.substeps = md->substeps; m.max_depth = maxd;
+  {
+    // Schedule of the forward subtree sums over four lane groups: an edge j -> parent(j) is
+    // ready once every edge into j is done; each step takes up to four ready edges with
+    // distinct parents, deepest child first (the longest remaining chain to the root).
+    std::vector<int> pending(J, 0), done(J, 0);
+    for (int j = 1; j < J; ++j)
+      if (m.parent[j] >= 0) pending[m.parent[j]]++;
+    for (int g = 0; g < 4; ++g)
+      for (int t = 0; t < SIM_MAXTS; ++t) m.ts_edge[g][t] = 0;
+    int left = 0;
+    for (int j = 1; j < J; ++j) left += (m.parent[j] >= 0) ? 1 : 0;
+    int steps = 0;
+    while (left > 0) {
+      if (steps >= SIM_MAXTS) return fail(SIM_E_MODEL, "subtree-sum schedule exceeds SIM_MAXTS steps");
+      std::vector<int> ready;
+      for (int j = 1; j < J; ++j)
+        if (m.parent[j] >= 0 && !done[j] && pending[j] == 0) ready.push_back(j);
+      std::stable_sort(ready.begin(), ready.end(), [&](int a, int b) { return m.depth[a] > m.depth[b]; });
+      std::vector<int> taken;
+      for (int j : ready) {
+        if ((int)taken.size() == 4) break;
+        bool clash = false;
+        for (int t : taken) clash = clash || (m.parent[t] == m.parent[j]);
+        if (!clash) taken.push_back(j);
+      }
+      for (size_t g = 0; g < taken.size(); ++g) {
+        const int j = taken[g];
+        m.ts_edge[g][steps] = (unsigned short)(j | (m.parent[j] << 5) | (1 << 10));
+        done[j] = 1;
+        --left;
+      }
+      for (int j : taken) pending[m.parent[j]]--;
+      ++steps;
+    }
+    m.ts_steps = steps;
+  }
   m.dt_sub = md->dt / md->substeps;
   m.g = md->gravity; m.kn = md->kn; m.kd = md->kd; m.kt = md->kt; m.mu = md->mu; m.klim = md->klim;
   m.ns = nq + nv + (m.has_last_action ? m.na : 0) + m.n_mtu;

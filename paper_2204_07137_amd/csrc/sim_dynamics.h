@@ -88,6 +88,7 @@ struct EnvLDST {
   real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
   // topology copies for arbitrary-index lookups
   int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ], t_qa[SIM_MAXJ];
+  unsigned short t_ts[4][SIM_MAXTS] __attribute__((aligned(16)));   // subtree-sum schedule
   real arm[SIM_MAXV];
   real j_off[SIM_MAXJ][3], j_ax[SIM_MAXJ][3], j_com[SIM_MAXJ][3], j_I6[SIM_MAXJ][6];
   int pairs[SIM_MAXPAIR];
@@ -122,6 +123,7 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, 
   jr.arm = m->armature[m->vadr[j]];
   jr.npair = m->npair;
   for (int p = ln; p < m->npair; p += SIM_WAVE) E.pairs[p] = m->pair[p];
+  reinterpret_cast<unsigned int*>(&E.t_ts[0][0])[ln] = reinterpret_cast<const unsigned int*>(&m->ts_edge[0][0])[ln];
   if (ln < SIM_MAXJ) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -330,6 +332,36 @@ __device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active
   for (int j = J - 1; j >= 1; --j) {
     int p = __builtin_amdgcn_readlane(par_reg, j);
     if (active && p >= 0) col[p * stride] += col[j * stride];
+  }
+}
+
+// The forward's subtree sums of 16 columns (Newton-Euler forces, composite inertias) along
+// the model's schedule: lane = (group g of four, column c of 16); at each step every group
+// adds one frame's row into its parent's.  A step holds no edge into a frame whose own
+// incoming edges are not all done, and no two edges into one parent, so the groups touch
+// disjoint rows and the LDS performs each step's accesses after the previous step's.
+template <class L>
+__device__ __forceinline__ void tree_sum_sched16(L& E, int nsteps, int ln) {
+  const int g = ln >> 4, c = ln & 15;
+  real* col = (c < 6) ? &E.F[0][c] : &E.Ic[0][c - 6];
+  const int st = (c < 6) ? 6 : 10;
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4* tp = reinterpret_cast<const u32x4*>(&E.t_ts[g][0]);
+  unsigned int w32[SIM_MAXTS / 2];
+#pragma unroll
+  for (int i = 0; i < SIM_MAXTS / 8; ++i) {
+    const u32x4 v = tp[i];
+    w32[4 * i] = v.x; w32[4 * i + 1] = v.y; w32[4 * i + 2] = v.z; w32[4 * i + 3] = v.w;
+  }
+#pragma unroll
+  for (int s = 0; s < SIM_MAXTS; ++s) {
+    if (s < nsteps) {
+      const unsigned int w = (w32[s >> 1] >> (16 * (s & 1))) & 0xffffu;
+      if (w) {
+        const int j = (int)(w & 31u), p = (int)((w >> 5) & 31u);
+        col[p * st] += col[j * st];
+      }
+    }
   }
 }
 
@@ -769,10 +801,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   }
   wsync();
   // ---- subtree sums of forces (6 columns) and composite inertias (10 columns)
-  {
-    real* col = (ln < 6) ? &E.F[0][ln] : &E.Ic[0][ln < 16 ? ln - 6 : 0];
-    tree_sum_cols(col, (ln < 6) ? 6 : 10, ln < 16, J, jr.par);
-  }
+  tree_sum_sched16(E, m->ts_steps, ln);
   wsync();
   // ---- bias into rhs; composite-inertia columns F_i = Ic_i S_i; root block of M
   if (ln < J) {

@@ -15,7 +15,7 @@ typedef GroupArgsT<real> GroupArgs;
 // Uniform model scalars, copied once per kernel into registers (the tables in global
 // memory are read only at kernel start).
 struct Scal {
-  int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
+  int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth, ts_steps;
   int n_mtu, n_motor, nck;
   real dt_sub, g, kn, kd, kt, mu, klim, chol_thr;
   real tau_act, fl_w, vmax;
@@ -25,7 +25,7 @@ __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   Scal s;
   s.J = m->J; s.nq = m->nq; s.nv = m->nv; s.na = m->na; s.nc = m->nc; s.ns = m->ns; s.od = m->od;
   s.task = m->task; s.floating = m->floating; s.has_last_action = m->has_last_action;
-  s.substeps = m->substeps; s.max_depth = m->max_depth;
+  s.substeps = m->substeps; s.max_depth = m->max_depth; s.ts_steps = m->ts_steps;
   s.dt_sub = m->dt_sub; s.g = m->g; s.kn = m->kn; s.kd = m->kd; s.kt = m->kt; s.mu = m->mu; s.klim = m->klim;
   s.chol_thr = m->chol_thr;
   s.n_mtu = m->n_mtu; s.n_motor = m->n_motor; s.nck = m->nck;

@@ -16,6 +16,7 @@
 #define SIM_MAXOBS 288   // observation width
 #define SIM_MAXHID 512   // MLP width
 #define SIM_MAXL 4       // MLP linear layers
+#define SIM_MAXTS 32     // steps of the scheduled subtree sums (a 32-frame chain needs 31)
 #define SIM_MAXPAIR 576  // (frame, ancestor-or-self) pairs of the mass matrix, 9 rounds of 64 lanes
 // linearisation tape of one substep: SIM_TAPE_REALS values (pre-substep state, frame
 // screws, velocities, bias accelerations and inertias, contact data, accelerations, new
@@ -43,6 +44,10 @@ struct DevModelT {
   T tau_act, fl_w, vmax;     // activation time constant, force-length width, max fibre speed (l_opt/s)
   int parent[SIM_MAXJ], jtype[SIM_MAXJ], qadr[SIM_MAXJ], vadr[SIM_MAXJ], depth[SIM_MAXJ];
   int first_child[SIM_MAXJ], next_sib[SIM_MAXJ], act_of_joint[SIM_MAXJ], limited[SIM_MAXJ];
+  // schedule of the forward subtree sums: at step s lane group g adds frame j into its parent p,
+  // ts_edge[g][s] = j | p << 5 | 1 << 10 (0: nothing); ts_steps steps
+  unsigned short ts_edge[4][SIM_MAXTS];
+  int ts_steps;
   T offset[SIM_MAXJ * 3], axis[SIM_MAXJ * 3], mass[SIM_MAXJ], com[SIM_MAXJ * 3];
   T inertia[SIM_MAXJ * 6];   // xx yy zz xy xz yz about the COM, frame axes
   T lower[SIM_MAXJ], upper[SIM_MAXJ], gear[SIM_MAXJ];
