@@ -182,6 +182,11 @@ typedef struct SimForwardIO {
   void* value;                              /* [N] out: critic value of s_h */
   uint8_t* nonfinite;                       /* [N] out, optional: 1 if s_h is not finite */
   int32_t* fp64_refactor_count;             /* [N] out, optional: substeps refactorised in FP64 */
+  /* Stochastic policy (Sec. 3.3: a_t ~ N(mu(s_t), sigma), sampled by reparameterisation):
+   * with both set, the pre-squash policy output is y_t = mu(o_t) + exp(log_std) * eps_t and
+   * the action squash(y_t); both null = the deterministic policy.  Closed loop only. */
+  const void* noise;                        /* [h][N][na] standard normal draws eps, or NULL */
+  const void* log_std;                      /* [na], or NULL */
 } SimForwardIO;
 
 typedef struct SimAdjointIO {
@@ -206,6 +211,11 @@ typedef struct SimAdjointIO {
                                                (d pi / d theta)^T dL/da_t, flat in layer order
                                                W_0 [out][in], b_0, W_1, b_1, ...; bitwise
                                                reproducible for a given handle */
+  const void* noise;                        /* as given to the forward (stochastic policy), or NULL */
+  const void* log_std;                      /* as given to the forward, or NULL */
+  void* dL_dlog_std;                        /* [na] optional out (with dL_dtheta and noise): the
+                                               sum over frames and envs of dL/dy_t * exp(log_std)
+                                               * eps_t; bitwise reproducible */
 } SimAdjointIO;
 
 /* Validates the model and options and uploads the constant tables to the current device.

@@ -137,7 +137,7 @@ def _layers(params):
 
 
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
-                  keep_graph=False, layers=None, action_offset=None, bf16=False):
+                  keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
@@ -145,6 +145,8 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     action_offset: optional [h, B, na] added to each action (used by finite-difference
     checks of dL/da_t).
     bf16: evaluate actor and critic with BF16 weights and layer inputs (mlp_forward_bf16).
+    noise [h, B, na], log_std [na]: the stochastic policy a_t ~ N(mu(s_t), sigma) sampled by
+    reparameterisation (Sec. 3.3): the pre-squash output is mu(o_t) + exp(log_std) noise_t.
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
     s = s0 if torch.is_tensor(s0) else _t(s0)
@@ -161,7 +163,11 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     for t in range(h):
         o = obs_fn(m, s)
         if actions is None:
-            a = squash(m, mlp(act_l, o))
+            y = mlp(act_l, o)
+            if noise is not None:
+                ls = log_std if torch.is_tensor(log_std) else _t(log_std)
+                y = y + torch.exp(ls) * (noise[t] if torch.is_tensor(noise) else _t(noise[t]))
+            a = squash(m, y)
         else:
             a = actions[t] if torch.is_tensor(actions[t]) else _t(actions[t])
         if action_offset is not None:
@@ -193,7 +199,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
-                        n_total=None, want_theta=False, bf16=False):
+                        n_total=None, want_theta=False, bf16=False, noise=None, log_std=None):
     """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
 
     Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
@@ -209,13 +215,18 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
     act_in = None
     if actions is not None:
         act_in = [_t(actions[t]).clone().requires_grad_(True) for t in range(h)]
+    ls = None
+    if noise is not None:
+        ls = _t(log_std).clone().requires_grad_(want_theta)
     out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
-                        layers=layers, bf16=bf16)
+                        layers=layers, bf16=bf16, noise=noise, log_std=ls)
     wrt = [s0t] + list(out["actions"])
     theta = []
     if want_theta and actor is not None:
         for (W, b) in layers[0]:
             theta += [W, b]
+        if ls is not None:
+            theta.append(ls)
     g = torch.autograd.grad(out["loss"], wrt + theta, allow_unused=True)
     gs0 = g[0]
     ga = torch.stack([x if x is not None else torch.zeros_like(out["actions"][0])
@@ -233,6 +244,9 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
     )
     if want_theta and actor is not None:
         gt = g[1 + h:]
+        if ls is not None:
+            res["dL_dlog_std"] = gt[-1].numpy()
+            gt = gt[:-1]
         res["dL_dtheta"] = [(gt[2 * i].numpy(), gt[2 * i + 1].numpy())
                             for i in range(len(gt) // 2)]
     return res

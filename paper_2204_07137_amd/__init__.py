@@ -49,7 +49,8 @@ class SimForwardIO(ctypes.Structure):
     _fields_ = [("s0", _p), ("actions_in", _p), ("actor_w", _p * MAXL), ("actor_b", _p * MAXL),
                 ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("workspace", _p),
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
-                ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p)]
+                ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p),
+                ("noise", _p), ("log_std", _p)]
 
 
 class SimAdjointIO(ctypes.Structure):
@@ -57,7 +58,7 @@ class SimAdjointIO(ctypes.Structure):
                 ("actor_w", _p * MAXL), ("actor_b", _p * MAXL), ("critic_w", _p * MAXL),
                 ("critic_b", _p * MAXL), ("workspace", _p), ("workspace_bytes", ctypes.c_size_t),
                 ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p),
-                ("dL_dtheta", _p)]
+                ("dL_dtheta", _p), ("noise", _p), ("log_std", _p), ("dL_dlog_std", _p)]
 
 
 class SimTuneResult(ctypes.Structure):
@@ -252,15 +253,16 @@ class Sim:
     def _ptr(t):
         return _p(t.data_ptr()) if t is not None else _p(0)
 
-    def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None):
-        """Run sim_forward_window.  Returns a dict of device tensors."""
-        out, io = self.forward_io(s0, actor, critic, actions_in)
+    def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None, noise=None, log_std=None):
+        """Run sim_forward_window.  Returns a dict of device tensors.  noise [h, N, na] and
+        log_std [na] select the stochastic policy y = mu(o) + exp(log_std) * noise."""
+        out, io = self.forward_io(s0, actor, critic, actions_in, noise=noise, log_std=log_std)
         t = self.torch
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
         return out
 
-    def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None):
+    def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None, noise=None, log_std=None):
         """Allocate the forward outputs (or reuse those of `out`, a previous result) and
         fill a SimForwardIO (no launch)."""
         t = self.torch
@@ -290,6 +292,12 @@ class Sim:
             assert actions_in.shape == (H, N, self.na)
             out["actions_in"] = actions_in
             io.actions_in = self._ptr(actions_in)
+        if noise is not None:
+            noise = self._dev(noise)
+            log_std = self._dev(log_std)
+            assert noise.shape == (H, N, self.na) and log_std.shape == (self.na,)
+            out["noise"], out["log_std"] = noise, log_std
+            io.noise, io.log_std = self._ptr(noise), self._ptr(log_std)
         self._set_weights(io, actor, critic, out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
@@ -352,6 +360,13 @@ class Sim:
         io.loss_scale = float(1.0 / (N * H) if loss_scale is None else loss_scale)
         io.dL_da = self._ptr(out["dL_da"])
         io.dL_ds0 = self._ptr(out["dL_ds0"])
+        if "noise" in fw:
+            io.noise, io.log_std = self._ptr(fw["noise"]), self._ptr(fw["log_std"])
+            if want_theta:
+                g = (prev["dL_dlog_std"] if prev is not None and "dL_dlog_std" in prev
+                     else t.empty(self.na, device="cuda", dtype=dt))
+                out["dL_dlog_std"] = g
+                io.dL_dlog_std = self._ptr(g)
         if want_theta:
             dims = self.actor_dims
             n = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))

@@ -492,6 +492,8 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.scale = (T)(1.0 / ((double)o.n_envs * o.horizon));
   A.s0 = static_cast<const T*>(io->s0);
   A.actions_in = static_cast<const T*>(io->actions_in);
+  A.noise = static_cast<const T*>(io->noise);
+  A.log_std = static_cast<const T*>(io->log_std);
   int rc;
   if (o.closed_loop) {
     rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off,
@@ -570,6 +572,10 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
   P.d1 = reinterpret_cast<T*>(ws + h->off_th_d1);
   P.part = reinterpret_cast<T*>(ws + h->off_th_part);
   P.out = static_cast<T*>(io->dL_dtheta);
+  P.mtu = (h->m64.task == TASK_MTU) ? 1 : 0;
+  P.noise = static_cast<const T*>(io->noise);
+  P.log_std = static_cast<const T*>(io->log_std);
+  P.out_log_std = static_cast<T*>(io->dL_dlog_std);
 }
 
 // ---------------------------------------------------------------- launches (FP32 / FP64)
@@ -639,6 +645,9 @@ static int check_forward_io(SimHandle* h, const SimForwardIO* io) {
   if (!io->s0 || !io->s_h || !io->obs || !io->actions || !io->rewards || !io->value)
     return fail(SIM_E_ARG, "sim_forward_window: null input/output pointer");
   if (!o.closed_loop && !io->actions_in) return fail(SIM_E_ARG, "open loop needs actions_in");
+  if ((io->noise != nullptr) != (io->log_std != nullptr))
+    return fail(SIM_E_ARG, "the stochastic policy needs both noise and log_std");
+  if (io->noise && !o.closed_loop) return fail(SIM_E_ARG, "noise needs the closed-loop policy");
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
   return SIM_OK;
@@ -657,6 +666,10 @@ static int check_adjoint_io(SimHandle* h, const SimAdjointIO* io) {
     for (int l = 0; l < o.actor_layers; ++l)
       if (!io->actor_w[l] || !io->actor_b[l]) return fail(SIM_E_ARG, "dL_dtheta needs the actor weights");
   }
+  if ((io->noise != nullptr) != (io->log_std != nullptr))
+    return fail(SIM_E_ARG, "the stochastic policy needs both noise and log_std");
+  if (io->dL_dlog_std && (!io->dL_dtheta || !io->noise))
+    return fail(SIM_E_ARG, "dL_dlog_std needs dL_dtheta and the forward's noise and log_std");
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
   return SIM_OK;

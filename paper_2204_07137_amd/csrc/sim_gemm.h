@@ -127,13 +127,34 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
       }
 }
 
-// adjoint of the pre-squash policy output: dL/dy = dL/da (1 - a^2)
-__global__ void k_theta_seed(const real* __restrict__ da, const real* __restrict__ a, real* __restrict__ d, long n) {
+// adjoint of the pre-squash policy output: dL/dy = dL/da da/dy with a = tanh(y) (1 - a^2)
+// or, for muscle excitations, u = (tanh(y) + 1) / 2 (2 u (1 - u))
+__global__ void k_theta_seed(const real* __restrict__ da, const real* __restrict__ a, real* __restrict__ d, long n,
+                             int mtu) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const real av = a[i];
-    d[i] = da[i] * (RL(1.0) - av * av);
+    d[i] = da[i] * (mtu ? RL(2.0) * av * (RL(1.0) - av) : RL(1.0) - av * av);
   }
+}
+
+// dL/dlog_std[i] = sum over rows of dL/dy[row][i] exp(log_std[i]) eps[row][i] (the
+// reparameterised sample y = mu + exp(log_std) eps); one block per action, a fixed-order
+// tree over 256 per-thread partial sums, so the result is reproducible
+__global__ __launch_bounds__(256) void k_log_std_grad(const real* __restrict__ d, const real* __restrict__ eps,
+                                                      const real* __restrict__ log_std, long rows, int na,
+                                                      real* __restrict__ out) {
+  __shared__ real part[256];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  real s = RL(0.0);
+  for (long r = tid; r < rows; r += 256) s += d[r * na + i] * eps[r * na + i];
+  part[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) out[i] = part[0] * m_exp(log_std[i]);
 }
 
 // sum of the split partials in split order; column `in` of each row is the bias gradient
@@ -171,7 +192,11 @@ int launch_theta(const ThetaArgsT<real>& T, void* stream) {
   }
   const int na = T.dims[L];
   const long nseed = (long)M * na;
-  hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed);
+  hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed,
+                     T.mtu);
+  if (T.noise && T.out_log_std)
+    hipLaunchKernelGGL(k_log_std_grad, dim3(na), dim3(256), 0, s, T.d0, T.noise, T.log_std, (long)M, na,
+                       T.out_log_std);
   real* dcur = T.d0;
   real* dnext = T.d1;
   const int chunk = ((M + T.splits - 1) / T.splits + GT_K - 1) / GT_K * GT_K;

@@ -53,7 +53,13 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
   if (A.closed_loop) {
     mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
-    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, E.y[i]);
+    if (A.noise) {
+      // stochastic policy, reparameterised (Sec. 3.3): y = mu(o) + exp(log_std) * eps
+      const real* ep = A.noise + ((size_t)t * N + env) * na;
+      for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, m_fma(m_exp(A.log_std[i]), ep[i], E.y[i]));
+    } else {
+      for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, E.y[i]);
+    }
   } else {
     const real* ai = A.actions_in + ((size_t)t * N + env) * na;
     for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = ai[i];

@@ -87,6 +87,8 @@ struct WinArgsT {
   T gamma, scale;
   const T* s0;
   const T* actions_in;
+  const T* noise;   // [h][N][na] standard normal draws of the stochastic policy, or null
+  const T* log_std; // [na] log of the policy's standard deviation (with noise)
   MlpArgsT<T> actor, critic;
   T* s_h;
   T* obs;
@@ -132,6 +134,10 @@ struct ThetaArgsT {
   const T* x0;                // [M][dims[0]] observations o_0 .. o_{h-1}
   const T* act;               // [M][na] actions
   const T* da;                // [M][na] dL/da
+  int mtu;                    // muscle task: actions u = (tanh(y) + 1) / 2, else a = tanh(y)
+  const T* noise;             // [M][na] draws of the stochastic policy, or null
+  const T* log_std;           // [na]
+  T* out_log_std;             // [na] dL/dlog_std (with noise), or null
   T* H[SIM_MAXL];             // H[l] (l >= 1): [M][dims[l]] hidden activations
   T* d0;                      // [M][max dim] layer adjoints (ping-pong)
   T* d1;

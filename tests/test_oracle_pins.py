@@ -834,3 +834,28 @@ def test_bf16_linear_backward_is_rounded_transpose_product():
     assert torch.equal(y.detach(), bf16_round(x.detach()) @ bf16_round(W).T + b)
     assert torch.equal(x.grad, bf16_round(gy) @ bf16_round(W))
     assert torch.allclose(Wg.grad, gy.T @ bf16_round(x.detach()), rtol=1e-15, atol=0)
+
+
+def test_stochastic_policy_zero_sigma_and_log_std_gradient():
+    """Stochastic policy of the oracle (reparameterised sample mu + exp(log_std) eps):
+    sigma -> 0 gives the deterministic window, and dL/dlog_std from reverse mode agrees
+    with central differences of the loss in log_std."""
+    import workloads as wl
+    from oracle import oracle_window, oracle_window_grads
+    W = wl.workload("cartpole", 4)
+    h = 6
+    rng = np.random.default_rng(21)
+    eps = rng.standard_normal((h, 4, 1))
+    det = oracle_window(W["model"], W["s0"], h, W["actor"], W["critic"])
+    zero = oracle_window(W["model"], W["s0"], h, W["actor"], W["critic"], noise=eps,
+                         log_std=np.array([-np.inf]))
+    assert float(det["loss"]) == float(zero["loss"])
+    ls = np.array([-0.7])
+    g = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], want_theta=True,
+                            noise=eps, log_std=ls)
+    e = 1e-6
+    lp = float(oracle_window(W["model"], W["s0"], h, W["actor"], W["critic"], noise=eps, log_std=ls + e)["loss"])
+    lm = float(oracle_window(W["model"], W["s0"], h, W["actor"], W["critic"], noise=eps, log_std=ls - e)["loss"])
+    fd = (lp - lm) / (2 * e)
+    assert abs(g["dL_dlog_std"][0] - fd) <= 1e-6 * max(1.0, abs(fd))
+    assert abs(fd) > 1e-8
