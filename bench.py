@@ -140,19 +140,20 @@ def copy_probe():
           flush=True)
 
 
-def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False):
+def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False, noise=None, log_std=None):
     """Forward + adjoint windows; per-launch HIP-event times on torch's current stream
-    (the stream the window kernels are launched on) and the wall time of the timed loop."""
+    (the stream the window kernels are launched on) and the wall time of the timed loop.
+    noise / log_std select the stochastic policy."""
     import torch
     for _ in range(warmup):
-        fw = sim.forward(s0, actor, critic)
+        fw = sim.forward(s0, actor, critic, noise=noise, log_std=log_std)
         sim.adjoint(fw, want_theta=want_theta)
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
         ev[i][0].record()
-        fw = sim.forward(s0, actor, critic)
+        fw = sim.forward(s0, actor, critic, noise=noise, log_std=log_std)
         ev[i][1].record()
         ad = sim.adjoint(fw, want_theta=want_theta)
         ev[i][2].record()
@@ -360,6 +361,15 @@ def main():
         out["policy_grad"] = {"ms": round(th_ms, 3), "rows": rows,
                               "mfma_tflops": round(th_flops / max(th_ms, 1e-6) / 1e9, 3),
                               "mfma_peak_fp32_tflops": 157.3}
+
+    # the same window under the stochastic policy (reparameterised Gaussian, draws as inputs)
+    rng = np.random.default_rng(7)
+    noise = torch.as_tensor(rng.standard_normal((h, N, md["na"])), dtype=torch.float32, device="cuda")
+    log_std = torch.full((md["na"],), -1.0, dtype=torch.float32, device="cuda")
+    sw, _, _, _, _ = time_windows(sim, s0, actor, critic, max(3, args.steps // 4), 1, noise=noise, log_std=log_std)
+    sval = N * h / (sw / max(3, args.steps // 4))
+    out["stochastic_policy"] = {"value": round(sval, 1), "unit": "env-steps/s", "log_std": -1.0,
+                                "vs_deterministic": round(sval / value, 3)}
 
     if not args.no_plain:
         # the same window on the other launch forms: the tape path (the forward records
