@@ -123,6 +123,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-morphology batch")
     ap.add_argument("--no-mtu", action="store_true", help="skip the muscle-driven humanoid")
+    ap.add_argument("--no-long", action="store_true", help="skip the long-window (h up to 256) section")
     return ap.parse_args()
 
 
@@ -274,6 +275,44 @@ def grad_err(a, b, per_env_axis=None):
     return out
 
 
+def long_windows(P, wl, torch, n_envs=256, horizons=(32, 64, 128, 256)):
+    """BPTT-style long windows of the humanoid (checkpointed, k = 16): FP32 throughput and
+    workspace, and the norms of the policy-parameter gradient and of dL/ds0 as the horizon
+    grows, from the FP64 kernels (FP32 overflows once they pass ~1e38)."""
+    W = wl.workload("humanoid", n_envs)
+    md = W["model"]
+    od = W["obs_dim"]
+    dims = ([od] + [w.shape[0] for w, _ in W["actor"]], [od] + [w.shape[0] for w, _ in W["critic"]])
+
+    def norm(x):
+        v = float(x.double().norm())
+        return v if np.isfinite(v) else "non-finite"
+
+    res = []
+    for h in horizons:
+        row = {"h": h}
+        for prec in ("fp32", "fp64"):
+            sim = P.Sim(md, n_envs, h, dims[0], dims[1], ckpt_interval=16, policy_grad=True, precision=prec)
+            s0 = sim._dev(W["s0"])
+            actor, critic = sim.weights(W["actor"]), sim.weights(W["critic"])
+            wall, _, _, fw, ad = time_windows(sim, s0, actor, critic, 1, 1, want_theta=True)
+            if prec == "fp32":
+                row["env_steps_per_s"] = round(n_envs * h / wall, 1)
+                row["workspace_gb"] = round(sim.ws_bytes / 1e9, 3)
+                row["fp32_grad_theta_norm"] = norm(ad["dL_dtheta_flat"])
+            else:
+                row["grad_theta_norm"] = norm(ad["dL_dtheta_flat"])
+                row["grad_s0_norm"] = norm(ad["dL_ds0"])
+                row["envs_nonfinite_state"] = int(fw["nonfinite"].sum())
+                finite_env = torch.isfinite(ad["dL_ds0"]).all(1)
+                row["grad_s0_norm_finite_envs"] = norm(ad["dL_ds0"][finite_env])
+                row["envs_nonfinite_grad"] = int((~finite_env).sum())
+            sim.close()
+        res.append(row)
+    return {"workload": f"humanoid {n_envs} envs, k=16, policy-parameter gradient; norms from the FP64 "
+                        f"kernels, throughput in FP32", "windows": res}
+
+
 def cpu_baseline(W, h, n_envs_sample=2):
     """The FP64 oracle (CPU, PyTorch) on a bounded sample of the same workload."""
     import torch
@@ -423,6 +462,8 @@ def main():
                        "published_hbm_gbs": HBM_PEAK_GBS}
     roof["frac_of_measured"] = round(achieved / ceil["fp32_valu_tflops"], 5)
 
+    if not args.no_long:
+        out["long_windows"] = long_windows(P, wl, torch)
     if not args.no_mtu:
         out["mtu"] = mtu_window(P, wl, torch)
     if not args.no_mixed:

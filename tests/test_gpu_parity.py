@@ -344,3 +344,16 @@ def test_fp64_fallback_factorisation():
     fw2 = sim2.forward(W["s0"], W["actor"], W["critic"])
     torch.cuda.synchronize()
     assert int(fw2["fp64_refactor_count"].sum()) == 0
+
+
+def test_long_window_fp64_matches_oracle():
+    """A BPTT-style long window (h = 128 frames, 512 substeps) through the checkpointed
+    path: the FP64 kernels against the oracle (CartPole, low sensitivity)."""
+    W = wl.workload("cartpole", 4)
+    h = 128
+    print("[long] cartpole h=128 fp64", flush=True)
+    sim, f, a = run(dict(W, n_envs=4), h, k=4, precision="fp64")
+    ref = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"])
+    assert relnorm(f["s_h"], ref["s_h"]) < 1e-10
+    assert relnorm(a["dL_da"], ref["dL_da"]) < 1e-9
+    assert relnorm(a["dL_ds0"], ref["dL_ds0"]) < 1e-9
