@@ -297,6 +297,67 @@ size_t sim_probe_fma_bytes(void);
 int sim_probe_fma(void* scratch, size_t scratch_bytes, void* hip_stream, double* tflops);
 int sim_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stream, double* gbs);
 
+/* ---- Learning-episode update (Sec. 3.3, Algorithm "SHAC" and Eqs. "critic_loss",
+ * "td-lambda"; hyperparameters of App. A.2).  The calls that follow a window: one Adam step
+ * of the policy on dL_dtheta, TD-lambda estimates of the window's states from the target
+ * critic, the critic's mean-squared-error fit over shuffled minibatches with Adam, and the
+ * smooth update of the target critic.  Pointers are device pointers unless stated;
+ * `precision` (SIM_PREC_FP32 / SIM_PREC_FP64) is the element type of the float buffers.
+ * Argument errors return SIM_E_ARG before any launch; failed launches SIM_E_HIP. */
+#define SIM_MAX_TENSORS 16
+
+/* Adam (Kingma and Ba) on n_tensors (<= SIM_MAX_TENSORS) parameter tensors: tensors and sizes
+ * are host arrays (device pointers, element counts); grad, m and v are flat device arrays of
+ * sum(sizes) elements in tensor order (for the actor: the layout of dL_dtheta, W_0, b_0, W_1,
+ * b_1, ...); step is this step's 1-based index (bias correction); m and v are updated. */
+int sim_adam_step(void* const* tensors, const size_t* sizes, int n_tensors, const void* grad, void* m,
+                  void* v, int step, double lr, double beta1, double beta2, double eps, int precision,
+                  void* hip_stream);
+
+/* target_i <- alpha target_i + (1 - alpha) online_i, elementwise per tensor (host arrays of
+ * device pointers and element counts). */
+int sim_soft_update(void* const* target, const void* const* online, const size_t* sizes, int n_tensors,
+                    double alpha, int precision, void* hip_stream);
+
+/* TD-lambda estimates: rewards [h][N]; values [h+1][N], the target critic at the window's
+ * states s_0 .. s_h (s_0's value is not used); out targets [h][N]. */
+int sim_td_lambda(const void* rewards, const void* values, int h, int n_envs, double gamma, double lambda,
+                  void* targets, int precision, void* hip_stream);
+
+/* The critic calls use the handle's critic shape and precision and a caller-owned workspace
+ * of at least sim_critic_workspace_bytes(h, rows) bytes (rows: the most rows of one call). */
+size_t sim_critic_workspace_bytes(const SimHandle* h, int rows);
+
+/* values [rows] = V(obs [rows][obs_dim]) with the given critic weights (host arrays of device
+ * pointers, W [out][in], b [out]). */
+int sim_critic_values(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
+                      const void* const* critic_b, void* values, void* workspace, size_t workspace_bytes,
+                      void* hip_stream);
+
+typedef struct SimCriticFitIO {
+  const void* obs;              /* [rows][obs_dim] states of the window (o_0 .. o_{h-1}) */
+  const void* targets;          /* [rows] their TD-lambda estimates (treated as constants) */
+  int rows;
+  const int32_t* perm;          /* [n_iter][rows] permutations of 0 .. rows-1 (device) */
+  int n_iter;                   /* passes over the rows */
+  int n_minibatch;              /* minibatches per pass: rows [mb rows / n, (mb + 1) rows / n) of perm */
+  void* critic_w[SIM_MAX_LAYERS];   /* the critic being fitted, updated in place */
+  void* critic_b[SIM_MAX_LAYERS];
+  void* adam_m;                 /* flat Adam moments of the critic (W_0, b_0, W_1, ...) */
+  void* adam_v;
+  int adam_step;                /* Adam steps taken before this call */
+  double lr, beta1, beta2, eps;
+  void* loss_out;               /* [n_iter * n_minibatch] optional: each minibatch's mean squared
+                                   error before its step */
+  void* workspace;
+  size_t workspace_bytes;
+} SimCriticFitIO;
+
+/* Fits the critic: for every pass and minibatch, the mean of (V(o) - target)^2 over the
+ * minibatch, its gradient through the critic's layers, one Adam step.  The order of the
+ * reductions is fixed, so the result is bitwise reproducible. */
+int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* sim_last_error(void);
 

@@ -1,0 +1,81 @@
+"""FP64 oracle of the learning-episode update (TEST INFRASTRUCTURE ONLY): the steps of the
+SHAC algorithm that follow a window (Sec. 3.3, Algorithm "SHAC" and Eqs. "critic_loss" and
+"td-lambda"), written in their defining form.
+
+* td_lambda: the estimate of Eq. "td-lambda", the lambda-weighted average of the k-step
+  returns G_t^k = sum_{l<k} gamma^l r_{t+l} + gamma^k V(s_{t+k}), summed term by term.
+* adam_step: Adam (Kingma and Ba) with bias-corrected moments.
+* critic_fit: the mean squared error of Eq. "critic_loss" over each minibatch of a shuffled
+  pass, its gradient by reverse mode, one Adam step per minibatch.
+* soft_update: the target critic update of the algorithm, alpha V' + (1 - alpha) V.
+"""
+import torch
+
+from .window import mlp_forward
+
+F64 = torch.float64
+
+
+def _t(x):
+    return x.detach().to(F64) if torch.is_tensor(x) else torch.as_tensor(x, dtype=F64)
+
+
+def td_lambda(rewards, values, gamma, lam):
+    """rewards [h, N], values [h+1, N] (V(s_0) .. V(s_h)) -> estimates [h, N]."""
+    r, v = _t(rewards), _t(values)
+    h = r.shape[0]
+    out = torch.zeros_like(r)
+    for t in range(h):
+        n = h - t
+
+        def G(k):
+            return sum(gamma ** l * r[t + l] for l in range(k)) + gamma ** k * v[t + k]
+        est = sum((1.0 - lam) * lam ** (k - 1) * G(k) for k in range(1, n))
+        out[t] = est + lam ** (n - 1) * G(n)
+    return out
+
+
+def adam_step(params, grads, m, v, step, lr, beta1, beta2, eps):
+    """One Adam step; returns (params, m, v) as new lists."""
+    P, M, V = [], [], []
+    for p, g, mm, vv in zip(params, grads, m, v):
+        p, g, mm, vv = _t(p), _t(g), _t(mm), _t(vv)
+        mm = beta1 * mm + (1.0 - beta1) * g
+        vv = beta2 * vv + (1.0 - beta2) * g * g
+        mhat = mm / (1.0 - beta1 ** step)
+        vhat = vv / (1.0 - beta2 ** step)
+        P.append(p - lr * mhat / (torch.sqrt(vhat) + eps))
+        M.append(mm)
+        V.append(vv)
+    return P, M, V
+
+
+def soft_update(target, online, alpha):
+    return [alpha * _t(a) + (1.0 - alpha) * _t(b) for a, b in zip(target, online)]
+
+
+def critic_values(layers, obs):
+    return mlp_forward([(_t(W), _t(b)) for W, b in layers], _t(obs))[:, 0]
+
+
+def critic_fit(layers, obs, targets, perm, n_minibatch, m, v, adam_step0, lr, beta1, beta2, eps):
+    """layers [(W, b)], obs [rows, od], targets [rows], perm [n_iter, rows]; m, v lists shaped
+    like the parameters (W_0, b_0, W_1, ...).  Returns (layers, m, v, losses)."""
+    params = [x for W, b in layers for x in (_t(W), _t(b))]
+    m = [_t(x) for x in m]
+    v = [_t(x) for x in v]
+    obs, targets = _t(obs), _t(targets)
+    rows = obs.shape[0]
+    step = adam_step0
+    losses = []
+    for it in range(len(perm)):
+        for mb in range(n_minibatch):
+            idx = torch.as_tensor(perm[it][mb * rows // n_minibatch:(mb + 1) * rows // n_minibatch], dtype=torch.long)
+            ps = [p.clone().requires_grad_(True) for p in params]
+            V = mlp_forward([(ps[2 * i], ps[2 * i + 1]) for i in range(len(ps) // 2)], obs[idx])[:, 0]
+            loss = ((V - targets[idx]) ** 2).mean()
+            grads = torch.autograd.grad(loss, ps)
+            losses.append(float(loss))
+            step += 1
+            params, m, v = adam_step(params, grads, m, v, step, lr, beta1, beta2, eps)
+    return [(params[2 * i], params[2 * i + 1]) for i in range(len(params) // 2)], m, v, losses

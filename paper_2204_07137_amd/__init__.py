@@ -66,10 +66,19 @@ class SimTuneResult(ctypes.Structure):
                 ("ms_window", _d), ("n_candidates", _i)]
 
 
+class SimCriticFitIO(ctypes.Structure):
+    _fields_ = [("obs", _p), ("targets", _p), ("rows", _i), ("perm", _p), ("n_iter", _i), ("n_minibatch", _i),
+                ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("adam_m", _p), ("adam_v", _p),
+                ("adam_step", _i), ("lr", _d), ("beta1", _d), ("beta2", _d), ("eps", _d), ("loss_out", _p),
+                ("workspace", _p), ("workspace_bytes", ctypes.c_size_t)]
+
+
 EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
            "sim_adjoint_window", "sim_destroy", "sim_last_error", "sim_group_create",
            "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
-           "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy"]
+           "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy", "sim_adam_step",
+           "sim_soft_update", "sim_td_lambda", "sim_critic_workspace_bytes", "sim_critic_values",
+           "sim_critic_fit"]
 MAX_GROUP = 6
 
 _LIB = None
@@ -116,6 +125,20 @@ def lib():
         L.sim_probe_fma.restype = _i
         L.sim_probe_copy.argtypes = [_p, _p, ctypes.c_size_t, _p, ctypes.POINTER(_d)]
         L.sim_probe_copy.restype = _i
+        L.sim_adam_step.argtypes = [ctypes.POINTER(_p), ctypes.POINTER(ctypes.c_size_t), _i, _p, _p, _p, _i,
+                                    _d, _d, _d, _d, _i, _p]
+        L.sim_adam_step.restype = _i
+        L.sim_soft_update.argtypes = [ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(ctypes.c_size_t), _i,
+                                      _d, _i, _p]
+        L.sim_soft_update.restype = _i
+        L.sim_td_lambda.argtypes = [_p, _p, _i, _i, _d, _d, _p, _i, _p]
+        L.sim_td_lambda.restype = _i
+        L.sim_critic_workspace_bytes.argtypes = [_p, _i]
+        L.sim_critic_workspace_bytes.restype = ctypes.c_size_t
+        L.sim_critic_values.argtypes = [_p, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _p, ctypes.c_size_t, _p]
+        L.sim_critic_values.restype = _i
+        L.sim_critic_fit.argtypes = [_p, ctypes.POINTER(SimCriticFitIO), _p]
+        L.sim_critic_fit.restype = _i
         _LIB = L
     return _LIB
 
@@ -226,6 +249,52 @@ class Sim:
         self.N, self.H = int(n_envs), int(horizon)
         self.ws_bytes = int(L.sim_workspace_bytes(h))
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+
+    def critic_workspace(self, rows):
+        """A device workspace for critic_values / critic_fit on up to `rows` rows."""
+        n = int(lib().sim_critic_workspace_bytes(self.h, int(rows)))
+        return self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
+
+    def critic_values(self, obs, critic, workspace=None):
+        """sim_critic_values: V(obs) for obs [rows, obs_dim] with critic [(W, b), ...] (device)."""
+        t = self.torch
+        obs = self._dev(obs).reshape(-1, self.od)
+        rows = obs.shape[0]
+        ws = workspace if workspace is not None else self.critic_workspace(rows)
+        cw = self.weights(critic)
+        w = (_p * MAXL)(*([_p(W.data_ptr()) for W, _ in cw] + [_p(0)] * (MAXL - len(cw))))
+        b = (_p * MAXL)(*([_p(B.data_ptr()) for _, B in cw] + [_p(0)] * (MAXL - len(cw))))
+        out = t.empty(rows, device="cuda", dtype=self.dtype)
+        _check(lib().sim_critic_values(self.h, _p(obs.data_ptr()), rows, w, b, _p(out.data_ptr()),
+                                       _p(ws.data_ptr()), ws.numel(), _stream()))
+        return out
+
+    def critic_fit(self, obs, targets, perm, n_minibatch, critic, adam_m, adam_v, adam_step, lr,
+                   beta1=0.7, beta2=0.95, eps=1e-8, workspace=None):
+        """sim_critic_fit: fits `critic` (a list of device (W, b) tensors of this handle's dtype,
+        updated in place) to targets [rows] on obs [rows, obs_dim] over len(perm) passes of
+        n_minibatch minibatches (perm [n_iter, rows] int32).  Returns the minibatch losses."""
+        t = self.torch
+        obs = self._dev(obs).reshape(-1, self.od)
+        targets = self._dev(targets).reshape(-1)
+        rows = obs.shape[0]
+        perm = perm.to(device="cuda", dtype=t.int32).contiguous()
+        n_iter = perm.shape[0]
+        ws = workspace if workspace is not None else self.critic_workspace(rows)
+        losses = t.empty(n_iter * n_minibatch, device="cuda", dtype=self.dtype)
+        io = SimCriticFitIO()
+        io.obs, io.targets, io.rows = _p(obs.data_ptr()), _p(targets.data_ptr()), rows
+        io.perm, io.n_iter, io.n_minibatch = _p(perm.data_ptr()), n_iter, int(n_minibatch)
+        for i, (W, B) in enumerate(critic):
+            assert W.dtype == self.dtype and W.is_cuda and W.is_contiguous() and B.is_contiguous()
+            io.critic_w[i] = W.data_ptr()
+            io.critic_b[i] = B.data_ptr()
+        io.adam_m, io.adam_v, io.adam_step = _p(adam_m.data_ptr()), _p(adam_v.data_ptr()), int(adam_step)
+        io.lr, io.beta1, io.beta2, io.eps = float(lr), float(beta1), float(beta2), float(eps)
+        io.loss_out = _p(losses.data_ptr())
+        io.workspace, io.workspace_bytes = _p(ws.data_ptr()), ws.numel()
+        _check(lib().sim_critic_fit(self.h, ctypes.byref(io), _stream()))
+        return losses
 
     def close(self):
         if getattr(self, "h", None):
@@ -468,6 +537,45 @@ def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget
     probe.close()
     return {"path": r.path, "ckpt_interval": r.ckpt_interval, "workspace_bytes": r.workspace_bytes,
             "ms_window": r.ms_window, "n_candidates": r.n_candidates, "keep": out}
+
+
+def _prec(t):
+    import torch
+    return {torch.float32: PREC["fp32"], torch.float64: PREC["fp64"]}[t.dtype]
+
+
+def _stream():
+    import torch
+    return _p(torch.cuda.current_stream().cuda_stream)
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.7, beta2=0.95, eps=1e-8):
+    """sim_adam_step: one Adam step on a list of device tensors whose gradient and moments are
+    the flat tensors grad, m, v (in list order); m and v are updated in place."""
+    n = len(params)
+    ptrs = (_p * n)(*[_p(t.data_ptr()) for t in params])
+    sizes = (ctypes.c_size_t * n)(*[t.numel() for t in params])
+    _check(lib().sim_adam_step(ptrs, sizes, n, _p(grad.data_ptr()), _p(m.data_ptr()), _p(v.data_ptr()), int(step),
+                               float(lr), float(beta1), float(beta2), float(eps), _prec(grad), _stream()))
+
+
+def soft_update(target, online, alpha):
+    """sim_soft_update: target_i <- alpha target_i + (1 - alpha) online_i for lists of tensors."""
+    n = len(target)
+    tp = (_p * n)(*[_p(t.data_ptr()) for t in target])
+    op = (_p * n)(*[_p(t.data_ptr()) for t in online])
+    sizes = (ctypes.c_size_t * n)(*[t.numel() for t in target])
+    _check(lib().sim_soft_update(tp, op, sizes, n, float(alpha), _prec(target[0]), _stream()))
+
+
+def td_lambda(rewards, values, gamma=0.99, lam=0.95):
+    """sim_td_lambda: TD-lambda estimates [h, N] from rewards [h, N] and values [h+1, N]."""
+    import torch
+    h, N = rewards.shape
+    out = torch.empty_like(rewards)
+    _check(lib().sim_td_lambda(_p(rewards.data_ptr()), _p(values.data_ptr()), h, N, float(gamma), float(lam),
+                               _p(out.data_ptr()), _prec(rewards), _stream()))
+    return out
 
 
 def probe_ceilings(copy_bytes=1 << 30):

@@ -9,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshacsim.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("shacsim_abi.hip", "kernels_f32.hip", "kernels_f64.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("sim_types.h", "sim_math.h", "sim_dynamics.h", "sim_task.h",
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("shacsim_abi.hip", "kernels_f32.hip", "kernels_f64.hip", "learn.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("sim_types.h", "sim_math.h", "sim_dynamics.h", "sim_task.h", "sim_gemm.h", "sim_learn.h",
                                                  "sim_kernels.h")] + [
     os.path.join(ROOT, "include", "shacsim.h")]
 

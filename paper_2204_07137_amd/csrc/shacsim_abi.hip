@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1051,4 +1052,228 @@ int sim_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stream, d
   *gbs = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
   g_err.clear();
   return SIM_OK;
+}
+
+// ======================================================================= learning-episode update
+static int learn_launch(float, const LearnAdamT<float>& A, void* s) { return sim_l32::launch_adam(A, s); }
+static int learn_launch(double, const LearnAdamT<double>& A, void* s) { return sim_l64::launch_adam(A, s); }
+static int soft_launch(float* t, const float* o, long n, double a, void* s) { return sim_l32::launch_soft_update(t, o, n, (float)a, s); }
+static int soft_launch(double* t, const double* o, long n, double a, void* s) { return sim_l64::launch_soft_update(t, o, n, a, s); }
+static int td_launch(const float* r, const float* v, int h, int N, double g, double l, float* out, void* s) {
+  return sim_l32::launch_td_lambda(r, v, h, N, (float)g, (float)l, out, s);
+}
+static int td_launch(const double* r, const double* v, int h, int N, double g, double l, double* out, void* s) {
+  return sim_l64::launch_td_lambda(r, v, h, N, g, l, out, s);
+}
+static int cv_launch(const ThetaArgsT<float>& T, float* out, void* s) { return sim_l32::launch_critic_values(T, out, s); }
+static int cv_launch(const ThetaArgsT<double>& T, double* out, void* s) { return sim_l64::launch_critic_values(T, out, s); }
+static int cf_launch(const CriticFitT<float>& F, void* s) { return sim_l32::launch_critic_fit(F, s); }
+static int cf_launch(const CriticFitT<double>& F, void* s) { return sim_l64::launch_critic_fit(F, s); }
+
+template <typename T>
+static int adam_impl(void* const* tensors, const size_t* sizes, int n, const void* grad, void* m, void* v, int step,
+                     double lr, double b1, double b2, double eps, void* stream) {
+  LearnAdamT<T> A;
+  std::memset(&A, 0, sizeof(A));
+  A.n = n;
+  for (int i = 0; i < n; ++i) {
+    A.p[i] = static_cast<T*>(tensors[i]);
+    A.size[i] = (long)sizes[i];
+  }
+  A.g = static_cast<const T*>(grad); A.m = static_cast<T*>(m); A.v = static_cast<T*>(v);
+  A.lr = (T)lr; A.b1 = (T)b1; A.b2 = (T)b2; A.eps = (T)eps;
+  A.bc1 = (T)(1.0 - std::pow(b1, (double)step));
+  A.bc2 = (T)(1.0 - std::pow(b2, (double)step));
+  if (learn_launch(T(), A, stream)) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" int sim_adam_step(void* const* tensors, const size_t* sizes, int n_tensors, const void* grad, void* m,
+                             void* v, int step, double lr, double beta1, double beta2, double eps, int precision,
+                             void* hip_stream) {
+  if (!tensors || !sizes || !grad || !m || !v || n_tensors < 1 || n_tensors > SIM_MAX_TENSORS)
+    return fail(SIM_E_ARG, "sim_adam_step: null pointer or tensor count outside 1..SIM_MAX_TENSORS");
+  for (int i = 0; i < n_tensors; ++i)
+    if (!tensors[i] || sizes[i] == 0) return fail(SIM_E_ARG, "sim_adam_step: null or empty tensor");
+  if (step < 1) return fail(SIM_E_ARG, "sim_adam_step: step counts from 1");
+  if (!(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return fail(SIM_E_ARG, "sim_adam_step: need lr >= 0, 0 <= beta < 1, eps > 0");
+  if (precision == SIM_PREC_FP32)
+    return adam_impl<float>(tensors, sizes, n_tensors, grad, m, v, step, lr, beta1, beta2, eps, hip_stream);
+  if (precision == SIM_PREC_FP64)
+    return adam_impl<double>(tensors, sizes, n_tensors, grad, m, v, step, lr, beta1, beta2, eps, hip_stream);
+  return fail(SIM_E_ARG, "sim_adam_step: unknown precision");
+}
+
+extern "C" int sim_soft_update(void* const* target, const void* const* online, const size_t* sizes, int n_tensors,
+                               double alpha, int precision, void* hip_stream) {
+  if (!target || !online || !sizes || n_tensors < 1 || n_tensors > SIM_MAX_TENSORS)
+    return fail(SIM_E_ARG, "sim_soft_update: null pointer or tensor count outside 1..SIM_MAX_TENSORS");
+  for (int i = 0; i < n_tensors; ++i)
+    if (!target[i] || !online[i] || sizes[i] == 0) return fail(SIM_E_ARG, "sim_soft_update: null or empty tensor");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(SIM_E_ARG, "sim_soft_update: alpha outside [0, 1]");
+  if (precision != SIM_PREC_FP32 && precision != SIM_PREC_FP64) return fail(SIM_E_ARG, "sim_soft_update: unknown precision");
+  int bad = 0;
+  for (int i = 0; i < n_tensors; ++i) {
+    if (precision == SIM_PREC_FP32)
+      bad |= soft_launch(static_cast<float*>(target[i]), static_cast<const float*>(online[i]), (long)sizes[i], alpha, hip_stream);
+    else
+      bad |= soft_launch(static_cast<double*>(target[i]), static_cast<const double*>(online[i]), (long)sizes[i], alpha, hip_stream);
+  }
+  if (bad) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" int sim_td_lambda(const void* rewards, const void* values, int h, int n_envs, double gamma, double lambda,
+                             void* targets, int precision, void* hip_stream) {
+  if (!rewards || !values || !targets || h < 1 || n_envs < 1) return fail(SIM_E_ARG, "sim_td_lambda: null pointer or empty window");
+  if (!(gamma >= 0.0 && gamma <= 1.0) || !(lambda >= 0.0 && lambda <= 1.0))
+    return fail(SIM_E_ARG, "sim_td_lambda: gamma and lambda must lie in [0, 1]");
+  int bad;
+  if (precision == SIM_PREC_FP32)
+    bad = td_launch(static_cast<const float*>(rewards), static_cast<const float*>(values), h, n_envs, gamma, lambda,
+                    static_cast<float*>(targets), hip_stream);
+  else if (precision == SIM_PREC_FP64)
+    bad = td_launch(static_cast<const double*>(rewards), static_cast<const double*>(values), h, n_envs, gamma, lambda,
+                    static_cast<double*>(targets), hip_stream);
+  else
+    return fail(SIM_E_ARG, "sim_td_lambda: unknown precision");
+  if (bad) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
+// workspace of the critic calls: x [rows][od], y [rows], V [rows], H[1..nl-1] [rows][dims],
+// d0 / d1 [rows][max width], split partials, the flat gradient
+#define CRITIC_SPLITS 32
+struct CriticWs {
+  size_t x, y, v, h[SIM_MAXL], d0, d1, part, grad, total;
+};
+static CriticWs critic_ws(const SimOptions& o, int rows, size_t e) {
+  CriticWs w = {};
+  const int L = o.critic_layers;
+  int maxd = 0;
+  size_t maxpart = 0, nparams = 0;
+  for (int l = 0; l <= L; ++l) maxd = std::max(maxd, o.critic_dims[l]);
+  for (int l = 0; l < L; ++l) {
+    maxpart = std::max(maxpart, (size_t)o.critic_dims[l + 1] * (o.critic_dims[l] + 1));
+    nparams += (size_t)o.critic_dims[l + 1] * (o.critic_dims[l] + 1);
+  }
+  size_t off = 0;
+  w.x = off; off = align256(off + (size_t)rows * o.critic_dims[0] * e);
+  w.y = off; off = align256(off + (size_t)rows * e);
+  w.v = off; off = align256(off + (size_t)rows * e);
+  for (int l = 1; l < L; ++l) { w.h[l] = off; off = align256(off + (size_t)rows * o.critic_dims[l] * e); }
+  w.d0 = off; off = align256(off + (size_t)rows * maxd * e);
+  w.d1 = off; off = align256(off + (size_t)rows * maxd * e);
+  w.part = off; off = align256(off + (size_t)CRITIC_SPLITS * maxpart * e);
+  w.grad = off; off = align256(off + nparams * e);
+  w.total = off;
+  return w;
+}
+
+extern "C" size_t sim_critic_workspace_bytes(const SimHandle* h, int rows) {
+  if (check_handle(const_cast<SimHandle*>(h)) || rows < 1) return 0;
+  const size_t e = (h->opt.precision == SIM_PREC_FP64) ? 8 : 4;
+  return critic_ws(h->opt, rows, e).total;
+}
+
+template <typename T>
+static void critic_theta_args(const SimHandle* h, const CriticWs& w, char* ws, const void* const* cw, const void* const* cb,
+                              int rows, ThetaArgsT<T>& P) {
+  const SimOptions& o = h->opt;
+  std::memset(&P, 0, sizeof(P));
+  P.M = rows;
+  P.nl = o.critic_layers;
+  for (int l = 0; l <= o.critic_layers; ++l) P.dims[l] = o.critic_dims[l];
+  P.splits = CRITIC_SPLITS;
+  long off = 0;
+  for (int l = 0; l < o.critic_layers; ++l) {
+    P.W[l] = static_cast<const T*>(cw[l]);
+    P.b[l] = static_cast<const T*>(cb[l]);
+    P.off_w[l] = off;
+    off += (long)o.critic_dims[l] * o.critic_dims[l + 1];
+    P.off_b[l] = off;
+    off += o.critic_dims[l + 1];
+    if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + w.h[l]);
+  }
+  P.d0 = reinterpret_cast<T*>(ws + w.d0);
+  P.d1 = reinterpret_cast<T*>(ws + w.d1);
+  P.part = reinterpret_cast<T*>(ws + w.part);
+  P.out = reinterpret_cast<T*>(ws + w.grad);
+}
+
+template <typename T>
+static int critic_values_impl(SimHandle* h, const void* obs, int rows, const void* const* cw, const void* const* cb,
+                              void* values, void* workspace, void* stream) {
+  const CriticWs w = critic_ws(h->opt, rows, sizeof(T));
+  ThetaArgsT<T> P;
+  critic_theta_args<T>(h, w, static_cast<char*>(workspace), cw, cb, rows, P);
+  P.x0 = static_cast<const T*>(obs);
+  if (cv_launch(P, static_cast<T*>(values), stream)) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" int sim_critic_values(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
+                                 const void* const* critic_b, void* values, void* workspace, size_t workspace_bytes,
+                                 void* hip_stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!obs || !values || !critic_w || !critic_b || rows < 1) return fail(SIM_E_ARG, "sim_critic_values: null pointer or no rows");
+  for (int l = 0; l < h->opt.critic_layers; ++l)
+    if (!critic_w[l] || !critic_b[l]) return fail(SIM_E_ARG, "sim_critic_values: null critic weights");
+  if (!workspace || workspace_bytes < sim_critic_workspace_bytes(h, rows))
+    return fail(SIM_E_WORKSPACE, "sim_critic_values: workspace smaller than sim_critic_workspace_bytes()");
+  return (h->opt.precision == SIM_PREC_FP64)
+             ? critic_values_impl<double>(h, obs, rows, critic_w, critic_b, values, workspace, hip_stream)
+             : critic_values_impl<float>(h, obs, rows, critic_w, critic_b, values, workspace, hip_stream);
+}
+
+template <typename T>
+static int critic_fit_impl(SimHandle* h, const SimCriticFitIO* io, void* stream) {
+  const CriticWs w = critic_ws(h->opt, io->rows, sizeof(T));
+  char* ws = static_cast<char*>(io->workspace);
+  CriticFitT<T> F;
+  std::memset(&F, 0, sizeof(F));
+  critic_theta_args<T>(h, w, ws, io->critic_w, io->critic_b, io->rows, F.G);
+  F.obs = static_cast<const T*>(io->obs);
+  F.targets = static_cast<const T*>(io->targets);
+  F.perm = io->perm;
+  F.rows = io->rows; F.n_iter = io->n_iter; F.n_mb = io->n_minibatch;
+  F.x = reinterpret_cast<T*>(ws + w.x);
+  F.y = reinterpret_cast<T*>(ws + w.y);
+  F.vbuf = reinterpret_cast<T*>(ws + w.v);
+  for (int l = 0; l < h->opt.critic_layers; ++l) {
+    F.W[l] = static_cast<T*>(io->critic_w[l]);
+    F.bvec[l] = static_cast<T*>(io->critic_b[l]);
+  }
+  F.m = static_cast<T*>(io->adam_m);
+  F.v = static_cast<T*>(io->adam_v);
+  F.adam_step = io->adam_step;
+  F.lr = (T)io->lr; F.b1 = (T)io->beta1; F.b2 = (T)io->beta2; F.eps = (T)io->eps;
+  F.loss_out = static_cast<T*>(io->loss_out);
+  if (cf_launch(F, stream)) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!io || !io->obs || !io->targets || !io->perm || !io->adam_m || !io->adam_v)
+    return fail(SIM_E_ARG, "sim_critic_fit: null pointer");
+  if (io->rows < 1 || io->n_iter < 1 || io->n_minibatch < 1 || io->n_minibatch > io->rows)
+    return fail(SIM_E_ARG, "sim_critic_fit: need rows >= 1, n_iter >= 1, 1 <= n_minibatch <= rows");
+  for (int l = 0; l < h->opt.critic_layers; ++l)
+    if (!io->critic_w[l] || !io->critic_b[l]) return fail(SIM_E_ARG, "sim_critic_fit: null critic weights");
+  if (io->adam_step < 0 || !(io->lr >= 0.0) || !(io->beta1 >= 0.0 && io->beta1 < 1.0) ||
+      !(io->beta2 >= 0.0 && io->beta2 < 1.0) || !(io->eps > 0.0))
+    return fail(SIM_E_ARG, "sim_critic_fit: need adam_step >= 0, lr >= 0, 0 <= beta < 1, eps > 0");
+  if (!io->workspace || io->workspace_bytes < sim_critic_workspace_bytes(h, io->rows))
+    return fail(SIM_E_WORKSPACE, "sim_critic_fit: workspace smaller than sim_critic_workspace_bytes()");
+  return (h->opt.precision == SIM_PREC_FP64) ? critic_fit_impl<double>(h, io, hip_stream)
+                                             : critic_fit_impl<float>(h, io, hip_stream);
 }

@@ -17,7 +17,7 @@
 #define GT_K 16
 #define GT_THREADS 256
 
-enum { EPI_STORE = 0, EPI_BIAS_ELU = 1, EPI_DELU = 2 };
+enum { EPI_STORE = 0, EPI_BIAS_ELU = 1, EPI_DELU = 2, EPI_BIAS = 3 };
 
 typedef float mfma_v4f __attribute__((__vector_size__(4 * sizeof(float))));
 typedef double mfma_v4d __attribute__((__vector_size__(4 * sizeof(double))));
@@ -48,7 +48,7 @@ struct GemmArgs {
   real* C;
   long ldc, split_stride;
   int epi;
-  const real* bias;  // EPI_BIAS_ELU: C = elu(acc + bias[n])
+  const real* bias;  // EPI_BIAS_ELU: C = elu(acc + bias[n]); EPI_BIAS: C = acc + bias[n]
   const real* Hm;    // EPI_DELU: C = acc * elu'(z), z > 0 <=> Hm > 0, else elu'(z) = Hm + 1
   long ldh;
 };
@@ -118,6 +118,8 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
           if (g.epi == EPI_BIAS_ELU) {
             v += g.bias[n];
             v = v > RL(0.0) ? v : m_expm1(v);
+          } else if (g.epi == EPI_BIAS) {
+            v += g.bias[n];
           } else if (g.epi == EPI_DELU) {
             const real hv = g.Hm[(long)m * g.ldh + n];
             v *= hv > RL(0.0) ? RL(1.0) : hv + RL(1.0);
@@ -174,10 +176,9 @@ static void launch_gemm(const GemmArgs& g, int splits, hipStream_t s) {
   hipLaunchKernelGGL(k_gemm, grid, dim3(GT_THREADS), 0, s, g);
 }
 
-int launch_theta(const ThetaArgsT<real>& T, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
+// the hidden layers of the network on T.M rows of T.x0 (H[l + 1] = elu(H[l] W_l^T + b_l))
+static void theta_hidden(const ThetaArgsT<real>& T, hipStream_t s) {
   const int M = T.M, L = T.nl;
-  // re-evaluate the hidden layers on the stored observations
   for (int l = 0; l + 1 < L; ++l) {
     const int ni = T.dims[l], no = T.dims[l + 1];
     GemmArgs g = {};
@@ -190,13 +191,25 @@ int launch_theta(const ThetaArgsT<real>& T, void* stream) {
     g.epi = EPI_BIAS_ELU; g.bias = T.b[l];
     launch_gemm(g, 1, s);
   }
-  const int na = T.dims[L];
-  const long nseed = (long)M * na;
-  hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed,
-                     T.mtu);
-  if (T.noise && T.out_log_std)
-    hipLaunchKernelGGL(k_log_std_grad, dim3(na), dim3(256), 0, s, T.d0, T.noise, T.log_std, (long)M, na,
-                       T.out_log_std);
+}
+
+// the linear output layer on the rows (out [M][dims[L]] = H[L-1] W^T + b)
+static void theta_output(const ThetaArgsT<real>& T, real* out, hipStream_t s) {
+  const int L = T.nl, ni = T.dims[L - 1], no = T.dims[L];
+  GemmArgs g = {};
+  g.A = (L == 1) ? T.x0 : T.H[L - 1];
+  g.sam = ni; g.sak = 1;
+  g.B = T.W[L - 1]; g.sbk = 1; g.sbn = ni;
+  g.M = T.M; g.N = no; g.K = ni;
+  g.k_chunk = (ni + GT_K - 1) / GT_K * GT_K;
+  g.C = out; g.ldc = no;
+  g.epi = EPI_BIAS; g.bias = T.b[L - 1];
+  launch_gemm(g, 1, s);
+}
+
+// given the output adjoint in T.d0, every layer's weight and bias gradient (flat in T.out)
+static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
+  const int M = T.M, L = T.nl;
   real* dcur = T.d0;
   real* dnext = T.d1;
   const int chunk = ((M + T.splits - 1) / T.splits + GT_K - 1) / GT_K * GT_K;
@@ -226,5 +239,20 @@ int launch_theta(const ThetaArgsT<real>& T, void* stream) {
       real* t = dcur; dcur = dnext; dnext = t;
     }
   }
+}
+
+int launch_theta(const ThetaArgsT<real>& T, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int M = T.M, L = T.nl;
+  // re-evaluate the hidden layers on the stored observations
+  theta_hidden(T, s);
+  const int na = T.dims[L];
+  const long nseed = (long)M * na;
+  hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed,
+                     T.mtu);
+  if (T.noise && T.out_log_std)
+    hipLaunchKernelGGL(k_log_std_grad, dim3(na), dim3(256), 0, s, T.d0, T.noise, T.log_std, (long)M, na,
+                       T.out_log_std);
+  theta_backward(T, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -1,0 +1,150 @@
+// The learning-episode update that follows a window (Sec. 3.3, Algorithm "SHAC"): one Adam
+// step of the policy, TD-lambda value estimates of the window's states from the target
+// critic, the critic's mean-squared-error fit over shuffled minibatches with Adam, and the
+// smooth update of the target critic.  The contractions run on the matrix cores through the
+// row-contraction GEMMs of the policy-parameter gradient (sim_gemm.h).
+//
+// Included inside a namespace with `real` defined as float or double, after sim_math.h and
+// sim_gemm.h.
+
+// Adam (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m / bc1) / (sqrt(v / bc2) + eps) with bc = 1 - b^t
+__global__ void k_adam(real* __restrict__ p, const real* __restrict__ g, real* __restrict__ mm,
+                       real* __restrict__ vv, long n, real lr, real b1, real b2, real eps, real bc1, real bc2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const real gi = g[i];
+  const real m = b1 * mm[i] + (RL(1.0) - b1) * gi;
+  const real v = b2 * vv[i] + (RL(1.0) - b2) * gi * gi;
+  mm[i] = m;
+  vv[i] = v;
+  p[i] -= lr * (m / bc1) / (m_sqrt(v / bc2) + eps);
+}
+
+// target <- alpha target + (1 - alpha) online
+__global__ void k_soft_update(real* __restrict__ t, const real* __restrict__ o, long n, real alpha) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = alpha * t[i] + (RL(1.0) - alpha) * o[i];
+}
+
+// TD-lambda estimates, one thread per env, by the backward recursion
+// G_t = r_t + gamma ((1 - lambda) V_{t+1} + lambda G_{t+1}) from G_h = V_h, which equals the
+// lambda-weighted average of the k-step returns of the definition.
+// r [h][N], v [h+1][N] (values of s_0 .. s_h; s_0's is not used), out [h][N]
+__global__ void k_td_lambda(const real* __restrict__ r, const real* __restrict__ v, int h, int N, real gamma,
+                            real lam, real* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  real G = v[(size_t)h * N + e];
+  for (int t = h - 1; t >= 0; --t) {
+    G = r[(size_t)t * N + e] + gamma * ((RL(1.0) - lam) * v[(size_t)(t + 1) * N + e] + lam * G);
+    out[(size_t)t * N + e] = G;
+  }
+}
+
+// minibatch rows: x[b] = obs[perm[b]], y[b] = targets[perm[b]]
+__global__ void k_gather_rows(const real* __restrict__ obs, const real* __restrict__ tgt, const int* __restrict__ perm,
+                              int B, int od, real* __restrict__ x, real* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)B * od) return;
+  const int b = (int)(i / od), c = (int)(i % od);
+  const int r = perm[b];
+  x[i] = obs[(long)r * od + c];
+  if (c == 0) y[b] = tgt[r];
+}
+
+// output adjoint of the mean squared error (1/B) sum (V - y)^2
+__global__ void k_mse_seed(const real* __restrict__ V, const real* __restrict__ y, int B, real* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) d[i] = RL(2.0) / (real)B * (V[i] - y[i]);
+}
+
+// the minibatch's mean squared error before the step, by a fixed-order tree (one block)
+__global__ __launch_bounds__(256) void k_mse_loss(const real* __restrict__ V, const real* __restrict__ y, int B,
+                                                  real* __restrict__ out) {
+  __shared__ real part[256];
+  real s = RL(0.0);
+  for (int i = threadIdx.x; i < B; i += 256) {
+    const real d = V[i] - y[i];
+    s += d * d;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0] / (real)B;
+}
+
+static void launch_adam_tensor(real* p, const real* g, real* m, real* v, long n, real lr, real b1, real b2, real eps,
+                               real bc1, real bc2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, bc1,
+                     bc2);
+}
+
+int launch_adam(const LearnAdamT<real>& A, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  long off = 0;
+  for (int i = 0; i < A.n; ++i) {
+    launch_adam_tensor(A.p[i], A.g + off, A.m + off, A.v + off, A.size[i], A.lr, A.b1, A.b2, A.eps, A.bc1, A.bc2, s);
+    off += A.size[i];
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_soft_update(real* t, const real* o, long n, real alpha, void* stream) {
+  hipLaunchKernelGGL(k_soft_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, t, o, n,
+                     alpha);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_td_lambda(const real* r, const real* v, int h, int N, real gamma, real lam, real* out, void* stream) {
+  hipLaunchKernelGGL(k_td_lambda, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, (hipStream_t)stream, r, v, h, N,
+                     gamma, lam, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_critic_values(const ThetaArgsT<real>& T, real* out, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  theta_hidden(T, s);
+  theta_output(T, out, s);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// n_iter passes over the rows in the order of perm[it], n_mb minibatches each; every
+// minibatch: gather, forward, MSE seed, layer gradients, one Adam step of the critic
+int launch_critic_fit(const CriticFitT<real>& F, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  ThetaArgsT<real> T = F.G;
+  int step = F.adam_step;
+  for (int it = 0; it < F.n_iter; ++it) {
+    for (int mb = 0; mb < F.n_mb; ++mb) {
+      const int r0 = (int)((long)mb * F.rows / F.n_mb), r1 = (int)((long)(mb + 1) * F.rows / F.n_mb);
+      const int B = r1 - r0;
+      if (B <= 0) continue;
+      const long nx = (long)B * T.dims[0];
+      hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, F.obs, F.targets,
+                         F.perm + (long)it * F.rows + r0, B, T.dims[0], F.x, F.y);
+      T.M = B;
+      T.x0 = F.x;
+      theta_hidden(T, s);
+      theta_output(T, F.vbuf, s);
+      if (F.loss_out)
+        hipLaunchKernelGGL(k_mse_loss, dim3(1), dim3(256), 0, s, F.vbuf, F.y, B, F.loss_out + it * F.n_mb + mb);
+      hipLaunchKernelGGL(k_mse_seed, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, F.vbuf, F.y, B, T.d0);
+      theta_backward(T, s);
+      ++step;
+      const real bc1 = RL(1.0) - (real)pow((double)F.b1, (double)step);
+      const real bc2 = RL(1.0) - (real)pow((double)F.b2, (double)step);
+      for (int l = 0; l < T.nl; ++l) {
+        const long nw = (long)T.dims[l] * T.dims[l + 1];
+        launch_adam_tensor(F.W[l], T.out + T.off_w[l], F.m + T.off_w[l], F.v + T.off_w[l], nw, F.lr, F.b1, F.b2,
+                           F.eps, bc1, bc2, s);
+        launch_adam_tensor(F.bvec[l], T.out + T.off_b[l], F.m + T.off_b[l], F.v + T.off_b[l], T.dims[l + 1], F.lr,
+                           F.b1, F.b2, F.eps, bc1, bc2, s);
+      }
+    }
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}

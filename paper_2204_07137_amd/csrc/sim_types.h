@@ -146,6 +146,40 @@ struct ThetaArgsT {
   long off_w[SIM_MAXL], off_b[SIM_MAXL];
 };
 
+// Adam over a list of parameter tensors whose gradient and moments are flat, in list order.
+#define SIM_MAX_TENSORS 16
+template <typename T>
+struct LearnAdamT {
+  int n;
+  T* p[SIM_MAX_TENSORS];
+  long size[SIM_MAX_TENSORS];
+  const T* g;
+  T* m;
+  T* v;
+  T lr, b1, b2, eps, bc1, bc2;   // bc = 1 - beta^step (bias corrections)
+};
+
+// Critic fit over shuffled minibatches (the layer gradients run through G, whose x0 / M are
+// set per minibatch and whose out is the flat gradient buffer).
+template <typename T>
+struct CriticFitT {
+  ThetaArgsT<T> G;      // layer-gradient pass
+  const T* obs;         // [rows][obs_dim]
+  const T* targets;     // [rows]
+  const int* perm;      // [n_iter][rows]
+  int rows, n_iter, n_mb;
+  T* x;                 // [rows][obs_dim] gathered minibatch
+  T* y;                 // [rows]
+  T* vbuf;              // [rows] critic outputs
+  T* W[SIM_MAXL];       // critic weights, updated in place
+  T* bvec[SIM_MAXL];
+  T* m;                 // flat Adam moments
+  T* v;
+  int adam_step;        // Adam steps taken before the call
+  T lr, b1, b2, eps;
+  T* loss_out;          // [n_iter * n_mb] minibatch losses before each step (optional)
+};
+
 // Launchers implemented once per arithmetic type (kernels_f32.hip, kernels_f64.hip).
 #define SIM_DECLARE_LAUNCHERS(NS, T)                                                        \
   namespace NS {                                                                            \
@@ -158,3 +192,14 @@ struct ThetaArgsT {
   }
 SIM_DECLARE_LAUNCHERS(sim_f32, float)
 SIM_DECLARE_LAUNCHERS(sim_f64, double)
+// the learning-episode update (learn.hip)
+#define SIM_DECLARE_LEARN(NS, T)                                                           \
+  namespace NS {                                                                           \
+  int launch_adam(const LearnAdamT<T>& A, void* stream);                                   \
+  int launch_soft_update(T* t, const T* o, long n, T alpha, void* stream);                 \
+  int launch_td_lambda(const T* r, const T* v, int h, int N, T gamma, T lam, T* out, void* stream); \
+  int launch_critic_values(const ThetaArgsT<T>& A, T* out, void* stream);                  \
+  int launch_critic_fit(const CriticFitT<T>& F, void* stream);                             \
+  }
+SIM_DECLARE_LEARN(sim_l32, float)
+SIM_DECLARE_LEARN(sim_l64, double)

@@ -1,0 +1,63 @@
+"""Pins of the learning-episode oracle (TD-lambda, Adam, critic fit) against textbook
+special cases and finite differences."""
+import numpy as np
+import torch
+
+from oracle.learn import td_lambda, adam_step, critic_fit, critic_values
+
+
+def test_td_lambda_special_cases():
+    rng = np.random.default_rng(5)
+    h, N, g = 7, 3, 0.9
+    r = rng.normal(size=(h, N))
+    v = rng.normal(size=(h + 1, N))
+    # lambda = 0: one-step temporal difference target
+    np.testing.assert_allclose(td_lambda(r, v, g, 0.0).numpy(), r + g * v[1:], rtol=0, atol=1e-13)
+    # lambda = 1: the discounted return to the end of the window, bootstrapped there
+    mc = np.stack([sum(g ** l * r[t + l] for l in range(h - t)) + g ** (h - t) * v[h] for t in range(h)])
+    np.testing.assert_allclose(td_lambda(r, v, g, 1.0).numpy(), mc, rtol=0, atol=1e-12)
+    # one frame: r_0 + gamma V(s_1) for any lambda
+    np.testing.assert_allclose(td_lambda(r[:1], v[:2], g, 0.37).numpy(), r[:1] + g * v[1:2], atol=1e-14)
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(6)
+    p = [torch.as_tensor(rng.normal(size=(4, 3)))]
+    gr = [torch.as_tensor(rng.normal(size=(4, 3)))]
+    z = [torch.zeros(4, 3, dtype=torch.float64)]
+    P, M, V = adam_step(p, gr, z, z, 1, 0.01, 0.7, 0.95, 1e-8)
+    # bias-corrected first moments are g and g^2: the step is lr g / (|g| + eps)
+    np.testing.assert_allclose(P[0].numpy(), (p[0] - 0.01 * gr[0] / (gr[0].abs() + 1e-8)).numpy(), atol=1e-15)
+    np.testing.assert_allclose(M[0].numpy(), 0.3 * gr[0].numpy(), atol=1e-15)
+    np.testing.assert_allclose(V[0].numpy(), 0.05 * gr[0].numpy() ** 2, atol=1e-15)
+
+
+def test_critic_fit_gradient_direction_and_descent():
+    rng = np.random.default_rng(7)
+    od, rows = 5, 24
+    layers = [(rng.normal(0, 0.4, (8, od)), rng.normal(0, 0.1, 8)),
+              (rng.normal(0, 0.4, (1, 8)), rng.normal(0, 0.1, 1))]
+    obs = rng.normal(size=(rows, od))
+    tgt = rng.normal(size=rows)
+    zeros = [np.zeros_like(x) for W, b in layers for x in (W, b)]
+    perm = [np.arange(rows)]
+    new, _, _, losses = critic_fit(layers, obs, tgt, perm, 1, zeros, zeros, 0, 1e-7, 0.7, 0.95, 1e-12)
+
+    def loss(Ls):
+        return float(((critic_values(Ls, obs) - torch.as_tensor(tgt)) ** 2).mean())
+    assert abs(losses[0] - loss(layers)) < 1e-14
+    # the first Adam step moves every weight against the sign of its gradient: compare
+    # with central differences of the loss on a few weights
+    e = 1e-6
+    for (i, j, k) in [(0, 0, 0), (0, 3, 2), (1, 0, 5)]:
+        Lp = [(W.copy(), b.copy()) for W, b in layers]
+        Lm = [(W.copy(), b.copy()) for W, b in layers]
+        Lp[i][0][j, k] += e
+        Lm[i][0][j, k] -= e
+        fd = (loss(Lp) - loss(Lm)) / (2 * e)
+        step = float(new[i][0][j, k]) - layers[i][0][j, k]
+        assert np.sign(step) == -np.sign(fd) and abs(fd) > 1e-9
+    # and a few passes with a usable rate reduce the loss
+    perm = [rng.permutation(rows) for _ in range(30)]
+    _, _, _, losses = critic_fit(layers, obs, tgt, perm, 2, zeros, zeros, 0, 1e-2, 0.7, 0.95, 1e-8)
+    assert np.mean(losses[-2:]) < 0.75 * np.mean(losses[:2])
