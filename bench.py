@@ -313,6 +313,53 @@ def long_windows(P, wl, torch, n_envs=256, horizons=(32, 64, 128, 256)):
                         f"kernels, throughput in FP32", "windows": res}
 
 
+def learning_episode(P, torch, sim, W, steps=3):
+    """SHAC learning episodes on the headline batch (Sec. 3.3, Algorithm "SHAC"; App. A.2
+    hyperparameters): the window with the policy-parameter gradient, one Adam step of the
+    actor, the target critic's values of the window's states, TD-lambda estimates, the critic
+    fit (16 passes x 4 minibatches, Adam), the target-critic update.  The start states are
+    the same every episode (a fixed benchmark batch)."""
+    N, h, od = sim.N, sim.H, sim.od
+    s0 = sim._dev(W["s0"])
+    actor = [(a.clone(), b.clone()) for a, b in sim.weights(W["actor"])]
+    critic = [(a.clone(), b.clone()) for a, b in sim.weights(W["critic"])]
+    target = [(a.clone(), b.clone()) for a, b in critic]
+    flat = lambda L: [x for pair in L for x in pair]
+    n_a, n_c = sum(x.numel() for x in flat(actor)), sum(x.numel() for x in flat(critic))
+    am, av = torch.zeros(n_a, device="cuda"), torch.zeros(n_a, device="cuda")
+    cm, cv = torch.zeros(n_c, device="cuda"), torch.zeros(n_c, device="cuda")
+    g = torch.Generator().manual_seed(3)
+    perm = torch.stack([torch.randperm(h * N, generator=g) for _ in range(16)]).to(torch.int32).cuda()
+    ws = sim.critic_workspace((h + 1) * N)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps + 1)]
+
+    def episode(i, e):
+        e[0].record()
+        fw = sim.forward(s0, actor, target)
+        ad = sim.adjoint(fw, want_theta=True)
+        e[1].record()
+        P.adam_step(flat(actor), ad["dL_dtheta_flat"], am, av, i + 1, 2e-3)
+        vals = sim.critic_values(fw["obs"], target, workspace=ws).reshape(h + 1, N)
+        tgt = P.td_lambda(fw["rewards"], vals, 0.99, 0.95).reshape(-1)
+        sim.critic_fit(fw["obs"][:h].reshape(-1, od), tgt, perm, 4, critic, cm, cv, i * 64, 5e-4, workspace=ws)
+        P.soft_update(flat(target), flat(critic), 0.995)
+        e[2].record()
+
+    episode(0, ev[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        episode(i + 1, ev[i + 1])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    upd = float(np.mean([a[1].elapsed_time(a[2]) for a in ev[1:]]))
+    win = float(np.mean([a[0].elapsed_time(a[1]) for a in ev[1:]]))
+    return {"workload": f"humanoid {N} envs, h={h}: window + policy gradient + actor Adam + TD-lambda + "
+                        f"critic fit 16 x 4 minibatches of {h * N // 4} rows + target update",
+            "ms_per_episode": round(wall * 1e3, 3), "episodes_per_s": round(1.0 / wall, 2),
+            "env_steps_per_s": round(N * h / wall, 1), "window_ms": round(win, 3), "update_ms": round(upd, 3)}
+
+
 def cpu_baseline(W, h, n_envs_sample=2):
     """The FP64 oracle (CPU, PyTorch) on a bounded sample of the same workload."""
     import torch
@@ -462,6 +509,8 @@ def main():
                        "published_hbm_gbs": HBM_PEAK_GBS}
     roof["frac_of_measured"] = round(achieved / ceil["fp32_valu_tflops"], 5)
 
+    if not args.no_theta:
+        out["learning_episode"] = learning_episode(P, torch, sim, W)
     if not args.no_long:
         out["long_windows"] = long_windows(P, wl, torch)
     if not args.no_mtu:
