@@ -128,6 +128,13 @@ typedef struct SimModelDesc {
   double tau_act;                /* s */
   double fl_width;
   double vmax;                   /* optimal fibre lengths per second */
+  /* Early termination (App. A.3: a task ends when the root falls below a height): with
+   * term_enabled, an env whose free root is below term_height (m, world z) at the end of a
+   * frame is marked done, replaced by its reset state (SimForwardIO.reset_states), and its
+   * discount restarts; the reset cuts the gradient (the reset state is a constant).  Needs a
+   * FREE root; runs on the persistent and tape paths. */
+  int term_enabled;
+  double term_height;
 } SimModelDesc;
 
 typedef struct SimOptions {
@@ -187,6 +194,10 @@ typedef struct SimForwardIO {
    * the action squash(y_t); both null = the deterministic policy.  Closed loop only. */
   const void* noise;                        /* [h][N][na] standard normal draws eps, or NULL */
   const void* log_std;                      /* [na], or NULL */
+  const void* reset_states;                 /* [N][ns] the states terminated envs restart from
+                                               (required with term_enabled) */
+  uint8_t* done;                            /* [h][N] out, optional: 1 if the env terminated at
+                                               the end of frame t */
 } SimForwardIO;
 
 typedef struct SimAdjointIO {

@@ -137,7 +137,8 @@ def _layers(params):
 
 
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
-                  keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None):
+                  keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None,
+                  reset_states=None):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
@@ -147,6 +148,10 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     bf16: evaluate actor and critic with BF16 weights and layer inputs (mlp_forward_bf16).
     noise [h, B, na], log_std [na]: the stochastic policy a_t ~ N(mu(s_t), sigma) sampled by
     reparameterisation (Sec. 3.3): the pre-squash output is mu(o_t) + exp(log_std) noise_t.
+    reset_states [B, n_s]: early termination (App. A.3) for a model with "term_height": an env
+    whose root is below that height at the end of a frame restarts from its reset state (a
+    constant), and its discount restarts at the next frame; a segment that ends in a
+    termination has no terminal value.
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
     s = s0 if torch.is_tensor(s0) else _t(s0)
@@ -160,6 +165,9 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     dt = m.dt / m.substeps
     mlp = mlp_forward_bf16 if bf16 else mlp_forward
     states, obs, acts, rews = [s], [], [], []
+    term_h = m.md.get("term_height") if reset_states is not None else None
+    t0 = torch.zeros(B, dtype=torch.long)
+    segs, dones = [], []
     for t in range(h):
         o = obs_fn(m, s)
         if actions is None:
@@ -185,6 +193,12 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
             for _ in range(m.substeps):
                 q, qd = substep(m, q, qd, a, dt)
             s = torch.cat([q, qd, a], 1) if m.md["has_last_action"] else torch.cat([q, qd], 1)
+        if term_h is not None:
+            done = s[:, 2] < term_h
+            s = torch.where(done[:, None], _t(reset_states), s)
+            segs.append(t0.clone())
+            dones.append(done)
+            t0 = torch.where(done, torch.full_like(t0, t + 1), t0)
         states.append(s)
         obs.append(o)
         acts.append(a)
@@ -192,14 +206,22 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     o_h = obs_fn(m, s)
     obs.append(o_h)
     value = mlp(crit_l, o_h)[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
-    disc = sum(gamma ** t * rews[t] for t in range(h))
-    loss = -(disc + gamma ** h * value).sum() / (N * h)
+    if term_h is None:
+        disc = sum(gamma ** t * rews[t] for t in range(h))
+        loss = -(disc + gamma ** h * value).sum() / (N * h)
+        done_out = None
+    else:
+        disc = sum(torch.pow(gamma, (t - segs[t]).to(F64)) * rews[t] for t in range(h))
+        live = (~dones[-1]).to(F64)
+        loss = -(disc + live * torch.pow(gamma, (h - t0).to(F64)) * value).sum() / (N * h)
+        done_out = torch.stack(dones)
     return dict(states=states, obs=obs, actions=acts, rewards=rews, value=value, loss=loss,
-                layers=layers)
+                layers=layers, done=done_out)
 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
-                        n_total=None, want_theta=False, bf16=False, noise=None, log_std=None):
+                        n_total=None, want_theta=False, bf16=False, noise=None, log_std=None,
+                        reset_states=None):
     """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
 
     Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
@@ -219,7 +241,7 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
     if noise is not None:
         ls = _t(log_std).clone().requires_grad_(want_theta)
     out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
-                        layers=layers, bf16=bf16, noise=noise, log_std=ls)
+                        layers=layers, bf16=bf16, noise=noise, log_std=ls, reset_states=reset_states)
     wrt = [s0t] + list(out["actions"])
     theta = []
     if want_theta and actor is not None:
@@ -242,6 +264,8 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
         dL_da=ga.detach().numpy(),
         dL_ds0=gs0.detach().numpy(),
     )
+    if out["done"] is not None:
+        res["done"] = out["done"].numpy()
     if want_theta and actor is not None:
         gt = g[1 + h:]
         if ls is not None:

@@ -34,7 +34,7 @@ class SimModelDesc(ctypes.Structure):
                 ("mu", _d), ("klim", _d), ("dt", _d), ("substeps", _i), ("task", _i),
                 ("has_last_action", _i), ("n_mtu", _i), ("mtu_npt", _p), ("mtu_body", _p),
                 ("mtu_pos", _p), ("mtu_fmax", _p), ("mtu_lopt", _p), ("mtu_lslack", _p),
-                ("tau_act", _d), ("fl_width", _d), ("vmax", _d)]
+                ("tau_act", _d), ("fl_width", _d), ("vmax", _d), ("term_enabled", _i), ("term_height", _d)]
 
 
 class SimOptions(ctypes.Structure):
@@ -50,7 +50,7 @@ class SimForwardIO(ctypes.Structure):
                 ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("workspace", _p),
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
                 ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p),
-                ("noise", _p), ("log_std", _p)]
+                ("noise", _p), ("log_std", _p), ("reset_states", _p), ("done", _p)]
 
 
 class SimAdjointIO(ctypes.Structure):
@@ -203,6 +203,9 @@ def model_desc(md):
         d.tau_act = float(md["tau_act"])
         d.fl_width = float(md["fl_width"])
         d.vmax = float(md["vmax"])
+    if md.get("term_height") is not None:
+        d.term_enabled = 1
+        d.term_height = float(md["term_height"])
     return d, keep
 
 
@@ -322,16 +325,21 @@ class Sim:
     def _ptr(t):
         return _p(t.data_ptr()) if t is not None else _p(0)
 
-    def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None, noise=None, log_std=None):
+    def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None, noise=None, log_std=None,
+                reset_states=None):
         """Run sim_forward_window.  Returns a dict of device tensors.  noise [h, N, na] and
-        log_std [na] select the stochastic policy y = mu(o) + exp(log_std) * noise."""
-        out, io = self.forward_io(s0, actor, critic, actions_in, noise=noise, log_std=log_std)
+        log_std [na] select the stochastic policy y = mu(o) + exp(log_std) * noise;
+        reset_states [N, ns] are the restart states of a model with early termination (the
+        result then holds done [h, N])."""
+        out, io = self.forward_io(s0, actor, critic, actions_in, noise=noise, log_std=log_std,
+                                  reset_states=reset_states)
         t = self.torch
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
         return out
 
-    def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None, noise=None, log_std=None):
+    def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None, noise=None, log_std=None,
+                   reset_states=None):
         """Allocate the forward outputs (or reuse those of `out`, a previous result) and
         fill a SimForwardIO (no launch)."""
         t = self.torch
@@ -361,6 +369,13 @@ class Sim:
             assert actions_in.shape == (H, N, self.na)
             out["actions_in"] = actions_in
             io.actions_in = self._ptr(actions_in)
+        if reset_states is not None:
+            reset_states = self._dev(reset_states)
+            assert reset_states.shape == (N, self.ns)
+            out["reset_states"] = reset_states
+            io.reset_states = self._ptr(reset_states)
+            out["done"] = t.zeros(H, N, dtype=t.uint8, device="cuda")
+            io.done = self._ptr(out["done"])
         if noise is not None:
             noise = self._dev(noise)
             log_std = self._dev(log_std)

@@ -37,7 +37,7 @@ struct SimHandle {
   size_t elem = 4;
   size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL], wp_actor_off[SIM_MAXL], wp_critic_off[SIM_MAXL];
   size_t bf_actor_off[SIM_MAXL][2], bf_critic_off[SIM_MAXL][2];   // BF16 forward / adjoint tiles
-  size_t off_ckpt = 0, off_adj = 0, off_tape = 0, ws_bytes = 0;
+  size_t off_ckpt = 0, off_adj = 0, off_tape = 0, off_done = 0, off_seg = 0, ws_bytes = 0;
   // policy-gradient scratch: hidden activations, two layer-adjoint buffers, split partials
   size_t off_th_h[SIM_MAXL], off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
   int th_splits = 0;
@@ -78,6 +78,7 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   d.npair = s.npair;
   for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
   d.tau_act = (T)s.tau_act; d.fl_w = (T)s.fl_w; d.vmax = (T)s.vmax;
+  d.term_h = (T)s.term_h;
   for (int i = 0; i < SIM_MAXMTU; ++i) {
     d.mtu_npt[i] = s.mtu_npt[i];
     d.mtu_fmax[i] = (T)s.mtu_fmax[i]; d.mtu_lopt[i] = (T)s.mtu_lopt[i]; d.mtu_lslack[i] = (T)s.mtu_lslack[i];
@@ -200,6 +201,9 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
   if (md->task == TASK_MTU && md->n_mtu < 1) return fail(SIM_E_MODEL, "the muscle task needs muscles");
   m.J = J; m.nq = nq; m.nv = nv; m.na = md->n_act + md->n_mtu; m.nc = md->n_contacts;
   m.n_mtu = md->n_mtu; m.n_motor = md->n_act; m.nck = nq + nv + md->n_mtu;
+  m.term = md->term_enabled ? 1 : 0;
+  m.term_h = md->term_height;
+  if (m.term && m.jtype[0] != J_FREE) return fail(SIM_E_MODEL, "early termination needs a FREE root");
   m.task = md->task; m.floating = (m.jtype[0] == J_FREE) ? 1 : 0;
   m.has_last_action = md->has_last_action ? 1 : 0;
   m.substeps = md->substeps; m.max_depth = maxd;
@@ -295,6 +299,8 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
   if (opt->policy_grad && !opt->closed_loop) return fail(SIM_E_ARG, "policy_grad needs the closed-loop policy");
   if (m.n_mtu > 0 && opt->path == SIM_PATH_PLAIN)
     return fail(SIM_E_UNSUPPORTED, "muscle models run on the persistent and tape paths");
+  if (m.term && opt->path == SIM_PATH_PLAIN)
+    return fail(SIM_E_UNSUPPORTED, "early termination runs on the persistent and tape paths");
   if (opt->mlp_precision != SIM_MLP_FP32 && opt->mlp_precision != SIM_MLP_BF16)
     return fail(SIM_E_ARG, "unknown mlp_precision");
   if (opt->mlp_precision == SIM_MLP_BF16 && opt->precision != SIM_PREC_FP32)
@@ -380,6 +386,10 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
                               : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
   h->off_tape = off;
   off = align256(off + tape_entries * sim_tape_bytes(e, m.n_mtu > 0));
+  h->off_done = off;
+  off = align256(off + (size_t)opt->horizon * N);
+  h->off_seg = off;
+  off = align256(off + (size_t)(opt->horizon + 1) * N * sizeof(int));
   for (int l = 0; l < SIM_MAXL; ++l) h->off_th_h[l] = 0;
   if (opt->policy_grad) {
     const size_t rows = N * (size_t)opt->horizon;
@@ -512,6 +522,10 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (h->opt.path == SIM_PATH_TAPE);
+  A.reset = static_cast<const T*>(io->reset_states);
+  A.done_out = io->done;
+  A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
+  A.seg_ws = reinterpret_cast<int*>(ws + h->off_seg);
   return SIM_OK;
 }
 
@@ -538,6 +552,8 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (o.path == SIM_PATH_TAPE);
+  A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
+  A.seg_ws = reinterpret_cast<int*>(ws + h->off_seg);
   A.obs_in = static_cast<const T*>(io->obs);
   A.actions_fw = static_cast<const T*>(io->actions);
   A.s_h_in = static_cast<const T*>(io->s_h);
@@ -649,6 +665,7 @@ static int check_forward_io(SimHandle* h, const SimForwardIO* io) {
   if ((io->noise != nullptr) != (io->log_std != nullptr))
     return fail(SIM_E_ARG, "the stochastic policy needs both noise and log_std");
   if (io->noise && !o.closed_loop) return fail(SIM_E_ARG, "noise needs the closed-loop policy");
+  if (h->m64.term && !io->reset_states) return fail(SIM_E_ARG, "early termination needs reset_states");
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
   return SIM_OK;

@@ -109,6 +109,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
   Chol C;
   int nfb = 0;
+  int t0 = 0;   // first frame of the current discount segment (early termination)
   for (int t = 0; t < A.h; ++t) {
     frame_begin(A, m, E, env, t, ln);
     for (int sub = 0; sub < S; ++sub) {
@@ -125,7 +126,22 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
       }
       nfb += fb;
     }
+    if (m->term) {
+      // early termination: the frame ended with the root below the height; the env restarts
+      // from its reset state, a constant, and its discount from the next frame
+      const int done = (E.q[2] < m->term_h) ? 1 : 0;
+      if (ln == 0) {
+        A.done_ws[(size_t)t * N + env] = (uint8_t)done;
+        if (A.done_out) A.done_out[(size_t)t * N + env] = (uint8_t)done;
+        A.seg_ws[(size_t)t * N + env] = t0;
+      }
+      if (done) {
+        load_state(m, E, A.reset + (size_t)env * m->ns, ln);
+        t0 = t + 1;
+      }
+    }
   }
+  if (m->term && ln == 0) A.seg_ws[(size_t)A.h * N + env] = t0;
   window_end(A, m, E, env, ln);
   if (ln == 0 && A.fallback) A.fallback[env] = nfb;
 }
@@ -146,7 +162,9 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
   for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
   __syncthreads();
   mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
-  real c = -m_pow(A.gamma, (real)A.h) * A.scale;
+  // terminal value discounted from the start of the last segment (early termination)
+  const int eh = m->term ? A.h - A.seg_ws[(size_t)A.h * A.N + env] : A.h;
+  real c = -m_pow(A.gamma, (real)eh) * A.scale;
   if (ln == 0) E.y[0] = c;
   __syncthreads();
   mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
@@ -179,7 +197,8 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   const real* at = A.actions_fw + ((size_t)t * N + env) * na;
   for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
   __syncthreads();
-  real c = -m_pow(A.gamma, (real)t) * A.scale;
+  const int et = m->term ? t - A.seg_ws[(size_t)t * N + env] : t;
+  real c = -m_pow(A.gamma, (real)et) * A.scale;
   task_reward_vjp(m, E.q, E.qd, E.a, c, E.qb, E.qdb, E.abar, ln);
   real* da = A.dL_da + ((size_t)t * N + env) * na;
   for (int i = ln; i < na; i += SIM_WAVE) da[i] = E.abar[i];
@@ -217,6 +236,15 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
   // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
   Chol C;
   for (int t = A.h - 1; t >= 0; --t) {
+    if (m->term && A.done_ws[(size_t)t * N + env]) {
+      // frame t ended with a reset: s_{t+1} is a constant, nothing flows back through it
+      for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = RL(0.0);
+      for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = RL(0.0);
+      for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+      if constexpr (L::kMtu > 0)
+        for (int i = ln; i < L::kMtu; i += SIM_WAVE) E.act_bar[i] = RL(0.0);
+      __syncthreads();
+    }
     const real* at = A.actions_fw + ((size_t)t * N + env) * na;
     for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
     if (A.tape_full) {

@@ -39,9 +39,11 @@ template <typename T>
 struct DevModelT {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth;
   int n_mtu, n_motor, nck;   // muscles; motors (the first n_motor actions); nq + nv + n_mtu
+  int term;                  // early termination below term_h (root height)
   T dt_sub, g, kn, kd, kt, mu, klim;
   T chol_thr;   // FP64 refactorisation when the smallest pivot <= chol_thr * largest diagonal
   T tau_act, fl_w, vmax;     // activation time constant, force-length width, max fibre speed (l_opt/s)
+  T term_h;
   int parent[SIM_MAXJ], jtype[SIM_MAXJ], qadr[SIM_MAXJ], vadr[SIM_MAXJ], depth[SIM_MAXJ];
   int first_child[SIM_MAXJ], next_sib[SIM_MAXJ], act_of_joint[SIM_MAXJ], limited[SIM_MAXJ];
   // schedule of the forward subtree sums: at step s lane group g adds frame j into its parent p,
@@ -108,6 +110,13 @@ struct WinArgsT {
   const T* grad_s_h;
   T* dL_da;
   T* dL_ds0;
+  // early termination: reset states [N][ns]; done flags [h][N] (workspace, and the optional
+  // output); seg [h+1][N]: the first frame of the discount segment that frame t belongs to
+  // (row h: the segment that the terminal value closes)
+  const T* reset;
+  uint8_t* done_out;
+  uint8_t* done_ws;
+  int* seg_ws;
 };
 
 // Several models' windows in one launch (mixed-morphology batch): work-table slot s covers

@@ -859,3 +859,29 @@ def test_stochastic_policy_zero_sigma_and_log_std_gradient():
     fd = (lp - lm) / (2 * e)
     assert abs(g["dL_dlog_std"][0] - fd) <= 1e-6 * max(1.0, abs(fd))
     assert abs(fd) > 1e-8
+
+
+def test_early_termination_restarts_window():
+    """Early termination in the oracle: an env that falls below the termination height in
+    frame 0 continues exactly as a fresh window from its reset state (its later rewards
+    discounted from the reset), and nothing flows back through the reset into s_0."""
+    import workloads as wl
+    from oracle import oracle_window, oracle_window_grads
+    W = wl.workload("ant", 1)
+    md = wl.with_termination(W["model"])
+    s_low = W["s0"].copy()
+    s_low[:, 2] = 0.2                                   # root below 0.27 m
+    reset = wl.initial_states(md, 1, seed=9)
+    h = 4
+    A = oracle_window(md, s_low, h, W["actor"], None, reset_states=reset)
+    assert A["done"][:, 0].tolist() == [True, False, False, False]
+    B = oracle_window(md, reset, h - 1, W["actor"], None)
+    r0 = float(A["rewards"][0][0])
+    assert abs(4 * float(A["loss"]) - 3 * float(B["loss"]) + r0) < 1e-12
+    gA = oracle_window_grads(md, s_low, h, W["actor"], None, reset_states=reset)
+    g1 = oracle_window_grads(md, s_low, 1, W["actor"], None)      # loss -r_0 alone
+    np.testing.assert_allclose(gA["dL_ds0"], g1["dL_ds0"] / 4, rtol=0, atol=1e-14)
+    # with no env below the height the window is the one without termination
+    C = oracle_window(md, W["s0"], h, W["actor"], W["critic"], reset_states=reset)
+    D = oracle_window(W["model"], W["s0"], h, W["actor"], W["critic"])
+    assert not C["done"].any() and float(C["loss"]) == float(D["loss"])

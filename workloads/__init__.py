@@ -6,9 +6,10 @@ MLP weights.  It holds none of the simulation arithmetic: no kinematics, no
 dynamics, no rewards.  Everything it returns is plain numpy data.
 """
 from .models import (FREE, HINGE, SLIDE, cartpole, ant, humanoid, mtu_humanoid, model_by_name,
-                     pendulum, free_body, sliding_block, chain, muscle_arm)
+                     pendulum, free_body, sliding_block, chain, muscle_arm,
+                     with_termination)
 from .inputs import initial_states, mlp_params, workload, WORKLOADS
 
 __all__ = ["FREE", "HINGE", "SLIDE", "cartpole", "ant", "humanoid", "mtu_humanoid", "model_by_name",
-           "pendulum", "free_body", "sliding_block", "chain", "muscle_arm",
+           "pendulum", "free_body", "sliding_block", "chain", "muscle_arm", "with_termination",
            "initial_states", "mlp_params", "workload", "WORKLOADS"]

@@ -166,7 +166,7 @@ def ant():
     # knees at their mean angle (lower leg tilted down by d50)
     h0 = 0.4 * np.sin(d50) + r_leg
     return b.build(substeps=16, kn=4.0e4, kd=1.0e4, kt=1.0e3, mu=0.75, klim=1.0e4,
-                   root_height=h0, has_last_action=1)
+                   root_height=h0, has_last_action=1, et_height=0.27)
 
 
 def _humanoid_frames(b, rng, motors=True):
@@ -260,7 +260,7 @@ def humanoid(seed=0):
     b = _Builder("humanoid", "humanoid")
     _humanoid_frames(b, rng, motors=True)
     return b.build(substeps=48, kn=4.0e4, kd=1.0e4, kt=1.0e3, mu=0.75, klim=1.0e4,
-                   root_height=_HUMANOID_H0, has_last_action=1)
+                   root_height=_HUMANOID_H0, has_last_action=1, et_height=0.74)
 
 
 # Muscle groups of the muscle-driven humanoid: (origin body, insertion body, count,
@@ -301,7 +301,7 @@ def mtu_humanoid(seed=0):
     b = _Builder("mtu_humanoid", "mtu")
     names, caps = _humanoid_frames(b, np.random.default_rng(seed), motors=False)
     md = b.build(substeps=48, kn=4.0e4, kd=1.0e4, kt=1.0e3, mu=0.75, klim=1.0e4,
-                 root_height=_HUMANOID_H0, has_last_action=0)
+                 root_height=_HUMANOID_H0, has_last_action=0, et_height=0.74)
     rng = np.random.default_rng([seed, 1])
     origin = _rest_origins(md)
     parent = md["parent"]
@@ -451,3 +451,12 @@ def muscle_arm(d=0.3, b=0.8, c=None, fmax=50.0, lopt=0.6, lslack=0.2):
 
 def model_by_name(name):
     return {"cartpole": cartpole, "ant": ant, "humanoid": humanoid, "mtu_humanoid": mtu_humanoid}[name]()
+
+
+def with_termination(md):
+    """A copy of a floating-base model with early termination at its task's root height
+    (App. A.3: Ant 0.27 m, Humanoid torso 0.74 m; the muscle humanoid shares the humanoid's
+    skeleton and root, so it takes the same height)."""
+    d = dict(md)
+    d["term_height"] = float(md["et_height"])
+    return d
