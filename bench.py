@@ -124,6 +124,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-morphology batch")
     ap.add_argument("--no-mtu", action="store_true", help="skip the muscle-driven humanoid")
     ap.add_argument("--no-long", action="store_true", help="skip the long-window (h up to 256) section")
+    ap.add_argument("--no-stoch", action="store_true", help="skip the stochastic-policy window")
+    ap.add_argument("--no-term", action="store_true", help="skip the window with early termination")
+    ap.add_argument("--no-learn", action="store_true", help="skip the learning-episode section")
     return ap.parse_args()
 
 
@@ -141,20 +144,21 @@ def copy_probe():
           flush=True)
 
 
-def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False, noise=None, log_std=None):
+def time_windows(sim, s0, actor, critic, steps, warmup, want_theta=False, noise=None, log_std=None,
+                 reset_states=None):
     """Forward + adjoint windows; per-launch HIP-event times on torch's current stream
     (the stream the window kernels are launched on) and the wall time of the timed loop.
-    noise / log_std select the stochastic policy."""
+    noise / log_std select the stochastic policy; reset_states early termination."""
     import torch
     for _ in range(warmup):
-        fw = sim.forward(s0, actor, critic, noise=noise, log_std=log_std)
+        fw = sim.forward(s0, actor, critic, noise=noise, log_std=log_std, reset_states=reset_states)
         sim.adjoint(fw, want_theta=want_theta)
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
         ev[i][0].record()
-        fw = sim.forward(s0, actor, critic, noise=noise, log_std=log_std)
+        fw = sim.forward(s0, actor, critic, noise=noise, log_std=log_std, reset_states=reset_states)
         ev[i][1].record()
         ad = sim.adjoint(fw, want_theta=want_theta)
         ev[i][2].record()
@@ -448,14 +452,33 @@ def main():
                               "mfma_tflops": round(th_flops / max(th_ms, 1e-6) / 1e9, 3),
                               "mfma_peak_fp32_tflops": 157.3}
 
-    # the same window under the stochastic policy (reparameterised Gaussian, draws as inputs)
-    rng = np.random.default_rng(7)
-    noise = torch.as_tensor(rng.standard_normal((h, N, md["na"])), dtype=torch.float32, device="cuda")
-    log_std = torch.full((md["na"],), -1.0, dtype=torch.float32, device="cuda")
-    sw, _, _, _, _ = time_windows(sim, s0, actor, critic, max(3, args.steps // 4), 1, noise=noise, log_std=log_std)
-    sval = N * h / (sw / max(3, args.steps // 4))
-    out["stochastic_policy"] = {"value": round(sval, 1), "unit": "env-steps/s", "log_std": -1.0,
-                                "vs_deterministic": round(sval / value, 3)}
+    if not args.no_stoch:
+        # the same window under the stochastic policy (reparameterised Gaussian, draws as inputs)
+        rng = np.random.default_rng(7)
+        noise = torch.as_tensor(rng.standard_normal((h, N, md["na"])), dtype=torch.float32, device="cuda")
+        log_std = torch.full((md["na"],), -1.0, dtype=torch.float32, device="cuda")
+        sw, _, _, _, _ = time_windows(sim, s0, actor, critic, max(3, args.steps // 4), 1, noise=noise,
+                                      log_std=log_std)
+        sval = N * h / (sw / max(3, args.steps // 4))
+        out["stochastic_policy"] = {"value": round(sval, 1), "unit": "env-steps/s", "log_std": -1.0,
+                                    "vs_deterministic": round(sval / value, 3)}
+
+    if not args.no_term:
+        # the same window with early termination at the humanoid's torso height (0.74 m):
+        # per-frame test, reset from per-env restart states, discount and gradient cut
+        mdt = wl.with_termination(md)
+        simt = P.Sim(mdt, N, h, actor_dims, critic_dims, ckpt_interval=args.k)
+        reset = simt._dev(wl.initial_states(mdt, N, seed=9))
+        n_t = max(3, args.steps // 4)
+        tw, _, _, tfw, _ = time_windows(simt, s0, actor, critic, n_t, 1, reset_states=reset)
+        tval = N * h / (tw / n_t)
+        done = tfw["done"].float()
+        out["early_termination"] = {"value": round(tval, 1), "unit": "env-steps/s",
+                                    "term_height_m": float(mdt["term_height"]),
+                                    "done_frac_per_frame": round(float(done.mean()), 4),
+                                    "envs_terminated": int((done.sum(0) > 0).sum()),
+                                    "vs_no_termination": round(tval / value, 3)}
+        simt.close()
 
     if not args.no_plain:
         # the same window on the other launch forms: the tape path (the forward records
@@ -509,7 +532,7 @@ def main():
                        "published_hbm_gbs": HBM_PEAK_GBS}
     roof["frac_of_measured"] = round(achieved / ceil["fp32_valu_tflops"], 5)
 
-    if not args.no_theta:
+    if not args.no_theta and not args.no_learn:
         out["learning_episode"] = learning_episode(P, torch, sim, W)
     if not args.no_long:
         out["long_windows"] = long_windows(P, wl, torch)

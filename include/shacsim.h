@@ -331,9 +331,11 @@ int sim_soft_update(void* const* target, const void* const* online, const size_t
                     double alpha, int precision, void* hip_stream);
 
 /* TD-lambda estimates: rewards [h][N]; values [h+1][N], the target critic at the window's
- * states s_0 .. s_h (s_0's value is not used); out targets [h][N]. */
-int sim_td_lambda(const void* rewards, const void* values, int h, int n_envs, double gamma, double lambda,
-                  void* targets, int precision, void* hip_stream);
+ * states s_0 .. s_h (s_0's value is not used); done [h][N] (device, optional: the forward
+ * window's termination flags), where a frame that ended in termination has the estimate r_t
+ * (its returns stop there and the fallen state has no value); out targets [h][N]. */
+int sim_td_lambda(const void* rewards, const void* values, const uint8_t* done, int h, int n_envs, double gamma,
+                  double lambda, void* targets, int precision, void* hip_stream);
 
 /* The critic calls use the handle's critic shape and precision and a caller-owned workspace
  * of at least sim_critic_workspace_bytes(h, rows) bytes (rows: the most rows of one call). */

@@ -20,16 +20,28 @@ def _t(x):
     return x.detach().to(F64) if torch.is_tensor(x) else torch.as_tensor(x, dtype=F64)
 
 
-def td_lambda(rewards, values, gamma, lam):
-    """rewards [h, N], values [h+1, N] (V(s_0) .. V(s_h)) -> estimates [h, N]."""
+def td_lambda(rewards, values, gamma, lam, done=None):
+    """rewards [h, N], values [h+1, N] (V(s_0) .. V(s_h)) -> estimates [h, N].
+
+    done [h, N] (optional) marks frames that ended in early termination: a k-step return
+    G_t^k that reaches such a frame t + j (j < k) stops there, with the rewards up to
+    r_{t+j} and no value (the failed state is worth nothing), so G_t^k = G_t^{j+1} for
+    every longer k."""
     r, v = _t(rewards), _t(values)
-    h = r.shape[0]
+    h, N = r.shape
+    dn = torch.zeros(h, N, dtype=torch.bool) if done is None else torch.as_tensor(done).bool()
     out = torch.zeros_like(r)
     for t in range(h):
         n = h - t
+        # d[e]: offset of the first terminated frame from t (n if none inside the window)
+        d = torch.full((N,), n, dtype=torch.long)
+        for j in reversed(range(n)):
+            d = torch.where(dn[t + j], torch.full_like(d, j), d)
 
         def G(k):
-            return sum(gamma ** l * r[t + l] for l in range(k)) + gamma ** k * v[t + k]
+            full = sum(gamma ** l * r[t + l] for l in range(k)) + gamma ** k * v[t + k]
+            cut = sum(gamma ** l * r[t + l] * (l <= d) for l in range(k))
+            return torch.where(k > d, cut, full)
         est = sum((1.0 - lam) * lam ** (k - 1) * G(k) for k in range(1, n))
         out[t] = est + lam ** (n - 1) * G(n)
     return out

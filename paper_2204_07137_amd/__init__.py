@@ -131,7 +131,7 @@ def lib():
         L.sim_soft_update.argtypes = [ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(ctypes.c_size_t), _i,
                                       _d, _i, _p]
         L.sim_soft_update.restype = _i
-        L.sim_td_lambda.argtypes = [_p, _p, _i, _i, _d, _d, _p, _i, _p]
+        L.sim_td_lambda.argtypes = [_p, _p, _p, _i, _i, _d, _d, _p, _i, _p]
         L.sim_td_lambda.restype = _i
         L.sim_critic_workspace_bytes.argtypes = [_p, _i]
         L.sim_critic_workspace_bytes.restype = ctypes.c_size_t
@@ -348,7 +348,9 @@ class Sim:
         assert s0.shape == (N, self.ns), (s0.shape, (N, self.ns))
         dt = self.dtype
         keys = ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count")
+        prev_done = None
         if out is not None:
+            prev_done = out.get("done")
             out = {k: out[k] for k in keys}
             out["s0"] = s0
         else:
@@ -374,7 +376,7 @@ class Sim:
             assert reset_states.shape == (N, self.ns)
             out["reset_states"] = reset_states
             io.reset_states = self._ptr(reset_states)
-            out["done"] = t.zeros(H, N, dtype=t.uint8, device="cuda")
+            out["done"] = prev_done if prev_done is not None else t.zeros(H, N, dtype=t.uint8, device="cuda")
             io.done = self._ptr(out["done"])
         if noise is not None:
             noise = self._dev(noise)
@@ -506,13 +508,14 @@ class Group:
             pass
 
     def forward(self, args, stream=None):
-        """args: per member (s0, actor, critic[, actions_in]).  Returns per-member dicts.
-        The output tensors are kept and reused by the next call, so repeated calls with the
-        same inputs replay one captured graph (copy results out before calling again)."""
+        """args: per member (s0, actor, critic[, actions_in]), or a dict of Sim.forward's
+        keywords (noise, log_std, reset_states ...).  Returns per-member dicts.  The output
+        tensors are kept and reused by the next call, so repeated calls with the same inputs
+        replay one captured graph (copy results out before calling again)."""
         outs, ios = [], []
         prev = getattr(self, "_fw", None) or [None] * len(self.sims)
         for sim, a, pv in zip(self.sims, args, prev):
-            o, io = sim.forward_io(*a, out=pv)
+            o, io = sim.forward_io(**a, out=pv) if isinstance(a, dict) else sim.forward_io(*a, out=pv)
             outs.append(o)
             ios.append(io)
         arr = (SimForwardIO * len(ios))(*ios)
@@ -583,12 +586,17 @@ def soft_update(target, online, alpha):
     _check(lib().sim_soft_update(tp, op, sizes, n, float(alpha), _prec(target[0]), _stream()))
 
 
-def td_lambda(rewards, values, gamma=0.99, lam=0.95):
-    """sim_td_lambda: TD-lambda estimates [h, N] from rewards [h, N] and values [h+1, N]."""
+def td_lambda(rewards, values, gamma=0.99, lam=0.95, done=None):
+    """sim_td_lambda: TD-lambda estimates [h, N] from rewards [h, N] and values [h+1, N];
+    done [h, N] uint8 (the forward window's termination flags) stops the returns."""
     import torch
     h, N = rewards.shape
     out = torch.empty_like(rewards)
-    _check(lib().sim_td_lambda(_p(rewards.data_ptr()), _p(values.data_ptr()), h, N, float(gamma), float(lam),
+    dp = None
+    if done is not None:
+        assert done.dtype == torch.uint8 and tuple(done.shape) == (h, N) and done.is_cuda
+        dp = _p(done.data_ptr())
+    _check(lib().sim_td_lambda(_p(rewards.data_ptr()), _p(values.data_ptr()), dp, h, N, float(gamma), float(lam),
                                _p(out.data_ptr()), _prec(rewards), _stream()))
     return out
 

@@ -1076,11 +1076,13 @@ static int learn_launch(float, const LearnAdamT<float>& A, void* s) { return sim
 static int learn_launch(double, const LearnAdamT<double>& A, void* s) { return sim_l64::launch_adam(A, s); }
 static int soft_launch(float* t, const float* o, long n, double a, void* s) { return sim_l32::launch_soft_update(t, o, n, (float)a, s); }
 static int soft_launch(double* t, const double* o, long n, double a, void* s) { return sim_l64::launch_soft_update(t, o, n, a, s); }
-static int td_launch(const float* r, const float* v, int h, int N, double g, double l, float* out, void* s) {
-  return sim_l32::launch_td_lambda(r, v, h, N, (float)g, (float)l, out, s);
+static int td_launch(const float* r, const float* v, const uint8_t* d, int h, int N, double g, double l, float* out,
+                     void* s) {
+  return sim_l32::launch_td_lambda(r, v, d, h, N, (float)g, (float)l, out, s);
 }
-static int td_launch(const double* r, const double* v, int h, int N, double g, double l, double* out, void* s) {
-  return sim_l64::launch_td_lambda(r, v, h, N, g, l, out, s);
+static int td_launch(const double* r, const double* v, const uint8_t* d, int h, int N, double g, double l, double* out,
+                     void* s) {
+  return sim_l64::launch_td_lambda(r, v, d, h, N, g, l, out, s);
 }
 static int cv_launch(const ThetaArgsT<float>& T, float* out, void* s) { return sim_l32::launch_critic_values(T, out, s); }
 static int cv_launch(const ThetaArgsT<double>& T, double* out, void* s) { return sim_l64::launch_critic_values(T, out, s); }
@@ -1143,17 +1145,18 @@ extern "C" int sim_soft_update(void* const* target, const void* const* online, c
   return SIM_OK;
 }
 
-extern "C" int sim_td_lambda(const void* rewards, const void* values, int h, int n_envs, double gamma, double lambda,
-                             void* targets, int precision, void* hip_stream) {
+extern "C" int sim_td_lambda(const void* rewards, const void* values, const uint8_t* done, int h, int n_envs,
+                             double gamma, double lambda, void* targets, int precision, void* hip_stream) {
   if (!rewards || !values || !targets || h < 1 || n_envs < 1) return fail(SIM_E_ARG, "sim_td_lambda: null pointer or empty window");
   if (!(gamma >= 0.0 && gamma <= 1.0) || !(lambda >= 0.0 && lambda <= 1.0))
     return fail(SIM_E_ARG, "sim_td_lambda: gamma and lambda must lie in [0, 1]");
   int bad;
   if (precision == SIM_PREC_FP32)
-    bad = td_launch(static_cast<const float*>(rewards), static_cast<const float*>(values), h, n_envs, gamma, lambda,
+    bad = td_launch(static_cast<const float*>(rewards), static_cast<const float*>(values), done, h, n_envs, gamma, lambda,
                     static_cast<float*>(targets), hip_stream);
   else if (precision == SIM_PREC_FP64)
-    bad = td_launch(static_cast<const double*>(rewards), static_cast<const double*>(values), h, n_envs, gamma, lambda,
+    bad = td_launch(static_cast<const double*>(rewards), static_cast<const double*>(values), done, h, n_envs, gamma,
+                    lambda,
                     static_cast<double*>(targets), hip_stream);
   else
     return fail(SIM_E_ARG, "sim_td_lambda: unknown precision");

@@ -31,13 +31,18 @@ __global__ void k_soft_update(real* __restrict__ t, const real* __restrict__ o, 
 // G_t = r_t + gamma ((1 - lambda) V_{t+1} + lambda G_{t+1}) from G_h = V_h, which equals the
 // lambda-weighted average of the k-step returns of the definition.
 // r [h][N], v [h+1][N] (values of s_0 .. s_h; s_0's is not used), out [h][N]
-__global__ void k_td_lambda(const real* __restrict__ r, const real* __restrict__ v, int h, int N, real gamma,
-                            real lam, real* __restrict__ out) {
+__global__ void k_td_lambda(const real* __restrict__ r, const real* __restrict__ v, const uint8_t* __restrict__ done,
+                            int h, int N, real gamma, real lam, real* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   real G = v[(size_t)h * N + e];
   for (int t = h - 1; t >= 0; --t) {
-    G = r[(size_t)t * N + e] + gamma * ((RL(1.0) - lam) * v[(size_t)(t + 1) * N + e] + lam * G);
+    // a frame that ended in termination returns its reward alone: every k-step return from
+    // it stops there and the fallen state has no value (s_{t+1} is already the reset state)
+    if (done && done[(size_t)t * N + e])
+      G = r[(size_t)t * N + e];
+    else
+      G = r[(size_t)t * N + e] + gamma * ((RL(1.0) - lam) * v[(size_t)(t + 1) * N + e] + lam * G);
     out[(size_t)t * N + e] = G;
   }
 }
@@ -99,9 +104,10 @@ int launch_soft_update(real* t, const real* o, long n, real alpha, void* stream)
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_td_lambda(const real* r, const real* v, int h, int N, real gamma, real lam, real* out, void* stream) {
-  hipLaunchKernelGGL(k_td_lambda, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, (hipStream_t)stream, r, v, h, N,
-                     gamma, lam, out);
+int launch_td_lambda(const real* r, const real* v, const uint8_t* done, int h, int N, real gamma, real lam,
+                     real* out, void* stream) {
+  hipLaunchKernelGGL(k_td_lambda, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, (hipStream_t)stream, r, v, done, h,
+                     N, gamma, lam, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

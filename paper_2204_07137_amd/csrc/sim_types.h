@@ -206,7 +206,7 @@ SIM_DECLARE_LAUNCHERS(sim_f64, double)
   namespace NS {                                                                           \
   int launch_adam(const LearnAdamT<T>& A, void* stream);                                   \
   int launch_soft_update(T* t, const T* o, long n, T alpha, void* stream);                 \
-  int launch_td_lambda(const T* r, const T* v, int h, int N, T gamma, T lam, T* out, void* stream); \
+  int launch_td_lambda(const T* r, const T* v, const uint8_t* d, int h, int N, T g, T l, T* out, void* s); \
   int launch_critic_values(const ThetaArgsT<T>& A, T* out, void* stream);                  \
   int launch_critic_fit(const CriticFitT<T>& F, void* stream);                             \
   }

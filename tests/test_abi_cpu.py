@@ -72,8 +72,8 @@ def test_null_arguments_rejected():
     assert L.sim_adam_step(z, n1, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1,
                            1e-3, 0.7, 0.95, 1e-8, 0, None) == -1          # null tensor
     assert L.sim_soft_update(None, None, None, 1, 0.5, 0, None) == -1
-    assert L.sim_td_lambda(None, None, 4, 4, 0.99, 0.95, None, 0, None) == -1
-    assert L.sim_td_lambda(ctypes.c_void_p(16), ctypes.c_void_p(16), 4, 4, 1.5, 0.95, ctypes.c_void_p(16), 0,
+    assert L.sim_td_lambda(None, None, None, 4, 4, 0.99, 0.95, None, 0, None) == -1
+    assert L.sim_td_lambda(ctypes.c_void_p(16), ctypes.c_void_p(16), None, 4, 4, 1.5, 0.95, ctypes.c_void_p(16), 0,
                            None) == -1                                     # gamma outside [0, 1]
     assert L.sim_critic_workspace_bytes(None, 16) == 0
     assert L.sim_critic_values(None, None, 1, None, None, None, None, 0, None) == -2

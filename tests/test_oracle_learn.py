@@ -20,6 +20,45 @@ def test_td_lambda_special_cases():
     np.testing.assert_allclose(td_lambda(r[:1], v[:2], g, 0.37).numpy(), r[:1] + g * v[1:2], atol=1e-14)
 
 
+def test_td_lambda_with_termination():
+    """Termination flags (App. A.3 heights; Sec. 3.3 resets): every return from a frame that
+    ended in termination stops there with no value."""
+    rng = np.random.default_rng(8)
+    h, N, g = 6, 4, 0.9
+    r = rng.normal(size=(h, N))
+    v = rng.normal(size=(h + 1, N))
+    done = np.zeros((h, N), bool)
+    done[2, 0] = True                         # env 0 fails in frame 2
+    done[0, 1] = done[4, 1] = True            # env 1 twice
+    done[:, 2] = True                         # env 2 in every frame
+    # lambda = 0: r_t + gamma V(s_{t+1}), without the value after a failed frame
+    np.testing.assert_allclose(td_lambda(r, v, g, 0.0, done).numpy(), r + g * v[1:] * ~done, rtol=0, atol=1e-13)
+    # lambda = 1: the discounted return to the first failure (inclusive) or to the window's
+    # end, bootstrapped only there
+    mc = np.zeros((h, N))
+    for e in range(N):
+        for t in range(h):
+            acc, k = 0.0, t
+            while True:
+                acc += g ** (k - t) * r[k, e]
+                if done[k, e]:
+                    break
+                k += 1
+                if k == h:
+                    acc += g ** (h - t) * v[h, e]
+                    break
+            mc[t, e] = acc
+    np.testing.assert_allclose(td_lambda(r, v, g, 1.0, done).numpy(), mc, rtol=0, atol=1e-12)
+    out = td_lambda(r, v, g, 0.8, done).numpy()
+    np.testing.assert_allclose(out[:, 2], r[:, 2], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(out[:, 3], td_lambda(r[:, 3:], v[:, 3:], g, 0.8).numpy()[:, 0], rtol=0, atol=1e-15)
+    # frames up to a failure do not see what comes after it
+    r2, v2 = r.copy(), v.copy()
+    r2[3:, 0] += 5.0
+    v2[3:, 0] -= 7.0
+    np.testing.assert_array_equal(td_lambda(r2, v2, g, 0.8, done).numpy()[:3, 0], out[:3, 0])
+
+
 def test_adam_first_step_closed_form():
     rng = np.random.default_rng(6)
     p = [torch.as_tensor(rng.normal(size=(4, 3)))]
