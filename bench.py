@@ -321,8 +321,10 @@ def learning_episode(P, torch, sim, W, steps=3):
     """SHAC learning episodes on the headline batch (Sec. 3.3, Algorithm "SHAC"; App. A.2
     hyperparameters): the window with the policy-parameter gradient, one Adam step of the
     actor, the target critic's values of the window's states, TD-lambda estimates, the critic
-    fit (16 passes x 4 minibatches, Adam), the target-critic update.  The start states are
-    the same every episode (a fixed benchmark batch)."""
+    fit (16 passes x 4 minibatches, Adam), the target-critic update, and the merge of the
+    window's observations into the running statistics that normalise the networks' inputs
+    in the next episode.  The start states are the same every episode (a fixed benchmark
+    batch)."""
     N, h, od = sim.N, sim.H, sim.od
     s0 = sim._dev(W["s0"])
     actor = [(a.clone(), b.clone()) for a, b in sim.weights(W["actor"])]
@@ -336,17 +338,22 @@ def learning_episode(P, torch, sim, W, steps=3):
     perm = torch.stack([torch.randperm(h * N, generator=g) for _ in range(16)]).to(torch.int32).cuda()
     ws = sim.critic_workspace((h + 1) * N)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps + 1)]
+    mean, var = torch.zeros(od, device="cuda"), torch.ones(od, device="cuda")
+    inv = torch.ones(od, device="cuda")
+    count = [0]
 
     def episode(i, e):
         e[0].record()
-        fw = sim.forward(s0, actor, target)
+        fw = sim.forward(s0, actor, target, obs_norm=(mean, inv))
         ad = sim.adjoint(fw, want_theta=True)
         e[1].record()
         P.adam_step(flat(actor), ad["dL_dtheta_flat"], am, av, i + 1, 2e-3)
-        vals = sim.critic_values(fw["obs"], target, workspace=ws).reshape(h + 1, N)
+        vals = sim.critic_values(fw["obs"], target, workspace=ws, obs_norm=(mean, inv)).reshape(h + 1, N)
         tgt = P.td_lambda(fw["rewards"], vals, 0.99, 0.95).reshape(-1)
-        sim.critic_fit(fw["obs"][:h].reshape(-1, od), tgt, perm, 4, critic, cm, cv, i * 64, 5e-4, workspace=ws)
+        sim.critic_fit(fw["obs"][:h].reshape(-1, od), tgt, perm, 4, critic, cm, cv, i * 64, 5e-4, workspace=ws,
+                       obs_norm=(mean, inv))
         P.soft_update(flat(target), flat(critic), 0.995)
+        count[0] = P.obs_stats_update(fw["obs"][:h], count[0], mean, var, inv)
         e[2].record()
 
     episode(0, ev[0])
@@ -359,7 +366,8 @@ def learning_episode(P, torch, sim, W, steps=3):
     upd = float(np.mean([a[1].elapsed_time(a[2]) for a in ev[1:]]))
     win = float(np.mean([a[0].elapsed_time(a[1]) for a in ev[1:]]))
     return {"workload": f"humanoid {N} envs, h={h}: window + policy gradient + actor Adam + TD-lambda + "
-                        f"critic fit 16 x 4 minibatches of {h * N // 4} rows + target update",
+                        f"critic fit 16 x 4 minibatches of {h * N // 4} rows + target update + "
+                        f"observation statistics",
             "ms_per_episode": round(wall * 1e3, 3), "episodes_per_s": round(1.0 / wall, 2),
             "env_steps_per_s": round(N * h / wall, 1), "window_ms": round(win, 3), "update_ms": round(upd, 3)}
 

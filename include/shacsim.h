@@ -198,6 +198,11 @@ typedef struct SimForwardIO {
                                                (required with term_enabled) */
   uint8_t* done;                            /* [h][N] out, optional: 1 if the env terminated at
                                                the end of frame t */
+  /* Observation normalisation (Sec. 3.3, running mean and deviation): with both set, the
+   * actor and the critic read (o - obs_mean) * obs_inv_std, both [obs_dim] (for example from
+   * sim_obs_stats_update); both NULL = raw observations.  The obs output stays raw. */
+  const void* obs_mean;
+  const void* obs_inv_std;
 } SimForwardIO;
 
 typedef struct SimAdjointIO {
@@ -227,6 +232,8 @@ typedef struct SimAdjointIO {
   void* dL_dlog_std;                        /* [na] optional out (with dL_dtheta and noise): the
                                                sum over frames and envs of dL/dy_t * exp(log_std)
                                                * eps_t; bitwise reproducible */
+  const void* obs_mean;                     /* as given to the forward, or NULL */
+  const void* obs_inv_std;
 } SimAdjointIO;
 
 /* Validates the model and options and uploads the constant tables to the current device.
@@ -342,10 +349,11 @@ int sim_td_lambda(const void* rewards, const void* values, const uint8_t* done, 
 size_t sim_critic_workspace_bytes(const SimHandle* h, int rows);
 
 /* values [rows] = V(obs [rows][obs_dim]) with the given critic weights (host arrays of device
- * pointers, W [out][in], b [out]). */
+ * pointers, W [out][in], b [out]); with obs_mean and obs_inv_std ([obs_dim], both or neither)
+ * the critic reads (obs - obs_mean) * obs_inv_std. */
 int sim_critic_values(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
-                      const void* const* critic_b, void* values, void* workspace, size_t workspace_bytes,
-                      void* hip_stream);
+                      const void* const* critic_b, const void* obs_mean, const void* obs_inv_std, void* values,
+                      void* workspace, size_t workspace_bytes, void* hip_stream);
 
 typedef struct SimCriticFitIO {
   const void* obs;              /* [rows][obs_dim] states of the window (o_0 .. o_{h-1}) */
@@ -364,7 +372,17 @@ typedef struct SimCriticFitIO {
                                    error before its step */
   void* workspace;
   size_t workspace_bytes;
+  const void* obs_mean;         /* [obs_dim] optional (with obs_inv_std): the critic reads */
+  const void* obs_inv_std;      /* (obs - obs_mean) * obs_inv_std */
 } SimCriticFitIO;
+
+/* Running observation statistics (Sec. 3.3): merges rows [rows][dim] of observations (device)
+ * into the running count, mean [dim] and population variance var [dim] of all observations
+ * merged before (count = 0: mean and var are only written), and writes
+ * inv_std [dim] = 1 / sqrt(var + eps).  The caller keeps the count: the new count is
+ * count + rows.  Pairwise (Chan-Golub-LeVeque) update with FP64 sums in a fixed order. */
+int sim_obs_stats_update(const void* obs, long rows, int dim, double count, void* mean, void* var, void* inv_std,
+                         double eps, int precision, void* hip_stream);
 
 /* Fits the critic: for every pass and minibatch, the mean of (V(o) - target)^2 over the
  * minibatch, its gradient through the critic's layers, one Adam step.  The order of the

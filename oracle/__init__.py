@@ -22,7 +22,7 @@ may import this package.  The product path never calls it.
 from .dynamics import (OracleModel, substep, dynamics_terms, kinetic_energy, potential_energy,
                        muscle_terms, activation_step)
 from .window import (oracle_window, oracle_window_grads, obs_fn, reward_fn, mlp_forward,
-                     mlp_forward_bf16, bf16_round, squash)
+                     mlp_forward_bf16, bf16_round, squash, normalize_obs)
 
 __all__ = ["OracleModel", "substep", "dynamics_terms", "kinetic_energy", "potential_energy",
-           "oracle_window", "oracle_window_grads", "obs_fn", "reward_fn", "mlp_forward"]
+           "oracle_window", "oracle_window_grads", "obs_fn", "reward_fn", "mlp_forward", "normalize_obs"]

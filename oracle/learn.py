@@ -47,6 +47,22 @@ def td_lambda(rewards, values, gamma, lam, done=None):
     return out
 
 
+def obs_stats_update(obs, count, mean, var, eps):
+    """Running observation statistics (Sec. 3.3): the mean and population variance of every
+    observation seen so far, from the first and second raw moments of the union of the
+    `count` earlier samples (summarised by mean and var) and the new rows obs [rows, dim].
+    Returns (count', mean', var', inv_std = 1 / sqrt(var' + eps))."""
+    x = _t(obs)
+    rows = x.shape[0]
+    n = count + rows
+    m0 = _t(mean) if count > 0 else torch.zeros(x.shape[1], dtype=torch.float64)
+    v0 = _t(var) if count > 0 else torch.zeros(x.shape[1], dtype=torch.float64)
+    first = (count * m0 + x.sum(0)) / n
+    second = (count * (v0 + m0 * m0) + (x * x).sum(0)) / n
+    v = second - first * first
+    return n, first, v, 1.0 / torch.sqrt(v + eps)
+
+
 def adam_step(params, grads, m, v, step, lr, beta1, beta2, eps):
     """One Adam step; returns (params, m, v) as new lists."""
     P, M, V = [], [], []

@@ -136,9 +136,18 @@ def _layers(params):
     return [(_t(W), _t(b)) for (W, b) in params]
 
 
+def normalize_obs(o, obs_norm):
+    """Observation normalisation with running statistics (Sec. 3.3): the networks read
+    (o - mean) * inv_std; obs_norm = (mean, inv_std), or None for the raw observation."""
+    if obs_norm is None:
+        return o
+    mean, inv_std = (x if torch.is_tensor(x) else _t(x) for x in obs_norm)
+    return (o - mean) * inv_std
+
+
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
                   keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None,
-                  reset_states=None):
+                  reset_states=None, obs_norm=None):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
@@ -152,6 +161,8 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     whose root is below that height at the end of a frame restarts from its reset state (a
     constant), and its discount restarts at the next frame; a segment that ends in a
     termination has no terminal value.
+    obs_norm = (mean, inv_std) [od]: actor and critic read normalised observations; the
+    returned obs stay raw.
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
     s = s0 if torch.is_tensor(s0) else _t(s0)
@@ -171,7 +182,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     for t in range(h):
         o = obs_fn(m, s)
         if actions is None:
-            y = mlp(act_l, o)
+            y = mlp(act_l, normalize_obs(o, obs_norm))
             if noise is not None:
                 ls = log_std if torch.is_tensor(log_std) else _t(log_std)
                 y = y + torch.exp(ls) * (noise[t] if torch.is_tensor(noise) else _t(noise[t]))
@@ -205,7 +216,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         rews.append(r)
     o_h = obs_fn(m, s)
     obs.append(o_h)
-    value = mlp(crit_l, o_h)[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
+    value = mlp(crit_l, normalize_obs(o_h, obs_norm))[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
     if term_h is None:
         disc = sum(gamma ** t * rews[t] for t in range(h))
         loss = -(disc + gamma ** h * value).sum() / (N * h)
@@ -221,7 +232,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
                         n_total=None, want_theta=False, bf16=False, noise=None, log_std=None,
-                        reset_states=None):
+                        reset_states=None, obs_norm=None):
     """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
 
     Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
@@ -241,7 +252,8 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
     if noise is not None:
         ls = _t(log_std).clone().requires_grad_(want_theta)
     out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
-                        layers=layers, bf16=bf16, noise=noise, log_std=ls, reset_states=reset_states)
+                        layers=layers, bf16=bf16, noise=noise, log_std=ls, reset_states=reset_states,
+                        obs_norm=obs_norm)
     wrt = [s0t] + list(out["actions"])
     theta = []
     if want_theta and actor is not None:

@@ -50,7 +50,8 @@ class SimForwardIO(ctypes.Structure):
                 ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("workspace", _p),
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
                 ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p),
-                ("noise", _p), ("log_std", _p), ("reset_states", _p), ("done", _p)]
+                ("noise", _p), ("log_std", _p), ("reset_states", _p), ("done", _p),
+                ("obs_mean", _p), ("obs_inv_std", _p)]
 
 
 class SimAdjointIO(ctypes.Structure):
@@ -58,7 +59,8 @@ class SimAdjointIO(ctypes.Structure):
                 ("actor_w", _p * MAXL), ("actor_b", _p * MAXL), ("critic_w", _p * MAXL),
                 ("critic_b", _p * MAXL), ("workspace", _p), ("workspace_bytes", ctypes.c_size_t),
                 ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p),
-                ("dL_dtheta", _p), ("noise", _p), ("log_std", _p), ("dL_dlog_std", _p)]
+                ("dL_dtheta", _p), ("noise", _p), ("log_std", _p), ("dL_dlog_std", _p),
+                ("obs_mean", _p), ("obs_inv_std", _p)]
 
 
 class SimTuneResult(ctypes.Structure):
@@ -70,7 +72,7 @@ class SimCriticFitIO(ctypes.Structure):
     _fields_ = [("obs", _p), ("targets", _p), ("rows", _i), ("perm", _p), ("n_iter", _i), ("n_minibatch", _i),
                 ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("adam_m", _p), ("adam_v", _p),
                 ("adam_step", _i), ("lr", _d), ("beta1", _d), ("beta2", _d), ("eps", _d), ("loss_out", _p),
-                ("workspace", _p), ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace", _p), ("workspace_bytes", ctypes.c_size_t), ("obs_mean", _p), ("obs_inv_std", _p)]
 
 
 EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
@@ -78,7 +80,7 @@ EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window"
            "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
            "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy", "sim_adam_step",
            "sim_soft_update", "sim_td_lambda", "sim_critic_workspace_bytes", "sim_critic_values",
-           "sim_critic_fit"]
+           "sim_critic_fit", "sim_obs_stats_update"]
 MAX_GROUP = 6
 
 _LIB = None
@@ -135,10 +137,13 @@ def lib():
         L.sim_td_lambda.restype = _i
         L.sim_critic_workspace_bytes.argtypes = [_p, _i]
         L.sim_critic_workspace_bytes.restype = ctypes.c_size_t
-        L.sim_critic_values.argtypes = [_p, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _p, ctypes.c_size_t, _p]
+        L.sim_critic_values.argtypes = [_p, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _p, _p, _p,
+                                        ctypes.c_size_t, _p]
         L.sim_critic_values.restype = _i
         L.sim_critic_fit.argtypes = [_p, ctypes.POINTER(SimCriticFitIO), _p]
         L.sim_critic_fit.restype = _i
+        L.sim_obs_stats_update.argtypes = [_p, ctypes.c_long, _i, _d, _p, _p, _p, _d, _i, _p]
+        L.sim_obs_stats_update.restype = _i
         _LIB = L
     return _LIB
 
@@ -258,8 +263,16 @@ class Sim:
         n = int(lib().sim_critic_workspace_bytes(self.h, int(rows)))
         return self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
 
-    def critic_values(self, obs, critic, workspace=None):
-        """sim_critic_values: V(obs) for obs [rows, obs_dim] with critic [(W, b), ...] (device)."""
+    def _norm_ptrs(self, obs_norm):
+        if obs_norm is None:
+            return _p(0), _p(0), None
+        mean, inv_std = (self._dev(x).reshape(-1) for x in obs_norm)
+        assert mean.shape == (self.od,) and inv_std.shape == (self.od,)
+        return _p(mean.data_ptr()), _p(inv_std.data_ptr()), (mean, inv_std)
+
+    def critic_values(self, obs, critic, workspace=None, obs_norm=None):
+        """sim_critic_values: V(obs) for obs [rows, obs_dim] with critic [(W, b), ...] (device);
+        obs_norm = (mean, inv_std) normalises the critic's input."""
         t = self.torch
         obs = self._dev(obs).reshape(-1, self.od)
         rows = obs.shape[0]
@@ -268,12 +281,14 @@ class Sim:
         w = (_p * MAXL)(*([_p(W.data_ptr()) for W, _ in cw] + [_p(0)] * (MAXL - len(cw))))
         b = (_p * MAXL)(*([_p(B.data_ptr()) for _, B in cw] + [_p(0)] * (MAXL - len(cw))))
         out = t.empty(rows, device="cuda", dtype=self.dtype)
-        _check(lib().sim_critic_values(self.h, _p(obs.data_ptr()), rows, w, b, _p(out.data_ptr()),
+        pm, ps, keep = self._norm_ptrs(obs_norm)
+        _check(lib().sim_critic_values(self.h, _p(obs.data_ptr()), rows, w, b, pm, ps, _p(out.data_ptr()),
                                        _p(ws.data_ptr()), ws.numel(), _stream()))
+        del keep
         return out
 
     def critic_fit(self, obs, targets, perm, n_minibatch, critic, adam_m, adam_v, adam_step, lr,
-                   beta1=0.7, beta2=0.95, eps=1e-8, workspace=None):
+                   beta1=0.7, beta2=0.95, eps=1e-8, workspace=None, obs_norm=None):
         """sim_critic_fit: fits `critic` (a list of device (W, b) tensors of this handle's dtype,
         updated in place) to targets [rows] on obs [rows, obs_dim] over len(perm) passes of
         n_minibatch minibatches (perm [n_iter, rows] int32).  Returns the minibatch losses."""
@@ -296,7 +311,9 @@ class Sim:
         io.lr, io.beta1, io.beta2, io.eps = float(lr), float(beta1), float(beta2), float(eps)
         io.loss_out = _p(losses.data_ptr())
         io.workspace, io.workspace_bytes = _p(ws.data_ptr()), ws.numel()
+        io.obs_mean, io.obs_inv_std, keep = self._norm_ptrs(obs_norm)
         _check(lib().sim_critic_fit(self.h, ctypes.byref(io), _stream()))
+        del keep
         return losses
 
     def close(self):
@@ -326,20 +343,21 @@ class Sim:
         return _p(t.data_ptr()) if t is not None else _p(0)
 
     def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None, noise=None, log_std=None,
-                reset_states=None):
+                reset_states=None, obs_norm=None):
         """Run sim_forward_window.  Returns a dict of device tensors.  noise [h, N, na] and
         log_std [na] select the stochastic policy y = mu(o) + exp(log_std) * noise;
         reset_states [N, ns] are the restart states of a model with early termination (the
-        result then holds done [h, N])."""
+        result then holds done [h, N]); obs_norm = (mean, inv_std) [obs_dim] normalises the
+        networks' inputs (the adjoint takes it from the result)."""
         out, io = self.forward_io(s0, actor, critic, actions_in, noise=noise, log_std=log_std,
-                                  reset_states=reset_states)
+                                  reset_states=reset_states, obs_norm=obs_norm)
         t = self.torch
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
         return out
 
     def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None, noise=None, log_std=None,
-                   reset_states=None):
+                   reset_states=None, obs_norm=None):
         """Allocate the forward outputs (or reuse those of `out`, a previous result) and
         fill a SimForwardIO (no launch)."""
         t = self.torch
@@ -384,6 +402,8 @@ class Sim:
             assert noise.shape == (H, N, self.na) and log_std.shape == (self.na,)
             out["noise"], out["log_std"] = noise, log_std
             io.noise, io.log_std = self._ptr(noise), self._ptr(log_std)
+        if obs_norm is not None:
+            io.obs_mean, io.obs_inv_std, out["obs_norm"] = self._norm_ptrs(obs_norm)
         self._set_weights(io, actor, critic, out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
@@ -446,6 +466,8 @@ class Sim:
         io.loss_scale = float(1.0 / (N * H) if loss_scale is None else loss_scale)
         io.dL_da = self._ptr(out["dL_da"])
         io.dL_ds0 = self._ptr(out["dL_ds0"])
+        if "obs_norm" in fw:
+            io.obs_mean, io.obs_inv_std = self._ptr(fw["obs_norm"][0]), self._ptr(fw["obs_norm"][1])
         if "noise" in fw:
             io.noise, io.log_std = self._ptr(fw["noise"]), self._ptr(fw["log_std"])
             if want_theta:
@@ -599,6 +621,18 @@ def td_lambda(rewards, values, gamma=0.99, lam=0.95, done=None):
     _check(lib().sim_td_lambda(_p(rewards.data_ptr()), _p(values.data_ptr()), dp, h, N, float(gamma), float(lam),
                                _p(out.data_ptr()), _prec(rewards), _stream()))
     return out
+
+
+def obs_stats_update(obs, count, mean, var, inv_std, eps=1e-5):
+    """sim_obs_stats_update: merges obs [rows, dim] (device) into the running statistics
+    (count, mean [dim], var [dim]) in place, writes inv_std = 1 / sqrt(var + eps), and
+    returns the new count."""
+    obs = obs.reshape(-1, mean.numel())
+    assert obs.is_contiguous() and all(x.dtype == obs.dtype and x.is_cuda for x in (mean, var, inv_std))
+    rows, dim = obs.shape
+    _check(lib().sim_obs_stats_update(_p(obs.data_ptr()), rows, dim, float(count), _p(mean.data_ptr()),
+                                      _p(var.data_ptr()), _p(inv_std.data_ptr()), float(eps), _prec(obs), _stream()))
+    return count + rows
 
 
 def probe_ceilings(copy_bytes=1 << 30):

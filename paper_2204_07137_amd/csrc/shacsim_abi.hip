@@ -526,6 +526,8 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.done_out = io->done;
   A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
   A.seg_ws = reinterpret_cast<int*>(ws + h->off_seg);
+  A.obs_mean = static_cast<const T*>(io->obs_mean);
+  A.obs_inv_std = static_cast<const T*>(io->obs_inv_std);
   return SIM_OK;
 }
 
@@ -560,6 +562,8 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.grad_s_h = static_cast<const T*>(io->grad_s_h);
   A.dL_da = static_cast<T*>(io->dL_da);
   A.dL_ds0 = static_cast<T*>(io->dL_ds0);
+  A.obs_mean = static_cast<const T*>(io->obs_mean);
+  A.obs_inv_std = static_cast<const T*>(io->obs_inv_std);
   return SIM_OK;
 }
 
@@ -583,6 +587,8 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
     if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + h->off_th_h[l]);
   }
   P.x0 = static_cast<const T*>(io->obs);
+  P.x_shift = static_cast<const T*>(io->obs_mean);
+  P.x_scale = static_cast<const T*>(io->obs_inv_std);
   P.act = static_cast<const T*>(io->actions);
   P.da = static_cast<const T*>(io->dL_da);
   P.d0 = reinterpret_cast<T*>(ws + h->off_th_d0);
@@ -666,6 +672,8 @@ static int check_forward_io(SimHandle* h, const SimForwardIO* io) {
     return fail(SIM_E_ARG, "the stochastic policy needs both noise and log_std");
   if (io->noise && !o.closed_loop) return fail(SIM_E_ARG, "noise needs the closed-loop policy");
   if (h->m64.term && !io->reset_states) return fail(SIM_E_ARG, "early termination needs reset_states");
+  if ((io->obs_mean != nullptr) != (io->obs_inv_std != nullptr))
+    return fail(SIM_E_ARG, "observation normalisation needs both obs_mean and obs_inv_std");
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
   return SIM_OK;
@@ -688,6 +696,8 @@ static int check_adjoint_io(SimHandle* h, const SimAdjointIO* io) {
     return fail(SIM_E_ARG, "the stochastic policy needs both noise and log_std");
   if (io->dL_dlog_std && (!io->dL_dtheta || !io->noise))
     return fail(SIM_E_ARG, "dL_dlog_std needs dL_dtheta and the forward's noise and log_std");
+  if ((io->obs_mean != nullptr) != (io->obs_inv_std != nullptr))
+    return fail(SIM_E_ARG, "observation normalisation needs both obs_mean and obs_inv_std");
   if (!io->workspace || io->workspace_bytes < h->ws_bytes)
     return fail(SIM_E_WORKSPACE, "workspace missing or smaller than sim_workspace_bytes()");
   return SIM_OK;
@@ -1165,6 +1175,25 @@ extern "C" int sim_td_lambda(const void* rewards, const void* values, const uint
   return SIM_OK;
 }
 
+extern "C" int sim_obs_stats_update(const void* obs, long rows, int dim, double count, void* mean, void* var,
+                                    void* inv_std, double eps, int precision, void* hip_stream) {
+  if (!obs || !mean || !var || !inv_std || rows < 1 || dim < 1)
+    return fail(SIM_E_ARG, "sim_obs_stats_update: null pointer or empty batch");
+  if (!(count >= 0.0) || !(eps >= 0.0)) return fail(SIM_E_ARG, "sim_obs_stats_update: need count >= 0 and eps >= 0");
+  int bad;
+  if (precision == SIM_PREC_FP32)
+    bad = sim_l32::launch_obs_stats(static_cast<const float*>(obs), rows, dim, count, static_cast<float*>(mean),
+                                    static_cast<float*>(var), static_cast<float*>(inv_std), eps, hip_stream);
+  else if (precision == SIM_PREC_FP64)
+    bad = sim_l64::launch_obs_stats(static_cast<const double*>(obs), rows, dim, count, static_cast<double*>(mean),
+                                    static_cast<double*>(var), static_cast<double*>(inv_std), eps, hip_stream);
+  else
+    return fail(SIM_E_ARG, "sim_obs_stats_update: unknown precision");
+  if (bad) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
 // workspace of the critic calls: x [rows][od], y [rows], V [rows], H[1..nl-1] [rows][dims],
 // d0 / d1 [rows][max width], split partials, the flat gradient
 #define CRITIC_SPLITS 32
@@ -1227,29 +1256,35 @@ static void critic_theta_args(const SimHandle* h, const CriticWs& w, char* ws, c
 
 template <typename T>
 static int critic_values_impl(SimHandle* h, const void* obs, int rows, const void* const* cw, const void* const* cb,
-                              void* values, void* workspace, void* stream) {
+                              const void* mean, const void* inv_std, void* values, void* workspace, void* stream) {
   const CriticWs w = critic_ws(h->opt, rows, sizeof(T));
   ThetaArgsT<T> P;
   critic_theta_args<T>(h, w, static_cast<char*>(workspace), cw, cb, rows, P);
   P.x0 = static_cast<const T*>(obs);
+  P.x_shift = static_cast<const T*>(mean);
+  P.x_scale = static_cast<const T*>(inv_std);
   if (cv_launch(P, static_cast<T*>(values), stream)) return launch_failed();
   g_err.clear();
   return SIM_OK;
 }
 
 extern "C" int sim_critic_values(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
-                                 const void* const* critic_b, void* values, void* workspace, size_t workspace_bytes,
-                                 void* hip_stream) {
+                                 const void* const* critic_b, const void* obs_mean, const void* obs_inv_std,
+                                 void* values, void* workspace, size_t workspace_bytes, void* hip_stream) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!obs || !values || !critic_w || !critic_b || rows < 1) return fail(SIM_E_ARG, "sim_critic_values: null pointer or no rows");
   for (int l = 0; l < h->opt.critic_layers; ++l)
     if (!critic_w[l] || !critic_b[l]) return fail(SIM_E_ARG, "sim_critic_values: null critic weights");
+  if ((obs_mean != nullptr) != (obs_inv_std != nullptr))
+    return fail(SIM_E_ARG, "sim_critic_values: observation normalisation needs both obs_mean and obs_inv_std");
   if (!workspace || workspace_bytes < sim_critic_workspace_bytes(h, rows))
     return fail(SIM_E_WORKSPACE, "sim_critic_values: workspace smaller than sim_critic_workspace_bytes()");
   return (h->opt.precision == SIM_PREC_FP64)
-             ? critic_values_impl<double>(h, obs, rows, critic_w, critic_b, values, workspace, hip_stream)
-             : critic_values_impl<float>(h, obs, rows, critic_w, critic_b, values, workspace, hip_stream);
+             ? critic_values_impl<double>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, workspace,
+                                          hip_stream)
+             : critic_values_impl<float>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, workspace,
+                                         hip_stream);
 }
 
 template <typename T>
@@ -1260,6 +1295,8 @@ static int critic_fit_impl(SimHandle* h, const SimCriticFitIO* io, void* stream)
   std::memset(&F, 0, sizeof(F));
   critic_theta_args<T>(h, w, ws, io->critic_w, io->critic_b, io->rows, F.G);
   F.obs = static_cast<const T*>(io->obs);
+  F.obs_mean = static_cast<const T*>(io->obs_mean);
+  F.obs_inv_std = static_cast<const T*>(io->obs_inv_std);
   F.targets = static_cast<const T*>(io->targets);
   F.perm = io->perm;
   F.rows = io->rows; F.n_iter = io->n_iter; F.n_mb = io->n_minibatch;
@@ -1292,6 +1329,8 @@ extern "C" int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_
   if (io->adam_step < 0 || !(io->lr >= 0.0) || !(io->beta1 >= 0.0 && io->beta1 < 1.0) ||
       !(io->beta2 >= 0.0 && io->beta2 < 1.0) || !(io->eps > 0.0))
     return fail(SIM_E_ARG, "sim_critic_fit: need adam_step >= 0, lr >= 0, 0 <= beta < 1, eps > 0");
+  if ((io->obs_mean != nullptr) != (io->obs_inv_std != nullptr))
+    return fail(SIM_E_ARG, "sim_critic_fit: observation normalisation needs both obs_mean and obs_inv_std");
   if (!io->workspace || io->workspace_bytes < sim_critic_workspace_bytes(h, io->rows))
     return fail(SIM_E_WORKSPACE, "sim_critic_fit: workspace smaller than sim_critic_workspace_bytes()");
   return (h->opt.precision == SIM_PREC_FP64) ? critic_fit_impl<double>(h, io, hip_stream)

@@ -51,6 +51,12 @@ struct GemmArgs {
   const real* bias;  // EPI_BIAS_ELU: C = elu(acc + bias[n]); EPI_BIAS: C = acc + bias[n]
   const real* Hm;    // EPI_DELU: C = acc * elu'(z), z > 0 <=> Hm > 0, else elu'(z) = Hm + 1
   long ldh;
+  // optional per-column affine on the operand loads (observation normalisation of a first
+  // layer's input): A(m, k) -> (A(m, k) - a_shift[k]) * a_scale[k], B(k, n) likewise by n
+  const real* a_shift;
+  const real* a_scale;
+  const real* b_shift;
+  const real* b_scale;
 };
 
 __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
@@ -76,7 +82,12 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
       const int mm = a_kfast ? e / GT_K : e % GT_M;
       const int kk = a_kfast ? e % GT_K : e / GT_M;
       const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < g.M && k < ke) ? g.A[(long)m * g.sam + (long)k * g.sak] : RL(0.0);
+      real v = RL(0.0);
+      if (m < g.M && k < ke) {
+        v = g.A[(long)m * g.sam + (long)k * g.sak];
+        if (g.a_shift) v = (v - g.a_shift[k]) * g.a_scale[k];
+      }
+      As[kk][mm] = v;
     }
 #pragma unroll
     for (int r = 0; r < GT_N * GT_K / GT_THREADS; ++r) {
@@ -86,8 +97,10 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
       const int n = n0 + nn, k = k0 + kk;
       real v = RL(0.0);
       if (k < ke) {
-        if (n < bcols) v = g.B[(long)k * g.sbk + (long)n * g.sbn];
-        else if (g.ones_col && n == g.N - 1) v = RL(1.0);
+        if (n < bcols) {
+          v = g.B[(long)k * g.sbk + (long)n * g.sbn];
+          if (g.b_shift) v = (v - g.b_shift[n]) * g.b_scale[n];
+        } else if (g.ones_col && n == g.N - 1) v = RL(1.0);
       }
       Bs[kk][nn] = v;
     }
@@ -189,6 +202,7 @@ static void theta_hidden(const ThetaArgsT<real>& T, hipStream_t s) {
     g.k_chunk = (ni + GT_K - 1) / GT_K * GT_K;
     g.C = T.H[l + 1]; g.ldc = no;
     g.epi = EPI_BIAS_ELU; g.bias = T.b[l];
+    if (l == 0) { g.a_shift = T.x_shift; g.a_scale = T.x_scale; }
     launch_gemm(g, 1, s);
   }
 }
@@ -204,6 +218,7 @@ static void theta_output(const ThetaArgsT<real>& T, real* out, hipStream_t s) {
   g.k_chunk = (ni + GT_K - 1) / GT_K * GT_K;
   g.C = out; g.ldc = no;
   g.epi = EPI_BIAS; g.bias = T.b[L - 1];
+  if (L == 1) { g.a_shift = T.x_shift; g.a_scale = T.x_scale; }
   launch_gemm(g, 1, s);
 }
 
@@ -223,6 +238,7 @@ static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
     g.M = no; g.N = ni + 1; g.K = M; g.k_chunk = chunk;
     g.C = T.part; g.ldc = ni + 1; g.split_stride = (long)no * (ni + 1);
     g.epi = EPI_STORE;
+    if (l == 0) { g.b_shift = T.x_shift; g.b_scale = T.x_scale; }
     launch_gemm(g, splits, s);
     const long nr = (long)no * (ni + 1);
     hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, T.part, splits,

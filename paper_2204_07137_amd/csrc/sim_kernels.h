@@ -42,6 +42,19 @@ __device__ __forceinline__ void load_qqd(const Scal* __restrict__ m, L& E, const
   __syncthreads();
 }
 
+// observation normalisation with running statistics (Sec. 3.3): the networks read
+// o_hat = (o - mean) * inv_std, so the observation adjoint is o_hat_bar * inv_std
+__device__ __forceinline__ void obs_normalize(const WinArgs& A, const Scal* __restrict__ m, real* o, int ln) {
+  if (!A.obs_mean) return;
+  for (int i = ln; i < m->od; i += SIM_WAVE) o[i] = (o[i] - A.obs_mean[i]) * A.obs_inv_std[i];
+  __syncthreads();
+}
+__device__ __forceinline__ void obs_adjoint_scale(const WinArgs& A, const Scal* __restrict__ m, real* ob, int ln) {
+  if (!A.obs_mean) return;
+  for (int i = ln; i < m->od; i += SIM_WAVE) ob[i] *= A.obs_inv_std[i];
+  __syncthreads();
+}
+
 // observation, action and reward at the start of frame t (state in E.q/E.qd, previous
 // action in E.a); leaves a_t in E.a.
 template <class L>
@@ -52,6 +65,7 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   real* ob = A.obs + ((size_t)t * N + env) * od;
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
   if (A.closed_loop) {
+    obs_normalize(A, m, E.obs, ln);
     mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
     if (A.noise) {
       // stochastic policy, reparameterised (Sec. 3.3): y = mu(o) + exp(log_std) * eps
@@ -79,6 +93,7 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restr
   task_obs(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)A.h * N + env) * od;
   for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
+  obs_normalize(A, m, E.obs, ln);
   mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
   if (ln == 0) A.value[env] = E.y[0];
   real* so = A.s_h + (size_t)env * ns;
@@ -161,6 +176,7 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
     for (int i = ln; i < L::kMtu; i += SIM_WAVE) E.act_bar[i] = RL(0.0);
   for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
   __syncthreads();
+  obs_normalize(A, m, E.obs, ln);
   mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
   // terminal value discounted from the start of the last segment (early termination)
   const int eh = m->term ? A.h - A.seg_ws[(size_t)A.h * A.N + env] : A.h;
@@ -168,6 +184,7 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
   if (ln == 0) E.y[0] = c;
   __syncthreads();
   mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
+  obs_adjoint_scale(A, m, E.obs, ln);
   // E.obs now holds obs_bar; E.a holds a_prev of s_h
   task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   if (A.grad_s_h) {
@@ -207,12 +224,14 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   if (A.closed_loop) {
     for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)t * N + env) * od + i];
     __syncthreads();
+    obs_normalize(A, m, E.obs, ln);
     mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
     for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
     mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
     for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
     __syncthreads();
+    obs_adjoint_scale(A, m, E.obs, ln);
     task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   } else {
     for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);

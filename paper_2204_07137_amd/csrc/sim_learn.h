@@ -48,14 +48,71 @@ __global__ void k_td_lambda(const real* __restrict__ r, const real* __restrict__
 }
 
 // minibatch rows: x[b] = obs[perm[b]], y[b] = targets[perm[b]]
+// (normalised with the running statistics when given: x = (o - mean) * inv_std)
 __global__ void k_gather_rows(const real* __restrict__ obs, const real* __restrict__ tgt, const int* __restrict__ perm,
-                              int B, int od, real* __restrict__ x, real* __restrict__ y) {
+                              int B, int od, const real* __restrict__ mean, const real* __restrict__ inv_std,
+                              real* __restrict__ x, real* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)B * od) return;
   const int b = (int)(i / od), c = (int)(i % od);
   const int r = perm[b];
-  x[i] = obs[(long)r * od + c];
+  real v = obs[(long)r * od + c];
+  if (mean) v = (v - mean[c]) * inv_std[c];
+  x[i] = v;
   if (c == 0) y[b] = tgt[r];
+}
+
+// Running observation statistics (Sec. 3.3): merges a batch of rows into the count, mean
+// and (population) variance of every observation seen before, by the pairwise update of
+// Chan, Golub and LeVeque: with the batch's own mean m_b and sum of squared deviations
+// M2_b, delta = m_b - mean, n = count + rows,
+//   mean' = mean + delta rows / n,   var' = (var count + M2_b + delta^2 count rows / n) / n,
+// and inv_std = 1 / sqrt(var' + eps).  A block owns 64 columns; its 16 row groups read
+// consecutive columns of a row (coalesced) and are summed in a fixed order, in FP64.
+#define OS_COLS 64
+#define OS_GROUPS 16
+__global__ __launch_bounds__(OS_COLS * OS_GROUPS) void k_obs_stats(const real* __restrict__ x, long rows, int od,
+                                                                    double count, real* __restrict__ mean,
+                                                                    real* __restrict__ var, real* __restrict__ inv_std,
+                                                                    double eps) {
+  __shared__ double red[OS_GROUPS][OS_COLS];
+  __shared__ double bmean[OS_COLS];
+  const int cl = threadIdx.x % OS_COLS, grp = threadIdx.x / OS_COLS;
+  const int c = blockIdx.x * OS_COLS + cl;
+  const bool ok = c < od;
+  double s = 0.0;
+  if (ok)
+    for (long r = grp; r < rows; r += OS_GROUPS) s += (double)x[r * od + c];
+  red[grp][cl] = s;
+  __syncthreads();
+  if (grp == 0) {
+    double t = 0.0;
+    for (int g = 0; g < OS_GROUPS; ++g) t += red[g][cl];
+    bmean[cl] = t / (double)rows;
+  }
+  __syncthreads();
+  const double bm = bmean[cl];
+  double q = 0.0;
+  if (ok)
+    for (long r = grp; r < rows; r += OS_GROUPS) {
+      const double d = (double)x[r * od + c] - bm;
+      q += d * d;
+    }
+  red[grp][cl] = q;
+  __syncthreads();
+  if (grp == 0 && ok) {
+    double m2b = 0.0;
+    for (int g = 0; g < OS_GROUPS; ++g) m2b += red[g][cl];
+    const double n = count + (double)rows;
+    const double m0 = count > 0.0 ? (double)mean[c] : 0.0;
+    const double v0 = count > 0.0 ? (double)var[c] : 0.0;
+    const double delta = bm - m0;
+    const double mn = m0 + delta * ((double)rows / n);
+    const double vn = (v0 * count + m2b + delta * delta * (count * (double)rows / n)) / n;
+    mean[c] = (real)mn;
+    var[c] = (real)vn;
+    inv_std[c] = (real)(1.0 / sqrt(vn + eps));
+  }
 }
 
 // output adjoint of the mean squared error (1/B) sum (V - y)^2
@@ -111,6 +168,13 @@ int launch_td_lambda(const real* r, const real* v, const uint8_t* done, int h, i
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int launch_obs_stats(const real* x, long rows, int od, double count, real* mean, real* var, real* inv_std,
+                     double eps, void* stream) {
+  hipLaunchKernelGGL(k_obs_stats, dim3((unsigned)((od + OS_COLS - 1) / OS_COLS)), dim3(OS_COLS * OS_GROUPS), 0,
+                     (hipStream_t)stream, x, rows, od, count, mean, var, inv_std, eps);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_critic_values(const ThetaArgsT<real>& T, real* out, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   theta_hidden(T, s);
@@ -131,7 +195,7 @@ int launch_critic_fit(const CriticFitT<real>& F, void* stream) {
       if (B <= 0) continue;
       const long nx = (long)B * T.dims[0];
       hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, F.obs, F.targets,
-                         F.perm + (long)it * F.rows + r0, B, T.dims[0], F.x, F.y);
+                         F.perm + (long)it * F.rows + r0, B, T.dims[0], F.obs_mean, F.obs_inv_std, F.x, F.y);
       T.M = B;
       T.x0 = F.x;
       theta_hidden(T, s);

@@ -117,6 +117,9 @@ struct WinArgsT {
   uint8_t* done_out;
   uint8_t* done_ws;
   int* seg_ws;
+  // observation normalisation: the networks see (o - obs_mean) * obs_inv_std (both [od]) or o
+  const T* obs_mean;
+  const T* obs_inv_std;
 };
 
 // Several models' windows in one launch (mixed-morphology batch): work-table slot s covers
@@ -141,6 +144,8 @@ struct ThetaArgsT {
   const T* W[SIM_MAXL];       // [out][in] caller weights
   const T* b[SIM_MAXL];
   const T* x0;                // [M][dims[0]] observations o_0 .. o_{h-1}
+  const T* x_shift;           // [dims[0]] or null: the first layer reads (x0 - x_shift) * x_scale
+  const T* x_scale;
   const T* act;               // [M][na] actions
   const T* da;                // [M][na] dL/da
   int mtu;                    // muscle task: actions u = (tanh(y) + 1) / 2, else a = tanh(y)
@@ -174,6 +179,8 @@ template <typename T>
 struct CriticFitT {
   ThetaArgsT<T> G;      // layer-gradient pass
   const T* obs;         // [rows][obs_dim]
+  const T* obs_mean;    // [obs_dim] or null: rows are gathered as (obs - obs_mean) * obs_inv_std
+  const T* obs_inv_std;
   const T* targets;     // [rows]
   const int* perm;      // [n_iter][rows]
   int rows, n_iter, n_mb;
@@ -208,6 +215,8 @@ SIM_DECLARE_LAUNCHERS(sim_f64, double)
   int launch_soft_update(T* t, const T* o, long n, T alpha, void* stream);                 \
   int launch_td_lambda(const T* r, const T* v, const uint8_t* d, int h, int N, T g, T l, T* out, void* s); \
   int launch_critic_values(const ThetaArgsT<T>& A, T* out, void* stream);                  \
+  int launch_obs_stats(const T* x, long rows, int od, double count, T* mean, T* var, T* inv_std, double eps,   \
+                       void* stream);                                                      \
   int launch_critic_fit(const CriticFitT<T>& F, void* stream);                             \
   }
 SIM_DECLARE_LEARN(sim_l32, float)

@@ -76,7 +76,13 @@ def test_null_arguments_rejected():
     assert L.sim_td_lambda(ctypes.c_void_p(16), ctypes.c_void_p(16), None, 4, 4, 1.5, 0.95, ctypes.c_void_p(16), 0,
                            None) == -1                                     # gamma outside [0, 1]
     assert L.sim_critic_workspace_bytes(None, 16) == 0
-    assert L.sim_critic_values(None, None, 1, None, None, None, None, 0, None) == -2
+    assert L.sim_critic_values(None, None, 1, None, None, None, None, None, None, 0, None) == -2
+    # running observation statistics: argument errors before any launch
+    v16 = ctypes.c_void_p(16)
+    assert L.sim_obs_stats_update(None, 4, 3, 0.0, v16, v16, v16, 1e-5, 0, None) == -1
+    assert L.sim_obs_stats_update(v16, 0, 3, 0.0, v16, v16, v16, 1e-5, 0, None) == -1       # no rows
+    assert L.sim_obs_stats_update(v16, 4, 3, -1.0, v16, v16, v16, 1e-5, 0, None) == -1      # negative count
+    assert L.sim_obs_stats_update(v16, 4, 3, 0.0, v16, v16, v16, 1e-5, 7, None) == -1       # precision
     assert L.sim_critic_fit(None, None, None) == -2
     # ceiling probes: argument errors before any launch
     d = ctypes.c_double()

@@ -3,7 +3,7 @@ special cases and finite differences."""
 import numpy as np
 import torch
 
-from oracle.learn import td_lambda, adam_step, critic_fit, critic_values
+from oracle.learn import td_lambda, adam_step, critic_fit, critic_values, obs_stats_update
 
 
 def test_td_lambda_special_cases():
@@ -100,3 +100,25 @@ def test_critic_fit_gradient_direction_and_descent():
     perm = [rng.permutation(rows) for _ in range(30)]
     _, _, _, losses = critic_fit(layers, obs, tgt, perm, 2, zeros, zeros, 0, 1e-2, 0.7, 0.95, 1e-8)
     assert np.mean(losses[-2:]) < 0.75 * np.mean(losses[:2])
+
+
+def test_obs_stats_streaming_equals_batch_moments():
+    """Running observation statistics (Sec. 3.3) merged over uneven chunks equal the mean and
+    population variance of all rows at once (numpy), and inv_std follows from them."""
+    rng = np.random.default_rng(9)
+    dim = 7
+    chunks = [rng.normal(loc=rng.normal(size=dim), scale=rng.uniform(0.2, 3.0, dim), size=(n, dim))
+              for n in (5, 1, 40, 13)]
+    count, mean, var = 0, None, None
+    for c in chunks:
+        count, mean, var, inv = obs_stats_update(c, count, mean, var, 1e-5)
+    allx = np.concatenate(chunks)
+    assert count == allx.shape[0]
+    np.testing.assert_allclose(mean.numpy(), allx.mean(0), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(var.numpy(), allx.var(0), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(inv.numpy(), 1.0 / np.sqrt(allx.var(0) + 1e-5), rtol=1e-12)
+    # a constant column has zero variance and inv_std 1 / sqrt(eps)
+    cnt, m1, v1, i1 = obs_stats_update(np.full((6, 2), 3.5), 0, None, None, 1e-4)
+    np.testing.assert_allclose(m1.numpy(), [3.5, 3.5], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(v1.numpy(), [0.0, 0.0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(i1.numpy(), [100.0, 100.0], rtol=1e-9)

@@ -885,3 +885,33 @@ def test_early_termination_restarts_window():
     C = oracle_window(md, W["s0"], h, W["actor"], W["critic"], reset_states=reset)
     D = oracle_window(W["model"], W["s0"], h, W["actor"], W["critic"])
     assert not C["done"].any() and float(C["loss"]) == float(D["loss"])
+
+
+def test_observation_normalisation_is_a_first_layer_fold():
+    """Observation normalisation (Sec. 3.3) in the oracle: reading (o - mu) * s through a first
+    layer (W, b) is the layer (W diag(s), b - W (mu * s)) on raw o, so the normalised window
+    equals the raw window with folded actor and critic (loss, dL/da, dL/ds0), and the actor's
+    first-layer gradients map back by dL/dW = dL/dW' diag(s) - dL/db' (mu * s)^T, dL/db = dL/db'."""
+    import workloads as wl
+    from oracle import oracle_window_grads
+    W = wl.workload("ant", 3)
+    od = W["obs_dim"]
+    rng = np.random.default_rng(4)
+    mu = rng.normal(0.0, 0.5, od)
+    sc = rng.uniform(0.3, 2.0, od)
+
+    def fold(layers):
+        (W0, b0), rest = layers[0], layers[1:]
+        return [(W0 * sc[None, :], b0 - W0 @ (mu * sc))] + list(rest)
+    h = 3
+    A = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], want_theta=True, obs_norm=(mu, sc))
+    B = oracle_window_grads(W["model"], W["s0"], h, fold(W["actor"]), fold(W["critic"]), want_theta=True)
+    assert abs(A["loss"] - B["loss"]) < 1e-12 * abs(B["loss"])
+    for key in ("actions", "rewards", "value", "dL_da", "dL_ds0", "obs"):
+        np.testing.assert_allclose(A[key], B[key], rtol=1e-9, atol=1e-12)
+    (gW, gb), (fW, fb) = A["dL_dtheta"][0], B["dL_dtheta"][0]
+    np.testing.assert_allclose(gb, fb, rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(gW, fW * sc[None, :] - np.outer(fb, mu * sc), rtol=1e-8, atol=1e-13)
+    for (a1, a2), (b1, b2) in zip(A["dL_dtheta"][1:], B["dL_dtheta"][1:]):
+        np.testing.assert_allclose(a1, b1, rtol=1e-9, atol=1e-14)
+        np.testing.assert_allclose(a2, b2, rtol=1e-9, atol=1e-14)
