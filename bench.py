@@ -323,8 +323,10 @@ def learning_episode(P, torch, sim, W, steps=3):
     actor, the target critic's values of the window's states, TD-lambda estimates, the critic
     fit (16 passes x 4 minibatches, Adam), the target-critic update, and the merge of the
     window's observations into the running statistics that normalise the networks' inputs
-    in the next episode.  The start states are the same every episode (a fixed benchmark
-    batch)."""
+    in the next episode.  Both learning rates decay linearly to zero over MAX_EPISODES
+    (App. A.2: actor 2e-3, critic 5e-4).  The start states are the same every episode (a
+    fixed benchmark batch)."""
+    MAX_EPISODES = 2000
     N, h, od = sim.N, sim.H, sim.od
     s0 = sim._dev(W["s0"])
     actor = [(a.clone(), b.clone()) for a, b in sim.weights(W["actor"])]
@@ -347,11 +349,12 @@ def learning_episode(P, torch, sim, W, steps=3):
         fw = sim.forward(s0, actor, target, obs_norm=(mean, inv))
         ad = sim.adjoint(fw, want_theta=True)
         e[1].record()
-        P.adam_step(flat(actor), ad["dL_dtheta_flat"], am, av, i + 1, 2e-3)
+        decay = max(1.0 - i / MAX_EPISODES, 0.0)
+        P.adam_step(flat(actor), ad["dL_dtheta_flat"], am, av, i + 1, 2e-3 * decay)
         vals = sim.critic_values(fw["obs"], target, workspace=ws, obs_norm=(mean, inv)).reshape(h + 1, N)
         tgt = P.td_lambda(fw["rewards"], vals, 0.99, 0.95).reshape(-1)
-        sim.critic_fit(fw["obs"][:h].reshape(-1, od), tgt, perm, 4, critic, cm, cv, i * 64, 5e-4, workspace=ws,
-                       obs_norm=(mean, inv))
+        sim.critic_fit(fw["obs"][:h].reshape(-1, od), tgt, perm, 4, critic, cm, cv, i * 64, 5e-4 * decay,
+                       workspace=ws, obs_norm=(mean, inv))
         P.soft_update(flat(target), flat(critic), 0.995)
         count[0] = P.obs_stats_update(fw["obs"][:h], count[0], mean, var, inv)
         e[2].record()

@@ -6,15 +6,16 @@
 // output adjoint with its input over all rows.
 //
 // Every contraction runs on the matrix cores: 64x64 output tiles staged through LDS in
-// K-slices of 16, four wavefronts per tile, each wavefront a 2x2 block of 16x16x4 MFMA
-// accumulators.  Row reductions (K = h*N) are split into fixed chunks whose partial tiles
+// K-slices of 32, four wavefronts per tile, each wavefront a 2x2 block of 16x16x4 MFMA
+// accumulators; the next slice is loaded into registers while the current one is
+// multiplied.  Row reductions (K = h*N) are split into fixed chunks whose partial tiles
 // are summed in a fixed order, so the gradient is bitwise reproducible.
 //
 // Included inside a namespace with `real` defined as float or double.
 
 #define GT_M 64
 #define GT_N 64
-#define GT_K 16
+#define GT_K 32
 #define GT_THREADS 256
 
 enum { EPI_STORE = 0, EPI_BIAS_ELU = 1, EPI_DELU = 2, EPI_BIAS = 3 };
@@ -59,6 +60,38 @@ struct GemmArgs {
   const real* b_scale;
 };
 
+// one K-slice of A and B into registers (zero outside the matrices and the split's chunk)
+#define GT_RA (GT_M * GT_K / GT_THREADS)
+#define GT_RB (GT_N * GT_K / GT_THREADS)
+__device__ __forceinline__ void gemm_load_slice(const GemmArgs& g, int tid, int m0, int n0, int k0, int ke, int bcols,
+                                                real (&ra)[GT_RA], real (&rb)[GT_RB]) {
+  const bool a_kfast = (g.sak == 1), b_kfast = (g.sbk == 1);
+#pragma unroll
+  for (int r = 0; r < GT_RA; ++r) {
+    const int e = tid + r * GT_THREADS;
+    const int m = m0 + (a_kfast ? e / GT_K : e % GT_M), k = k0 + (a_kfast ? e % GT_K : e / GT_M);
+    real v = RL(0.0);
+    if (m < g.M && k < ke) {
+      v = g.A[(long)m * g.sam + (long)k * g.sak];
+      if (g.a_shift) v = (v - g.a_shift[k]) * g.a_scale[k];
+    }
+    ra[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < GT_RB; ++r) {
+    const int e = tid + r * GT_THREADS;
+    const int n = n0 + (b_kfast ? e / GT_K : e % GT_N), k = k0 + (b_kfast ? e % GT_K : e / GT_N);
+    real v = RL(0.0);
+    if (k < ke) {
+      if (n < bcols) {
+        v = g.B[(long)k * g.sbk + (long)n * g.sbn];
+        if (g.b_shift) v = (v - g.b_shift[n]) * g.b_scale[n];
+      } else if (g.ones_col && n == g.N - 1) v = RL(1.0);
+    }
+    rb[r] = v;
+  }
+}
+
 __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
   __shared__ real As[GT_K][GT_M + 4];
   __shared__ real Bs[GT_K][GT_N + 4];
@@ -75,36 +108,22 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
     for (int j = 0; j < 2; ++j) acc[i][j] = mfma_v4{RL(0.0), RL(0.0), RL(0.0), RL(0.0)};
 
   const bool a_kfast = (g.sak == 1), b_kfast = (g.sbk == 1);
+  real ra[GT_RA], rb[GT_RB];
+  if (kb < ke) gemm_load_slice(g, tid, m0, n0, kb, ke, bcols, ra, rb);
   for (int k0 = kb; k0 < ke; k0 += GT_K) {
 #pragma unroll
-    for (int r = 0; r < GT_M * GT_K / GT_THREADS; ++r) {
+    for (int r = 0; r < GT_RA; ++r) {
       const int e = tid + r * GT_THREADS;
-      const int mm = a_kfast ? e / GT_K : e % GT_M;
-      const int kk = a_kfast ? e % GT_K : e / GT_M;
-      const int m = m0 + mm, k = k0 + kk;
-      real v = RL(0.0);
-      if (m < g.M && k < ke) {
-        v = g.A[(long)m * g.sam + (long)k * g.sak];
-        if (g.a_shift) v = (v - g.a_shift[k]) * g.a_scale[k];
-      }
-      As[kk][mm] = v;
+      As[a_kfast ? e % GT_K : e / GT_M][a_kfast ? e / GT_K : e % GT_M] = ra[r];
     }
 #pragma unroll
-    for (int r = 0; r < GT_N * GT_K / GT_THREADS; ++r) {
+    for (int r = 0; r < GT_RB; ++r) {
       const int e = tid + r * GT_THREADS;
-      const int nn = b_kfast ? e / GT_K : e % GT_N;
-      const int kk = b_kfast ? e % GT_K : e / GT_N;
-      const int n = n0 + nn, k = k0 + kk;
-      real v = RL(0.0);
-      if (k < ke) {
-        if (n < bcols) {
-          v = g.B[(long)k * g.sbk + (long)n * g.sbn];
-          if (g.b_shift) v = (v - g.b_shift[n]) * g.b_scale[n];
-        } else if (g.ones_col && n == g.N - 1) v = RL(1.0);
-      }
-      Bs[kk][nn] = v;
+      Bs[b_kfast ? e % GT_K : e / GT_N][b_kfast ? e / GT_K : e % GT_N] = rb[r];
     }
     __syncthreads();
+    // the next slice's loads are in flight while this one is multiplied
+    if (k0 + GT_K < ke) gemm_load_slice(g, tid, m0, n0, k0 + GT_K, ke, bcols, ra, rb);
 #pragma unroll
     for (int k4 = 0; k4 < GT_K; k4 += 4) {
       const int kr = k4 + (lane >> 4);

@@ -8,17 +8,24 @@
 // sim_gemm.h.
 
 // Adam (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
-// p -= lr (m / bc1) / (sqrt(v / bc2) + eps) with bc = 1 - b^t
-__global__ void k_adam(real* __restrict__ p, const real* __restrict__ g, real* __restrict__ mm,
-                       real* __restrict__ vv, long n, real lr, real b1, real b2, real eps, real bc1, real bc2) {
+// p -= lr (m / bc1) / (sqrt(v / bc2) + eps) with bc = 1 - b^t, over every tensor of a list in
+// one launch: the gradient and moments are flat with the tensors in list order, and element i
+// belongs to the tensor whose range holds it
+__global__ void k_adam_multi(LearnAdamT<real> A, long total) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const real gi = g[i];
-  const real m = b1 * mm[i] + (RL(1.0) - b1) * gi;
-  const real v = b2 * vv[i] + (RL(1.0) - b2) * gi * gi;
-  mm[i] = m;
-  vv[i] = v;
-  p[i] -= lr * (m / bc1) / (m_sqrt(v / bc2) + eps);
+  if (i >= total) return;
+  int t = 0;
+  long base = 0;
+  while (t + 1 < A.n && i >= base + A.size[t]) {
+    base += A.size[t];
+    ++t;
+  }
+  const real gi = A.g[i];
+  const real m = A.b1 * A.m[i] + (RL(1.0) - A.b1) * gi;
+  const real v = A.b2 * A.v[i] + (RL(1.0) - A.b2) * gi * gi;
+  A.m[i] = m;
+  A.v[i] = v;
+  A.p[t][i - base] -= A.lr * (m / A.bc1) / (m_sqrt(v / A.bc2) + A.eps);
 }
 
 // target <- alpha target + (1 - alpha) online
@@ -68,9 +75,26 @@ __global__ void k_gather_rows(const real* __restrict__ obs, const real* __restri
 // M2_b, delta = m_b - mean, n = count + rows,
 //   mean' = mean + delta rows / n,   var' = (var count + M2_b + delta^2 count rows / n) / n,
 // and inv_std = 1 / sqrt(var' + eps).  A block owns 64 columns; its 16 row groups read
-// consecutive columns of a row (coalesced) and are summed in a fixed order, in FP64.
+// consecutive columns of a row (coalesced) and are summed in a fixed order, in FP64.  Each
+// thread keeps eight independent partial sums so that eight loads are in flight at once.
 #define OS_COLS 64
 #define OS_GROUPS 16
+#define OS_UNROLL 8
+
+// sum over rows r = grp, grp + OS_GROUPS, ... of f(x[r][c]), in a fixed order
+template <class F>
+__device__ __forceinline__ double os_column_sum(const real* __restrict__ x, long rows, int od, int c, int grp, F f) {
+  double p[OS_UNROLL];
+#pragma unroll
+  for (int u = 0; u < OS_UNROLL; ++u) p[u] = 0.0;
+  long r = grp;
+  for (; r + (long)(OS_UNROLL - 1) * OS_GROUPS < rows; r += (long)OS_UNROLL * OS_GROUPS) {
+#pragma unroll
+    for (int u = 0; u < OS_UNROLL; ++u) p[u] += f((double)x[(r + (long)u * OS_GROUPS) * od + c]);
+  }
+  for (; r < rows; r += OS_GROUPS) p[0] += f((double)x[r * od + c]);
+  return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
 __global__ __launch_bounds__(OS_COLS * OS_GROUPS) void k_obs_stats(const real* __restrict__ x, long rows, int od,
                                                                     double count, real* __restrict__ mean,
                                                                     real* __restrict__ var, real* __restrict__ inv_std,
@@ -81,8 +105,7 @@ __global__ __launch_bounds__(OS_COLS * OS_GROUPS) void k_obs_stats(const real* _
   const int c = blockIdx.x * OS_COLS + cl;
   const bool ok = c < od;
   double s = 0.0;
-  if (ok)
-    for (long r = grp; r < rows; r += OS_GROUPS) s += (double)x[r * od + c];
+  if (ok) s = os_column_sum(x, rows, od, c, grp, [](double v) { return v; });
   red[grp][cl] = s;
   __syncthreads();
   if (grp == 0) {
@@ -93,11 +116,7 @@ __global__ __launch_bounds__(OS_COLS * OS_GROUPS) void k_obs_stats(const real* _
   __syncthreads();
   const double bm = bmean[cl];
   double q = 0.0;
-  if (ok)
-    for (long r = grp; r < rows; r += OS_GROUPS) {
-      const double d = (double)x[r * od + c] - bm;
-      q += d * d;
-    }
+  if (ok) q = os_column_sum(x, rows, od, c, grp, [bm](double v) { const double d = v - bm; return d * d; });
   red[grp][cl] = q;
   __syncthreads();
   if (grp == 0 && ok) {
@@ -139,19 +158,14 @@ __global__ __launch_bounds__(256) void k_mse_loss(const real* __restrict__ V, co
   if (threadIdx.x == 0) *out = part[0] / (real)B;
 }
 
-static void launch_adam_tensor(real* p, const real* g, real* m, real* v, long n, real lr, real b1, real b2, real eps,
-                               real bc1, real bc2, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, bc1,
-                     bc2);
+static void launch_adam_multi(const LearnAdamT<real>& A, hipStream_t s) {
+  long total = 0;
+  for (int i = 0; i < A.n; ++i) total += A.size[i];
+  hipLaunchKernelGGL(k_adam_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, total);
 }
 
 int launch_adam(const LearnAdamT<real>& A, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
-  long off = 0;
-  for (int i = 0; i < A.n; ++i) {
-    launch_adam_tensor(A.p[i], A.g + off, A.m + off, A.v + off, A.size[i], A.lr, A.b1, A.b2, A.eps, A.bc1, A.bc2, s);
-    off += A.size[i];
-  }
+  launch_adam_multi(A, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -207,13 +221,18 @@ int launch_critic_fit(const CriticFitT<real>& F, void* stream) {
       ++step;
       const real bc1 = RL(1.0) - (real)pow((double)F.b1, (double)step);
       const real bc2 = RL(1.0) - (real)pow((double)F.b2, (double)step);
+      // one Adam launch over all layers (the flat gradient holds W_0, b_0, W_1, ... in order)
+      LearnAdamT<real> A = {};
+      A.n = 2 * T.nl;
       for (int l = 0; l < T.nl; ++l) {
-        const long nw = (long)T.dims[l] * T.dims[l + 1];
-        launch_adam_tensor(F.W[l], T.out + T.off_w[l], F.m + T.off_w[l], F.v + T.off_w[l], nw, F.lr, F.b1, F.b2,
-                           F.eps, bc1, bc2, s);
-        launch_adam_tensor(F.bvec[l], T.out + T.off_b[l], F.m + T.off_b[l], F.v + T.off_b[l], T.dims[l + 1], F.lr,
-                           F.b1, F.b2, F.eps, bc1, bc2, s);
+        A.p[2 * l] = F.W[l];
+        A.size[2 * l] = (long)T.dims[l] * T.dims[l + 1];
+        A.p[2 * l + 1] = F.bvec[l];
+        A.size[2 * l + 1] = T.dims[l + 1];
       }
+      A.g = T.out; A.m = F.m; A.v = F.v;
+      A.lr = F.lr; A.b1 = F.b1; A.b2 = F.b2; A.eps = F.eps; A.bc1 = bc1; A.bc2 = bc2;
+      launch_adam_multi(A, s);
     }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
