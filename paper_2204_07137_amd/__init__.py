@@ -653,7 +653,28 @@ def probe_ceilings(copy_bytes=1 << 30):
     return {"fp32_valu_tflops": tf.value, "copy_gbs": gb.value, "copy_bytes": copy_bytes}
 
 
-def window_function():
+def window_loss(fw, gamma):
+    """The short-horizon actor loss (Sec. 3.3) of a forward result: -1/(N h) sum over envs
+    of sum_t gamma^(t - t0) r_t + gamma^(h - t0) V(o_h), with t0 the first frame of the
+    env's discount segment (0 without early termination; a segment that ends in termination
+    has no terminal value)."""
+    import torch
+    rew, value = fw["rewards"], fw["value"]
+    H, N = rew.shape
+    if "done" not in fw:
+        disc = torch.stack([gamma ** t * rew[t] for t in range(H)]).sum(0)
+        return -(disc + gamma ** H * value).sum() / (N * H)
+    done = fw["done"].bool()
+    t0 = torch.zeros(N, dtype=rew.dtype, device=rew.device)
+    disc = torch.zeros(N, dtype=rew.dtype, device=rew.device)
+    for t in range(H):
+        disc = disc + torch.pow(torch.full_like(t0, gamma), t - t0) * rew[t]
+        t0 = torch.where(done[t], torch.full_like(t0, t + 1), t0)
+    live = (~done[H - 1]).to(rew.dtype)
+    return -(disc + live * torch.pow(torch.full_like(t0, gamma), H - t0) * value).sum() / (N * H)
+
+
+def window_function(noise=None, reset_states=None, obs_norm=None):
     """torch.autograd.Function over one window: forward -> sim_forward_window, backward ->
     sim_adjoint_window.
 
@@ -661,21 +682,27 @@ def window_function():
     flat sequence W_0, b_0, W_1, b_1, ... returns (loss, s_h, obs, actions, rewards,
     value).  Gradients flow to s0 (total, through the closed-loop policy), to actions_in
     in open loop, and to the actor parameters when the handle was created with
-    policy_grad=True.  The loss is the short-horizon actor loss; a gradient arriving on
-    s_h is propagated through the window as well."""
+    policy_grad=True.  The loss is the short-horizon actor loss (window_loss); a gradient
+    arriving on s_h is propagated through the window as well.
+
+    The returned class is bound to the optional inputs given here: noise [h, N, na] selects
+    the stochastic policy, whose log_std [na] is then the LAST element of actor_params (and
+    receives dL/dlog_std); reset_states [N, ns] enables early termination (the handle's
+    model has a termination height); obs_norm = (mean, inv_std) normalises the networks'
+    inputs."""
     import torch
 
     class ShacWindow(torch.autograd.Function):
         @staticmethod
         def forward(ctx, sim, s0, actions_in, critic, *actor_params):
-            actor = ([(actor_params[2 * i].detach(), actor_params[2 * i + 1].detach())
-                      for i in range(len(actor_params) // 2)] if actor_params else None)
+            params = list(actor_params)
+            log_std = params.pop().detach() if noise is not None else None
+            actor = ([(params[2 * i].detach(), params[2 * i + 1].detach())
+                      for i in range(len(params) // 2)] if params else None)
             fw = sim.forward(s0.detach(), actor, critic,
-                             actions_in.detach() if actions_in is not None else None)
-            g = sim.opt.gamma
-            H, N = sim.H, sim.N
-            disc = torch.stack([g ** t * fw["rewards"][t] for t in range(H)]).sum(0)
-            loss = -(disc + g ** H * fw["value"]).sum() / (N * H)
+                             actions_in.detach() if actions_in is not None else None, noise=noise,
+                             log_std=log_std, reset_states=reset_states, obs_norm=obs_norm)
+            loss = window_loss(fw, sim.opt.gamma)
             ctx.sim, ctx.fw, ctx.open_loop = sim, fw, actions_in is not None
             ctx.n_actor = len(actor_params)
             ctx.mark_non_differentiable(fw["obs"], fw["actions"], fw["rewards"], fw["value"])
@@ -692,6 +719,8 @@ def window_function():
             gth = [None] * ctx.n_actor
             if want:
                 gth = [x for pair in ad["dL_dtheta"] for x in pair]
+                if noise is not None:
+                    gth.append(ad["dL_dlog_std"])
             return (None, gs0, ga, None, *gth)
 
     return ShacWindow

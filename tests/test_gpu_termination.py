@@ -140,3 +140,34 @@ def test_group_with_a_terminating_member_matches_members():
         b = {k: v.double().cpu().numpy() for k, v in ga[i].items() if torch.is_tensor(v)}
         for key in ("dL_da", "dL_ds0"):
             assert np.array_equal(solo_a[i][key], b[key]), (i, key)
+
+
+def test_autograd_window_with_termination_noise_and_normalisation():
+    """torch.autograd.Function over an FP64 Ant window that combines early termination, the
+    stochastic policy and observation normalisation: the loss (with the segment discounts)
+    and the gradients to s0, the actor parameters and log_std match the oracle."""
+    N, h = 8, 5
+    W, md, s0, reset = _case("ant", N, 0.2)
+    od, na = W["obs_dim"], W["model"]["na"]
+    rng = np.random.default_rng(21)
+    noise = rng.standard_normal((h, N, na))
+    log_std = rng.uniform(-1.5, -0.5, na)
+    mu, sc = rng.normal(0.0, 0.5, od), rng.uniform(0.3, 2.0, od)
+    sim = P.Sim(md, N, h, [od] + [w.shape[0] for w, _ in W["actor"]], [od] + [w.shape[0] for w, _ in W["critic"]],
+                ckpt_interval=4, precision="fp64", policy_grad=True)
+    dev = lambda x: torch.as_tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+    Fn = P.window_function(noise=dev(noise), reset_states=dev(reset), obs_norm=(dev(mu), dev(sc)))
+    s0_t = dev(s0).requires_grad_(True)
+    params = [dev(x).requires_grad_(True) for pair in W["actor"] for x in pair] + [dev(log_std).requires_grad_(True)]
+    print("[term autograd] ant fp64 termination + noise + obs_norm", flush=True)
+    loss, *_ = Fn.apply(sim, s0_t, None, W["critic"], *params)
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = oracle_window_grads(md, s0, h, W["actor"], W["critic"], want_theta=True, noise=noise, log_std=log_std,
+                              reset_states=reset, obs_norm=(mu, sc))
+    assert ref["done"].any()
+    assert abs(float(loss.detach()) - ref["loss"]) < 1e-10 * abs(ref["loss"])
+    assert relnorm(s0_t.grad.cpu().numpy(), ref["dL_ds0"]) < 1e-9
+    got = np.concatenate([p.grad.cpu().numpy().ravel() for p in params])
+    want = np.concatenate([x.ravel() for pair in ref["dL_dtheta"] for x in pair] + [ref["dL_dlog_std"]])
+    assert relnorm(got, want) < 1e-9
