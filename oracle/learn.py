@@ -103,7 +103,7 @@ def critic_fit(layers, obs, targets, perm, n_minibatch, m, v, adam_step0, lr, be
             V = mlp_forward([(ps[2 * i], ps[2 * i + 1]) for i in range(len(ps) // 2)], obs[idx])[:, 0]
             loss = ((V - targets[idx]) ** 2).mean()
             grads = torch.autograd.grad(loss, ps)
-            losses.append(float(loss))
+            losses.append(float(loss.detach()))
             step += 1
             params, m, v = adam_step(params, grads, m, v, step, lr, beta1, beta2, eps)
     return [(params[2 * i], params[2 * i + 1]) for i in range(len(params) // 2)], m, v, losses

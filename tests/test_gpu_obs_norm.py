@@ -152,3 +152,27 @@ def test_normalised_critic_values_and_fit_match_oracle(precision, tol):
     init_w = np.concatenate([x.ravel() for pair in W["critic"] for x in pair])
     assert relnorm(losses.double().cpu().numpy(), ref_losses) < (1e-9 if precision == "fp64" else 1e-4)
     assert relnorm(got_w - init_w, want_w - init_w) < (1e-8 if precision == "fp64" else 2e-2)
+
+
+def _cos(x, y):
+    x, y = np.asarray(x, np.float64).ravel(), np.asarray(y, np.float64).ravel()
+    return float(x @ y / (np.linalg.norm(x) * np.linalg.norm(y)))
+
+
+@pytest.mark.parametrize("name,N,h,k", [("mtu", 2, 2, 16), ("ant", 8, 4, 16)])
+def test_normalised_bf16_mlps_match_oracle_bf16_emulation(name, N, h, k):
+    """Normalised inputs into the BF16 matrix-core MLPs: the input is normalised in FP32 and
+    then rounded to BF16, as the oracle's BF16 emulation normalises and then rounds; the bar
+    is that of the unnormalised BF16 test (states 1e-4, gradient cosine 0.999, relative norm
+    1e-3)."""
+    W = wl.workload(name, N)
+    stats = _stats(W["obs_dim"], seed=10)
+    print(f"[obs-norm bf16] {name} N={N} h={h}", flush=True)
+    sim = _sim(W, N, h, ckpt_interval=k, mlp_precision="bf16")
+    f, a = _run(sim, W, stats, want_theta=False)
+    ref = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], n_total=N, bf16=True, obs_norm=stats)
+    assert float((np.abs(f["s_h"] - ref["s_h"]).max(1) / np.abs(ref["s_h"]).max(1)).max()) < 1e-4
+    assert relnorm(f["actions"], ref["actions"]) < 1e-4
+    assert relnorm(f["value"], ref["value"]) < 1e-4
+    for got, want in ((a["dL_da"], ref["dL_da"]), (a["dL_ds0"], ref["dL_ds0"])):
+        assert _cos(got, want) >= 0.999 and relnorm(got, want) <= 1e-3
