@@ -442,6 +442,11 @@ def main():
             "avg_ms": {"k_window_adj": round(float(np.mean(adj_ms)), 3),
                        "k_window_fwd": round(float(np.mean(fwd_ms)), 3)}}
 
+    n_eval = N * h * S * len(md["contact_body"])
+    contacts = {"adhesive_frac": round(float(fw["adhesive_count"].double().sum()) / n_eval, 6),
+                "evaluations": n_eval,
+                "what": "contact evaluations (envs x frames x substeps x contacts) whose literal "
+                        "normal force pulls (d < 0, d_dot > k_n / k_d)"}
     out = {"metric": METRIC, "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -450,7 +455,7 @@ def main():
                                   f"S={S} substeps, checkpoint k={args.k}, actor 76-256-128-21, "
                                   f"critic 76-128-128-1", "envs": N, "h": h, "substeps": S,
                       "ckpt_interval": args.k, "path": "persistent"},
-           "roofline": roof}
+           "roofline": roof, "contacts": contacts}
 
     if not args.no_theta:
         # policy-parameter gradient pass: adjoint with and without it, the difference

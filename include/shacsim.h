@@ -203,6 +203,10 @@ typedef struct SimForwardIO {
    * sim_obs_stats_update); both NULL = raw observations.  The obs output stays raw. */
   const void* obs_mean;
   const void* obs_inv_std;
+  /* [N] out, optional: per env, the contact evaluations of the window (substeps x contacts)
+   * that penetrate (d < 0) with a pulling normal force, i.e. where the literal damping term
+   * of the contact model (Sec. 3.1) exceeds the stiffness term (d_dot > k_n / k_d). */
+  int32_t* adhesive_count;
 } SimForwardIO;
 
 typedef struct SimAdjointIO {

@@ -101,7 +101,7 @@ def count_window(md, s0, h, actor, critic):
     s0t = torch.as_tensor(s0, dtype=torch.float64).clone().requires_grad_(True)
     cf = OpCounter()
     with cf:
-        out = oracle_window(md, s0t, h, actor, critic, keep_graph=True)
+        out = oracle_window(md, s0t, h, actor, critic, keep_graph=True, diagnostics=False)
     cr = OpCounter()
     with cr:
         torch.autograd.grad(out["loss"], [s0t] + list(out["actions"]))

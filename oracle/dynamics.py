@@ -334,10 +334,14 @@ def integrate(m, q, qd_new, dt):
     return torch.cat(parts, 1)
 
 
-def substep(m, q, qd, a, dt, act=None):
+def substep(m, q, qd, a, dt, act=None, stats=None):
     """One semi-implicit Euler substep of M qdd = J^T f + c + tau (Sec. 3.1).  Muscle
-    models also take the activations ``act`` and return the updated ones."""
+    models also take the activations ``act`` and return the updated ones.  ``stats``, a
+    list, receives per env the number of contacts that penetrate with a pulling normal
+    force (the literal damping term exceeding the stiffness term)."""
     T = dynamics_terms(m, q, qd)
+    if stats is not None and "contact_d" in T:
+        stats.append(((T["contact_d"] < 0.0) & (T["contact_f"][..., 2] < 0.0)).sum(1))
     tau = joint_torques(m, q, a) + T["tau_contact"] - T["bias"]
     if m.n_mtu:
         tau = tau + muscle_terms(m, T, qd, act)["tau"]

@@ -147,7 +147,7 @@ def normalize_obs(o, obs_norm):
 
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
                   keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None,
-                  reset_states=None, obs_norm=None):
+                  reset_states=None, obs_norm=None, diagnostics=True):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
@@ -163,6 +163,8 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     termination has no terminal value.
     obs_norm = (mean, inv_std) [od]: actor and critic read normalised observations; the
     returned obs stay raw.
+    diagnostics: also count, per env, the contact evaluations whose normal force pulls
+    ("adhesive"); off when only the method's own arithmetic should run.
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
     s = s0 if torch.is_tensor(s0) else _t(s0)
@@ -179,6 +181,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     term_h = m.md.get("term_height") if reset_states is not None else None
     t0 = torch.zeros(B, dtype=torch.long)
     segs, dones = [], []
+    adh = [] if diagnostics else None
     for t in range(h):
         o = obs_fn(m, s)
         if actions is None:
@@ -198,11 +201,11 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         if m.n_mtu:
             act = s[:, nq + nv:nq + nv + m.n_mtu]
             for _ in range(m.substeps):
-                q, qd, act = substep(m, q, qd, a, dt, act)
+                q, qd, act = substep(m, q, qd, a, dt, act, stats=adh)
             s = torch.cat([q, qd, act], 1)
         else:
             for _ in range(m.substeps):
-                q, qd = substep(m, q, qd, a, dt)
+                q, qd = substep(m, q, qd, a, dt, stats=adh)
             s = torch.cat([q, qd, a], 1) if m.md["has_last_action"] else torch.cat([q, qd], 1)
         if term_h is not None:
             done = s[:, 2] < term_h
@@ -226,8 +229,9 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         live = (~dones[-1]).to(F64)
         loss = -(disc + live * torch.pow(gamma, (h - t0).to(F64)) * value).sum() / (N * h)
         done_out = torch.stack(dones)
+    adhesive = torch.stack(adh).sum(0) if adh else torch.zeros(B, dtype=torch.long)
     return dict(states=states, obs=obs, actions=acts, rewards=rews, value=value, loss=loss,
-                layers=layers, done=done_out)
+                layers=layers, done=done_out, adhesive=adhesive)
 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
@@ -276,6 +280,7 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
         dL_da=ga.detach().numpy(),
         dL_ds0=gs0.detach().numpy(),
     )
+    res["adhesive"] = out["adhesive"].numpy()
     if out["done"] is not None:
         res["done"] = out["done"].numpy()
     if want_theta and actor is not None:

@@ -51,7 +51,7 @@ class SimForwardIO(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
                 ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p),
                 ("noise", _p), ("log_std", _p), ("reset_states", _p), ("done", _p),
-                ("obs_mean", _p), ("obs_inv_std", _p)]
+                ("obs_mean", _p), ("obs_inv_std", _p), ("adhesive_count", _p)]
 
 
 class SimAdjointIO(ctypes.Structure):
@@ -365,7 +365,7 @@ class Sim:
         s0 = self._dev(s0)
         assert s0.shape == (N, self.ns), (s0.shape, (N, self.ns))
         dt = self.dtype
-        keys = ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count")
+        keys = ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count")
         prev_done = None
         if out is not None:
             prev_done = out.get("done")
@@ -381,6 +381,7 @@ class Sim:
                 value=t.empty(N, device="cuda", dtype=dt),
                 nonfinite=t.zeros(N, dtype=t.uint8, device="cuda"),
                 fp64_refactor_count=t.zeros(N, dtype=t.int32, device="cuda"),
+                adhesive_count=t.zeros(N, dtype=t.int32, device="cuda"),
             )
         io = SimForwardIO()
         io.s0 = self._ptr(s0)
@@ -407,7 +408,7 @@ class Sim:
         self._set_weights(io, actor, critic, out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
-        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count"):
+        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count"):
             setattr(io, k, self._ptr(out[k]))
         out["_io"] = io
         return out, io

@@ -518,6 +518,7 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.rewards = static_cast<T*>(io->rewards); A.value = static_cast<T*>(io->value);
   A.nonfinite = io->nonfinite;
   A.fallback = io->fp64_refactor_count;
+  A.adhesive = io->adhesive_count;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);

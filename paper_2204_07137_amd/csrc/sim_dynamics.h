@@ -92,6 +92,7 @@ struct EnvLDST {
   real arm[SIM_MAXV];
   real j_off[SIM_MAXJ][3], j_ax[SIM_MAXJ][3], j_com[SIM_MAXJ][3], j_I6[SIM_MAXJ][6];
   int pairs[SIM_MAXPAIR];
+  int nadh;   // contacts of the last substep whose normal force pulled (see the contact phase)
   // policy / critic
   real obs[SIM_MAXOBS];
   union {
@@ -731,6 +732,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   }
   wsync();
   // ---- contacts (lane = contact)
+  bool adh = false;
   if (ln < nc) {
     int b = cr.body;
     f3 xc = add3(ld3(E.p[b]), mv3(E.R[b], cr.pos));
@@ -744,6 +746,12 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     st3(E.cx[ln], xp);
     st3(E.cvel[ln], vpt);
     E.cdep[ln] = d;
+    // the literal damping term makes a penetrating contact pull when d_dot > k_n / k_d
+    adh = (d < RL(0.0)) && (f.z < RL(0.0));
+  }
+  {
+    const unsigned long long bal = __ballot(adh);
+    if (ln == 0) E.nadh = __popcll(bal);
   }
   wsync();
   if constexpr (L::kMtu > 0) muscle_wrenches(m, E, ln);

@@ -123,7 +123,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
   const int S = m->substeps, nqv = m->nck, N = A.N;
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
   Chol C;
-  int nfb = 0;
+  int nfb = 0, nadh = 0;
   int t0 = 0;   // first frame of the current discount segment (early termination)
   for (int t = 0; t < A.h; ++t) {
     frame_begin(A, m, E, env, t, ln);
@@ -140,6 +140,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
         substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
       }
       nfb += fb;
+      nadh += E.nadh;
     }
     if (m->term) {
       // early termination: the frame ended with the root below the height; the env restarts
@@ -159,6 +160,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
   if (m->term && ln == 0) A.seg_ws[(size_t)A.h * N + env] = t0;
   window_end(A, m, E, env, ln);
   if (ln == 0 && A.fallback) A.fallback[env] = nfb;
+  if (ln == 0 && A.adhesive) A.adhesive[env] = nadh;
 }
 
 // ======================================================================= persistent adjoint
@@ -411,6 +413,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_frame(WinArgs A, int t) {
     load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
     store_qqd(m, E, A.ckpt + (size_t)env * nqv, ln);
     if (ln == 0 && A.fallback) A.fallback[env] = 0;
+    if (ln == 0 && A.adhesive) A.adhesive[env] = 0;
   } else {
     load_qqd(m, E, A.ckpt + ((size_t)(t * S) * N + env) * nqv, ln);
     const real* ap = A.actions + ((size_t)(t - 1) * N + env) * na;
@@ -440,6 +443,7 @@ __global__ __launch_bounds__(SIM_WAVE) void k_plain_substep(WinArgs A, int t, in
   substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
   store_qqd(m, E, A.ckpt + ((size_t)(gi + 1) * N + env) * nqv, ln);
   if (ln == 0 && A.fallback) A.fallback[env] += fb;
+  if (ln == 0 && A.adhesive) A.adhesive[env] += E.nadh;
 }
 
 __global__ __launch_bounds__(SIM_WAVE) void k_plain_end(WinArgs A) {

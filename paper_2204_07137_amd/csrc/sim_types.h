@@ -99,6 +99,7 @@ struct WinArgsT {
   T* value;
   uint8_t* nonfinite;
   int* fallback;    // [N] substeps whose factorisation fell back to FP64 (optional)
+  int* adhesive;    // [N] contact evaluations (substep x contact) with a pulling normal force (optional)
   T* ckpt;          // [n_ckpt][N][nq+nv] (persistent and plain paths)
   T* adj;           // [N][nq+nv+na] adjoint carried between plain launches
   T* tape;          // tape_full: [h*S][N] tape entries written by the forward; else the

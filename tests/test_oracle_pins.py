@@ -915,3 +915,26 @@ def test_observation_normalisation_is_a_first_layer_fold():
     for (a1, a2), (b1, b2) in zip(A["dL_dtheta"][1:], B["dL_dtheta"][1:]):
         np.testing.assert_allclose(a1, b1, rtol=1e-9, atol=1e-14)
         np.testing.assert_allclose(a2, b2, rtol=1e-9, atol=1e-14)
+
+
+def test_adhesive_contact_count_threshold():
+    """The literal normal force (-k_n + k_d d_dot) min(d, 0) of Sec. 3.1 pulls exactly when a
+    penetrating contact separates faster than k_n / k_d: an Ant lowered 5 cm (its 4 foot
+    spheres penetrate), moving straight up at k_n / k_d +- 0.5 m/s, counts all penetrating
+    contacts or none as pulling in its first substep."""
+    import workloads as wl
+    from oracle import OracleModel, substep, dynamics_terms
+    W = wl.workload("ant", 1)
+    m = OracleModel(W["model"])
+    s0 = torch.as_tensor(W["s0"], dtype=torch.float64)
+    q, qd = s0[:, :m.nq].clone(), torch.zeros(1, m.nv, dtype=torch.float64)
+    q[:, 2] -= 0.05
+    a = torch.zeros(1, m.na, dtype=torch.float64)
+    vcrit = m.kn / m.kd
+    npen = int((dynamics_terms(m, q, qd)["contact_d"] < 0.0).sum())
+    assert npen == 4
+    for vz, want in ((vcrit + 0.5, npen), (vcrit - 0.5, 0), (-1.0, 0)):
+        qd[:, 2] = vz
+        stats = []
+        substep(m, q, qd, a, m.dt / m.substeps, stats=stats)
+        assert int(stats[0][0]) == want, (vz, int(stats[0][0]))
