@@ -455,7 +455,12 @@ def main():
                                   f"S={S} substeps, checkpoint k={args.k}, actor 76-256-128-21, "
                                   f"critic 76-128-128-1", "envs": N, "h": h, "substeps": S,
                       "ckpt_interval": args.k, "path": "persistent"},
-           "roofline": roof, "contacts": contacts}
+           "roofline": roof, "contacts": contacts,
+           # the paper's own figures (App. A.4, wall-clock breakdown of a training episode),
+           # context only: another GPU, 64 envs, and its backward includes the actor update
+           "paper_context": {"humanoid_env_steps_per_s": 711, "muscle_humanoid_env_steps_per_s": 826,
+                             "derived_as": "64 envs x 32 steps / (forward + backward seconds)",
+                             "hardware": "NVIDIA TITAN X, Intel Xeon E5-2620", "precision": "not stated"}}
 
     if not args.no_theta:
         # policy-parameter gradient pass: adjoint with and without it, the difference
