@@ -375,6 +375,38 @@ def learning_episode(P, torch, sim, W, steps=3):
             "env_steps_per_s": round(N * h / wall, 1), "window_ms": round(win, 3), "update_ms": round(upd, 3)}
 
 
+def fd_directions(sim64, W, ad64, h, n_dirs=8):
+    """Central differences of the full FP64 window loss along one random direction per
+    sampled env (8 envs, indices from seed 4; positions and velocities, root quaternion
+    fixed) against the adjoint's directional derivative, at eps 1e-3 and 1e-6: reported,
+    not gated (the contact-rich h = 32 window is far from linear on these scales)."""
+    import torch
+    md, N = W["model"], sim64.N
+    g = sim64.opt.gamma
+    rng = np.random.default_rng(4)
+    envs = np.sort(rng.choice(N, n_dirs, replace=False))
+    ns = W["s0"].shape[1]
+    U = np.zeros((N, ns))
+    for e in envs:
+        u = rng.standard_normal(ns)
+        u[3:7] = 0.0
+        u[md["nq"] + md["nv"]:] = 0.0
+        U[e] = u / np.linalg.norm(u)
+    want = (ad64["dL_ds0"].cpu().numpy() * U).sum(1)[envs]
+
+    def env_losses(s0):
+        f = sim64.forward(s0, W["actor"], W["critic"])
+        torch.cuda.synchronize()
+        r, v = f["rewards"].cpu().numpy(), f["value"].cpu().numpy()
+        return -(sum(g ** t * r[t] for t in range(h)) + g ** h * v) / (N * h)
+    res = {"envs": [int(e) for e in envs], "h": h}
+    for eps in (1e-3, 1e-6):
+        fd = ((env_losses(W["s0"] + eps * U) - env_losses(W["s0"] - eps * U)) / (2 * eps))[envs]
+        rel = np.abs(fd - want) / np.maximum(np.abs(want), 1e-300)
+        res[f"eps_{eps:g}"] = {"median_rel_err": float(np.median(rel)), "max_rel_err": float(rel.max())}
+    return res
+
+
 def cpu_baseline(W, h, n_envs_sample=2):
     """The FP64 oracle (CPU, PyTorch) on a bounded sample of the same workload."""
     import torch
@@ -584,6 +616,7 @@ def main():
                                          "dL_ds0": grad_err(adp["dL_ds0"], ad64["dL_ds0"], 0),
                                          "s_h_relmax": float(((fwp["s_h"] - fw64["s_h"]).abs().max()
                                                               / fw64["s_h"].abs().max()))}
+        out["fd_directions"] = fd_directions(sim64, W, ad64, h)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, h)
     print(json.dumps(out), flush=True)

@@ -357,3 +357,43 @@ def test_long_window_fp64_matches_oracle():
     assert relnorm(f["s_h"], ref["s_h"]) < 1e-10
     assert relnorm(a["dL_da"], ref["dL_da"]) < 1e-9
     assert relnorm(a["dL_ds0"], ref["dL_ds0"]) < 1e-9
+
+
+def test_humanoid_adjoint_matches_central_differences_of_the_gpu_forward():
+    """The GPU adjoint against central differences of the GPU forward itself (FP64 kernels),
+    at the humanoid configuration's batch (1024 envs, k = 4), on 8 sampled envs (indices
+    from seed 4), one random direction in each env's positions and velocities (the root
+    quaternion left fixed).  The envs are independent, so all 8 directions are taken in one
+    pair of windows and compared through each env's share of the loss.  h = 4 frames
+    keeps the window smooth on the scale of eps = 1e-6, where the oracle's own central
+    differences agree with its reverse mode to ~1e-11."""
+    W = wl.workload("humanoid", 1024)
+    md = W["model"]
+    N, h, eps = 1024, 4, 1e-6
+    od = W["obs_dim"]
+    sim = P.Sim(md, N, h, [od] + [w.shape[0] for w, _ in W["actor"]], [od] + [w.shape[0] for w, _ in W["critic"]],
+                ckpt_interval=4, precision="fp64")
+    rng = np.random.default_rng(4)
+    envs = np.sort(rng.choice(N, 8, replace=False))
+    ns = W["s0"].shape[1]
+    U = np.zeros((N, ns))
+    for e in envs:
+        u = rng.standard_normal(ns)
+        u[3:7] = 0.0                                    # root quaternion
+        u[md["nq"] + md["nv"]:] = 0.0                   # last action (zero at the window start)
+        U[e] = u / np.linalg.norm(u)
+    print("[fd] humanoid fp64 N=1024 h=4, 8 sampled envs", flush=True)
+    fw = sim.forward(W["s0"], W["actor"], W["critic"])
+    ad = sim.adjoint(fw)
+    torch.cuda.synchronize()
+    want = (ad["dL_ds0"].cpu().numpy() * U).sum(1)[envs]
+    g = sim.opt.gamma
+
+    def env_losses(s0):
+        f = sim.forward(s0, W["actor"], W["critic"])
+        torch.cuda.synchronize()
+        r = f["rewards"].cpu().numpy()
+        v = f["value"].cpu().numpy()
+        return -(sum(g ** t * r[t] for t in range(h)) + g ** h * v) / (N * h)
+    fd = ((env_losses(W["s0"] + eps * U) - env_losses(W["s0"] - eps * U)) / (2 * eps))[envs]
+    assert np.all(np.abs(fd - want) <= 1e-6 * np.abs(want) + 1e-12 * np.abs(want).max()), (fd, want)
