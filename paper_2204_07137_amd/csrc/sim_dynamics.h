@@ -1196,19 +1196,31 @@ __device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, 
   for (int i = 0; i < L::kTapeBytes / 1024; ++i) __builtin_nontemporal_store(src[i * SIM_WAVE + ln], &dst[i * SIM_WAVE + ln]);
 }
 
-// Restores the block with direct global-to-LDS transfers (no registers in flight,
-// non-temporal), then the factor's rows and columns and the pivots into registers.
-template <int NV, class L>
-__device__ __forceinline__ void tape_load(L& E, Chol& C, int& fb, int ln, const real* __restrict__ tp) {
-  const char* g = reinterpret_cast<const char*>(tp);
-  char* l = reinterpret_cast<char*>(&E.q[0]);
-  __syncthreads();   // earlier LDS reads of the block complete before the transfer overwrites it
+// A tape entry held in registers (16 bytes per lane per KB): the adjoint loads the next
+// entry while the current substep's reverse runs, so the load latency is hidden.
+template <class L>
+struct TapeRegs {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 v[L::kTapeBytes / 1024];
+};
+
+template <class L>
+__device__ __forceinline__ void tape_prefetch(TapeRegs<L>& P, const real* __restrict__ tp, int ln) {
+  typedef typename TapeRegs<L>::u32x4 u32x4;
+  const u32x4* src = reinterpret_cast<const u32x4*>(tp);
+  // each lane reads back exactly the 16-byte words it stored (tape_store)
 #pragma unroll
-  for (int i = 0; i < L::kTapeBytes / 1024; ++i)
-    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + i * 1024 + ln * 16),
-                                     (__attribute__((address_space(3))) void*)(l + i * 1024), 16, 0,
-                                     /* non-temporal */ 2);
-  __builtin_amdgcn_s_waitcnt(0);
+  for (int i = 0; i < L::kTapeBytes / 1024; ++i) P.v[i] = __builtin_nontemporal_load(&src[i * SIM_WAVE + ln]);
+}
+
+// tape_load from a prefetched entry
+template <int NV, class L>
+__device__ __forceinline__ void tape_load_regs(L& E, Chol& C, int& fb, int ln, const TapeRegs<L>& P) {
+  typedef typename TapeRegs<L>::u32x4 u32x4;
+  u32x4* dst = reinterpret_cast<u32x4*>(&E.q[0]);
+  __syncthreads();   // earlier LDS reads of the block complete before it is overwritten
+#pragma unroll
+  for (int i = 0; i < L::kTapeBytes / 1024; ++i) dst[i * SIM_WAVE + ln] = P.v[i];
   __syncthreads();
   const int lr = ln < NV ? ln : 0;
 #pragma unroll

@@ -269,11 +269,14 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
     const real* at = A.actions_fw + ((size_t)t * N + env) * na;
     for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
     if (A.tape_full) {
-      // the forward stored every substep's pre-state and linearisation
+      // the forward stored every substep's pre-state and linearisation; the next (earlier)
+      // entry is loaded into registers while the current one is reversed
+      TapeRegs<L> P;
+      tape_prefetch(P, A.tape + (((size_t)t * S + S - 1) * N + env) * L::kTapeReals, ln);
       for (int sub = S - 1; sub >= 0; --sub) {
-        const size_t c = (size_t)t * S + sub;
         int fb;
-        tape_load<NV>(E, C, fb, ln, A.tape + (c * N + env) * L::kTapeReals);
+        tape_load_regs<NV>(E, C, fb, ln, P);
+        if (sub > 0) tape_prefetch(P, A.tape + (((size_t)t * S + sub - 1) * N + env) * L::kTapeReals, ln);
         if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
       }
@@ -291,14 +294,18 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
           tape_store<NV>(E, C, fb, ln, tseg + (size_t)i * L::kTapeReals);
           commit_substep(m, E, ln);
         }
+        // the segment's recorded entries are loaded into registers one ahead of their use
+        TapeRegs<L> P;
         {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+          if (k >= 2) tape_prefetch(P, tseg + (size_t)(k - 2) * L::kTapeReals, ln);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
         for (int i = k - 2; i >= 0; --i) {
           int fb;
-          tape_load<NV>(E, C, fb, ln, tseg + (size_t)i * L::kTapeReals);
+          tape_load_regs<NV>(E, C, fb, ln, P);
+          if (i > 0) tape_prefetch(P, tseg + (size_t)(i - 1) * L::kTapeReals, ln);
           if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
