@@ -37,7 +37,8 @@ struct SimHandle {
   size_t elem = 4;
   size_t wt_actor_off[SIM_MAXL], wt_critic_off[SIM_MAXL], wp_actor_off[SIM_MAXL], wp_critic_off[SIM_MAXL];
   size_t bf_actor_off[SIM_MAXL][2], bf_critic_off[SIM_MAXL][2];   // BF16 forward / adjoint tiles
-  size_t off_ckpt = 0, off_adj = 0, off_tape = 0, off_done = 0, off_seg = 0, ws_bytes = 0;
+  size_t off_ckpt = 0, off_adj = 0, off_tape = 0, off_done = 0, off_seg = 0, off_hid = 0, ws_bytes = 0;
+  int hid_w = 0;   // the actor's hidden widths, summed (closed loop)
   // policy-gradient scratch: hidden activations, two layer-adjoint buffers, split partials
   size_t off_th_h[SIM_MAXL], off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
   int th_splits = 0;
@@ -390,6 +391,11 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   off = align256(off + (size_t)opt->horizon * N);
   h->off_seg = off;
   off = align256(off + (size_t)(opt->horizon + 1) * N * sizeof(int));
+  h->hid_w = 0;
+  if (opt->closed_loop)
+    for (int l = 1; l < opt->actor_layers; ++l) h->hid_w += opt->actor_dims[l];
+  h->off_hid = off;
+  off = align256(off + e * (size_t)opt->horizon * N * h->hid_w);
   for (int l = 0; l < SIM_MAXL; ++l) h->off_th_h[l] = 0;
   if (opt->policy_grad) {
     const size_t rows = N * (size_t)opt->horizon;
@@ -529,6 +535,8 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.seg_ws = reinterpret_cast<int*>(ws + h->off_seg);
   A.obs_mean = static_cast<const T*>(io->obs_mean);
   A.obs_inv_std = static_cast<const T*>(io->obs_inv_std);
+  A.hid = reinterpret_cast<T*>(ws + h->off_hid);
+  A.hid_w = h->hid_w;
   return SIM_OK;
 }
 
@@ -565,6 +573,8 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.dL_ds0 = static_cast<T*>(io->dL_ds0);
   A.obs_mean = static_cast<const T*>(io->obs_mean);
   A.obs_inv_std = static_cast<const T*>(io->obs_inv_std);
+  A.hid = reinterpret_cast<T*>(ws + h->off_hid);
+  A.hid_w = h->hid_w;
   return SIM_OK;
 }
 

@@ -67,6 +67,13 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   if (A.closed_loop) {
     obs_normalize(A, m, E.obs, ln);
     mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
+    // keep the hidden activations for the adjoint's input VJP (at most two hidden layers)
+    {
+      real* hs = A.hid + ((size_t)t * N + env) * A.hid_w;
+      const int d1 = A.actor.nl > 1 ? A.actor.dims[1] : 0, d2 = A.actor.nl > 2 ? A.actor.dims[2] : 0;
+      for (int i = ln; i < d1; i += SIM_WAVE) hs[i] = E.h0[i];
+      for (int i = ln; i < d2; i += SIM_WAVE) hs[d1 + i] = E.h1[i];
+    }
     if (A.noise) {
       // stochastic policy, reparameterised (Sec. 3.3): y = mu(o) + exp(log_std) * eps
       const real* ep = A.noise + ((size_t)t * N + env) * na;
@@ -224,10 +231,15 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   // a_prev of s_t is a_{t-1} (or the a_prev of s_0); its adjoint starts at zero
   __syncthreads();
   if (A.closed_loop) {
-    for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)t * N + env) * od + i];
+    // the actor's hidden activations as the forward stored them (the values a re-evaluation
+    // on the stored observation would give, bit for bit)
+    {
+      const real* hs = A.hid + ((size_t)t * N + env) * A.hid_w;
+      const int d1 = A.actor.nl > 1 ? A.actor.dims[1] : 0, d2 = A.actor.nl > 2 ? A.actor.dims[2] : 0;
+      for (int i = ln; i < d1; i += SIM_WAVE) E.h0[i] = hs[i];
+      for (int i = ln; i < d2; i += SIM_WAVE) E.h1[i] = hs[d1 + i];
+    }
     __syncthreads();
-    obs_normalize(A, m, E.obs, ln);
-    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
     for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
     mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
@@ -240,6 +252,7 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
     __syncthreads();
   }
   (void)ns;
+  (void)od;
 }
 
 // One environment's reverse window.

@@ -121,6 +121,10 @@ struct WinArgsT {
   // observation normalisation: the networks see (o - obs_mean) * obs_inv_std (both [od]) or o
   const T* obs_mean;
   const T* obs_inv_std;
+  // the actor's hidden activations of every frame, [h][N][hid_w] (workspace, closed loop):
+  // written by the forward, read by the adjoint's input VJP
+  T* hid;
+  int hid_w;
 };
 
 // Several models' windows in one launch (mixed-morphology batch): work-table slot s covers
