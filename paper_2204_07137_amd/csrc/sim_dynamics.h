@@ -1218,10 +1218,12 @@ template <int NV, class L>
 __device__ __forceinline__ void tape_load_regs(L& E, Chol& C, int& fb, int ln, const TapeRegs<L>& P) {
   typedef typename TapeRegs<L>::u32x4 u32x4;
   u32x4* dst = reinterpret_cast<u32x4*>(&E.q[0]);
-  __syncthreads();   // earlier LDS reads of the block complete before it is overwritten
+  // LDS ordering only (one wavefront per environment): the tape stores still in flight
+  // need not complete here, and the registers wait for their own loads
+  wsync();   // earlier LDS reads of the block complete before it is overwritten
 #pragma unroll
   for (int i = 0; i < L::kTapeBytes / 1024; ++i) dst[i * SIM_WAVE + ln] = P.v[i];
-  __syncthreads();
+  wsync();
   const int lr = ln < NV ? ln : 0;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
