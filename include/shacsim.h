@@ -207,6 +207,12 @@ typedef struct SimForwardIO {
    * that penetrate (d < 0) with a pulling normal force, i.e. where the literal damping term
    * of the contact model (Sec. 3.1) exceeds the stiffness term (d_dot > k_n / k_d). */
   int32_t* adhesive_count;
+  /* The short-horizon actor loss (Sec. 3.3, Eq. "policy_loss"), optional outputs: loss_env [N]
+   * each env's term -1/(N h) (sum_t gamma^(t - t0) r_t + gamma^(h - t0) V(o_h)), with t0 the
+   * start of the env's discount segment (0 without early termination; no terminal value
+   * after a termination in the last frame), and loss [1] their sum in a fixed order. */
+  void* loss_env;
+  void* loss;
 } SimForwardIO;
 
 typedef struct SimAdjointIO {

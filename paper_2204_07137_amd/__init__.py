@@ -51,7 +51,7 @@ class SimForwardIO(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
                 ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p),
                 ("noise", _p), ("log_std", _p), ("reset_states", _p), ("done", _p),
-                ("obs_mean", _p), ("obs_inv_std", _p), ("adhesive_count", _p)]
+                ("obs_mean", _p), ("obs_inv_std", _p), ("adhesive_count", _p), ("loss_env", _p), ("loss", _p)]
 
 
 class SimAdjointIO(ctypes.Structure):
@@ -365,7 +365,8 @@ class Sim:
         s0 = self._dev(s0)
         assert s0.shape == (N, self.ns), (s0.shape, (N, self.ns))
         dt = self.dtype
-        keys = ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count")
+        keys = ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count",
+                "loss_env", "loss")
         prev_done = None
         if out is not None:
             prev_done = out.get("done")
@@ -382,6 +383,8 @@ class Sim:
                 nonfinite=t.zeros(N, dtype=t.uint8, device="cuda"),
                 fp64_refactor_count=t.zeros(N, dtype=t.int32, device="cuda"),
                 adhesive_count=t.zeros(N, dtype=t.int32, device="cuda"),
+                loss_env=t.empty(N, device="cuda", dtype=dt),
+                loss=t.empty(1, device="cuda", dtype=dt),
             )
         io = SimForwardIO()
         io.s0 = self._ptr(s0)
@@ -408,7 +411,8 @@ class Sim:
         self._set_weights(io, actor, critic, out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
-        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count"):
+        for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count",
+                  "loss_env", "loss"):
             setattr(io, k, self._ptr(out[k]))
         out["_io"] = io
         return out, io
@@ -654,27 +658,6 @@ def probe_ceilings(copy_bytes=1 << 30):
     return {"fp32_valu_tflops": tf.value, "copy_gbs": gb.value, "copy_bytes": copy_bytes}
 
 
-def window_loss(fw, gamma):
-    """The short-horizon actor loss (Sec. 3.3) of a forward result: -1/(N h) sum over envs
-    of sum_t gamma^(t - t0) r_t + gamma^(h - t0) V(o_h), with t0 the first frame of the
-    env's discount segment (0 without early termination; a segment that ends in termination
-    has no terminal value)."""
-    import torch
-    rew, value = fw["rewards"], fw["value"]
-    H, N = rew.shape
-    if "done" not in fw:
-        disc = torch.stack([gamma ** t * rew[t] for t in range(H)]).sum(0)
-        return -(disc + gamma ** H * value).sum() / (N * H)
-    done = fw["done"].bool()
-    t0 = torch.zeros(N, dtype=rew.dtype, device=rew.device)
-    disc = torch.zeros(N, dtype=rew.dtype, device=rew.device)
-    for t in range(H):
-        disc = disc + torch.pow(torch.full_like(t0, gamma), t - t0) * rew[t]
-        t0 = torch.where(done[t], torch.full_like(t0, t + 1), t0)
-    live = (~done[H - 1]).to(rew.dtype)
-    return -(disc + live * torch.pow(torch.full_like(t0, gamma), H - t0) * value).sum() / (N * H)
-
-
 def window_function(noise=None, reset_states=None, obs_norm=None):
     """torch.autograd.Function over one window: forward -> sim_forward_window, backward ->
     sim_adjoint_window.
@@ -683,7 +666,8 @@ def window_function(noise=None, reset_states=None, obs_norm=None):
     flat sequence W_0, b_0, W_1, b_1, ... returns (loss, s_h, obs, actions, rewards,
     value).  Gradients flow to s0 (total, through the closed-loop policy), to actions_in
     in open loop, and to the actor parameters when the handle was created with
-    policy_grad=True.  The loss is the short-horizon actor loss (window_loss); a gradient
+    policy_grad=True.  The loss is the short-horizon actor loss, as the forward window computes
+    it (the loss output of sim_forward_window); a gradient
     arriving on s_h is propagated through the window as well.
 
     The returned class is bound to the optional inputs given here: noise [h, N, na] selects
@@ -703,7 +687,7 @@ def window_function(noise=None, reset_states=None, obs_norm=None):
             fw = sim.forward(s0.detach(), actor, critic,
                              actions_in.detach() if actions_in is not None else None, noise=noise,
                              log_std=log_std, reset_states=reset_states, obs_norm=obs_norm)
-            loss = window_loss(fw, sim.opt.gamma)
+            loss = fw["loss"].reshape(())
             ctx.sim, ctx.fw, ctx.open_loop = sim, fw, actions_in is not None
             ctx.n_actor = len(actor_params)
             ctx.mark_non_differentiable(fw["obs"], fw["actions"], fw["rewards"], fw["value"])

@@ -525,6 +525,8 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.nonfinite = io->nonfinite;
   A.fallback = io->fp64_refactor_count;
   A.adhesive = io->adhesive_count;
+  A.loss_env = static_cast<T*>(io->loss_env);
+  A.loss = static_cast<T*>(io->loss);
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);

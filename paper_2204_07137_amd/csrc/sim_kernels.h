@@ -604,6 +604,42 @@ int launch_prep_weights(const real* W, real* WT, real* Wp, int n_out, int n_in, 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// The short-horizon actor loss of the window (Sec. 3.3, Eq. "policy_loss") from the frames'
+// rewards and the terminal values: per env
+//   l_e = -scale (sum_t gamma^(t - t0(t)) r_t + live_e gamma^(h - t0) V_e),
+// with t0(t) the first frame of frame t's discount segment (0 without early termination) and
+// live_e = 0 when the last frame ended in termination.  One block; the envs' losses are
+// summed in a fixed order.
+__global__ __launch_bounds__(1024) void k_window_loss(WinArgs A) {
+  __shared__ real part[1024];
+  const int N = A.N, h = A.h;
+  const uint8_t* done = A.model->term ? A.done_ws : nullptr;
+  real acc = RL(0.0);
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    real disc = RL(0.0);
+    int t0 = 0;
+    for (int t = 0; t < h; ++t) {
+      disc += m_pow(A.gamma, (real)(t - t0)) * A.rewards[(size_t)t * N + e];
+      if (done && done[(size_t)t * N + e]) t0 = t + 1;
+    }
+    const bool live = !(done && done[(size_t)(h - 1) * N + e]);
+    const real le = -A.scale * (disc + (live ? m_pow(A.gamma, (real)(h - t0)) * A.value[e] : RL(0.0)));
+    if (A.loss_env) A.loss_env[e] = le;
+    acc += le;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && A.loss) A.loss[0] = part[0];
+}
+
+static void launch_window_loss(const WinArgs& A, hipStream_t s) {
+  if (A.loss_env || A.loss) hipLaunchKernelGGL(k_window_loss, dim3(1), dim3(1024), 0, s, A);
+}
+
 template <int NV>
 static void launch_forward_nv(const WinArgs& A, int plain, int substeps, int mtu, hipStream_t s) {
   dim3 grid(A.N), block(SIM_WAVE);
@@ -657,6 +693,7 @@ int launch_forward(const WinArgs& A, int plain, int substeps, int nv, int mtu, v
       default: launch_forward_nv<SIM_MAXV>(A, plain, substeps, 0, s);
     }
   }
+  launch_window_loss(A, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -690,5 +727,7 @@ int launch_group(const GroupArgs& G, int adjoint, int mtu, void* stream) {
     if (adjoint) hipLaunchKernelGGL(k_group<true>, grid, block, 0, st, G);
     else hipLaunchKernelGGL(k_group<false>, grid, block, 0, st, G);
   }
+  if (!adjoint)
+    for (int s = 0; s < G.n; ++s) launch_window_loss(G.A[s], st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -125,6 +125,9 @@ struct WinArgsT {
   // written by the forward, read by the adjoint's input VJP
   T* hid;
   int hid_w;
+  // the window's loss: per env [N] and the sum over envs [1] (forward, optional)
+  T* loss_env;
+  T* loss;
 };
 
 // Several models' windows in one launch (mixed-morphology batch): work-table slot s covers

@@ -54,7 +54,7 @@ def test_group_matches_members_bitwise_and_orders_by_cost():
     torch.cuda.synchronize()
     for i in range(len(sims)):
         a, b = _np(solo_f[i]), _np(gf[i])
-        for key in ("s_h", "obs", "actions", "rewards", "value"):
+        for key in ("s_h", "obs", "actions", "rewards", "value", "loss_env", "loss"):
             assert np.array_equal(a[key], b[key]), (i, key)
         a, b = _np(solo_a[i]), _np(ga[i])
         for key in ("dL_da", "dL_ds0", "dL_dtheta_flat"):

@@ -397,3 +397,21 @@ def test_humanoid_adjoint_matches_central_differences_of_the_gpu_forward():
         return -(sum(g ** t * r[t] for t in range(h)) + g ** h * v) / (N * h)
     fd = ((env_losses(W["s0"] + eps * U) - env_losses(W["s0"] - eps * U)) / (2 * eps))[envs]
     assert np.all(np.abs(fd - want) <= 1e-6 * np.abs(want) + 1e-12 * np.abs(want).max()), (fd, want)
+
+
+@pytest.mark.parametrize("path", ["persistent", "plain"])
+def test_window_loss_output_matches_oracle(path):
+    """The forward's loss outputs (per env and total, Sec. 3.3) against the oracle's loss,
+    FP64 kernels, Ant N 8 h 4, persistent and plain launch forms."""
+    W = wl.workload("ant", 8)
+    od = W["obs_dim"]
+    kw = dict(path=P.PATH_PLAIN) if path == "plain" else dict(ckpt_interval=4)
+    sim = P.Sim(W["model"], 8, 4, [od] + [w.shape[0] for w, _ in W["actor"]],
+                [od] + [w.shape[0] for w, _ in W["critic"]], precision="fp64", **kw)
+    print(f"[loss] ant fp64 {path}", flush=True)
+    fw = sim.forward(W["s0"], W["actor"], W["critic"])
+    torch.cuda.synchronize()
+    ref = oracle_window(W["model"], W["s0"], 4, W["actor"], W["critic"])
+    per_env = -(sum(0.99 ** t * ref["rewards"][t] for t in range(4)) + 0.99 ** 4 * ref["value"]) / 32
+    assert abs(float(fw["loss"][0]) - float(ref["loss"])) < 1e-12 * abs(float(ref["loss"]))
+    np.testing.assert_allclose(fw["loss_env"].cpu().numpy(), per_env.numpy(), rtol=1e-12, atol=1e-15)

@@ -36,7 +36,7 @@ def _run(W, md, s0, reset, h, want_theta=False, **kw):
     fw = sim.forward(s0, W["actor"], W["critic"], reset_states=reset)
     ad = sim.adjoint(fw, want_theta=want_theta)
     torch.cuda.synchronize()
-    f = {k: fw[k].double().cpu().numpy() for k in ("s_h", "actions", "rewards", "value", "done")}
+    f = {k: fw[k].double().cpu().numpy() for k in ("s_h", "actions", "rewards", "value", "done", "loss", "loss_env")}
     a = {k: ad[k].double().cpu().numpy() for k in ("dL_da", "dL_ds0")}
     if want_theta:
         a["theta"] = ad["dL_dtheta_flat"].double().cpu().numpy()
@@ -56,6 +56,9 @@ def test_termination_fp64_matches_oracle(path):
     assert np.array_equal(f["done"].astype(bool), ref["done"])
     for key in ("s_h", "actions", "rewards", "value"):
         assert relnorm(f[key], ref[key]) < 1e-10, key
+    # the window's loss output, with the segment discounts and no value after a last-frame reset
+    assert abs(f["loss"][0] - ref["loss"]) < 1e-10 * abs(ref["loss"])
+    assert abs(f["loss_env"].sum() - f["loss"][0]) < 1e-12 * abs(ref["loss"])
     want_theta = np.concatenate([x.ravel() for pair in ref["dL_dtheta"] for x in pair])
     for got, want in ((a["dL_da"], ref["dL_da"]), (a["dL_ds0"], ref["dL_ds0"]), (a["theta"], want_theta)):
         assert relnorm(got, want) < 1e-9
@@ -77,7 +80,7 @@ def test_termination_paths_bitwise_and_inactive_is_unchanged():
     f0, a0 = _run(W, md, s0, reset, h, ckpt_interval=4)
     f1, a1 = _run(W, md, s0, reset, h, path=P.PATH_TAPE)
     assert f0["done"].any()
-    for key in ("s_h", "actions", "rewards", "value", "done"):
+    for key in ("s_h", "actions", "rewards", "value", "done", "loss", "loss_env"):
         assert np.array_equal(f0[key], f1[key]), key
     assert np.array_equal(a0["dL_da"], a1["dL_da"]) and np.array_equal(a0["dL_ds0"], a1["dL_ds0"])
     # standing humanoids do not fall within three frames: termination on or off is the same window
