@@ -131,3 +131,45 @@ def test_autotuner_picks_a_valid_configuration():
     with pytest.raises(P.SimError) as e:
         P.tune(W["model"], 64, h, *dims, W["s0"], W["actor"], W["critic"], budget_bytes=1, reps=1)
     assert e.value.code == -5
+
+
+def test_group_with_stochastic_normalised_member_matches_members():
+    """A group whose Ant member runs the stochastic policy with observation normalisation and
+    the policy-parameter gradient (dL/dlog_std included), beside a plain Humanoid member:
+    each member bitwise equal to its own calls."""
+    h = 3
+    rng = np.random.default_rng(17)
+    sims, args = [], []
+    for name, n, k in (("ant", 40, 4), ("humanoid", 24, 16)):
+        W = wl.workload(name, n)
+        od = W["obs_dim"]
+        sim = P.Sim(W["model"], n, h, [od] + [w.shape[0] for w, _ in W["actor"]],
+                    [od] + [w.shape[0] for w, _ in W["critic"]], ckpt_interval=k, policy_grad=True)
+        a = dict(s0=sim._dev(W["s0"]), actor=sim.weights(W["actor"]), critic=sim.weights(W["critic"]))
+        if name == "ant":
+            na = W["model"]["na"]
+            a["noise"] = sim._dev(rng.standard_normal((h, n, na)))
+            a["log_std"] = sim._dev(rng.uniform(-1.5, -0.5, na))
+            a["obs_norm"] = (sim._dev(rng.normal(0.0, 0.5, od)), sim._dev(rng.uniform(0.3, 2.0, od)))
+        sims.append(sim)
+        args.append(a)
+    print("[group] ant 40 (stochastic, normalised) + humanoid 24, h=3", flush=True)
+    solo_f, solo_a = [], []
+    for sim, a in zip(sims, args):
+        fw = sim.forward(**a)
+        ad = sim.adjoint(fw, want_theta=True)
+        solo_f.append(_np(fw))
+        solo_a.append(_np(ad))
+    torch.cuda.synchronize()
+    G = P.Group(sims)
+    gf = G.forward(args)
+    ga = G.adjoint(gf, want_theta=True)
+    torch.cuda.synchronize()
+    for i in range(2):
+        b = _np(gf[i])
+        for key in ("s_h", "obs", "actions", "rewards", "value", "loss_env", "loss"):
+            assert np.array_equal(solo_f[i][key], b[key]), (i, key)
+        b = _np(ga[i])
+        keys = ("dL_da", "dL_ds0", "dL_dtheta_flat") + (("dL_dlog_std",) if i == 0 else ())
+        for key in keys:
+            assert np.array_equal(solo_a[i][key], b[key]), (i, key)
