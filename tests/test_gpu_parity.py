@@ -415,3 +415,28 @@ def test_window_loss_output_matches_oracle(path):
     per_env = -(sum(0.99 ** t * ref["rewards"][t] for t in range(4)) + 0.99 ** 4 * ref["value"]) / 32
     assert abs(float(fw["loss"][0]) - float(ref["loss"])) < 1e-12 * abs(float(ref["loss"]))
     np.testing.assert_allclose(fw["loss_env"].cpu().numpy(), per_env.numpy(), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,N,h,kw", [("ant", 1, 1, dict(ckpt_interval=16)), ("ant", 3, 1, dict(path=P.PATH_TAPE)),
+                                         ("humanoid", 1, 2, dict(ckpt_interval=48)),
+                                         ("cartpole", 5, 1, dict(path=P.PATH_PLAIN))],
+                         ids=["ant-N1-h1", "ant-N3-h1-tape", "humanoid-N1-h2-k48", "cartpole-N5-h1-plain"])
+def test_degenerate_windows_fp64_match_oracle(name, N, h, kw):
+    """Degenerate shapes: one environment, a one-frame window, one checkpoint per frame
+    (k = S), a ragged env count, on every launch form: FP64 kernels against the oracle,
+    including the policy-parameter gradient and the loss output."""
+    W = wl.workload(name, N)
+    od = W["obs_dim"]
+    sim = P.Sim(W["model"], N, h, [od] + [w.shape[0] for w, _ in W["actor"]],
+                [od] + [w.shape[0] for w, _ in W["critic"]], precision="fp64", policy_grad=True, **kw)
+    print(f"[edge] {name} N={N} h={h} {kw}", flush=True)
+    fw = sim.forward(W["s0"], W["actor"], W["critic"])
+    ad = sim.adjoint(fw, want_theta=True)
+    torch.cuda.synchronize()
+    ref = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], want_theta=True)
+    assert relnorm(fw["s_h"].cpu().numpy(), ref["s_h"]) < 1e-10
+    assert abs(float(fw["loss"][0]) - ref["loss"]) < 1e-10 * abs(ref["loss"])
+    assert relnorm(ad["dL_da"].cpu().numpy(), ref["dL_da"]) < 1e-9
+    assert relnorm(ad["dL_ds0"].cpu().numpy(), ref["dL_ds0"]) < 1e-9
+    want = np.concatenate([x.ravel() for pair in ref["dL_dtheta"] for x in pair])
+    assert relnorm(ad["dL_dtheta_flat"].cpu().numpy(), want) < 1e-9
