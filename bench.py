@@ -500,7 +500,10 @@ def main():
                                              want_theta=True)
         th_ms = max(float(np.median(adj_th_ms)) - float(np.median(adj_ms)), 0.0)
         rows = N * h
-        th_flops = 3 * 2 * rows * sum(a * b for a, b in zip(actor_dims[:-1], actor_dims[1:]))
+        # the contractions the pass runs: every layer's weight gradient and the input adjoints
+        # of layers 1.. (the hidden activations are the window's own, FP32 networks)
+        layer = [a * b for a, b in zip(actor_dims[:-1], actor_dims[1:])]
+        th_flops = 2 * rows * (sum(layer) + sum(layer[1:]))
         out["policy_grad"] = {"ms": round(th_ms, 3), "rows": rows,
                               "mfma_tflops": round(th_flops / max(th_ms, 1e-6) / 1e9, 3),
                               "mfma_peak_fp32_tflops": 157.3}

@@ -608,6 +608,18 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
   P.d1 = reinterpret_cast<T*>(ws + h->off_th_d1);
   P.part = reinterpret_cast<T*>(ws + h->off_th_part);
   P.out = static_cast<T*>(io->dL_dtheta);
+  // with FP32/FP64 networks the gradient is taken at the activations the window itself
+  // computed (stored by the forward), rows (t, env) as the observations'
+  if (o.mlp_precision != SIM_MLP_BF16 && h->hid_w > 0) {
+    T* hid = reinterpret_cast<T*>(ws + h->off_hid);
+    long off_l = 0;
+    for (int l = 1; l < o.actor_layers; ++l) {
+      P.H[l] = hid + off_l;
+      P.ldH[l] = h->hid_w;
+      off_l += o.actor_dims[l];
+    }
+    P.hidden_given = 1;
+  }
   P.mtu = (h->m64.task == TASK_MTU) ? 1 : 0;
   P.noise = static_cast<const T*>(io->noise);
   P.log_std = static_cast<const T*>(io->log_std);

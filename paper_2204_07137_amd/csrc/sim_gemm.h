@@ -251,9 +251,10 @@ static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
   for (int l = L - 1; l >= 0; --l) {
     const int ni = T.dims[l], no = T.dims[l + 1];
     const real* xin = (l == 0) ? T.x0 : T.H[l];
+    const long ldx = (l > 0 && T.ldH[l]) ? T.ldH[l] : ni;
     GemmArgs g = {};
     g.A = dcur; g.sam = 1; g.sak = no;
-    g.B = xin; g.sbk = ni; g.sbn = 1; g.ones_col = 1;
+    g.B = xin; g.sbk = ldx; g.sbn = 1; g.ones_col = 1;
     g.M = no; g.N = ni + 1; g.K = M; g.k_chunk = chunk;
     g.C = T.part; g.ldc = ni + 1; g.split_stride = (long)no * (ni + 1);
     g.epi = EPI_STORE;
@@ -269,7 +270,7 @@ static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
       g2.M = M; g2.N = ni; g2.K = no;
       g2.k_chunk = (no + GT_K - 1) / GT_K * GT_K;
       g2.C = dnext; g2.ldc = ni;
-      g2.epi = EPI_DELU; g2.Hm = T.H[l]; g2.ldh = ni;
+      g2.epi = EPI_DELU; g2.Hm = T.H[l]; g2.ldh = ldx;
       launch_gemm(g2, 1, s);
       real* t = dcur; dcur = dnext; dnext = t;
     }
@@ -279,8 +280,8 @@ static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
 int launch_theta(const ThetaArgsT<real>& T, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const int M = T.M, L = T.nl;
-  // re-evaluate the hidden layers on the stored observations
-  theta_hidden(T, s);
+  // the hidden layers on the stored observations, unless the window stored them
+  if (!T.hidden_given) theta_hidden(T, s);
   const int na = T.dims[L];
   const long nseed = (long)M * na;
   hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed,

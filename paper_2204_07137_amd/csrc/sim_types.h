@@ -161,6 +161,8 @@ struct ThetaArgsT {
   const T* log_std;           // [na]
   T* out_log_std;             // [na] dL/dlog_std (with noise), or null
   T* H[SIM_MAXL];             // H[l] (l >= 1): [M][dims[l]] hidden activations
+  long ldH[SIM_MAXL];         // row stride of H[l] (0: dims[l])
+  int hidden_given;           // H holds the activations already (the window's own): no recompute
   T* d0;                      // [M][max dim] layer adjoints (ping-pong)
   T* d1;
   T* part;                    // [splits][max out*(in+1)] partial weight gradients
