@@ -608,8 +608,8 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
   P.d1 = reinterpret_cast<T*>(ws + h->off_th_d1);
   P.part = reinterpret_cast<T*>(ws + h->off_th_part);
   P.out = static_cast<T*>(io->dL_dtheta);
-  // with FP32/FP64 networks the gradient is taken at the activations the window itself
-  // computed (stored by the forward), rows (t, env) as the observations'
+  // the gradient is taken at the activations the window itself computed (stored by the
+  // forward), rows (t, env) as the observations' (handles with BF16 MLPs have no dL/dtheta)
   if (o.mlp_precision != SIM_MLP_BF16 && h->hid_w > 0) {
     T* hid = reinterpret_cast<T*>(ws + h->off_hid);
     long off_l = 0;

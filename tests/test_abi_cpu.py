@@ -127,3 +127,15 @@ def test_too_many_joints_rejected():
     md["task"] = "none"
     rc, msg = _create(md, critic=[1, 1])
     assert rc == -4 and "n_joints" in msg
+
+
+def test_termination_model_and_path_checks():
+    """Early termination needs a free root and runs on the persistent and tape paths only:
+    both are rejected at sim_create, before anything reaches the device."""
+    import workloads as wl
+    cp = wl.with_termination(dict(wl.workload("cartpole", 4)["model"], et_height=0.5))
+    rc, msg = _create(cp)
+    assert rc == -4 and "FREE root" in msg
+    ant = wl.with_termination(wl.workload("ant", 4)["model"])
+    rc, msg = _create(ant, path=1, k=1)
+    assert rc == -6 and "persistent and tape" in msg
