@@ -5,15 +5,16 @@
 // tanh and every ELU layer, and the weight gradient of a layer is the contraction of its
 // output adjoint with its input over all rows.
 //
-// Every contraction runs on the matrix cores: 64x64 output tiles staged through LDS in
-// K-slices of 32, four wavefronts per tile, each wavefront a 2x2 block of 16x16x4 MFMA
-// accumulators; the next slice is loaded into registers while the current one is
-// multiplied.  Row reductions (K = h*N) are split into fixed chunks whose partial tiles
+// Every contraction runs on the matrix cores: 32x64 output tiles staged through LDS in
+// K-slices of 32, four wavefronts per tile, each wavefront a 1x2 block of 16x16x4 MFMA
+// accumulators (small tiles give the 8192-row critic GEMMs two tiles per CU); the next
+// slice is loaded into registers while the current one is multiplied.  Row reductions (K = h*N) are split into fixed chunks whose partial tiles
 // are summed in a fixed order, so the gradient is bitwise reproducible.
 //
 // Included inside a namespace with `real` defined as float or double.
 
-#define GT_M 64
+#define GT_M 32
+#define GT_MI (GT_M / 32)   // 16-row accumulator blocks per wavefront
 #define GT_N 64
 #define GT_K 32
 #define GT_THREADS 256
@@ -99,11 +100,11 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
   const int m0 = blockIdx.x * GT_M, n0 = blockIdx.y * GT_N;
   const int kb = blockIdx.z * g.k_chunk;
   const int ke = min(g.K, kb + g.k_chunk);
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  const int wm = (wv >> 1) * (16 * GT_MI), wn = (wv & 1) * 32;
   const int bcols = g.ones_col ? g.N - 1 : g.N;
-  mfma_v4 acc[2][2];
+  mfma_v4 acc[GT_MI][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < GT_MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = mfma_v4{RL(0.0), RL(0.0), RL(0.0), RL(0.0)};
 
@@ -127,18 +128,19 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int k4 = 0; k4 < GT_K; k4 += 4) {
       const int kr = k4 + (lane >> 4);
-      real a0 = As[kr][wm + (lane & 15)], a1 = As[kr][wm + 16 + (lane & 15)];
       real b0 = Bs[kr][wn + (lane & 15)], b1 = Bs[kr][wn + 16 + (lane & 15)];
-      acc[0][0] = mfma_16x16x4(a0, b0, acc[0][0]);
-      acc[0][1] = mfma_16x16x4(a0, b1, acc[0][1]);
-      acc[1][0] = mfma_16x16x4(a1, b0, acc[1][0]);
-      acc[1][1] = mfma_16x16x4(a1, b1, acc[1][1]);
+#pragma unroll
+      for (int i = 0; i < GT_MI; ++i) {
+        const real a = As[kr][wm + 16 * i + (lane & 15)];
+        acc[i][0] = mfma_16x16x4(a, b0, acc[i][0]);
+        acc[i][1] = mfma_16x16x4(a, b1, acc[i][1]);
+      }
     }
     __syncthreads();
   }
   real* C = g.C + (long)blockIdx.z * g.split_stride;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < GT_MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
