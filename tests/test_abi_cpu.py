@@ -139,3 +139,27 @@ def test_termination_model_and_path_checks():
     ant = wl.with_termination(wl.workload("ant", 4)["model"])
     rc, msg = _create(ant, path=1, k=1)
     assert rc == -6 and "persistent and tape" in msg
+
+
+def _header_members(struct):
+    """Member names, in order, of `typedef struct <struct> { ... } <struct>;` in shacsim.h."""
+    src = open(os.path.join(ROOT, "include", "shacsim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct, struct), src, flags=re.S).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(","):           # "double lr, beta1, beta2, eps"
+            m = re.search(r"\**\s*([A-Za-z_]\w*)\s*(\[[^\]]*\])*\s*$", part.strip())
+            names.append(m.group(1))
+    return names
+
+
+@pytest.mark.parametrize("struct", ["SimModelDesc", "SimOptions", "SimForwardIO", "SimAdjointIO", "SimTuneResult",
+                                    "SimCriticFitIO"])
+def test_binding_structs_match_the_header(struct):
+    """The ctypes structures of the binding declare the C structs' members in the same order
+    (a mismatch would shift every later field of a call)."""
+    assert [f[0] for f in getattr(P, struct)._fields_] == _header_members(struct)
