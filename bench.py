@@ -25,15 +25,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/s fwd+adjoint (h=32), 21-DOF humanoid ×1024 envs; grad err vs FP64"
 
-# MI355X figures used for the roofline (per GPU)
+# MI355X figures used for the roofline (per GPU): AMD's published FP32 vector peak (packed
+# FP32, 157.3 TFLOP/s); the same units without packed instructions give half of it, which is
+# reported beside it (this build does not emit packed FP32)
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
-FP32_VALU_PEAK_TFLOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_GHZ / 1e3   # non-packed FMA
+FP32_VALU_PEAK_TFLOPS = 157.3
+FP32_VALU_NONPACKED_TFLOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_GHZ / 1e3
 HBM_PEAK_GBS = 8000.0
 # Operations of the FP64 oracle per humanoid env-step (forward window, reverse-mode pass),
 # counted at the dispatcher by oracle/count_ops.py (re-derived by tests/test_oracle_count.py).
 # The oracle builds the mass matrix and bias in their dense defining form, so these exceed
 # the recursive algorithm's count below; they are reported as context, not as the roofline.
 ORACLE_OPS_PER_ENV_STEP = {"forward": 9205415, "reverse": 23383710}
+# Algorithmic operations of the humanoid, counted by the same counter on the oracle's
+# recursive form of the dynamics (oracle/recursive.py, equal to the defining form to
+# rounding; re-derived by tests/test_oracle_count.py): one substep (kinematics, contacts,
+# recursive Newton-Euler bias, composite-rigid-body mass matrix, Cholesky and solve,
+# integration) and its implicit-function adjoint (integrator reverse, the two triangular
+# solves of lambda, inverse dynamics at the solved accelerations and its vector-Jacobian
+# product), and the per-frame work around them (observation, actor MLP, squash, reward, and
+# their reverse with the actor's input VJP).  Recomputation from checkpoints is not counted.
+ALGO_OPS = {"substep_forward": 27116, "substep_reverse": 28937, "frame_forward": 111285, "frame_reverse": 112118}
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_window_kernels_humanoid1024_k4.json")
 PLAIN_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_plain_kernels_humanoid1024.json")
 
@@ -77,35 +89,25 @@ def adjoint_traffic(n_envs, k):
     return float(rec["bytes_per_launch"])
 
 
-def substep_flops(md):
-    """Floating-point operations (FMA = 2) of one forward substep and of one substep
-    adjoint of the recursive algorithm, from the model's structure.  Counts per phase:
-    kinematics/velocity/bias acceleration per hinge 185 (root 45), contact force 55 per
-    sphere, body inertia + Newton-Euler force 245 per frame, subtree sums 16 per edge,
-    bias projection and CRBA column 11 + 11 * depth per hinge (root block 36), dense
-    Cholesky 2 n^3 / 3, two triangular solves 2 n^2, integration 2 per hinge + 46 root.
-    Adjoint: integrator 60, lambda solves 2 n^2, accelerations / virtual velocities 54 per
-    hinge, contact adjoints 120 per sphere, per-body products 300 per frame, 42 subtree
-    sums per edge, closed-form derivatives 200 per hinge (1800 root), update 50."""
-    J = int(md["n_joints"])
-    nv = int(md["nv"])
-    nc = len(md["contact_body"])
-    par = md["parent"]
-    depth = np.zeros(J, int)
-    for j in range(J):
-        depth[j] = 0 if par[j] < 0 else depth[par[j]] + 1
-    hinges = [j for j in range(J) if md["jtype"][j] != 0]
-    free = J - len(hinges)
-    fwd = (185 * len(hinges) + 45 * free + 55 * nc + 245 * J + 16 * (J - 1)
-           + sum(11 + 11 * depth[j] for j in hinges) + 36 * free
-           + 2 * nv ** 3 / 3 + 2 * nv * nv + 2 * len(hinges) + 46 * free)
-    adj = (60 + 2 * nv * nv + 54 * len(hinges) + 120 * nc + 300 * J + 42 * (J - 1)
-           + 200 * len(hinges) + 1800 * free + 50)
-    return float(fwd), float(adj)
-
-
 def mlp_flops(dims):
     return float(sum(2 * a * b for a, b in zip(dims[:-1], dims[1:])))
+
+
+def algorithmic_bytes(md, n_envs, h, k, actor_dims, elem=4):
+    """HBM bytes per env-step that the checkpointed window must move: per frame the
+    observation, action, reward and dL/da; the checkpoints (S / k states of q, qd) written by
+    the forward and read by the adjoint; the actor's hidden activations written by the forward
+    and read by the adjoint; s0, s_h, dL/ds0 and the terminal observation once per window."""
+    S = int(md["substeps"])
+    nq, nv, na = int(md["nq"]), int(md["nv"]), int(md["na"])
+    od = actor_dims[0]
+    ns = nq + nv + (na if md["has_last_action"] else 0)
+    hid = sum(actor_dims[1:-1])
+    per_frame = (od + 2 * na + 1) + 2 * (S // k) * (nq + nv) + 2 * hid
+    per_window = 3 * ns + od
+    return {"per_env_step": elem * (per_frame + per_window / h),
+            "what": f"obs + action + reward + dL/da, {S // k} checkpoints written and read, hidden "
+                    f"activations written and read, per frame; s0, s_h, dL/ds0, o_h per window (FP32)"}
 
 
 def parse():
@@ -407,24 +409,28 @@ def fd_directions(sim64, W, ad64, h, n_dirs=8):
     return res
 
 
-def cpu_baseline(W, h, n_envs_sample=2):
-    """The FP64 oracle (CPU, PyTorch) on a bounded sample of the same workload."""
+def cpu_baseline(W, h_sample=2, n_envs_sample=64):
+    """The FP64 oracle (CPU, PyTorch) on a bounded sample of the same workload: n_envs_sample
+    envs of the headline batch over h_sample frames, forward and reverse, scaled to env-steps
+    per second (the oracle's cost is linear in frames; envs run as one batch).  cores is the
+    process's CPU time over the wall time of the run: the threads it kept busy."""
     import torch
     from oracle import oracle_window_grads
-    t0 = time.time()
-    oracle_window_grads(W["model"], W["s0"][:n_envs_sample], h, W["actor"], W["critic"],
+    t0, c0 = time.time(), time.process_time()
+    oracle_window_grads(W["model"], W["s0"][:n_envs_sample], h_sample, W["actor"], W["critic"],
                         n_total=W["n_envs"])
-    dt = time.time() - t0
+    dt, dc = time.time() - t0, time.process_time() - c0
     cpu = ""
     try:
         with open("/proc/cpuinfo") as fh:
             cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n_envs_sample * h / dt, "unit": "env-steps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle", "cpu": cpu, "nproc": os.cpu_count(),
-            "sample": f"{n_envs_sample} humanoid envs x h={h} frames (48 substeps each), fwd+reverse, "
-                      f"{dt:.1f} s wall"}
+    return {"value": n_envs_sample * h_sample / dt, "unit": "env-steps/s", "cores": round(dc / dt, 1),
+            "kind": "oracle", "cpu": cpu, "nproc": os.cpu_count(), "torch_threads": torch.get_num_threads(),
+            "sample": f"{n_envs_sample} humanoid envs of the headline batch x h={h_sample} frames (48 substeps "
+                      f"each), fwd+reverse, {dt:.1f} s wall; env-steps/s of the sample (the oracle's cost "
+                      f"is linear in frames)"}
 
 
 def main():
@@ -457,22 +463,37 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = N * h / (wall / args.steps)
 
-    # roofline of the dominant kernel (the adjoint window kernel)
-    f_sub, a_sub = substep_flops(md)
-    mlp_a = mlp_flops(actor_dims)
-    adj_flops_env_step = S * (f_sub + a_sub) + 2 * mlp_a + mlp_a     # re-linearise + reverse, MLP fwd + VJP
-    fwd_flops_env_step = S * f_sub + mlp_a
+    # roofline of the dominant kernel (the adjoint window kernel): counted algorithmic
+    # operations (ALGO_OPS) per env-step, without the recomputation of the forward
+    adj_flops_env_step = S * ALGO_OPS["substep_reverse"] + ALGO_OPS["frame_reverse"]
+    fwd_flops_env_step = S * ALGO_OPS["substep_forward"] + ALGO_OPS["frame_forward"]
     adj_launch_flops = adj_flops_env_step * N * h
     adj_avg_s = float(np.mean(adj_ms)) / 1e3
+    fwd_avg_s = float(np.mean(fwd_ms)) / 1e3
     achieved = adj_launch_flops / adj_avg_s / 1e12
+    fwd_achieved = fwd_flops_env_step * N * h / fwd_avg_s / 1e12
+    hbm = algorithmic_bytes(md, N, h, args.k, actor_dims)
+    step_s = wall / args.steps
     roof = {"bound": "alu", "kernel": "k_window_adj", "achieved": round(achieved, 4),
-            "peak": round(FP32_VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 5), "traffic": adjoint_traffic(N, args.k),
             "traffic_unit": "bytes per launch, profiler FETCH_SIZE + WRITE_SIZE scaled by a copy of known size",
-            "flops_per_env_step": {"adjoint_kernel": adj_flops_env_step, "forward_kernel": fwd_flops_env_step},
+            "flops_per_env_step": {"adjoint_kernel": adj_flops_env_step, "forward_kernel": fwd_flops_env_step,
+                                   "counted": "oracle recursive form (oracle/count_ops.py), no recompute"},
+            "frac_of_nonpacked_peak": round(achieved / FP32_VALU_NONPACKED_TFLOPS, 5),
+            "nonpacked_peak": round(FP32_VALU_NONPACKED_TFLOPS, 1),
+            "forward_kernel": {"achieved": round(fwd_achieved, 4), "frac": round(fwd_achieved / FP32_VALU_PEAK_TFLOPS, 5)},
             "oracle_ops_per_env_step": ORACLE_OPS_PER_ENV_STEP,
             "avg_ms": {"k_window_adj": round(float(np.mean(adj_ms)), 3),
                        "k_window_fwd": round(float(np.mean(fwd_ms)), 3)}}
+    # HBM: the window's algorithmic bytes over the step, and the adjoint kernel's counted bytes
+    hbm_out = {"algorithmic_bytes_per_env_step": hbm["per_env_step"], "what": hbm["what"],
+               "algorithmic_gbs": round(hbm["per_env_step"] * N * h / step_s / 1e9, 2),
+               "algorithmic_frac": round(hbm["per_env_step"] * N * h / step_s / 1e9 / HBM_PEAK_GBS, 6)}
+    if roof["traffic"] is not None:
+        hbm_out["adjoint_counter_gbs"] = round(roof["traffic"] / adj_avg_s / 1e9, 1)
+        hbm_out["adjoint_counter_frac"] = round(roof["traffic"] / adj_avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    roof["hbm"] = hbm_out
 
     n_eval = N * h * S * len(md["contact_body"])
     contacts = {"adhesive_frac": round(float(fw["adhesive_count"].double().sum()) / n_eval, 6),
@@ -567,8 +588,7 @@ def main():
                              "launches_per_step": 2 * (h * (S + 1) + 1),
                              "persistent_speedup": round(value / pval, 3),
                              "tape_speedup": round(tval / pval, 3)}
-        # the plain adjoint re-linearises each substep from its stored pre-state, like the
-        # persistent one: the same work per window
+        # the same algorithmic work per window as the persistent path
         plain_flops = (fwd_flops_env_step + adj_flops_env_step) * N * h
         plain_s = pw / args.plain_steps
         out["plain_path"]["achieved_tflops"] = round(plain_flops / plain_s / 1e12, 4)
@@ -582,8 +602,9 @@ def main():
 
     # measured device ceilings beside the published ones
     ceil = P.probe_ceilings()
-    out["ceilings"] = {"measured_fp32_valu_tflops": round(ceil["fp32_valu_tflops"], 2),
-                       "published_fp32_valu_tflops_nonpacked": round(FP32_VALU_PEAK_TFLOPS, 1),
+    out["ceilings"] = {"measured_fp32_valu_tflops_nonpacked": round(ceil["fp32_valu_tflops"], 2),
+                       "published_fp32_valu_tflops": FP32_VALU_PEAK_TFLOPS,
+                       "published_fp32_valu_tflops_nonpacked": round(FP32_VALU_NONPACKED_TFLOPS, 1),
                        "measured_copy_gbs": round(ceil["copy_gbs"], 1),
                        "published_hbm_gbs": HBM_PEAK_GBS}
     roof["frac_of_measured"] = round(achieved / ceil["fp32_valu_tflops"], 5)
@@ -621,7 +642,7 @@ def main():
                                                               / fw64["s_h"].abs().max()))}
         out["fd_directions"] = fd_directions(sim64, W, ad64, h)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, h)
+        out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
 
 

@@ -261,8 +261,14 @@ int sim_forward_window(SimHandle* h, const SimForwardIO* io, void* hip_stream);
 
 /* Reverse of the forward window: dL/da_t and dL/ds_0 of the actor loss and, when
  * dL_dtheta is given, the actor's parameter gradient (App. A.1).  The parameter gradient
- * re-evaluates the actor on the stored observations and contracts the layer adjoints with
- * the layer inputs over all h*N rows on the matrix cores. */
+ * takes the actor's hidden activations that the forward stored in the workspace for every
+ * frame and env, carries the action adjoint back through the layers and contracts the layer
+ * adjoints with the layer inputs over all h*N rows on the matrix cores.
+ * The adjoint reads what the matching forward left in the workspace (checkpoints, tape,
+ * hidden activations, termination flags): no other forward on the same handle and workspace
+ * may run between a window's forward and its adjoint, or the gradients are those of the
+ * other window.  Nothing here can detect that; the Python binding tags each forward and
+ * refuses an adjoint of a stale one. */
 int sim_adjoint_window(SimHandle* h, const SimAdjointIO* io, void* hip_stream);
 
 void sim_destroy(SimHandle* h);
@@ -401,6 +407,14 @@ int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_stream);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char* sim_last_error(void);
+
+/* ---- Layout of the ABI structures as this library was compiled, for bindings written in
+ * other languages to check their own declarations against: for the structure `which`, its
+ * size in bytes (field < 0) or the byte offset of its field-th member in declaration order
+ * (0-based).  Returns (size_t)-1 for an unknown structure or member index.  Pure host code. */
+enum { SIM_ABI_MODEL_DESC = 0, SIM_ABI_OPTIONS = 1, SIM_ABI_FORWARD_IO = 2, SIM_ABI_ADJOINT_IO = 3,
+       SIM_ABI_TUNE_RESULT = 4, SIM_ABI_CRITIC_FIT_IO = 5 };
+size_t sim_abi_layout(int which, int field);
 
 #ifdef __cplusplus
 }

@@ -119,5 +119,74 @@ def count_env_step(name="humanoid"):
             "uncounted_ops": sorted(set(cf.uncounted) | set(cr.uncounted))}
 
 
+def count_recursive_substep(name="humanoid"):
+    """Algorithmic operations of one substep of the recursive algorithms (``recursive``) and
+    of its adjoint by the implicit-function theorem, counted on one env.
+
+    forward: kinematics, velocities, contact forces, recursive Newton-Euler bias, composite-
+    rigid-body mass matrix, Cholesky factorisation and solve, semi-implicit Euler.
+    reverse: the integrator's reverse, lambda = M^{-1} q_ddot_bar by the two triangular solves
+    of the cached factor, inverse dynamics at the solved q_ddot on the forward's kinematics
+    (the accelerations and Newton-Euler forces the derivative needs), and its vector-Jacobian
+    product with lambda with respect to (q, q_dot, a) through kinematics, contacts, limits and
+    actuation.  Re-running the forward (recomputation from a checkpoint) is not counted: it is a
+    memory trade-off, not part of the algorithm."""
+    import workloads as wl
+    from .dynamics import OracleModel, integrate, joint_torques
+    from .recursive import inverse_dynamics, kinematics, substep_recursive
+    W = wl.workload(name, 1)
+    m = OracleModel(W["model"])
+    dt = m.dt / m.substeps
+    s = torch.as_tensor(W["s0"], dtype=torch.float64)
+    q0, qd0 = s[:, :m.nq].clone(), s[:, m.nq:m.nq + m.nv].clone()
+    a0 = torch.full((1, m.na), 0.3, dtype=torch.float64)
+    with OpCounter() as cf:
+        substep_recursive(m, q0, qd0, a0, dt)
+    q = q0.clone().requires_grad_(True)
+    qd = qd0.clone().requires_grad_(True)
+    a = a0.clone().requires_grad_(True)
+    with torch.no_grad():
+        _, qd_new0, qdd0, L = substep_recursive(m, q0, qd0, a0, dt)
+    qd_new = qd_new0.clone().requires_grad_(True)
+    q_new = integrate(m, q, qd_new, dt)
+    kin = kinematics(m, q, qd)
+    gq, gqd = torch.ones_like(q_new), torch.ones_like(qd_new)
+    cr = OpCounter()
+    with cr:
+        # integrator: q' = integrate(q, qd'), qd' = qd + dt qdd
+        bq, bqdn = torch.autograd.grad(q_new, [q, qd_new], gq, retain_graph=True)
+        bqdn = bqdn + gqd
+        qddbar = dt * bqdn
+        lam = torch.cholesky_solve(qddbar[..., None], L)[..., 0]
+        ID = inverse_dynamics(m, q, qd, qdd0, kin=kin) - joint_torques(m, q, a)
+        gq_id, gqd_id, _ = torch.autograd.grad(ID, [q, qd, a], -lam)
+        bq + gq_id, bqdn + gqd_id                    # the adjoints of the pre-substep state
+    return {"forward": cf.flops, "reverse": cr.flops, "nv": m.nv,
+            "uncounted_ops": sorted(set(cf.uncounted) | set(cr.uncounted))}
+
+
+def count_frame_level(name="humanoid"):
+    """Operations of the per-frame work of one env around the substeps: observation, actor
+    MLP, squash and reward (forward), and their reverse: the reward's and the observation's
+    vector-Jacobian products and the actor's input VJP (the policy feedback of App. A.1)."""
+    import workloads as wl
+    from .dynamics import OracleModel
+    from .window import _layers, mlp_forward, obs_fn, reward_fn, squash
+    W = wl.workload(name, 1)
+    m = OracleModel(W["model"])
+    s = torch.as_tensor(W["s0"], dtype=torch.float64).clone().requires_grad_(True)
+    act = _layers(W["actor"])
+    with OpCounter() as cf:
+        o = obs_fn(m, s)
+        a = squash(m, mlp_forward(act, o))
+        r = reward_fn(m, s, a)
+    with OpCounter() as cr:
+        torch.autograd.grad(r.sum() + (a * torch.ones_like(a)).sum(), [s])
+    return {"forward": cf.flops, "reverse": cr.flops,
+            "uncounted_ops": sorted(set(cf.uncounted) | set(cr.uncounted))}
+
+
 if __name__ == "__main__":
     print(count_env_step())
+    print(count_recursive_substep())
+    print(count_frame_level())

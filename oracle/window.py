@@ -136,6 +136,14 @@ def _layers(params):
     return [(_t(W), _t(b)) for (W, b) in params]
 
 
+def fp32_round(x):
+    """Each entry rounded to the nearest float32 value (round to nearest even), kept in
+    float64.  The derivative is taken as the identity (straight through), so that the
+    reverse pass of a rounded window is the FP64 adjoint along the rounded trajectory."""
+    r = x.detach().to(torch.float32).to(F64)
+    return x + (r - x).detach()
+
+
 def normalize_obs(o, obs_norm):
     """Observation normalisation with running statistics (Sec. 3.3): the networks read
     (o - mean) * inv_std; obs_norm = (mean, inv_std), or None for the raw observation."""
@@ -147,7 +155,7 @@ def normalize_obs(o, obs_norm):
 
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
                   keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None,
-                  reset_states=None, obs_norm=None, diagnostics=True):
+                  reset_states=None, obs_norm=None, diagnostics=True, fp32_floor=False):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
@@ -165,6 +173,13 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     returned obs stay raw.
     diagnostics: also count, per env, the contact evaluations whose normal force pulls
     ("adhesive"); off when only the method's own arithmetic should run.
+    fp32_floor: the FP32 storage floor.  The initial states and the network weights are
+    rounded to float32 on entry, every action when it is formed, and the dynamic state
+    (q, qd and the muscle activations) after every substep; all arithmetic stays FP64.  It
+    measures how far the window alone carries the rounding of the state that any FP32
+    simulator stores (the intrinsic sensitivity floor of an FP32 window).  Off, nothing
+    changes.
+    The result holds the loss and, in loss_env [B], each env's term of it.
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
     s = s0 if torch.is_tensor(s0) else _t(s0)
@@ -174,6 +189,11 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         layers = (_layers(actor) if actor is not None else None,
                   _layers(critic) if critic is not None else None)
     act_l, crit_l = layers
+    if fp32_floor:
+        s = fp32_round(s)
+        act_l = [(fp32_round(W), fp32_round(b)) for (W, b) in act_l] if act_l is not None else None
+        crit_l = [(fp32_round(W), fp32_round(b)) for (W, b) in crit_l] if crit_l is not None else None
+    rnd = fp32_round if fp32_floor else (lambda x: x)
     nq, nv = m.nq, m.nv
     dt = m.dt / m.substeps
     mlp = mlp_forward_bf16 if bf16 else mlp_forward
@@ -192,6 +212,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
             a = squash(m, y)
         else:
             a = actions[t] if torch.is_tensor(actions[t]) else _t(actions[t])
+        a = rnd(a)
         if action_offset is not None:
             a = a + _t(action_offset[t])
         if keep_graph and not a.requires_grad:
@@ -202,10 +223,12 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
             act = s[:, nq + nv:nq + nv + m.n_mtu]
             for _ in range(m.substeps):
                 q, qd, act = substep(m, q, qd, a, dt, act, stats=adh)
+                q, qd, act = rnd(q), rnd(qd), rnd(act)
             s = torch.cat([q, qd, act], 1)
         else:
             for _ in range(m.substeps):
                 q, qd = substep(m, q, qd, a, dt, stats=adh)
+                q, qd = rnd(q), rnd(qd)
             s = torch.cat([q, qd, a], 1) if m.md["has_last_action"] else torch.cat([q, qd], 1)
         if term_h is not None:
             done = s[:, 2] < term_h
@@ -223,21 +246,25 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     if term_h is None:
         disc = sum(gamma ** t * rews[t] for t in range(h))
         loss = -(disc + gamma ** h * value).sum() / (N * h)
+        loss_env = -(disc + gamma ** h * value) / (N * h)
         done_out = None
     else:
         disc = sum(torch.pow(gamma, (t - segs[t]).to(F64)) * rews[t] for t in range(h))
         live = (~dones[-1]).to(F64)
         loss = -(disc + live * torch.pow(gamma, (h - t0).to(F64)) * value).sum() / (N * h)
+        loss_env = -(disc + live * torch.pow(gamma, (h - t0).to(F64)) * value) / (N * h)
         done_out = torch.stack(dones)
     adhesive = torch.stack(adh).sum(0) if adh else torch.zeros(B, dtype=torch.long)
     return dict(states=states, obs=obs, actions=acts, rewards=rews, value=value, loss=loss,
-                layers=layers, done=done_out, adhesive=adhesive)
+                loss_env=loss_env, layers=layers, done=done_out, adhesive=adhesive)
 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
                         n_total=None, want_theta=False, bf16=False, noise=None, log_std=None,
-                        reset_states=None, obs_norm=None):
+                        reset_states=None, obs_norm=None, fp32_floor=False):
     """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
+    fp32_floor: as for oracle_window (the FP32 storage floor); the gradients are then the
+    FP64 adjoint along the rounded trajectory.
 
     Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
     value [B], loss, dL/da [h,B,na], dL/ds0 [B,n_s] and, if asked, dL/dtheta as a
@@ -257,7 +284,7 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
         ls = _t(log_std).clone().requires_grad_(want_theta)
     out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
                         layers=layers, bf16=bf16, noise=noise, log_std=ls, reset_states=reset_states,
-                        obs_norm=obs_norm)
+                        obs_norm=obs_norm, fp32_floor=fp32_floor)
     wrt = [s0t] + list(out["actions"])
     theta = []
     if want_theta and actor is not None:
@@ -277,6 +304,7 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
         rewards=torch.stack(out["rewards"]).detach().numpy(),
         value=out["value"].detach().numpy(),
         loss=float(out["loss"].detach()),
+        loss_env=out["loss_env"].detach().numpy(),
         dL_da=ga.detach().numpy(),
         dL_ds0=gs0.detach().numpy(),
     )

@@ -80,7 +80,7 @@ EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window"
            "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
            "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy", "sim_adam_step",
            "sim_soft_update", "sim_td_lambda", "sim_critic_workspace_bytes", "sim_critic_values",
-           "sim_critic_fit", "sim_obs_stats_update"]
+           "sim_critic_fit", "sim_obs_stats_update", "sim_abi_layout"]
 MAX_GROUP = 6
 
 _LIB = None
@@ -144,6 +144,8 @@ def lib():
         L.sim_critic_fit.restype = _i
         L.sim_obs_stats_update.argtypes = [_p, ctypes.c_long, _i, _d, _p, _p, _p, _d, _i, _p]
         L.sim_obs_stats_update.restype = _i
+        L.sim_abi_layout.argtypes = [_i, _i]
+        L.sim_abi_layout.restype = ctypes.c_size_t
         _LIB = L
     return _LIB
 
@@ -257,6 +259,13 @@ class Sim:
         self.N, self.H = int(n_envs), int(horizon)
         self.ws_bytes = int(L.sim_workspace_bytes(h))
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+        # serial number of the last forward enqueued on this handle's workspace: an adjoint
+        # reads what its own forward left there, so it is refused once another forward ran
+        self._fwd_serial = 0
+
+    def _stamp(self, out):
+        self._fwd_serial += 1
+        out["_serial"] = self._fwd_serial
 
     def critic_workspace(self, rows):
         """A device workspace for critic_values / critic_fit on up to `rows` rows."""
@@ -354,6 +363,7 @@ class Sim:
         t = self.torch
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
+        self._stamp(out)
         return out
 
     def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None, noise=None, log_std=None,
@@ -445,7 +455,12 @@ class Sim:
 
     def adjoint_io(self, fw, actor=None, critic=None, grad_s_h=None, loss_scale=None, want_theta=False,
                    out=None):
-        """Allocate the adjoint outputs (or reuse those of `out`) and fill a SimAdjointIO."""
+        """Allocate the adjoint outputs (or reuse those of `out`) and fill a SimAdjointIO.
+        Raises if fw is not the result of the last forward run on this handle (the workspace
+        then holds another window's checkpoints and activations)."""
+        if fw.get("_serial") != self._fwd_serial:
+            raise RuntimeError("adjoint of a stale forward: another forward ran on this handle since "
+                               "(its workspace holds that window); run the forward again first")
         t = self.torch
         N, H = self.N, self.H
         dt = self.dtype
@@ -548,6 +563,8 @@ class Group:
         arr = (SimForwardIO * len(ios))(*ios)
         st = stream if stream is not None else self.torch.cuda.current_stream()
         _check(lib().sim_group_forward(self.g, arr, _p(st.cuda_stream)))
+        for sim, o in zip(self.sims, outs):
+            sim._stamp(o)
         self._fw = outs
         return outs
 

@@ -3,10 +3,11 @@
 #include <math.h>
 #include "sim_types.h"
 
-// FP64 path: every model runs the padded 32-DOF kernel
-// DOF counts of muscle-driven models with a kernel of their own (the humanoid skeleton)
-#define SIM_NV_LIST_MTU(X)
-#define SIM_NV_LIST(X)
+// DOF counts compiled as kernels of their own: the humanoid's 27, for torque and muscle
+// models, so that the FP64 parity runs cover the DOF-specialised kernel of the production
+// path; every other model runs the padded 32-DOF kernel
+#define SIM_NV_LIST_MTU(X) X(27)
+#define SIM_NV_LIST(X) X(27)
 
 namespace sim_f64 {
 typedef double real;

@@ -39,8 +39,9 @@ struct SimHandle {
   size_t bf_actor_off[SIM_MAXL][2], bf_critic_off[SIM_MAXL][2];   // BF16 forward / adjoint tiles
   size_t off_ckpt = 0, off_adj = 0, off_tape = 0, off_done = 0, off_seg = 0, off_hid = 0, ws_bytes = 0;
   int hid_w = 0;   // the actor's hidden widths, summed (closed loop)
-  // policy-gradient scratch: hidden activations, two layer-adjoint buffers, split partials
-  size_t off_th_h[SIM_MAXL], off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
+  // policy-gradient scratch: two layer-adjoint buffers, split partials (the hidden
+  // activations are the window's own, at off_hid)
+  size_t off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
   int th_splits = 0;
   int n_ckpt = 0;
   int device = -1;
@@ -48,6 +49,88 @@ struct SimHandle {
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- ABI layout
+// Byte offsets of the members of the ABI structures, in declaration order, as compiled here.
+static const size_t kLayoutSimModelDesc[] = {
+    offsetof(SimModelDesc, n_joints), offsetof(SimModelDesc, parent), offsetof(SimModelDesc, jtype),
+    offsetof(SimModelDesc, offset), offsetof(SimModelDesc, axis), offsetof(SimModelDesc, mass),
+    offsetof(SimModelDesc, com), offsetof(SimModelDesc, inertia), offsetof(SimModelDesc, limited),
+    offsetof(SimModelDesc, lower), offsetof(SimModelDesc, upper), offsetof(SimModelDesc, n_act),
+    offsetof(SimModelDesc, act_joint), offsetof(SimModelDesc, gear), offsetof(SimModelDesc, armature),
+    offsetof(SimModelDesc, n_contacts), offsetof(SimModelDesc, contact_body),
+    offsetof(SimModelDesc, contact_pos), offsetof(SimModelDesc, contact_radius),
+    offsetof(SimModelDesc, gravity), offsetof(SimModelDesc, kn), offsetof(SimModelDesc, kd),
+    offsetof(SimModelDesc, kt), offsetof(SimModelDesc, mu), offsetof(SimModelDesc, klim),
+    offsetof(SimModelDesc, dt), offsetof(SimModelDesc, substeps), offsetof(SimModelDesc, task),
+    offsetof(SimModelDesc, has_last_action), offsetof(SimModelDesc, n_mtu), offsetof(SimModelDesc, mtu_npt),
+    offsetof(SimModelDesc, mtu_body), offsetof(SimModelDesc, mtu_pos), offsetof(SimModelDesc, mtu_fmax),
+    offsetof(SimModelDesc, mtu_lopt), offsetof(SimModelDesc, mtu_lslack), offsetof(SimModelDesc, tau_act),
+    offsetof(SimModelDesc, fl_width), offsetof(SimModelDesc, vmax), offsetof(SimModelDesc, term_enabled),
+    offsetof(SimModelDesc, term_height),
+};
+static const size_t kLayoutSimOptions[] = {
+    offsetof(SimOptions, n_envs), offsetof(SimOptions, horizon), offsetof(SimOptions, ckpt_interval),
+    offsetof(SimOptions, path), offsetof(SimOptions, closed_loop), offsetof(SimOptions, actor_layers),
+    offsetof(SimOptions, actor_dims), offsetof(SimOptions, critic_layers), offsetof(SimOptions, critic_dims),
+    offsetof(SimOptions, gamma), offsetof(SimOptions, precision), offsetof(SimOptions, chol_fp64_threshold),
+    offsetof(SimOptions, policy_grad), offsetof(SimOptions, mlp_precision),
+};
+static const size_t kLayoutSimForwardIO[] = {
+    offsetof(SimForwardIO, s0), offsetof(SimForwardIO, actions_in), offsetof(SimForwardIO, actor_w),
+    offsetof(SimForwardIO, actor_b), offsetof(SimForwardIO, critic_w), offsetof(SimForwardIO, critic_b),
+    offsetof(SimForwardIO, workspace), offsetof(SimForwardIO, workspace_bytes), offsetof(SimForwardIO, s_h),
+    offsetof(SimForwardIO, obs), offsetof(SimForwardIO, actions), offsetof(SimForwardIO, rewards),
+    offsetof(SimForwardIO, value), offsetof(SimForwardIO, nonfinite),
+    offsetof(SimForwardIO, fp64_refactor_count), offsetof(SimForwardIO, noise),
+    offsetof(SimForwardIO, log_std), offsetof(SimForwardIO, reset_states), offsetof(SimForwardIO, done),
+    offsetof(SimForwardIO, obs_mean), offsetof(SimForwardIO, obs_inv_std),
+    offsetof(SimForwardIO, adhesive_count), offsetof(SimForwardIO, loss_env), offsetof(SimForwardIO, loss),
+};
+static const size_t kLayoutSimAdjointIO[] = {
+    offsetof(SimAdjointIO, s0), offsetof(SimAdjointIO, actions), offsetof(SimAdjointIO, obs),
+    offsetof(SimAdjointIO, s_h), offsetof(SimAdjointIO, actor_w), offsetof(SimAdjointIO, actor_b),
+    offsetof(SimAdjointIO, critic_w), offsetof(SimAdjointIO, critic_b), offsetof(SimAdjointIO, workspace),
+    offsetof(SimAdjointIO, workspace_bytes), offsetof(SimAdjointIO, grad_s_h),
+    offsetof(SimAdjointIO, loss_scale), offsetof(SimAdjointIO, dL_da), offsetof(SimAdjointIO, dL_ds0),
+    offsetof(SimAdjointIO, dL_dtheta), offsetof(SimAdjointIO, noise), offsetof(SimAdjointIO, log_std),
+    offsetof(SimAdjointIO, dL_dlog_std), offsetof(SimAdjointIO, obs_mean),
+    offsetof(SimAdjointIO, obs_inv_std),
+};
+static const size_t kLayoutSimTuneResult[] = {
+    offsetof(SimTuneResult, path), offsetof(SimTuneResult, ckpt_interval),
+    offsetof(SimTuneResult, workspace_bytes), offsetof(SimTuneResult, ms_window),
+    offsetof(SimTuneResult, n_candidates),
+};
+static const size_t kLayoutSimCriticFitIO[] = {
+    offsetof(SimCriticFitIO, obs), offsetof(SimCriticFitIO, targets), offsetof(SimCriticFitIO, rows),
+    offsetof(SimCriticFitIO, perm), offsetof(SimCriticFitIO, n_iter), offsetof(SimCriticFitIO, n_minibatch),
+    offsetof(SimCriticFitIO, critic_w), offsetof(SimCriticFitIO, critic_b), offsetof(SimCriticFitIO, adam_m),
+    offsetof(SimCriticFitIO, adam_v), offsetof(SimCriticFitIO, adam_step), offsetof(SimCriticFitIO, lr),
+    offsetof(SimCriticFitIO, beta1), offsetof(SimCriticFitIO, beta2), offsetof(SimCriticFitIO, eps),
+    offsetof(SimCriticFitIO, loss_out), offsetof(SimCriticFitIO, workspace),
+    offsetof(SimCriticFitIO, workspace_bytes), offsetof(SimCriticFitIO, obs_mean),
+    offsetof(SimCriticFitIO, obs_inv_std),
+};
+
+extern "C" size_t sim_abi_layout(int which, int field) {
+  const size_t* tab = nullptr;
+  size_t n = 0, size = 0;
+#define SIM_LAYOUT_CASE(id, S) \
+  case id: tab = kLayout##S; n = sizeof(kLayout##S) / sizeof(size_t); size = sizeof(S); break;
+  switch (which) {
+    SIM_LAYOUT_CASE(SIM_ABI_MODEL_DESC, SimModelDesc)
+    SIM_LAYOUT_CASE(SIM_ABI_OPTIONS, SimOptions)
+    SIM_LAYOUT_CASE(SIM_ABI_FORWARD_IO, SimForwardIO)
+    SIM_LAYOUT_CASE(SIM_ABI_ADJOINT_IO, SimAdjointIO)
+    SIM_LAYOUT_CASE(SIM_ABI_TUNE_RESULT, SimTuneResult)
+    SIM_LAYOUT_CASE(SIM_ABI_CRITIC_FIT_IO, SimCriticFitIO)
+    default: return (size_t)-1;
+  }
+#undef SIM_LAYOUT_CASE
+  if (field < 0) return size;
+  return (size_t)field < n ? tab[field] : (size_t)-1;
+}
 
 extern "C" const char* sim_last_error(void) { return g_err.c_str(); }
 
@@ -396,14 +479,9 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
     for (int l = 1; l < opt->actor_layers; ++l) h->hid_w += opt->actor_dims[l];
   h->off_hid = off;
   off = align256(off + e * (size_t)opt->horizon * N * h->hid_w);
-  for (int l = 0; l < SIM_MAXL; ++l) h->off_th_h[l] = 0;
   if (opt->policy_grad) {
     const size_t rows = N * (size_t)opt->horizon;
     size_t maxw = 0, maxpart = 0;
-    for (int l = 1; l < opt->actor_layers; ++l) {
-      h->off_th_h[l] = off;
-      off = align256(off + e * rows * opt->actor_dims[l]);
-    }
     for (int l = 0; l < opt->actor_layers; ++l) {
       maxw = std::max(maxw, (size_t)opt->actor_dims[l + 1]);
       maxpart = std::max(maxpart, (size_t)opt->actor_dims[l + 1] * (opt->actor_dims[l] + 1));
@@ -597,7 +675,6 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
     off += (long)o.actor_dims[l] * o.actor_dims[l + 1];
     P.off_b[l] = off;
     off += o.actor_dims[l + 1];
-    if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + h->off_th_h[l]);
   }
   P.x0 = static_cast<const T*>(io->obs);
   P.x_shift = static_cast<const T*>(io->obs_mean);
@@ -609,8 +686,9 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
   P.part = reinterpret_cast<T*>(ws + h->off_th_part);
   P.out = static_cast<T*>(io->dL_dtheta);
   // the gradient is taken at the activations the window itself computed (stored by the
-  // forward), rows (t, env) as the observations' (handles with BF16 MLPs have no dL/dtheta)
-  if (o.mlp_precision != SIM_MLP_BF16 && h->hid_w > 0) {
+  // forward), rows (t, env) as the observations' (handles with BF16 MLPs have no dL/dtheta,
+  // and an actor without hidden layers has none to store)
+  if (h->hid_w > 0) {
     T* hid = reinterpret_cast<T*>(ws + h->off_hid);
     long off_l = 0;
     for (int l = 1; l < o.actor_layers; ++l) {

@@ -1,9 +1,11 @@
 // Policy-parameter gradient of the short-horizon actor loss (App. A.1, the dL/dtheta
 // term): given dL/da_t of every environment and frame, the gradient is the sum over all
-// h*N (frame, env) rows of (d pi(o_t) / d theta)^T dL/da_t.  The actor is re-evaluated on
-// the observations the forward window stored, the action adjoint is carried back through
-// tanh and every ELU layer, and the weight gradient of a layer is the contraction of its
-// output adjoint with its input over all rows.
+// h*N (frame, env) rows of (d pi(o_t) / d theta)^T dL/da_t.  The layer inputs are the
+// observations and the hidden activations that the forward window stored for every frame
+// and env; the action adjoint is carried back through the squash and every ELU layer, and
+// the weight gradient of a layer is the contraction of its output adjoint with its input
+// over all rows.  The critic's calls (values, minibatch fit) use the same kernels and
+// compute their hidden layers as GEMMs with a fused bias + ELU epilogue.
 //
 // Every contraction runs on the matrix cores: 32x64 output tiles staged through LDS in
 // K-slices of 32, four wavefronts per tile, each wavefront a 1x2 block of 16x16x4 MFMA

@@ -163,3 +163,21 @@ def test_binding_structs_match_the_header(struct):
     """The ctypes structures of the binding declare the C structs' members in the same order
     (a mismatch would shift every later field of a call)."""
     assert [f[0] for f in getattr(P, struct)._fields_] == _header_members(struct)
+
+
+ABI_IDS = {"SimModelDesc": 0, "SimOptions": 1, "SimForwardIO": 2, "SimAdjointIO": 3, "SimTuneResult": 4,
+           "SimCriticFitIO": 5}
+
+
+@pytest.mark.parametrize("struct", sorted(ABI_IDS))
+def test_binding_struct_sizes_and_offsets_match_the_library(struct):
+    """Byte size and every member's byte offset of the binding's ctypes structures equal those
+    the library was compiled with (sim_abi_layout): a changed member type would move them."""
+    L = P.lib()
+    cls = getattr(P, struct)
+    sid = ABI_IDS[struct]
+    assert ctypes.sizeof(cls) == L.sim_abi_layout(sid, -1)
+    for i, (name, _) in enumerate(cls._fields_):
+        assert getattr(cls, name).offset == L.sim_abi_layout(sid, i), (struct, name)
+    assert L.sim_abi_layout(sid, len(cls._fields_)) == ctypes.c_size_t(-1).value
+    assert L.sim_abi_layout(99, 0) == ctypes.c_size_t(-1).value

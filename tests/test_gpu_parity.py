@@ -8,12 +8,17 @@ Tolerances
   amplified by the window's sensitivity, which the oracle itself measures: ~1e3..1e4 for
   the Ant window and up to ~1e7 for the Humanoid (contact-rich, random policy, 1536
   substeps).  Bounds: CartPole 1e-12, Ant 1e-9, Humanoid 1e-6 (relative norm).
-* FP32 production path: states within 1e-4 relative and gradients with cosine >= 0.999
-  and relative norm error <= 1e-3 against FP64, on windows short enough that FP32
-  rounding, amplified by the dynamics, stays below those bounds (CartPole h = 32, Ant
-  h = 8, Humanoid h = 4).  Over the full h = 32 window the FP32 error of the contact-rich
-  tasks reaches the FP32 sensitivity floor of the dynamics and is reported by bench.py
-  against the FP64 kernels instead of being asserted here.
+* FP32 production path against the oracle: states within 1e-4 relative and gradients with
+  cosine >= 0.999 and relative norm error <= 1e-3, on windows short enough that FP32 storage
+  rounding, amplified by the dynamics, stays below those bounds.  For the humanoid that
+  horizon is measured by the oracle alone (tests/golden/fp32_floor.json: the oracle's window
+  with its state rounded to float32 after every substep, against the plain FP64 window, on
+  the 8 envs of the headline batch drawn with seed 4): the longest window on which every one
+  of those envs stays under the bar.  CartPole runs the full window; Ant h = 8.
+* FP32 over the full headline window (humanoid, N = 1024, h = 32, k = 4): the storage floor
+  there is far above the bar (the contact-rich closed loop amplifies a 6e-8 change to O(1)),
+  so no FP32 path can meet it; the test asserts instead that the FP32 kernels' error against
+  the FP64 kernels is that of FP32 storage and no larger (criterion in the test).
 * Checkpoint intervals, the plain per-step path and single-env launches are compared
   bitwise (same kernels, same order of operations).
 """
@@ -44,6 +49,18 @@ def state_rel(x, y):
     return float((np.abs(x - y).max(-1) / np.abs(y).max(-1)).max())
 
 
+def _floor():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fp32_floor.json")) as fh:
+        return json.load(fh)
+
+
+FLOOR = _floor()
+HUM_ENVS = FLOOR["humanoid"]["envs"]          # the 8 envs of the headline batch drawn with seed 4
+HUM_H32 = FLOOR["humanoid"]["h_max_under_bar"]
+
+
 def make_sim(W, h, k=None, path=P.PATH_PERSISTENT, precision="fp32", closed_loop=True):
     od = W["obs_dim"]
     actor_dims = [od] + [w.shape[0] for w, _ in W["actor"]] if closed_loop else None
@@ -64,7 +81,7 @@ def run(W, h, actions_in=None, **kw):
 
 FULL = [("cartpole", 16, None, list(range(16)), 1e-12),
         ("ant", 1024, 16, [0, 517], 1e-9),
-        ("humanoid", 1024, 16, [3], 1e-6)]
+        ("humanoid", 1024, 16, HUM_ENVS, 1e-6)]
 
 
 @pytest.mark.parametrize("name,N,k,envs,tol", FULL, ids=[c[0] for c in FULL])
@@ -86,11 +103,14 @@ def test_fp64_kernels_match_oracle_full_window(name, N, k, envs, tol):
 
 SHORT = [("cartpole", 16, 32, None, list(range(16))),
          ("ant", 1024, 8, 16, [0, 517]),
-         ("humanoid", 1024, 4, 16, [3])]
+         ("humanoid", 1024, HUM_H32, 4, HUM_ENVS)]
 
 
 @pytest.mark.parametrize("name,N,h,k,envs", SHORT, ids=[c[0] for c in SHORT])
 def test_fp32_kernels_match_oracle(name, N, h, k, envs):
+    """The FP32 path at the benchmark's launch configuration (humanoid: N = 1024, k = 4)
+    against the FP64 oracle: every sampled env's state, and the gradients of the sampled envs
+    together, at the spec bar."""
     W = wl.workload(name, N)
     print(f"[fp32] {name} N={N} h={h} k={k} envs={envs}", flush=True)
     _, fw, ad = run(W, h, k=k)

@@ -40,3 +40,28 @@ def test_humanoid_env_step_count_matches_bench():
     assert not got["uncounted_ops"], got["uncounted_ops"]
     assert got["forward"] == bench.ORACLE_OPS_PER_ENV_STEP["forward"]
     assert got["reverse"] == bench.ORACLE_OPS_PER_ENV_STEP["reverse"]
+
+
+def test_recursive_substep_counts_match_bench():
+    """The algorithmic operation counts of one humanoid substep (recursive algorithms) and of
+    its implicit-function adjoint, and of the per-frame work around the substeps, that the
+    benchmark's roofline uses."""
+    import bench
+    from oracle.count_ops import count_frame_level, count_recursive_substep
+    sub = count_recursive_substep("humanoid")
+    fr = count_frame_level("humanoid")
+    assert not sub["uncounted_ops"] and not fr["uncounted_ops"]
+    assert (sub["forward"], sub["reverse"]) == (bench.ALGO_OPS["substep_forward"], bench.ALGO_OPS["substep_reverse"])
+    assert (fr["forward"], fr["reverse"]) == (bench.ALGO_OPS["frame_forward"], bench.ALGO_OPS["frame_reverse"])
+
+
+def test_recursive_counts_scale_like_the_textbook():
+    """The counts grow as the algorithms do: the Cholesky factorisation's n^3 / 3 and the two
+    solves' 2 n^2 are inside the forward count, and the substep costs more with more bodies,
+    DOFs and contacts (CartPole < Ant < Humanoid)."""
+    from oracle.count_ops import count_recursive_substep
+    c = {n: count_recursive_substep(n) for n in ("cartpole", "ant", "humanoid")}
+    assert c["cartpole"]["forward"] < c["ant"]["forward"] < c["humanoid"]["forward"]
+    assert c["cartpole"]["reverse"] < c["ant"]["reverse"] < c["humanoid"]["reverse"]
+    n = c["humanoid"]["nv"]
+    assert c["humanoid"]["forward"] > n ** 3 // 3 + 2 * n * n

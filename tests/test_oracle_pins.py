@@ -538,14 +538,6 @@ def test_policy_weight_fd_like_paper_check():
         assert abs(fd - an) <= 1e-6 * abs(fd) + floor, (li, idx, fd, an)
 
 
-def test_window_adjoint_fd_humanoid_short():
-    W = wl.workload("humanoid", 1024)
-    h = 1
-    coords_a = [(0, 0, 0), (0, 0, 7), (0, 0, 20)]
-    coords_s = [(0, 2), (0, 9), (0, 40), (0, 60)]
-    _fd_check(W, h, [5], coords_a, coords_s, 1e-6, 1e-5)
-
-
 def test_window_adjoint_fd_open_loop_ant():
     W = wl.workload("ant", 64)
     h = 2
@@ -938,3 +930,196 @@ def test_adhesive_contact_count_threshold():
         stats = []
         substep(m, q, qd, a, m.dt / m.substeps, stats=stats)
         assert int(stats[0][0]) == want, (vz, int(stats[0][0]))
+
+
+# ------------------------------------------------------------------ observation tables, value by value
+
+def _obs_tables():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "obs_tables.json")))
+
+
+def _blocks(rows):
+    """Start index and width of every row of an observation table."""
+    out, i = {}, 0
+    for name, n in rows:
+        out[name] = (i, n)
+        i += n
+    return out, i
+
+
+def test_cartpole_obs_entries_follow_the_table():
+    """Every entry of the CartPole observation on a hand-built state, in the order and with
+    the widths of App. A.3's table: x, x_dot, (sin theta, cos theta), theta_dot."""
+    blk, n = _blocks(_obs_tables()["cartpole"]["rows"])
+    m = OracleModel(wl.cartpole())
+    x, th, xd, thd = 0.3, 2.0, -0.7, 1.9
+    o = obs_fn(m, T([[x, th, xd, thd]]))[0].numpy()
+    assert o.shape == (n,)
+    want = {"cart_position": [x], "cart_velocity": [xd], "sin_cos_pole_angle": [np.sin(th), np.cos(th)],
+            "pole_angular_velocity": [thd]}
+    for name, (i, w) in blk.items():
+        assert np.array_equal(o[i:i + w], np.asarray(want[name])), name
+
+
+@pytest.mark.parametrize("name", ["ant", "humanoid"])
+def test_floating_base_obs_entries_follow_the_table(name):
+    """Every entry of the Ant / Humanoid observation on a hand-built state with distinct
+    values, block by block as App. A.3's table lists them.  The root is turned by
+    Rz(alpha) Rx(beta), so the up projection (body z on world z) is cos(beta) and the heading
+    projection (body x on world x) is cos(alpha), in closed form."""
+    tab = _obs_tables()[name]
+    blk, n = _blocks(tab["rows"])
+    W = wl.workload(name, 1)
+    md = W["model"]
+    m = OracleModel(md)
+    nq, nv, na = m.nq, m.nv, m.na
+    nh = nq - 7
+    alpha, beta = 0.7, 0.4
+    ca, sa, cb, sb = np.cos(alpha / 2), np.sin(alpha / 2), np.cos(beta / 2), np.sin(beta / 2)
+    quat = [ca * cb, ca * sb, sa * sb, sa * cb]
+    pos = [1.5, -2.5, 0.9]
+    hinge = 0.01 * (np.arange(nh) + 1)
+    vlin, vang = [0.11, 0.22, 0.33], [-0.44, 0.55, -0.66]
+    hvel = -0.1 * (np.arange(nh) + 1)
+    aprev = 0.5 - 0.03 * np.arange(na)
+    s = np.concatenate([pos, quat, hinge, vlin, vang, hvel, aprev])[None]
+    o = obs_fn(m, T(s))[0].numpy()
+    assert o.shape == (n,)
+    want = {"base_height": [pos[2]], "torso_height": [pos[2]],
+            "base_quaternion": quat, "torso_quaternion": quat,
+            "base_linear_velocity": vlin, "torso_linear_velocity": vlin,
+            "base_angular_velocity": vang, "torso_angular_velocity": vang,
+            "joint_angles": hinge, "joint_velocities": hvel,
+            "up_heading": [np.cos(beta), np.cos(alpha)], "last_actions": aprev}
+    for row, (i, w) in blk.items():
+        np.testing.assert_allclose(o[i:i + w], np.asarray(want[row]), rtol=0, atol=1e-15, err_msg=row)
+
+
+# ------------------------------------------------------------------ humanoid window adjoint vs FD, 8 envs
+
+def test_window_adjoint_fd_humanoid_eight_envs_every_coordinate():
+    """Central differences (eps 1e-6) of each env's loss term over a 4-frame humanoid window
+    (App. A.5's finite-difference check), on the 8 envs of the headline batch drawn with seed 4:
+    every action coordinate of every frame and every initial-state coordinate except the root
+    quaternion, against the reverse-mode dL/da and dL/ds0.  The envs are independent, so all
+    the perturbed windows run as one batch of copies and each copy's own loss term is read.
+    The window is piecewise smooth (a contact switches on at the first substep it penetrates),
+    so a pair whose +-eps interval holds such a switch is not differentiable there; those pairs
+    (at most 1 % of them) are differenced again at eps / 10, where the switch falls outside."""
+    W = wl.workload("humanoid", 1024)
+    md, N, h, eps = W["model"], 1024, 4, 1e-6
+    envs = np.sort(np.random.default_rng(4).choice(N, 8, replace=False))
+    s0 = W["s0"][envs]
+    E, ns, na = len(envs), s0.shape[1], md["na"]
+    g = oracle_window_grads(md, s0, h, W["actor"], W["critic"], n_total=N)
+    coords = [("a", t, k) for t in range(h) for k in range(na)] + [("s", k) for k in range(ns) if not 3 <= k < 7]
+    m = OracleModel(md)
+    lay = ([(T(Wt), T(b)) for Wt, b in W["actor"]], [(T(Wt), T(b)) for Wt, b in W["critic"]])
+
+    def central(pairs, step):
+        """Central differences of the env's loss term for (coordinate index, env index) pairs."""
+        S0 = np.repeat(s0[[e for _, e in pairs]], 2, 0)
+        DA = np.zeros((h, 2 * len(pairs), na))
+        for i, (c, _) in enumerate(pairs):
+            co = coords[c]
+            for sg, sign in enumerate((1.0, -1.0)):
+                if co[0] == "a":
+                    DA[co[1], 2 * i + sg, co[2]] = sign * step
+                else:
+                    S0[2 * i + sg, co[1]] += sign * step
+        le = []
+        chunk = 512
+        for i in range(0, S0.shape[0], chunk):
+            out = oracle_window(m, T(S0[i:i + chunk]), h, n_total=N, layers=lay,
+                                action_offset=DA[:, i:i + chunk], diagnostics=False)
+            le.append(out["loss_env"].numpy())
+        le = np.concatenate(le).reshape(len(pairs), 2)
+        return (le[:, 0] - le[:, 1]) / (2 * step)
+
+    pairs = [(c, e) for c in range(len(coords)) for e in range(E)]
+    an = np.array([g["dL_da"][coords[c][1], e, coords[c][2]] if coords[c][0] == "a" else g["dL_ds0"][e, coords[c][1]]
+                   for c, e in pairs])
+    L0 = np.abs(oracle_window(m, T(s0), h, n_total=N, layers=lay, diagnostics=False)["loss_env"].numpy())
+    L0p = np.array([L0[e] for _, e in pairs])
+    fd = central(pairs, eps)
+    bad = np.abs(fd - an) > 1e-5 * np.abs(fd) + 50 * 2.2e-16 * L0p / eps
+    assert bad.mean() <= 0.01, bad.sum()
+    redo = [p for p, b in zip(pairs, bad) if b]
+    if redo:
+        fd2 = central(redo, eps / 10)
+        an2, L2 = an[bad], L0p[bad]
+        still = np.abs(fd2 - an2) > 1e-5 * np.abs(fd2) + 50 * 2.2e-16 * L2 / (eps / 10)
+        assert not still.any(), [(coords[c], int(envs[e]), f, a) for (c, e), f, a, s in zip(redo, fd2, an2, still) if s]
+    assert np.abs(an).max() > 0 and (np.abs(an) > 0).mean() > 0.9
+
+
+# ------------------------------------------------------------------ recursive form vs defining form
+
+@pytest.mark.parametrize("name", ["cartpole", "ant", "humanoid"])
+def test_recursive_algorithms_equal_the_defining_form(name):
+    """The composite-rigid-body mass matrix and the recursive Newton-Euler inverse dynamics
+    equal the defining sums over bodies (M = sum J^T I J, b = sum J^T (I (Jdot qd - a_g) +
+    V x* I V), contacts through point Jacobians) on random states with penetrating contacts,
+    and a recursive substep equals the oracle's substep, to rounding."""
+    from oracle import recursive as RC
+    W = wl.workload(name, 4)
+    m = OracleModel(W["model"])
+    rng = np.random.default_rng(11)
+    q = T(W["s0"])[:, :m.nq].clone()
+    if name != "cartpole":
+        q[:, 7:] += T(rng.normal(0, 0.3, (4, m.nq - 7)))
+        q[:, 2] -= 0.05                                  # push the contact spheres into the ground
+    qd = T(rng.normal(size=(4, m.nv)))
+    qdd = T(rng.normal(size=(4, m.nv)))
+    a = T(rng.uniform(-1, 1, (4, m.na)))
+    Td = D.dynamics_terms(m, q, qd)
+    if name != "cartpole":
+        assert bool((Td["contact_d"] < 0).any())
+    M = RC.mass_matrix(m, q)
+    assert float((M - Td["M"]).abs().max()) <= 1e-13 * float(Td["M"].abs().max())
+    b = Td["bias"] - Td["tau_contact"]
+    ID0 = RC.inverse_dynamics(m, q, qd, torch.zeros_like(qd))
+    assert float((ID0 - b).abs().max()) <= 1e-13 * float(b.abs().max())
+    ID1 = RC.inverse_dynamics(m, q, qd, qdd)
+    want = ID0 + (Td["M"] @ qdd[..., None])[..., 0]
+    assert float((ID1 - want).abs().max()) <= 1e-13 * float(want.abs().max())
+    q1, qd1 = D.substep(m, q, qd, a, 1.0 / 240)
+    q2, qd2, _, _ = RC.substep_recursive(m, q, qd, a, 1.0 / 240)
+    assert float((q1 - q2).abs().max()) <= 1e-12 and float((qd1 - qd2).abs().max()) <= 1e-12 * float(qd1.abs().max())
+
+
+# ------------------------------------------------------------------ the FP32 storage floor mode
+
+def test_fp32_floor_mode_off_is_the_fp64_window_and_on_stores_float32():
+    """Off, the floor switch changes nothing (bitwise).  On, every state after a frame,
+    every action and the initial state hold float32 values (the storage an FP32 simulator
+    has) while the arithmetic stays FP64, the result moves by about the float32 resolution,
+    and the gradients are the FP64 adjoint along the rounded trajectory (straight through the
+    rounding): on a one-frame CartPole window they agree with the plain FP64 gradients to the
+    size of that move."""
+    from oracle.window import fp32_round
+    W = wl.workload("cartpole")
+    md, h = W["model"], 3
+    a = oracle_window(md, W["s0"], h, W["actor"], W["critic"])
+    b = oracle_window(md, W["s0"], h, W["actor"], W["critic"], fp32_floor=False)
+    for key in ("value", "loss", "loss_env"):
+        assert torch.equal(a[key], b[key])
+    for x, y in zip(a["states"], b["states"]):
+        assert torch.equal(x, y)
+    c = oracle_window(md, W["s0"], h, W["actor"], W["critic"], fp32_floor=True)
+    for x in c["states"] + c["actions"]:
+        assert torch.equal(x, x.to(torch.float32).to(F64))
+    d = float((c["states"][-1] - a["states"][-1]).abs().max() / a["states"][-1].abs().max())
+    assert 1e-9 < d < 1e-5
+    x = T([1.0 + 2.0 ** -30, 3.0]).requires_grad_(True)
+    y = fp32_round(x)
+    assert float(y[0].detach()) == 1.0 and float(y[1].detach()) == 3.0
+    g, = torch.autograd.grad((y * T([2.0, 5.0])).sum(), x)
+    assert torch.equal(g, T([2.0, 5.0]))
+    r0 = oracle_window_grads(md, W["s0"], 1, W["actor"], W["critic"])
+    r1 = oracle_window_grads(md, W["s0"], 1, W["actor"], W["critic"], fp32_floor=True)
+    for key in ("dL_da", "dL_ds0"):
+        assert np.linalg.norm(r1[key] - r0[key]) <= 1e-5 * np.linalg.norm(r0[key])
+    assert np.abs(r1["loss_env"].sum() - r1["loss"]) <= 1e-15 * abs(r1["loss"])
