@@ -409,7 +409,7 @@ def fd_directions(sim64, W, ad64, h, n_dirs=8):
     return res
 
 
-def cpu_baseline(W, h_sample=2, n_envs_sample=64):
+def cpu_baseline(W, h_sample=16, n_envs_sample=64):
     """The FP64 oracle (CPU, PyTorch) on a bounded sample of the same workload: n_envs_sample
     envs of the headline batch over h_sample frames, forward and reverse, scaled to env-steps
     per second (the oracle's cost is linear in frames; envs run as one batch).  cores is the

@@ -182,3 +182,29 @@ def test_bf16_mlp_matches_oracle_bf16_emulation(name, N, h, k):
     # the BF16 policy differs from the FP32 one by far more than the parity above
     ref32 = oracle_window_grads(W["model"], W["s0"], h, W["actor"], W["critic"], n_total=N)
     assert relnorm(fw["actions"], ref32["actions"]) > 10 * relnorm(fw["actions"], ref["actions"])
+
+
+def test_bf16_muscle_humanoid_full_batch_matches_oracle_bf16_emulation():
+    """The configuration's own launch (152-unit humanoid, 2048 envs, k = 16, BF16 networks,
+    FP32 dynamics) against the oracle's BF16 emulation on the 4 envs drawn with seed 4, over
+    the longest window on which twice the oracle's FP32 storage floor stays under the bar for
+    those envs (tests/golden/fp32_floor.json, h_gate): states 1e-4, gradient cosine 0.999 and
+    relative norm 1e-3 over the sampled envs together."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fp32_floor.json")) as fh:
+        fl = json.load(fh)["mtu"]
+    envs, h, N = fl["envs"], fl["h_gate"], fl["n_envs"]
+    W = wl.workload("mtu", N)
+    print(f"[bf16 mlp] mtu N={N} h={h} k=16 envs={envs}", flush=True)
+    sim = _mtu_sim(W, N, h, ckpt_interval=16, mlp_precision="bf16")
+    fw = sim.forward(W["s0"], W["actor"], W["critic"])
+    ad = sim.adjoint(fw)
+    torch.cuda.synchronize()
+    fw, ad = _np(fw), _np(ad)
+    ref = oracle_window_grads(W["model"], W["s0"][envs], h, W["actor"], W["critic"], n_total=N, bf16=True)
+    sh, rs = fw["s_h"][envs], ref["s_h"]
+    assert float((np.abs(sh - rs).max(1) / np.abs(rs).max(1)).max()) < 1e-4
+    assert relnorm(fw["actions"][:, envs], ref["actions"]) < 1e-4
+    for got, want in ((ad["dL_da"][:, envs], ref["dL_da"]), (ad["dL_ds0"][envs], ref["dL_ds0"])):
+        assert cosine(got, want) >= 0.999 and relnorm(got, want) <= 1e-3

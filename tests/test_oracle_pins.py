@@ -1123,3 +1123,31 @@ def test_fp32_floor_mode_off_is_the_fp64_window_and_on_stores_float32():
     for key in ("dL_da", "dL_ds0"):
         assert np.linalg.norm(r1[key] - r0[key]) <= 1e-5 * np.linalg.norm(r0[key])
     assert np.abs(r1["loss_env"].sum() - r1["loss"]) <= 1e-15 * abs(r1["loss"])
+
+
+def test_fp32_floor_file_is_the_oracles_and_states_the_conditioning():
+    """tests/golden/fp32_floor.json holds the oracle's own numbers: its one-frame humanoid row
+    is recomputed here, and its summary follows from its rows.  It also states the
+    conditioning of the headline window: at h = 32 no sampled env's FP32 storage floor is under
+    the parity bar (an FP32 window cannot meet it there), while at h = 1 every one is."""
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_fp32_floor as MF
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fp32_floor.json")) as fh:
+        fl = json.load(fh)
+    hum = fl["humanoid"]
+    assert hum["envs"] == [int(e) for e in np.sort(np.random.default_rng(4).choice(1024, 8, replace=False))]
+    row = MF.floor_rows("humanoid", 1024, hum["envs"], [1])[0]
+    stored = next(r for r in hum["rows"] if r["h"] == 1)
+    for a, b in zip(row["per_env"], stored["per_env"]):
+        for key in ("dL_da_rel", "dL_ds0_rel", "s_h_rel"):
+            assert a[key] == pytest.approx(b[key], rel=1e-9, abs=1e-18), key
+    summary = MF.summarise(json.loads(json.dumps(fl)))
+    for key in ("humanoid", "mtu"):
+        assert summary[key]["h_max_under_bar"] == fl[key]["h_max_under_bar"]
+        assert summary[key]["h_gate"] == fl[key]["h_gate"] <= fl[key]["h_max_under_bar"]
+    r32 = next(r for r in hum["rows"] if r["h"] == 32)
+    assert not any(MF.under_bar(e) for e in r32["per_env"])
+    assert all(MF.under_bar(e) for e in next(r for r in hum["rows"] if r["h"] == 1)["per_env"])
