@@ -400,6 +400,20 @@ typedef struct SimCriticFitIO {
 int sim_obs_stats_update(const void* obs, long rows, int dim, double count, void* mean, void* var, void* inv_std,
                          double eps, int precision, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sim_critic_values without a workspace.
+ * The critic's hidden-layer activations live in a static device array of 64 MiB that the
+ * library holds on every GPU it runs on until the process ends, so rows x (sum of the critic's
+ * hidden widths) x element size must fit in 64 MiB (after 256-byte alignment of each layer's
+ * block; the humanoid's 76-128-128-1 critic in FP32: 65536 rows), else SIM_E_WORKSPACE before
+ * any launch.  Arguments, layouts and results as for sim_critic_values; nothing is allocated
+ * or freed.  Every call on a GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and give wrong values; serialise them.  The array keeps the last
+ * call's activations, which nothing reads. */
+int sim_critic_values_noalloc(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
+                              const void* const* critic_b, const void* obs_mean, const void* obs_inv_std,
+                              void* values, void* hip_stream);
+
 /* Fits the critic: for every pass and minibatch, the mean of (V(o) - target)^2 over the
  * minibatch, its gradient through the critic's layers, one Adam step.  The order of the
  * reductions is fixed, so the result is bitwise reproducible. */

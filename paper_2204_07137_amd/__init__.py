@@ -80,7 +80,7 @@ EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window"
            "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
            "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy", "sim_adam_step",
            "sim_soft_update", "sim_td_lambda", "sim_critic_workspace_bytes", "sim_critic_values",
-           "sim_critic_fit", "sim_obs_stats_update", "sim_abi_layout"]
+           "sim_critic_fit", "sim_obs_stats_update", "sim_abi_layout", "sim_critic_values_noalloc"]
 MAX_GROUP = 6
 
 _LIB = None
@@ -144,6 +144,8 @@ def lib():
         L.sim_critic_fit.restype = _i
         L.sim_obs_stats_update.argtypes = [_p, ctypes.c_long, _i, _d, _p, _p, _p, _d, _i, _p]
         L.sim_obs_stats_update.restype = _i
+        L.sim_critic_values_noalloc.argtypes = [_p, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _p, _p, _p]
+        L.sim_critic_values_noalloc.restype = _i
         L.sim_abi_layout.argtypes = [_i, _i]
         L.sim_abi_layout.restype = ctypes.c_size_t
         _LIB = L

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,30 @@ static thread_local std::string g_err;
 static int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+// ---------------------------------------------------------------- allocation-free critic values
+// The scratch of sim_critic_values_noalloc (the critic's hidden-layer activations) is a
+// static device array, held by every GPU the library runs on until the process ends.  In host
+// code its name is only a host-side stand-in: the device address is taken once per device at
+// set-up (sim_create, or the entry point's first call on a device) with hipGetSymbolAddress,
+// and only that address is passed to kernels.
+#define SIM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define SIM_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[SIM_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SIM_MAX_DEVICES];
+
+// the device address of `scratch` on device dev, which must be the current device
+static void* scratch_on_device(int dev) {
+  if (dev < 0 || dev >= SIM_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
 }
 
 static const uint32_t kMagic = 0x53484143u;
@@ -410,6 +435,10 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   h->ns = m.ns; h->od = m.od; h->nq = m.nq; h->nv = m.nv; h->na = m.na; h->substeps = m.substeps;
   h->elem = (opt->precision == SIM_PREC_FP64) ? 8 : 4;
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(SIM_E_HIP, "hipGetDevice failed"); }
+  if (!scratch_on_device(h->device)) {
+    delete h;
+    return fail(SIM_E_HIP, "sim_create: hipGetSymbolAddress of the static scratch failed on this device");
+  }
   size_t msz = (opt->precision == SIM_PREC_FP64) ? sizeof(DevModelT<double>) : sizeof(DevModelT<float>);
   const void* src = (opt->precision == SIM_PREC_FP64) ? (const void*)&h->m64 : (const void*)&h->m32;
   if (hipMalloc(&h->dev_model, msz) != hipSuccess) { delete h; return fail(SIM_E_HIP, "hipMalloc failed"); }
@@ -1388,6 +1417,70 @@ extern "C" int sim_critic_values(SimHandle* h, const void* obs, int rows, const 
                                           hip_stream)
              : critic_values_impl<float>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, workspace,
                                          hip_stream);
+}
+
+// the critic's hidden-layer activations [rows][dims[l]] (l = 1 .. L-1), one after the other
+static size_t critic_hidden_bytes(const SimOptions& o, int rows, size_t e, size_t* off) {
+  size_t total = 0;
+  for (int l = 1; l < o.critic_layers; ++l) {
+    if (off) off[l] = total;
+    total = align256(total + (size_t)rows * o.critic_dims[l] * e);
+  }
+  return total;
+}
+
+template <typename T>
+static int critic_values_noalloc_impl(SimHandle* h, const void* obs, int rows, const void* const* cw,
+                                      const void* const* cb, const void* mean, const void* inv_std, void* values,
+                                      char* scr, void* stream) {
+  const SimOptions& o = h->opt;
+  size_t off[SIM_MAXL] = {};
+  critic_hidden_bytes(o, rows, sizeof(T), off);
+  ThetaArgsT<T> P;
+  std::memset(&P, 0, sizeof(P));
+  P.M = rows;
+  P.nl = o.critic_layers;
+  for (int l = 0; l <= o.critic_layers; ++l) P.dims[l] = o.critic_dims[l];
+  for (int l = 0; l < o.critic_layers; ++l) {
+    P.W[l] = static_cast<const T*>(cw[l]);
+    P.b[l] = static_cast<const T*>(cb[l]);
+    if (l >= 1) P.H[l] = reinterpret_cast<T*>(scr + off[l]);
+  }
+  P.x0 = static_cast<const T*>(obs);
+  P.x_shift = static_cast<const T*>(mean);
+  P.x_scale = static_cast<const T*>(inv_std);
+  if (cv_launch(P, static_cast<T*>(values), stream)) return launch_failed();
+  g_err.clear();
+  return SIM_OK;
+}
+
+extern "C" int sim_critic_values_noalloc(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
+                                         const void* const* critic_b, const void* obs_mean, const void* obs_inv_std,
+                                         void* values, void* hip_stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!obs || !values || !critic_w || !critic_b || rows < 1)
+    return fail(SIM_E_ARG, "sim_critic_values_noalloc: null pointer or no rows");
+  for (int l = 0; l < h->opt.critic_layers; ++l)
+    if (!critic_w[l] || !critic_b[l]) return fail(SIM_E_ARG, "sim_critic_values_noalloc: null critic weights");
+  if ((obs_mean != nullptr) != (obs_inv_std != nullptr))
+    return fail(SIM_E_ARG, "sim_critic_values_noalloc: observation normalisation needs both obs_mean and obs_inv_std");
+  const size_t e = h->elem;
+  const size_t per_row = critic_hidden_bytes(h->opt, 1, e, nullptr);
+  if (critic_hidden_bytes(h->opt, rows, e, nullptr) > SIM_NOALLOC_SCRATCH_BYTES)
+    return fail(SIM_E_WORKSPACE, "sim_critic_values_noalloc: " + std::to_string(rows) + " rows need more than the " +
+                                     std::to_string(SIM_NOALLOC_SCRATCH_BYTES >> 20) + " MiB static scratch (about " +
+                                     std::to_string(per_row ? SIM_NOALLOC_SCRATCH_BYTES / per_row : 0) +
+                                     " rows of this critic fit)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_E_HIP, "sim_critic_values_noalloc: hipGetDevice failed");
+  char* scr = static_cast<char*>(scratch_on_device(dev));
+  if (!scr) return fail(SIM_E_HIP, "sim_critic_values_noalloc: hipGetSymbolAddress of the static scratch failed");
+  return (h->opt.precision == SIM_PREC_FP64)
+             ? critic_values_noalloc_impl<double>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, scr,
+                                                  hip_stream)
+             : critic_values_noalloc_impl<float>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, scr,
+                                                 hip_stream);
 }
 
 template <typename T>
