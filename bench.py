@@ -218,9 +218,11 @@ def mixed_batch(P, wl, torch, budget_gb=64.0, steps=3):
         r = P.tune(W["model"], n, h, ad_, cd_, W["s0"], W["actor"], W["critic"], budget_bytes=int(left), reps=1)
         left -= r["workspace_bytes"]
         kw = dict(path=P.PATH_TAPE) if r["path"] == P.PATH_TAPE else dict(ckpt_interval=r["ckpt_interval"])
-        sim = P.Sim(W["model"], n, h, ad_, cd_, **kw)
+        sim = P.Sim(W["model"], n, h, ad_, cd_, lanes_per_env=r["lanes_per_env"], **kw)
         tuned.append({"model": name, "envs": n, "path": "tape" if r["path"] == P.PATH_TAPE else "persistent",
-                      "k": r["ckpt_interval"], "ms_window": round(r["ms_window"], 3),
+                      "k": r["ckpt_interval"], "lanes_per_env": r["lanes_per_env"],
+                      "candidates": r["n_candidates"], "ms_window": round(r["ms_window"], 3),
+                      "env_steps_per_s": round(n * h / (r["ms_window"] / 1e3), 1),
                       "workspace_gb": round(r["workspace_bytes"] / 1e9, 2)})
         sims.append(sim)
         args.append((sim._dev(W["s0"]), sim.weights(W["actor"]), sim.weights(W["critic"])))
@@ -256,8 +258,8 @@ def mixed_batch(P, wl, torch, budget_gb=64.0, steps=3):
     tp = (time.perf_counter() - t0) / steps
     order = [members[i][0] for i in G.order()]
     return {"workload": "4096 cartpole + 2048 ant + 1024 humanoid + 512 muscle-humanoid envs, h=32, one "
-                        "graph-captured group launch per direction (autotuned path / k per model, 64 GB "
-                        "workspace budget)",
+                        "graph-captured group launch per direction (autotuned path / k / lanes per env per "
+                        "model, 64 GB workspace budget)",
             "value": round(total_envs * h / tg, 1), "unit": "env-steps/s", "ms_per_step": round(tg * 1e3, 3),
             "dispatch_order": order, "tuned": tuned, "graph_captures": G.captures(),
             "plain_per_model": {"value": round(total_envs * h / tp, 1), "ms_per_step": round(tp * 1e3, 3)},

@@ -169,6 +169,15 @@ typedef struct SimOptions {
                                     layer inputs and FP32 accumulation, biases and activations;
                                     their input adjoints likewise (the output adjoint in BF16).
                                     The dynamics stay FP32. */
+  int lanes_per_env;             /* 0: the full per-environment layout, one environment per 64-lane
+                                    wavefront (every model); 16, 32 or 64: the compact layout of
+                                    small torque-driven models (at most 16 frames, 16 DOFs, 16
+                                    contacts, 16 actions, 64 observations, MLP widths <= 128 and
+                                    <= 8 x lanes, 64 mass-matrix pairs, frames / DOFs / contacts
+                                    / coordinates <= lanes), 64 / lanes environments per
+                                    wavefront and several wavefronts per CU; n_envs must then be a
+                                    multiple of 64 / lanes.  FP32 path, FP32 MLPs, persistent or
+                                    tape path.  Results are bitwise those of the full layout. */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;
@@ -301,8 +310,10 @@ void sim_group_destroy(SimGroup* g);
 
 /* ---- Autotuner.  Times forward + adjoint windows of one model on the caller's inputs
  * for every launch configuration whose workspace fits workspace_budget: the tape path and
- * the persistent path at every checkpoint interval k dividing S; returns the fastest
- * (median of reps windows after a warm-up).  opt supplies everything else (N, h, MLP
+ * the persistent path at every checkpoint interval k dividing S, each in the full layout and,
+ * for small models whose n_envs allows it, in the compact layout with 64, 32 and 16 lanes per
+ * environment (opt->lanes_per_env is ignored); returns the fastest (median of reps windows
+ * after a warm-up).  opt supplies everything else (N, h, MLP
  * shapes, precision).  io supplies s0, the weights (or actions_in) and the forward output
  * buffers, which the tuner overwrites; its workspace fields are ignored.  A set-up call:
  * it allocates and frees its own workspaces and synchronizes the stream. */
@@ -312,6 +323,7 @@ typedef struct SimTuneResult {
   size_t workspace_bytes;        /* workspace of the chosen configuration */
   double ms_window;              /* its forward + adjoint time per window */
   int n_candidates;              /* configurations timed */
+  int lanes_per_env;             /* the chosen layout (SimOptions.lanes_per_env) */
 } SimTuneResult;
 int sim_tune(const SimModelDesc* model, const SimOptions* opt, const SimForwardIO* io,
              size_t workspace_budget, int reps, void* hip_stream, SimTuneResult* out);

@@ -42,7 +42,7 @@ class SimOptions(ctypes.Structure):
                 ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
                 ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
                 ("precision", _i), ("chol_fp64_threshold", _d), ("policy_grad", _i),
-                ("mlp_precision", _i)]
+                ("mlp_precision", _i), ("lanes_per_env", _i)]
 
 
 class SimForwardIO(ctypes.Structure):
@@ -65,7 +65,7 @@ class SimAdjointIO(ctypes.Structure):
 
 class SimTuneResult(ctypes.Structure):
     _fields_ = [("path", _i), ("ckpt_interval", _i), ("workspace_bytes", ctypes.c_size_t),
-                ("ms_window", _d), ("n_candidates", _i)]
+                ("ms_window", _d), ("n_candidates", _i), ("lanes_per_env", _i)]
 
 
 class SimCriticFitIO(ctypes.Structure):
@@ -223,7 +223,7 @@ class Sim:
 
     def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
                  path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6,
-                 policy_grad=False, mlp_precision="fp32"):
+                 policy_grad=False, mlp_precision="fp32", lanes_per_env=0):
         import torch
         self.torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -250,6 +250,7 @@ class Sim:
         o.chol_fp64_threshold = float(chol_fp64_threshold)
         o.policy_grad = 1 if policy_grad else 0
         o.mlp_precision = {"fp32": 0, "bf16": 1}[mlp_precision]
+        o.lanes_per_env = int(lanes_per_env)
         self.actor_dims = list(actor_dims) if actor_dims is not None else None
         h = _p()
         _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
@@ -586,9 +587,9 @@ class Group:
 
 def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget_bytes,
          reps=3, precision="fp32", gamma=0.99):
-    """Run sim_tune: the fastest launch configuration (path, k) of this model within a
-    workspace budget.  Returns a dict with path, ckpt_interval, workspace_bytes,
-    ms_window and n_candidates."""
+    """Run sim_tune: the fastest launch configuration (path, k, layout) of this model within a
+    workspace budget.  Returns a dict with path, ckpt_interval, lanes_per_env,
+    workspace_bytes, ms_window and n_candidates."""
     import torch
     probe = Sim(md, n_envs, horizon, actor_dims, critic_dims, ckpt_interval=md["substeps"],
                 precision=precision, gamma=gamma)
@@ -599,8 +600,9 @@ def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget
                           int(budget_bytes), int(reps),
                           _p(st.cuda_stream), ctypes.byref(r)))
     probe.close()
-    return {"path": r.path, "ckpt_interval": r.ckpt_interval, "workspace_bytes": r.workspace_bytes,
-            "ms_window": r.ms_window, "n_candidates": r.n_candidates, "keep": out}
+    return {"path": r.path, "ckpt_interval": r.ckpt_interval, "lanes_per_env": r.lanes_per_env,
+            "workspace_bytes": r.workspace_bytes, "ms_window": r.ms_window, "n_candidates": r.n_candidates,
+            "keep": out}
 
 
 def _prec(t):

@@ -9,9 +9,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshacsim.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("shacsim_abi.hip", "kernels_f32.hip", "kernels_f64.hip", "learn.hip")]
+# the window kernels are split over several units (one precision's full layouts, compact
+# layouts and group kernels) that compile in parallel
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels_f32_group_fwd.hip", "kernels_f32_group_adj.hip", "kernels_f32.hip",
+                                                  "kernels_f32_compact.hip", "kernels_f64.hip", "kernels_f64_group_fwd.hip",
+                                                  "kernels_f64_group_adj.hip", "shacsim_abi.hip", "learn.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("sim_types.h", "sim_math.h", "sim_dynamics.h", "sim_task.h", "sim_gemm.h", "sim_learn.h",
-                                                 "sim_kernels.h")] + [
+                                                 "sim_kernels.h", "sim_unit_f32.h", "sim_unit_f64.h")] + [
     os.path.join(ROOT, "include", "shacsim.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

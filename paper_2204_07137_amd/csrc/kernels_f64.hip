@@ -1,19 +1,4 @@
-// FP64 instantiation of the window kernels (reference-precision path on the GPU).
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include "sim_types.h"
-
-// DOF counts compiled as kernels of their own: the humanoid's 27, for torque and muscle
-// models, so that the FP64 parity runs cover the DOF-specialised kernel of the production
-// path; every other model runs the padded 32-DOF kernel
-#define SIM_NV_LIST_MTU(X) X(27)
-#define SIM_NV_LIST(X) X(27)
-
-namespace sim_f64 {
-typedef double real;
-#include "sim_math.h"
-#include "sim_dynamics.h"
-#include "sim_task.h"
-#include "sim_kernels.h"
-#include "sim_gemm.h"
-}  // namespace sim_f64
+// FP64 window kernels: full and muscle layouts, plain per-substep path, MLP weight preparation,
+// window loss and the policy-parameter gradient.
+#define SIM_EMIT_MAIN 1
+#include "sim_unit_f64.h"

@@ -99,7 +99,7 @@ static const size_t kLayoutSimOptions[] = {
     offsetof(SimOptions, path), offsetof(SimOptions, closed_loop), offsetof(SimOptions, actor_layers),
     offsetof(SimOptions, actor_dims), offsetof(SimOptions, critic_layers), offsetof(SimOptions, critic_dims),
     offsetof(SimOptions, gamma), offsetof(SimOptions, precision), offsetof(SimOptions, chol_fp64_threshold),
-    offsetof(SimOptions, policy_grad), offsetof(SimOptions, mlp_precision),
+    offsetof(SimOptions, policy_grad), offsetof(SimOptions, mlp_precision), offsetof(SimOptions, lanes_per_env),
 };
 static const size_t kLayoutSimForwardIO[] = {
     offsetof(SimForwardIO, s0), offsetof(SimForwardIO, actions_in), offsetof(SimForwardIO, actor_w),
@@ -125,7 +125,7 @@ static const size_t kLayoutSimAdjointIO[] = {
 static const size_t kLayoutSimTuneResult[] = {
     offsetof(SimTuneResult, path), offsetof(SimTuneResult, ckpt_interval),
     offsetof(SimTuneResult, workspace_bytes), offsetof(SimTuneResult, ms_window),
-    offsetof(SimTuneResult, n_candidates),
+    offsetof(SimTuneResult, n_candidates), offsetof(SimTuneResult, lanes_per_env),
 };
 static const size_t kLayoutSimCriticFitIO[] = {
     offsetof(SimCriticFitIO, obs), offsetof(SimCriticFitIO, targets), offsetof(SimCriticFitIO, rows),
@@ -416,6 +416,26 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
     return fail(SIM_E_ARG, "BF16 MLPs run in the FP32 path");
   if (opt->mlp_precision == SIM_MLP_BF16 && opt->policy_grad)
     return fail(SIM_E_UNSUPPORTED, "the policy-parameter gradient runs with FP32 MLPs");
+  if (opt->lanes_per_env != 0) {
+    const int ln = opt->lanes_per_env;
+    if (ln != 16 && ln != 32 && ln != 64) return fail(SIM_E_ARG, "lanes_per_env must be 0, 16, 32 or 64");
+    if (opt->precision != SIM_PREC_FP32 || opt->mlp_precision != SIM_MLP_FP32)
+      return fail(SIM_E_UNSUPPORTED, "the compact layout runs in the FP32 path with FP32 MLPs");
+    if (m.n_mtu > 0) return fail(SIM_E_UNSUPPORTED, "the compact layout is for torque-driven models");
+    if (opt->path == SIM_PATH_PLAIN) return fail(SIM_E_UNSUPPORTED, "the compact layout runs on the persistent and tape paths");
+    if (m.J > SIM_CJ || m.nv > SIM_CV || m.nc > SIM_CC || m.na > SIM_CA || m.od > SIM_COBS || m.npair > SIM_CPAIR)
+      return fail(SIM_E_UNSUPPORTED, "model beyond the compact layout (16 frames, DOFs, contacts and actions, "
+                                     "64 observations, 64 mass-matrix pairs)");
+    if (m.J > ln || m.nv > ln || m.nc > ln || m.nq > ln)
+      return fail(SIM_E_UNSUPPORTED, "frames, DOFs, contacts and coordinates must not exceed lanes_per_env");
+    const int wmax = std::min(SIM_CHID, 8 * ln);
+    for (int l = 0; l <= opt->critic_layers; ++l)
+      if (opt->critic_dims[l] > wmax) return fail(SIM_E_UNSUPPORTED, "critic width beyond the compact layout");
+    if (opt->closed_loop)
+      for (int l = 0; l <= opt->actor_layers; ++l)
+        if (opt->actor_dims[l] > wmax) return fail(SIM_E_UNSUPPORTED, "actor width beyond the compact layout");
+    if (opt->n_envs % (SIM_WAVE / ln) != 0) return fail(SIM_E_ARG, "n_envs must be a multiple of 64 / lanes_per_env");
+  }
   return SIM_OK;
 }
 
@@ -498,7 +518,7 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   const size_t tape_entries = (opt->path == SIM_PATH_TAPE) ? (size_t)opt->horizon * m.substeps * N
                               : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
   h->off_tape = off;
-  off = align256(off + tape_entries * sim_tape_bytes(e, m.n_mtu > 0));
+  off = align256(off + tape_entries * sim_tape_bytes(e, m.n_mtu > 0, opt->lanes_per_env != 0));
   h->off_done = off;
   off = align256(off + (size_t)opt->horizon * N);
   h->off_seg = off;
@@ -742,11 +762,13 @@ static int do_prep(const WinArgsT<double>& A, void* s) {
   int bad = A.closed_loop ? launch_transposes(A.actor, s) : 0;
   return bad | launch_transposes(A.critic, s);
 }
-static int do_window(const WinArgsT<float>& A, int adjoint, int plain, int S, int nv, int mtu, void* s) {
-  return adjoint ? sim_f32::launch_adjoint(A, plain, S, nv, mtu, s) : sim_f32::launch_forward(A, plain, S, nv, mtu, s);
+static int do_window(const WinArgsT<float>& A, int adjoint, int plain, int S, int nv, int mtu, int lanes, void* s) {
+  return adjoint ? sim_f32::launch_adjoint(A, plain, S, nv, mtu, lanes, s)
+                 : sim_f32::launch_forward(A, plain, S, nv, mtu, lanes, s);
 }
-static int do_window(const WinArgsT<double>& A, int adjoint, int plain, int S, int nv, int mtu, void* s) {
-  return adjoint ? sim_f64::launch_adjoint(A, plain, S, nv, mtu, s) : sim_f64::launch_forward(A, plain, S, nv, mtu, s);
+static int do_window(const WinArgsT<double>& A, int adjoint, int plain, int S, int nv, int mtu, int lanes, void* s) {
+  return adjoint ? sim_f64::launch_adjoint(A, plain, S, nv, mtu, lanes, s)
+                 : sim_f64::launch_forward(A, plain, S, nv, mtu, lanes, s);
 }
 static int do_theta(const ThetaArgsT<float>& P, void* s) { return sim_f32::launch_theta(P, s); }
 static int do_theta(const ThetaArgsT<double>& P, void* s) { return sim_f64::launch_theta(P, s); }
@@ -755,11 +777,11 @@ static int group_has_mtu(const int* mtu, int n) {
     if (mtu[i]) return 1;
   return 0;
 }
-static int do_group(const GroupArgsT<float>& G, int adjoint, void* s) {
-  return sim_f32::launch_group(G, adjoint, group_has_mtu(G.mtu, G.n), s);
+static int do_group(const GroupArgsT<float>& G, int adjoint, size_t lds, void* s) {
+  return sim_f32::launch_group(G, adjoint, group_has_mtu(G.mtu, G.n), lds, s);
 }
-static int do_group(const GroupArgsT<double>& G, int adjoint, void* s) {
-  return sim_f64::launch_group(G, adjoint, group_has_mtu(G.mtu, G.n), s);
+static int do_group(const GroupArgsT<double>& G, int adjoint, size_t lds, void* s) {
+  return sim_f64::launch_group(G, adjoint, group_has_mtu(G.mtu, G.n), lds, s);
 }
 
 static int launch_failed() {
@@ -772,7 +794,8 @@ static int run_forward(SimHandle* h, const SimForwardIO* io, void* stream) {
   int rc = build_forward_args<T>(h, io, A);
   if (rc) return rc;
   int bad = do_prep(A, stream);
-  bad |= do_window(A, 0, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, h->m64.n_mtu > 0, stream);
+  bad |= do_window(A, 0, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, h->m64.n_mtu > 0, h->opt.lanes_per_env,
+                   stream);
   return bad ? launch_failed() : SIM_OK;
 }
 
@@ -781,7 +804,8 @@ static int run_adjoint(SimHandle* h, const SimAdjointIO* io, void* stream) {
   WinArgsT<T> A;
   int rc = build_adjoint_args<T>(h, io, A);
   if (rc) return rc;
-  if (do_window(A, 1, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, h->m64.n_mtu > 0, stream))
+  if (do_window(A, 1, h->opt.path == SIM_PATH_PLAIN, h->substeps, h->nv, h->m64.n_mtu > 0, h->opt.lanes_per_env,
+                stream))
     return launch_failed();
   if (io->dL_dtheta) {
     ThetaArgsT<T> P;
@@ -861,11 +885,17 @@ struct SimGroup {
   hipGraphExec_t exec[2] = {nullptr, nullptr};   // forward, adjoint
   std::string key[2];                 // launch arguments the graph was captured with
   int captures = 0;
+  size_t lds = 0;                     // LDS bytes of a group block: the largest a member needs
   uint32_t magic = kGroupMagic;
 };
 
 // Per-env cost estimate of one window: substeps times a per-substep operation count
 // (factorisation, tree passes, contacts) plus the policy MLP per frame.
+// blocks (wavefronts) of a member: one env each in the full layouts, 64 / lanes in the compact one
+static int member_blocks(const SimHandle* h) {
+  return h->opt.lanes_per_env ? h->opt.n_envs / (SIM_WAVE / h->opt.lanes_per_env) : h->opt.n_envs;
+}
+
 static double member_cost(const SimHandle* h) {
   const double nv = h->nv, J = h->m64.J, nc = h->m64.nc;
   double mlp = 0;
@@ -905,6 +935,17 @@ extern "C" int sim_group_create(SimHandle* const* members, int n, const double* 
     g->order[i] = i;
   }
   std::stable_sort(g->order, g->order + n, [g](int a, int b) { return g->cost[a] > g->cost[b]; });
+  for (int i = 0; i < n; ++i) {
+    const int lanes = members[i]->opt.lanes_per_env, mtu = members[i]->m64.n_mtu > 0;
+    const size_t b = (g->precision == SIM_PREC_FP64) ? sim_f64::group_lds_bytes(lanes, mtu)
+                                                     : sim_f32::group_lds_bytes(lanes, mtu);
+    g->lds = std::max(g->lds, b);
+  }
+  const int prep = (g->precision == SIM_PREC_FP64) ? sim_f64::prepare_group(g->lds) : sim_f32::prepare_group(g->lds);
+  if (prep) {
+    delete g;
+    return fail(SIM_E_HIP, "sim_group_create: the group kernels cannot be given the members' LDS");
+  }
   if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
     delete g;
     return fail(SIM_E_HIP, "hipStreamCreate failed");
@@ -975,14 +1016,15 @@ static int run_group_forward(SimGroup* g, const SimForwardIO* ios, void* stream)
     G.start[s] = start;
     G.nv[s] = h->nv;
     G.mtu[s] = h->m64.n_mtu > 0;
-    start += h->opt.n_envs;
+    G.lanes[s] = h->opt.lanes_per_env;
+    start += member_blocks(h);
   }
   G.start[g->n] = start;
   std::string key(reinterpret_cast<const char*>(&G), sizeof(G));
   return group_launch(g, 0, key, stream, [&](void* cs) {
     int bad = 0;
     for (int s = 0; s < G.n; ++s) bad |= do_prep(G.A[s], cs);
-    return bad | do_group(G, 0, cs);
+    return bad | do_group(G, 0, g->lds, cs);
   });
 }
 
@@ -1003,7 +1045,8 @@ static int run_group_adjoint(SimGroup* g, const SimAdjointIO* ios, void* stream)
     G.start[s] = start;
     G.nv[s] = h->nv;
     G.mtu[s] = h->m64.n_mtu > 0;
-    start += h->opt.n_envs;
+    G.lanes[s] = h->opt.lanes_per_env;
+    start += member_blocks(h);
     has_theta[s] = ios[mi].dL_dtheta != nullptr;
     if (has_theta[s]) {
       build_theta_args<T>(h, &ios[mi], P[s]);
@@ -1013,7 +1056,7 @@ static int run_group_adjoint(SimGroup* g, const SimAdjointIO* ios, void* stream)
   G.start[g->n] = start;
   key.append(reinterpret_cast<const char*>(&G), sizeof(G));
   return group_launch(g, 1, key, stream, [&](void* cs) {
-    int bad = do_group(G, 1, cs);
+    int bad = do_group(G, 1, g->lds, cs);
     for (int s = 0; s < G.n; ++s)
       if (has_theta[s]) bad |= do_theta(P[s], cs);
     return bad;
@@ -1054,11 +1097,22 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
   if (reps < 1) return fail(SIM_E_ARG, "sim_tune: reps must be >= 1");
   std::memset(out, 0, sizeof(*out));
   hipStream_t st = (hipStream_t)hip_stream;
-  struct Cand { int path, k; };
+  struct Cand { int path, k, lanes; };
   std::vector<Cand> cands;
-  cands.push_back({SIM_PATH_TAPE, 1});
-  for (int k = 1; k <= model->substeps; ++k)
-    if (model->substeps % k == 0) cands.push_back({SIM_PATH_PERSISTENT, k});
+  for (int lanes : {0, 64, 32, 16}) {
+    if (lanes) {
+      // the compact layout only where the model and batch allow it
+      SimOptions o = *opt;
+      o.lanes_per_env = lanes;
+      o.path = SIM_PATH_TAPE;
+      o.ckpt_interval = 1;
+      DevModelT<double> m;
+      if (build_model(model, m) || check_options(&o, m)) continue;
+    }
+    cands.push_back({SIM_PATH_TAPE, 1, lanes});
+    for (int k = 1; k <= model->substeps; ++k)
+      if (model->substeps % k == 0) cands.push_back({SIM_PATH_PERSISTENT, k, lanes});
+  }
   double best = -1.0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SIM_E_HIP, "hipEventCreate failed");
@@ -1067,6 +1121,7 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
     SimOptions o = *opt;
     o.path = c.path;
     o.ckpt_interval = c.k;
+    o.lanes_per_env = c.lanes;
     SimHandle* h = nullptr;
     rc = sim_create(model, &o, &h);
     if (rc) break;
@@ -1126,6 +1181,7 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
       out->ckpt_interval = c.k;
       out->workspace_bytes = ws;
       out->ms_window = med;
+      out->lanes_per_env = c.lanes;
     }
   }
   hipEventDestroy(e0);

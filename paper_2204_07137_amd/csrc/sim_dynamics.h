@@ -38,83 +38,94 @@ struct ContactRegs {
 #define SIM_MUS_CA 3
 static_assert(3 * SIM_MUS_CA <= SIM_MUS_CF, "adjoint muscle tables fit the forward's space");
 
-// Per-environment LDS of one wavefront.  MAXA: action capacity; NMTU: muscle capacity
-// (0 for torque-driven models, whose layout then carries no muscle fields).
-template <int MAXA, int NMTU>
+// Per-environment LDS of one environment.  MAXA: action capacity; NMTU: muscle capacity
+// (0 for torque-driven models, whose layout then carries no muscle fields); LANES: the lanes
+// of a wavefront that simulate the environment (64, or 16 / 32 with 64 / LANES environments
+// per wavefront); CJ, CV, CC, COBS, CHID, CPAIR: capacities of frames, DOFs, contact spheres,
+// observation, MLP width and mass-matrix pairs.
+template <int MAXA, int NMTU, int LANES = SIM_WAVE, int CJ = SIM_MAXJ, int CV = SIM_MAXV, int CC = SIM_MAXC,
+          int COBS = SIM_MAXOBS, int CHID = SIM_MAXHID, int CPAIR = SIM_MAXPAIR>
 struct EnvLDST {
   static constexpr int kMtu = NMTU;
   static constexpr int kMaxA = MAXA;
+  static constexpr int kLanes = LANES;
+  static constexpr int kJ = CJ, kV = CV, kQ = CV + 1, kC = CC, kObs = COBS, kHid = CHID, kPair = CPAIR;
   // reals of the tape entry: the block below up to and including tfb, plus the frame
   // transforms and activations for muscle models
-  static constexpr int kTapeUsed = SIM_TAPE_REALS + (NMTU > 0 ? 12 * SIM_MAXJ + NMTU : 0);
+  static constexpr int kTapeBase = sim_tape_reals(CJ, CV, CC);
+  static constexpr int kTapeUsed = kTapeBase + (NMTU > 0 ? 12 * CJ + NMTU : 0);
   static constexpr int kTapeBytes = (kTapeUsed * (int)sizeof(real) + 1023) / 1024 * 1024;
   static constexpr int kTapeReals = kTapeBytes / (int)sizeof(real);   // stride of one tape entry
-  static constexpr int kBlockReals = SIM_TAPE_REALS + 12 * SIM_MAXJ + NMTU;
+  static constexpr int kBlockReals = kTapeBase + 12 * CJ + NMTU;
   static constexpr int kPad = kTapeReals > kBlockReals ? kTapeReals - kBlockReals : 0;
   // The linearisation of the current substep, one contiguous 1 KB-padded block so that it
   // moves to and from HBM as whole 64-lane x 16-byte transfers (the linearisation tape).
   // For torque-driven models the entry ends inside R (R and p are then rebuilt by any
   // recomputation and never read by the adjoint).
   struct __attribute__((aligned(16))) {
-    real q[SIM_MAXQ], qd[SIM_MAXV];   // state before the substep
-    real S[SIM_MAXJ][6], v[SIM_MAXJ][6], ab[SIM_MAXJ][6], Ib[SIM_MAXJ][10];
-    real cf[SIM_MAXC][3], cx[SIM_MAXC][3], cvel[SIM_MAXC][3], cdep[SIM_MAXC];
-    real qdd[SIM_MAXV], qdn[SIM_MAXV];
-    real M[SIM_MAXV][SIM_MAXV + 1];    // mass matrix, then the Cholesky rows
-    real tdinv[SIM_MAXV], tfb[SIM_MAXV];
-    real R[SIM_MAXJ][9], p[SIM_MAXJ][3];
+    real q[CV + 1], qd[CV];   // state before the substep
+    real S[CJ][6], v[CJ][6], ab[CJ][6], Ib[CJ][10];
+    real cf[CC][3], cx[CC][3], cvel[CC][3], cdep[CC];
+    real qdd[CV], qdn[CV];
+    real M[CV][CV + 1];    // mass matrix, then the Cholesky rows
+    real tdinv[CV], tfb[CV];
+    real R[CJ][9], p[CJ][3];
     real act[NMTU];                    // muscle activations before the substep
     real tpad[kPad];
   };
   real a[MAXA];
-  real qn[SIM_MAXQ];
+  real qn[CV + 1];
   real actn[NMTU];                     // activations after the substep
   real act_bar[NMTU];
   // substep scratch: the forward's Newton-Euler forces, CRBA columns and composite
   // inertias, and the adjoint's per-body terms with their subtree sums (never live together)
   union {
     struct {
-      real F[SIM_MAXJ][6], Fi[SIM_MAXJ][6];
-      real Ic[SIM_MAXJ][10];
+      real F[CJ][6], Fi[CJ][6];
+      real Ic[CJ][10];
     };
-    real acc[SIM_MAXJ][42];
+    real acc[CJ][42];
   };
-  real vec[SIM_MAXV];
+  real vec[CV];
   real O[4];
   // adjoint
-  real W[SIM_MAXJ][6], A[SIM_MAXJ][6];
-  real cAb[SIM_MAXC][6], cVb[SIM_MAXC][6];
-  real qb[SIM_MAXQ], qdb[SIM_MAXV], abar[MAXA];
-  real lam[SIM_MAXV], dPq[SIM_MAXV], dPqd[SIM_MAXV];
+  real W[CJ][6], A[CJ][6];
+  real cAb[CC][6], cVb[CC][6];
+  real qb[CV + 1], qdb[CV], abar[MAXA];
+  real lam[CV], dPq[CV], dPqd[CV];
   // topology copies for arbitrary-index lookups
-  int t_next_sib[SIM_MAXJ], t_type[SIM_MAXJ], t_va[SIM_MAXJ], t_parent[SIM_MAXJ], t_qa[SIM_MAXJ];
+  int t_next_sib[CJ], t_type[CJ], t_va[CJ], t_parent[CJ], t_qa[CJ];
   unsigned short t_ts[4][SIM_MAXTS] __attribute__((aligned(16)));   // subtree-sum schedule
-  real arm[SIM_MAXV];
-  real j_off[SIM_MAXJ][3], j_ax[SIM_MAXJ][3], j_com[SIM_MAXJ][3], j_I6[SIM_MAXJ][6];
-  int pairs[SIM_MAXPAIR];
+  real arm[CV];
+  real j_off[CJ][3], j_ax[CJ][3], j_com[CJ][3], j_I6[CJ][6];
+  int pairs[CPAIR];
   int nadh;   // contacts of the last substep whose normal force pulled (see the contact phase)
   // policy / critic
-  real obs[SIM_MAXOBS];
+  real obs[COBS];
   union {
     struct {
-      real h0[SIM_MAXHID], h1[SIM_MAXHID], y[SIM_MAXHID], gb[SIM_MAXHID];
-      uint16_t xb16[SIM_MAXHID] __attribute__((aligned(16)));   // BF16 layer operand
+      real h0[CHID], h1[CHID], y[CHID], gb[CHID];
+      uint16_t xb16[CHID] __attribute__((aligned(16)));   // BF16 layer operand
     };
-    double M64[SIM_MAXV][SIM_MAXV];   // FP64 refactorisation (never live at the same time as the MLP)
+    double M64[CV][CV];   // FP64 refactorisation (never live at the same time as the MLP)
     // per-body muscle wrenches and their adjoint terms (substep-local), accumulated in
     // several copies (see muscle_wrenches); copy 0 of each table holds the sums
-    real mus[SIM_MUS_CF * SIM_MUS_STRIDE];
+    real mus[NMTU > 0 ? SIM_MUS_CF * SIM_MUS_STRIDE : 1];
   };
   real red[4];
 };
 typedef EnvLDST<SIM_MAXA, 0> EnvLDS;             // torque-driven models
 typedef EnvLDST<SIM_MAXAM, SIM_MAXMTU> EnvLDSM;  // muscle-driven models
+// small torque-driven models: LN lanes per environment, 64 / LN environments per wavefront
+template <int LN>
+using EnvLDSC = EnvLDST<SIM_CA, 0, LN, SIM_CJ, SIM_CV, SIM_CC, SIM_COBS, SIM_CHID, SIM_CPAIR>;
 // four environments per CU (160 KB of LDS) in FP32, for both layouts
 static_assert(sizeof(real) != 4 || sizeof(EnvLDSM) <= 40960, "muscle LDS layout exceeds a quarter of the CU's LDS");
 
 template <class L>
 __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, int ln,
                                           JointRegs& jr, ContactRegs& cr) {
+  constexpr int LN = L::kLanes;
   int j = ln < m->J ? ln : 0;
   jr.par = m->parent[j]; jr.type = m->jtype[j]; jr.qa = m->qadr[j]; jr.va = m->vadr[j];
   jr.depth = ln < m->J ? m->depth[j] : -1;
@@ -123,25 +134,26 @@ __device__ __forceinline__ void load_regs(const DevModel* __restrict__ m, L& E, 
   jr.cmask = ln < m->J ? m->cmask[j] : 0u;
   jr.arm = m->armature[m->vadr[j]];
   jr.npair = m->npair;
-  for (int p = ln; p < m->npair; p += SIM_WAVE) E.pairs[p] = m->pair[p];
-  reinterpret_cast<unsigned int*>(&E.t_ts[0][0])[ln] = reinterpret_cast<const unsigned int*>(&m->ts_edge[0][0])[ln];
-  if (ln < SIM_MAXJ) {
+  for (int p = ln; p < m->npair; p += LN) E.pairs[p] = m->pair[p];
+  for (int i = ln; i < 2 * SIM_MAXTS; i += LN)
+    reinterpret_cast<unsigned int*>(&E.t_ts[0][0])[i] = reinterpret_cast<const unsigned int*>(&m->ts_edge[0][0])[i];
+  for (int f = ln; f < L::kJ; f += LN) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      E.j_off[ln][k] = m->offset[3 * ln + k];
-      E.j_ax[ln][k] = m->axis[3 * ln + k];
-      E.j_com[ln][k] = m->com[3 * ln + k];
+      E.j_off[f][k] = m->offset[3 * f + k];
+      E.j_ax[f][k] = m->axis[3 * f + k];
+      E.j_com[f][k] = m->com[3 * f + k];
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) E.j_I6[ln][k] = m->inertia[6 * ln + k];
+    for (int k = 0; k < 6; ++k) E.j_I6[f][k] = m->inertia[6 * f + k];
   }
   int c = ln < m->nc ? ln : 0;
   cr.body = m->cbody[c]; cr.pos = ld3(&m->cpos[3 * c]); cr.rad = m->crad[c];
-  if (ln < SIM_MAXJ) {
-    E.t_next_sib[ln] = m->next_sib[ln]; E.t_type[ln] = m->jtype[ln];
-    E.t_va[ln] = m->vadr[ln]; E.t_parent[ln] = m->parent[ln]; E.t_qa[ln] = m->qadr[ln];
-    E.arm[ln] = m->armature[ln];
+  for (int f = ln; f < L::kJ; f += LN) {
+    E.t_next_sib[f] = m->next_sib[f]; E.t_type[f] = m->jtype[f];
+    E.t_va[f] = m->vadr[f]; E.t_parent[f] = m->parent[f]; E.t_qa[f] = m->qadr[f];
   }
+  for (int f = ln; f < L::kV; f += LN) E.arm[f] = m->armature[f];
   wsync();
 }
 
@@ -241,12 +253,12 @@ struct Chol {
 
 // On entry C.row[k] = M[ln][k].  Right-looking factorisation; the column-k entries of the
 // other rows are broadcast with readlane.
-template <int NV>
+template <int NV, int LN>
 __device__ __forceinline__ void chol_factor(Chol& C, int ln, real& minpiv) {
   minpiv = RL(3.0e38);
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    real piv = rdl(C.row[k], k);
+    real piv = bcast<LN>(C.row[k], k);
     minpiv = m_fmin(minpiv, piv);
     real inv = m_rsqrt(piv);
     real d = piv * inv;
@@ -255,24 +267,24 @@ __device__ __forceinline__ void chol_factor(Chol& C, int ln, real& minpiv) {
     C.row[k] = lk;
     real ljk[NV];
 #pragma unroll
-    for (int j = k + 1; j < NV; ++j) ljk[j] = rdl(lk, j);
+    for (int j = k + 1; j < NV; ++j) ljk[j] = bcast<LN>(lk, j);
 #pragma unroll
     for (int j = k + 1; j < NV; ++j) C.row[j] = m_fma(-lk, ljk[j], C.row[j]);
   }
 }
 
 // solve L L^T x = b for b given in lane ln (row ln)
-template <int NV>
+template <int NV, int LN>
 __device__ __forceinline__ real chol_solve(const Chol& C, int ln, real b) {
   real y = b;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    real yk = rdl(y, k) * C.dinv[k];
+    real yk = bcast<LN>(y, k) * C.dinv[k];
     y = (ln == k) ? yk : (ln > k ? m_fma(-C.row[k], yk, y) : y);
   }
 #pragma unroll
   for (int k = NV - 1; k >= 0; --k) {
-    real xk = rdl(y, k) * C.dinv[k];
+    real xk = bcast<LN>(y, k) * C.dinv[k];
     y = (ln == k) ? xk : (ln < k ? m_fma(-C.col[k], xk, y) : y);
   }
   return y;
@@ -308,16 +320,17 @@ __device__ __forceinline__ void chol64_factor(L& E, int nv, int ln) {
 
 template <int NV, class L>
 __device__ __forceinline__ double chol64_solve(L& E, int ln, double b) {
+  constexpr int LN = L::kLanes;
   double y = b;
 #pragma unroll 1
   for (int k = 0; k < NV; ++k) {
-    double yk = rdl(y, k) / E.M64[k][k];
+    double yk = bcast<LN>(y, k) / E.M64[k][k];
     if (ln == k) y = yk;
     else if (ln > k && ln < NV) y -= E.M64[ln][k] * yk;
   }
 #pragma unroll 1
   for (int k = NV - 1; k >= 0; --k) {
-    double xk = rdl(y, k) / E.M64[k][k];
+    double xk = bcast<LN>(y, k) / E.M64[k][k];
     if (ln == k) y = xk;
     else if (ln < k) y -= E.M64[k][ln] * xk;
   }
@@ -341,26 +354,37 @@ __device__ __forceinline__ void tree_sum_cols(real* col, int stride, bool active
 // adds one frame's row into its parent's.  A step holds no edge into a frame whose own
 // incoming edges are not all done, and no two edges into one parent, so the groups touch
 // disjoint rows and the LDS performs each step's accesses after the previous step's.
+// With fewer than 64 lanes per environment a lane serves several groups, one after the
+// other within each step (the groups of a step touch disjoint rows, so the order of a step's
+// groups does not change any sum).
 template <class L>
 __device__ __forceinline__ void tree_sum_sched16(L& E, int nsteps, int ln) {
-  const int g = ln >> 4, c = ln & 15;
+  constexpr int LN = L::kLanes, NG = SIM_WAVE / LN;   // schedule groups per lane
+  const int c = ln & 15;
   real* col = (c < 6) ? &E.F[0][c] : &E.Ic[0][c - 6];
   const int st = (c < 6) ? 6 : 10;
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  const u32x4* tp = reinterpret_cast<const u32x4*>(&E.t_ts[g][0]);
-  unsigned int w32[SIM_MAXTS / 2];
+  unsigned int w32[NG][SIM_MAXTS / 2];
 #pragma unroll
-  for (int i = 0; i < SIM_MAXTS / 8; ++i) {
-    const u32x4 v = tp[i];
-    w32[4 * i] = v.x; w32[4 * i + 1] = v.y; w32[4 * i + 2] = v.z; w32[4 * i + 3] = v.w;
+  for (int r = 0; r < NG; ++r) {
+    const int g = r * (LN / 16) + (ln >> 4);
+    const u32x4* tp = reinterpret_cast<const u32x4*>(&E.t_ts[g][0]);
+#pragma unroll
+    for (int i = 0; i < SIM_MAXTS / 8; ++i) {
+      const u32x4 v = tp[i];
+      w32[r][4 * i] = v.x; w32[r][4 * i + 1] = v.y; w32[r][4 * i + 2] = v.z; w32[r][4 * i + 3] = v.w;
+    }
   }
 #pragma unroll
   for (int s = 0; s < SIM_MAXTS; ++s) {
     if (s < nsteps) {
-      const unsigned int w = (w32[s >> 1] >> (16 * (s & 1))) & 0xffffu;
-      if (w) {
-        const int j = (int)(w & 31u), p = (int)((w >> 5) & 31u);
-        col[p * st] += col[j * st];
+#pragma unroll
+      for (int r = 0; r < NG; ++r) {
+        const unsigned int w = (w32[r][s >> 1] >> (16 * (s & 1))) & 0xffffu;
+        if (w) {
+          const int j = (int)(w & 31u), p = (int)((w >> 5) & 31u);
+          col[p * st] += col[j * st];
+        }
       }
     }
   }
@@ -370,16 +394,18 @@ __device__ __forceinline__ void tree_sum_sched16(L& E, int nsteps, int ln) {
 // the partial sums of the frame the link names and takes over its link (ceil(log2(depth +
 // 1)) rounds).  Values move between lanes by wavefront permutes, so every lane must be
 // active.
+template <int LN>
 __device__ __forceinline__ sv pull_sv(sv x, int src) {
-  return mksv(mk3(pull(x.a.x, src), pull(x.a.y, src), pull(x.a.z, src)),
-              mk3(pull(x.l.x, src), pull(x.l.y, src), pull(x.l.z, src)));
+  return mksv(mk3(pull_g<LN>(x.a.x, src), pull_g<LN>(x.a.y, src), pull_g<LN>(x.a.z, src)),
+              mk3(pull_g<LN>(x.l.x, src), pull_g<LN>(x.l.y, src), pull_g<LN>(x.l.z, src)));
 }
+template <int LN>
 __device__ __forceinline__ void path_sum2(sv& x, sv& z, int link, int rounds) {
   for (int r = 0; r < rounds; ++r) {
-    const int src = link >= 0 ? link : (int)threadIdx.x;
-    const sv yx = pull_sv(x, src);
-    const sv yz = pull_sv(z, src);
-    const int nl = pull(link, src);
+    const int src = link >= 0 ? link : grp_lane<LN>();
+    const sv yx = pull_sv<LN>(x, src);
+    const sv yz = pull_sv<LN>(z, src);
+    const int nl = pull_g<LN>(link, src);
     if (link >= 0) {
       x = addsv(yx, x);
       z = addsv(yz, z);
@@ -606,13 +632,14 @@ template <int NV, class L>
 __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E,
                                                 const JointRegs& jr, const ContactRegs& cr, int ln,
                                                 Chol& C, bool inplace, int& fb) {
+  constexpr int LN = L::kLanes;
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real g = m->g;
   const real dt = m->dt_sub;
   // reference point O = root position (floating) or world origin
   if (ln < 3) E.O[ln] = m->floating ? E.q[ln] : RL(0.0);
   // clear M
-  for (int i = ln; i < SIM_MAXV * (SIM_MAXV + 1); i += SIM_WAVE) (&E.M[0][0])[i] = RL(0.0);
+  for (int i = ln; i < L::kV * (L::kV + 1); i += LN) (&E.M[0][0])[i] = RL(0.0);
   wsync();
   // ---- local joint rotations (all lanes at once), then kinematics, velocities and bias
   // accelerations along the root paths; each lane keeps its own frame's results in registers
@@ -664,9 +691,9 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       const int src = link >= 0 ? link : ln;
       real Ra[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Ra[k] = pull(R[k], src);
-      const f3 pa = mk3(pull(p.x, src), pull(p.y, src), pull(p.z, src));
-      const int nl = pull(link, src);
+      for (int k = 0; k < 9; ++k) Ra[k] = pull_g<LN>(R[k], src);
+      const f3 pa = mk3(pull_g<LN>(p.x, src), pull_g<LN>(p.y, src), pull_g<LN>(p.z, src));
+      const int nl = pull_g<LN>(link, src);
       if (link >= 0) {
         real Rn[9];
 #pragma unroll
@@ -710,9 +737,9 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     int link = (ln < J) ? jr.par : -1;
     for (int r = 0; r < rounds; ++r) {
       const int src = link >= 0 ? link : ln;
-      const sv Va = pull_sv(V, src);
-      const sv Ca = pull_sv(Cs, src);
-      const int nl = pull(link, src);
+      const sv Va = pull_sv<LN>(V, src);
+      const sv Ca = pull_sv<LN>(Cs, src);
+      const int nl = pull_g<LN>(link, src);
       if (link >= 0) {
         Cs = addsv(addsv(Ca, Cs), crm(Va, V));
         V = addsv(Va, V);
@@ -750,7 +777,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     adh = (d < RL(0.0)) && (f.z < RL(0.0));
   }
   {
-    const unsigned long long bal = __ballot(adh);
+    const unsigned long long bal = grp_ballot<LN>(adh);
     if (ln == 0) E.nadh = __popcll(bal);
   }
   wsync();
@@ -847,8 +874,8 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   }
   wsync();
   // ---- CRBA entries M[va_k][va_i] = S_k . F_i, one (frame, ancestor) pair per lane and round
-  for (int r = 0; r * SIM_WAVE < jr.npair; ++r) {
-    int pi = r * SIM_WAVE + ln;
+  for (int r = 0; r * LN < jr.npair; ++r) {
+    int pi = r * LN + ln;
     int pk = pi < jr.npair ? E.pairs[pi] : 0;
     if (pk) {
       int i = pk & 31, k = (pk >> 5) & 31, vi = (pk >> 10) & 31, vk = (pk >> 15) & 31;
@@ -872,8 +899,8 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   for (int k = 0; k < NV; ++k)
     C.row[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : ((ln == k) ? RL(1.0) : RL(0.0));
   real minpiv;
-  real dmax = wave_max(ln < nv ? E.M[ln < nv ? ln : 0][ln < nv ? ln : 0] : RL(0.0));
-  chol_factor<NV>(C, ln, minpiv);
+  real dmax = grp_max<LN>(ln < nv ? E.M[ln < nv ? ln : 0][ln < nv ? ln : 0] : RL(0.0));
+  chol_factor<NV, LN>(C, ln, minpiv);
   fb = 0;
   if (sizeof(real) == 4 && !(minpiv > m->chol_thr * dmax)) fb = 1;
   real b = ln < nv ? E.vec[ln] : RL(0.0);
@@ -891,7 +918,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     const int lc = ln < NV ? ln : 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) C.col[k] = (ln < NV) ? E.M[k][lc] : RL(0.0);
-    x = chol_solve<NV>(C, ln, b);
+    x = chol_solve<NV, LN>(C, ln, b);
   }
   if (ln < nv) {
     E.qdd[ln] = x;
@@ -941,6 +968,7 @@ template <int NV, class L>
 __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m, L& E,
                                                      const JointRegs& jr, const ContactRegs& cr, int ln,
                                                      const Chol& C, int fb) {
+  constexpr int LN = L::kLanes;
   const int J = m->J, nv = m->nv, nc = m->nc;
   const real dt = m->dt_sub;
   const real g = m->g;
@@ -987,7 +1015,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
   // ---- lambda = M^{-1} qdd_bar with the cached factor (lane = DOF)
   {
     real rb = ln < nv ? dt * E.qdb[ln] : RL(0.0);
-    real lam = fb ? (real)chol64_solve<NV>(E, ln, (double)rb) : chol_solve<NV>(C, ln, rb);
+    real lam = fb ? (real)chol64_solve<NV>(E, ln, (double)rb) : chol_solve<NV, LN>(C, ln, rb);
     if (ln < nv) E.lam[ln] = lam;
   }
   wsync();
@@ -1014,7 +1042,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
   {
     int rounds = 0;
     while ((1 << rounds) <= m->max_depth) ++rounds;
-    path_sum2(A, W, (ln < J) ? jr.par : -1, rounds);
+    path_sum2<LN>(A, W, (ln < J) ? jr.par : -1, rounds);
   }
   if (ln < J) {
     stsv(E.A[ln], A);
@@ -1074,7 +1102,12 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(o + 24, Fn); stsv(o + 30, Ab); stsv(o + 36, Vb);
   }
   wsync();
-  tree_sum_cols(&E.acc[0][ln < 42 ? ln : 0], 42, ln < 42, J, jr.par);
+  // one lane per column of the 42 (several passes with fewer than 42 lanes per environment)
+#pragma unroll
+  for (int c0 = 0; c0 < 42; c0 += LN) {
+    const int c = c0 + ln;
+    tree_sum_cols(&E.acc[0][c < 42 ? c : 0], 42, c < 42, J, jr.par);
+  }
   wsync();
   // ---- derivatives of lambda^T ID per joint (lane = joint)
   if (ln < J) {
@@ -1175,15 +1208,18 @@ __device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, L& E,
   wsync();
 }
 
+// A tape entry moves as whole 16-byte words: the environment's lanes take kTapeBytes / (16 LN)
+// of them each, lane ln the words ln, ln + LN, ...
 template <int NV, class L>
 __device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, real* __restrict__ tp) {
+  constexpr int LN = L::kLanes, NW = L::kTapeBytes / (16 * LN);
   static_assert(offsetof(L, q) == 0, "tape block first");
   static_assert(offsetof(L, tpad) + sizeof(real) * L::kPad - offsetof(L, q) >= (size_t)L::kTapeBytes,
                 "tape entry inside the LDS block");
   real dv = RL(0.0);
 #pragma unroll
   for (int k = 0; k < NV; ++k) dv = (ln == k) ? C.dinv[k] : dv;
-  if (ln < SIM_MAXV) {
+  if (ln < L::kV) {
     E.tdinv[ln] = dv;
     E.tfb[ln] = fb ? RL(1.0) : RL(0.0);
   }
@@ -1193,7 +1229,7 @@ __device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, 
   u32x4* dst = reinterpret_cast<u32x4*>(tp);
   // streaming (non-temporal) stores: the tape must not displace the policy weights in L2
 #pragma unroll
-  for (int i = 0; i < L::kTapeBytes / 1024; ++i) __builtin_nontemporal_store(src[i * SIM_WAVE + ln], &dst[i * SIM_WAVE + ln]);
+  for (int i = 0; i < NW; ++i) __builtin_nontemporal_store(src[i * LN + ln], &dst[i * LN + ln]);
 }
 
 // A tape entry held in registers (16 bytes per lane per KB): the adjoint loads the next
@@ -1201,7 +1237,7 @@ __device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, 
 template <class L>
 struct TapeRegs {
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  u32x4 v[L::kTapeBytes / 1024];
+  u32x4 v[L::kTapeBytes / (16 * L::kLanes)];
 };
 
 template <class L>
@@ -1210,7 +1246,7 @@ __device__ __forceinline__ void tape_prefetch(TapeRegs<L>& P, const real* __rest
   const u32x4* src = reinterpret_cast<const u32x4*>(tp);
   // each lane reads back exactly the 16-byte words it stored (tape_store)
 #pragma unroll
-  for (int i = 0; i < L::kTapeBytes / 1024; ++i) P.v[i] = __builtin_nontemporal_load(&src[i * SIM_WAVE + ln]);
+  for (int i = 0; i < L::kTapeBytes / (16 * L::kLanes); ++i) P.v[i] = __builtin_nontemporal_load(&src[i * L::kLanes + ln]);
 }
 
 // tape_load from a prefetched entry
@@ -1222,7 +1258,7 @@ __device__ __forceinline__ void tape_load_regs(L& E, Chol& C, int& fb, int ln, c
   // need not complete here, and the registers wait for their own loads
   wsync();   // earlier LDS reads of the block complete before it is overwritten
 #pragma unroll
-  for (int i = 0; i < L::kTapeBytes / 1024; ++i) dst[i * SIM_WAVE + ln] = P.v[i];
+  for (int i = 0; i < L::kTapeBytes / (16 * L::kLanes); ++i) dst[i * L::kLanes + ln] = P.v[i];
   wsync();
   const int lr = ln < NV ? ln : 0;
 #pragma unroll
@@ -1231,5 +1267,7 @@ __device__ __forceinline__ void tape_load_regs(L& E, Chol& C, int& fb, int ln, c
     C.col[k] = (ln < NV) ? E.M[k][lr] : RL(0.0);
     C.dinv[k] = E.tdinv[k];
   }
-  fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
+  // uniform over the environment's lanes (its own LDS); over the wavefront only with 64 lanes
+  if constexpr (L::kLanes == SIM_WAVE) fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
+  else fb = (E.tfb[0] != RL(0.0)) ? 1 : 0;
 }

@@ -1,23 +1,48 @@
 // Window kernels (persistent and plain per-step paths) and their launchers, for one
-// arithmetic type.  Included inside the namespace of kernels_f32.hip / kernels_f64.hip.
+// arithmetic type.  Included inside the namespace of one precision by several translation
+// units, which compile in parallel: SIM_EMIT_MAIN emits the full and muscle layouts' windows,
+// the plain path, the weight preparation, the window loss and the group launcher;
+// SIM_EMIT_COMPACT the compact layouts' windows; SIM_EMIT_GROUP_FWD / SIM_EMIT_GROUP_ADJ the
+// forward / adjoint mixed-morphology group kernel.
+#ifndef SIM_EMIT_MAIN
+#define SIM_EMIT_MAIN 0
+#endif
+#ifndef SIM_EMIT_COMPACT
+#define SIM_EMIT_COMPACT 0
+#endif
+#ifndef SIM_EMIT_GROUP_FWD
+#define SIM_EMIT_GROUP_FWD 0
+#endif
+#ifndef SIM_EMIT_GROUP_ADJ
+#define SIM_EMIT_GROUP_ADJ 0
+#endif
+
+// launchers defined by another unit of the same precision
+int launch_compact(const WinArgs& A, int adjoint, int nv, int lanes, void* stream);
+void launch_window_loss(const WinArgs& A, hipStream_t s);
+int launch_group_fwd(const GroupArgs& G, size_t lds_bytes, hipStream_t s);
+int launch_group_adj(const GroupArgs& G, size_t lds_bytes, hipStream_t s);
+int prepare_group_fwd(size_t lds_bytes);
+int prepare_group_adj(size_t lds_bytes);
 
 // ======================================================================= device helpers
-__device__ __forceinline__ bool all_finite_wave(bool ok) {
-  return __all(ok);
+template <int LN>
+__device__ __forceinline__ bool all_finite_env(bool ok) {
+  return grp_all<LN>(ok);
 }
 
 template <class L>
 __device__ __forceinline__ void load_state(const Scal* __restrict__ m, L& E, const real* s, int ln) {
   int nq = m->nq, nv = m->nv;
-  for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = s[i];
-  for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = s[nq + i];
+  for (int i = ln; i < nq; i += L::kLanes) E.q[i] = s[i];
+  for (int i = ln; i < nv; i += L::kLanes) E.qd[i] = s[nq + i];
   if (m->has_last_action)
-    for (int i = ln; i < m->na; i += SIM_WAVE) E.a[i] = s[nq + nv + i];
+    for (int i = ln; i < m->na; i += L::kLanes) E.a[i] = s[nq + nv + i];
   else
-    for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.a[i] = RL(0.0);
+    for (int i = ln; i < L::kMaxA; i += L::kLanes) E.a[i] = RL(0.0);
   if constexpr (L::kMtu > 0) {
     const int o = nq + nv + (m->has_last_action ? m->na : 0);
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = s[o + i];
+    for (int i = ln; i < m->n_mtu; i += L::kLanes) E.act[i] = s[o + i];
   }
   __syncthreads();
 }
@@ -26,32 +51,34 @@ __device__ __forceinline__ void load_state(const Scal* __restrict__ m, L& E, con
 template <class L>
 __device__ __forceinline__ void store_qqd(const Scal* __restrict__ m, const L& E, real* dst, int ln) {
   int nq = m->nq, nv = m->nv;
-  for (int i = ln; i < nq; i += SIM_WAVE) dst[i] = E.q[i];
-  for (int i = ln; i < nv; i += SIM_WAVE) dst[nq + i] = E.qd[i];
+  for (int i = ln; i < nq; i += L::kLanes) dst[i] = E.q[i];
+  for (int i = ln; i < nv; i += L::kLanes) dst[nq + i] = E.qd[i];
   if constexpr (L::kMtu > 0)
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) dst[nq + nv + i] = E.act[i];
+    for (int i = ln; i < m->n_mtu; i += L::kLanes) dst[nq + nv + i] = E.act[i];
 }
 
 template <class L>
 __device__ __forceinline__ void load_qqd(const Scal* __restrict__ m, L& E, const real* src, int ln) {
   int nq = m->nq, nv = m->nv;
-  for (int i = ln; i < nq; i += SIM_WAVE) E.q[i] = src[i];
-  for (int i = ln; i < nv; i += SIM_WAVE) E.qd[i] = src[nq + i];
+  for (int i = ln; i < nq; i += L::kLanes) E.q[i] = src[i];
+  for (int i = ln; i < nv; i += L::kLanes) E.qd[i] = src[nq + i];
   if constexpr (L::kMtu > 0)
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = src[nq + nv + i];
+    for (int i = ln; i < m->n_mtu; i += L::kLanes) E.act[i] = src[nq + nv + i];
   __syncthreads();
 }
 
 // observation normalisation with running statistics (Sec. 3.3): the networks read
 // o_hat = (o - mean) * inv_std, so the observation adjoint is o_hat_bar * inv_std
+template <int LN>
 __device__ __forceinline__ void obs_normalize(const WinArgs& A, const Scal* __restrict__ m, real* o, int ln) {
   if (!A.obs_mean) return;
-  for (int i = ln; i < m->od; i += SIM_WAVE) o[i] = (o[i] - A.obs_mean[i]) * A.obs_inv_std[i];
+  for (int i = ln; i < m->od; i += LN) o[i] = (o[i] - A.obs_mean[i]) * A.obs_inv_std[i];
   __syncthreads();
 }
+template <int LN>
 __device__ __forceinline__ void obs_adjoint_scale(const WinArgs& A, const Scal* __restrict__ m, real* ob, int ln) {
   if (!A.obs_mean) return;
-  for (int i = ln; i < m->od; i += SIM_WAVE) ob[i] *= A.obs_inv_std[i];
+  for (int i = ln; i < m->od; i += LN) ob[i] *= A.obs_inv_std[i];
   __syncthreads();
 }
 
@@ -61,35 +88,35 @@ template <class L>
 __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __restrict__ m, L& E,
                                             int env, int t, int ln) {
   const int N = A.N, od = m->od, na = m->na;
-  task_obs(m, E.q, E.qd, E.a, E.act, E.obs, ln);
+  task_obs<L::kLanes>(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)t * N + env) * od;
-  for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
+  for (int i = ln; i < od; i += L::kLanes) ob[i] = E.obs[i];
   if (A.closed_loop) {
-    obs_normalize(A, m, E.obs, ln);
-    mlp_forward(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
+    obs_normalize<L::kLanes>(A, m, E.obs, ln);
+    mlp_forward<L::kLanes>(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
     // keep the hidden activations for the adjoint's input VJP (at most two hidden layers)
     {
       real* hs = A.hid + ((size_t)t * N + env) * A.hid_w;
       const int d1 = A.actor.nl > 1 ? A.actor.dims[1] : 0, d2 = A.actor.nl > 2 ? A.actor.dims[2] : 0;
-      for (int i = ln; i < d1; i += SIM_WAVE) hs[i] = E.h0[i];
-      for (int i = ln; i < d2; i += SIM_WAVE) hs[d1 + i] = E.h1[i];
+      for (int i = ln; i < d1; i += L::kLanes) hs[i] = E.h0[i];
+      for (int i = ln; i < d2; i += L::kLanes) hs[d1 + i] = E.h1[i];
     }
     if (A.noise) {
       // stochastic policy, reparameterised (Sec. 3.3): y = mu(o) + exp(log_std) * eps
       const real* ep = A.noise + ((size_t)t * N + env) * na;
-      for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, m_fma(m_exp(A.log_std[i]), ep[i], E.y[i]));
+      for (int i = ln; i < na; i += L::kLanes) E.a[i] = squash(m, m_fma(m_exp(A.log_std[i]), ep[i], E.y[i]));
     } else {
-      for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = squash(m, E.y[i]);
+      for (int i = ln; i < na; i += L::kLanes) E.a[i] = squash(m, E.y[i]);
     }
   } else {
     const real* ai = A.actions_in + ((size_t)t * N + env) * na;
-    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = ai[i];
+    for (int i = ln; i < na; i += L::kLanes) E.a[i] = ai[i];
   }
   __syncthreads();
   real r = task_reward(m, E.q, E.qd, E.a, ln);
   if (ln == 0) A.rewards[(size_t)t * N + env] = r;
   real* ao = A.actions + ((size_t)t * N + env) * na;
-  for (int i = ln; i < na; i += SIM_WAVE) ao[i] = E.a[i];
+  for (int i = ln; i < na; i += L::kLanes) ao[i] = E.a[i];
   __syncthreads();
 }
 
@@ -97,23 +124,23 @@ template <class L>
 __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restrict__ m, L& E,
                                            int env, int ln) {
   const int N = A.N, od = m->od, ns = m->ns, nq = m->nq, nv = m->nv, na = m->na;
-  task_obs(m, E.q, E.qd, E.a, E.act, E.obs, ln);
+  task_obs<L::kLanes>(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)A.h * N + env) * od;
-  for (int i = ln; i < od; i += SIM_WAVE) ob[i] = E.obs[i];
-  obs_normalize(A, m, E.obs, ln);
-  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
+  for (int i = ln; i < od; i += L::kLanes) ob[i] = E.obs[i];
+  obs_normalize<L::kLanes>(A, m, E.obs, ln);
+  mlp_forward<L::kLanes>(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
   if (ln == 0) A.value[env] = E.y[0];
   real* so = A.s_h + (size_t)env * ns;
   bool ok = true;
-  for (int i = ln; i < nq; i += SIM_WAVE) { so[i] = E.q[i]; ok = ok && m_isfinite(E.q[i]); }
-  for (int i = ln; i < nv; i += SIM_WAVE) { so[nq + i] = E.qd[i]; ok = ok && m_isfinite(E.qd[i]); }
+  for (int i = ln; i < nq; i += L::kLanes) { so[i] = E.q[i]; ok = ok && m_isfinite(E.q[i]); }
+  for (int i = ln; i < nv; i += L::kLanes) { so[nq + i] = E.qd[i]; ok = ok && m_isfinite(E.qd[i]); }
   if (m->has_last_action)
-    for (int i = ln; i < na; i += SIM_WAVE) so[nq + nv + i] = E.a[i];
+    for (int i = ln; i < na; i += L::kLanes) so[nq + nv + i] = E.a[i];
   if constexpr (L::kMtu > 0) {
     const int o = nq + nv + (m->has_last_action ? na : 0);
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) { so[o + i] = E.act[i]; ok = ok && m_isfinite(E.act[i]); }
+    for (int i = ln; i < m->n_mtu; i += L::kLanes) { so[o + i] = E.act[i]; ok = ok && m_isfinite(E.act[i]); }
   }
-  bool all = all_finite_wave(ok);
+  bool all = all_finite_env<L::kLanes>(ok);
   if (ln == 0 && A.nonfinite) A.nonfinite[env] = all ? 0 : 1;
 }
 
@@ -123,7 +150,7 @@ template <int NV, class L>
 __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
-  const int ln = threadIdx.x;
+  const int ln = grp_lane<L::kLanes>();
   JointRegs jr;
   ContactRegs cr;
   load_regs(A.model, E, ln, jr, cr);
@@ -178,33 +205,33 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
   const int ns = m->ns, nq = m->nq, nv = m->nv, na = m->na, od = m->od;
   const real* sh = A.s_h_in + (size_t)env * ns;
   load_state(m, E, sh, ln);
-  for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = RL(0.0);
-  for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = RL(0.0);
-  for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+  for (int i = ln; i < L::kQ; i += L::kLanes) E.qb[i] = RL(0.0);
+  for (int i = ln; i < L::kV; i += L::kLanes) E.qdb[i] = RL(0.0);
+  for (int i = ln; i < L::kMaxA; i += L::kLanes) E.abar[i] = RL(0.0);
   if constexpr (L::kMtu > 0)
-    for (int i = ln; i < L::kMtu; i += SIM_WAVE) E.act_bar[i] = RL(0.0);
-  for (int i = ln; i < od; i += SIM_WAVE) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
+    for (int i = ln; i < L::kMtu; i += L::kLanes) E.act_bar[i] = RL(0.0);
+  for (int i = ln; i < od; i += L::kLanes) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
   __syncthreads();
-  obs_normalize(A, m, E.obs, ln);
-  mlp_forward(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
+  obs_normalize<L::kLanes>(A, m, E.obs, ln);
+  mlp_forward<L::kLanes>(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
   // terminal value discounted from the start of the last segment (early termination)
   const int eh = m->term ? A.h - A.seg_ws[(size_t)A.h * A.N + env] : A.h;
   real c = -m_pow(A.gamma, (real)eh) * A.scale;
   if (ln == 0) E.y[0] = c;
   __syncthreads();
-  mlp_vjp_input(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
-  obs_adjoint_scale(A, m, E.obs, ln);
+  mlp_vjp_input<L::kLanes>(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
+  obs_adjoint_scale<L::kLanes>(A, m, E.obs, ln);
   // E.obs now holds obs_bar; E.a holds a_prev of s_h
-  task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
+  task_obs_vjp<L::kLanes>(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   if (A.grad_s_h) {
     const real* gs = A.grad_s_h + (size_t)env * ns;
-    for (int i = ln; i < nq; i += SIM_WAVE) E.qb[i] += gs[i];
-    for (int i = ln; i < nv; i += SIM_WAVE) E.qdb[i] += gs[nq + i];
+    for (int i = ln; i < nq; i += L::kLanes) E.qb[i] += gs[i];
+    for (int i = ln; i < nv; i += L::kLanes) E.qdb[i] += gs[nq + i];
     if (m->has_last_action)
-      for (int i = ln; i < na; i += SIM_WAVE) E.abar[i] += gs[nq + nv + i];
+      for (int i = ln; i < na; i += L::kLanes) E.abar[i] += gs[nq + nv + i];
     if constexpr (L::kMtu > 0) {
       const int o = nq + nv + (m->has_last_action ? na : 0);
-      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act_bar[i] += gs[o + i];
+      for (int i = ln; i < m->n_mtu; i += L::kLanes) E.act_bar[i] += gs[o + i];
     }
   }
   __syncthreads();
@@ -221,13 +248,13 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   // frame-start state and a_t
   if (load_start) load_qqd(m, E, A.ckpt + ((size_t)(t * S / A.k) * N + env) * nck, ln);
   const real* at = A.actions_fw + ((size_t)t * N + env) * na;
-  for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+  for (int i = ln; i < na; i += L::kLanes) E.a[i] = at[i];
   __syncthreads();
   const int et = m->term ? t - A.seg_ws[(size_t)t * N + env] : t;
   real c = -m_pow(A.gamma, (real)et) * A.scale;
-  task_reward_vjp(m, E.q, E.qd, E.a, c, E.qb, E.qdb, E.abar, ln);
+  task_reward_vjp<L::kLanes>(m, E.q, E.qd, E.a, c, E.qb, E.qdb, E.abar, ln);
   real* da = A.dL_da + ((size_t)t * N + env) * na;
-  for (int i = ln; i < na; i += SIM_WAVE) da[i] = E.abar[i];
+  for (int i = ln; i < na; i += L::kLanes) da[i] = E.abar[i];
   // a_prev of s_t is a_{t-1} (or the a_prev of s_0); its adjoint starts at zero
   __syncthreads();
   if (A.closed_loop) {
@@ -236,19 +263,19 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
     {
       const real* hs = A.hid + ((size_t)t * N + env) * A.hid_w;
       const int d1 = A.actor.nl > 1 ? A.actor.dims[1] : 0, d2 = A.actor.nl > 2 ? A.actor.dims[2] : 0;
-      for (int i = ln; i < d1; i += SIM_WAVE) E.h0[i] = hs[i];
-      for (int i = ln; i < d2; i += SIM_WAVE) E.h1[i] = hs[d1 + i];
+      for (int i = ln; i < d1; i += L::kLanes) E.h0[i] = hs[i];
+      for (int i = ln; i < d2; i += L::kLanes) E.h1[i] = hs[d1 + i];
     }
     __syncthreads();
-    for (int i = ln; i < na; i += SIM_WAVE) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
+    for (int i = ln; i < na; i += L::kLanes) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
-    mlp_vjp_input(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
-    for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+    mlp_vjp_input<L::kLanes>(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
+    for (int i = ln; i < L::kMaxA; i += L::kLanes) E.abar[i] = RL(0.0);
     __syncthreads();
-    obs_adjoint_scale(A, m, E.obs, ln);
-    task_obs_vjp(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
+    obs_adjoint_scale<L::kLanes>(A, m, E.obs, ln);
+    task_obs_vjp<L::kLanes>(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
   } else {
-    for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+    for (int i = ln; i < L::kMaxA; i += L::kLanes) E.abar[i] = RL(0.0);
     __syncthreads();
   }
   (void)ns;
@@ -260,7 +287,7 @@ template <int NV, class L>
 __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
-  const int ln = threadIdx.x;
+  const int ln = grp_lane<L::kLanes>();
   JointRegs jr;
   ContactRegs cr;
   load_regs(A.model, E, ln, jr, cr);
@@ -272,15 +299,15 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
   for (int t = A.h - 1; t >= 0; --t) {
     if (m->term && A.done_ws[(size_t)t * N + env]) {
       // frame t ended with a reset: s_{t+1} is a constant, nothing flows back through it
-      for (int i = ln; i < SIM_MAXQ; i += SIM_WAVE) E.qb[i] = RL(0.0);
-      for (int i = ln; i < SIM_MAXV; i += SIM_WAVE) E.qdb[i] = RL(0.0);
-      for (int i = ln; i < L::kMaxA; i += SIM_WAVE) E.abar[i] = RL(0.0);
+      for (int i = ln; i < L::kQ; i += L::kLanes) E.qb[i] = RL(0.0);
+      for (int i = ln; i < L::kV; i += L::kLanes) E.qdb[i] = RL(0.0);
+      for (int i = ln; i < L::kMaxA; i += L::kLanes) E.abar[i] = RL(0.0);
       if constexpr (L::kMtu > 0)
-        for (int i = ln; i < L::kMtu; i += SIM_WAVE) E.act_bar[i] = RL(0.0);
+        for (int i = ln; i < L::kMtu; i += L::kLanes) E.act_bar[i] = RL(0.0);
       __syncthreads();
     }
     const real* at = A.actions_fw + ((size_t)t * N + env) * na;
-    for (int i = ln; i < na; i += SIM_WAVE) E.a[i] = at[i];
+    for (int i = ln; i < na; i += L::kLanes) E.a[i] = at[i];
     if (A.tape_full) {
       // the forward stored every substep's pre-state and linearisation; the next (earlier)
       // entry is loaded into registers while the current one is reversed
@@ -328,47 +355,41 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
     adjoint_frame(A, m, E, env, t, ln, false);
   }
   real* d0 = A.dL_ds0 + (size_t)env * ns;
-  for (int i = ln; i < nq; i += SIM_WAVE) d0[i] = E.qb[i];
-  for (int i = ln; i < nv; i += SIM_WAVE) d0[nq + i] = E.qdb[i];
+  for (int i = ln; i < nq; i += L::kLanes) d0[i] = E.qb[i];
+  for (int i = ln; i < nv; i += L::kLanes) d0[nq + i] = E.qdb[i];
   if (m->has_last_action)
-    for (int i = ln; i < na; i += SIM_WAVE) d0[nq + nv + i] = E.abar[i];
+    for (int i = ln; i < na; i += L::kLanes) d0[nq + nv + i] = E.abar[i];
   if constexpr (L::kMtu > 0) {
     const int o = nq + nv + (m->has_last_action ? na : 0);
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) d0[o + i] = E.act_bar[i];
+    for (int i = ln; i < m->n_mtu; i += L::kLanes) d0[o + i] = E.act_bar[i];
   }
 }
 
-template <int NV>
+// One workgroup of one wavefront runs 64 / L::kLanes environments, each on L::kLanes lanes
+// with its own LDS block (full layouts: one environment per wavefront).
+template <int NV, class L>
 __global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
-  __shared__ EnvLDS E;
-  window_fwd_body<NV>(A, blockIdx.x, E);
+  constexpr int EPW = SIM_WAVE / L::kLanes;
+  __shared__ L E[EPW];
+  const int g = EPW == 1 ? 0 : (int)threadIdx.x / L::kLanes;
+  window_fwd_body<NV>(A, blockIdx.x * EPW + g, E[g]);
 }
 
-template <int NV>
+template <int NV, class L>
 __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
-  __shared__ EnvLDS E;
-  window_adj_body<NV>(A, blockIdx.x, E);
-}
-
-// muscle-driven models: the larger LDS layout with activations and muscle terms
-template <int NV>
-__global__ __launch_bounds__(SIM_WAVE) void k_window_fwd_m(WinArgs A) {
-  __shared__ EnvLDSM E;
-  window_fwd_body<NV>(A, blockIdx.x, E);
-}
-
-template <int NV>
-__global__ __launch_bounds__(SIM_WAVE) void k_window_adj_m(WinArgs A) {
-  __shared__ EnvLDSM E;
-  window_adj_body<NV>(A, blockIdx.x, E);
+  constexpr int EPW = SIM_WAVE / L::kLanes;
+  __shared__ L E[EPW];
+  const int g = EPW == 1 ? 0 : (int)threadIdx.x / L::kLanes;
+  window_adj_body<NV>(A, blockIdx.x * EPW + g, E[g]);
 }
 
 // ======================================================================= mixed-morphology group
-// One launch over the envs of several models: block b runs env b - start[s] of the model in
-// work-table slot s (slots ordered by decreasing per-env cost, so the longest windows are
-// dispatched first).  Each slot's model runs the DOF-specialised body of its own kernel.
-// A group with a muscle model reserves the muscle LDS layout for every block; the other
-// slots view the same storage with the torque-model layout.
+// One launch over the envs of several models: block b runs the envs of block b - start[s] of
+// the model in work-table slot s (slots ordered by decreasing per-env cost, so the longest
+// windows are dispatched first).  Each slot's model runs the DOF-specialised body of its own
+// kernel in its own LDS layout: torque models one env per wavefront in the full layout or
+// 64 / lanes envs per wavefront in the compact layout, muscle models the muscle layout.  The
+// block's LDS (dynamic) is the largest any member needs; each slot views it in its layout.
 __device__ __forceinline__ int group_slot(const GroupArgs& G, int b) {
   int s = 0;
   for (int i = 1; i < G.n; ++i) s = (b >= G.start[i]) ? i : s;
@@ -401,22 +422,38 @@ __device__ __forceinline__ void group_muscle(const GroupArgs& G, int s, int env,
   }
 }
 
+template <bool ADJ, int LN>
+__device__ __forceinline__ void group_compact(const GroupArgs& G, int s, int blk, char* buf) {
+  constexpr int EPW = SIM_WAVE / LN;
+  EnvLDSC<LN>* E = reinterpret_cast<EnvLDSC<LN>*>(buf);
+  const int g = EPW == 1 ? 0 : (int)threadIdx.x / LN;
+  const int env = blk * EPW + g;
+  switch (G.nv[s]) {
+#define SIM_GROUP_C(n) case n: group_body<ADJ, n>(G.A[s], env, E[g]); break;
+    SIM_NV_LIST_SMALL(SIM_GROUP_C)
+#undef SIM_GROUP_C
+    default: group_body<ADJ, SIM_CV>(G.A[s], env, E[g]);
+  }
+}
+
 template <bool ADJ>
 __global__ __launch_bounds__(SIM_WAVE) void k_group(GroupArgs G) {
-  __shared__ EnvLDS E;
+  extern __shared__ __attribute__((aligned(16))) char gbuf[];
   const int s = group_slot(G, blockIdx.x);
-  group_torque<ADJ>(G, s, blockIdx.x - G.start[s], E);
+  const int blk = blockIdx.x - G.start[s];
+  if (G.mtu[s]) {
+    group_muscle<ADJ>(G, s, blk, *reinterpret_cast<EnvLDSM*>(gbuf));
+    return;
+  }
+  if constexpr (SIM_COMPACT) {
+    if (G.lanes[s] == 16) { group_compact<ADJ, 16>(G, s, blk, gbuf); return; }
+    if (G.lanes[s] == 32) { group_compact<ADJ, 32>(G, s, blk, gbuf); return; }
+    if (G.lanes[s] == 64) { group_compact<ADJ, 64>(G, s, blk, gbuf); return; }
+  }
+  group_torque<ADJ>(G, s, blk, *reinterpret_cast<EnvLDS*>(gbuf));
 }
 
-template <bool ADJ>
-__global__ __launch_bounds__(SIM_WAVE) void k_group_m(GroupArgs G) {
-  __shared__ __attribute__((aligned(16))) char buf[sizeof(EnvLDSM) > sizeof(EnvLDS) ? sizeof(EnvLDSM) : sizeof(EnvLDS)];
-  const int s = group_slot(G, blockIdx.x);
-  const int env = blockIdx.x - G.start[s];
-  if (G.mtu[s]) group_muscle<ADJ>(G, s, env, *reinterpret_cast<EnvLDSM*>(buf));
-  else group_torque<ADJ>(G, s, env, *reinterpret_cast<EnvLDS*>(buf));
-}
-
+#if SIM_EMIT_MAIN
 // ======================================================================= plain path kernels
 // One launch per frame start and one per substep; the state goes through HBM between
 // launches (ckpt holds every substep's state, k = 1).
@@ -636,33 +673,28 @@ __global__ __launch_bounds__(1024) void k_window_loss(WinArgs A) {
   if (threadIdx.x == 0 && A.loss) A.loss[0] = part[0];
 }
 
-static void launch_window_loss(const WinArgs& A, hipStream_t s) {
+void launch_window_loss(const WinArgs& A, hipStream_t s) {
   if (A.loss_env || A.loss) hipLaunchKernelGGL(k_window_loss, dim3(1), dim3(1024), 0, s, A);
 }
+#endif  // SIM_EMIT_MAIN
 
+template <int NV, class L>
+static void launch_window(const WinArgs& A, int adjoint, hipStream_t s) {
+  dim3 grid(A.N / (SIM_WAVE / L::kLanes)), block(SIM_WAVE);
+  if (adjoint) hipLaunchKernelGGL((k_window_adj<NV, L>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_window_fwd<NV, L>), grid, block, 0, s, A);
+}
+
+#if SIM_EMIT_MAIN
 template <int NV>
-static void launch_forward_nv(const WinArgs& A, int plain, int substeps, int mtu, hipStream_t s) {
+static void launch_plain(const WinArgs& A, int adjoint, int substeps, hipStream_t s) {
   dim3 grid(A.N), block(SIM_WAVE);
-  if (mtu) {
-    hipLaunchKernelGGL(k_window_fwd_m<NV>, grid, block, 0, s, A);
-  } else if (!plain) {
-    hipLaunchKernelGGL(k_window_fwd<NV>, grid, block, 0, s, A);
-  } else {
+  if (!adjoint) {
     for (int t = 0; t < A.h; ++t) {
       hipLaunchKernelGGL(k_plain_frame, grid, block, 0, s, A, t);
       for (int sub = 0; sub < substeps; ++sub) hipLaunchKernelGGL(k_plain_substep<NV>, grid, block, 0, s, A, t, sub);
     }
     hipLaunchKernelGGL(k_plain_end, grid, block, 0, s, A);
-  }
-}
-
-template <int NV>
-static void launch_adjoint_nv(const WinArgs& A, int plain, int substeps, int mtu, hipStream_t s) {
-  dim3 grid(A.N), block(SIM_WAVE);
-  if (mtu) {
-    hipLaunchKernelGGL(k_window_adj_m<NV>, grid, block, 0, s, A);
-  } else if (!plain) {
-    hipLaunchKernelGGL(k_window_adj<NV>, grid, block, 0, s, A);
   } else {
     hipLaunchKernelGGL(k_plain_adj_seed, grid, block, 0, s, A);
     for (int t = A.h - 1; t >= 0; --t) {
@@ -673,61 +705,124 @@ static void launch_adjoint_nv(const WinArgs& A, int plain, int substeps, int mtu
   }
 }
 
+template <int NV>
+static void launch_torque_nv(const WinArgs& A, int adjoint, int plain, int substeps, int lanes, hipStream_t s) {
+  if (plain) launch_plain<NV>(A, adjoint, substeps, s);
+  else launch_window<NV, EnvLDS>(A, adjoint, s);
+  (void)lanes;
+}
+
+#if !SIM_COMPACT
+int launch_compact(const WinArgs&, int, int, int, void*) { return -1; }
+#endif
+
 // Torque-driven models have a kernel per DOF count in SIM_NV_LIST, muscle-driven ones per
-// DOF count in SIM_NV_LIST_MTU; every other model runs the padded 32-DOF kernel.  The
-// plain path exists for torque-driven models only (the host rejects the other case).
-int launch_forward(const WinArgs& A, int plain, int substeps, int nv, int mtu, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
+// DOF count in SIM_NV_LIST_MTU, small models in the compact layout (lanes 16 / 32 / 64) per
+// DOF count in SIM_NV_LIST_SMALL; every other model runs the padded kernel of its layout.  The
+// plain path exists for torque-driven models in the full layout only (the host rejects the
+// other cases).
+static void launch_dispatch(const WinArgs& A, int adjoint, int plain, int substeps, int nv, int mtu, int lanes,
+                            hipStream_t s) {
   if (mtu) {
     switch (nv) {
-#define SIM_CASE_FM(n) case n: launch_forward_nv<n>(A, 0, substeps, 1, s); break;
-      SIM_NV_LIST_MTU(SIM_CASE_FM)
-#undef SIM_CASE_FM
-      default: launch_forward_nv<SIM_MAXV>(A, 0, substeps, 1, s);
+#define SIM_CASE_M(n) case n: launch_window<n, EnvLDSM>(A, adjoint, s); break;
+      SIM_NV_LIST_MTU(SIM_CASE_M)
+#undef SIM_CASE_M
+      default: launch_window<SIM_MAXV, EnvLDSM>(A, adjoint, s);
     }
+  } else if (lanes) {
+    launch_compact(A, adjoint, nv, lanes, s);
   } else {
     switch (nv) {
-#define SIM_CASE_F(n) case n: launch_forward_nv<n>(A, plain, substeps, 0, s); break;
-      SIM_NV_LIST(SIM_CASE_F)
-#undef SIM_CASE_F
-      default: launch_forward_nv<SIM_MAXV>(A, plain, substeps, 0, s);
+#define SIM_CASE_T(n) case n: launch_torque_nv<n>(A, adjoint, plain, substeps, 0, s); break;
+      SIM_NV_LIST(SIM_CASE_T)
+#undef SIM_CASE_T
+      default: launch_torque_nv<SIM_MAXV>(A, adjoint, plain, substeps, 0, s);
     }
   }
+}
+
+int launch_forward(const WinArgs& A, int plain, int substeps, int nv, int mtu, int lanes, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  launch_dispatch(A, 0, plain, substeps, nv, mtu, lanes, s);
   launch_window_loss(A, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_adjoint(const WinArgs& A, int plain, int substeps, int nv, int mtu, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
-  if (mtu) {
-    switch (nv) {
-#define SIM_CASE_AM(n) case n: launch_adjoint_nv<n>(A, 0, substeps, 1, s); break;
-      SIM_NV_LIST_MTU(SIM_CASE_AM)
-#undef SIM_CASE_AM
-      default: launch_adjoint_nv<SIM_MAXV>(A, 0, substeps, 1, s);
-    }
-  } else {
-    switch (nv) {
-#define SIM_CASE_A(n) case n: launch_adjoint_nv<n>(A, plain, substeps, 0, s); break;
-      SIM_NV_LIST(SIM_CASE_A)
-#undef SIM_CASE_A
-      default: launch_adjoint_nv<SIM_MAXV>(A, plain, substeps, 0, s);
-    }
-  }
+int launch_adjoint(const WinArgs& A, int plain, int substeps, int nv, int mtu, int lanes, void* stream) {
+  launch_dispatch(A, 1, plain, substeps, nv, mtu, lanes, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_group(const GroupArgs& G, int adjoint, int mtu, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  dim3 grid(G.start[G.n]), block(SIM_WAVE);
-  if (mtu) {
-    if (adjoint) hipLaunchKernelGGL(k_group_m<true>, grid, block, 0, st, G);
-    else hipLaunchKernelGGL(k_group_m<false>, grid, block, 0, st, G);
-  } else {
-    if (adjoint) hipLaunchKernelGGL(k_group<true>, grid, block, 0, st, G);
-    else hipLaunchKernelGGL(k_group<false>, grid, block, 0, st, G);
+#endif  // SIM_EMIT_MAIN
+
+#if SIM_EMIT_COMPACT
+template <int NV>
+static void launch_compact_nv(const WinArgs& A, int adjoint, int lanes, hipStream_t s) {
+  if (lanes == 16) launch_window<NV, EnvLDSC<16>>(A, adjoint, s);
+  else if (lanes == 32) launch_window<NV, EnvLDSC<32>>(A, adjoint, s);
+  else launch_window<NV, EnvLDSC<64>>(A, adjoint, s);
+}
+
+int launch_compact(const WinArgs& A, int adjoint, int nv, int lanes, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (nv) {
+#define SIM_CASE_C(n) case n: launch_compact_nv<n>(A, adjoint, lanes, s); break;
+    SIM_NV_LIST_SMALL(SIM_CASE_C)
+#undef SIM_CASE_C
+    default: launch_compact_nv<SIM_CV>(A, adjoint, lanes, s);
   }
-  if (!adjoint)
-    for (int s = 0; s < G.n; ++s) launch_window_loss(G.A[s], st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+#endif  // SIM_EMIT_COMPACT
+
+#if SIM_EMIT_MAIN
+// LDS bytes of one group block for a member: muscle layout, full torque layout (lanes 0) or
+// 64 / lanes compact layouts
+size_t group_lds_bytes(int lanes, int mtu) {
+  if (mtu) return sizeof(EnvLDSM);
+  if (!SIM_COMPACT) return sizeof(EnvLDS);
+  if (lanes == 16) return 4 * sizeof(EnvLDSC<16>);
+  if (lanes == 32) return 2 * sizeof(EnvLDSC<32>);
+  if (lanes == 64) return sizeof(EnvLDSC<64>);
+  return sizeof(EnvLDS);
+}
+
+int launch_group(const GroupArgs& G, int adjoint, int mtu, size_t lds_bytes, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  (void)mtu;
+  int bad = adjoint ? launch_group_adj(G, lds_bytes, st) : launch_group_fwd(G, lds_bytes, st);
+  if (!adjoint)
+    for (int s = 0; s < G.n; ++s) launch_window_loss(G.A[s], st);
+  return (bad || hipGetLastError() != hipSuccess) ? -1 : 0;
+}
+
+// the largest dynamic LDS the group kernels may be launched with (above the default limit
+// of 64 KB the kernels must be allowed it once, before any launch or capture)
+int prepare_group(size_t lds_bytes) {
+  if (lds_bytes <= 65536) return 0;
+  return (prepare_group_fwd(lds_bytes) || prepare_group_adj(lds_bytes)) ? -1 : 0;
+}
+#endif  // SIM_EMIT_MAIN
+
+#if SIM_EMIT_GROUP_FWD
+int launch_group_fwd(const GroupArgs& G, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_group<false>, dim3(G.start[G.n]), dim3(SIM_WAVE), lds_bytes, s, G);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int prepare_group_fwd(size_t lds_bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) == hipSuccess ? 0 : -1;
+}
+#endif  // SIM_EMIT_GROUP_FWD
+
+#if SIM_EMIT_GROUP_ADJ
+int launch_group_adj(const GroupArgs& G, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_group<true>, dim3(G.start[G.n]), dim3(SIM_WAVE), lds_bytes, s, G);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int prepare_group_adj(size_t lds_bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group<true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) == hipSuccess ? 0 : -1;
+}
+#endif  // SIM_EMIT_GROUP_ADJ

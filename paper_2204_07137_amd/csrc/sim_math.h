@@ -98,6 +98,36 @@ __device__ __forceinline__ double pull(double x, int src) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// ---- one environment on LN lanes of a wavefront (LN = 16, 32 or 64; an environment's lanes
+// are contiguous and aligned).  With LN = 64 these are the plain wavefront operations.
+template <int LN>
+__device__ __forceinline__ int grp_base() { return LN == SIM_WAVE ? 0 : ((int)threadIdx.x & (SIM_WAVE - LN)); }
+template <int LN>
+__device__ __forceinline__ int grp_lane() { return LN == SIM_WAVE ? (int)threadIdx.x : ((int)threadIdx.x & (LN - 1)); }
+// the value of the environment's lane k (k the same on all lanes of the environment)
+template <int LN, class T>
+__device__ __forceinline__ T bcast(T x, int k) {
+  if constexpr (LN == SIM_WAVE) return rdl(x, k);
+  else return pull(x, grp_base<LN>() + k);
+}
+// the value of the environment's lane src (src chosen per lane); every lane must be active
+template <int LN, class T>
+__device__ __forceinline__ T pull_g(T x, int src) {
+  return pull(x, grp_base<LN>() + src);
+}
+// bits of the environment's lanes in a wavefront ballot
+template <int LN>
+__device__ __forceinline__ unsigned long long grp_ballot(bool p) {
+  const unsigned long long b = __ballot(p);
+  if constexpr (LN == SIM_WAVE) return b;
+  else return (b >> grp_base<LN>()) & ((1ull << LN) - 1ull);
+}
+template <int LN>
+__device__ __forceinline__ bool grp_all(bool p) {
+  if constexpr (LN == SIM_WAVE) return __all(p);
+  else return grp_ballot<LN>(!p) == 0ull;
+}
+
 // ------------------------------------------------------------------ small vector math
 struct f3 { real x, y, z; };
 __device__ __forceinline__ f3 mk3(real a, real b, real c) { f3 r; r.x = a; r.y = b; r.z = c; return r; }
@@ -156,10 +186,11 @@ __device__ __forceinline__ sv iapply(const real* I, sv v) {
   return mksv(add3(Iw, cross3(h, v.l)), add3(scl3(v.l, m), cross3(w, h)));
 }
 
-// wave-wide max (butterfly over 64 lanes)
-__device__ __forceinline__ real wave_max(real x) {
+// max over the environment's LN lanes (butterfly)
+template <int LN>
+__device__ __forceinline__ real grp_max(real x) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = m_fmax(x, __shfl_xor(x, off, SIM_WAVE));
+  for (int off = LN / 2; off >= 1; off >>= 1) x = m_fmax(x, __shfl_xor(x, off, SIM_WAVE));
   return x;
 }
 

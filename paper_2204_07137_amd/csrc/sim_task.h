@@ -122,12 +122,13 @@ __device__ __forceinline__ void load_lane_block(const real* __restrict__ p, real
   }
 }
 
-// Each lane owns NCH consecutive outputs (rows padded to 64 * NCH), so a weight row is one
-// coalesced vector load per lane; 16 input rows are kept in flight.
-template <int NCH>
+// Each of the environment's LN lanes owns NCH consecutive outputs (rows padded to a multiple
+// of 64 = NCH * LN), so a weight row is one coalesced vector load per lane; 16 input rows are
+// kept in flight.
+template <int NCH, int LN>
 __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const real* __restrict__ bb,
                                               const real* in, real* dst, int ni, int no, bool hidden, int ln) {
-  const int nop = NCH * SIM_WAVE;
+  const int nop = NCH * LN;
   real acc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -154,10 +155,10 @@ __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const
 }
 
 // input adjoint of one layer: lane owns NCH consecutive inputs
-template <int NCH>
+template <int NCH, int LN>
 __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const real* g, real* acc_out,
                                               int ni, int no, int ln) {
-  const int nip = NCH * SIM_WAVE;
+  const int nip = NCH * LN;
   real acc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc[c] = RL(0.0);
@@ -174,27 +175,31 @@ __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const 
   for (int c = 0; c < NCH; ++c) acc_out[c] = acc[c];
 }
 
-// x (LDS, dims[0]) -> out (LDS, dims[nl]); hidden activations kept in h0 / h1 (<= 2 hidden)
+// x (LDS, dims[0]) -> out (LDS, dims[nl]); hidden activations kept in h0 / h1 (<= 2 hidden).
+// The BF16 matrix-core layers need a whole wavefront per environment (LN = 64).
+template <int LN>
 __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, real* h0, real* h1,
                                             real* out, uint16_t* xb, int ln) {
-  if (P.bf16) {
-    mlp_forward_bf16(P, x, h0, h1, out, xb, ln);
-    return;
+  if constexpr (LN == SIM_WAVE) {
+    if (P.bf16) {
+      mlp_forward_bf16(P, x, h0, h1, out, xb, ln);
+      return;
+    }
   }
   const real* in = x;
   for (int l = 0; l < P.nl; ++l) {
     int ni = P.dims[l], no = P.dims[l + 1];
     real* dst = (l == P.nl - 1) ? out : ((l & 1) ? h1 : h0);
     bool hidden = l < P.nl - 1;
-    switch (pad64(no) / SIM_WAVE) {
-      case 1: mlp_layer_fwd<1>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      case 2: mlp_layer_fwd<2>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      case 3: mlp_layer_fwd<3>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      case 4: mlp_layer_fwd<4>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      case 5: mlp_layer_fwd<5>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      case 6: mlp_layer_fwd<6>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      case 7: mlp_layer_fwd<7>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
-      default: mlp_layer_fwd<8>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+    switch (pad64(no) / LN) {
+      case 1: mlp_layer_fwd<1, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 2: mlp_layer_fwd<2, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 3: mlp_layer_fwd<3, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 4: mlp_layer_fwd<4, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 5: mlp_layer_fwd<5, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 6: mlp_layer_fwd<6, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      case 7: mlp_layer_fwd<7, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
+      default: mlp_layer_fwd<8, LN>(P.WT[l], P.b[l], in, dst, ni, no, hidden, ln); break;
     }
     wsync();
     in = dst;
@@ -203,32 +208,37 @@ __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, rea
 
 // Given the output adjoint gout (LDS, dims[nl]) and the forward activations kept by
 // mlp_forward, writes the input adjoint to xbar (LDS, dims[0]).  Scratch: gbuf (>= max width).
+// The widths of a layout with LN < 64 lanes are limited to 8 * LN (the host checks).
+#define SIM_MAX_NCH (SIM_MAXHID / SIM_WAVE)
+template <int LN>
 __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, const real* h1,
                                               real* gout, real* gbuf, real* xbar, uint16_t* xb, int ln) {
-  if (P.bf16) {
-    mlp_vjp_input_bf16(P, h0, h1, gout, gbuf, xbar, xb, ln);
-    return;
+  if constexpr (LN == SIM_WAVE) {
+    if (P.bf16) {
+      mlp_vjp_input_bf16(P, h0, h1, gout, gbuf, xbar, xb, ln);
+      return;
+    }
   }
   real* g = gout;
   for (int l = P.nl - 1; l >= 0; --l) {
     int ni = P.dims[l], no = P.dims[l + 1];
     real* dst = (l == 0) ? xbar : gbuf;
-    real acc[SIM_MAXHID / SIM_WAVE];
-    switch (pad64(ni) / SIM_WAVE) {
-      case 1: mlp_layer_vjp<1>(P.W[l], g, acc, ni, no, ln); break;
-      case 2: mlp_layer_vjp<2>(P.W[l], g, acc, ni, no, ln); break;
-      case 3: mlp_layer_vjp<3>(P.W[l], g, acc, ni, no, ln); break;
-      case 4: mlp_layer_vjp<4>(P.W[l], g, acc, ni, no, ln); break;
-      case 5: mlp_layer_vjp<5>(P.W[l], g, acc, ni, no, ln); break;
-      case 6: mlp_layer_vjp<6>(P.W[l], g, acc, ni, no, ln); break;
-      case 7: mlp_layer_vjp<7>(P.W[l], g, acc, ni, no, ln); break;
-      default: mlp_layer_vjp<8>(P.W[l], g, acc, ni, no, ln); break;
+    real acc[SIM_MAX_NCH];
+    switch (pad64(ni) / LN) {
+      case 1: mlp_layer_vjp<1, LN>(P.W[l], g, acc, ni, no, ln); break;
+      case 2: mlp_layer_vjp<2, LN>(P.W[l], g, acc, ni, no, ln); break;
+      case 3: mlp_layer_vjp<3, LN>(P.W[l], g, acc, ni, no, ln); break;
+      case 4: mlp_layer_vjp<4, LN>(P.W[l], g, acc, ni, no, ln); break;
+      case 5: mlp_layer_vjp<5, LN>(P.W[l], g, acc, ni, no, ln); break;
+      case 6: mlp_layer_vjp<6, LN>(P.W[l], g, acc, ni, no, ln); break;
+      case 7: mlp_layer_vjp<7, LN>(P.W[l], g, acc, ni, no, ln); break;
+      default: mlp_layer_vjp<8, LN>(P.W[l], g, acc, ni, no, ln); break;
     }
     wsync();   // every lane has read g before dst (which may alias g) is written
     const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
-    const int nch = pad64(ni) / SIM_WAVE;
+    const int nch = pad64(ni) / LN;
 #pragma unroll
-    for (int c = 0; c < SIM_MAXHID / SIM_WAVE; ++c) {
+    for (int c = 0; c < SIM_MAX_NCH; ++c) {
       const int i = ln * nch + c;
       if (c < nch && i < ni) {
         real v = acc[c];
@@ -259,15 +269,16 @@ __device__ __forceinline__ real squash_grad(const Scal* __restrict__ m, real a) 
 // s = [q | qd | a_prev | act];  obs written to o (LDS).  The muscle task observes the
 // humanoid skeleton entries (no last action), zero padding up to entry 128 and the
 // muscle activations.
+template <int LN>
 __device__ __forceinline__ void task_obs(const Scal* __restrict__ m, const real* q, const real* qd,
                                          const real* aprev, const real* act, real* o, int ln) {
   if (m->task == TASK_NONE) {
     // no task: the observation is the state [q | qd | a_prev | act]
     const int nq = m->nq, nv = m->nv, na = m->has_last_action ? m->na : 0;
-    for (int i = ln; i < nq; i += SIM_WAVE) o[i] = q[i];
-    for (int i = ln; i < nv; i += SIM_WAVE) o[nq + i] = qd[i];
-    for (int i = ln; i < na; i += SIM_WAVE) o[nq + nv + i] = aprev[i];
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) o[nq + nv + na + i] = act[i];
+    for (int i = ln; i < nq; i += LN) o[i] = q[i];
+    for (int i = ln; i < nv; i += LN) o[nq + i] = qd[i];
+    for (int i = ln; i < na; i += LN) o[nq + nv + i] = aprev[i];
+    for (int i = ln; i < m->n_mtu; i += LN) o[nq + nv + na + i] = act[i];
   } else if (m->task == TASK_CARTPOLE) {
     if (ln == 0) {
       real sn, cs;
@@ -285,29 +296,30 @@ __device__ __forceinline__ void task_obs(const Scal* __restrict__ m, const real*
       o[11 + 2 * nh] = RL(1.0) - RL(2.0) * (x * x + y * y) / n2;       // up
       o[12 + 2 * nh] = RL(1.0) - RL(2.0) * (y * y + z * z) / n2;       // heading
     }
-    for (int i = ln; i < nh; i += SIM_WAVE) {
+    for (int i = ln; i < nh; i += LN) {
       o[11 + i] = q[7 + i];
       o[11 + nh + i] = qd[6 + i];
     }
     if (m->has_last_action)
-      for (int i = ln; i < m->na; i += SIM_WAVE) o[13 + 2 * nh + i] = aprev[i];
+      for (int i = ln; i < m->na; i += LN) o[13 + 2 * nh + i] = aprev[i];
     if (m->task == TASK_MTU) {
-      for (int i = 13 + 2 * nh + ln; i < 128; i += SIM_WAVE) o[i] = RL(0.0);
-      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) o[128 + i] = act[i];
+      for (int i = 13 + 2 * nh + ln; i < 128; i += LN) o[i] = RL(0.0);
+      for (int i = ln; i < m->n_mtu; i += LN) o[128 + i] = act[i];
     }
   }
   wsync();
 }
 
 // adjoint of task_obs: adds (d obs / d s)^T obar to (qb, qdb, abar_prev, act_bar)
+template <int LN>
 __device__ __forceinline__ void task_obs_vjp(const Scal* __restrict__ m, const real* q, const real* ob,
                                              real* qb, real* qdb, real* apb, real* actb, int ln) {
   if (m->task == TASK_NONE) {
     const int nq = m->nq, nv = m->nv, na = m->has_last_action ? m->na : 0;
-    for (int i = ln; i < nq; i += SIM_WAVE) qb[i] += ob[i];
-    for (int i = ln; i < nv; i += SIM_WAVE) qdb[i] += ob[nq + i];
-    for (int i = ln; i < na; i += SIM_WAVE) apb[i] += ob[nq + nv + i];
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) actb[i] += ob[nq + nv + na + i];
+    for (int i = ln; i < nq; i += LN) qb[i] += ob[i];
+    for (int i = ln; i < nv; i += LN) qdb[i] += ob[nq + i];
+    for (int i = ln; i < na; i += LN) apb[i] += ob[nq + nv + i];
+    for (int i = ln; i < m->n_mtu; i += LN) actb[i] += ob[nq + nv + na + i];
   } else if (m->task == TASK_CARTPOLE) {
     if (ln == 0) {
       real sn, cs;
@@ -331,14 +343,14 @@ __device__ __forceinline__ void task_obs_vjp(const Scal* __restrict__ m, const r
 #pragma unroll
       for (int k = 0; k < 6; ++k) qdb[k] += ob[5 + k];
     }
-    for (int i = ln; i < nh; i += SIM_WAVE) {
+    for (int i = ln; i < nh; i += LN) {
       qb[7 + i] += ob[11 + i];
       qdb[6 + i] += ob[11 + nh + i];
     }
     if (m->has_last_action)
-      for (int i = ln; i < m->na; i += SIM_WAVE) apb[i] += ob[13 + 2 * nh + i];
+      for (int i = ln; i < m->na; i += LN) apb[i] += ob[13 + 2 * nh + i];
     if (m->task == TASK_MTU)
-      for (int i = ln; i < m->n_mtu; i += SIM_WAVE) actb[i] += ob[128 + i];
+      for (int i = ln; i < m->n_mtu; i += LN) actb[i] += ob[128 + i];
   }
   wsync();
 }
@@ -379,6 +391,7 @@ __device__ __forceinline__ real task_reward(const Scal* __restrict__ m, const re
 }
 
 // adds c * dR/ds to (qb, qdb) and c * dR/da to abar
+template <int LN>
 __device__ __forceinline__ void task_reward_vjp(const Scal* __restrict__ m, const real* q, const real* qd,
                                                 const real* a, real c, real* qb, real* qdb, real* abar,
                                                 int ln) {
@@ -416,9 +429,9 @@ __device__ __forceinline__ void task_reward_vjp(const Scal* __restrict__ m, cons
       }
     }
     if (m->task == TASK_HUMANOID)
-      for (int i = ln; i < m->na; i += SIM_WAVE) abar[i] += c * (-RL(0.004) * a[i]);
+      for (int i = ln; i < m->na; i += LN) abar[i] += c * (-RL(0.004) * a[i]);
     if (m->task == TASK_MTU)
-      for (int i = ln; i < m->na; i += SIM_WAVE) abar[i] += c * (-RL(0.002) * a[i]);
+      for (int i = ln; i < m->na; i += LN) abar[i] += c * (-RL(0.002) * a[i]);
   }
   wsync();
 }

@@ -23,12 +23,30 @@
 // velocities, the Cholesky rows, pivots and flag), plus the frame transforms and the
 // activations for muscle models, padded to whole 1 KB blocks
 #define SIM_TAPE_REALS 2465
+// The compact per-environment LDS layout of small torque-driven models (CartPole, Ant): every
+// table sized for at most SIM_C* entries, about a third of the full layout, so that more
+// environments share a CU and several can share one wavefront (lanes per env 16, 32 or 64).
+#define SIM_CJ 16        // joint frames
+#define SIM_CV 16        // velocity DOFs (position coordinates: SIM_CV + 1)
+#define SIM_CC 16        // contact spheres
+#define SIM_CA 16        // actions
+#define SIM_COBS 64      // observation width
+#define SIM_CHID 128     // MLP width
+#define SIM_CPAIR 64     // mass-matrix pairs
+// reals of the linearisation tape block of a layout for J frames, V DOFs and C contacts:
+// q, qd, S / v / ab / Ib per frame, force / point / velocity / depth per contact, qdd, qdn,
+// the mass-matrix rows (V x (V + 1)), reciprocal pivots and the fallback flag
+constexpr int sim_tape_reals(int J, int V, int C) {
+  return (V + 1) + V + 28 * J + 10 * C + 2 * V + V * (V + 1) + 2 * V;
+}
+static_assert(sim_tape_reals(32, 32, 32) == SIM_TAPE_REALS, "tape block of the full layout");
 // BF16 tile bytes of one layer's forward or input-adjoint operand set
 static inline size_t sim_bf16_tiles_bytes(int n_rows, int n_k) {
   return (size_t)((n_rows + 15) / 16) * ((n_k + 31) / 32) * 64 * 8 * 2;
 }
-static inline size_t sim_tape_bytes(size_t elem, int muscles) {
-  size_t n = SIM_TAPE_REALS + (muscles ? 12 * SIM_MAXJ + SIM_MAXMTU : 0);
+static inline size_t sim_tape_bytes(size_t elem, int muscles, int compact = 0) {
+  size_t n = compact ? (size_t)sim_tape_reals(SIM_CJ, SIM_CV, SIM_CC)
+                     : SIM_TAPE_REALS + (muscles ? 12 * SIM_MAXJ + SIM_MAXMTU : 0);
   return (n * elem + 1023) / 1024 * 1024;
 }
 
@@ -136,9 +154,10 @@ struct WinArgsT {
 template <typename T>
 struct GroupArgsT {
   int n;
-  int start[SIM_MAXGROUP + 1];
+  int start[SIM_MAXGROUP + 1];   // first block of each slot (a block holds 64 / lanes envs)
   int nv[SIM_MAXGROUP];
   int mtu[SIM_MAXGROUP];      // slot's model has muscles
+  int lanes[SIM_MAXGROUP];    // 0: full layout, one env per wavefront; 16 / 32 / 64: compact layout
   WinArgsT<T> A[SIM_MAXGROUP];
 };
 
@@ -209,12 +228,14 @@ struct CriticFitT {
 // Launchers implemented once per arithmetic type (kernels_f32.hip, kernels_f64.hip).
 #define SIM_DECLARE_LAUNCHERS(NS, T)                                                        \
   namespace NS {                                                                            \
-  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, void* stream); \
-  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, void* stream); \
+  int launch_forward(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, int lanes, void* stream); \
+  int launch_adjoint(const WinArgsT<T>& A, int plain, int substeps, int nv, int mtu, int lanes, void* stream); \
   int launch_prep_weights(const T* W, T* WT, T* Wp, int n_out, int n_in, void* stream);   \
   int launch_prep_bf16(const T* W, uint16_t* Pf, uint16_t* Pb, int n_out, int n_in, void* stream); \
   int launch_theta(const ThetaArgsT<T>& A, void* stream);                                  \
-  int launch_group(const GroupArgsT<T>& G, int adjoint, int mtu, void* stream);            \
+  int launch_group(const GroupArgsT<T>& G, int adjoint, int mtu, size_t lds_bytes, void* stream); \
+  size_t group_lds_bytes(int lanes, int mtu);                                              \
+  int prepare_group(size_t lds_bytes);                                                     \
   }
 SIM_DECLARE_LAUNCHERS(sim_f32, float)
 SIM_DECLARE_LAUNCHERS(sim_f64, double)

@@ -43,6 +43,7 @@ def _create(md, **kw):
     o.policy_grad = kw.get("policy_grad", 0)
     o.mlp_precision = kw.get("mlp_precision", 0)
     o.precision = kw.get("precision", 0)
+    o.lanes_per_env = kw.get("lanes", 0)
     h = ctypes.c_void_p()
     rc = P.lib().sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h))
     return rc, P.lib().sim_last_error().decode()
@@ -181,3 +182,24 @@ def test_binding_struct_sizes_and_offsets_match_the_library(struct):
         assert getattr(cls, name).offset == L.sim_abi_layout(sid, i), (struct, name)
     assert L.sim_abi_layout(sid, len(cls._fields_)) == ctypes.c_size_t(-1).value
     assert L.sim_abi_layout(99, 0) == ctypes.c_size_t(-1).value
+
+
+def test_compact_layout_checks():
+    """lanes_per_env (the compact layout, several small envs per wavefront) is checked at
+    sim_create, before anything reaches the device: lane counts, precision, BF16 networks,
+    muscle models, the plain path, models beyond its capacities, and n_envs that do not fill
+    whole wavefronts are refused."""
+    ant = wl.workload("ant", 4)["model"]
+    for lanes, kw, code, text in ((8, {}, -1, "lanes_per_env"),
+                                  (16, dict(precision=1), -6, "FP32"),
+                                  (16, dict(mlp_precision=1), -6, "FP32 MLPs"),
+                                  (16, dict(path=1, k=1), -6, "persistent and tape"),
+                                  (16, dict(n_envs=6), -1, "multiple of 64 / lanes_per_env"),
+                                  (16, dict(critic=[37, 256, 1]), -6, "critic width")):
+        rc, msg = _create(ant, lanes=lanes, **kw)
+        assert rc == code and text in msg, (lanes, kw, rc, msg)
+    rc, msg = _create(wl.humanoid(), lanes=32, critic=[76, 8, 1])
+    assert rc == -6 and "beyond the compact layout" in msg
+    mm = wl.mtu_humanoid()
+    rc, msg = _create(mm, lanes=64, critic=[280, 8, 1])
+    assert rc == -6 and "torque-driven" in msg

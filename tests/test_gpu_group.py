@@ -119,14 +119,18 @@ def test_autotuner_picks_a_valid_configuration():
     print("[tune] ant 64 h=2, unlimited budget", flush=True)
     r = P.tune(W["model"], 64, h, *dims, W["s0"], W["actor"], W["critic"], budget_bytes=1 << 40, reps=2)
     divisors = [k for k in range(1, 17) if 16 % k == 0]
-    assert r["n_candidates"] == len(divisors) + 1
+    # the full layout and the compact one at 64, 32 and 16 lanes per env, each on the tape path
+    # and every checkpoint interval
+    assert r["n_candidates"] == 4 * (len(divisors) + 1)
     assert r["path"] in (P.PATH_TAPE, P.PATH_PERSISTENT) and r["ms_window"] > 0
-    # a budget below the tape path's workspace leaves only checkpointed configurations
-    tape = P.Sim(W["model"], 64, h, *dims, path=P.PATH_TAPE)
-    k16 = P.Sim(W["model"], 64, h, *dims, ckpt_interval=16)
+    assert r["lanes_per_env"] in (0, 16, 32, 64)
+    # a budget below every tape path's workspace leaves only checkpointed configurations
+    tape = P.Sim(W["model"], 64, h, *dims, path=P.PATH_TAPE, lanes_per_env=64)
+    k1 = P.Sim(W["model"], 64, h, *dims, ckpt_interval=1)
+    assert k1.ws_bytes < tape.ws_bytes
     print("[tune] ant 64 h=2, budget below the tape path", flush=True)
     r2 = P.tune(W["model"], 64, h, *dims, W["s0"], W["actor"], W["critic"],
-                budget_bytes=(tape.ws_bytes + k16.ws_bytes) // 2, reps=1)
+                budget_bytes=(tape.ws_bytes + k1.ws_bytes) // 2, reps=1)
     assert r2["path"] == P.PATH_PERSISTENT and r2["workspace_bytes"] < tape.ws_bytes
     with pytest.raises(P.SimError) as e:
         P.tune(W["model"], 64, h, *dims, W["s0"], W["actor"], W["critic"], budget_bytes=1, reps=1)
