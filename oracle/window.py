@@ -63,14 +63,28 @@ def mlp_forward_bf16(layers, x):
     return h
 
 
-def mlp_forward(layers, x):
-    """ELU hidden layers, linear output (App. A.2 network description, LayerNorm off)."""
+def layer_norm(a, g, b, eps):
+    """Layer normalisation of each row of a (Ba, Kiros and Hinton): the row's mean and
+    population variance, a_hat = (a - mean) / sqrt(var + eps), then the gain and bias,
+    g * a_hat + b."""
+    mu = a.mean(-1, keepdim=True)
+    var = ((a - mu) ** 2).mean(-1, keepdim=True)
+    return g * ((a - mu) / torch.sqrt(var + eps)) + b
+
+
+def mlp_forward(layers, x, ln=None, ln_eps=1e-5):
+    """ELU hidden layers, linear output (App. A.2 network description).  ln: None (no
+    normalisation), or per hidden layer the (gain, bias) of a layer normalisation applied to
+    that layer's ELU output (App. A.2: layer normalisation on each hidden layer)."""
     h = x
     n = len(layers)
     for i, (W, b) in enumerate(layers):
         h = h @ W.T + b
         if i < n - 1:
             h = torch.where(h > 0, h, torch.expm1(torch.clamp(h, max=0.0)))
+            if ln is not None:
+                g, beta = ln[i]
+                h = layer_norm(h, g, beta, ln_eps)
     return h
 
 
@@ -136,6 +150,10 @@ def _layers(params):
     return [(_t(W), _t(b)) for (W, b) in params]
 
 
+def _ln(params):
+    return None if params is None else [(_t(g), _t(b)) for (g, b) in params]
+
+
 def fp32_round(x):
     """Each entry rounded to the nearest float32 value (round to nearest even), kept in
     float64.  The derivative is taken as the identity (straight through), so that the
@@ -155,7 +173,8 @@ def normalize_obs(o, obs_norm):
 
 def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, n_total=None,
                   keep_graph=False, layers=None, action_offset=None, bf16=False, noise=None, log_std=None,
-                  reset_states=None, obs_norm=None, diagnostics=True, fp32_floor=False):
+                  reset_states=None, obs_norm=None, diagnostics=True, fp32_floor=False, actor_ln=None,
+                  critic_ln=None, ln_eps=1e-5):
     """Run one window.  Returns a dict of float64 tensors (numpy on request by caller).
 
     s0: [B, n_s]; actions (open loop) [h, B, na] or None (closed loop through ``actor``).
@@ -179,6 +198,8 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     measures how far the window alone carries the rounding of the state that any FP32
     simulator stores (the intrinsic sensitivity floor of an FP32 window).  Off, nothing
     changes.
+    actor_ln / critic_ln: per hidden layer the (gain, bias) of the layer normalisation of the
+    actor's / critic's hidden layers (App. A.2), or None; ln_eps its variance offset.
     The result holds the loss and, in loss_env [B], each env's term of it.
     """
     m = md if isinstance(md, OracleModel) else OracleModel(md)
@@ -189,6 +210,8 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         layers = (_layers(actor) if actor is not None else None,
                   _layers(critic) if critic is not None else None)
     act_l, crit_l = layers
+    a_ln = actor_ln if actor_ln is None or torch.is_tensor(actor_ln[0][0]) else _ln(actor_ln)
+    c_ln = critic_ln if critic_ln is None or torch.is_tensor(critic_ln[0][0]) else _ln(critic_ln)
     if fp32_floor:
         s = fp32_round(s)
         act_l = [(fp32_round(W), fp32_round(b)) for (W, b) in act_l] if act_l is not None else None
@@ -196,7 +219,12 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     rnd = fp32_round if fp32_floor else (lambda x: x)
     nq, nv = m.nq, m.nv
     dt = m.dt / m.substeps
-    mlp = mlp_forward_bf16 if bf16 else mlp_forward
+    if bf16:
+        if a_ln is not None or c_ln is not None:
+            raise ValueError("layer normalisation is not modelled with BF16 networks")
+        mlp = lambda lay, x, ln=None: mlp_forward_bf16(lay, x)
+    else:
+        mlp = lambda lay, x, ln=None: mlp_forward(lay, x, ln, ln_eps)
     states, obs, acts, rews = [s], [], [], []
     term_h = m.md.get("term_height") if reset_states is not None else None
     t0 = torch.zeros(B, dtype=torch.long)
@@ -205,7 +233,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
     for t in range(h):
         o = obs_fn(m, s)
         if actions is None:
-            y = mlp(act_l, normalize_obs(o, obs_norm))
+            y = mlp(act_l, normalize_obs(o, obs_norm), a_ln)
             if noise is not None:
                 ls = log_std if torch.is_tensor(log_std) else _t(log_std)
                 y = y + torch.exp(ls) * (noise[t] if torch.is_tensor(noise) else _t(noise[t]))
@@ -242,7 +270,7 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
         rews.append(r)
     o_h = obs_fn(m, s)
     obs.append(o_h)
-    value = mlp(crit_l, normalize_obs(o_h, obs_norm))[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
+    value = mlp(crit_l, normalize_obs(o_h, obs_norm), c_ln)[:, 0] if crit_l is not None else torch.zeros(B, dtype=F64)
     if term_h is None:
         disc = sum(gamma ** t * rews[t] for t in range(h))
         loss = -(disc + gamma ** h * value).sum() / (N * h)
@@ -261,10 +289,13 @@ def oracle_window(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99, 
 
 def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=0.99,
                         n_total=None, want_theta=False, bf16=False, noise=None, log_std=None,
-                        reset_states=None, obs_norm=None, fp32_floor=False):
+                        reset_states=None, obs_norm=None, fp32_floor=False, actor_ln=None, critic_ln=None,
+                        ln_eps=1e-5):
     """Window forward plus its exact reverse (App. A.1) by reverse-mode differentiation.
     fp32_floor: as for oracle_window (the FP32 storage floor); the gradients are then the
     FP64 adjoint along the rounded trajectory.
+    actor_ln / critic_ln, ln_eps: as for oracle_window; with want_theta the result also holds
+    dL_dln, the (gain, bias) gradients of the actor's layer normalisations.
 
     Returns numpy arrays: s_h, obs [h+1,B,od], actions [h,B,na], rewards [h,B],
     value [B], loss, dL/da [h,B,na], dL/ds0 [B,n_s] and, if asked, dL/dtheta as a
@@ -282,14 +313,22 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
     ls = None
     if noise is not None:
         ls = _t(log_std).clone().requires_grad_(want_theta)
+    a_ln = None
+    if actor_ln is not None:
+        a_ln = [(_t(g).clone().requires_grad_(want_theta), _t(b).clone().requires_grad_(want_theta))
+                for (g, b) in actor_ln]
     out = oracle_window(md, s0t, h, actor, critic, act_in, gamma, n_total, keep_graph=True,
                         layers=layers, bf16=bf16, noise=noise, log_std=ls, reset_states=reset_states,
-                        obs_norm=obs_norm, fp32_floor=fp32_floor)
+                        obs_norm=obs_norm, fp32_floor=fp32_floor, actor_ln=a_ln, critic_ln=critic_ln,
+                        ln_eps=ln_eps)
     wrt = [s0t] + list(out["actions"])
     theta = []
     if want_theta and actor is not None:
         for (W, b) in layers[0]:
             theta += [W, b]
+        if a_ln is not None:
+            for (g, b) in a_ln:
+                theta += [g, b]
         if ls is not None:
             theta.append(ls)
     g = torch.autograd.grad(out["loss"], wrt + theta, allow_unused=True)
@@ -316,6 +355,9 @@ def oracle_window_grads(md, s0, h, actor=None, critic=None, actions=None, gamma=
         if ls is not None:
             res["dL_dlog_std"] = gt[-1].numpy()
             gt = gt[:-1]
-        res["dL_dtheta"] = [(gt[2 * i].numpy(), gt[2 * i + 1].numpy())
-                            for i in range(len(gt) // 2)]
+        nl = len(layers[0])
+        res["dL_dtheta"] = [(gt[2 * i].numpy(), gt[2 * i + 1].numpy()) for i in range(nl)]
+        if a_ln is not None:
+            res["dL_dln"] = [(gt[2 * nl + 2 * i].numpy(), gt[2 * nl + 2 * i + 1].numpy())
+                             for i in range(len(a_ln))]
     return res

@@ -64,6 +64,7 @@ struct SimHandle {
   size_t bf_actor_off[SIM_MAXL][2], bf_critic_off[SIM_MAXL][2];   // BF16 forward / adjoint tiles
   size_t off_ckpt = 0, off_adj = 0, off_tape = 0, off_done = 0, off_seg = 0, off_hid = 0, ws_bytes = 0;
   int hid_w = 0;   // the actor's hidden widths, summed (closed loop)
+  int tape_ws = 0;   // reals between consecutive tape entries
   // policy-gradient scratch: two layer-adjoint buffers, split partials (the hidden
   // activations are the window's own, at off_hid)
   size_t off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
@@ -186,6 +187,8 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   d.ts_steps = s.ts_steps;
   d.npair = s.npair;
   for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
+  d.tape_nw = s.tape_nw;
+  for (int w = 0; w < SIM_MAXTAPEW; ++w) d.tape_off[w] = s.tape_off[w];
   d.tau_act = (T)s.tau_act; d.fl_w = (T)s.fl_w; d.vmax = (T)s.vmax;
   d.term_h = (T)s.term_h;
   for (int i = 0; i < SIM_MAXMTU; ++i) {
@@ -439,6 +442,40 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
   return SIM_OK;
 }
 
+// The words of a packed tape entry (the fields the adjoint reads, at the model's own sizes) and
+// the block offset of each, for the LDS layout the handle runs in (capacities J, V, C):
+// q, qd, S / v / ab / Ib of the frames, the contacts' force / point / velocity / depth, qdd,
+// the lower triangle of the Cholesky factor row by row, the reciprocal pivots, the fallback
+// flag, and for muscle models the frame rotations and positions and the activations.
+static void build_tape_map(DevModelT<double>& m, int J, int V, int C) {
+  const SimTapeLayout T = sim_tape_layout(J, V, C);
+  int w = 0;
+  auto run = [&](int base, int n) {
+    for (int i = 0; i < n; ++i) m.tape_off[w++] = (unsigned short)(base + i);
+  };
+  run(T.q, m.nq);
+  run(T.qd, m.nv);
+  run(T.S, 6 * m.J);
+  run(T.v, 6 * m.J);
+  run(T.ab, 6 * m.J);
+  run(T.Ib, 10 * m.J);
+  run(T.cf, 3 * m.nc);
+  run(T.cx, 3 * m.nc);
+  run(T.cvel, 3 * m.nc);
+  run(T.cdep, m.nc);
+  run(T.qdd, m.nv);
+  for (int r = 0; r < m.nv; ++r) run(T.M + r * (V + 1), r + 1);
+  run(T.tdinv, m.nv);
+  run(T.tfb, 1);
+  if (m.n_mtu > 0) {
+    run(T.R, 9 * m.J);
+    run(T.p, 3 * m.J);
+    run(T.act, m.n_mtu);
+  }
+  m.tape_nw = w;
+  for (int i = w; i < SIM_MAXTAPEW; ++i) m.tape_off[i] = 0;
+}
+
 extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHandle** out) {
   if (!md || !opt || !out) return fail(SIM_E_ARG, "sim_create: null argument");
   *out = nullptr;
@@ -449,6 +486,8 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   if (rc) return rc;
   SimHandle* h = new SimHandle();
   m.chol_thr = opt->chol_fp64_threshold;
+  if (opt->lanes_per_env) build_tape_map(m, SIM_CJ, SIM_CV, SIM_CC);
+  else build_tape_map(m, SIM_MAXJ, SIM_MAXV, SIM_MAXC);
   h->m64 = m;
   convert_model(m, h->m32);
   h->opt = *opt;
@@ -518,7 +557,9 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   const size_t tape_entries = (opt->path == SIM_PATH_TAPE) ? (size_t)opt->horizon * m.substeps * N
                               : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
   h->off_tape = off;
-  off = align256(off + tape_entries * sim_tape_bytes(e, m.n_mtu > 0, opt->lanes_per_env != 0));
+  // packed entries, each rounded up to 64 reals
+  h->tape_ws = (m.tape_nw + 63) / 64 * 64;
+  off = align256(off + tape_entries * (size_t)h->tape_ws * e);
   h->off_done = off;
   off = align256(off + (size_t)opt->horizon * N);
   h->off_seg = off;
@@ -658,6 +699,7 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (h->opt.path == SIM_PATH_TAPE);
+  A.tape_ws = h->tape_ws;
   A.reset = static_cast<const T*>(io->reset_states);
   A.done_out = io->done;
   A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
@@ -692,6 +734,7 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (o.path == SIM_PATH_TAPE);
+  A.tape_ws = h->tape_ws;
   A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
   A.seg_ws = reinterpret_cast<int*>(ws + h->off_seg);
   A.obs_in = static_cast<const T*>(io->obs);

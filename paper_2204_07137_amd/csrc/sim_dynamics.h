@@ -50,18 +50,15 @@ struct EnvLDST {
   static constexpr int kMaxA = MAXA;
   static constexpr int kLanes = LANES;
   static constexpr int kJ = CJ, kV = CV, kQ = CV + 1, kC = CC, kObs = COBS, kHid = CHID, kPair = CPAIR;
-  // reals of the tape entry: the block below up to and including tfb, plus the frame
-  // transforms and activations for muscle models
-  static constexpr int kTapeBase = sim_tape_reals(CJ, CV, CC);
-  static constexpr int kTapeUsed = kTapeBase + (NMTU > 0 ? 12 * CJ + NMTU : 0);
-  static constexpr int kTapeBytes = (kTapeUsed * (int)sizeof(real) + 1023) / 1024 * 1024;
-  static constexpr int kTapeReals = kTapeBytes / (int)sizeof(real);   // stride of one tape entry
-  static constexpr int kBlockReals = kTapeBase + 12 * CJ + NMTU;
-  static constexpr int kPad = kTapeReals > kBlockReals ? kTapeReals - kBlockReals : 0;
-  // The linearisation of the current substep, one contiguous 1 KB-padded block so that it
-  // moves to and from HBM as whole 64-lane x 16-byte transfers (the linearisation tape).
-  // For torque-driven models the entry ends inside R (R and p are then rebuilt by any
-  // recomputation and never read by the adjoint).
+  // the most words a packed tape entry of this layout can hold (every frame, DOF and contact
+  // in use: the lower triangle of the factor, no new velocities), and per lane
+  static constexpr int kTapeMaxWords = (CV + 1) + CV + 28 * CJ + 10 * CC + CV + CV * (CV + 1) / 2 + CV + 1 +
+                                       (NMTU > 0 ? 12 * CJ + NMTU : 0);
+  static constexpr int kTapeWordsPerLane = (kTapeMaxWords + LANES - 1) / LANES;
+  // The linearisation of the current substep, one contiguous block whose fields
+  // sim_tape_layout describes; a tape entry holds the words of it that the model uses
+  // (for torque-driven models no R and p: those are rebuilt by any recomputation and never
+  // read by the adjoint).
   struct __attribute__((aligned(16))) {
     real q[CV + 1], qd[CV];   // state before the substep
     real S[CJ][6], v[CJ][6], ab[CJ][6], Ib[CJ][10];
@@ -71,7 +68,6 @@ struct EnvLDST {
     real tdinv[CV], tfb[CV];
     real R[CJ][9], p[CJ][3];
     real act[NMTU];                    // muscle activations before the substep
-    real tpad[kPad];
   };
   real a[MAXA];
   real qn[CV + 1];
@@ -1208,14 +1204,27 @@ __device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, L& E,
   wsync();
 }
 
-// A tape entry moves as whole 16-byte words: the environment's lanes take kTapeBytes / (16 LN)
-// of them each, lane ln the words ln, ln + LN, ...
+// The block's fields sit where sim_tape_layout says (the host builds the word maps from it).
+template <class L>
+__device__ __forceinline__ constexpr bool tape_layout_ok() {
+  constexpr SimTapeLayout T = sim_tape_layout(L::kJ, L::kV, L::kC);
+  constexpr size_t r = sizeof(real);
+  return offsetof(L, qd) == T.qd * r && offsetof(L, S) == T.S * r && offsetof(L, v) == T.v * r &&
+         offsetof(L, ab) == T.ab * r && offsetof(L, Ib) == T.Ib * r && offsetof(L, cf) == T.cf * r &&
+         offsetof(L, cx) == T.cx * r && offsetof(L, cvel) == T.cvel * r && offsetof(L, cdep) == T.cdep * r &&
+         offsetof(L, qdd) == T.qdd * r && offsetof(L, qdn) == T.qdn * r && offsetof(L, M) == T.M * r &&
+         offsetof(L, tdinv) == T.tdinv * r && offsetof(L, tfb) == T.tfb * r && offsetof(L, R) == T.R * r &&
+         offsetof(L, p) == T.p * r && (L::kMtu == 0 || offsetof(L, act) == T.act * r);
+}
+
+// A packed tape entry: word w of the entry is real m->tab->tape_off[w] of the block; lane ln
+// of the environment moves words ln, ln + LN, ...  (consecutive lanes, consecutive words).
 template <int NV, class L>
-__device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, real* __restrict__ tp) {
-  constexpr int LN = L::kLanes, NW = L::kTapeBytes / (16 * LN);
+__device__ __forceinline__ void tape_store(const Scal* __restrict__ m, L& E, const Chol& C, int fb, int ln,
+                                           real* __restrict__ tp) {
   static_assert(offsetof(L, q) == 0, "tape block first");
-  static_assert(offsetof(L, tpad) + sizeof(real) * L::kPad - offsetof(L, q) >= (size_t)L::kTapeBytes,
-                "tape entry inside the LDS block");
+  static_assert(tape_layout_ok<L>(), "LDS block as sim_tape_layout describes it");
+  constexpr int LN = L::kLanes;
   real dv = RL(0.0);
 #pragma unroll
   for (int k = 0; k < NV; ++k) dv = (ln == k) ? C.dinv[k] : dv;
@@ -1224,48 +1233,71 @@ __device__ __forceinline__ void tape_store(L& E, const Chol& C, int fb, int ln, 
     E.tfb[ln] = fb ? RL(1.0) : RL(0.0);
   }
   wsync();
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  const u32x4* src = reinterpret_cast<const u32x4*>(&E.q[0]);
-  u32x4* dst = reinterpret_cast<u32x4*>(tp);
+  const real* blk = &E.q[0];
+  const unsigned short* __restrict__ off = m->tab->tape_off;
+  const int nw = m->tape_nw;
   // streaming (non-temporal) stores: the tape must not displace the policy weights in L2
 #pragma unroll
-  for (int i = 0; i < NW; ++i) __builtin_nontemporal_store(src[i * LN + ln], &dst[i * LN + ln]);
+  for (int i = 0; i < L::kTapeWordsPerLane; ++i) {
+    const int w = i * LN + ln;
+    if (w < nw) __builtin_nontemporal_store(blk[off[w]], &tp[w]);
+  }
 }
 
-// A tape entry held in registers (16 bytes per lane per KB): the adjoint loads the next
-// entry while the current substep's reverse runs, so the load latency is hidden.
+// A tape entry held in registers (the lane's words): the adjoint loads the next entry while
+// the current substep's reverse runs, so the load latency is hidden.
 template <class L>
 struct TapeRegs {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  u32x4 v[L::kTapeBytes / (16 * L::kLanes)];
+  real v[L::kTapeWordsPerLane];
 };
 
 template <class L>
-__device__ __forceinline__ void tape_prefetch(TapeRegs<L>& P, const real* __restrict__ tp, int ln) {
-  typedef typename TapeRegs<L>::u32x4 u32x4;
-  const u32x4* src = reinterpret_cast<const u32x4*>(tp);
-  // each lane reads back exactly the 16-byte words it stored (tape_store)
+__device__ __forceinline__ void tape_prefetch(const Scal* __restrict__ m, TapeRegs<L>& P, const real* __restrict__ tp,
+                                              int ln) {
+  constexpr int LN = L::kLanes;
+  const int nw = m->tape_nw;
 #pragma unroll
-  for (int i = 0; i < L::kTapeBytes / (16 * L::kLanes); ++i) P.v[i] = __builtin_nontemporal_load(&src[i * L::kLanes + ln]);
+  for (int i = 0; i < L::kTapeWordsPerLane; ++i) {
+    const int w = i * LN + ln;
+    P.v[i] = (w < nw) ? __builtin_nontemporal_load(&tp[w]) : RL(0.0);
+  }
 }
 
-// tape_load from a prefetched entry
+// tape_load from a prefetched entry: the words back into the block, the new velocities
+// rebuilt as the forward computed them (qdn = qd + dt qdd), the factor into registers
 template <int NV, class L>
-__device__ __forceinline__ void tape_load_regs(L& E, Chol& C, int& fb, int ln, const TapeRegs<L>& P) {
-  typedef typename TapeRegs<L>::u32x4 u32x4;
-  u32x4* dst = reinterpret_cast<u32x4*>(&E.q[0]);
+__device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, L& E, Chol& C, int& fb, int ln,
+                                               const TapeRegs<L>& P) {
+  constexpr int LN = L::kLanes;
+  real* blk = &E.q[0];
+  const unsigned short* __restrict__ off = m->tab->tape_off;
+  const int nw = m->tape_nw;
   // LDS ordering only (one wavefront per environment): the tape stores still in flight
   // need not complete here, and the registers wait for their own loads
   wsync();   // earlier LDS reads of the block complete before it is overwritten
 #pragma unroll
-  for (int i = 0; i < L::kTapeBytes / (16 * L::kLanes); ++i) dst[i * L::kLanes + ln] = P.v[i];
+  for (int i = 0; i < L::kTapeWordsPerLane; ++i) {
+    const int w = i * LN + ln;
+    if (w < nw) blk[off[w]] = P.v[i];
+  }
   wsync();
-  const int lr = ln < NV ? ln : 0;
+  if (ln < m->nv) {
+    const real dt = m->dt_sub;
+    real qdn = E.qd[ln] + dt * E.qdd[ln];
+    E.qdn[ln] = qdn;
+  }
+  wsync();
+  // the entry holds the model's nv rows of the factor (lower triangle) and pivots; a kernel
+  // compiled for NV > nv pads the matrix with the identity, whose factor is the identity
+  // (pivots 1), as the forward's factorisation left it
+  const int nv = m->nv;
+  const int lr = ln < nv ? ln : 0;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    C.row[k] = (ln < NV) ? E.M[lr][k] : RL(0.0);
-    C.col[k] = (ln < NV) ? E.M[k][lr] : RL(0.0);
-    C.dinv[k] = E.tdinv[k];
+    const real pad = (ln == k) ? RL(1.0) : RL(0.0);
+    C.row[k] = (ln < nv && k < nv) ? E.M[lr][k] : pad;
+    C.col[k] = (ln < nv && k < nv) ? E.M[k][lr] : pad;
+    C.dinv[k] = (k < nv) ? E.tdinv[k] : RL(1.0);
   }
   // uniform over the environment's lanes (its own LDS); over the wavefront only with 64 lanes
   if constexpr (L::kLanes == SIM_WAVE) fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);

@@ -167,7 +167,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
       if (A.tape_full) {
         // the tape entry holds the pre-substep state and the linearisation
         substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-        tape_store<NV>(E, C, fb, ln, A.tape + ((size_t)gi * N + env) * L::kTapeReals);
+        tape_store<NV>(m, E, C, fb, ln, A.tape + ((size_t)gi * N + env) * A.tape_ws);
         commit_substep(m, E, ln);
       } else {
         if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
@@ -312,16 +312,16 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
       // the forward stored every substep's pre-state and linearisation; the next (earlier)
       // entry is loaded into registers while the current one is reversed
       TapeRegs<L> P;
-      tape_prefetch(P, A.tape + (((size_t)t * S + S - 1) * N + env) * L::kTapeReals, ln);
+      tape_prefetch(m, P, A.tape + (((size_t)t * S + S - 1) * N + env) * A.tape_ws, ln);
       for (int sub = S - 1; sub >= 0; --sub) {
         int fb;
-        tape_load_regs<NV>(E, C, fb, ln, P);
-        if (sub > 0) tape_prefetch(P, A.tape + (((size_t)t * S + sub - 1) * N + env) * L::kTapeReals, ln);
+        tape_load_regs<NV>(m, E, C, fb, ln, P);
+        if (sub > 0) tape_prefetch(m, P, A.tape + (((size_t)t * S + sub - 1) * N + env) * A.tape_ws, ln);
         if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
       }
     } else {
-      real* tseg = A.tape + (size_t)env * (k - 1) * L::kTapeReals;
+      real* tseg = A.tape + (size_t)env * (k - 1) * A.tape_ws;
       for (int sg = S / k - 1; sg >= 0; --sg) {
         int c = (t * S + sg * k) / k;
         const real* ck = A.ckpt + ((size_t)c * N + env) * nqv;
@@ -331,7 +331,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         for (int i = 0; i < k - 1; ++i) {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          tape_store<NV>(E, C, fb, ln, tseg + (size_t)i * L::kTapeReals);
+          tape_store<NV>(m, E, C, fb, ln, tseg + (size_t)i * A.tape_ws);
           commit_substep(m, E, ln);
         }
         // the segment's recorded entries are loaded into registers one ahead of their use
@@ -339,13 +339,13 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          if (k >= 2) tape_prefetch(P, tseg + (size_t)(k - 2) * L::kTapeReals, ln);
+          if (k >= 2) tape_prefetch(m, P, tseg + (size_t)(k - 2) * A.tape_ws, ln);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
         for (int i = k - 2; i >= 0; --i) {
           int fb;
-          tape_load_regs<NV>(E, C, fb, ln, P);
-          if (i > 0) tape_prefetch(P, tseg + (size_t)(i - 1) * L::kTapeReals, ln);
+          tape_load_regs<NV>(m, E, C, fb, ln, P);
+          if (i > 0) tape_prefetch(m, P, tseg + (size_t)(i - 1) * A.tape_ws, ln);
           if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }

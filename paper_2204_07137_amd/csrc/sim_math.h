@@ -17,6 +17,7 @@ typedef GroupArgsT<real> GroupArgs;
 struct Scal {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth, ts_steps, term;
   int n_mtu, n_motor, nck;
+  int tape_nw;           // words of a packed tape entry
   real dt_sub, g, kn, kd, kt, mu, klim, chol_thr;
   real tau_act, fl_w, vmax, term_h;
   const DevModel* tab;   // the model's tables (muscle paths) in global memory
@@ -31,6 +32,7 @@ __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   s.n_mtu = m->n_mtu; s.n_motor = m->n_motor; s.nck = m->nck;
   s.tau_act = m->tau_act; s.fl_w = m->fl_w; s.vmax = m->vmax;
   s.term = m->term; s.term_h = m->term_h;
+  s.tape_nw = m->tape_nw;
   s.tab = m;
   return s;
 }

@@ -40,14 +40,29 @@ constexpr int sim_tape_reals(int J, int V, int C) {
   return (V + 1) + V + 28 * J + 10 * C + 2 * V + V * (V + 1) + 2 * V;
 }
 static_assert(sim_tape_reals(32, 32, 32) == SIM_TAPE_REALS, "tape block of the full layout");
+// Offsets (in reals from the block's start) of the fields of the linearisation block of a
+// layout with capacities J frames, V DOFs, C contacts, in their order in LDS: the state before
+// the substep, per frame the screw, velocity, bias acceleration and spatial inertia, per contact
+// the force, point, velocity and depth, the accelerations, new velocities, mass-matrix rows
+// (then the Cholesky rows), reciprocal pivots, fallback flag, frame rotations and positions
+// and the muscle activations.
+struct SimTapeLayout { int q, qd, S, v, ab, Ib, cf, cx, cvel, cdep, qdd, qdn, M, tdinv, tfb, R, p, act; };
+constexpr SimTapeLayout sim_tape_layout(int J, int V, int C) {
+  return SimTapeLayout{0, V + 1, 2 * V + 1, 2 * V + 1 + 6 * J, 2 * V + 1 + 12 * J, 2 * V + 1 + 18 * J,
+                       2 * V + 1 + 28 * J, 2 * V + 1 + 28 * J + 3 * C, 2 * V + 1 + 28 * J + 6 * C,
+                       2 * V + 1 + 28 * J + 9 * C, 2 * V + 1 + 28 * J + 10 * C, 3 * V + 1 + 28 * J + 10 * C,
+                       4 * V + 1 + 28 * J + 10 * C, 4 * V + 1 + 28 * J + 10 * C + V * (V + 1),
+                       5 * V + 1 + 28 * J + 10 * C + V * (V + 1), 6 * V + 1 + 28 * J + 10 * C + V * (V + 1),
+                       6 * V + 1 + 37 * J + 10 * C + V * (V + 1), 6 * V + 1 + 40 * J + 10 * C + V * (V + 1)};
+}
+// The tape entry of a substep holds only the fields the reverse reads, for the model's own
+// sizes: q (nq), qd (nv), S / v / ab / Ib of its J frames, the nc contacts' data, qdd, the lower
+// triangle of the Cholesky factor row by row, the reciprocal pivots and the flag (muscle models
+// also R, p and the activations); word w of an entry comes from block real tape_off[w].
+#define SIM_MAXTAPEW 2432
 // BF16 tile bytes of one layer's forward or input-adjoint operand set
 static inline size_t sim_bf16_tiles_bytes(int n_rows, int n_k) {
   return (size_t)((n_rows + 15) / 16) * ((n_k + 31) / 32) * 64 * 8 * 2;
-}
-static inline size_t sim_tape_bytes(size_t elem, int muscles, int compact = 0) {
-  size_t n = compact ? (size_t)sim_tape_reals(SIM_CJ, SIM_CV, SIM_CC)
-                     : SIM_TAPE_REALS + (muscles ? 12 * SIM_MAXJ + SIM_MAXMTU : 0);
-  return (n * elem + 1023) / 1024 * 1024;
 }
 
 enum { J_FREE = 0, J_HINGE = 1, J_SLIDE = 2 };
@@ -79,6 +94,9 @@ struct DevModelT {
   // ancestors-or-self: packed i | k << 5 | va_i << 10 | va_k << 15 | (k is FREE) << 20 | 1 << 21
   int npair;
   int pair[SIM_MAXPAIR];
+  // the packed linearisation tape: words per entry and the block offset of every word
+  int tape_nw;
+  unsigned short tape_off[SIM_MAXTAPEW];
   // muscle-tendon units, point-major so that lanes (one unit each) read contiguously
   int mtu_npt[SIM_MAXMTU];
   int mtu_body[SIM_MAXMPT * SIM_MAXMTU];     // [point][unit]
@@ -121,8 +139,9 @@ struct WinArgsT {
   T* ckpt;          // [n_ckpt][N][nq+nv] (persistent and plain paths)
   T* adj;           // [N][nq+nv+na] adjoint carried between plain launches
   T* tape;          // tape_full: [h*S][N] tape entries written by the forward; else the
-                    // adjoint's segment tape [N][k-1] entries (sim_tape_bytes each)
+                    // adjoint's segment tape [N][k-1] entries, tape_ws reals apart
   int tape_full;
+  int tape_ws;      // reals between consecutive tape entries (the packed words, rounded up)
   const T* obs_in;
   const T* actions_fw;
   const T* s_h_in;

@@ -1151,3 +1151,71 @@ def test_fp32_floor_file_is_the_oracles_and_states_the_conditioning():
     r32 = next(r for r in hum["rows"] if r["h"] == 32)
     assert not any(MF.under_bar(e) for e in r32["per_env"])
     assert all(MF.under_bar(e) for e in next(r for r in hum["rows"] if r["h"] == 1)["per_env"])
+
+
+# ------------------------------------------------------------------ layer normalisation of the hidden layers
+
+def test_layer_norm_hand_case_and_library():
+    """The oracle's layer normalisation on a hand-computed row (mean 2, population variance
+    2/3) and against torch's own layer_norm on random rows; the MLP applies it after each
+    hidden layer's ELU and not after the output layer."""
+    from oracle.window import layer_norm
+    a = T([[1.0, 2.0, 3.0]])
+    g, b = T([2.0, 1.0, 0.5]), T([0.1, 0.0, -0.1])
+    s = np.sqrt(2.0 / 3.0 + 1e-5)
+    want = [2.0 * (-1.0 / s) + 0.1, 0.0, 0.5 * (1.0 / s) - 0.1]
+    assert np.allclose(layer_norm(a, g, b, 1e-5)[0].numpy(), want, rtol=0, atol=1e-15)
+    x = T(np.random.default_rng(1).normal(size=(5, 7)))
+    g7, b7 = T(np.linspace(0.5, 1.5, 7)), T(np.linspace(-0.2, 0.2, 7))
+    lib = torch.nn.functional.layer_norm(x, (7,), g7, b7, 1e-5)
+    assert torch.allclose(layer_norm(x, g7, b7, 1e-5), lib, rtol=0, atol=1e-14)
+    W1, b1 = T([[1.0, -2.0], [0.5, 0.5], [2.0, 1.0]]), T([0.0, -1.0, 0.3])
+    W2, b2 = T([[1.0, 1.0, -1.0]]), T([0.25])
+    x2 = T([[1.0, 1.0]])
+    gl, bl = T([1.0, 2.0, 0.5]), T([0.0, 0.1, 0.2])
+    hid = torch.nn.functional.elu(x2 @ W1.T + b1)
+    want_y = layer_norm(hid, gl, bl, 1e-5) @ W2.T + b2
+    assert torch.allclose(mlp_forward([(W1, b1), (W2, b2)], x2, [(gl, bl)]), want_y, rtol=0, atol=1e-15)
+
+
+def test_window_adjoint_fd_with_layer_norm_cartpole():
+    """Central differences of the CartPole window loss with layer normalisation on the actor's
+    and critic's hidden layers: every action and initial-state coordinate of two envs over 8
+    frames, and single gains / biases of the actor's normalisations against dL/dln."""
+    W = wl.workload("cartpole")
+    md, h, N, eps = W["model"], 8, 16, 1e-6
+    rng = np.random.default_rng(2)
+    aln = [(rng.uniform(0.5, 1.5, 64), rng.normal(0, 0.1, 64)) for _ in range(2)]
+    cln = [(rng.uniform(0.5, 1.5, 64), rng.normal(0, 0.1, 64)) for _ in range(2)]
+    s0 = W["s0"][[0, 5]]
+    g = oracle_window_grads(md, s0, h, W["actor"], W["critic"], n_total=N, want_theta=True, actor_ln=aln,
+                            critic_ln=cln)
+    m = OracleModel(md)
+    lay = ([(T(Wt), T(b)) for Wt, b in W["actor"]], [(T(Wt), T(b)) for Wt, b in W["critic"]])
+
+    def loss(ds=None, da=None, ln=aln):
+        s = T(s0).clone() + (T(ds) if ds is not None else 0.0)
+        return float(oracle_window(m, s, h, n_total=N, layers=lay, action_offset=da, actor_ln=ln,
+                                   critic_ln=cln)["loss"])
+    L0 = abs(loss())
+    floor = 50 * 2.2e-16 * L0 / eps
+    for t in range(h):
+        for e in range(2):
+            da = np.zeros((h, 2, 1))
+            da[t, e, 0] = eps
+            fd = (loss(da=da) - loss(da=-da)) / (2 * eps)
+            assert abs(fd - g["dL_da"][t, e, 0]) <= 1e-6 * abs(fd) + floor, (t, e)
+    for e in range(2):
+        for k in range(4):
+            ds = np.zeros_like(s0)
+            ds[e, k] = eps
+            fd = (loss(ds=ds) - loss(ds=-ds)) / (2 * eps)
+            assert abs(fd - g["dL_ds0"][e, k]) <= 1e-6 * abs(fd) + floor, (e, k)
+    for (li, which, j) in ((0, 0, 3), (1, 1, 40), (1, 0, 7)):
+        lp = [(x.copy(), y.copy()) for x, y in aln]
+        lm = [(x.copy(), y.copy()) for x, y in aln]
+        lp[li][which][j] += eps
+        lm[li][which][j] -= eps
+        fd = (loss(ln=lp) - loss(ln=lm)) / (2 * eps)
+        an = g["dL_dln"][li][which][j]
+        assert abs(fd - an) <= 1e-6 * abs(fd) + floor, (li, which, j, fd, an)
