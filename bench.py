@@ -3,6 +3,7 @@ humanoid, 1024 envs, h = 32 frames, 48 substeps per frame (checkpoint every k su
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--k 4] [--no-cpu-baseline]
                     [--no-parity] [--no-plain] [--no-theta] [--copy-probe]
+    SHACSIM_LIB=phase python bench.py --phase-profile [--model humanoid] [--path persistent|tape]
 
 Prints one JSON line.  A step is one sim_forward_window + sim_adjoint_window pair over
 one batch of synthetic inputs already resident in HBM.  Beside the headline number the
@@ -129,7 +130,49 @@ def parse():
     ap.add_argument("--no-stoch", action="store_true", help="skip the stochastic-policy window")
     ap.add_argument("--no-term", action="store_true", help="skip the window with early termination")
     ap.add_argument("--no-learn", action="store_true", help="skip the learning-episode section")
+    ap.add_argument("--phase-profile", action="store_true",
+                    help="only the per-phase cycles of the window kernels (run with SHACSIM_LIB=phase after "
+                         "python -m paper_2204_07137_amd.build --phase-profile)")
+    ap.add_argument("--model", default="humanoid", help="workload of --phase-profile")
+    ap.add_argument("--path", default="persistent", choices=("persistent", "tape"), help="launch form of --phase-profile")
     return ap.parse_args()
+
+
+def phase_profile(args):
+    """Shader-clock cycles per environment and substep of every phase of the forward and the
+    adjoint window kernels (the library's phase marks), one window after a warm-up, with the
+    kernels' event times for comparison (cycles at the measured clock)."""
+    import torch
+    import workloads as wl
+    import paper_2204_07137_amd as P
+    W = wl.workload(args.model, args.envs)
+    md, od, h = W["model"], W["obs_dim"], W["h"]
+    S = int(md["substeps"])
+    kw = dict(path=P.PATH_TAPE) if args.path == "tape" else dict(ckpt_interval=args.k)
+    sim = P.Sim(md, args.envs, h, [od] + [w.shape[0] for w, _ in W["actor"]],
+                [od] + [w.shape[0] for w, _ in W["critic"]], **kw)
+    s0, actor, critic = sim._dev(W["s0"]), sim.weights(W["actor"]), sim.weights(W["critic"])
+    fw = sim.forward(s0, actor, critic)
+    sim.adjoint(fw)
+    torch.cuda.synchronize()
+    P.phase_profile(reset=True)
+    out = {"workload": f"{args.model} {args.envs} envs, h={h}, S={S}, {args.path}" +
+                       (f" k={args.k}" if args.path == "persistent" else ""),
+           "unit": "shader-clock cycles per env and substep (sum over the env's wavefront time)"}
+    env_sub = args.envs * h * S
+    for name, run in (("forward", lambda: sim.forward(s0, actor, critic)), ("adjoint", lambda: sim.adjoint(fw))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = run()
+        e1.record()
+        torch.cuda.synchronize()
+        if name == "forward":
+            fw = r
+        cyc = P.phase_profile(reset=True)
+        per = {k: round(v / env_sub, 1) for k, v in cyc.items() if v}
+        out[name] = {"ms": round(e0.elapsed_time(e1), 3), "total": round(sum(cyc.values()) / env_sub, 1),
+                     "phases": per}
+    print(json.dumps(out), flush=True)
 
 
 def copy_probe():
@@ -448,6 +491,9 @@ def main():
     torch.manual_seed(0)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.phase_profile:
+        phase_profile(args)
         return
     W = wl.workload("humanoid", args.envs)
     md = W["model"]

@@ -442,6 +442,16 @@ enum { SIM_ABI_MODEL_DESC = 0, SIM_ABI_OPTIONS = 1, SIM_ABI_FORWARD_IO = 2, SIM_
        SIM_ABI_TUNE_RESULT = 4, SIM_ABI_CRITIC_FIT_IO = 5 };
 size_t sim_abi_layout(int which, int field);
 
+/* ---- Phase profile of the window kernels (diagnostics, not part of the method).  A library
+ * built with -DSIM_PHASE_PROFILE (python -m paper_2204_07137_amd.build --phase-profile, which
+ * writes libshacsim_phase.so) accumulates the shader-clock cycles every environment spends in
+ * each phase of the persistent and tape window kernels (kinematics, contacts, Cholesky, ...;
+ * the ids are the PH_* constants of csrc/sim_math.h) into a per-device table of 40 totals.
+ * This call synchronises the current device, copies the first n (0 <= n <= 40) totals to the
+ * host array out and, if reset, clears the table.  Returns the number of phases (40), or
+ * SIM_E_UNSUPPORTED from a product build (no table, no marks). */
+int sim_phase_profile(unsigned long long* out, int n, int reset);
+
 #ifdef __cplusplus
 }
 #endif

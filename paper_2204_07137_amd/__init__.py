@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libshacsim.so")
+# the phase-profiling build (libshacsim_phase.so) is selected with SHACSIM_LIB=phase
+LIB_PATH = os.path.join(HERE, "libshacsim_phase.so" if os.environ.get("SHACSIM_LIB") == "phase" else "libshacsim.so")
 
 MAXL = 4
 PATH_PERSISTENT, PATH_PLAIN, PATH_TAPE = 0, 1, 2
@@ -80,7 +81,8 @@ EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window"
            "sim_group_forward", "sim_group_adjoint", "sim_group_info", "sim_group_destroy",
            "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy", "sim_adam_step",
            "sim_soft_update", "sim_td_lambda", "sim_critic_workspace_bytes", "sim_critic_values",
-           "sim_critic_fit", "sim_obs_stats_update", "sim_abi_layout", "sim_critic_values_noalloc"]
+           "sim_critic_fit", "sim_obs_stats_update", "sim_abi_layout", "sim_critic_values_noalloc",
+           "sim_phase_profile"]
 MAX_GROUP = 6
 
 _LIB = None
@@ -148,6 +150,8 @@ def lib():
         L.sim_critic_values_noalloc.restype = _i
         L.sim_abi_layout.argtypes = [_i, _i]
         L.sim_abi_layout.restype = ctypes.c_size_t
+        L.sim_phase_profile.argtypes = [_p, _i, _i]
+        L.sim_phase_profile.restype = _i
         _LIB = L
     return _LIB
 
@@ -659,6 +663,24 @@ def obs_stats_update(obs, count, mean, var, inv_std, eps=1e-5):
     _check(lib().sim_obs_stats_update(_p(obs.data_ptr()), rows, dim, float(count), _p(mean.data_ptr()),
                                       _p(var.data_ptr()), _p(inv_std.data_ptr()), float(eps), _prec(obs), _stream()))
     return count + rows
+
+
+PHASES = ["frame_begin", "fk", "velocities", "contacts", "muscles", "newton_euler", "subtree_sums",
+          "bias_crba_columns", "crba", "cholesky", "factor_lds", "solve", "integrate", "tape_store", "commit",
+          "checkpoint", "adj_seed", "adj_integrator", "adj_lambda", "adj_path_sums", "adj_contacts",
+          "adj_muscles", "adj_body_terms", "adj_subtree_sums", "adj_derivatives", "adj_state", "tape_load",
+          "tape_prefetch", "adj_frame", "window_end", "termination"]
+
+
+def phase_profile(reset=True):
+    """Per-phase shader-clock cycle totals of the window kernels since the last reset (a
+    library built with --phase-profile and loaded with SHACSIM_LIB=phase), as {phase: cycles}."""
+    L = lib()
+    buf = (ctypes.c_ulonglong * 40)()
+    n = L.sim_phase_profile(ctypes.cast(buf, _p), 40, 1 if reset else 0)
+    if n < 0:
+        _check(n)
+    return {name: int(buf[i]) for i, name in enumerate(PHASES)}
 
 
 def probe_ceilings(copy_bytes=1 << 30):

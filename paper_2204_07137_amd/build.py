@@ -1,6 +1,7 @@
 """Build step: compiles the HIP sources into the in-tree shared library libshacsim.so.
 
-    python -m paper_2204_07137_amd.build
+    python -m paper_2204_07137_amd.build                   # libshacsim.so
+    python -m paper_2204_07137_amd.build --phase-profile   # libshacsim_phase.so (phase marks)
 """
 import os
 import subprocess
@@ -9,6 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshacsim.so")
+LIB_PHASE = os.path.join(HERE, "libshacsim_phase.so")
 # the window kernels are split over several units (one precision's full layouts, compact
 # layouts and group kernels) that compile in parallel
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels_f32_group_fwd.hip", "kernels_f32_group_adj.hip", "kernels_f32.hip",
@@ -33,15 +35,18 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    objdir = os.path.join(HERE, "_build")
+def build(verbose=False, phase_profile=False):
+    """Compiles the library; with phase_profile the window kernels carry the phase marks
+    (-DSIM_PHASE_PROFILE) and the result is libshacsim_phase.so."""
+    lib = LIB_PHASE if phase_profile else LIB
+    objdir = os.path.join(HERE, "_build_phase" if phase_profile else "_build")
     os.makedirs(objdir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-I", os.path.join(ROOT, "include"),
-                                                              "-c", src, "-o", obj]
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + (["-DSIM_PHASE_PROFILE"] if phase_profile else []) + [
+            "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
@@ -53,15 +58,15 @@ def build(verbose=False):
             failed = True
     if failed:
         raise RuntimeError("hipcc failed compiling libshacsim sources")
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}"] + objs + ["-o", LIB + ".tmp"]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}"] + objs + ["-o", lib + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed linking libshacsim.so")
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed linking {os.path.basename(lib)}")
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
-    print("built", LIB)
+    out = build(verbose=True, phase_profile="--phase-profile" in sys.argv[1:])
+    print("built", out)

@@ -51,6 +51,24 @@ static void* scratch_on_device(int dev) {
   return g_scratch_ptr[dev];
 }
 
+// ---------------------------------------------------------------- phase profile
+// A build with -DSIM_PHASE_PROFILE gives the window kernels this table of per-phase cycle
+// totals (device address per device, as for the scratch above); sim_phase_profile reads it.
+#ifdef SIM_PHASE_PROFILE
+static __device__ unsigned long long phase_table[SIM_NPHASE];
+static unsigned long long* g_phase_ptr[SIM_MAX_DEVICES];
+static unsigned long long* phase_on_device(int dev) {
+  if (dev < 0 || dev >= SIM_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_phase_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(phase_table)) != hipSuccess) return nullptr;
+    g_phase_ptr[dev] = static_cast<unsigned long long*>(p);
+  }
+  return g_phase_ptr[dev];
+}
+#endif
+
 static const uint32_t kMagic = 0x53484143u;
 
 struct SimHandle {
@@ -442,16 +460,21 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
   return SIM_OK;
 }
 
-// The words of a packed tape entry (the fields the adjoint reads, at the model's own sizes) and
-// the block offset of each, for the LDS layout the handle runs in (capacities J, V, C):
-// q, qd, S / v / ab / Ib of the frames, the contacts' force / point / velocity / depth, qdd,
-// the lower triangle of the Cholesky factor row by row, the reciprocal pivots, the fallback
-// flag, and for muscle models the frame rotations and positions and the activations.
-static void build_tape_map(DevModelT<double>& m, int J, int V, int C) {
+// The 16-byte chunks of a packed tape entry (those holding a field the adjoint reads, at the
+// model's own sizes) and the block offset of each, for the LDS layout the handle runs in
+// (capacities J, V, C) and its element size: q, qd, S / v / ab / Ib of the frames, the
+// contacts' force / point / velocity / depth, qdd, the lower triangle of the Cholesky factor row
+// by row, the reciprocal pivots, the fallback flag, and for muscle models the frame rotations
+// and positions and the activations.  The fields are in increasing block order, so a chunk
+// shared by two runs is listed once.
+static void build_tape_map(DevModelT<double>& m, int J, int V, int C, int elem) {
   const SimTapeLayout T = sim_tape_layout(J, V, C);
-  int w = 0;
+  const int wpc = 16 / elem;   // words per chunk
+  int w = 0, last = -1;
   auto run = [&](int base, int n) {
-    for (int i = 0; i < n; ++i) m.tape_off[w++] = (unsigned short)(base + i);
+    if (n <= 0) return;
+    for (int c = base / wpc; c <= (base + n - 1) / wpc; ++c)
+      if (c != last) { m.tape_off[w++] = (unsigned short)c; last = c; }
   };
   run(T.q, m.nq);
   run(T.qd, m.nv);
@@ -486,8 +509,18 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   if (rc) return rc;
   SimHandle* h = new SimHandle();
   m.chol_thr = opt->chol_fp64_threshold;
-  if (opt->lanes_per_env) build_tape_map(m, SIM_CJ, SIM_CV, SIM_CC);
-  else build_tape_map(m, SIM_MAXJ, SIM_MAXV, SIM_MAXC);
+  {
+    const int elem = (opt->precision == SIM_PREC_FP64) ? 8 : 4;
+    if (opt->lanes_per_env) build_tape_map(m, SIM_CJ, SIM_CV, SIM_CC, elem);
+    else build_tape_map(m, SIM_MAXJ, SIM_MAXV, SIM_MAXC, elem);
+    // the kernels hold an entry's chunk offsets in registers sized for this bound
+    const int cap = opt->lanes_per_env ? sim_tape_chunk_cap(SIM_CJ, SIM_CV, SIM_CC, 0, elem)
+                                       : sim_tape_chunk_cap(SIM_MAXJ, SIM_MAXV, SIM_MAXC, m.n_mtu > 0 ? SIM_MAXMTU : 0, elem);
+    if (m.tape_nw > cap || m.tape_nw > SIM_MAXTAPEW) {
+      delete h;
+      return fail(SIM_E_MODEL, "sim_create: linearisation tape entry beyond the layout's chunk capacity");
+    }
+  }
   h->m64 = m;
   convert_model(m, h->m32);
   h->opt = *opt;
@@ -557,8 +590,8 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   const size_t tape_entries = (opt->path == SIM_PATH_TAPE) ? (size_t)opt->horizon * m.substeps * N
                               : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
   h->off_tape = off;
-  // packed entries, each rounded up to 64 reals
-  h->tape_ws = (m.tape_nw + 63) / 64 * 64;
+  // packed entries of 16-byte chunks, each entry rounded up to 256 bytes
+  h->tape_ws = (m.tape_nw * 16 / (int)e + 256 / (int)e - 1) / (256 / (int)e) * (256 / (int)e);
   off = align256(off + tape_entries * (size_t)h->tape_ws * e);
   h->off_done = off;
   off = align256(off + (size_t)opt->horizon * N);
@@ -700,6 +733,9 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (h->opt.path == SIM_PATH_TAPE);
   A.tape_ws = h->tape_ws;
+#ifdef SIM_PHASE_PROFILE
+  A.prof = phase_on_device(h->device);
+#endif
   A.reset = static_cast<const T*>(io->reset_states);
   A.done_out = io->done;
   A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
@@ -735,6 +771,9 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (o.path == SIM_PATH_TAPE);
   A.tape_ws = h->tape_ws;
+#ifdef SIM_PHASE_PROFILE
+  A.prof = phase_on_device(h->device);
+#endif
   A.done_ws = reinterpret_cast<uint8_t*>(ws + h->off_done);
   A.seg_ws = reinterpret_cast<int*>(ws + h->off_seg);
   A.obs_in = static_cast<const T*>(io->obs);
@@ -1630,4 +1669,25 @@ extern "C" int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_
     return fail(SIM_E_WORKSPACE, "sim_critic_fit: workspace smaller than sim_critic_workspace_bytes()");
   return (h->opt.precision == SIM_PREC_FP64) ? critic_fit_impl<double>(h, io, hip_stream)
                                              : critic_fit_impl<float>(h, io, hip_stream);
+}
+
+// ---------------------------------------------------------------- phase profile readout
+extern "C" int sim_phase_profile(unsigned long long* out, int n, int reset) {
+#ifdef SIM_PHASE_PROFILE
+  if (!out || n < 0 || n > SIM_NPHASE) return fail(SIM_E_ARG, "sim_phase_profile: out and 0 <= n <= SIM_NPHASE");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_E_HIP, "hipGetDevice failed");
+  unsigned long long* p = phase_on_device(dev);
+  if (!p) return fail(SIM_E_HIP, "sim_phase_profile: hipGetSymbolAddress failed");
+  if (hipDeviceSynchronize() != hipSuccess) return fail(SIM_E_HIP, "hipDeviceSynchronize failed");
+  if (n > 0 && hipMemcpy(out, p, n * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SIM_E_HIP, "hipMemcpy failed");
+  if (reset && hipMemset(p, 0, SIM_NPHASE * sizeof(unsigned long long)) != hipSuccess)
+    return fail(SIM_E_HIP, "hipMemset failed");
+  if (reset && hipDeviceSynchronize() != hipSuccess) return fail(SIM_E_HIP, "hipDeviceSynchronize failed");
+  return SIM_NPHASE;
+#else
+  (void)out; (void)n; (void)reset;
+  return fail(SIM_E_UNSUPPORTED, "sim_phase_profile: this library was built without -DSIM_PHASE_PROFILE");
+#endif
 }

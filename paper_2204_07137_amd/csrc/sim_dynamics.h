@@ -50,11 +50,8 @@ struct EnvLDST {
   static constexpr int kMaxA = MAXA;
   static constexpr int kLanes = LANES;
   static constexpr int kJ = CJ, kV = CV, kQ = CV + 1, kC = CC, kObs = COBS, kHid = CHID, kPair = CPAIR;
-  // the most words a packed tape entry of this layout can hold (every frame, DOF and contact
-  // in use: the lower triangle of the factor, no new velocities), and per lane
-  static constexpr int kTapeMaxWords = (CV + 1) + CV + 28 * CJ + 10 * CC + CV + CV * (CV + 1) / 2 + CV + 1 +
-                                       (NMTU > 0 ? 12 * CJ + NMTU : 0);
-  static constexpr int kTapeWordsPerLane = (kTapeMaxWords + LANES - 1) / LANES;
+  // the most 16-byte chunks a packed tape entry of this layout can need, and per lane
+  static constexpr int kTapeChunksPerLane = (sim_tape_chunk_cap(CJ, CV, CC, NMTU, (int)sizeof(real)) + LANES - 1) / LANES;
   // The linearisation of the current substep, one contiguous block whose fields
   // sim_tape_layout describes; a tape entry holds the words of it that the model uses
   // (for torque-driven models no R and p: those are rebuilt by any recomputation and never
@@ -109,6 +106,9 @@ struct EnvLDST {
     real mus[NMTU > 0 ? SIM_MUS_CF * SIM_MUS_STRIDE : 1];
   };
   real red[4];
+#ifdef SIM_PHASE_PROFILE
+  unsigned long long prof[SIM_NPHASE + 1];   // phase cycle totals and the last mark's time
+#endif
 };
 typedef EnvLDST<SIM_MAXA, 0> EnvLDS;             // torque-driven models
 typedef EnvLDST<SIM_MAXAM, SIM_MAXMTU> EnvLDSM;  // muscle-driven models
@@ -704,6 +704,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       }
     }
   }
+  SIM_PHASE(E, PH_F_FK);
   // motion subspaces: a hinge turns about its own axis, so its world axis is R ax either
   // side of the joint rotation; a slide keeps the parent's rotation
   sv u = zsv(), c = zsv();
@@ -754,6 +755,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     stsv(E.ab[ln], ab);
   }
   wsync();
+  SIM_PHASE(E, PH_F_VEL);
   // ---- contacts (lane = contact)
   bool adh = false;
   if (ln < nc) {
@@ -777,7 +779,11 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     if (ln == 0) E.nadh = __popcll(bal);
   }
   wsync();
-  if constexpr (L::kMtu > 0) muscle_wrenches(m, E, ln);
+  SIM_PHASE(E, PH_F_CONTACT);
+  if constexpr (L::kMtu > 0) {
+    muscle_wrenches(m, E, ln);
+    SIM_PHASE(E, PH_F_MUSCLE);
+  }
   // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
   if (ln < J) {
     real mass = jr.mass;
@@ -831,9 +837,11 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     }
   }
   wsync();
+  SIM_PHASE(E, PH_F_NE);
   // ---- subtree sums of forces (6 columns) and composite inertias (10 columns)
   tree_sum_sched16(E, m->ts_steps, ln);
   wsync();
+  SIM_PHASE(E, PH_F_TREESUM);
   // ---- bias into rhs; composite-inertia columns F_i = Ic_i S_i; root block of M
   if (ln < J) {
     sv F = ldsv(E.F[ln]);
@@ -869,6 +877,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     }
   }
   wsync();
+  SIM_PHASE(E, PH_F_BIAS);
   // ---- CRBA entries M[va_k][va_i] = S_k . F_i, one (frame, ancestor) pair per lane and round
   for (int r = 0; r * LN < jr.npair; ++r) {
     int pi = r * LN + ln;
@@ -890,6 +899,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     }
   }
   wsync();
+  SIM_PHASE(E, PH_F_CRBA);
   // ---- Cholesky and solve (lane = DOF); rows >= nv padded with the identity
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -901,8 +911,10 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   if (sizeof(real) == 4 && !(minpiv > m->chol_thr * dmax)) fb = 1;
   real b = ln < nv ? E.vec[ln] : RL(0.0);
   real x;
+  SIM_PHASE(E, PH_F_CHOL);
   if (fb) {
     chol64_factor<NV>(E, nv, ln);
+    SIM_PHASE(E, PH_F_FACTOR);
     x = (real)chol64_solve<NV>(E, ln, (double)b);
   } else {
     wsync();
@@ -914,6 +926,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     const int lc = ln < NV ? ln : 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) C.col[k] = (ln < NV) ? E.M[k][lc] : RL(0.0);
+    SIM_PHASE(E, PH_F_FACTOR);
     x = chol_solve<NV, LN>(C, ln, b);
   }
   if (ln < nv) {
@@ -922,6 +935,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     E.qdn[ln] = qdn;
   }
   wsync();
+  SIM_PHASE(E, PH_F_SOLVE);
   // ---- positions with the new velocities (lane = joint)
   if (ln < J) {
     if (jr.type == J_FREE) {
@@ -954,6 +968,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = E.actn[i];
     wsync();
   }
+  SIM_PHASE(E, PH_F_INTEG);
 }
 
 // --------------------------------------------------------------- adjoint of one substep
@@ -1008,6 +1023,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     }
   }
   wsync();
+  SIM_PHASE(E, PH_A_INTEG);
   // ---- lambda = M^{-1} qdd_bar with the cached factor (lane = DOF)
   {
     real rb = ln < nv ? dt * E.qdb[ln] : RL(0.0);
@@ -1015,6 +1031,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     if (ln < nv) E.lam[ln] = lam;
   }
   wsync();
+  SIM_PHASE(E, PH_A_LAMBDA);
   // actuation adjoint and full accelerations / virtual velocities
   if (ln < J && jr.act >= 0) E.abar[jr.act] += jr.gear * E.lam[jr.va];
   // local terms (lane = joint), then their sums along each root path by pointer jumping
@@ -1045,6 +1062,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(E.W[ln], W);
   }
   wsync();
+  SIM_PHASE(E, PH_A_PATH);
   // ---- contact adjoints (lane = contact)
   if (ln < nc) {
     int b = cr.body;
@@ -1070,7 +1088,11 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(E.cVb[ln], spf(x, vbar));
   }
   wsync();
-  if constexpr (L::kMtu > 0) muscle_adjoint(m, E, ln);
+  SIM_PHASE(E, PH_A_CONTACT);
+  if constexpr (L::kMtu > 0) {
+    muscle_adjoint(m, E, ln);
+    SIM_PHASE(E, PH_A_MUSCLE);
+  }
   // ---- per-body terms (lane = joint): P Q R T Fn Ab Vb
   if (ln < J) {
     const real* Ib = E.Ib[ln];
@@ -1098,6 +1120,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     stsv(o + 24, Fn); stsv(o + 30, Ab); stsv(o + 36, Vb);
   }
   wsync();
+  SIM_PHASE(E, PH_A_BODY);
   // one lane per column of the 42 (several passes with fewer than 42 lanes per environment)
 #pragma unroll
   for (int c0 = 0; c0 < 42; c0 += LN) {
@@ -1105,6 +1128,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     tree_sum_cols(&E.acc[0][c < 42 ? c : 0], 42, c < 42, J, jr.par);
   }
   wsync();
+  SIM_PHASE(E, PH_A_TREESUM);
   // ---- derivatives of lambda^T ID per joint (lane = joint)
   if (ln < J) {
     const real* o = E.acc[ln];
@@ -1150,6 +1174,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     }
   }
   wsync();
+  SIM_PHASE(E, PH_A_DERIV);
   // ---- adjoint of the pre-substep state
   if (ln < nv) E.qdb[ln] -= E.dPqd[ln];
   if (ln < J) {
@@ -1172,6 +1197,7 @@ __device__ __forceinline__ void substep_adjoint_core(const Scal* __restrict__ m,
     }
   }
   wsync();
+  SIM_PHASE(E, PH_A_STATE);
 }
 
 // Adjoint of one substep from its pre-state alone: the forward linearisation is
@@ -1202,6 +1228,7 @@ __device__ __forceinline__ void commit_substep(const Scal* __restrict__ m, L& E,
   if constexpr (L::kMtu > 0)
     for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.act[i] = E.actn[i];
   wsync();
+  SIM_PHASE(E, PH_COMMIT);
 }
 
 // The block's fields sit where sim_tape_layout says (the host builds the word maps from it).
@@ -1217,10 +1244,30 @@ __device__ __forceinline__ constexpr bool tape_layout_ok() {
          offsetof(L, p) == T.p * r && (L::kMtu == 0 || offsetof(L, act) == T.act * r);
 }
 
-// A packed tape entry: word w of the entry is real m->tab->tape_off[w] of the block; lane ln
-// of the environment moves words ln, ln + LN, ...  (consecutive lanes, consecutive words).
+typedef unsigned int tape_u32x4 __attribute__((ext_vector_type(4)));
+
+// The block offsets (16-byte units) of the chunks this lane moves: chunk w of a packed entry is
+// the block's chunk m->tab->tape_off[w], and lane ln of the environment moves chunks ln, ln + LN,
+// ... (consecutive lanes, consecutive 16 bytes).  Read once per kernel into registers; -1 past
+// the entry's last chunk.
+template <class L>
+struct TapeMap {
+  int off[L::kTapeChunksPerLane];
+};
+template <class L>
+__device__ __forceinline__ TapeMap<L> tape_map(const Scal* __restrict__ m, int ln) {
+  TapeMap<L> T;
+  const int nw = m->tape_nw;
+#pragma unroll
+  for (int i = 0; i < L::kTapeChunksPerLane; ++i) {
+    const int w = i * L::kLanes + ln;
+    T.off[i] = (w < nw) ? (int)m->tab->tape_off[w] : -1;
+  }
+  return T;
+}
+
 template <int NV, class L>
-__device__ __forceinline__ void tape_store(const Scal* __restrict__ m, L& E, const Chol& C, int fb, int ln,
+__device__ __forceinline__ void tape_store(const TapeMap<L>& T, L& E, const Chol& C, int fb, int ln,
                                            real* __restrict__ tp) {
   static_assert(offsetof(L, q) == 0, "tape block first");
   static_assert(tape_layout_ok<L>(), "LDS block as sim_tape_layout describes it");
@@ -1233,53 +1280,43 @@ __device__ __forceinline__ void tape_store(const Scal* __restrict__ m, L& E, con
     E.tfb[ln] = fb ? RL(1.0) : RL(0.0);
   }
   wsync();
-  const real* blk = &E.q[0];
-  const unsigned short* __restrict__ off = m->tab->tape_off;
-  const int nw = m->tape_nw;
+  const tape_u32x4* blk = reinterpret_cast<const tape_u32x4*>(&E.q[0]);
+  tape_u32x4* dst = reinterpret_cast<tape_u32x4*>(tp);
   // streaming (non-temporal) stores: the tape must not displace the policy weights in L2
 #pragma unroll
-  for (int i = 0; i < L::kTapeWordsPerLane; ++i) {
-    const int w = i * LN + ln;
-    if (w < nw) __builtin_nontemporal_store(blk[off[w]], &tp[w]);
-  }
+  for (int i = 0; i < L::kTapeChunksPerLane; ++i)
+    if (T.off[i] >= 0) __builtin_nontemporal_store(blk[T.off[i]], &dst[i * LN + ln]);
+  SIM_PHASE(E, PH_TAPE_STORE);
 }
 
-// A tape entry held in registers (the lane's words): the adjoint loads the next entry while
+// A tape entry held in registers (the lane's chunks): the adjoint loads the next entry while
 // the current substep's reverse runs, so the load latency is hidden.
 template <class L>
 struct TapeRegs {
-  real v[L::kTapeWordsPerLane];
+  tape_u32x4 v[L::kTapeChunksPerLane];
 };
 
 template <class L>
-__device__ __forceinline__ void tape_prefetch(const Scal* __restrict__ m, TapeRegs<L>& P, const real* __restrict__ tp,
+__device__ __forceinline__ void tape_prefetch(const TapeMap<L>& T, TapeRegs<L>& P, const real* __restrict__ tp,
                                               int ln) {
-  constexpr int LN = L::kLanes;
-  const int nw = m->tape_nw;
+  const tape_u32x4* src = reinterpret_cast<const tape_u32x4*>(tp);
 #pragma unroll
-  for (int i = 0; i < L::kTapeWordsPerLane; ++i) {
-    const int w = i * LN + ln;
-    P.v[i] = (w < nw) ? __builtin_nontemporal_load(&tp[w]) : RL(0.0);
-  }
+  for (int i = 0; i < L::kTapeChunksPerLane; ++i)
+    if (T.off[i] >= 0) P.v[i] = __builtin_nontemporal_load(&src[i * L::kLanes + ln]);
 }
 
-// tape_load from a prefetched entry: the words back into the block, the new velocities
+// tape_load from a prefetched entry: the chunks back into the block, the new velocities
 // rebuilt as the forward computed them (qdn = qd + dt qdd), the factor into registers
 template <int NV, class L>
-__device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, L& E, Chol& C, int& fb, int ln,
-                                               const TapeRegs<L>& P) {
-  constexpr int LN = L::kLanes;
-  real* blk = &E.q[0];
-  const unsigned short* __restrict__ off = m->tab->tape_off;
-  const int nw = m->tape_nw;
+__device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, const TapeMap<L>& T, L& E, Chol& C,
+                                               int& fb, int ln, const TapeRegs<L>& P) {
+  tape_u32x4* blk = reinterpret_cast<tape_u32x4*>(&E.q[0]);
   // LDS ordering only (one wavefront per environment): the tape stores still in flight
   // need not complete here, and the registers wait for their own loads
   wsync();   // earlier LDS reads of the block complete before it is overwritten
 #pragma unroll
-  for (int i = 0; i < L::kTapeWordsPerLane; ++i) {
-    const int w = i * LN + ln;
-    if (w < nw) blk[off[w]] = P.v[i];
-  }
+  for (int i = 0; i < L::kTapeChunksPerLane; ++i)
+    if (T.off[i] >= 0) blk[T.off[i]] = P.v[i];
   wsync();
   if (ln < m->nv) {
     const real dt = m->dt_sub;
@@ -1302,4 +1339,5 @@ __device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, L& E,
   // uniform over the environment's lanes (its own LDS); over the wavefront only with 64 lanes
   if constexpr (L::kLanes == SIM_WAVE) fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
   else fb = (E.tfb[0] != RL(0.0)) ? 1 : 0;
+  SIM_PHASE(E, PH_TAPE_LOAD);
 }

@@ -156,21 +156,29 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
   load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nqv = m->nck, N = A.N;
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
+  const TapeMap<L> TM = tape_map<L>(m, ln);
+#ifdef SIM_PHASE_PROFILE
+  phase_start<L::kLanes>(E.prof);
+#endif
   Chol C;
   int nfb = 0, nadh = 0;
   int t0 = 0;   // first frame of the current discount segment (early termination)
   for (int t = 0; t < A.h; ++t) {
     frame_begin(A, m, E, env, t, ln);
+    SIM_PHASE(E, PH_FRAME_BEGIN);
     for (int sub = 0; sub < S; ++sub) {
       int gi = t * S + sub;
       int fb;
       if (A.tape_full) {
         // the tape entry holds the pre-substep state and the linearisation
         substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-        tape_store<NV>(m, E, C, fb, ln, A.tape + ((size_t)gi * N + env) * A.tape_ws);
+        tape_store<NV>(TM, E, C, fb, ln, A.tape + ((size_t)gi * N + env) * A.tape_ws);
         commit_substep(m, E, ln);
       } else {
-        if (gi % A.k == 0) store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
+        if (gi % A.k == 0) {
+          store_qqd(m, E, A.ckpt + ((size_t)(gi / A.k) * N + env) * nqv, ln);
+          SIM_PHASE(E, PH_CKPT);
+        }
         substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
       }
       nfb += fb;
@@ -189,12 +197,17 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
         load_state(m, E, A.reset + (size_t)env * m->ns, ln);
         t0 = t + 1;
       }
+      SIM_PHASE(E, PH_TERM);
     }
   }
   if (m->term && ln == 0) A.seg_ws[(size_t)A.h * N + env] = t0;
   window_end(A, m, E, env, ln);
   if (ln == 0 && A.fallback) A.fallback[env] = nfb;
   if (ln == 0 && A.adhesive) A.adhesive[env] = nadh;
+#ifdef SIM_PHASE_PROFILE
+  SIM_PHASE(E, PH_WINDOW_END);
+  phase_flush<L::kLanes>(E.prof, A.prof);
+#endif
 }
 
 // ======================================================================= persistent adjoint
@@ -293,7 +306,12 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
   load_regs(A.model, E, ln, jr, cr);
   const int S = m->substeps, nq = m->nq, nv = m->nv, na = m->na, ns = m->ns, N = A.N, k = A.k;
   const int nqv = m->nck;
+  const TapeMap<L> TM = tape_map<L>(m, ln);
+#ifdef SIM_PHASE_PROFILE
+  phase_start<L::kLanes>(E.prof);
+#endif
   adjoint_seed(A, m, E, env, ln);
+  SIM_PHASE(E, PH_A_SEED);
   // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
   Chol C;
   for (int t = A.h - 1; t >= 0; --t) {
@@ -312,11 +330,12 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
       // the forward stored every substep's pre-state and linearisation; the next (earlier)
       // entry is loaded into registers while the current one is reversed
       TapeRegs<L> P;
-      tape_prefetch(m, P, A.tape + (((size_t)t * S + S - 1) * N + env) * A.tape_ws, ln);
+      tape_prefetch(TM, P, A.tape + (((size_t)t * S + S - 1) * N + env) * A.tape_ws, ln);
       for (int sub = S - 1; sub >= 0; --sub) {
         int fb;
-        tape_load_regs<NV>(m, E, C, fb, ln, P);
-        if (sub > 0) tape_prefetch(m, P, A.tape + (((size_t)t * S + sub - 1) * N + env) * A.tape_ws, ln);
+        tape_load_regs<NV>(m, TM, E, C, fb, ln, P);
+        if (sub > 0) tape_prefetch(TM, P, A.tape + (((size_t)t * S + sub - 1) * N + env) * A.tape_ws, ln);
+        SIM_PHASE(E, PH_TAPE_PREFETCH);
         if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
       }
@@ -326,12 +345,13 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         int c = (t * S + sg * k) / k;
         const real* ck = A.ckpt + ((size_t)c * N + env) * nqv;
         load_qqd(m, E, ck, ln);
+        SIM_PHASE(E, PH_CKPT);
         // recompute the segment from its checkpoint, recording pre-states and
         // linearisations; the last substep's linearisation stays on chip
         for (int i = 0; i < k - 1; ++i) {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          tape_store<NV>(m, E, C, fb, ln, tseg + (size_t)i * A.tape_ws);
+          tape_store<NV>(TM, E, C, fb, ln, tseg + (size_t)i * A.tape_ws);
           commit_substep(m, E, ln);
         }
         // the segment's recorded entries are loaded into registers one ahead of their use
@@ -339,13 +359,15 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          if (k >= 2) tape_prefetch(m, P, tseg + (size_t)(k - 2) * A.tape_ws, ln);
+          if (k >= 2) tape_prefetch(TM, P, tseg + (size_t)(k - 2) * A.tape_ws, ln);
+          SIM_PHASE(E, PH_TAPE_PREFETCH);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
         for (int i = k - 2; i >= 0; --i) {
           int fb;
-          tape_load_regs<NV>(m, E, C, fb, ln, P);
-          if (i > 0) tape_prefetch(m, P, tseg + (size_t)(i - 1) * A.tape_ws, ln);
+          tape_load_regs<NV>(m, TM, E, C, fb, ln, P);
+          if (i > 0) tape_prefetch(TM, P, tseg + (size_t)(i - 1) * A.tape_ws, ln);
+          SIM_PHASE(E, PH_TAPE_PREFETCH);
           if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
@@ -353,6 +375,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
     }
     // the reverse sweep ends on the frame's first substep: E.q/E.qd = s_t
     adjoint_frame(A, m, E, env, t, ln, false);
+    SIM_PHASE(E, PH_A_FRAME);
   }
   real* d0 = A.dL_ds0 + (size_t)env * ns;
   for (int i = ln; i < nq; i += L::kLanes) d0[i] = E.qb[i];
@@ -363,6 +386,9 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
     const int o = nq + nv + (m->has_last_action ? na : 0);
     for (int i = ln; i < m->n_mtu; i += L::kLanes) d0[o + i] = E.act_bar[i];
   }
+#ifdef SIM_PHASE_PROFILE
+  phase_flush<L::kLanes>(E.prof, A.prof);
+#endif
 }
 
 // One workgroup of one wavefront runs 64 / L::kLanes environments, each on L::kLanes lanes

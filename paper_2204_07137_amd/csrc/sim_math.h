@@ -87,6 +87,52 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---- phase profile.  A build with -DSIM_PHASE_PROFILE accumulates, per environment, the
+// shader-clock cycles (s_memtime) from one mark to the next under the id of the later mark, in
+// the environment's LDS, and adds the totals to a device table when the window ends; in the
+// product build the marks are empty.  A mark names the phase that ends at it.
+#define SIM_NPHASE 40
+enum {
+  PH_FRAME_BEGIN = 0,   // observation, actor, reward, action store (frame start)
+  PH_F_FK = 1,          // joint rotations and frame transforms (pointer jumping)
+  PH_F_VEL = 2,         // motion subspaces, velocities, bias accelerations
+  PH_F_CONTACT = 3,     // contact forces
+  PH_F_MUSCLE = 4,      // muscle wrenches
+  PH_F_NE = 5,          // body inertias, Newton-Euler forces, joint torques
+  PH_F_TREESUM = 6,     // subtree sums of forces and composite inertias
+  PH_F_BIAS = 7,        // bias into the right-hand side, CRBA columns, root block
+  PH_F_CRBA = 8,        // mass-matrix entries
+  PH_F_CHOL = 9,        // Cholesky factorisation (with the row load and the pivot test)
+  PH_F_FACTOR = 10,     // factor rows to LDS and columns back (or the FP64 fallback)
+  PH_F_SOLVE = 11,      // the two triangular solves and the velocity update
+  PH_F_INTEG = 12,      // positions (and activations), in-place commit
+  PH_TAPE_STORE = 13,   // a tape entry to HBM
+  PH_COMMIT = 14,       // post-substep state made current
+  PH_CKPT = 15,         // checkpoint store / load
+  PH_A_SEED = 16,       // terminal critic seed
+  PH_A_INTEG = 17,      // integrator reverse
+  PH_A_LAMBDA = 18,     // lambda = M^-1 qdd_bar
+  PH_A_PATH = 19,       // accelerations and virtual velocities along the root paths
+  PH_A_CONTACT = 20,    // contact adjoints
+  PH_A_MUSCLE = 21,     // muscle adjoints
+  PH_A_BODY = 22,       // per-body terms
+  PH_A_TREESUM = 23,    // subtree sums of the seven spatial vectors
+  PH_A_DERIV = 24,      // closed-form derivatives per joint
+  PH_A_STATE = 25,      // adjoint of the pre-substep state
+  PH_TAPE_LOAD = 26,    // a prefetched entry back into LDS and the factor into registers
+  PH_TAPE_PREFETCH = 27,// issuing the next entry's loads
+  PH_A_FRAME = 28,      // frame-level reverse (reward, actor input VJP, observation)
+  PH_WINDOW_END = 29,   // terminal observation, critic, outputs
+  PH_TERM = 30          // early-termination test and reset
+};
+#ifdef SIM_PHASE_PROFILE
+template <int LN>
+__device__ __forceinline__ void phase_mark(unsigned long long* P, int id);
+#define SIM_PHASE(E, id) phase_mark<L::kLanes>((E).prof, (id))
+#else
+#define SIM_PHASE(E, id) ((void)0)
+#endif
+
 // lane src's value, src chosen per lane (a wavefront-wide permute through the LDS
 // crossbar: no LDS memory, no barrier); every lane of the wavefront must be active
 __device__ __forceinline__ int pull(int x, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, x); }
@@ -106,6 +152,29 @@ template <int LN>
 __device__ __forceinline__ int grp_base() { return LN == SIM_WAVE ? 0 : ((int)threadIdx.x & (SIM_WAVE - LN)); }
 template <int LN>
 __device__ __forceinline__ int grp_lane() { return LN == SIM_WAVE ? (int)threadIdx.x : ((int)threadIdx.x & (LN - 1)); }
+#ifdef SIM_PHASE_PROFILE
+template <int LN>
+__device__ __forceinline__ void phase_mark(unsigned long long* P, int id) {
+  const unsigned long long now = __builtin_amdgcn_s_memtime();
+  if (grp_lane<LN>() == 0) {
+    P[id] += now - P[SIM_NPHASE];
+    P[SIM_NPHASE] = now;
+  }
+}
+template <int LN>
+__device__ __forceinline__ void phase_start(unsigned long long* P) {
+  if (grp_lane<LN>() == 0) {
+    for (int i = 0; i < SIM_NPHASE; ++i) P[i] = 0ull;
+    P[SIM_NPHASE] = __builtin_amdgcn_s_memtime();
+  }
+}
+template <int LN>
+__device__ __forceinline__ void phase_flush(const unsigned long long* P, unsigned long long* out) {
+  if (out && grp_lane<LN>() == 0)
+    for (int i = 0; i < SIM_NPHASE; ++i) atomicAdd(&out[i], P[i]);
+}
+#endif
+
 // the value of the environment's lane k (k the same on all lanes of the environment)
 template <int LN, class T>
 __device__ __forceinline__ T bcast(T x, int k) {

@@ -58,8 +58,15 @@ constexpr SimTapeLayout sim_tape_layout(int J, int V, int C) {
 // The tape entry of a substep holds only the fields the reverse reads, for the model's own
 // sizes: q (nq), qd (nv), S / v / ab / Ib of its J frames, the nc contacts' data, qdd, the lower
 // triangle of the Cholesky factor row by row, the reciprocal pivots and the flag (muscle models
-// also R, p and the activations); word w of an entry comes from block real tape_off[w].
-#define SIM_MAXTAPEW 2432
+// also R, p and the activations).  It moves in 16-byte chunks of the block: chunk w of an entry
+// is the block's chunk tape_off[w] (in 16-byte units), and the list holds every chunk that
+// contains one of those words.  A run of n words covers at most ceil(n / words-per-chunk) + 1
+// chunks, so an entry never needs more than sim_tape_chunk_cap chunks.
+constexpr int sim_tape_chunk_cap(int J, int V, int C, int nmtu, int elem) {
+  return (((V + 1) + V + 28 * J + 10 * C + V + V * (V + 1) / 2 + V + 1 + (nmtu > 0 ? 12 * J + nmtu : 0)) * elem + 15) / 16 +
+         2 * (V + 16);
+}
+#define SIM_MAXTAPEW 2432   // capacity of the chunk list (the largest layout in FP64 needs 1305)
 // BF16 tile bytes of one layer's forward or input-adjoint operand set
 static inline size_t sim_bf16_tiles_bytes(int n_rows, int n_k) {
   return (size_t)((n_rows + 15) / 16) * ((n_k + 31) / 32) * 64 * 8 * 2;
@@ -94,7 +101,8 @@ struct DevModelT {
   // ancestors-or-self: packed i | k << 5 | va_i << 10 | va_k << 15 | (k is FREE) << 20 | 1 << 21
   int npair;
   int pair[SIM_MAXPAIR];
-  // the packed linearisation tape: words per entry and the block offset of every word
+  // the packed linearisation tape: 16-byte chunks per entry and the block offset of every
+  // chunk, in 16-byte units
   int tape_nw;
   unsigned short tape_off[SIM_MAXTAPEW];
   // muscle-tendon units, point-major so that lanes (one unit each) read contiguously
@@ -165,6 +173,8 @@ struct WinArgsT {
   // the window's loss: per env [N] and the sum over envs [1] (forward, optional)
   T* loss_env;
   T* loss;
+  // phase-profile build only: [SIM_NPHASE] shader-clock cycle totals over all environments
+  unsigned long long* prof;
 };
 
 // Several models' windows in one launch (mixed-morphology batch): work-table slot s covers

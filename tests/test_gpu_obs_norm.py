@@ -117,8 +117,17 @@ def test_obs_stats_update_matches_oracle(dt, tol):
     assert relnorm(inv.double().cpu().numpy(), ri.numpy()) < tol
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_normalised_critic_values_and_fit_match_oracle(precision, tol):
+@pytest.mark.parametrize("precision,tol,adam_eps,fit_tol",
+                         [("fp64", 1e-12, 1e-8, 1e-8), ("fp32", 1e-5, 1e-8, 2e-2), ("fp32", 1e-5, 1e-3, 1e-4)])
+def test_normalised_critic_values_and_fit_match_oracle(precision, tol, adam_eps, fit_tol):
+    """Critic values and eight Adam steps of the critic fit against the oracle on normalised
+    rows.  The bar on the weight change: Adam's step lr m / (sqrt(v) + eps) is close to
+    lr sign(g) for every entry whose gradient g is far above eps, so a weight whose minibatch
+    gradient is a sum that nearly cancels changes sign under FP32 rounding of its terms and
+    moves by about 2 lr the other way (an O(1) relative error in that entry).  With eps = 1e-8
+    such entries are why the FP32 weight change is held to 2e-2 in relative norm (a few
+    entries in 10^4); with eps = 1e-3 the step is a smooth function of g at that scale and the
+    FP32 change is held to 1e-4, the bar of the losses."""
     W = wl.workload("humanoid", 64)
     h, N = 4, 64
     sim = _sim(W, N, h, ckpt_interval=16, precision=precision)
@@ -142,16 +151,18 @@ def test_normalised_critic_values_and_fit_match_oracle(precision, tol):
     n = sum(Wl.size + bl.size for Wl, bl in W["critic"])
     m = torch.zeros(n, dtype=sim.dtype, device="cuda")
     v = torch.zeros(n, dtype=sim.dtype, device="cuda")
-    losses = sim.critic_fit(obs, tgt, torch.as_tensor(perm), 2, crit, m, v, 0, 5e-4, obs_norm=(mu, sc))
+    losses = sim.critic_fit(obs, tgt, torch.as_tensor(perm), 2, crit, m, v, 0, 5e-4, eps=adam_eps, obs_norm=(mu, sc))
     torch.cuda.synchronize()
     zeros = [np.zeros_like(x) for Wl, bl in W["critic"] for x in (Wl, bl)]
     ref_layers, _, _, ref_losses = OL.critic_fit(W["critic"], normalize_obs(obs.double().cpu(), (mu, sc)),
-                                                 tgt.double().cpu(), perm, 2, zeros, zeros, 0, 5e-4, 0.7, 0.95, 1e-8)
+                                                 tgt.double().cpu(), perm, 2, zeros, zeros, 0, 5e-4, 0.7, 0.95, adam_eps)
     got_w = np.concatenate([x.double().cpu().numpy().ravel() for pair in crit for x in pair])
     want_w = np.concatenate([x.numpy().ravel() for pair in ref_layers for x in pair])
     init_w = np.concatenate([x.ravel() for pair in W["critic"] for x in pair])
     assert relnorm(losses.double().cpu().numpy(), ref_losses) < (1e-9 if precision == "fp64" else 1e-4)
-    assert relnorm(got_w - init_w, want_w - init_w) < (1e-8 if precision == "fp64" else 2e-2)
+    err = relnorm(got_w - init_w, want_w - init_w)
+    print(f"[obs-norm] critic fit {precision} eps={adam_eps}: weight-change relnorm {err:.3e}", flush=True)
+    assert err < fit_tol
 
 
 def _cos(x, y):
