@@ -91,7 +91,6 @@ __device__ __forceinline__ void wsync() {
 // shader-clock cycles (s_memtime) from one mark to the next under the id of the later mark, in
 // the environment's LDS, and adds the totals to a device table when the window ends; in the
 // product build the marks are empty.  A mark names the phase that ends at it.
-#define SIM_NPHASE 40
 enum {
   PH_FRAME_BEGIN = 0,   // observation, actor, reward, action store (frame start)
   PH_F_FK = 1,          // joint rotations and frame transforms (pointer jumping)

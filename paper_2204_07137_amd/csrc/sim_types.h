@@ -126,6 +126,9 @@ struct MlpArgsT {
   const T* src[SIM_MAXL];      // [out][in] caller weights, copied by the prep kernel
 };
 
+// phases of the window kernels' profile (a build with -DSIM_PHASE_PROFILE; ids in sim_math.h)
+#define SIM_NPHASE 40
+
 template <typename T>
 struct WinArgsT {
   const DevModelT<T>* model;

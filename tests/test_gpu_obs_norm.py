@@ -118,16 +118,12 @@ def test_obs_stats_update_matches_oracle(dt, tol):
 
 
 @pytest.mark.parametrize("precision,tol,adam_eps,fit_tol",
-                         [("fp64", 1e-12, 1e-8, 1e-8), ("fp32", 1e-5, 1e-8, 2e-2), ("fp32", 1e-5, 1e-3, 1e-4)])
+                         [("fp64", 1e-12, 1e-8, 1e-8), ("fp32", 1e-5, 1e-8, 1e-4), ("fp32", 1e-5, 1e-3, 1e-4)])
 def test_normalised_critic_values_and_fit_match_oracle(precision, tol, adam_eps, fit_tol):
     """Critic values and eight Adam steps of the critic fit against the oracle on normalised
-    rows.  The bar on the weight change: Adam's step lr m / (sqrt(v) + eps) is close to
-    lr sign(g) for every entry whose gradient g is far above eps, so a weight whose minibatch
-    gradient is a sum that nearly cancels changes sign under FP32 rounding of its terms and
-    moves by about 2 lr the other way (an O(1) relative error in that entry).  With eps = 1e-8
-    such entries are why the FP32 weight change is held to 2e-2 in relative norm (a few
-    entries in 10^4); with eps = 1e-3 the step is a smooth function of g at that scale and the
-    FP32 change is held to 1e-4, the bar of the losses."""
+    rows.  The FP32 weight change is held to the bar of the FP32 losses (1e-4 relative norm),
+    for Adam's usual eps and for a large eps under which the step is a smooth function of the
+    gradient (measured: 2e-6 and 3e-6)."""
     W = wl.workload("humanoid", 64)
     h, N = 4, 64
     sim = _sim(W, N, h, ckpt_interval=16, precision=precision)
