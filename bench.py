@@ -82,10 +82,10 @@ def traffic_record(path):
     return rec if rec.get("source_sha256") == kernel_source_hash() else None
 
 
-def adjoint_traffic(n_envs, k):
+def adjoint_traffic(n_envs, k, fc):
     """HBM bytes per k_window_adj launch at the headline workload, or None."""
     rec = traffic_record(TRAFFIC_RECORD)
-    if rec is None or n_envs != 1024 or k != 4:
+    if rec is None or n_envs != 1024 or k != 4 or bool(rec.get("factor_cache", False)) != fc:
         return None
     return float(rec["bytes_per_launch"])
 
@@ -94,21 +94,27 @@ def mlp_flops(dims):
     return float(sum(2 * a * b for a, b in zip(dims[:-1], dims[1:])))
 
 
-def algorithmic_bytes(md, n_envs, h, k, actor_dims, elem=4):
+def algorithmic_bytes(md, n_envs, h, k, actor_dims, elem=4, fc=False):
     """HBM bytes per env-step that the checkpointed window must move: per frame the
     observation, action, reward and dL/da; the checkpoints (S / k states of q, qd) written by
     the forward and read by the adjoint; the actor's hidden activations written by the forward
-    and read by the adjoint; s0, s_h, dL/ds0 and the terminal observation once per window."""
+    and read by the adjoint; with the factor cache, every substep's factor (lower triangle),
+    reciprocal pivots, flag and accelerations, written and read; s0, s_h, dL/ds0 and the
+    terminal observation once per window."""
     S = int(md["substeps"])
     nq, nv, na = int(md["nq"]), int(md["nv"]), int(md["na"])
     od = actor_dims[0]
     ns = nq + nv + (na if md["has_last_action"] else 0)
     hid = sum(actor_dims[1:-1])
     per_frame = (od + 2 * na + 1) + 2 * (S // k) * (nq + nv) + 2 * hid
+    if fc:
+        per_frame += 2 * S * (nv * (nv + 1) // 2 + 2 * nv + 1)
     per_window = 3 * ns + od
     return {"per_env_step": elem * (per_frame + per_window / h),
             "what": f"obs + action + reward + dL/da, {S // k} checkpoints written and read, hidden "
-                    f"activations written and read, per frame; s0, s_h, dL/ds0, o_h per window (FP32)"}
+                    f"activations written and read" + (", the cached factor and accelerations of "
+                    f"{S} substeps written and read" if fc else "") +
+                    ", per frame; s0, s_h, dL/ds0, o_h per window (FP32)"}
 
 
 def parse():
@@ -117,6 +123,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--no-factor-cache", action="store_true",
+                    help="headline without the factor cache (the adjoint recomputes whole substeps)")
     ap.add_argument("--envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -148,7 +156,8 @@ def phase_profile(args):
     W = wl.workload(args.model, args.envs)
     md, od, h = W["model"], W["obs_dim"], W["h"]
     S = int(md["substeps"])
-    kw = dict(path=P.PATH_TAPE) if args.path == "tape" else dict(ckpt_interval=args.k)
+    kw = dict(path=P.PATH_TAPE) if args.path == "tape" else dict(ckpt_interval=args.k,
+                                                                  factor_cache=not args.no_factor_cache)
     sim = P.Sim(md, args.envs, h, [od] + [w.shape[0] for w, _ in W["actor"]],
                 [od] + [w.shape[0] for w, _ in W["critic"]], **kw)
     s0, actor, critic = sim._dev(W["s0"]), sim.weights(W["actor"]), sim.weights(W["critic"])
@@ -157,7 +166,8 @@ def phase_profile(args):
     torch.cuda.synchronize()
     P.phase_profile(reset=True)
     out = {"workload": f"{args.model} {args.envs} envs, h={h}, S={S}, {args.path}" +
-                       (f" k={args.k}" if args.path == "persistent" else ""),
+                       (f" k={args.k}" + ("" if args.no_factor_cache else ", factor cache")
+                        if args.path == "persistent" else ""),
            "unit": "shader-clock cycles per env and substep (sum over the env's wavefront time)"}
     env_sub = args.envs * h * S
     for name, run in (("forward", lambda: sim.forward(s0, actor, critic)), ("adjoint", lambda: sim.adjoint(fw))):
@@ -261,9 +271,11 @@ def mixed_batch(P, wl, torch, budget_gb=64.0, steps=3):
         r = P.tune(W["model"], n, h, ad_, cd_, W["s0"], W["actor"], W["critic"], budget_bytes=int(left), reps=1)
         left -= r["workspace_bytes"]
         kw = dict(path=P.PATH_TAPE) if r["path"] == P.PATH_TAPE else dict(ckpt_interval=r["ckpt_interval"])
-        sim = P.Sim(W["model"], n, h, ad_, cd_, lanes_per_env=r["lanes_per_env"], **kw)
+        sim = P.Sim(W["model"], n, h, ad_, cd_, lanes_per_env=r["lanes_per_env"],
+                    factor_cache=bool(r["factor_cache"]), **kw)
         tuned.append({"model": name, "envs": n, "path": "tape" if r["path"] == P.PATH_TAPE else "persistent",
                       "k": r["ckpt_interval"], "lanes_per_env": r["lanes_per_env"],
+                      "factor_cache": bool(r["factor_cache"]),
                       "candidates": r["n_candidates"], "ms_window": round(r["ms_window"], 3),
                       "env_steps_per_s": round(n * h / (r["ms_window"] / 1e3), 1),
                       "workspace_gb": round(r["workspace_bytes"] / 1e9, 2)})
@@ -503,7 +515,9 @@ def main():
     actor_dims = [od] + [w.shape[0] for w, _ in W["actor"]]
     critic_dims = [od] + [w.shape[0] for w, _ in W["critic"]]
     N = args.envs
-    sim = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=args.k, policy_grad=not args.no_theta)
+    fc = not args.no_factor_cache
+    sim = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=args.k, policy_grad=not args.no_theta,
+                factor_cache=fc)
     s0 = sim._dev(W["s0"])
     actor = sim.weights(W["actor"])
     critic = sim.weights(W["critic"])
@@ -520,11 +534,11 @@ def main():
     fwd_avg_s = float(np.mean(fwd_ms)) / 1e3
     achieved = adj_launch_flops / adj_avg_s / 1e12
     fwd_achieved = fwd_flops_env_step * N * h / fwd_avg_s / 1e12
-    hbm = algorithmic_bytes(md, N, h, args.k, actor_dims)
+    hbm = algorithmic_bytes(md, N, h, args.k, actor_dims, fc=fc)
     step_s = wall / args.steps
     roof = {"bound": "alu", "kernel": "k_window_adj", "achieved": round(achieved, 4),
             "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 5), "traffic": adjoint_traffic(N, args.k),
+            "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 5), "traffic": adjoint_traffic(N, args.k, fc),
             "traffic_unit": "bytes per launch, profiler FETCH_SIZE + WRITE_SIZE scaled by a copy of known size",
             "flops_per_env_step": {"adjoint_kernel": adj_flops_env_step, "forward_kernel": fwd_flops_env_step,
                                    "counted": "oracle recursive form (oracle/count_ops.py), no recompute"},
@@ -553,9 +567,11 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": f"humanoid 13 bodies / 21 hinges / 10 contacts, {N} envs, h={h}, "
-                                  f"S={S} substeps, checkpoint k={args.k}, actor 76-256-128-21, "
+                                  f"S={S} substeps, checkpoint k={args.k}"
+                                  f"{', cached factorisation' if fc else ''}, actor 76-256-128-21, "
                                   f"critic 76-128-128-1", "envs": N, "h": h, "substeps": S,
-                      "ckpt_interval": args.k, "path": "persistent"},
+                      "ckpt_interval": args.k, "path": "persistent", "factor_cache": fc,
+                      "workspace_gb": round(sim.ws_bytes / 1e9, 3)},
            "roofline": roof, "contacts": contacts,
            # the paper's own figures (App. A.4, wall-clock breakdown of a training episode),
            # context only: another GPU, 64 envs, and its backward includes the actor update
@@ -617,12 +633,21 @@ def main():
                             "workspace_gb": round(tape.ws_bytes / 1e9, 2),
                             "vs_persistent": round(tval / value, 3)}
         del tape
+        # the same checkpoint interval with the other factor-cache setting
+        so = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=args.k, factor_cache=not fc)
+        ow, of, oa, _, _ = time_windows(so, s0, actor, critic, max(3, args.steps // 4), 1)
+        oval = N * h / (ow / max(3, args.steps // 4))
+        out["recompute_path" if fc else "factor_cache_path"] = {
+            "value": round(oval, 1), "unit": "env-steps/s", "factor_cache": not fc,
+            "fwd_ms": round(float(np.mean(of)), 3), "adj_ms": round(float(np.mean(oa)), 3),
+            "workspace_gb": round(so.ws_bytes / 1e9, 3), "vs_headline": round(oval / value, 3)}
+        del so
         sweep = {}
         for kk in (4, 8, 16):
             if kk == args.k:
                 sweep[str(kk)] = round(value, 1)
                 continue
-            sk = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=kk)
+            sk = P.Sim(md, N, h, actor_dims, critic_dims, ckpt_interval=kk, factor_cache=fc)
             kw, _, _, _, _ = time_windows(sk, s0, actor, critic, 3, 1)
             sweep[str(kk)] = round(N * h / (kw / 3), 1)
             del sk

@@ -178,6 +178,16 @@ typedef struct SimOptions {
                                     wavefront and several wavefronts per CU; n_envs must then be a
                                     multiple of 64 / lanes.  FP32 path, FP32 MLPs, persistent or
                                     tape path.  Results are bitwise those of the full layout. */
+  int factor_cache;              /* persistent path, torque-driven models: 1 = the forward also
+                                    keeps every substep's Cholesky factor, reciprocal pivots and
+                                    accelerations qdd (the factorisation cached for the backward
+                                    pass, Sec. 3.1; about 1.6 KB per substep and env for the
+                                    27-DOF humanoid in FP32), and the adjoint rebuilds each
+                                    checkpoint segment's states from the accelerations and
+                                    recomputes only the kinematics, contacts and body inertias of
+                                    each substep (no mass matrix, factorisation or solve).
+                                    0 = the adjoint recomputes whole substeps from the
+                                    checkpoints.  Results are bitwise the same either way. */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;
@@ -310,7 +320,8 @@ void sim_group_destroy(SimGroup* g);
 
 /* ---- Autotuner.  Times forward + adjoint windows of one model on the caller's inputs
  * for every launch configuration whose workspace fits workspace_budget: the tape path and
- * the persistent path at every checkpoint interval k dividing S, each in the full layout and,
+ * the persistent path at every checkpoint interval k dividing S (for torque-driven models
+ * with and without the factor cache), each in the full layout and,
  * for small models whose n_envs allows it, in the compact layout with 64, 32 and 16 lanes per
  * environment (opt->lanes_per_env is ignored); returns the fastest (median of reps windows
  * after a warm-up).  opt supplies everything else (N, h, MLP
@@ -324,6 +335,7 @@ typedef struct SimTuneResult {
   double ms_window;              /* its forward + adjoint time per window */
   int n_candidates;              /* configurations timed */
   int lanes_per_env;             /* the chosen layout (SimOptions.lanes_per_env) */
+  int factor_cache;              /* the chosen SimOptions.factor_cache */
 } SimTuneResult;
 int sim_tune(const SimModelDesc* model, const SimOptions* opt, const SimForwardIO* io,
              size_t workspace_budget, int reps, void* hip_stream, SimTuneResult* out);

@@ -43,7 +43,7 @@ class SimOptions(ctypes.Structure):
                 ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
                 ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
                 ("precision", _i), ("chol_fp64_threshold", _d), ("policy_grad", _i),
-                ("mlp_precision", _i), ("lanes_per_env", _i)]
+                ("mlp_precision", _i), ("lanes_per_env", _i), ("factor_cache", _i)]
 
 
 class SimForwardIO(ctypes.Structure):
@@ -66,7 +66,7 @@ class SimAdjointIO(ctypes.Structure):
 
 class SimTuneResult(ctypes.Structure):
     _fields_ = [("path", _i), ("ckpt_interval", _i), ("workspace_bytes", ctypes.c_size_t),
-                ("ms_window", _d), ("n_candidates", _i), ("lanes_per_env", _i)]
+                ("ms_window", _d), ("n_candidates", _i), ("lanes_per_env", _i), ("factor_cache", _i)]
 
 
 class SimCriticFitIO(ctypes.Structure):
@@ -227,7 +227,7 @@ class Sim:
 
     def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
                  path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6,
-                 policy_grad=False, mlp_precision="fp32", lanes_per_env=0):
+                 policy_grad=False, mlp_precision="fp32", lanes_per_env=0, factor_cache=False):
         import torch
         self.torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -255,6 +255,7 @@ class Sim:
         o.policy_grad = 1 if policy_grad else 0
         o.mlp_precision = {"fp32": 0, "bf16": 1}[mlp_precision]
         o.lanes_per_env = int(lanes_per_env)
+        o.factor_cache = 1 if factor_cache else 0
         self.actor_dims = list(actor_dims) if actor_dims is not None else None
         h = _p()
         _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
@@ -592,7 +593,7 @@ class Group:
 def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget_bytes,
          reps=3, precision="fp32", gamma=0.99):
     """Run sim_tune: the fastest launch configuration (path, k, layout) of this model within a
-    workspace budget.  Returns a dict with path, ckpt_interval, lanes_per_env,
+    workspace budget.  Returns a dict with path, ckpt_interval, lanes_per_env, factor_cache,
     workspace_bytes, ms_window and n_candidates."""
     import torch
     probe = Sim(md, n_envs, horizon, actor_dims, critic_dims, ckpt_interval=md["substeps"],
@@ -605,7 +606,7 @@ def tune(md, n_envs, horizon, actor_dims, critic_dims, s0, actor, critic, budget
                           _p(st.cuda_stream), ctypes.byref(r)))
     probe.close()
     return {"path": r.path, "ckpt_interval": r.ckpt_interval, "lanes_per_env": r.lanes_per_env,
-            "workspace_bytes": r.workspace_bytes, "ms_window": r.ms_window, "n_candidates": r.n_candidates,
+            "factor_cache": r.factor_cache, "workspace_bytes": r.workspace_bytes, "ms_window": r.ms_window, "n_candidates": r.n_candidates,
             "keep": out}
 
 
@@ -669,7 +670,7 @@ PHASES = ["frame_begin", "fk", "velocities", "contacts", "muscles", "newton_eule
           "bias_crba_columns", "crba", "cholesky", "factor_lds", "solve", "integrate", "tape_store", "commit",
           "checkpoint", "adj_seed", "adj_integrator", "adj_lambda", "adj_path_sums", "adj_contacts",
           "adj_muscles", "adj_body_terms", "adj_subtree_sums", "adj_derivatives", "adj_state", "tape_load",
-          "tape_prefetch", "adj_frame", "window_end", "termination"]
+          "tape_prefetch", "adj_frame", "window_end", "termination", "fc_states"]
 
 
 def phase_profile(reset=True):

@@ -83,6 +83,8 @@ struct SimHandle {
   size_t off_ckpt = 0, off_adj = 0, off_tape = 0, off_done = 0, off_seg = 0, off_hid = 0, ws_bytes = 0;
   int hid_w = 0;   // the actor's hidden widths, summed (closed loop)
   int tape_ws = 0;   // reals between consecutive tape entries
+  int fc_ws = 0;     // reals between consecutive factor-cache entries
+  size_t off_fc = 0, off_fcq = 0;
   // policy-gradient scratch: two layer-adjoint buffers, split partials (the hidden
   // activations are the window's own, at off_hid)
   size_t off_th_d0 = 0, off_th_d1 = 0, off_th_part = 0;
@@ -119,6 +121,7 @@ static const size_t kLayoutSimOptions[] = {
     offsetof(SimOptions, actor_dims), offsetof(SimOptions, critic_layers), offsetof(SimOptions, critic_dims),
     offsetof(SimOptions, gamma), offsetof(SimOptions, precision), offsetof(SimOptions, chol_fp64_threshold),
     offsetof(SimOptions, policy_grad), offsetof(SimOptions, mlp_precision), offsetof(SimOptions, lanes_per_env),
+    offsetof(SimOptions, factor_cache),
 };
 static const size_t kLayoutSimForwardIO[] = {
     offsetof(SimForwardIO, s0), offsetof(SimForwardIO, actions_in), offsetof(SimForwardIO, actor_w),
@@ -145,6 +148,7 @@ static const size_t kLayoutSimTuneResult[] = {
     offsetof(SimTuneResult, path), offsetof(SimTuneResult, ckpt_interval),
     offsetof(SimTuneResult, workspace_bytes), offsetof(SimTuneResult, ms_window),
     offsetof(SimTuneResult, n_candidates), offsetof(SimTuneResult, lanes_per_env),
+    offsetof(SimTuneResult, factor_cache),
 };
 static const size_t kLayoutSimCriticFitIO[] = {
     offsetof(SimCriticFitIO, obs), offsetof(SimCriticFitIO, targets), offsetof(SimCriticFitIO, rows),
@@ -207,6 +211,8 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   for (int p = 0; p < SIM_MAXPAIR; ++p) d.pair[p] = s.pair[p];
   d.tape_nw = s.tape_nw;
   for (int w = 0; w < SIM_MAXTAPEW; ++w) d.tape_off[w] = s.tape_off[w];
+  d.fc_nw = s.fc_nw;
+  for (int w = 0; w < SIM_MAXFCW; ++w) d.fc_off[w] = s.fc_off[w];
   d.tau_act = (T)s.tau_act; d.fl_w = (T)s.fl_w; d.vmax = (T)s.vmax;
   d.term_h = (T)s.term_h;
   for (int i = 0; i < SIM_MAXMTU; ++i) {
@@ -437,6 +443,10 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
     return fail(SIM_E_ARG, "BF16 MLPs run in the FP32 path");
   if (opt->mlp_precision == SIM_MLP_BF16 && opt->policy_grad)
     return fail(SIM_E_UNSUPPORTED, "the policy-parameter gradient runs with FP32 MLPs");
+  if (opt->factor_cache != 0 && opt->factor_cache != 1) return fail(SIM_E_ARG, "factor_cache must be 0 or 1");
+  if (opt->factor_cache && opt->path != SIM_PATH_PERSISTENT)
+    return fail(SIM_E_ARG, "the factor cache belongs to the persistent (checkpointed) path");
+  if (opt->factor_cache && m.n_mtu > 0) return fail(SIM_E_UNSUPPORTED, "the factor cache is for torque-driven models");
   if (opt->lanes_per_env != 0) {
     const int ln = opt->lanes_per_env;
     if (ln != 16 && ln != 32 && ln != 64) return fail(SIM_E_ARG, "lanes_per_env must be 0, 16, 32 or 64");
@@ -499,6 +509,25 @@ static void build_tape_map(DevModelT<double>& m, int J, int V, int C, int elem) 
   for (int i = w; i < SIM_MAXTAPEW; ++i) m.tape_off[i] = 0;
 }
 
+// The 16-byte chunks of a factor-cache entry: the lower triangle of the Cholesky factor row by
+// row, the reciprocal pivots and the fallback flag (the accelerations travel in a row of their
+// own).
+static void build_fc_map(DevModelT<double>& m, int J, int V, int C, int elem) {
+  const SimTapeLayout T = sim_tape_layout(J, V, C);
+  const int wpc = 16 / elem;
+  int w = 0, last = -1;
+  auto run = [&](int base, int n) {
+    if (n <= 0) return;
+    for (int c = base / wpc; c <= (base + n - 1) / wpc; ++c)
+      if (c != last) { m.fc_off[w++] = (unsigned short)c; last = c; }
+  };
+  for (int r = 0; r < m.nv; ++r) run(T.M + r * (V + 1), r + 1);
+  run(T.tdinv, m.nv);
+  run(T.tfb, 1);
+  m.fc_nw = w;
+  for (int i = w; i < SIM_MAXFCW; ++i) m.fc_off[i] = 0;
+}
+
 extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHandle** out) {
   if (!md || !opt || !out) return fail(SIM_E_ARG, "sim_create: null argument");
   *out = nullptr;
@@ -511,8 +540,18 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   m.chol_thr = opt->chol_fp64_threshold;
   {
     const int elem = (opt->precision == SIM_PREC_FP64) ? 8 : 4;
-    if (opt->lanes_per_env) build_tape_map(m, SIM_CJ, SIM_CV, SIM_CC, elem);
-    else build_tape_map(m, SIM_MAXJ, SIM_MAXV, SIM_MAXC, elem);
+    if (opt->lanes_per_env) {
+      build_tape_map(m, SIM_CJ, SIM_CV, SIM_CC, elem);
+      build_fc_map(m, SIM_CJ, SIM_CV, SIM_CC, elem);
+    } else {
+      build_tape_map(m, SIM_MAXJ, SIM_MAXV, SIM_MAXC, elem);
+      build_fc_map(m, SIM_MAXJ, SIM_MAXV, SIM_MAXC, elem);
+    }
+    const int fcap = sim_fc_chunk_cap(opt->lanes_per_env ? SIM_CV : SIM_MAXV, elem);
+    if (m.fc_nw > fcap || m.fc_nw > SIM_MAXFCW) {
+      delete h;
+      return fail(SIM_E_MODEL, "sim_create: factor-cache entry beyond the layout's chunk capacity");
+    }
     // the kernels hold an entry's chunk offsets in registers sized for this bound
     const int cap = opt->lanes_per_env ? sim_tape_chunk_cap(SIM_CJ, SIM_CV, SIM_CC, 0, elem)
                                        : sim_tape_chunk_cap(SIM_MAXJ, SIM_MAXV, SIM_MAXC, m.n_mtu > 0 ? SIM_MAXMTU : 0, elem);
@@ -586,13 +625,23 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   h->off_adj = off;
   off = align256(off + e * N * (nqv + m.na));
   // linearisation tape: every substep of the window (tape path) or one recomputed
-  // segment but its last substep per env (persistent path)
+  // segment but its last substep per env (persistent path); with the factor cache, the
+  // pre-substep states of one segment per env instead
   const size_t tape_entries = (opt->path == SIM_PATH_TAPE) ? (size_t)opt->horizon * m.substeps * N
-                              : (opt->path == SIM_PATH_PERSISTENT) ? N * (size_t)(opt->ckpt_interval - 1) : 0;
+                              : (opt->path == SIM_PATH_PERSISTENT && !opt->factor_cache)
+                                  ? N * (size_t)(opt->ckpt_interval - 1) : 0;
   h->off_tape = off;
   // packed entries of 16-byte chunks, each entry rounded up to 256 bytes
   h->tape_ws = (m.tape_nw * 16 / (int)e + 256 / (int)e - 1) / (256 / (int)e) * (256 / (int)e);
   off = align256(off + tape_entries * (size_t)h->tape_ws * e);
+  if (opt->factor_cache) off = align256(off + e * N * (size_t)opt->ckpt_interval * nqv);
+  // factor cache: [h S][N] entries and [h S][N][nv] accelerations
+  h->fc_ws = opt->factor_cache ? (m.fc_nw * 16 / (int)e + 256 / (int)e - 1) / (256 / (int)e) * (256 / (int)e) : 0;
+  h->off_fc = off;
+  const size_t fc_subs = opt->factor_cache ? (size_t)opt->horizon * m.substeps * N : 0;
+  off = align256(off + e * fc_subs * (size_t)h->fc_ws);
+  h->off_fcq = off;
+  off = align256(off + e * fc_subs * (size_t)m.nv);
   h->off_done = off;
   off = align256(off + (size_t)opt->horizon * N);
   h->off_seg = off;
@@ -733,6 +782,11 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (h->opt.path == SIM_PATH_TAPE);
   A.tape_ws = h->tape_ws;
+  if (h->opt.factor_cache) {
+    A.fc = reinterpret_cast<T*>(ws + h->off_fc);
+    A.fcq = reinterpret_cast<T*>(ws + h->off_fcq);
+    A.fc_ws = h->fc_ws;
+  }
 #ifdef SIM_PHASE_PROFILE
   A.prof = phase_on_device(h->device);
 #endif
@@ -771,6 +825,11 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   A.tape = reinterpret_cast<T*>(ws + h->off_tape);
   A.tape_full = (o.path == SIM_PATH_TAPE);
   A.tape_ws = h->tape_ws;
+  if (h->opt.factor_cache) {
+    A.fc = reinterpret_cast<T*>(ws + h->off_fc);
+    A.fcq = reinterpret_cast<T*>(ws + h->off_fcq);
+    A.fc_ws = h->fc_ws;
+  }
 #ifdef SIM_PHASE_PROFILE
   A.prof = phase_on_device(h->device);
 #endif
@@ -1179,7 +1238,7 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
   if (reps < 1) return fail(SIM_E_ARG, "sim_tune: reps must be >= 1");
   std::memset(out, 0, sizeof(*out));
   hipStream_t st = (hipStream_t)hip_stream;
-  struct Cand { int path, k, lanes; };
+  struct Cand { int path, k, lanes, fc; };
   std::vector<Cand> cands;
   for (int lanes : {0, 64, 32, 16}) {
     if (lanes) {
@@ -1188,12 +1247,26 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
       o.lanes_per_env = lanes;
       o.path = SIM_PATH_TAPE;
       o.ckpt_interval = 1;
+      o.factor_cache = 0;
       DevModelT<double> m;
       if (build_model(model, m) || check_options(&o, m)) continue;
     }
-    cands.push_back({SIM_PATH_TAPE, 1, lanes});
+    bool fc_ok = false;
+    {
+      SimOptions o = *opt;
+      o.lanes_per_env = lanes;
+      o.path = SIM_PATH_PERSISTENT;
+      o.ckpt_interval = model->substeps;
+      o.factor_cache = 1;
+      DevModelT<double> m;
+      fc_ok = !build_model(model, m) && !check_options(&o, m);
+    }
+    cands.push_back({SIM_PATH_TAPE, 1, lanes, 0});
     for (int k = 1; k <= model->substeps; ++k)
-      if (model->substeps % k == 0) cands.push_back({SIM_PATH_PERSISTENT, k, lanes});
+      if (model->substeps % k == 0) {
+        cands.push_back({SIM_PATH_PERSISTENT, k, lanes, 0});
+        if (fc_ok) cands.push_back({SIM_PATH_PERSISTENT, k, lanes, 1});
+      }
   }
   double best = -1.0;
   hipEvent_t e0, e1;
@@ -1204,6 +1277,7 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
     o.path = c.path;
     o.ckpt_interval = c.k;
     o.lanes_per_env = c.lanes;
+    o.factor_cache = c.fc;
     SimHandle* h = nullptr;
     rc = sim_create(model, &o, &h);
     if (rc) break;
@@ -1264,6 +1338,7 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
       out->workspace_bytes = ws;
       out->ms_window = med;
       out->lanes_per_env = c.lanes;
+      out->factor_cache = c.fc;
     }
   }
   hipEventDestroy(e0);

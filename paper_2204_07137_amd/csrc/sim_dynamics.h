@@ -50,8 +50,10 @@ struct EnvLDST {
   static constexpr int kMaxA = MAXA;
   static constexpr int kLanes = LANES;
   static constexpr int kJ = CJ, kV = CV, kQ = CV + 1, kC = CC, kObs = COBS, kHid = CHID, kPair = CPAIR;
-  // the most 16-byte chunks a packed tape entry of this layout can need, and per lane
+  // the most 16-byte chunks a packed tape entry / a factor-cache entry of this layout can need,
+  // per lane
   static constexpr int kTapeChunksPerLane = (sim_tape_chunk_cap(CJ, CV, CC, NMTU, (int)sizeof(real)) + LANES - 1) / LANES;
+  static constexpr int kFcChunksPerLane = (sim_fc_chunk_cap(CV, (int)sizeof(real)) + LANES - 1) / LANES;
   // The linearisation of the current substep, one contiguous block whose fields
   // sim_tape_layout describes; a tape entry holds the words of it that the model uses
   // (for torque-driven models no R and p: those are rebuilt by any recomputation and never
@@ -624,18 +626,18 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
   wsync();
 }
 
-template <int NV, class L>
-__device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E,
-                                                const JointRegs& jr, const ContactRegs& cr, int ln,
-                                                Chol& C, bool inplace, int& fb) {
+// Kinematics and contacts of the substep (the part of the forward that the reverse reads back,
+// besides the factor and the accelerations): reference point, joint rotations, frame
+// transforms, screws, velocities and bias accelerations, contact forces.  Leaves the lane's
+// frame rotation and position in R, p and its screw, velocity and bias acceleration in S, v, ab.
+template <class L>
+__device__ __forceinline__ void substep_kin(const Scal* __restrict__ m, L& E, const JointRegs& jr,
+                                            const ContactRegs& cr, int ln, real* R, f3& p, sv& S, sv& v, sv& ab) {
   constexpr int LN = L::kLanes;
-  const int J = m->J, nv = m->nv, nc = m->nc;
+  const int J = m->J, nc = m->nc;
   const real g = m->g;
-  const real dt = m->dt_sub;
   // reference point O = root position (floating) or world origin
   if (ln < 3) E.O[ln] = m->floating ? E.q[ln] : RL(0.0);
-  // clear M
-  for (int i = ln; i < L::kV * (L::kV + 1); i += LN) (&E.M[0][0])[i] = RL(0.0);
   wsync();
   // ---- local joint rotations (all lanes at once), then kinematics, velocities and bias
   // accelerations along the root paths; each lane keeps its own frame's results in registers
@@ -662,9 +664,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
       }
     }
   }
-  real R[9];
-  f3 p;
-  sv S = zsv(), v, ab;
+  S = zsv();
   int rounds = 0;
   while ((1 << rounds) <= m->max_depth) ++rounds;
   {
@@ -780,37 +780,91 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   }
   wsync();
   SIM_PHASE(E, PH_F_CONTACT);
+}
+
+// The world spatial inertia (10 numbers) of the lane's body from its frame R, p.
+template <class L>
+__device__ __forceinline__ void body_inertia(const L& E, const JointRegs& jr, int ln, const real* R, f3 p,
+                                             real* Ib) {
+  real mass = jr.mass;
+  f3 c = add3(p, mv3(R, ld3(E.j_com[ln])));
+  // Ic_w = R I R^T
+  const real* I6 = E.j_I6[ln];
+  real Il[9] = {I6[0], I6[3], I6[4], I6[3], I6[1], I6[5], I6[4], I6[5], I6[2]};
+  real T[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) T[3 * r + k] = R[3 * r] * Il[k] + R[3 * r + 1] * Il[3 + k] + R[3 * r + 2] * Il[6 + k];
+  real Iw[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Iw[3 * r + k] = T[3 * r] * R[3 * k] + T[3 * r + 1] * R[3 * k + 1] + T[3 * r + 2] * R[3 * k + 2];
+  real cc = dot3(c, c);
+  Ib[0] = mass;
+  Ib[1] = mass * c.x; Ib[2] = mass * c.y; Ib[3] = mass * c.z;
+  Ib[4] = Iw[0] + mass * (cc - c.x * c.x);
+  Ib[5] = Iw[4] + mass * (cc - c.y * c.y);
+  Ib[6] = Iw[8] + mass * (cc - c.z * c.z);
+  Ib[7] = Iw[1] - mass * c.x * c.y;
+  Ib[8] = Iw[2] - mass * c.x * c.z;
+  Ib[9] = Iw[5] - mass * c.y * c.z;
+}
+
+// Positions from the new velocities E.qdn (semi-implicit Euler; the free root's orientation
+// by the exact exponential map) into E.qn, and the muscle activations into E.actn.
+template <class L>
+__device__ __forceinline__ void integrate_positions(const Scal* __restrict__ m, L& E, const JointRegs& jr, int ln) {
+  const real dt = m->dt_sub;
+  const int J = m->J;
+  // ---- positions with the new velocities (lane = joint)
+  if (ln < J) {
+    if (jr.type == J_FREE) {
+      int qa = jr.qa, va = jr.va;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) E.qn[qa + k] = E.q[qa + k] + dt * E.qdn[va + k];
+      f3 w = mk3(E.qdn[va + 3], E.qdn[va + 4], E.qdn[va + 5]);
+      real c, s, dc, ds;
+      dq_coeffs(dot3(w, w), RL(0.5) * dt, c, s, dc, ds);
+      real a0 = c, a1 = s * w.x, a2 = s * w.y, a3 = s * w.z;
+      real b0 = E.q[qa + 3], b1 = E.q[qa + 4], b2 = E.q[qa + 5], b3 = E.q[qa + 6];
+      E.qn[qa + 3] = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
+      E.qn[qa + 4] = a0 * b1 + a1 * b0 + a2 * b3 - a3 * b2;
+      E.qn[qa + 5] = a0 * b2 - a1 * b3 + a2 * b0 + a3 * b1;
+      E.qn[qa + 6] = a0 * b3 + a1 * b2 - a2 * b1 + a3 * b0;
+    } else {
+      E.qn[jr.qa] = E.q[jr.qa] + dt * E.qdn[jr.va];
+    }
+  }
+  if constexpr (L::kMtu > 0) {
+    // activation lag, explicit with the pre-substep activation
+    const real ka = dt / m->tau_act;
+    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.actn[i] = E.act[i] + ka * (E.a[m->n_motor + i] - E.act[i]);
+  }
+}
+
+template <int NV, class L>
+__device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E,
+                                                const JointRegs& jr, const ContactRegs& cr, int ln,
+                                                Chol& C, bool inplace, int& fb) {
+  constexpr int LN = L::kLanes;
+  const int J = m->J, nv = m->nv;
+  const real dt = m->dt_sub;
+  // clear M
+  for (int i = ln; i < L::kV * (L::kV + 1); i += LN) (&E.M[0][0])[i] = RL(0.0);
+  real R[9];
+  f3 p;
+  sv S, v, ab;
+  substep_kin(m, E, jr, cr, ln, R, p, S, v, ab);
   if constexpr (L::kMtu > 0) {
     muscle_wrenches(m, E, ln);
     SIM_PHASE(E, PH_F_MUSCLE);
   }
   // ---- body inertias and Newton-Euler forces (lane = joint), joint torques
   if (ln < J) {
-    real mass = jr.mass;
-    f3 c = add3(p, mv3(R, ld3(E.j_com[ln])));
-    // Ic_w = R I R^T
-    const real* I6 = E.j_I6[ln];
-    real Il[9] = {I6[0], I6[3], I6[4], I6[3], I6[1], I6[5], I6[4], I6[5], I6[2]};
-    real T[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) T[3 * r + k] = R[3 * r] * Il[k] + R[3 * r + 1] * Il[3 + k] + R[3 * r + 2] * Il[6 + k];
-    real Iw[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) Iw[3 * r + k] = T[3 * r] * R[3 * k] + T[3 * r + 1] * R[3 * k + 1] + T[3 * r + 2] * R[3 * k + 2];
-    real cc = dot3(c, c);
     real Ib[10];
-    Ib[0] = mass;
-    Ib[1] = mass * c.x; Ib[2] = mass * c.y; Ib[3] = mass * c.z;
-    Ib[4] = Iw[0] + mass * (cc - c.x * c.x);
-    Ib[5] = Iw[4] + mass * (cc - c.y * c.y);
-    Ib[6] = Iw[8] + mass * (cc - c.z * c.z);
-    Ib[7] = Iw[1] - mass * c.x * c.y;
-    Ib[8] = Iw[2] - mass * c.x * c.z;
-    Ib[9] = Iw[5] - mass * c.y * c.z;
+    body_inertia(E, jr, ln, R, p, Ib);
 #pragma unroll
     for (int k = 0; k < 10; ++k) { E.Ib[ln][k] = Ib[k]; E.Ic[ln][k] = Ib[k]; }
     sv hv = iapply(Ib, v);
@@ -936,30 +990,7 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   }
   wsync();
   SIM_PHASE(E, PH_F_SOLVE);
-  // ---- positions with the new velocities (lane = joint)
-  if (ln < J) {
-    if (jr.type == J_FREE) {
-      int qa = jr.qa, va = jr.va;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) E.qn[qa + k] = E.q[qa + k] + dt * E.qdn[va + k];
-      f3 w = mk3(E.qdn[va + 3], E.qdn[va + 4], E.qdn[va + 5]);
-      real c, s, dc, ds;
-      dq_coeffs(dot3(w, w), RL(0.5) * dt, c, s, dc, ds);
-      real a0 = c, a1 = s * w.x, a2 = s * w.y, a3 = s * w.z;
-      real b0 = E.q[qa + 3], b1 = E.q[qa + 4], b2 = E.q[qa + 5], b3 = E.q[qa + 6];
-      E.qn[qa + 3] = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
-      E.qn[qa + 4] = a0 * b1 + a1 * b0 + a2 * b3 - a3 * b2;
-      E.qn[qa + 5] = a0 * b2 - a1 * b3 + a2 * b0 + a3 * b1;
-      E.qn[qa + 6] = a0 * b3 + a1 * b2 - a2 * b1 + a3 * b0;
-    } else {
-      E.qn[jr.qa] = E.q[jr.qa] + dt * E.qdn[jr.va];
-    }
-  }
-  if constexpr (L::kMtu > 0) {
-    // activation lag, explicit with the pre-substep activation
-    const real ka = dt / m->tau_act;
-    for (int i = ln; i < m->n_mtu; i += SIM_WAVE) E.actn[i] = E.act[i] + ka * (E.a[m->n_motor + i] - E.act[i]);
-  }
+  integrate_positions(m, E, jr, ln);
   wsync();
   if (inplace) {
     if (ln < m->nq) E.q[ln] = E.qn[ln];
@@ -969,6 +1000,26 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
     wsync();
   }
   SIM_PHASE(E, PH_F_INTEG);
+}
+
+// What the reverse of a substep reads of its forward when the factor and the accelerations
+// come from the factor cache: the kinematics, the contacts and the body inertias of the
+// pre-substep state, computed by the forward's own code.
+template <class L>
+__device__ __forceinline__ void substep_kinematics(const Scal* __restrict__ m, L& E, const JointRegs& jr,
+                                                   const ContactRegs& cr, int ln) {
+  real R[9];
+  f3 p;
+  sv S, v, ab;
+  substep_kin(m, E, jr, cr, ln, R, p, S, v, ab);
+  if (ln < m->J) {
+    real Ib[10];
+    body_inertia(E, jr, ln, R, p, Ib);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) E.Ib[ln][k] = Ib[k];
+  }
+  wsync();
+  SIM_PHASE(E, PH_F_NE);
 }
 
 // --------------------------------------------------------------- adjoint of one substep
@@ -1246,32 +1297,65 @@ __device__ __forceinline__ constexpr bool tape_layout_ok() {
 
 typedef unsigned int tape_u32x4 __attribute__((ext_vector_type(4)));
 
-// The block offsets (16-byte units) of the chunks this lane moves: chunk w of a packed entry is
-// the block's chunk m->tab->tape_off[w], and lane ln of the environment moves chunks ln, ln + LN,
-// ... (consecutive lanes, consecutive 16 bytes).  Read once per kernel into registers; -1 past
-// the entry's last chunk.
-template <class L>
-struct TapeMap {
-  int off[L::kTapeChunksPerLane];
+// An entry (tape or factor cache) moves in 16-byte chunks of the LDS block: chunk w of the entry
+// is the block's chunk off[w] (16-byte units from the block's start), and lane ln of the
+// environment moves chunks ln, ln + LN, ... (consecutive lanes, consecutive 16 bytes).  A lane
+// reads its chunks' block offsets once per kernel into registers; -1 past the entry's end.
+template <int NCH>
+struct ChunkMap {
+  int off[NCH];
 };
-template <class L>
-__device__ __forceinline__ TapeMap<L> tape_map(const Scal* __restrict__ m, int ln) {
-  TapeMap<L> T;
-  const int nw = m->tape_nw;
+template <int NCH>
+struct ChunkRegs {
+  tape_u32x4 v[NCH];
+};
+template <int NCH, int LN>
+__device__ __forceinline__ ChunkMap<NCH> chunk_map(const unsigned short* __restrict__ off, int nw, int ln) {
+  ChunkMap<NCH> T;
 #pragma unroll
-  for (int i = 0; i < L::kTapeChunksPerLane; ++i) {
-    const int w = i * L::kLanes + ln;
-    T.off[i] = (w < nw) ? (int)m->tab->tape_off[w] : -1;
+  for (int i = 0; i < NCH; ++i) {
+    const int w = i * LN + ln;
+    T.off[i] = (w < nw) ? (int)off[w] : -1;
   }
   return T;
 }
+// streaming (non-temporal) stores and loads: entries must not displace the policy weights in L2
+template <int NCH, int LN>
+__device__ __forceinline__ void chunks_store(const ChunkMap<NCH>& T, const real* blk, real* __restrict__ dst, int ln) {
+  const tape_u32x4* b = reinterpret_cast<const tape_u32x4*>(blk);
+  tape_u32x4* d = reinterpret_cast<tape_u32x4*>(dst);
+#pragma unroll
+  for (int i = 0; i < NCH; ++i)
+    if (T.off[i] >= 0) __builtin_nontemporal_store(b[T.off[i]], &d[i * LN + ln]);
+}
+template <int NCH, int LN>
+__device__ __forceinline__ void chunks_prefetch(const ChunkMap<NCH>& T, ChunkRegs<NCH>& P, const real* __restrict__ src,
+                                                int ln) {
+  const tape_u32x4* s = reinterpret_cast<const tape_u32x4*>(src);
+#pragma unroll
+  for (int i = 0; i < NCH; ++i)
+    if (T.off[i] >= 0) P.v[i] = __builtin_nontemporal_load(&s[i * LN + ln]);
+}
+template <int NCH>
+__device__ __forceinline__ void chunks_restore(const ChunkMap<NCH>& T, real* blk, const ChunkRegs<NCH>& P) {
+  tape_u32x4* b = reinterpret_cast<tape_u32x4*>(blk);
+#pragma unroll
+  for (int i = 0; i < NCH; ++i)
+    if (T.off[i] >= 0) b[T.off[i]] = P.v[i];
+}
 
+template <class L>
+using TapeMap = ChunkMap<L::kTapeChunksPerLane>;
+template <class L>
+using TapeRegs = ChunkRegs<L::kTapeChunksPerLane>;
+template <class L>
+__device__ __forceinline__ TapeMap<L> tape_map(const Scal* __restrict__ m, int ln) {
+  return chunk_map<L::kTapeChunksPerLane, L::kLanes>(m->tab->tape_off, m->tape_nw, ln);
+}
+
+// the reciprocal pivots and the fallback flag into the block (both entries carry them)
 template <int NV, class L>
-__device__ __forceinline__ void tape_store(const TapeMap<L>& T, L& E, const Chol& C, int fb, int ln,
-                                           real* __restrict__ tp) {
-  static_assert(offsetof(L, q) == 0, "tape block first");
-  static_assert(tape_layout_ok<L>(), "LDS block as sim_tape_layout describes it");
-  constexpr int LN = L::kLanes;
+__device__ __forceinline__ void stash_pivots(L& E, const Chol& C, int fb, int ln) {
   real dv = RL(0.0);
 #pragma unroll
   for (int k = 0; k < NV; ++k) dv = (ln == k) ? C.dinv[k] : dv;
@@ -1280,53 +1364,13 @@ __device__ __forceinline__ void tape_store(const TapeMap<L>& T, L& E, const Chol
     E.tfb[ln] = fb ? RL(1.0) : RL(0.0);
   }
   wsync();
-  const tape_u32x4* blk = reinterpret_cast<const tape_u32x4*>(&E.q[0]);
-  tape_u32x4* dst = reinterpret_cast<tape_u32x4*>(tp);
-  // streaming (non-temporal) stores: the tape must not displace the policy weights in L2
-#pragma unroll
-  for (int i = 0; i < L::kTapeChunksPerLane; ++i)
-    if (T.off[i] >= 0) __builtin_nontemporal_store(blk[T.off[i]], &dst[i * LN + ln]);
-  SIM_PHASE(E, PH_TAPE_STORE);
 }
 
-// A tape entry held in registers (the lane's chunks): the adjoint loads the next entry while
-// the current substep's reverse runs, so the load latency is hidden.
-template <class L>
-struct TapeRegs {
-  tape_u32x4 v[L::kTapeChunksPerLane];
-};
-
-template <class L>
-__device__ __forceinline__ void tape_prefetch(const TapeMap<L>& T, TapeRegs<L>& P, const real* __restrict__ tp,
-                                              int ln) {
-  const tape_u32x4* src = reinterpret_cast<const tape_u32x4*>(tp);
-#pragma unroll
-  for (int i = 0; i < L::kTapeChunksPerLane; ++i)
-    if (T.off[i] >= 0) P.v[i] = __builtin_nontemporal_load(&src[i * L::kLanes + ln]);
-}
-
-// tape_load from a prefetched entry: the chunks back into the block, the new velocities
-// rebuilt as the forward computed them (qdn = qd + dt qdd), the factor into registers
+// The factor into registers from the block: the model's nv rows of the factor (lower
+// triangle) and pivots; a kernel compiled for NV > nv pads the matrix with the identity, whose
+// factor is the identity (pivots 1), as the forward's factorisation left it.
 template <int NV, class L>
-__device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, const TapeMap<L>& T, L& E, Chol& C,
-                                               int& fb, int ln, const TapeRegs<L>& P) {
-  tape_u32x4* blk = reinterpret_cast<tape_u32x4*>(&E.q[0]);
-  // LDS ordering only (one wavefront per environment): the tape stores still in flight
-  // need not complete here, and the registers wait for their own loads
-  wsync();   // earlier LDS reads of the block complete before it is overwritten
-#pragma unroll
-  for (int i = 0; i < L::kTapeChunksPerLane; ++i)
-    if (T.off[i] >= 0) blk[T.off[i]] = P.v[i];
-  wsync();
-  if (ln < m->nv) {
-    const real dt = m->dt_sub;
-    real qdn = E.qd[ln] + dt * E.qdd[ln];
-    E.qdn[ln] = qdn;
-  }
-  wsync();
-  // the entry holds the model's nv rows of the factor (lower triangle) and pivots; a kernel
-  // compiled for NV > nv pads the matrix with the identity, whose factor is the identity
-  // (pivots 1), as the forward's factorisation left it
+__device__ __forceinline__ void factor_from_block(const Scal* __restrict__ m, const L& E, Chol& C, int& fb, int ln) {
   const int nv = m->nv;
   const int lr = ln < nv ? ln : 0;
 #pragma unroll
@@ -1339,5 +1383,118 @@ __device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, const
   // uniform over the environment's lanes (its own LDS); over the wavefront only with 64 lanes
   if constexpr (L::kLanes == SIM_WAVE) fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
   else fb = (E.tfb[0] != RL(0.0)) ? 1 : 0;
+}
+
+// the new velocities as the forward computed them (qdn = qd + dt qdd)
+template <class L>
+__device__ __forceinline__ void rebuild_qdn(const Scal* __restrict__ m, L& E, int ln) {
+  if (ln < m->nv) {
+    const real dt = m->dt_sub;
+    real qdn = E.qd[ln] + dt * E.qdd[ln];
+    E.qdn[ln] = qdn;
+  }
+  wsync();
+}
+
+template <int NV, class L>
+__device__ __forceinline__ void tape_store(const TapeMap<L>& T, L& E, const Chol& C, int fb, int ln,
+                                           real* __restrict__ tp) {
+  static_assert(offsetof(L, q) == 0, "tape block first");
+  static_assert(tape_layout_ok<L>(), "LDS block as sim_tape_layout describes it");
+  stash_pivots<NV>(E, C, fb, ln);
+  chunks_store<L::kTapeChunksPerLane, L::kLanes>(T, &E.q[0], tp, ln);
+  SIM_PHASE(E, PH_TAPE_STORE);
+}
+
+// A tape entry held in registers (the lane's chunks): the adjoint loads the next entry while
+// the current substep's reverse runs, so the load latency is hidden.
+template <class L>
+__device__ __forceinline__ void tape_prefetch(const TapeMap<L>& T, TapeRegs<L>& P, const real* __restrict__ tp,
+                                              int ln) {
+  chunks_prefetch<L::kTapeChunksPerLane, L::kLanes>(T, P, tp, ln);
+}
+
+// tape_load from a prefetched entry: the chunks back into the block, the new velocities
+// rebuilt, the factor into registers
+template <int NV, class L>
+__device__ __forceinline__ void tape_load_regs(const Scal* __restrict__ m, const TapeMap<L>& T, L& E, Chol& C,
+                                               int& fb, int ln, const TapeRegs<L>& P) {
+  // LDS ordering only (one wavefront per environment): the tape stores still in flight
+  // need not complete here, and the registers wait for their own loads
+  wsync();   // earlier LDS reads of the block complete before it is overwritten
+  chunks_restore<L::kTapeChunksPerLane>(T, &E.q[0], P);
+  wsync();
+  rebuild_qdn(m, E, ln);
+  factor_from_block<NV>(m, E, C, fb, ln);
   SIM_PHASE(E, PH_TAPE_LOAD);
+}
+
+// ---- factor cache (persistent path): the forward keeps every substep's Cholesky factor,
+// reciprocal pivots and fallback flag (an entry of chunks of the block) and its accelerations
+// qdd (a row of nv values); the adjoint rebuilds the states of a checkpoint segment from the
+// accelerations and recomputes only the kinematics, contacts and inertias of each substep.
+template <class L>
+using FcMap = ChunkMap<L::kFcChunksPerLane>;
+template <class L>
+struct FcRegs {
+  ChunkRegs<L::kFcChunksPerLane> c;
+  real qdd, q, qd;   // lane ln: qdd[ln], and q[ln], qd[ln] of the pre-substep state
+};
+template <class L>
+__device__ __forceinline__ FcMap<L> fc_map(const Scal* __restrict__ m, int ln) {
+  return chunk_map<L::kFcChunksPerLane, L::kLanes>(m->tab->fc_off, m->fc_nw, ln);
+}
+
+template <int NV, class L>
+__device__ __forceinline__ void fc_store(const Scal* __restrict__ m, const FcMap<L>& T, L& E, const Chol& C, int fb,
+                                         int ln, real* __restrict__ entry, real* __restrict__ qrow) {
+  stash_pivots<NV>(E, C, fb, ln);
+  chunks_store<L::kFcChunksPerLane, L::kLanes>(T, &E.q[0], entry, ln);
+  if (ln < m->nv) qrow[ln] = E.qdd[ln];
+  SIM_PHASE(E, PH_TAPE_STORE);
+}
+
+// the entry, the accelerations and the pre-substep state [q | qd] (at most one coordinate and
+// one velocity per lane: torque models, nq and nv at most the environment's lanes) into registers
+template <class L>
+__device__ __forceinline__ void fc_prefetch(const Scal* __restrict__ m, const FcMap<L>& T, FcRegs<L>& P,
+                                            const real* __restrict__ entry, const real* __restrict__ qrow,
+                                            const real* __restrict__ pre, int ln) {
+  chunks_prefetch<L::kFcChunksPerLane, L::kLanes>(T, P.c, entry, ln);
+  P.qdd = (ln < m->nv) ? qrow[ln] : RL(0.0);
+  P.q = (ln < m->nq) ? pre[ln] : RL(0.0);
+  P.qd = (ln < m->nv) ? pre[m->nq + ln] : RL(0.0);
+}
+
+// a prefetched entry back: the pre-substep state, factor and pivots into the block and
+// registers, qdd and the new velocities
+template <int NV, class L>
+__device__ __forceinline__ void fc_load_regs(const Scal* __restrict__ m, const FcMap<L>& T, L& E, Chol& C, int& fb,
+                                             int ln, const FcRegs<L>& P) {
+  wsync();
+  chunks_restore<L::kFcChunksPerLane>(T, &E.q[0], P.c);
+  if (ln < m->nq) E.q[ln] = P.q;
+  if (ln < m->nv) {
+    E.qd[ln] = P.qd;
+    E.qdd[ln] = P.qdd;
+  }
+  wsync();
+  rebuild_qdn(m, E, ln);
+  factor_from_block<NV>(m, E, C, fb, ln);
+  SIM_PHASE(E, PH_TAPE_LOAD);
+}
+
+// the substep's accelerations (lane ln: qdd[ln]) from the cache, then the post-substep state
+// made current (the state recursion of the forward, without its dynamics)
+template <class L>
+__device__ __forceinline__ void fc_step_state(const Scal* __restrict__ m, L& E, const JointRegs& jr, real qdd,
+                                              int ln) {
+  if (ln < m->nv) E.qdd[ln] = qdd;
+  wsync();
+  rebuild_qdn(m, E, ln);
+  integrate_positions(m, E, jr, ln);
+  wsync();
+  if (ln < m->nq) E.q[ln] = E.qn[ln];
+  if (ln < m->nv) E.qd[ln] = E.qdn[ln];
+  wsync();
 }

@@ -157,6 +157,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
   const int S = m->substeps, nqv = m->nck, N = A.N;
   load_state(m, E, A.s0 + (size_t)env * m->ns, ln);
   const TapeMap<L> TM = tape_map<L>(m, ln);
+  const FcMap<L> FM = fc_map<L>(m, ln);
 #ifdef SIM_PHASE_PROFILE
   phase_start<L::kLanes>(E.prof);
 #endif
@@ -180,6 +181,9 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
           SIM_PHASE(E, PH_CKPT);
         }
         substep_forward<NV>(m, E, jr, cr, ln, C, true, fb);
+        if constexpr (L::kMtu == 0)
+          if (A.fc) fc_store<NV>(m, FM, E, C, fb, ln, A.fc + ((size_t)gi * N + env) * A.fc_ws,
+                                 A.fcq + ((size_t)gi * N + env) * m->nv);
       }
       nfb += fb;
       nadh += E.nadh;
@@ -307,6 +311,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
   const int S = m->substeps, nq = m->nq, nv = m->nv, na = m->na, ns = m->ns, N = A.N, k = A.k;
   const int nqv = m->nck;
   const TapeMap<L> TM = tape_map<L>(m, ln);
+  const FcMap<L> FM = fc_map<L>(m, ln);
 #ifdef SIM_PHASE_PROFILE
   phase_start<L::kLanes>(E.prof);
 #endif
@@ -330,14 +335,54 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
       // the forward stored every substep's pre-state and linearisation; the next (earlier)
       // entry is loaded into registers while the current one is reversed
       TapeRegs<L> P;
-      tape_prefetch(TM, P, A.tape + (((size_t)t * S + S - 1) * N + env) * A.tape_ws, ln);
+      tape_prefetch<L>(TM, P, A.tape + (((size_t)t * S + S - 1) * N + env) * A.tape_ws, ln);
       for (int sub = S - 1; sub >= 0; --sub) {
         int fb;
         tape_load_regs<NV>(m, TM, E, C, fb, ln, P);
-        if (sub > 0) tape_prefetch(TM, P, A.tape + (((size_t)t * S + sub - 1) * N + env) * A.tape_ws, ln);
+        if (sub > 0) tape_prefetch<L>(TM, P, A.tape + (((size_t)t * S + sub - 1) * N + env) * A.tape_ws, ln);
         SIM_PHASE(E, PH_TAPE_PREFETCH);
         if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
+      }
+    } else if (L::kMtu == 0 && A.fc) {
+      // factor cache: per segment, the pre-substep states are rebuilt from the checkpoint with
+      // the cached accelerations (kept in the segment scratch), then each substep is reversed
+      // from its state, its cached factor and its recomputed kinematics
+      real* pre = A.tape + (size_t)env * k * nqv;
+      for (int sg = S / k - 1; sg >= 0; --sg) {
+        const int g = (t * S + sg * k) / k;
+        load_qqd(m, E, A.ckpt + ((size_t)g * N + env) * nqv, ln);
+        SIM_PHASE(E, PH_CKPT);
+        // each substep's accelerations are loaded one substep ahead of their use
+        real qnext = (ln < nv && k > 1) ? A.fcq[((size_t)g * k * N + env) * nv + ln] : RL(0.0);
+        for (int i = 0; i < k; ++i) {
+          store_qqd(m, E, pre + (size_t)i * nqv, ln);
+          if (i < k - 1) {
+            const real qcur = qnext;
+            if (i + 2 < k && ln < nv) qnext = A.fcq[(((size_t)g * k + i + 1) * N + env) * nv + ln];
+            fc_step_state(m, E, jr, qcur, ln);
+          }
+        }
+        SIM_PHASE(E, PH_FC_STATES);
+        FcRegs<L> P;
+        {
+          const size_t gi = (size_t)g * k + k - 1;
+          fc_prefetch(m, FM, P, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv,
+                      pre + (size_t)(k - 1) * nqv, ln);
+        }
+        for (int i = k - 1; i >= 0; --i) {
+          int fb;
+          fc_load_regs<NV>(m, FM, E, C, fb, ln, P);
+          if (i > 0) {
+            const size_t gi = (size_t)g * k + i - 1;
+            fc_prefetch(m, FM, P, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv,
+                        pre + (size_t)(i - 1) * nqv, ln);
+          }
+          SIM_PHASE(E, PH_TAPE_PREFETCH);
+          if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+          else substep_kinematics(m, E, jr, cr, ln);
+          substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
+        }
       }
     } else {
       real* tseg = A.tape + (size_t)env * (k - 1) * A.tape_ws;
@@ -359,14 +404,14 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         {
           int fb;
           substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          if (k >= 2) tape_prefetch(TM, P, tseg + (size_t)(k - 2) * A.tape_ws, ln);
+          if (k >= 2) tape_prefetch<L>(TM, P, tseg + (size_t)(k - 2) * A.tape_ws, ln);
           SIM_PHASE(E, PH_TAPE_PREFETCH);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
         for (int i = k - 2; i >= 0; --i) {
           int fb;
           tape_load_regs<NV>(m, TM, E, C, fb, ln, P);
-          if (i > 0) tape_prefetch(TM, P, tseg + (size_t)(i - 1) * A.tape_ws, ln);
+          if (i > 0) tape_prefetch<L>(TM, P, tseg + (size_t)(i - 1) * A.tape_ws, ln);
           SIM_PHASE(E, PH_TAPE_PREFETCH);
           if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);

@@ -17,7 +17,8 @@ typedef GroupArgsT<real> GroupArgs;
 struct Scal {
   int J, nq, nv, na, nc, ns, od, task, floating, has_last_action, substeps, max_depth, ts_steps, term;
   int n_mtu, n_motor, nck;
-  int tape_nw;           // words of a packed tape entry
+  int tape_nw;           // 16-byte chunks of a packed tape entry
+  int fc_nw;             // 16-byte chunks of a factor-cache entry
   real dt_sub, g, kn, kd, kt, mu, klim, chol_thr;
   real tau_act, fl_w, vmax, term_h;
   const DevModel* tab;   // the model's tables (muscle paths) in global memory
@@ -33,6 +34,7 @@ __device__ __forceinline__ Scal load_scal(const DevModel* __restrict__ m) {
   s.tau_act = m->tau_act; s.fl_w = m->fl_w; s.vmax = m->vmax;
   s.term = m->term; s.term_h = m->term_h;
   s.tape_nw = m->tape_nw;
+  s.fc_nw = m->fc_nw;
   s.tab = m;
   return s;
 }
@@ -122,7 +124,8 @@ enum {
   PH_TAPE_PREFETCH = 27,// issuing the next entry's loads
   PH_A_FRAME = 28,      // frame-level reverse (reward, actor input VJP, observation)
   PH_WINDOW_END = 29,   // terminal observation, critic, outputs
-  PH_TERM = 30          // early-termination test and reset
+  PH_TERM = 30,         // early-termination test and reset
+  PH_FC_STATES = 31     // factor cache: a segment's pre-substep states from the cached accelerations
 };
 #ifdef SIM_PHASE_PROFILE
 template <int LN>

@@ -66,6 +66,10 @@ constexpr int sim_tape_chunk_cap(int J, int V, int C, int nmtu, int elem) {
   return (((V + 1) + V + 28 * J + 10 * C + V + V * (V + 1) / 2 + V + 1 + (nmtu > 0 ? 12 * J + nmtu : 0)) * elem + 15) / 16 +
          2 * (V + 16);
 }
+// A factor-cache entry: the lower triangle of the Cholesky factor row by row, the reciprocal
+// pivots and the fallback flag, in 16-byte chunks of the block (fc_off, as tape_off).
+constexpr int sim_fc_chunk_cap(int V, int elem) { return ((V * (V + 1) / 2 + V + 1) * elem + 15) / 16 + 2 * (V + 2); }
+#define SIM_MAXFCW 384
 #define SIM_MAXTAPEW 2432   // capacity of the chunk list (the largest layout in FP64 needs 1305)
 // BF16 tile bytes of one layer's forward or input-adjoint operand set
 static inline size_t sim_bf16_tiles_bytes(int n_rows, int n_k) {
@@ -105,6 +109,9 @@ struct DevModelT {
   // chunk, in 16-byte units
   int tape_nw;
   unsigned short tape_off[SIM_MAXTAPEW];
+  // the factor-cache entry: chunks per entry and their block offsets (16-byte units)
+  int fc_nw;
+  unsigned short fc_off[SIM_MAXFCW];
   // muscle-tendon units, point-major so that lanes (one unit each) read contiguously
   int mtu_npt[SIM_MAXMTU];
   int mtu_body[SIM_MAXMPT * SIM_MAXMTU];     // [point][unit]
@@ -153,6 +160,12 @@ struct WinArgsT {
                     // adjoint's segment tape [N][k-1] entries, tape_ws reals apart
   int tape_full;
   int tape_ws;      // reals between consecutive tape entries (the packed words, rounded up)
+  // factor cache (persistent path, optional): fc [h*S][N] entries fc_ws reals apart, fcq
+  // [h*S][N][nv] accelerations; the adjoint keeps a segment's pre-substep states in tape
+  // ([N][k][nck])
+  T* fc;
+  T* fcq;
+  int fc_ws;
   const T* obs_in;
   const T* actions_fw;
   const T* s_h_in;

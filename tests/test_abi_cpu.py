@@ -44,6 +44,7 @@ def _create(md, **kw):
     o.mlp_precision = kw.get("mlp_precision", 0)
     o.precision = kw.get("precision", 0)
     o.lanes_per_env = kw.get("lanes", 0)
+    o.factor_cache = kw.get("factor_cache", 0)
     h = ctypes.c_void_p()
     rc = P.lib().sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h))
     return rc, P.lib().sim_last_error().decode()
@@ -202,4 +203,17 @@ def test_compact_layout_checks():
     assert rc == -6 and "beyond the compact layout" in msg
     mm = wl.mtu_humanoid()
     rc, msg = _create(mm, lanes=64, critic=[280, 8, 1])
+    assert rc == -6 and "torque-driven" in msg
+
+
+def test_factor_cache_checks():
+    """The factor cache belongs to the persistent path of torque-driven models: any other path,
+    a muscle model or a flag other than 0 / 1 is refused at sim_create."""
+    ant = wl.workload("ant", 4)["model"]
+    for kw, code, text in ((dict(factor_cache=2), -1, "factor_cache"),
+                           (dict(factor_cache=1, path=2, k=1), -1, "persistent"),
+                           (dict(factor_cache=1, path=1, k=1), -1, "persistent")):
+        rc, msg = _create(ant, **kw)
+        assert rc == code and text in msg, (kw, rc, msg)
+    rc, msg = _create(wl.mtu_humanoid(), factor_cache=1, critic=[280, 8, 1])
     assert rc == -6 and "torque-driven" in msg

@@ -126,7 +126,8 @@ def test_group_with_compact_members_matches_members():
 
 def test_autotuner_chooses_among_layouts():
     """For CartPole the tuner times the full layout and the compact one at 64, 32 and 16 lanes
-    per env, each on the tape path and every checkpoint interval, and reports its choice."""
+    per env, each on the tape path and every checkpoint interval with and without the factor
+    cache, and reports its choice."""
     W = wl.workload("cartpole", 256)
     od = W["obs_dim"]
     print("[compact] tuner cartpole 256", flush=True)
@@ -134,5 +135,5 @@ def test_autotuner_chooses_among_layouts():
                [od] + [w.shape[0] for w, _ in W["critic"]], W["s0"], W["actor"], W["critic"],
                budget_bytes=1 << 34, reps=1)
     n_k = sum(1 for k in range(1, 5) if 4 % k == 0)                 # S = 4
-    assert r["n_candidates"] == 4 * (1 + n_k)
+    assert r["n_candidates"] == 4 * (1 + 2 * n_k)
     assert r["lanes_per_env"] in (0, 16, 32, 64)

@@ -120,8 +120,9 @@ def test_autotuner_picks_a_valid_configuration():
     r = P.tune(W["model"], 64, h, *dims, W["s0"], W["actor"], W["critic"], budget_bytes=1 << 40, reps=2)
     divisors = [k for k in range(1, 17) if 16 % k == 0]
     # the full layout and the compact one at 64, 32 and 16 lanes per env, each on the tape path
-    # and every checkpoint interval
-    assert r["n_candidates"] == 4 * (len(divisors) + 1)
+    # and every checkpoint interval with and without the factor cache
+    assert r["n_candidates"] == 4 * (2 * len(divisors) + 1)
+    assert r["factor_cache"] in (0, 1)
     assert r["path"] in (P.PATH_TAPE, P.PATH_PERSISTENT) and r["ms_window"] > 0
     assert r["lanes_per_env"] in (0, 16, 32, 64)
     # a budget below every tape path's workspace leaves only checkpointed configurations
