@@ -187,7 +187,16 @@ typedef struct SimOptions {
                                     recomputes only the kinematics, contacts and body inertias of
                                     each substep (no mass matrix, factorisation or solve).
                                     0 = the adjoint recomputes whole substeps from the
-                                    checkpoints.  Results are bitwise the same either way. */
+                                    checkpoints.  Results are bitwise the same either way.
+                                    Needs ckpt_interval <= 16. */
+  int layer_norm;                /* 1: every hidden layer of the actor and of the critic is followed
+                                    by a layer normalisation of its ELU outputs, y = g (e - mean)
+                                    / sqrt(var + 1e-5) + beta over the layer's outputs (App. A.2);
+                                    the gains and biases are window inputs (actor_ln_* /
+                                    critic_ln_*), and dL_dtheta then holds their gradients after
+                                    each hidden layer's W, b.  FP32 / FP64 MLPs; the window and its
+                                    policy gradient (sim_critic_values / sim_critic_fit refuse such
+                                    a handle).  0: no normalisation (the benchmark configurations). */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;
@@ -199,6 +208,11 @@ typedef struct SimForwardIO {
   const void* actor_b[SIM_MAX_LAYERS];      /* b [out] */
   const void* critic_w[SIM_MAX_LAYERS];
   const void* critic_b[SIM_MAX_LAYERS];
+  const void* actor_ln_g[SIM_MAX_LAYERS];   /* with opt.layer_norm: per hidden layer l of the actor,
+                                               its normalisation's gain [dims[l+1]] */
+  const void* actor_ln_b[SIM_MAX_LAYERS];   /* and bias [dims[l+1]] (device; unused entries NULL) */
+  const void* critic_ln_g[SIM_MAX_LAYERS];  /* the same for the critic */
+  const void* critic_ln_b[SIM_MAX_LAYERS];
   void* workspace;                          /* sim_workspace_bytes() bytes, 256-byte aligned */
   size_t workspace_bytes;
   void* s_h;                                /* [N][ns] out: state after h frames */
@@ -243,6 +257,10 @@ typedef struct SimAdjointIO {
   const void* actor_b[SIM_MAX_LAYERS];
   const void* critic_w[SIM_MAX_LAYERS];
   const void* critic_b[SIM_MAX_LAYERS];
+  const void* actor_ln_g[SIM_MAX_LAYERS];   /* as given to the forward (opt.layer_norm) */
+  const void* actor_ln_b[SIM_MAX_LAYERS];
+  const void* critic_ln_g[SIM_MAX_LAYERS];
+  const void* critic_ln_b[SIM_MAX_LAYERS];
   void* workspace;                          /* written by the matching forward */
   size_t workspace_bytes;
   const void* grad_s_h;                     /* [N][ns] optional extra upstream dL/ds_h */
@@ -254,8 +272,10 @@ typedef struct SimAdjointIO {
   void* dL_dtheta;                          /* optional out (needs opt.policy_grad): dL/dtheta of the
                                                actor (App. A.1), the sum over frames and envs of
                                                (d pi / d theta)^T dL/da_t, flat in layer order
-                                               W_0 [out][in], b_0, W_1, b_1, ...; bitwise
-                                               reproducible for a given handle */
+                                               W_0 [out][in], b_0, W_1, b_1, ... (with
+                                               opt.layer_norm each hidden layer's W, b are
+                                               followed by its normalisation's gain and bias);
+                                               bitwise reproducible for a given handle */
   const void* noise;                        /* as given to the forward (stochastic policy), or NULL */
   const void* log_std;                      /* as given to the forward, or NULL */
   void* dL_dlog_std;                        /* [na] optional out (with dL_dtheta and noise): the
@@ -321,7 +341,7 @@ void sim_group_destroy(SimGroup* g);
 /* ---- Autotuner.  Times forward + adjoint windows of one model on the caller's inputs
  * for every launch configuration whose workspace fits workspace_budget: the tape path and
  * the persistent path at every checkpoint interval k dividing S (for torque-driven models
- * with and without the factor cache), each in the full layout and,
+ * and k <= 16 with and without the factor cache), each in the full layout and,
  * for small models whose n_envs allows it, in the compact layout with 64, 32 and 16 lanes per
  * environment (opt->lanes_per_env is ignored); returns the fastest (median of reps windows
  * after a warm-up).  opt supplies everything else (N, h, MLP

@@ -43,12 +43,13 @@ class SimOptions(ctypes.Structure):
                 ("closed_loop", _i), ("actor_layers", _i), ("actor_dims", _i * (MAXL + 1)),
                 ("critic_layers", _i), ("critic_dims", _i * (MAXL + 1)), ("gamma", _d),
                 ("precision", _i), ("chol_fp64_threshold", _d), ("policy_grad", _i),
-                ("mlp_precision", _i), ("lanes_per_env", _i), ("factor_cache", _i)]
+                ("mlp_precision", _i), ("lanes_per_env", _i), ("factor_cache", _i), ("layer_norm", _i)]
 
 
 class SimForwardIO(ctypes.Structure):
     _fields_ = [("s0", _p), ("actions_in", _p), ("actor_w", _p * MAXL), ("actor_b", _p * MAXL),
-                ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("workspace", _p),
+                ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("actor_ln_g", _p * MAXL),
+                ("actor_ln_b", _p * MAXL), ("critic_ln_g", _p * MAXL), ("critic_ln_b", _p * MAXL), ("workspace", _p),
                 ("workspace_bytes", ctypes.c_size_t), ("s_h", _p), ("obs", _p), ("actions", _p),
                 ("rewards", _p), ("value", _p), ("nonfinite", _p), ("fp64_refactor_count", _p),
                 ("noise", _p), ("log_std", _p), ("reset_states", _p), ("done", _p),
@@ -58,8 +59,9 @@ class SimForwardIO(ctypes.Structure):
 class SimAdjointIO(ctypes.Structure):
     _fields_ = [("s0", _p), ("actions", _p), ("obs", _p), ("s_h", _p),
                 ("actor_w", _p * MAXL), ("actor_b", _p * MAXL), ("critic_w", _p * MAXL),
-                ("critic_b", _p * MAXL), ("workspace", _p), ("workspace_bytes", ctypes.c_size_t),
-                ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p),
+                ("critic_b", _p * MAXL), ("actor_ln_g", _p * MAXL), ("actor_ln_b", _p * MAXL),
+                ("critic_ln_g", _p * MAXL), ("critic_ln_b", _p * MAXL), ("workspace", _p),
+                ("workspace_bytes", ctypes.c_size_t), ("grad_s_h", _p), ("loss_scale", _d), ("dL_da", _p), ("dL_ds0", _p),
                 ("dL_dtheta", _p), ("noise", _p), ("log_std", _p), ("dL_dlog_std", _p),
                 ("obs_mean", _p), ("obs_inv_std", _p)]
 
@@ -227,7 +229,7 @@ class Sim:
 
     def __init__(self, md, n_envs, horizon, actor_dims=None, critic_dims=None, ckpt_interval=None,
                  path=PATH_PERSISTENT, gamma=0.99, precision="fp32", chol_fp64_threshold=1e-6,
-                 policy_grad=False, mlp_precision="fp32", lanes_per_env=0, factor_cache=False):
+                 policy_grad=False, mlp_precision="fp32", lanes_per_env=0, factor_cache=False, layer_norm=False):
         import torch
         self.torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -256,6 +258,8 @@ class Sim:
         o.mlp_precision = {"fp32": 0, "bf16": 1}[mlp_precision]
         o.lanes_per_env = int(lanes_per_env)
         o.factor_cache = 1 if factor_cache else 0
+        o.layer_norm = 1 if layer_norm else 0
+        self.layer_norm = bool(layer_norm)
         self.actor_dims = list(actor_dims) if actor_dims is not None else None
         h = _p()
         _check(L.sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
@@ -360,14 +364,16 @@ class Sim:
         return _p(t.data_ptr()) if t is not None else _p(0)
 
     def forward(self, s0, actor=None, critic=None, actions_in=None, stream=None, noise=None, log_std=None,
-                reset_states=None, obs_norm=None):
+                reset_states=None, obs_norm=None, actor_ln=None, critic_ln=None):
         """Run sim_forward_window.  Returns a dict of device tensors.  noise [h, N, na] and
         log_std [na] select the stochastic policy y = mu(o) + exp(log_std) * noise;
         reset_states [N, ns] are the restart states of a model with early termination (the
         result then holds done [h, N]); obs_norm = (mean, inv_std) [obs_dim] normalises the
-        networks' inputs (the adjoint takes it from the result)."""
+        networks' inputs (the adjoint takes it from the result); actor_ln / critic_ln (handle
+        with layer_norm) are per hidden layer the (gain, bias) of its normalisation."""
         out, io = self.forward_io(s0, actor, critic, actions_in, noise=noise, log_std=log_std,
-                                  reset_states=reset_states, obs_norm=obs_norm)
+                                  reset_states=reset_states, obs_norm=obs_norm, actor_ln=actor_ln,
+                                  critic_ln=critic_ln)
         t = self.torch
         st = stream if stream is not None else t.cuda.current_stream()
         _check(lib().sim_forward_window(self.h, ctypes.byref(io), _p(st.cuda_stream)))
@@ -375,7 +381,7 @@ class Sim:
         return out
 
     def forward_io(self, s0, actor=None, critic=None, actions_in=None, out=None, noise=None, log_std=None,
-                   reset_states=None, obs_norm=None):
+                   reset_states=None, obs_norm=None, actor_ln=None, critic_ln=None):
         """Allocate the forward outputs (or reuse those of `out`, a previous result) and
         fill a SimForwardIO (no launch)."""
         t = self.torch
@@ -427,6 +433,7 @@ class Sim:
         if obs_norm is not None:
             io.obs_mean, io.obs_inv_std, out["obs_norm"] = self._norm_ptrs(obs_norm)
         self._set_weights(io, actor, critic, out)
+        self._set_ln(io, actor_ln, critic_ln, out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
         for k in ("s_h", "obs", "actions", "rewards", "value", "nonfinite", "fp64_refactor_count", "adhesive_count",
@@ -434,6 +441,20 @@ class Sim:
             setattr(io, k, self._ptr(out[k]))
         out["_io"] = io
         return out, io
+
+    def _set_ln(self, io, actor_ln, critic_ln, keep):
+        """The layer normalisations' gains and biases (handle with layer_norm): device copies in
+        the handle's dtype kept in `keep`, pointers into io."""
+        if actor_ln is not None:
+            aln = [(self._dev(g).reshape(-1).contiguous(), self._dev(b).reshape(-1).contiguous()) for g, b in actor_ln]
+            keep["actor_ln"] = aln
+            for i, (g, b) in enumerate(aln):
+                io.actor_ln_g[i], io.actor_ln_b[i] = g.data_ptr(), b.data_ptr()
+        if critic_ln is not None:
+            cln = [(self._dev(g).reshape(-1).contiguous(), self._dev(b).reshape(-1).contiguous()) for g, b in critic_ln]
+            keep["critic_ln"] = cln
+            for i, (g, b) in enumerate(cln):
+                io.critic_ln_g[i], io.critic_ln_b[i] = g.data_ptr(), b.data_ptr()
 
     def _set_weights(self, io, actor, critic, keep):
         if actor is not None:
@@ -485,6 +506,7 @@ class Sim:
         io.s_h = self._ptr(fw["s_h"])
         self._set_weights(io, actor if actor is not None else fw.get("actor"),
                           critic if critic is not None else fw["critic"], out)
+        self._set_ln(io, fw.get("actor_ln"), fw.get("critic_ln"), out)
         io.workspace = self._ptr(self.workspace)
         io.workspace_bytes = self.workspace.numel()
         if grad_s_h is not None:
@@ -505,18 +527,26 @@ class Sim:
                 io.dL_dlog_std = self._ptr(g)
         if want_theta:
             dims = self.actor_dims
-            n = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+            nl = len(dims) - 1
+            lnw = 2 * sum(dims[1:-1]) if self.layer_norm else 0
+            n = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(nl)) + lnw
             flat = (prev["dL_dtheta_flat"] if prev is not None and "dL_dtheta_flat" in prev
                     else t.empty(n, device="cuda", dtype=dt))
             out["dL_dtheta_flat"] = flat
             io.dL_dtheta = self._ptr(flat)
-            views, off = [], 0
-            for i in range(len(dims) - 1):
+            views, lnv, off = [], [], 0
+            for i in range(nl):
                 nw = dims[i] * dims[i + 1]
                 views.append((flat[off:off + nw].view(dims[i + 1], dims[i]),
                               flat[off + nw:off + nw + dims[i + 1]]))
                 off += nw + dims[i + 1]
+                if self.layer_norm and i < nl - 1:
+                    w = dims[i + 1]
+                    lnv.append((flat[off:off + w], flat[off + w:off + 2 * w]))
+                    off += 2 * w
             out["dL_dtheta"] = views
+            if self.layer_norm:
+                out["dL_dln"] = lnv
         out["_io"] = io
         return out, io
 

@@ -84,6 +84,7 @@ struct SimHandle {
   int hid_w = 0;   // the actor's hidden widths, summed (closed loop)
   int tape_ws = 0;   // reals between consecutive tape entries
   int fc_ws = 0;     // reals between consecutive factor-cache entries
+  size_t off_th_y = 0, off_th_lnp = 0;   // policy gradient with layer normalisation
   size_t off_fc = 0, off_fcq = 0;
   // policy-gradient scratch: two layer-adjoint buffers, split partials (the hidden
   // activations are the window's own, at off_hid)
@@ -121,12 +122,13 @@ static const size_t kLayoutSimOptions[] = {
     offsetof(SimOptions, actor_dims), offsetof(SimOptions, critic_layers), offsetof(SimOptions, critic_dims),
     offsetof(SimOptions, gamma), offsetof(SimOptions, precision), offsetof(SimOptions, chol_fp64_threshold),
     offsetof(SimOptions, policy_grad), offsetof(SimOptions, mlp_precision), offsetof(SimOptions, lanes_per_env),
-    offsetof(SimOptions, factor_cache),
+    offsetof(SimOptions, factor_cache), offsetof(SimOptions, layer_norm),
 };
 static const size_t kLayoutSimForwardIO[] = {
     offsetof(SimForwardIO, s0), offsetof(SimForwardIO, actions_in), offsetof(SimForwardIO, actor_w),
     offsetof(SimForwardIO, actor_b), offsetof(SimForwardIO, critic_w), offsetof(SimForwardIO, critic_b),
-    offsetof(SimForwardIO, workspace), offsetof(SimForwardIO, workspace_bytes), offsetof(SimForwardIO, s_h),
+    offsetof(SimForwardIO, actor_ln_g), offsetof(SimForwardIO, actor_ln_b), offsetof(SimForwardIO, critic_ln_g),
+    offsetof(SimForwardIO, critic_ln_b), offsetof(SimForwardIO, workspace), offsetof(SimForwardIO, workspace_bytes), offsetof(SimForwardIO, s_h),
     offsetof(SimForwardIO, obs), offsetof(SimForwardIO, actions), offsetof(SimForwardIO, rewards),
     offsetof(SimForwardIO, value), offsetof(SimForwardIO, nonfinite),
     offsetof(SimForwardIO, fp64_refactor_count), offsetof(SimForwardIO, noise),
@@ -137,7 +139,9 @@ static const size_t kLayoutSimForwardIO[] = {
 static const size_t kLayoutSimAdjointIO[] = {
     offsetof(SimAdjointIO, s0), offsetof(SimAdjointIO, actions), offsetof(SimAdjointIO, obs),
     offsetof(SimAdjointIO, s_h), offsetof(SimAdjointIO, actor_w), offsetof(SimAdjointIO, actor_b),
-    offsetof(SimAdjointIO, critic_w), offsetof(SimAdjointIO, critic_b), offsetof(SimAdjointIO, workspace),
+    offsetof(SimAdjointIO, critic_w), offsetof(SimAdjointIO, critic_b), offsetof(SimAdjointIO, actor_ln_g),
+    offsetof(SimAdjointIO, actor_ln_b), offsetof(SimAdjointIO, critic_ln_g), offsetof(SimAdjointIO, critic_ln_b),
+    offsetof(SimAdjointIO, workspace),
     offsetof(SimAdjointIO, workspace_bytes), offsetof(SimAdjointIO, grad_s_h),
     offsetof(SimAdjointIO, loss_scale), offsetof(SimAdjointIO, dL_da), offsetof(SimAdjointIO, dL_ds0),
     offsetof(SimAdjointIO, dL_dtheta), offsetof(SimAdjointIO, noise), offsetof(SimAdjointIO, log_std),
@@ -443,10 +447,15 @@ static int check_options(const SimOptions* opt, const DevModelT<double>& m) {
     return fail(SIM_E_ARG, "BF16 MLPs run in the FP32 path");
   if (opt->mlp_precision == SIM_MLP_BF16 && opt->policy_grad)
     return fail(SIM_E_UNSUPPORTED, "the policy-parameter gradient runs with FP32 MLPs");
+  if (opt->layer_norm != 0 && opt->layer_norm != 1) return fail(SIM_E_ARG, "layer_norm must be 0 or 1");
+  if (opt->layer_norm && opt->mlp_precision != SIM_MLP_FP32)
+    return fail(SIM_E_UNSUPPORTED, "layer normalisation runs with FP32 / FP64 MLPs");
   if (opt->factor_cache != 0 && opt->factor_cache != 1) return fail(SIM_E_ARG, "factor_cache must be 0 or 1");
   if (opt->factor_cache && opt->path != SIM_PATH_PERSISTENT)
     return fail(SIM_E_ARG, "the factor cache belongs to the persistent (checkpointed) path");
   if (opt->factor_cache && m.n_mtu > 0) return fail(SIM_E_UNSUPPORTED, "the factor cache is for torque-driven models");
+  if (opt->factor_cache && opt->ckpt_interval > SIM_FC_MAXK)
+    return fail(SIM_E_UNSUPPORTED, "the factor cache takes checkpoint intervals up to 16");
   if (opt->lanes_per_env != 0) {
     const int ln = opt->lanes_per_env;
     if (ln != 16 && ln != 32 && ln != 64) return fail(SIM_E_ARG, "lanes_per_env must be 0, 16, 32 or 64");
@@ -647,8 +656,11 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
   h->off_seg = off;
   off = align256(off + (size_t)(opt->horizon + 1) * N * sizeof(int));
   h->hid_w = 0;
-  if (opt->closed_loop)
+  if (opt->closed_loop) {
     for (int l = 1; l < opt->actor_layers; ++l) h->hid_w += opt->actor_dims[l];
+    // with layer normalisation each hidden layer's mean and inverse deviation follow
+    if (opt->layer_norm && opt->actor_layers > 1) h->hid_w += 2 * (opt->actor_layers - 1);
+  }
   h->off_hid = off;
   off = align256(off + e * (size_t)opt->horizon * N * h->hid_w);
   if (opt->policy_grad) {
@@ -666,6 +678,15 @@ extern "C" int sim_create(const SimModelDesc* md, const SimOptions* opt, SimHand
     off = align256(off + e * rows * maxw);
     h->off_th_part = off;
     off = align256(off + e * (size_t)h->th_splits * maxpart);
+    if (opt->layer_norm) {
+      // the normalised hidden layers of every row and the gain / bias partials
+      size_t hw = 0;
+      for (int l = 1; l < opt->actor_layers; ++l) hw += opt->actor_dims[l];
+      h->off_th_y = off;
+      off = align256(off + e * rows * hw);
+      h->off_th_lnp = off;
+      off = align256(off + e * (size_t)SIM_LN_BLOCKS * 2 * maxw);
+    }
   }
   h->ws_bytes = off;
   *out = h;
@@ -706,9 +727,19 @@ static int check_handle(SimHandle* h) {
 template <typename T>
 static int fill_mlp(MlpArgsT<T>& P, int nl, const int* dims, const void* const* W, const void* const* b,
                     char* ws, const size_t* wt_off, const size_t* wp_off, const size_t (*bf_off)[2], int bf16,
-                    const char* what) {
+                    const char* what, int ln = 0, const void* const* lng = nullptr, const void* const* lnb = nullptr) {
   P.nl = nl;
   P.bf16 = bf16;
+  P.ln = ln;
+  P.ln_eps = (T)1e-5;
+  for (int l = 0; l < SIM_MAXL; ++l) { P.lng[l] = nullptr; P.lnb[l] = nullptr; }
+  if (ln)
+    for (int l = 0; l + 1 < nl; ++l) {
+      if (!lng || !lnb || !lng[l] || !lnb[l])
+        return fail(SIM_E_ARG, std::string(what) + ": layer_norm needs every hidden layer's gain and bias");
+      P.lng[l] = static_cast<const T*>(lng[l]);
+      P.lnb[l] = static_cast<const T*>(lnb[l]);
+    }
   for (int l = 0; l < SIM_MAXL; ++l) {
     P.Pf[l] = (bf16 && l < nl) ? reinterpret_cast<const uint16_t*>(ws + bf_off[l][0]) : nullptr;
     P.Pb[l] = (bf16 && l < nl) ? reinterpret_cast<const uint16_t*>(ws + bf_off[l][1]) : nullptr;
@@ -764,11 +795,13 @@ static int build_forward_args(SimHandle* h, const SimForwardIO* io, WinArgsT<T>&
   int rc;
   if (o.closed_loop) {
     rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off,
-                  h->bf_actor_off, o.mlp_precision == SIM_MLP_BF16, "actor");
+                  h->bf_actor_off, o.mlp_precision == SIM_MLP_BF16, "actor", o.layer_norm, io->actor_ln_g,
+                  io->actor_ln_b);
     if (rc) return rc;
   }
   rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off,
-                h->wp_critic_off, h->bf_critic_off, o.mlp_precision == SIM_MLP_BF16, "critic");
+                h->wp_critic_off, h->bf_critic_off, o.mlp_precision == SIM_MLP_BF16, "critic", o.layer_norm,
+                io->critic_ln_g, io->critic_ln_b);
   if (rc) return rc;
   A.s_h = static_cast<T*>(io->s_h); A.obs = static_cast<T*>(io->obs); A.actions = static_cast<T*>(io->actions);
   A.rewards = static_cast<T*>(io->rewards); A.value = static_cast<T*>(io->value);
@@ -814,11 +847,13 @@ static int build_adjoint_args(SimHandle* h, const SimAdjointIO* io, WinArgsT<T>&
   int rc;
   if (o.closed_loop) {
     rc = fill_mlp(A.actor, o.actor_layers, o.actor_dims, io->actor_w, io->actor_b, ws, h->wt_actor_off, h->wp_actor_off,
-                  h->bf_actor_off, o.mlp_precision == SIM_MLP_BF16, "actor");
+                  h->bf_actor_off, o.mlp_precision == SIM_MLP_BF16, "actor", o.layer_norm, io->actor_ln_g,
+                  io->actor_ln_b);
     if (rc) return rc;
   }
   rc = fill_mlp(A.critic, o.critic_layers, o.critic_dims, io->critic_w, io->critic_b, ws, h->wt_critic_off,
-                h->wp_critic_off, h->bf_critic_off, o.mlp_precision == SIM_MLP_BF16, "critic");
+                h->wp_critic_off, h->bf_critic_off, o.mlp_precision == SIM_MLP_BF16, "critic", o.layer_norm,
+                io->critic_ln_g, io->critic_ln_b);
   if (rc) return rc;
   A.ckpt = reinterpret_cast<T*>(ws + h->off_ckpt);
   A.adj = reinterpret_cast<T*>(ws + h->off_adj);
@@ -865,6 +900,15 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
     off += (long)o.actor_dims[l] * o.actor_dims[l + 1];
     P.off_b[l] = off;
     off += o.actor_dims[l + 1];
+    if (o.layer_norm && l + 1 < o.actor_layers) {
+      // the hidden layer's normalisation gain and bias follow its W, b
+      P.lng[l] = static_cast<const T*>(io->actor_ln_g[l]);
+      P.lnb[l] = static_cast<const T*>(io->actor_ln_b[l]);
+      P.off_g[l] = off;
+      off += o.actor_dims[l + 1];
+      P.off_beta[l] = off;
+      off += o.actor_dims[l + 1];
+    }
   }
   P.x0 = static_cast<const T*>(io->obs);
   P.x_shift = static_cast<const T*>(io->obs_mean);
@@ -887,6 +931,19 @@ static void build_theta_args(SimHandle* h, const SimAdjointIO* io, ThetaArgsT<T>
       off_l += o.actor_dims[l];
     }
     P.hidden_given = 1;
+    if (o.layer_norm && o.actor_layers > 1) {
+      P.ln = 1;
+      P.st = hid + off_l;
+      P.ldst = h->hid_w;
+      T* y = reinterpret_cast<T*>(ws + h->off_th_y);
+      long yo = 0;
+      for (int l = 1; l < o.actor_layers; ++l) {
+        P.Y[l] = y + yo;
+        yo += (long)P.M * o.actor_dims[l];
+      }
+      P.lnpart = reinterpret_cast<T*>(ws + h->off_th_lnp);
+      P.ln_blocks = SIM_LN_BLOCKS;
+    }
   }
   P.mtu = (h->m64.task == TASK_MTU) ? 1 : 0;
   P.noise = static_cast<const T*>(io->noise);
@@ -1251,21 +1308,17 @@ extern "C" int sim_tune(const SimModelDesc* model, const SimOptions* opt, const 
       DevModelT<double> m;
       if (build_model(model, m) || check_options(&o, m)) continue;
     }
-    bool fc_ok = false;
-    {
-      SimOptions o = *opt;
-      o.lanes_per_env = lanes;
-      o.path = SIM_PATH_PERSISTENT;
-      o.ckpt_interval = model->substeps;
-      o.factor_cache = 1;
-      DevModelT<double> m;
-      fc_ok = !build_model(model, m) && !check_options(&o, m);
-    }
     cands.push_back({SIM_PATH_TAPE, 1, lanes, 0});
     for (int k = 1; k <= model->substeps; ++k)
       if (model->substeps % k == 0) {
         cands.push_back({SIM_PATH_PERSISTENT, k, lanes, 0});
-        if (fc_ok) cands.push_back({SIM_PATH_PERSISTENT, k, lanes, 1});
+        SimOptions o = *opt;
+        o.lanes_per_env = lanes;
+        o.path = SIM_PATH_PERSISTENT;
+        o.ckpt_interval = k;
+        o.factor_cache = 1;
+        DevModelT<double> m;
+        if (!build_model(model, m) && !check_options(&o, m)) cands.push_back({SIM_PATH_PERSISTENT, k, lanes, 1});
       }
   }
   double best = -1.0;
@@ -1618,6 +1671,8 @@ extern "C" int sim_critic_values(SimHandle* h, const void* obs, int rows, const 
                                  void* values, void* workspace, size_t workspace_bytes, void* hip_stream) {
   int rc = check_handle(h);
   if (rc) return rc;
+  if (h->opt.layer_norm)
+    return fail(SIM_E_UNSUPPORTED, "sim_critic_values: layer normalisation is implemented in the window and its policy gradient");
   if (!obs || !values || !critic_w || !critic_b || rows < 1) return fail(SIM_E_ARG, "sim_critic_values: null pointer or no rows");
   for (int l = 0; l < h->opt.critic_layers; ++l)
     if (!critic_w[l] || !critic_b[l]) return fail(SIM_E_ARG, "sim_critic_values: null critic weights");
@@ -1672,6 +1727,8 @@ extern "C" int sim_critic_values_noalloc(SimHandle* h, const void* obs, int rows
                                          void* values, void* hip_stream) {
   int rc = check_handle(h);
   if (rc) return rc;
+  if (h->opt.layer_norm)
+    return fail(SIM_E_UNSUPPORTED, "sim_critic_values_noalloc: layer normalisation is implemented in the window and its policy gradient");
   if (!obs || !values || !critic_w || !critic_b || rows < 1)
     return fail(SIM_E_ARG, "sim_critic_values_noalloc: null pointer or no rows");
   for (int l = 0; l < h->opt.critic_layers; ++l)
@@ -1729,6 +1786,8 @@ static int critic_fit_impl(SimHandle* h, const SimCriticFitIO* io, void* stream)
 extern "C" int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_stream) {
   int rc = check_handle(h);
   if (rc) return rc;
+  if (h->opt.layer_norm)
+    return fail(SIM_E_UNSUPPORTED, "sim_critic_fit: layer normalisation is implemented in the window and its policy gradient");
   if (!io || !io->obs || !io->targets || !io->perm || !io->adam_m || !io->adam_v)
     return fail(SIM_E_ARG, "sim_critic_fit: null pointer");
   if (io->rows < 1 || io->n_iter < 1 || io->n_minibatch < 1 || io->n_minibatch > io->rows)

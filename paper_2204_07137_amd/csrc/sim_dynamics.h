@@ -108,6 +108,7 @@ struct EnvLDST {
     real mus[NMTU > 0 ? SIM_MUS_CF * SIM_MUS_STRIDE : 1];
   };
   real red[4];
+  real lnst[2 * SIM_MAXL];   // per hidden layer: mean and inverse deviation of its normalisation
 #ifdef SIM_PHASE_PROFILE
   unsigned long long prof[SIM_NPHASE + 1];   // phase cycle totals and the last mark's time
 #endif
@@ -1464,6 +1465,14 @@ __device__ __forceinline__ void fc_prefetch(const Scal* __restrict__ m, const Fc
   P.qdd = (ln < m->nv) ? qrow[ln] : RL(0.0);
   P.q = (ln < m->nq) ? pre[ln] : RL(0.0);
   P.qd = (ln < m->nv) ? pre[m->nq + ln] : RL(0.0);
+}
+
+// the entry and the accelerations only (the pre-substep state is filled in later)
+template <class L>
+__device__ __forceinline__ void fc_prefetch_entry(const Scal* __restrict__ m, const FcMap<L>& T, FcRegs<L>& P,
+                                                  const real* __restrict__ entry, const real* __restrict__ qrow, int ln) {
+  chunks_prefetch<L::kFcChunksPerLane, L::kLanes>(T, P.c, entry, ln);
+  P.qdd = (ln < m->nv) ? qrow[ln] : RL(0.0);
 }
 
 // a prefetched entry back: the pre-substep state, factor and pivots into the block and

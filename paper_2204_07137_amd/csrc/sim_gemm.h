@@ -207,6 +207,90 @@ __global__ void k_split_reduce(const real* __restrict__ part, int splits, long s
   else gb[o] = s;
 }
 
+// ---- layer normalisation of the hidden layers (App. A.2) in the policy-gradient pass
+// the normalised layer inputs from the window's ELU outputs and per-row statistics (the window's
+// own expression, so the values are those its actor consumed)
+__global__ void k_ln_apply(const real* __restrict__ E, long lde, const real* __restrict__ st, long ldst, int j,
+                           const real* __restrict__ g, const real* __restrict__ b, real* __restrict__ Y, long M,
+                           int n) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * n) return;
+  const long r = idx / n;
+  const int c = (int)(idx % n);
+  const real mu = st[r * ldst + 2 * j], is = st[r * ldst + 2 * j + 1];
+  Y[idx] = m_fma(g[c], (E[r * lde + c] - mu) * is, b[c]);
+}
+
+// Adjoint through the normalisation and the ELU of hidden layer j, row by row: dY [M][n] (the
+// adjoint of the normalised outputs) -> D [M][n] (the adjoint of the pre-activations), with
+// a = (e - mean) r and u = g dY, ebar = r (u - mean(u) - a mean(u a)), D = ebar ELU'(z).  One
+// wavefront per row at a time (lane c holds columns c, c + 64, ...); each block also sums, over
+// its rows in a fixed order, dY a (the gain gradient) and dY (the bias gradient) per column
+// into part[block][0 / 1][n], reduced across blocks in block order by k_ln_reduce.
+#define SIM_LN_Q (SIM_MAXHID / SIM_WAVE)
+__global__ __launch_bounds__(256) void k_ln_backward(const real* __restrict__ dY, const real* __restrict__ E, long lde,
+                                                     const real* __restrict__ st, long ldst, int j,
+                                                     const real* __restrict__ g, real* __restrict__ D, long M, int n,
+                                                     real* __restrict__ part) {
+  __shared__ real red[4][2][SIM_MAXHID];
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  real pg[SIM_LN_Q], pb[SIM_LN_Q];
+#pragma unroll
+  for (int q = 0; q < SIM_LN_Q; ++q) { pg[q] = RL(0.0); pb[q] = RL(0.0); }
+  for (long r = (long)blockIdx.x * 4 + wave; r < M; r += (long)gridDim.x * 4) {
+    const real mu = st[r * ldst + 2 * j], is = st[r * ldst + 2 * j + 1];
+    real u[SIM_LN_Q], a[SIM_LN_Q], ev[SIM_LN_Q];
+    real su = RL(0.0), sua = RL(0.0);
+#pragma unroll
+    for (int q = 0; q < SIM_LN_Q; ++q) {
+      const int c = lane + SIM_WAVE * q;
+      u[q] = a[q] = ev[q] = RL(0.0);
+      if (c < n) {
+        const real dy = dY[r * n + c];
+        ev[q] = E[r * lde + c];
+        a[q] = (ev[q] - mu) * is;
+        u[q] = g[c] * dy;
+        su += u[q];
+        sua = m_fma(u[q], a[q], sua);
+        pg[q] = m_fma(dy, a[q], pg[q]);
+        pb[q] += dy;
+      }
+    }
+    const real mu_u = wave_sum(su) / (real)n, mu_ua = wave_sum(sua) / (real)n;
+#pragma unroll
+    for (int q = 0; q < SIM_LN_Q; ++q) {
+      const int c = lane + SIM_WAVE * q;
+      if (c < n) {
+        const real eb = is * (u[q] - mu_u - a[q] * mu_ua);
+        D[r * n + c] = eb * ((ev[q] > RL(0.0)) ? RL(1.0) : ev[q] + RL(1.0));
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SIM_LN_Q; ++q) {
+    const int c = lane + SIM_WAVE * q;
+    if (c < n) { red[wave][0][c] = pg[q]; red[wave][1][c] = pb[q]; }
+  }
+  __syncthreads();
+  for (int c = (int)threadIdx.x; c < n; c += 256) {
+    part[((long)blockIdx.x * 2 + 0) * n + c] = ((red[0][0][c] + red[1][0][c]) + red[2][0][c]) + red[3][0][c];
+    part[((long)blockIdx.x * 2 + 1) * n + c] = ((red[0][1][c] + red[1][1][c]) + red[2][1][c]) + red[3][1][c];
+  }
+}
+
+__global__ void k_ln_reduce(const real* __restrict__ part, int nb, int n, real* __restrict__ gg,
+                            real* __restrict__ gb) {
+  const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= n) return;
+  real s0 = RL(0.0), s1 = RL(0.0);
+  for (int z = 0; z < nb; ++z) {
+    s0 += part[((long)z * 2 + 0) * n + c];
+    s1 += part[((long)z * 2 + 1) * n + c];
+  }
+  gg[c] = s0;
+  gb[c] = s1;
+}
+
 static void launch_gemm(const GemmArgs& g, int splits, hipStream_t s) {
   dim3 grid((g.M + GT_M - 1) / GT_M, (g.N + GT_N - 1) / GT_N, splits);
   hipLaunchKernelGGL(k_gemm, grid, dim3(GT_THREADS), 0, s, g);
@@ -254,8 +338,10 @@ static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
   const int splits = (M + chunk - 1) / chunk;
   for (int l = L - 1; l >= 0; --l) {
     const int ni = T.dims[l], no = T.dims[l + 1];
-    const real* xin = (l == 0) ? T.x0 : T.H[l];
-    const long ldx = (l > 0 && T.ldH[l]) ? T.ldH[l] : ni;
+    // layer l's input: the observations, the hidden activations, or their normalisations
+    const real* xin = (l == 0) ? T.x0 : (T.ln ? T.Y[l] : T.H[l]);
+    const long ldx = (l > 0 && !T.ln && T.ldH[l]) ? T.ldH[l] : ni;
+    const long ldh = (l > 0 && T.ldH[l]) ? T.ldH[l] : ni;
     GemmArgs g = {};
     g.A = dcur; g.sam = 1; g.sak = no;
     g.B = xin; g.sbk = ldx; g.sbn = 1; g.ones_col = 1;
@@ -274,9 +360,20 @@ static void theta_backward(const ThetaArgsT<real>& T, hipStream_t s) {
       g2.M = M; g2.N = ni; g2.K = no;
       g2.k_chunk = (no + GT_K - 1) / GT_K * GT_K;
       g2.C = dnext; g2.ldc = ni;
-      g2.epi = EPI_DELU; g2.Hm = T.H[l]; g2.ldh = ldx;
-      launch_gemm(g2, 1, s);
-      real* t = dcur; dcur = dnext; dnext = t;
+      if (!T.ln) {
+        g2.epi = EPI_DELU; g2.Hm = T.H[l]; g2.ldh = ldh;
+        launch_gemm(g2, 1, s);
+        real* t = dcur; dcur = dnext; dnext = t;
+      } else {
+        // the adjoint of the normalised outputs, then through the normalisation and the ELU
+        // into dcur (whose layer-l adjoint has been consumed)
+        g2.epi = EPI_STORE;
+        launch_gemm(g2, 1, s);
+        hipLaunchKernelGGL(k_ln_backward, dim3(T.ln_blocks), dim3(256), 0, s, dnext, T.H[l], ldh, T.st, T.ldst, l - 1,
+                           T.lng[l - 1], dcur, (long)M, ni, T.lnpart);
+        hipLaunchKernelGGL(k_ln_reduce, dim3((ni + 255) / 256), dim3(256), 0, s, T.lnpart, T.ln_blocks, ni,
+                           T.out + T.off_g[l - 1], T.out + T.off_beta[l - 1]);
+      }
     }
   }
 }
@@ -285,7 +382,16 @@ int launch_theta(const ThetaArgsT<real>& T, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const int M = T.M, L = T.nl;
   // the hidden layers on the stored observations, unless the window stored them
-  if (!T.hidden_given) theta_hidden(T, s);
+  if (!T.hidden_given) {
+    if (T.ln) return -1;   // normalised layers: only the window's own activations
+    theta_hidden(T, s);
+  }
+  if (T.ln)
+    for (int l = 1; l < L; ++l) {
+      const long n = (long)M * T.dims[l];
+      hipLaunchKernelGGL(k_ln_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T.H[l], T.ldH[l], T.st,
+                         T.ldst, l - 1, T.lng[l - 1], T.lnb[l - 1], T.Y[l], (long)M, T.dims[l]);
+    }
   const int na = T.dims[L];
   const long nseed = (long)M * na;
   hipLaunchKernelGGL(k_theta_seed, dim3((unsigned)((nseed + 255) / 256)), dim3(256), 0, s, T.da, T.act, T.d0, nseed,

@@ -93,13 +93,16 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   for (int i = ln; i < od; i += L::kLanes) ob[i] = E.obs[i];
   if (A.closed_loop) {
     obs_normalize<L::kLanes>(A, m, E.obs, ln);
-    mlp_forward<L::kLanes>(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
-    // keep the hidden activations for the adjoint's input VJP (at most two hidden layers)
+    mlp_forward<L::kLanes>(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln, E.gb, E.lnst);
+    // keep the hidden activations for the adjoint's input VJP (at most two hidden layers; with
+    // layer normalisation the ELU outputs and then each hidden layer's mean and inverse
+    // deviation)
     {
       real* hs = A.hid + ((size_t)t * N + env) * A.hid_w;
       const int d1 = A.actor.nl > 1 ? A.actor.dims[1] : 0, d2 = A.actor.nl > 2 ? A.actor.dims[2] : 0;
       for (int i = ln; i < d1; i += L::kLanes) hs[i] = E.h0[i];
       for (int i = ln; i < d2; i += L::kLanes) hs[d1 + i] = E.h1[i];
+      if (A.actor.ln && ln < 2 * (A.actor.nl - 1)) hs[d1 + d2 + ln] = E.lnst[ln];
     }
     if (A.noise) {
       // stochastic policy, reparameterised (Sec. 3.3): y = mu(o) + exp(log_std) * eps
@@ -128,7 +131,7 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restr
   real* ob = A.obs + ((size_t)A.h * N + env) * od;
   for (int i = ln; i < od; i += L::kLanes) ob[i] = E.obs[i];
   obs_normalize<L::kLanes>(A, m, E.obs, ln);
-  mlp_forward<L::kLanes>(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
+  mlp_forward<L::kLanes>(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln, E.gb, E.lnst);
   if (ln == 0) A.value[env] = E.y[0];
   real* so = A.s_h + (size_t)env * ns;
   bool ok = true;
@@ -230,13 +233,13 @@ __device__ __forceinline__ void adjoint_seed(const WinArgs& A, const Scal* __res
   for (int i = ln; i < od; i += L::kLanes) E.obs[i] = A.obs_in[((size_t)A.h * A.N + env) * od + i];
   __syncthreads();
   obs_normalize<L::kLanes>(A, m, E.obs, ln);
-  mlp_forward<L::kLanes>(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln);
+  mlp_forward<L::kLanes>(A.critic, E.obs, E.h0, E.h1, E.y, E.xb16, ln, E.gb, E.lnst);
   // terminal value discounted from the start of the last segment (early termination)
   const int eh = m->term ? A.h - A.seg_ws[(size_t)A.h * A.N + env] : A.h;
   real c = -m_pow(A.gamma, (real)eh) * A.scale;
   if (ln == 0) E.y[0] = c;
   __syncthreads();
-  mlp_vjp_input<L::kLanes>(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
+  mlp_vjp_input<L::kLanes>(A.critic, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln, E.lnst);
   obs_adjoint_scale<L::kLanes>(A, m, E.obs, ln);
   // E.obs now holds obs_bar; E.a holds a_prev of s_h
   task_obs_vjp<L::kLanes>(m, E.q, E.obs, E.qb, E.qdb, E.abar, E.act_bar, ln);
@@ -282,11 +285,12 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
       const int d1 = A.actor.nl > 1 ? A.actor.dims[1] : 0, d2 = A.actor.nl > 2 ? A.actor.dims[2] : 0;
       for (int i = ln; i < d1; i += L::kLanes) E.h0[i] = hs[i];
       for (int i = ln; i < d2; i += L::kLanes) E.h1[i] = hs[d1 + i];
+      if (A.actor.ln && ln < 2 * (A.actor.nl - 1)) E.lnst[ln] = hs[d1 + d2 + ln];
     }
     __syncthreads();
     for (int i = ln; i < na; i += L::kLanes) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
-    mlp_vjp_input<L::kLanes>(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln);
+    mlp_vjp_input<L::kLanes>(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln, E.lnst);
     for (int i = ln; i < L::kMaxA; i += L::kLanes) E.abar[i] = RL(0.0);
     __syncthreads();
     obs_adjoint_scale<L::kLanes>(A, m, E.obs, ln);
@@ -297,6 +301,41 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
   }
   (void)ns;
   (void)od;
+}
+
+// The inputs of one checkpoint segment's state rebuild (factor cache), loaded into registers a
+// segment ahead of their use: the checkpoint (lane ln: q[ln], qd[ln]) and the accelerations of
+// the segment's first k - 1 substeps (lane ln: qdd[ln] of each).
+struct FcSeg {
+  real q, qd;
+  real qdd[SIM_FC_MAXK - 1];
+};
+template <class L>
+__device__ __forceinline__ void fc_seg_prefetch(const WinArgs& A, const Scal* __restrict__ m, FcSeg& G, int g, int env,
+                                                int ln) {
+  const int nq = m->nq, nv = m->nv, k = A.k, N = A.N;
+  const real* ck = A.ckpt + ((size_t)g * N + env) * m->nck;
+  G.q = (ln < nq) ? ck[ln] : RL(0.0);
+  G.qd = (ln < nv) ? ck[nq + ln] : RL(0.0);
+#pragma unroll
+  for (int i = 0; i < SIM_FC_MAXK - 1; ++i)
+    if (i < k - 1) G.qdd[i] = (ln < nv) ? A.fcq[(((size_t)g * k + i) * N + env) * nv + ln] : RL(0.0);
+}
+// the segment's pre-substep states from its checkpoint and cached accelerations: states 0 ..
+// k - 2 into the per-env scratch pre, state k - 1 left in the block
+template <class L>
+__device__ __forceinline__ void fc_rebuild_states(const Scal* __restrict__ m, L& E, const JointRegs& jr, const FcSeg& G,
+                                                  int k, real* __restrict__ pre, int ln) {
+  if (ln < m->nq) E.q[ln] = G.q;
+  if (ln < m->nv) E.qd[ln] = G.qd;
+  wsync();
+#pragma unroll
+  for (int i = 0; i < SIM_FC_MAXK - 1; ++i) {
+    if (i < k - 1) {
+      store_qqd(m, E, pre + (size_t)i * m->nck, ln);
+      fc_step_state(m, E, jr, G.qdd[i], ln);
+    }
+  }
 }
 
 // One environment's reverse window.
@@ -319,6 +358,15 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
   SIM_PHASE(E, PH_A_SEED);
   // E.abar holds the adjoint of a_prev(s_h) = a_{h-1}: it seeds dL/da_{h-1}
   Chol C;
+  // factor cache: the next segment's rebuild inputs and the next entry, loaded ahead
+  FcSeg NS;
+  FcRegs<L> FP;
+  if (L::kMtu == 0 && A.fc) {
+    const int G = A.h * S / k;
+    fc_seg_prefetch<L>(A, m, NS, G - 1, env, ln);
+    const size_t gi = (size_t)G * k - 1;
+    fc_prefetch_entry(m, FM, FP, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv, ln);
+  }
   for (int t = A.h - 1; t >= 0; --t) {
     if (m->term && A.done_ws[(size_t)t * N + env]) {
       // frame t ended with a reset: s_{t+1} is a constant, nothing flows back through it
@@ -346,37 +394,28 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
       }
     } else if (L::kMtu == 0 && A.fc) {
       // factor cache: per segment, the pre-substep states are rebuilt from the checkpoint with
-      // the cached accelerations (kept in the segment scratch), then each substep is reversed
-      // from its state, its cached factor and its recomputed kinematics
+      // the cached accelerations, then each substep is reversed from its state, its cached
+      // factor and its recomputed kinematics; every load is issued a substep (entries) or a
+      // segment (rebuild inputs) ahead of its use
       real* pre = A.tape + (size_t)env * k * nqv;
       for (int sg = S / k - 1; sg >= 0; --sg) {
         const int g = (t * S + sg * k) / k;
-        load_qqd(m, E, A.ckpt + ((size_t)g * N + env) * nqv, ln);
-        SIM_PHASE(E, PH_CKPT);
-        // each substep's accelerations are loaded one substep ahead of their use
-        real qnext = (ln < nv && k > 1) ? A.fcq[((size_t)g * k * N + env) * nv + ln] : RL(0.0);
-        for (int i = 0; i < k; ++i) {
-          store_qqd(m, E, pre + (size_t)i * nqv, ln);
-          if (i < k - 1) {
-            const real qcur = qnext;
-            if (i + 2 < k && ln < nv) qnext = A.fcq[(((size_t)g * k + i + 1) * N + env) * nv + ln];
-            fc_step_state(m, E, jr, qcur, ln);
-          }
-        }
+        const FcSeg CS = NS;
+        if (g > 0) fc_seg_prefetch<L>(A, m, NS, g - 1, env, ln);
+        fc_rebuild_states(m, E, jr, CS, k, pre, ln);
+        FP.q = (ln < m->nq) ? E.q[ln] : RL(0.0);
+        FP.qd = (ln < nv) ? E.qd[ln] : RL(0.0);
         SIM_PHASE(E, PH_FC_STATES);
-        FcRegs<L> P;
-        {
-          const size_t gi = (size_t)g * k + k - 1;
-          fc_prefetch(m, FM, P, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv,
-                      pre + (size_t)(k - 1) * nqv, ln);
-        }
         for (int i = k - 1; i >= 0; --i) {
           int fb;
-          fc_load_regs<NV>(m, FM, E, C, fb, ln, P);
+          fc_load_regs<NV>(m, FM, E, C, fb, ln, FP);
           if (i > 0) {
             const size_t gi = (size_t)g * k + i - 1;
-            fc_prefetch(m, FM, P, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv,
+            fc_prefetch(m, FM, FP, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv,
                         pre + (size_t)(i - 1) * nqv, ln);
+          } else if (g > 0) {
+            const size_t gi = (size_t)g * k - 1;
+            fc_prefetch_entry(m, FM, FP, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv, ln);
           }
           SIM_PHASE(E, PH_TAPE_PREFETCH);
           if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);

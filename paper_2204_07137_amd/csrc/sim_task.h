@@ -175,11 +175,49 @@ __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const 
   for (int c = 0; c < NCH; ++c) acc_out[c] = acc[c];
 }
 
+// sum over the environment's LN lanes (butterfly; every lane receives the sum)
+template <int LN>
+__device__ __forceinline__ real grp_sum(real x) {
+#pragma unroll
+  for (int off = LN / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, SIM_WAVE);
+  return x;
+}
+
+// Layer normalisation of a hidden layer (App. A.2), e (LDS, n values: the ELU outputs) ->
+// y (LDS): mean and population variance over the n values (each lane sums a strided share,
+// then a butterfly over the environment's lanes), y = g (e - mean) / sqrt(var + eps) + beta.
+// The mean and 1 / sqrt(var + eps) are left in st[0], st[1] for the input adjoint.
+template <int LN>
+__device__ __forceinline__ void ln_forward(const MlpArgs& P, int l, const real* e, real* y, real* st, int n, int ln) {
+  real s = RL(0.0);
+  for (int i = ln; i < n; i += LN) s += e[i];
+  const real mu = grp_sum<LN>(s) / (real)n;
+  real v = RL(0.0);
+  for (int i = ln; i < n; i += LN) {
+    const real d = e[i] - mu;
+    v = m_fma(d, d, v);
+  }
+  const real var = grp_sum<LN>(v) / (real)n;
+  const real is = RL(1.0) / m_sqrt(var + P.ln_eps);
+  const real* g = P.lng[l];
+  const real* b = P.lnb[l];
+  for (int i = ln; i < n; i += LN) y[i] = m_fma(g[i], (e[i] - mu) * is, b[i]);
+  if (ln == 0) {
+    st[0] = mu;
+    st[1] = is;
+  }
+  wsync();
+}
+
 // x (LDS, dims[0]) -> out (LDS, dims[nl]); hidden activations kept in h0 / h1 (<= 2 hidden).
+// With layer normalisation, h0 / h1 keep the ELU outputs, the normalised layer outputs (the
+// next layer's input) go through ybuf, and the mean and inverse deviation of hidden layer l
+// are left in st[2 l], st[2 l + 1].
 // The BF16 matrix-core layers need a whole wavefront per environment (LN = 64).
 template <int LN>
 __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, real* h0, real* h1,
-                                            real* out, uint16_t* xb, int ln) {
+                                            real* out, uint16_t* xb, int ln, real* ybuf = nullptr,
+                                            real* st = nullptr) {
   if constexpr (LN == SIM_WAVE) {
     if (P.bf16) {
       mlp_forward_bf16(P, x, h0, h1, out, xb, ln);
@@ -203,6 +241,10 @@ __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, rea
     }
     wsync();
     in = dst;
+    if (hidden && P.ln) {
+      ln_forward<LN>(P, l, dst, ybuf, st + 2 * l, no, ln);
+      in = ybuf;
+    }
   }
 }
 
@@ -212,7 +254,8 @@ __device__ __forceinline__ void mlp_forward(const MlpArgs& P, const real* x, rea
 #define SIM_MAX_NCH (SIM_MAXHID / SIM_WAVE)
 template <int LN>
 __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, const real* h1,
-                                              real* gout, real* gbuf, real* xbar, uint16_t* xb, int ln) {
+                                              real* gout, real* gbuf, real* xbar, uint16_t* xb, int ln,
+                                              const real* st = nullptr) {
   if constexpr (LN == SIM_WAVE) {
     if (P.bf16) {
       mlp_vjp_input_bf16(P, h0, h1, gout, gbuf, xbar, xb, ln);
@@ -237,6 +280,31 @@ __device__ __forceinline__ void mlp_vjp_input(const MlpArgs& P, const real* h0, 
     wsync();   // every lane has read g before dst (which may alias g) is written
     const real* hin = (l >= 1) ? (((l - 1) & 1) ? h1 : h0) : nullptr;
     const int nch = pad64(ni) / LN;
+    if (hin && P.ln) {
+      // through the normalisation of hidden layer l - 1: with a = (e - mean) r (r the inverse
+      // deviation) and u = g * ybar, ebar = r (u - mean(u) - a mean(u a))
+      const real mu = st[2 * (l - 1)], r = st[2 * (l - 1) + 1];
+      const real* gg = P.lng[l - 1];
+      real su = RL(0.0), sua = RL(0.0);
+#pragma unroll
+      for (int c = 0; c < SIM_MAX_NCH; ++c) {
+        const int i = ln * nch + c;
+        if (c < nch && i < ni) {
+          const real u = gg[i] * acc[c];
+          su += u;
+          sua = m_fma(u, (hin[i] - mu) * r, sua);
+        }
+      }
+      const real mu_u = grp_sum<LN>(su) / (real)ni, mu_ua = grp_sum<LN>(sua) / (real)ni;
+#pragma unroll
+      for (int c = 0; c < SIM_MAX_NCH; ++c) {
+        const int i = ln * nch + c;
+        if (c < nch && i < ni) {
+          const real a = (hin[i] - mu) * r;
+          acc[c] = r * (gg[i] * acc[c] - mu_u - a * mu_ua);
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < SIM_MAX_NCH; ++c) {
       const int i = ln * nch + c;

@@ -70,6 +70,8 @@ constexpr int sim_tape_chunk_cap(int J, int V, int C, int nmtu, int elem) {
 // pivots and the fallback flag, in 16-byte chunks of the block (fc_off, as tape_off).
 constexpr int sim_fc_chunk_cap(int V, int elem) { return ((V * (V + 1) / 2 + V + 1) * elem + 15) / 16 + 2 * (V + 2); }
 #define SIM_MAXFCW 384
+// the factor cache's adjoint holds a checkpoint segment's accelerations in registers: k <= 16
+#define SIM_FC_MAXK 16
 #define SIM_MAXTAPEW 2432   // capacity of the chunk list (the largest layout in FP64 needs 1305)
 // BF16 tile bytes of one layer's forward or input-adjoint operand set
 static inline size_t sim_bf16_tiles_bytes(int n_rows, int n_k) {
@@ -131,7 +133,17 @@ struct MlpArgsT {
   const T* WT[SIM_MAXL];       // [in][pad64(out)] zero-padded copy (workspace)
   const T* b[SIM_MAXL];        // [out] (caller)
   const T* src[SIM_MAXL];      // [out][in] caller weights, copied by the prep kernel
+  // layer normalisation of every hidden layer's ELU output (App. A.2), or none (ln = 0):
+  // y = g (e - mean(e)) / sqrt(var(e) + ln_eps) + beta over the layer's outputs
+  int ln;
+  T ln_eps;
+  const T* lng[SIM_MAXL];      // [out] gain of hidden layer l (caller)
+  const T* lnb[SIM_MAXL];      // [out] bias of hidden layer l (caller)
 };
+
+// blocks of the policy-gradient pass's layer-normalisation adjoint (fixed: their partial sums
+// are reduced in block order, so the result does not depend on the row count)
+#define SIM_LN_BLOCKS 256
 
 // phases of the window kernels' profile (a build with -DSIM_PHASE_PROFILE; ids in sim_math.h)
 #define SIM_NPHASE 40
@@ -232,6 +244,19 @@ struct ThetaArgsT {
   T* part;                    // [splits][max out*(in+1)] partial weight gradients
   T* out;                     // flat dL/dtheta: W_0, b_0, W_1, b_1, ...
   long off_w[SIM_MAXL], off_b[SIM_MAXL];
+  // layer normalisation of the hidden layers (window's activations only): H[l] then holds the
+  // ELU outputs, st + r * ldst the per-row mean and inverse deviation of each hidden layer, Y[l]
+  // ([M][dims[l]], scratch) the normalised layer inputs, lnpart ([ln_blocks][2][max width])
+  // the per-block partial sums of the gain and bias gradients (flat at off_g / off_beta)
+  int ln;
+  const T* lng[SIM_MAXL];
+  const T* lnb[SIM_MAXL];
+  const T* st;
+  long ldst;
+  T* Y[SIM_MAXL];
+  T* lnpart;
+  int ln_blocks;
+  long off_g[SIM_MAXL], off_beta[SIM_MAXL];
 };
 
 // Adam over a list of parameter tensors whose gradient and moments are flat, in list order.

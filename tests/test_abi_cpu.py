@@ -45,6 +45,7 @@ def _create(md, **kw):
     o.precision = kw.get("precision", 0)
     o.lanes_per_env = kw.get("lanes", 0)
     o.factor_cache = kw.get("factor_cache", 0)
+    o.layer_norm = kw.get("layer_norm", 0)
     h = ctypes.c_void_p()
     rc = P.lib().sim_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h))
     return rc, P.lib().sim_last_error().decode()
@@ -217,3 +218,15 @@ def test_factor_cache_checks():
         assert rc == code and text in msg, (kw, rc, msg)
     rc, msg = _create(wl.mtu_humanoid(), factor_cache=1, critic=[280, 8, 1])
     assert rc == -6 and "torque-driven" in msg
+
+
+def test_layer_norm_checks():
+    """layer_norm takes 0 or 1 and runs with FP32 / FP64 networks, not the BF16 matrix-core
+    MLPs."""
+    ant = wl.workload("ant", 4)["model"]
+    rc, msg = _create(ant, layer_norm=2)
+    assert rc == -1 and "layer_norm" in msg
+    rc, msg = _create(ant, layer_norm=1, mlp_precision=1)
+    assert rc == -6 and "layer normalisation" in msg
+    rc, msg = _create(ant, layer_norm=1)
+    assert rc in (0, -3), msg   # past the option checks (no device here: the first HIP call fails)
