@@ -244,6 +244,12 @@ def mtu_window(P, wl, torch, steps=3):
     s0 = sim._dev(W["s0"])
     actor, critic = sim.weights(W["actor"]), sim.weights(W["critic"])
     wall, fwd_ms, adj_ms, fw, ad = time_windows(sim, s0, actor, critic, steps, 1)
+    # the same window on the tape path (no recomputation in the adjoint)
+    st = P.Sim(W["model"], N, h, ad_, cd_, path=P.PATH_TAPE, mlp_precision="bf16")
+    twall, tfwd, tadj, _, _ = time_windows(st, s0, actor, critic, steps, 1)
+    tape = {"value": round(N * h / (twall / steps), 1), "fwd_ms": round(float(np.mean(tfwd)), 3),
+            "adj_ms": round(float(np.mean(tadj)), 3), "workspace_gb": round(st.ws_bytes / 1e9, 2)}
+    st.close()
     sim64 = P.Sim(W["model"], N, h, ad_, cd_, ckpt_interval=16, precision="fp64")
     fw64 = sim64.forward(W["s0"], W["actor"], W["critic"])
     ad64 = sim64.adjoint(fw64)
@@ -251,6 +257,7 @@ def mtu_window(P, wl, torch, steps=3):
     return {"workload": f"muscle humanoid, 152 MTUs, {N} envs, h={h}, S=48, k=16, BF16 MFMA actor/critic",
             "value": round(N * h / (wall / steps), 1), "unit": "env-steps/s",
             "fwd_ms": round(float(np.mean(fwd_ms)), 3), "adj_ms": round(float(np.mean(adj_ms)), 3),
+            "workspace_gb": round(sim.ws_bytes / 1e9, 2), "tape_path": tape,
             "err_vs_fp64": {"dL_da": grad_err(ad["dL_da"], ad64["dL_da"], 1),
                             "dL_ds0": grad_err(ad["dL_ds0"], ad64["dL_ds0"], 0),
                             "actions_t0_relmax": float(((fw["actions"][0].double() - fw64["actions"][0]).abs().max()

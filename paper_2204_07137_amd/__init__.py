@@ -700,7 +700,8 @@ PHASES = ["frame_begin", "fk", "velocities", "contacts", "muscles", "newton_eule
           "bias_crba_columns", "crba", "cholesky", "factor_lds", "solve", "integrate", "tape_store", "commit",
           "checkpoint", "adj_seed", "adj_integrator", "adj_lambda", "adj_path_sums", "adj_contacts",
           "adj_muscles", "adj_body_terms", "adj_subtree_sums", "adj_derivatives", "adj_state", "tape_load",
-          "tape_prefetch", "adj_frame", "window_end", "termination", "fc_states"]
+          "tape_prefetch", "adj_frame", "window_end", "termination", "fc_states", "muscle_paths",
+          "muscle_accumulate", "adj_muscle_paths", "adj_muscle_derivatives", "adj_muscle_accumulate"]
 
 
 def phase_profile(reset=True):

@@ -186,6 +186,21 @@ extern "C" size_t sim_abi_layout(int which, int field) {
 
 extern "C" const char* sim_last_error(void) { return g_err.c_str(); }
 
+// the muscle tables in the packed form the kernels read (one vector load per point and unit)
+template <typename T>
+static void pack_mtu_tables(DevModelT<T>& d) {
+  for (int k = 0; k < SIM_MAXMPT; ++k)
+    for (int i = 0; i < SIM_MAXMTU; ++i) {
+      T* pt = &d.mtu_pt[(k * SIM_MAXMTU + i) * 4];
+      for (int c = 0; c < 3; ++c) pt[c] = d.mtu_pos[(k * 3 + c) * SIM_MAXMTU + i];
+      pt[3] = (T)d.mtu_body[k * SIM_MAXMTU + i];
+    }
+  for (int i = 0; i < SIM_MAXMTU; ++i) {
+    T* pr = &d.mtu_par[i * 4];
+    pr[0] = d.mtu_fmax[i]; pr[1] = d.mtu_lopt[i]; pr[2] = d.mtu_lslack[i]; pr[3] = (T)d.mtu_npt[i];
+  }
+}
+
 template <typename T>
 static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   std::memcpy(&d, &s, offsetof(DevModelT<double>, dt_sub));   // leading ints
@@ -225,6 +240,7 @@ static void convert_model(const DevModelT<double>& s, DevModelT<T>& d) {
   }
   for (int i = 0; i < SIM_MAXMPT * SIM_MAXMTU; ++i) d.mtu_body[i] = s.mtu_body[i];
   for (int i = 0; i < SIM_MAXMPT * 3 * SIM_MAXMTU; ++i) d.mtu_pos[i] = (T)s.mtu_pos[i];
+  pack_mtu_tables(d);
   for (int c = 0; c < SIM_MAXC; ++c) {
     d.cbody[c] = s.cbody[c];
     d.crad[c] = (T)s.crad[c];
@@ -338,6 +354,7 @@ static int build_model(const SimModelDesc* md, DevModelT<double>& m) {
     }
     m.tau_act = md->tau_act; m.fl_w = md->fl_width; m.vmax = md->vmax;
   }
+  pack_mtu_tables(m);
   if (md->task == TASK_MTU && md->n_mtu < 1) return fail(SIM_E_MODEL, "the muscle task needs muscles");
   m.J = J; m.nq = nq; m.nv = nv; m.na = md->n_act + md->n_mtu; m.nc = md->n_contacts;
   m.n_mtu = md->n_mtu; m.n_motor = md->n_act; m.nck = nq + nv + md->n_mtu;

@@ -427,19 +427,24 @@ struct MtuPath {
   int b[SIM_MAXMPT];
   int np;
   real F, Fr, fl, fv, lt, L, Ld;
+  real fmax, lopt;
 };
 
 template <class L>
 __device__ __forceinline__ void mtu_path(const Scal* __restrict__ m, const L& E, int i, MtuPath& P,
                                          real act) {
+  typedef real rv4 __attribute__((ext_vector_type(4)));
   const DevModel* __restrict__ T = m->tab;
-  P.np = T->mtu_npt[i];
+  const rv4 par = *reinterpret_cast<const rv4*>(&T->mtu_par[4 * i]);
+  P.np = (int)par[3];
+  P.fmax = par[0];
+  P.lopt = par[1];
 #pragma unroll
   for (int k = 0; k < SIM_MAXMPT; ++k) {
     // the model tables repeat the last point in the slots past it
-    const int b = T->mtu_body[k * SIM_MAXMTU + i];
-    f3 r = mk3(T->mtu_pos[(k * 3 + 0) * SIM_MAXMTU + i], T->mtu_pos[(k * 3 + 1) * SIM_MAXMTU + i],
-               T->mtu_pos[(k * 3 + 2) * SIM_MAXMTU + i]);
+    const rv4 w = *reinterpret_cast<const rv4*>(&T->mtu_pt[4 * (k * SIM_MAXMTU + i)]);
+    const int b = (int)w[3];
+    f3 r = mk3(w[0], w[1], w[2]);
     P.b[k] = b;
     P.x[k] = add3(ld3(E.p[b]), mv3(E.R[b], r));
     P.v[k] = ptv(ldsv(E.v[b]), P.x[k]);
@@ -460,14 +465,14 @@ __device__ __forceinline__ void mtu_path(const Scal* __restrict__ m, const L& E,
       P.il[k] = RL(0.0);
     }
   }
-  const real lopt = T->mtu_lopt[i];
+  const real lopt = P.lopt;
   P.L = Lp;
   P.Ld = Ld;
-  P.lt = (Lp - T->mtu_lslack[i]) / lopt;
+  P.lt = (Lp - par[2]) / lopt;
   const real z = (P.lt - RL(1.0)) / m->fl_w;
   P.fl = m_exp(-z * z);
   P.fv = RL(1.0) + Ld / (m->vmax * lopt);
-  P.Fr = T->mtu_fmax[i] * act * P.fl * P.fv;
+  P.Fr = P.fmax * act * P.fl * P.fv;
   P.F = P.Fr > RL(0.0) ? P.Fr : RL(0.0);
 }
 
@@ -510,11 +515,13 @@ __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E
   for (int i = ln; i < SIM_MUS_CF * SIM_MUS_STRIDE; i += SIM_WAVE) E.mus[i] = RL(0.0);
   wsync();
   real* fm = &E.mus[(ln % SIM_MUS_CF) * SIM_MUS_STRIDE];
+  SIM_PHASE(E, PH_F_MUSCLE);
   for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
     const int i = i0 + ln;
     if (i < m->n_mtu) {
       MtuPath P;
       mtu_path(m, E, i, P, E.act[i]);
+      SIM_PHASE(E, PH_FM_PATH);
       // consecutive points on one body are summed first: one addition per run of points
       sv acc = zsv();
       int cur = P.b[0];
@@ -532,6 +539,7 @@ __device__ __forceinline__ void muscle_wrenches(const Scal* __restrict__ m, L& E
         }
       }
       lds_add6(fm + cur * 6, acc);
+      SIM_PHASE(E, PH_FM_ACC);
     }
   }
   wsync();
@@ -554,13 +562,14 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
   real* fm = &E.mus[cp * SIM_MUS_STRIDE];
   real* mab = &E.mus[(SIM_MUS_CA + cp) * SIM_MUS_STRIDE];
   real* mvb = &E.mus[(2 * SIM_MUS_CA + cp) * SIM_MUS_STRIDE];
-  const DevModel* __restrict__ T = m->tab;
+  SIM_PHASE(E, PH_A_MUSCLE);
   for (int i0 = 0; i0 < m->n_mtu; i0 += SIM_WAVE) {
     const int i = i0 + ln;
     if (i < m->n_mtu) {
       const real act = E.act[i];
       MtuPath P;
       mtu_path(m, E, i, P, act);
+      SIM_PHASE(E, PH_AM_PATH);
       f3 nu[SIM_MAXMPT];
 #pragma unroll
       for (int k = 0; k < SIM_MAXMPT; ++k) nu[k] = ptv(ldsv(E.W[P.b[k]]), P.x[k]);
@@ -570,7 +579,7 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
         if (k + 1 < P.np) delta += dot3(P.u[k], sub3(nu[k + 1], nu[k]));
       // at zero raw tension (e.g. zero activation) the derivative is the active branch's
       const bool on = P.Fr >= RL(0.0);
-      const real lopt = T->mtu_lopt[i], fmax = T->mtu_fmax[i];
+      const real lopt = P.lopt, fmax = P.fmax;
       const real z = (P.lt - RL(1.0)) / m->fl_w;
       const real dFdL = on ? fmax * act * P.fv * P.fl * (-RL(2.0) * z / m->fl_w) / lopt : RL(0.0);
       const real dFdLd = on ? fmax * act * P.fl / (m->vmax * lopt) : RL(0.0);
@@ -592,6 +601,7 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
           xb[k] = sub3(xb[k], g);
         }
       }
+      SIM_PHASE(E, PH_AM_DERIV);
       // consecutive points on one body are summed first (see muscle_wrenches)
       sv af = zsv(), aa = zsv(), av = zsv();
       int cur = P.b[0];
@@ -620,6 +630,7 @@ __device__ __forceinline__ void muscle_adjoint(const Scal* __restrict__ m, L& E,
       lds_add6(fm + cur * 6, af);
       lds_add6(mab + cur * 6, aa);
       lds_add6(mvb + cur * 6, av);
+      SIM_PHASE(E, PH_AM_ACC);
     }
   }
   wsync();

@@ -147,9 +147,15 @@ __device__ __forceinline__ void window_end(const WinArgs& A, const Scal* __restr
   if (ln == 0 && A.nonfinite) A.nonfinite[env] = all ? 0 : 1;
 }
 
+// Launch forms a window kernel is compiled for: any (chosen per launch from the arguments, as in
+// the group kernels), or one fixed form, so that the kernel carries only that form's code and
+// registers.
+enum { KP_ANY = -1, KP_TAPE = 0, KP_FC = 1, KP_CKPT = 2 };
+
 // ======================================================================= persistent forward
-// One environment's forward window (the wavefront owns env; E is its LDS).
-template <int NV, class L>
+// One environment's forward window (the wavefront owns env; E is its LDS).  PATH: KP_TAPE,
+// KP_CKPT (checkpoints, with or without the factor cache) or KP_ANY.
+template <int NV, class L, int PATH = KP_ANY>
 __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E) {
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
@@ -173,7 +179,7 @@ __device__ __forceinline__ void window_fwd_body(const WinArgs& A, int env, L& E)
     for (int sub = 0; sub < S; ++sub) {
       int gi = t * S + sub;
       int fb;
-      if (A.tape_full) {
+      if (PATH == KP_TAPE || (PATH == KP_ANY && A.tape_full)) {
         // the tape entry holds the pre-substep state and the linearisation
         substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         tape_store<NV>(TM, E, C, fb, ln, A.tape + ((size_t)gi * N + env) * A.tape_ws);
@@ -338,9 +344,12 @@ __device__ __forceinline__ void fc_rebuild_states(const Scal* __restrict__ m, L&
   }
 }
 
-// One environment's reverse window.
-template <int NV, class L>
+// One environment's reverse window.  PATH: KP_TAPE, KP_FC, KP_CKPT (checkpoints without the
+// factor cache) or KP_ANY.
+template <int NV, class L, int PATH = KP_ANY>
 __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E) {
+  const bool use_tape = PATH == KP_TAPE || (PATH == KP_ANY && A.tape_full);
+  const bool use_fc = L::kMtu == 0 && (PATH == KP_FC || (PATH == KP_ANY && A.fc));
   const Scal scl = load_scal(A.model);
   const Scal* m = &scl;
   const int ln = grp_lane<L::kLanes>();
@@ -361,7 +370,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
   // factor cache: the next segment's rebuild inputs and the next entry, loaded ahead
   FcSeg NS;
   FcRegs<L> FP;
-  if (L::kMtu == 0 && A.fc) {
+  if (use_fc) {
     const int G = A.h * S / k;
     fc_seg_prefetch<L>(A, m, NS, G - 1, env, ln);
     const size_t gi = (size_t)G * k - 1;
@@ -379,7 +388,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
     }
     const real* at = A.actions_fw + ((size_t)t * N + env) * na;
     for (int i = ln; i < na; i += L::kLanes) E.a[i] = at[i];
-    if (A.tape_full) {
+    if (use_tape) {
       // the forward stored every substep's pre-state and linearisation; the next (earlier)
       // entry is loaded into registers while the current one is reversed
       TapeRegs<L> P;
@@ -392,7 +401,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
         substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
       }
-    } else if (L::kMtu == 0 && A.fc) {
+    } else if (use_fc) {
       // factor cache: per segment, the pre-substep states are rebuilt from the checkpoint with
       // the cached accelerations, then each substep is reversed from its state, its cached
       // factor and its recomputed kinematics; every load is issued a substep (entries) or a
@@ -477,20 +486,20 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
 
 // One workgroup of one wavefront runs 64 / L::kLanes environments, each on L::kLanes lanes
 // with its own LDS block (full layouts: one environment per wavefront).
-template <int NV, class L>
+template <int NV, class L, int PATH>
 __global__ __launch_bounds__(SIM_WAVE) void k_window_fwd(WinArgs A) {
   constexpr int EPW = SIM_WAVE / L::kLanes;
   __shared__ L E[EPW];
   const int g = EPW == 1 ? 0 : (int)threadIdx.x / L::kLanes;
-  window_fwd_body<NV>(A, blockIdx.x * EPW + g, E[g]);
+  window_fwd_body<NV, L, PATH>(A, blockIdx.x * EPW + g, E[g]);
 }
 
-template <int NV, class L>
+template <int NV, class L, int PATH>
 __global__ __launch_bounds__(SIM_WAVE) void k_window_adj(WinArgs A) {
   constexpr int EPW = SIM_WAVE / L::kLanes;
   __shared__ L E[EPW];
   const int g = EPW == 1 ? 0 : (int)threadIdx.x / L::kLanes;
-  window_adj_body<NV>(A, blockIdx.x * EPW + g, E[g]);
+  window_adj_body<NV, L, PATH>(A, blockIdx.x * EPW + g, E[g]);
 }
 
 // ======================================================================= mixed-morphology group
@@ -788,11 +797,24 @@ void launch_window_loss(const WinArgs& A, hipStream_t s) {
 }
 #endif  // SIM_EMIT_MAIN
 
+// The full and muscle layouts have a kernel per launch form; the compact layouts (small
+// models) one kernel that reads the form from its arguments.
 template <int NV, class L>
 static void launch_window(const WinArgs& A, int adjoint, hipStream_t s) {
   dim3 grid(A.N / (SIM_WAVE / L::kLanes)), block(SIM_WAVE);
-  if (adjoint) hipLaunchKernelGGL((k_window_adj<NV, L>), grid, block, 0, s, A);
-  else hipLaunchKernelGGL((k_window_fwd<NV, L>), grid, block, 0, s, A);
+  if constexpr (L::kLanes == SIM_WAVE) {
+    if (adjoint) {
+      if (A.tape_full) hipLaunchKernelGGL((k_window_adj<NV, L, KP_TAPE>), grid, block, 0, s, A);
+      else if (L::kMtu == 0 && A.fc) hipLaunchKernelGGL((k_window_adj<NV, L, L::kMtu == 0 ? KP_FC : KP_CKPT>), grid, block, 0, s, A);
+      else hipLaunchKernelGGL((k_window_adj<NV, L, KP_CKPT>), grid, block, 0, s, A);
+    } else {
+      if (A.tape_full) hipLaunchKernelGGL((k_window_fwd<NV, L, KP_TAPE>), grid, block, 0, s, A);
+      else hipLaunchKernelGGL((k_window_fwd<NV, L, KP_CKPT>), grid, block, 0, s, A);
+    }
+  } else {
+    if (adjoint) hipLaunchKernelGGL((k_window_adj<NV, L, KP_ANY>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_window_fwd<NV, L, KP_ANY>), grid, block, 0, s, A);
+  }
 }
 
 #if SIM_EMIT_MAIN

@@ -125,7 +125,12 @@ enum {
   PH_A_FRAME = 28,      // frame-level reverse (reward, actor input VJP, observation)
   PH_WINDOW_END = 29,   // terminal observation, critic, outputs
   PH_TERM = 30,         // early-termination test and reset
-  PH_FC_STATES = 31     // factor cache: a segment's pre-substep states from the cached accelerations
+  PH_FC_STATES = 31,   // factor cache: a segment's pre-substep states from the cached accelerations
+  PH_FM_PATH = 32,     // forward muscles: path geometry and tensions (per pass of 64 units)
+  PH_FM_ACC = 33,      // forward muscles: point forces into the per-body wrench table
+  PH_AM_PATH = 34,     // muscle adjoint: path geometry and tensions recomputed
+  PH_AM_DERIV = 35,    // muscle adjoint: virtual velocities, tension and direction derivatives
+  PH_AM_ACC = 36       // muscle adjoint: per-body terms into the three tables
 };
 #ifdef SIM_PHASE_PROFILE
 template <int LN>

@@ -119,6 +119,10 @@ struct DevModelT {
   int mtu_body[SIM_MAXMPT * SIM_MAXMTU];     // [point][unit]
   T mtu_pos[SIM_MAXMPT * 3 * SIM_MAXMTU];    // [point][xyz][unit], in the body frame
   T mtu_fmax[SIM_MAXMTU], mtu_lopt[SIM_MAXMTU], mtu_lslack[SIM_MAXMTU];
+  // the same tables packed for one vector load per point and one per unit (what the kernels
+  // read): [point][unit][x, y, z, body] and [unit][F_max, l_opt, l_slack, points]
+  T mtu_pt[SIM_MAXMPT * SIM_MAXMTU * 4] __attribute__((aligned(32)));
+  T mtu_par[SIM_MAXMTU * 4] __attribute__((aligned(32)));
 };
 
 template <typename T>
