@@ -1486,11 +1486,12 @@ __device__ __forceinline__ void fc_prefetch_entry(const Scal* __restrict__ m, co
   P.qdd = (ln < m->nv) ? qrow[ln] : RL(0.0);
 }
 
-// a prefetched entry back: the pre-substep state, factor and pivots into the block and
-// registers, qdd and the new velocities
-template <int NV, class L>
-__device__ __forceinline__ void fc_load_regs(const Scal* __restrict__ m, const FcMap<L>& T, L& E, Chol& C, int& fb,
-                                             int ln, const FcRegs<L>& P) {
+// a prefetched entry back: the pre-substep state, factor and pivots into the block, qdd and
+// the new velocities, and the substep's fallback flag (the factor enters registers later, with
+// factor_from_block, so that it is not live across the kinematics recomputation)
+template <class L>
+__device__ __forceinline__ void fc_load_regs(const Scal* __restrict__ m, const FcMap<L>& T, L& E, int& fb, int ln,
+                                             const FcRegs<L>& P) {
   wsync();
   chunks_restore<L::kFcChunksPerLane>(T, &E.q[0], P.c);
   if (ln < m->nq) E.q[ln] = P.q;
@@ -1500,7 +1501,9 @@ __device__ __forceinline__ void fc_load_regs(const Scal* __restrict__ m, const F
   }
   wsync();
   rebuild_qdn(m, E, ln);
-  factor_from_block<NV>(m, E, C, fb, ln);
+  // uniform over the environment's lanes (its own LDS); over the wavefront only with 64 lanes
+  if constexpr (L::kLanes == SIM_WAVE) fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
+  else fb = (E.tfb[0] != RL(0.0)) ? 1 : 0;
   SIM_PHASE(E, PH_TAPE_LOAD);
 }
 

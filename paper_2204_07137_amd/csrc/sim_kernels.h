@@ -417,7 +417,7 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
         SIM_PHASE(E, PH_FC_STATES);
         for (int i = k - 1; i >= 0; --i) {
           int fb;
-          fc_load_regs<NV>(m, FM, E, C, fb, ln, FP);
+          fc_load_regs(m, FM, E, fb, ln, FP);
           if (i > 0) {
             const size_t gi = (size_t)g * k + i - 1;
             fc_prefetch(m, FM, FP, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv,
@@ -427,8 +427,15 @@ __device__ __forceinline__ void window_adj_body(const WinArgs& A, int env, L& E)
             fc_prefetch_entry(m, FM, FP, A.fc + (gi * N + env) * A.fc_ws, A.fcq + (gi * N + env) * nv, ln);
           }
           SIM_PHASE(E, PH_TAPE_PREFETCH);
-          if (fb) substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
-          else substep_kinematics(m, E, jr, cr, ln);
+          if (fb) {
+            substep_forward<NV>(m, E, jr, cr, ln, C, false, fb);
+          } else {
+            // the factor enters registers only now: it is not live across the kinematics
+            substep_kinematics(m, E, jr, cr, ln);
+            int fb2;
+            factor_from_block<NV>(m, E, C, fb2, ln);
+            SIM_PHASE(E, PH_TAPE_LOAD);
+          }
           substep_adjoint_core<NV>(m, E, jr, cr, ln, C, fb);
         }
       }
