@@ -642,7 +642,7 @@ def main():
         # the same window with early termination at the humanoid's torso height (0.74 m):
         # per-frame test, reset from per-env restart states, discount and gradient cut
         mdt = wl.with_termination(md)
-        simt = P.Sim(mdt, N, h, actor_dims, critic_dims, ckpt_interval=args.k)
+        simt = P.Sim(mdt, N, h, actor_dims, critic_dims, ckpt_interval=args.k, factor_cache=fc)
         reset = simt._dev(wl.initial_states(mdt, N, seed=9))
         n_t = max(3, args.steps // 4)
         tw, _, _, tfw, _ = time_windows(simt, s0, actor, critic, n_t, 1, reset_states=reset)

@@ -967,9 +967,15 @@ __device__ __forceinline__ void substep_forward(const Scal* __restrict__ m, L& E
   wsync();
   SIM_PHASE(E, PH_F_CRBA);
   // ---- Cholesky and solve (lane = DOF); rows >= nv padded with the identity
+  if (nv == NV) {
+    // no padding: the lanes past the matrix read row 0; no lane of the matrix reads them back
 #pragma unroll
-  for (int k = 0; k < NV; ++k)
-    C.row[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : ((ln == k) ? RL(1.0) : RL(0.0));
+    for (int k = 0; k < NV; ++k) C.row[k] = E.M[ln < nv ? ln : 0][k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      C.row[k] = (ln < nv && k < nv) ? E.M[ln < nv ? ln : 0][k] : ((ln == k) ? RL(1.0) : RL(0.0));
+  }
   real minpiv;
   real dmax = grp_max<LN>(ln < nv ? E.M[ln < nv ? ln : 0][ln < nv ? ln : 0] : RL(0.0));
   chol_factor<NV, LN>(C, ln, minpiv);
@@ -1385,12 +1391,22 @@ template <int NV, class L>
 __device__ __forceinline__ void factor_from_block(const Scal* __restrict__ m, const L& E, Chol& C, int& fb, int ln) {
   const int nv = m->nv;
   const int lr = ln < nv ? ln : 0;
+  if (nv == NV) {
+    // no padding: the lanes past the matrix read row 0 and are never read by the solves
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const real pad = (ln == k) ? RL(1.0) : RL(0.0);
-    C.row[k] = (ln < nv && k < nv) ? E.M[lr][k] : pad;
-    C.col[k] = (ln < nv && k < nv) ? E.M[k][lr] : pad;
-    C.dinv[k] = (k < nv) ? E.tdinv[k] : RL(1.0);
+    for (int k = 0; k < NV; ++k) {
+      C.row[k] = E.M[lr][k];
+      C.col[k] = E.M[k][lr];
+      C.dinv[k] = E.tdinv[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const real pad = (ln == k) ? RL(1.0) : RL(0.0);
+      C.row[k] = (ln < nv && k < nv) ? E.M[lr][k] : pad;
+      C.col[k] = (ln < nv && k < nv) ? E.M[k][lr] : pad;
+      C.dinv[k] = (k < nv) ? E.tdinv[k] : RL(1.0);
+    }
   }
   // uniform over the environment's lanes (its own LDS); over the wavefront only with 64 lanes
   if constexpr (L::kLanes == SIM_WAVE) fb = __builtin_amdgcn_readfirstlane(E.tfb[0] != RL(0.0) ? 1 : 0);
