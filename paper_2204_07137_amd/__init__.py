@@ -10,8 +10,10 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# the phase-profiling build (libshacsim_phase.so) is selected with SHACSIM_LIB=phase
-LIB_PATH = os.path.join(HERE, "libshacsim_phase.so" if os.environ.get("SHACSIM_LIB") == "phase" else "libshacsim.so")
+# another build of the library (libshacsim_<name>.so, e.g. the phase-profiling build
+# libshacsim_phase.so) is selected with SHACSIM_LIB=<name>
+LIB_PATH = os.path.join(HERE, f"libshacsim_{os.environ['SHACSIM_LIB']}.so" if os.environ.get("SHACSIM_LIB")
+                        else "libshacsim.so")
 
 MAXL = 4
 PATH_PERSISTENT, PATH_PLAIN, PATH_TAPE = 0, 1, 2
