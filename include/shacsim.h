@@ -194,9 +194,11 @@ typedef struct SimOptions {
                                     / sqrt(var + 1e-5) + beta over the layer's outputs (App. A.2);
                                     the gains and biases are window inputs (actor_ln_* /
                                     critic_ln_*), and dL_dtheta then holds their gradients after
-                                    each hidden layer's W, b.  FP32 / FP64 MLPs; the window and its
-                                    policy gradient (sim_critic_values / sim_critic_fit refuse such
-                                    a handle).  0: no normalisation (the benchmark configurations). */
+                                    each hidden layer's W, b.  FP32 / FP64 MLPs.  The critic calls
+                                    take the critic's gains and biases too (sim_critic_values_ln,
+                                    SimCriticFitIO.critic_ln_*; sim_critic_values and
+                                    sim_critic_values_noalloc refuse such a handle).  0: no
+                                    normalisation (the benchmark configurations). */
 } SimOptions;
 
 typedef struct SimHandle SimHandle;
@@ -415,6 +417,16 @@ int sim_critic_values(SimHandle* h, const void* obs, int rows, const void* const
                       const void* const* critic_b, const void* obs_mean, const void* obs_inv_std, void* values,
                       void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* sim_critic_values for a handle with layer_norm (App. A.2: a layer normalisation after every
+ * hidden layer's ELU): critic_ln_g / critic_ln_b are host arrays of device pointers to each
+ * hidden layer's gain and bias [dims[l + 1]].  Each row's mean and variance are computed over
+ * the layer's outputs (one wavefront per row, a fixed butterfly order).  Without layer_norm
+ * the gains and biases are ignored and may be null. */
+int sim_critic_values_ln(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
+                         const void* const* critic_b, const void* const* critic_ln_g,
+                         const void* const* critic_ln_b, const void* obs_mean, const void* obs_inv_std,
+                         void* values, void* workspace, size_t workspace_bytes, void* hip_stream);
+
 typedef struct SimCriticFitIO {
   const void* obs;              /* [rows][obs_dim] states of the window (o_0 .. o_{h-1}) */
   const void* targets;          /* [rows] their TD-lambda estimates (treated as constants) */
@@ -434,6 +446,11 @@ typedef struct SimCriticFitIO {
   size_t workspace_bytes;
   const void* obs_mean;         /* [obs_dim] optional (with obs_inv_std): the critic reads */
   const void* obs_inv_std;      /* (obs - obs_mean) * obs_inv_std */
+  void* critic_ln_g[SIM_MAX_LAYERS];   /* with layer_norm: each hidden layer's normalisation gain */
+  void* critic_ln_b[SIM_MAX_LAYERS];   /* and bias [dims[l + 1]], updated in place; adam_m / adam_v
+                                          then hold W_0, b_0, g_0, beta_0, W_1, ... (the gain and
+                                          bias of a hidden layer after its W, b).  Ignored
+                                          without layer_norm. */
 } SimCriticFitIO;
 
 /* Running observation statistics (Sec. 3.3): merges rows [rows][dim] of observations (device)

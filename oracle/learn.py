@@ -82,14 +82,41 @@ def soft_update(target, online, alpha):
     return [alpha * _t(a) + (1.0 - alpha) * _t(b) for a, b in zip(target, online)]
 
 
-def critic_values(layers, obs):
-    return mlp_forward([(_t(W), _t(b)) for W, b in layers], _t(obs))[:, 0]
+def critic_values(layers, obs, ln=None):
+    """V(obs); ln: None, or per hidden layer the (gain, bias) of its layer normalisation."""
+    lnt = None if ln is None else [(_t(g), _t(b)) for g, b in ln]
+    return mlp_forward([(_t(W), _t(b)) for W, b in layers], _t(obs), ln=lnt)[:, 0]
 
 
-def critic_fit(layers, obs, targets, perm, n_minibatch, m, v, adam_step0, lr, beta1, beta2, eps):
+def _flat_params(layers, ln):
+    """The critic's parameters in the library's order: per layer W, b, and after a hidden
+    layer's W, b its normalisation gain and bias (with ln)."""
+    out = []
+    for i, (W, b) in enumerate(layers):
+        out += [_t(W), _t(b)]
+        if ln is not None and i < len(layers) - 1:
+            out += [_t(ln[i][0]), _t(ln[i][1])]
+    return out
+
+
+def _unflat(params, n_layers, with_ln):
+    layers, ln, k = [], [], 0
+    for i in range(n_layers):
+        layers.append((params[k], params[k + 1]))
+        k += 2
+        if with_ln and i < n_layers - 1:
+            ln.append((params[k], params[k + 1]))
+            k += 2
+    return layers, (ln if with_ln else None)
+
+
+def critic_fit(layers, obs, targets, perm, n_minibatch, m, v, adam_step0, lr, beta1, beta2, eps, ln=None):
     """layers [(W, b)], obs [rows, od], targets [rows], perm [n_iter, rows]; m, v lists shaped
-    like the parameters (W_0, b_0, W_1, ...).  Returns (layers, m, v, losses)."""
-    params = [x for W, b in layers for x in (_t(W), _t(b))]
+    like the parameters in the library's order (W_0, b_0, [g_0, beta_0,] W_1, ...); ln: None or
+    the (gain, bias) of each hidden layer's normalisation, fitted with the weights.
+    Returns (layers, m, v, losses), and with ln (layers, ln, m, v, losses)."""
+    n_layers = len(layers)
+    params = _flat_params(layers, ln)
     m = [_t(x) for x in m]
     v = [_t(x) for x in v]
     obs, targets = _t(obs), _t(targets)
@@ -100,10 +127,14 @@ def critic_fit(layers, obs, targets, perm, n_minibatch, m, v, adam_step0, lr, be
         for mb in range(n_minibatch):
             idx = torch.as_tensor(perm[it][mb * rows // n_minibatch:(mb + 1) * rows // n_minibatch], dtype=torch.long)
             ps = [p.clone().requires_grad_(True) for p in params]
-            V = mlp_forward([(ps[2 * i], ps[2 * i + 1]) for i in range(len(ps) // 2)], obs[idx])[:, 0]
+            lay, lnp = _unflat(ps, n_layers, ln is not None)
+            V = mlp_forward(lay, obs[idx], ln=lnp)[:, 0]
             loss = ((V - targets[idx]) ** 2).mean()
             grads = torch.autograd.grad(loss, ps)
             losses.append(float(loss.detach()))
             step += 1
             params, m, v = adam_step(params, grads, m, v, step, lr, beta1, beta2, eps)
-    return [(params[2 * i], params[2 * i + 1]) for i in range(len(params) // 2)], m, v, losses
+    lay, lnp = _unflat(params, n_layers, ln is not None)
+    if ln is None:
+        return lay, m, v, losses
+    return lay, lnp, m, v, losses

@@ -77,7 +77,8 @@ class SimCriticFitIO(ctypes.Structure):
     _fields_ = [("obs", _p), ("targets", _p), ("rows", _i), ("perm", _p), ("n_iter", _i), ("n_minibatch", _i),
                 ("critic_w", _p * MAXL), ("critic_b", _p * MAXL), ("adam_m", _p), ("adam_v", _p),
                 ("adam_step", _i), ("lr", _d), ("beta1", _d), ("beta2", _d), ("eps", _d), ("loss_out", _p),
-                ("workspace", _p), ("workspace_bytes", ctypes.c_size_t), ("obs_mean", _p), ("obs_inv_std", _p)]
+                ("workspace", _p), ("workspace_bytes", ctypes.c_size_t), ("obs_mean", _p), ("obs_inv_std", _p),
+                ("critic_ln_g", _p * MAXL), ("critic_ln_b", _p * MAXL)]
 
 
 EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window",
@@ -86,6 +87,7 @@ EXPORTS = ["sim_create", "sim_workspace_bytes", "sim_dims", "sim_forward_window"
            "sim_tune", "sim_probe_fma_bytes", "sim_probe_fma", "sim_probe_copy", "sim_adam_step",
            "sim_soft_update", "sim_td_lambda", "sim_critic_workspace_bytes", "sim_critic_values",
            "sim_critic_fit", "sim_obs_stats_update", "sim_abi_layout", "sim_critic_values_noalloc",
+           "sim_critic_values_ln",
            "sim_phase_profile"]
 MAX_GROUP = 6
 
@@ -146,6 +148,9 @@ def lib():
         L.sim_critic_values.argtypes = [_p, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _p, _p, _p,
                                         ctypes.c_size_t, _p]
         L.sim_critic_values.restype = _i
+        L.sim_critic_values_ln.argtypes = [_p, _p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p),
+                                           ctypes.POINTER(_p), _p, _p, _p, _p, ctypes.c_size_t, _p]
+        L.sim_critic_values_ln.restype = _i
         L.sim_critic_fit.argtypes = [_p, ctypes.POINTER(SimCriticFitIO), _p]
         L.sim_critic_fit.restype = _i
         L.sim_obs_stats_update.argtypes = [_p, ctypes.c_long, _i, _d, _p, _p, _p, _d, _i, _p]
@@ -293,9 +298,10 @@ class Sim:
         assert mean.shape == (self.od,) and inv_std.shape == (self.od,)
         return _p(mean.data_ptr()), _p(inv_std.data_ptr()), (mean, inv_std)
 
-    def critic_values(self, obs, critic, workspace=None, obs_norm=None):
+    def critic_values(self, obs, critic, workspace=None, obs_norm=None, critic_ln=None):
         """sim_critic_values: V(obs) for obs [rows, obs_dim] with critic [(W, b), ...] (device);
-        obs_norm = (mean, inv_std) normalises the critic's input."""
+        obs_norm = (mean, inv_std) normalises the critic's input; critic_ln [(g, beta)] per hidden
+        layer (a handle with layer_norm: sim_critic_values_ln)."""
         t = self.torch
         obs = self._dev(obs).reshape(-1, self.od)
         rows = obs.shape[0]
@@ -305,16 +311,26 @@ class Sim:
         b = (_p * MAXL)(*([_p(B.data_ptr()) for _, B in cw] + [_p(0)] * (MAXL - len(cw))))
         out = t.empty(rows, device="cuda", dtype=self.dtype)
         pm, ps, keep = self._norm_ptrs(obs_norm)
-        _check(lib().sim_critic_values(self.h, _p(obs.data_ptr()), rows, w, b, pm, ps, _p(out.data_ptr()),
-                                       _p(ws.data_ptr()), ws.numel(), _stream()))
+        if critic_ln is None:
+            _check(lib().sim_critic_values(self.h, _p(obs.data_ptr()), rows, w, b, pm, ps, _p(out.data_ptr()),
+                                           _p(ws.data_ptr()), ws.numel(), _stream()))
+        else:
+            cln = [(self._dev(g).reshape(-1), self._dev(be).reshape(-1)) for g, be in critic_ln]
+            lg = (_p * MAXL)(*([_p(g.data_ptr()) for g, _ in cln] + [_p(0)] * (MAXL - len(cln))))
+            lb = (_p * MAXL)(*([_p(be.data_ptr()) for _, be in cln] + [_p(0)] * (MAXL - len(cln))))
+            _check(lib().sim_critic_values_ln(self.h, _p(obs.data_ptr()), rows, w, b, lg, lb, pm, ps,
+                                              _p(out.data_ptr()), _p(ws.data_ptr()), ws.numel(), _stream()))
+            del cln
         del keep
         return out
 
     def critic_fit(self, obs, targets, perm, n_minibatch, critic, adam_m, adam_v, adam_step, lr,
-                   beta1=0.7, beta2=0.95, eps=1e-8, workspace=None, obs_norm=None):
+                   beta1=0.7, beta2=0.95, eps=1e-8, workspace=None, obs_norm=None, critic_ln=None):
         """sim_critic_fit: fits `critic` (a list of device (W, b) tensors of this handle's dtype,
         updated in place) to targets [rows] on obs [rows, obs_dim] over len(perm) passes of
-        n_minibatch minibatches (perm [n_iter, rows] int32).  Returns the minibatch losses."""
+        n_minibatch minibatches (perm [n_iter, rows] int32).  With layer_norm, critic_ln is a
+        list of device (g, beta) tensors per hidden layer, updated in place too, and the flat
+        Adam moments hold W_0, b_0, g_0, beta_0, W_1, ...  Returns the minibatch losses."""
         t = self.torch
         obs = self._dev(obs).reshape(-1, self.od)
         targets = self._dev(targets).reshape(-1)
@@ -330,6 +346,10 @@ class Sim:
             assert W.dtype == self.dtype and W.is_cuda and W.is_contiguous() and B.is_contiguous()
             io.critic_w[i] = W.data_ptr()
             io.critic_b[i] = B.data_ptr()
+        for i, (g, be) in enumerate(critic_ln or []):
+            assert g.dtype == self.dtype and g.is_cuda and g.is_contiguous() and be.is_contiguous()
+            io.critic_ln_g[i] = g.data_ptr()
+            io.critic_ln_b[i] = be.data_ptr()
         io.adam_m, io.adam_v, io.adam_step = _p(adam_m.data_ptr()), _p(adam_v.data_ptr()), int(adam_step)
         io.lr, io.beta1, io.beta2, io.eps = float(lr), float(beta1), float(beta2), float(eps)
         io.loss_out = _p(losses.data_ptr())

@@ -162,7 +162,7 @@ static const size_t kLayoutSimCriticFitIO[] = {
     offsetof(SimCriticFitIO, beta1), offsetof(SimCriticFitIO, beta2), offsetof(SimCriticFitIO, eps),
     offsetof(SimCriticFitIO, loss_out), offsetof(SimCriticFitIO, workspace),
     offsetof(SimCriticFitIO, workspace_bytes), offsetof(SimCriticFitIO, obs_mean),
-    offsetof(SimCriticFitIO, obs_inv_std),
+    offsetof(SimCriticFitIO, obs_inv_std), offsetof(SimCriticFitIO, critic_ln_g), offsetof(SimCriticFitIO, critic_ln_b),
 };
 
 extern "C" size_t sim_abi_layout(int which, int field) {
@@ -1614,6 +1614,7 @@ extern "C" int sim_obs_stats_update(const void* obs, long rows, int dim, double 
 #define CRITIC_SPLITS 32
 struct CriticWs {
   size_t x, y, v, h[SIM_MAXL], d0, d1, part, grad, total;
+  size_t yn[SIM_MAXL], st, lnpart;   // with layer normalisation
 };
 static CriticWs critic_ws(const SimOptions& o, int rows, size_t e) {
   CriticWs w = {};
@@ -1624,6 +1625,7 @@ static CriticWs critic_ws(const SimOptions& o, int rows, size_t e) {
   for (int l = 0; l < L; ++l) {
     maxpart = std::max(maxpart, (size_t)o.critic_dims[l + 1] * (o.critic_dims[l] + 1));
     nparams += (size_t)o.critic_dims[l + 1] * (o.critic_dims[l] + 1);
+    if (o.layer_norm && l + 1 < L) nparams += 2 * (size_t)o.critic_dims[l + 1];
   }
   size_t off = 0;
   w.x = off; off = align256(off + (size_t)rows * o.critic_dims[0] * e);
@@ -1634,6 +1636,12 @@ static CriticWs critic_ws(const SimOptions& o, int rows, size_t e) {
   w.d1 = off; off = align256(off + (size_t)rows * maxd * e);
   w.part = off; off = align256(off + (size_t)CRITIC_SPLITS * maxpart * e);
   w.grad = off; off = align256(off + nparams * e);
+  if (o.layer_norm && L > 1) {
+    // the normalised hidden layers, their per-row statistics, the gain / bias partials
+    for (int l = 1; l < L; ++l) { w.yn[l] = off; off = align256(off + (size_t)rows * o.critic_dims[l] * e); }
+    w.st = off; off = align256(off + (size_t)rows * 2 * (L - 1) * e);
+    w.lnpart = off; off = align256(off + (size_t)SIM_LN_BLOCKS * 2 * maxd * e);
+  }
   w.total = off;
   return w;
 }
@@ -1646,13 +1654,14 @@ extern "C" size_t sim_critic_workspace_bytes(const SimHandle* h, int rows) {
 
 template <typename T>
 static void critic_theta_args(const SimHandle* h, const CriticWs& w, char* ws, const void* const* cw, const void* const* cb,
-                              int rows, ThetaArgsT<T>& P) {
+                              const void* const* clg, const void* const* clb, int rows, ThetaArgsT<T>& P) {
   const SimOptions& o = h->opt;
   std::memset(&P, 0, sizeof(P));
   P.M = rows;
   P.nl = o.critic_layers;
   for (int l = 0; l <= o.critic_layers; ++l) P.dims[l] = o.critic_dims[l];
   P.splits = CRITIC_SPLITS;
+  const bool ln = o.layer_norm && o.critic_layers > 1;
   long off = 0;
   for (int l = 0; l < o.critic_layers; ++l) {
     P.W[l] = static_cast<const T*>(cw[l]);
@@ -1661,7 +1670,25 @@ static void critic_theta_args(const SimHandle* h, const CriticWs& w, char* ws, c
     off += (long)o.critic_dims[l] * o.critic_dims[l + 1];
     P.off_b[l] = off;
     off += o.critic_dims[l + 1];
+    if (ln && l + 1 < o.critic_layers) {
+      // the hidden layer's normalisation gain and bias follow its W, b
+      P.lng[l] = static_cast<const T*>(clg[l]);
+      P.lnb[l] = static_cast<const T*>(clb[l]);
+      P.off_g[l] = off;
+      off += o.critic_dims[l + 1];
+      P.off_beta[l] = off;
+      off += o.critic_dims[l + 1];
+    }
     if (l >= 1) P.H[l] = reinterpret_cast<T*>(ws + w.h[l]);
+  }
+  if (ln) {
+    P.ln = 1;
+    P.ln_eps = (T)1e-5;
+    P.st = reinterpret_cast<T*>(ws + w.st);
+    P.ldst = 2 * (o.critic_layers - 1);
+    for (int l = 1; l < o.critic_layers; ++l) P.Y[l] = reinterpret_cast<T*>(ws + w.yn[l]);
+    P.lnpart = reinterpret_cast<T*>(ws + w.lnpart);
+    P.ln_blocks = SIM_LN_BLOCKS;
   }
   P.d0 = reinterpret_cast<T*>(ws + w.d0);
   P.d1 = reinterpret_cast<T*>(ws + w.d1);
@@ -1671,10 +1698,11 @@ static void critic_theta_args(const SimHandle* h, const CriticWs& w, char* ws, c
 
 template <typename T>
 static int critic_values_impl(SimHandle* h, const void* obs, int rows, const void* const* cw, const void* const* cb,
-                              const void* mean, const void* inv_std, void* values, void* workspace, void* stream) {
+                              const void* const* clg, const void* const* clb, const void* mean, const void* inv_std,
+                              void* values, void* workspace, void* stream) {
   const CriticWs w = critic_ws(h->opt, rows, sizeof(T));
   ThetaArgsT<T> P;
-  critic_theta_args<T>(h, w, static_cast<char*>(workspace), cw, cb, rows, P);
+  critic_theta_args<T>(h, w, static_cast<char*>(workspace), cw, cb, clg, clb, rows, P);
   P.x0 = static_cast<const T*>(obs);
   P.x_shift = static_cast<const T*>(mean);
   P.x_scale = static_cast<const T*>(inv_std);
@@ -1683,25 +1711,48 @@ static int critic_values_impl(SimHandle* h, const void* obs, int rows, const voi
   return SIM_OK;
 }
 
+// the checks and the launch of sim_critic_values and sim_critic_values_ln
+static int critic_values_checked(SimHandle* h, const char* fn, const void* obs, int rows, const void* const* critic_w,
+                                 const void* const* critic_b, const void* const* ln_g, const void* const* ln_b,
+                                 const void* obs_mean, const void* obs_inv_std, void* values, void* workspace,
+                                 size_t workspace_bytes, void* hip_stream) {
+  const std::string f(fn);
+  if (!obs || !values || !critic_w || !critic_b || rows < 1) return fail(SIM_E_ARG, f + ": null pointer or no rows");
+  for (int l = 0; l < h->opt.critic_layers; ++l)
+    if (!critic_w[l] || !critic_b[l]) return fail(SIM_E_ARG, f + ": null critic weights");
+  if (h->opt.layer_norm)
+    for (int l = 0; l + 1 < h->opt.critic_layers; ++l)
+      if (!ln_g || !ln_b || !ln_g[l] || !ln_b[l]) return fail(SIM_E_ARG, f + ": null layer-normalisation gain or bias");
+  if ((obs_mean != nullptr) != (obs_inv_std != nullptr))
+    return fail(SIM_E_ARG, f + ": observation normalisation needs both obs_mean and obs_inv_std");
+  if (!workspace || workspace_bytes < sim_critic_workspace_bytes(h, rows))
+    return fail(SIM_E_WORKSPACE, f + ": workspace smaller than sim_critic_workspace_bytes()");
+  return (h->opt.precision == SIM_PREC_FP64)
+             ? critic_values_impl<double>(h, obs, rows, critic_w, critic_b, ln_g, ln_b, obs_mean, obs_inv_std, values,
+                                          workspace, hip_stream)
+             : critic_values_impl<float>(h, obs, rows, critic_w, critic_b, ln_g, ln_b, obs_mean, obs_inv_std, values,
+                                         workspace, hip_stream);
+}
+
 extern "C" int sim_critic_values(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
                                  const void* const* critic_b, const void* obs_mean, const void* obs_inv_std,
                                  void* values, void* workspace, size_t workspace_bytes, void* hip_stream) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (h->opt.layer_norm)
-    return fail(SIM_E_UNSUPPORTED, "sim_critic_values: layer normalisation is implemented in the window and its policy gradient");
-  if (!obs || !values || !critic_w || !critic_b || rows < 1) return fail(SIM_E_ARG, "sim_critic_values: null pointer or no rows");
-  for (int l = 0; l < h->opt.critic_layers; ++l)
-    if (!critic_w[l] || !critic_b[l]) return fail(SIM_E_ARG, "sim_critic_values: null critic weights");
-  if ((obs_mean != nullptr) != (obs_inv_std != nullptr))
-    return fail(SIM_E_ARG, "sim_critic_values: observation normalisation needs both obs_mean and obs_inv_std");
-  if (!workspace || workspace_bytes < sim_critic_workspace_bytes(h, rows))
-    return fail(SIM_E_WORKSPACE, "sim_critic_values: workspace smaller than sim_critic_workspace_bytes()");
-  return (h->opt.precision == SIM_PREC_FP64)
-             ? critic_values_impl<double>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, workspace,
-                                          hip_stream)
-             : critic_values_impl<float>(h, obs, rows, critic_w, critic_b, obs_mean, obs_inv_std, values, workspace,
-                                         hip_stream);
+    return fail(SIM_E_UNSUPPORTED, "sim_critic_values: a handle with layer normalisation takes sim_critic_values_ln");
+  return critic_values_checked(h, "sim_critic_values", obs, rows, critic_w, critic_b, nullptr, nullptr, obs_mean,
+                               obs_inv_std, values, workspace, workspace_bytes, hip_stream);
+}
+
+extern "C" int sim_critic_values_ln(SimHandle* h, const void* obs, int rows, const void* const* critic_w,
+                                    const void* const* critic_b, const void* const* critic_ln_g,
+                                    const void* const* critic_ln_b, const void* obs_mean, const void* obs_inv_std,
+                                    void* values, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  return critic_values_checked(h, "sim_critic_values_ln", obs, rows, critic_w, critic_b, critic_ln_g, critic_ln_b,
+                               obs_mean, obs_inv_std, values, workspace, workspace_bytes, hip_stream);
 }
 
 // the critic's hidden-layer activations [rows][dims[l]] (l = 1 .. L-1), one after the other
@@ -1745,7 +1796,7 @@ extern "C" int sim_critic_values_noalloc(SimHandle* h, const void* obs, int rows
   int rc = check_handle(h);
   if (rc) return rc;
   if (h->opt.layer_norm)
-    return fail(SIM_E_UNSUPPORTED, "sim_critic_values_noalloc: layer normalisation is implemented in the window and its policy gradient");
+    return fail(SIM_E_UNSUPPORTED, "sim_critic_values_noalloc: a handle with layer normalisation takes sim_critic_values_ln (with a workspace)");
   if (!obs || !values || !critic_w || !critic_b || rows < 1)
     return fail(SIM_E_ARG, "sim_critic_values_noalloc: null pointer or no rows");
   for (int l = 0; l < h->opt.critic_layers; ++l)
@@ -1776,7 +1827,7 @@ static int critic_fit_impl(SimHandle* h, const SimCriticFitIO* io, void* stream)
   char* ws = static_cast<char*>(io->workspace);
   CriticFitT<T> F;
   std::memset(&F, 0, sizeof(F));
-  critic_theta_args<T>(h, w, ws, io->critic_w, io->critic_b, io->rows, F.G);
+  critic_theta_args<T>(h, w, ws, io->critic_w, io->critic_b, io->critic_ln_g, io->critic_ln_b, io->rows, F.G);
   F.obs = static_cast<const T*>(io->obs);
   F.obs_mean = static_cast<const T*>(io->obs_mean);
   F.obs_inv_std = static_cast<const T*>(io->obs_inv_std);
@@ -1789,6 +1840,10 @@ static int critic_fit_impl(SimHandle* h, const SimCriticFitIO* io, void* stream)
   for (int l = 0; l < h->opt.critic_layers; ++l) {
     F.W[l] = static_cast<T*>(io->critic_w[l]);
     F.bvec[l] = static_cast<T*>(io->critic_b[l]);
+    if (F.G.ln && l + 1 < h->opt.critic_layers) {
+      F.lng[l] = static_cast<T*>(io->critic_ln_g[l]);
+      F.lnb[l] = static_cast<T*>(io->critic_ln_b[l]);
+    }
   }
   F.m = static_cast<T*>(io->adam_m);
   F.v = static_cast<T*>(io->adam_v);
@@ -1803,10 +1858,12 @@ static int critic_fit_impl(SimHandle* h, const SimCriticFitIO* io, void* stream)
 extern "C" int sim_critic_fit(SimHandle* h, const SimCriticFitIO* io, void* hip_stream) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->opt.layer_norm)
-    return fail(SIM_E_UNSUPPORTED, "sim_critic_fit: layer normalisation is implemented in the window and its policy gradient");
   if (!io || !io->obs || !io->targets || !io->perm || !io->adam_m || !io->adam_v)
     return fail(SIM_E_ARG, "sim_critic_fit: null pointer");
+  if (h->opt.layer_norm)
+    for (int l = 0; l + 1 < h->opt.critic_layers; ++l)
+      if (!io->critic_ln_g[l] || !io->critic_ln_b[l])
+        return fail(SIM_E_ARG, "sim_critic_fit: null layer-normalisation gain or bias");
   if (io->rows < 1 || io->n_iter < 1 || io->n_minibatch < 1 || io->n_minibatch > io->rows)
     return fail(SIM_E_ARG, "sim_critic_fit: need rows >= 1, n_iter >= 1, 1 <= n_minibatch <= rows");
   for (int l = 0; l < h->opt.critic_layers; ++l)

@@ -221,6 +221,39 @@ __global__ void k_ln_apply(const real* __restrict__ E, long lde, const real* __r
   Y[idx] = m_fma(g[c], (E[r * lde + c] - mu) * is, b[c]);
 }
 
+// Layer normalisation of hidden layer j row by row, computing its statistics (the critic's
+// passes, which have no window activations): one wavefront per row; lane c sums columns c,
+// c + 64, ... and a butterfly over the wavefront gives the row's mean and population
+// variance; st[r ldst + 2 j] / [.. + 1] receive the mean and 1 / sqrt(var + eps), and
+// Y [M][n] = g (E - mean) / sqrt(var + eps) + b as k_ln_apply forms it.
+__global__ __launch_bounds__(256) void k_ln_forward(const real* __restrict__ E, long lde, real* __restrict__ st,
+                                                    long ldst, int j, const real* __restrict__ g,
+                                                    const real* __restrict__ b, real* __restrict__ Y, long M, int n,
+                                                    real eps) {
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const long r = (long)blockIdx.x * 4 + wave;
+  if (r >= M) return;   // uniform over the wavefront
+  const real* e = E + r * lde;
+  real sm = RL(0.0);
+  for (int c = lane; c < n; c += SIM_WAVE) sm += e[c];
+#pragma unroll
+  for (int o = SIM_WAVE / 2; o > 0; o >>= 1) sm += __shfl_xor(sm, o);
+  const real mu = sm / (real)n;
+  real sv2 = RL(0.0);
+  for (int c = lane; c < n; c += SIM_WAVE) {
+    const real d = e[c] - mu;
+    sv2 = m_fma(d, d, sv2);
+  }
+#pragma unroll
+  for (int o = SIM_WAVE / 2; o > 0; o >>= 1) sv2 += __shfl_xor(sv2, o);
+  const real is = RL(1.0) / m_sqrt(sv2 / (real)n + eps);
+  for (int c = lane; c < n; c += SIM_WAVE) Y[r * n + c] = m_fma(g[c], (e[c] - mu) * is, b[c]);
+  if (lane == 0) {
+    st[r * ldst + 2 * j] = mu;
+    st[r * ldst + 2 * j + 1] = is;
+  }
+}
+
 // Adjoint through the normalisation and the ELU of hidden layer j, row by row: dY [M][n] (the
 // adjoint of the normalised outputs) -> D [M][n] (the adjoint of the pre-activations), with
 // a = (e - mean) r and u = g dY, ebar = r (u - mean(u) - a mean(u a)), D = ebar ELU'(z).  One
@@ -302,7 +335,7 @@ static void theta_hidden(const ThetaArgsT<real>& T, hipStream_t s) {
   for (int l = 0; l + 1 < L; ++l) {
     const int ni = T.dims[l], no = T.dims[l + 1];
     GemmArgs g = {};
-    g.A = (l == 0) ? T.x0 : T.H[l];
+    g.A = (l == 0) ? T.x0 : (T.ln ? T.Y[l] : T.H[l]);
     g.sam = ni; g.sak = 1;
     g.B = T.W[l]; g.sbk = 1; g.sbn = ni;
     g.M = M; g.N = no; g.K = ni;
@@ -311,6 +344,9 @@ static void theta_hidden(const ThetaArgsT<real>& T, hipStream_t s) {
     g.epi = EPI_BIAS_ELU; g.bias = T.b[l];
     if (l == 0) { g.a_shift = T.x_shift; g.a_scale = T.x_scale; }
     launch_gemm(g, 1, s);
+    if (T.ln)
+      hipLaunchKernelGGL(k_ln_forward, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, T.H[l + 1], (long)no, T.st,
+                         T.ldst, l, T.lng[l], T.lnb[l], T.Y[l + 1], (long)M, no, T.ln_eps);
   }
 }
 
@@ -318,7 +354,7 @@ static void theta_hidden(const ThetaArgsT<real>& T, hipStream_t s) {
 static void theta_output(const ThetaArgsT<real>& T, real* out, hipStream_t s) {
   const int L = T.nl, ni = T.dims[L - 1], no = T.dims[L];
   GemmArgs g = {};
-  g.A = (L == 1) ? T.x0 : T.H[L - 1];
+  g.A = (L == 1) ? T.x0 : (T.ln ? T.Y[L - 1] : T.H[L - 1]);
   g.sam = ni; g.sak = 1;
   g.B = T.W[L - 1]; g.sbk = 1; g.sbn = ni;
   g.M = T.M; g.N = no; g.K = ni;

@@ -221,14 +221,21 @@ int launch_critic_fit(const CriticFitT<real>& F, void* stream) {
       ++step;
       const real bc1 = RL(1.0) - (real)pow((double)F.b1, (double)step);
       const real bc2 = RL(1.0) - (real)pow((double)F.b2, (double)step);
-      // one Adam launch over all layers (the flat gradient holds W_0, b_0, W_1, ... in order)
+      // one Adam launch over all layers (the flat gradient holds W_0, b_0, W_1, ... in order;
+      // with layer normalisation a hidden layer's gain and bias follow its W, b)
       LearnAdamT<real> A = {};
-      A.n = 2 * T.nl;
+      A.n = 0;
       for (int l = 0; l < T.nl; ++l) {
-        A.p[2 * l] = F.W[l];
-        A.size[2 * l] = (long)T.dims[l] * T.dims[l + 1];
-        A.p[2 * l + 1] = F.bvec[l];
-        A.size[2 * l + 1] = T.dims[l + 1];
+        A.p[A.n] = F.W[l];
+        A.size[A.n++] = (long)T.dims[l] * T.dims[l + 1];
+        A.p[A.n] = F.bvec[l];
+        A.size[A.n++] = T.dims[l + 1];
+        if (T.ln && l + 1 < T.nl) {
+          A.p[A.n] = F.lng[l];
+          A.size[A.n++] = T.dims[l + 1];
+          A.p[A.n] = F.lnb[l];
+          A.size[A.n++] = T.dims[l + 1];
+        }
       }
       A.g = T.out; A.m = F.m; A.v = F.v;
       A.lr = F.lr; A.b1 = F.b1; A.b2 = F.b2; A.eps = F.eps; A.bc1 = bc1; A.bc2 = bc2;

@@ -248,14 +248,16 @@ struct ThetaArgsT {
   T* part;                    // [splits][max out*(in+1)] partial weight gradients
   T* out;                     // flat dL/dtheta: W_0, b_0, W_1, b_1, ...
   long off_w[SIM_MAXL], off_b[SIM_MAXL];
-  // layer normalisation of the hidden layers (window's activations only): H[l] then holds the
-  // ELU outputs, st + r * ldst the per-row mean and inverse deviation of each hidden layer, Y[l]
-  // ([M][dims[l]], scratch) the normalised layer inputs, lnpart ([ln_blocks][2][max width])
-  // the per-block partial sums of the gain and bias gradients (flat at off_g / off_beta)
+  // layer normalisation of the hidden layers: H[l] then holds the ELU outputs, st + r * ldst
+  // the per-row mean and inverse deviation of each hidden layer (the window's, or computed by
+  // the hidden-layer pass with ln_eps), Y[l] ([M][dims[l]], scratch) the normalised layer
+  // inputs, lnpart ([ln_blocks][2][max width]) the per-block partial sums of the gain and bias
+  // gradients (flat at off_g / off_beta)
   int ln;
+  T ln_eps;
   const T* lng[SIM_MAXL];
   const T* lnb[SIM_MAXL];
-  const T* st;
+  T* st;
   long ldst;
   T* Y[SIM_MAXL];
   T* lnpart;
@@ -292,6 +294,8 @@ struct CriticFitT {
   T* vbuf;              // [rows] critic outputs
   T* W[SIM_MAXL];       // critic weights, updated in place
   T* bvec[SIM_MAXL];
+  T* lng[SIM_MAXL];     // with layer normalisation: the hidden layers' gains and biases, updated
+  T* lnb[SIM_MAXL];     // in place (G.lng / G.lnb view the same arrays)
   T* m;                 // flat Adam moments
   T* v;
   int adam_step;        // Adam steps taken before the call

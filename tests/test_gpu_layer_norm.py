@@ -1,14 +1,16 @@
 """Layer normalisation of the hidden layers of the actor and the critic (App. A.2: ELU hidden
 layers, each followed by a layer normalisation with a gain and a bias), switched on with
 SimOptions.layer_norm: the in-kernel MLPs of the window, their input adjoints, the
-policy-parameter gradient (which then includes the gains and biases) and the critic values,
-against the oracle's layer-normalised MLP (oracle.window.mlp_forward with ln)."""
+policy-parameter gradient (which then includes the gains and biases), and the critic values
+and critic fit of the learning episode, against the oracle's layer-normalised MLP
+(oracle.window.mlp_forward with ln) and its critic fit (oracle.learn.critic_fit with ln)."""
 import numpy as np
 import pytest
 import torch
 
 import paper_2204_07137_amd as P
 import workloads as wl
+from oracle import learn as OL
 from oracle import oracle_window_grads
 
 pytestmark = pytest.mark.gpu
@@ -95,10 +97,9 @@ def test_layer_norm_changes_the_window_and_fp32_meets_the_bar():
     assert relnorm(fp["actions"].double().cpu().numpy(), f["actions"]) > 1e-2
 
 
-def test_layer_norm_paths_bitwise_and_critic_values():
+def test_layer_norm_paths_bitwise():
     """The tape path, the factor cache and the plain path run the same normalised arithmetic
-    as the checkpointed path (bitwise); the critic calls of the learning episode refuse a
-    normalised handle."""
+    as the checkpointed path (bitwise)."""
     W, ad, cd, a_ln, c_ln = _case("ant", 64)
     h = 3
     print("[layer norm] ant fp32 paths", flush=True)
@@ -109,7 +110,62 @@ def test_layer_norm_paths_bitwise_and_critic_values():
             assert np.array_equal(f0[key], f1[key]), (kw, key)
         for key in a0:
             assert np.array_equal(a0[key], a1[key]), (kw, key)
-    # the critic calls of the learning episode do not take the normalised networks
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_layer_norm_critic_values_and_fit_match_oracle(precision):
+    """The learning episode's critic calls with normalised hidden layers: the critic's values
+    (sim_critic_values_ln) and 4 passes x 4 minibatches of the critic fit, whose Adam moments
+    and updates include the gains and biases (library order W, b, g, beta per hidden layer),
+    against the oracle's fit of the same normalised critic; the un-normalised entry points
+    refuse the handle."""
+    W, ad, cd, a_ln, c_ln = _case("ant", 32)
+    sim = P.Sim(W["model"], 32, 4, ad, cd, precision=precision, layer_norm=True, ckpt_interval=4)
+    rng = np.random.default_rng(5)
+    rows = 96
+    obs = rng.normal(size=(rows, W["obs_dim"]))
+    print(f"[layer norm] critic values and fit, {precision}", flush=True)
+    vals = sim.critic_values(obs, W["critic"], critic_ln=c_ln)
+    torch.cuda.synchronize()
+    ref = OL.critic_values(W["critic"], obs, ln=c_ln).numpy()
+    assert relnorm(vals.double().cpu().numpy(), ref) < (1e-12 if precision == "fp64" else 1e-5)
+    tgt = rng.normal(size=rows)
+    perm = np.stack([rng.permutation(rows) for _ in range(4)]).astype(np.int32)
+    crit = [(sim._dev(Wl), sim._dev(bl)) for Wl, bl in W["critic"]]
+    cln = [(sim._dev(g), sim._dev(b)) for g, b in c_ln]
+    flat0 = []
+    for i, (Wl, bl) in enumerate(W["critic"]):
+        flat0 += [Wl.ravel(), bl.ravel()]
+        if i < len(W["critic"]) - 1:
+            flat0 += [c_ln[i][0].ravel(), c_ln[i][1].ravel()]
+    n = sum(x.size for x in flat0)
+    m = torch.zeros(n, dtype=sim.dtype, device="cuda")
+    v = torch.zeros(n, dtype=sim.dtype, device="cuda")
+    losses = sim.critic_fit(obs, tgt, torch.as_tensor(perm), 4, crit, m, v, 0, 5e-3, critic_ln=cln)
+    torch.cuda.synchronize()
+    zeros = []
+    for i, (Wl, bl) in enumerate(W["critic"]):
+        zeros += [np.zeros_like(Wl), np.zeros_like(bl)]
+        if i < len(W["critic"]) - 1:
+            zeros += [np.zeros_like(c_ln[i][0]), np.zeros_like(c_ln[i][1])]
+    rl, rln, rm, _, rlosses = OL.critic_fit(W["critic"], obs, tgt, perm, 4, zeros, zeros, 0, 5e-3, 0.7, 0.95, 1e-8,
+                                            ln=c_ln)
+    got, want = [], []
+    for i, ((Wg, bg), (Wr, br)) in enumerate(zip(crit, rl)):
+        got += [Wg, bg]
+        want += [Wr, br]
+        if i < len(rl) - 1:
+            got += list(cln[i])
+            want += list(rln[i])
+    got = np.concatenate([x.double().cpu().numpy().ravel() for x in got])
+    want = np.concatenate([x.numpy().ravel() for x in want])
+    init = np.concatenate(flat0)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert relnorm(losses.double().cpu().numpy(), rlosses) < tol
+    assert relnorm(got - init, want - init) < (1e-8 if precision == "fp64" else 1e-3)
+    assert relnorm(m.double().cpu().numpy(), np.concatenate([x.numpy().ravel() for x in rm])) < (
+        1e-8 if precision == "fp64" else 1e-3)
+    # the entry points without the gains and biases refuse a normalised handle
     with pytest.raises(P.SimError) as e:
-        sim.critic_values(torch.zeros(4, W["obs_dim"], device="cuda"), W["critic"])
-    assert "layer normalisation" in str(e.value)
+        sim.critic_values(obs, W["critic"])
+    assert "sim_critic_values_ln" in str(e.value)

@@ -102,6 +102,46 @@ def test_critic_fit_gradient_direction_and_descent():
     assert np.mean(losses[-2:]) < 0.75 * np.mean(losses[:2])
 
 
+def test_critic_fit_with_layer_norm_follows_the_loss_gradient():
+    """The critic fit with layer normalisation (App. A.2) on every hidden layer: with zero
+    moments and an Adam epsilon far above every gradient, the first step moves each
+    parameter by -lr g / (|g| + eps), so (lr = eps) the step is -g to a relative 1e-6; every
+    weight, bias, gain and normalisation bias (in the library's order W, b, g, beta per hidden
+    layer) is held to central differences of the minibatch loss."""
+    rng = np.random.default_rng(17)
+    od, rows = 5, 16
+    layers = [(rng.normal(0, 0.4, (6, od)), rng.normal(0, 0.1, 6)),
+              (rng.normal(0, 0.4, (4, 6)), rng.normal(0, 0.1, 4)),
+              (rng.normal(0, 0.4, (1, 4)), rng.normal(0, 0.1, 1))]
+    ln = [(rng.uniform(0.5, 1.5, 6), rng.normal(0, 0.2, 6)), (rng.uniform(0.5, 1.5, 4), rng.normal(0, 0.2, 4))]
+    obs = rng.normal(size=(rows, od))
+    tgt = rng.normal(size=rows)
+    flat = [W for W in (layers[0][0], layers[0][1], ln[0][0], ln[0][1], layers[1][0], layers[1][1], ln[1][0],
+                        ln[1][1], layers[2][0], layers[2][1])]
+    zeros = [np.zeros_like(x) for x in flat]
+    big = 1e6
+    new_layers, new_ln, _, _, losses = critic_fit(layers, obs, tgt, [np.arange(rows)], 1, zeros, zeros, 0, big,
+                                                  0.7, 0.95, big, ln=ln)
+    new_flat = [new_layers[0][0], new_layers[0][1], new_ln[0][0], new_ln[0][1], new_layers[1][0],
+                new_layers[1][1], new_ln[1][0], new_ln[1][1], new_layers[2][0], new_layers[2][1]]
+
+    def loss(fl):
+        Ls = [(fl[0], fl[1]), (fl[4], fl[5]), (fl[8], fl[9])]
+        lnp = [(fl[2], fl[3]), (fl[6], fl[7])]
+        return float(((critic_values(Ls, obs, ln=lnp) - torch.as_tensor(tgt)) ** 2).mean())
+    assert abs(losses[0] - loss(flat)) < 1e-14
+    e = 1e-6
+    for t, x in enumerate(flat):
+        for idx in [(0,) * x.ndim, tuple(s - 1 for s in x.shape)]:
+            fp = [y.copy() for y in flat]
+            fm = [y.copy() for y in flat]
+            fp[t][idx] += e
+            fm[t][idx] -= e
+            fd = (loss(fp) - loss(fm)) / (2 * e)
+            g = -(float(new_flat[t][idx]) - x[idx])
+            assert abs(g - fd) <= 1e-6 * max(abs(fd), 1e-3), (t, idx, g, fd)
+
+
 def test_obs_stats_streaming_equals_batch_moments():
     """Running observation statistics (Sec. 3.3) merged over uneven chunks equal the mean and
     population variance of all rows at once (numpy), and inv_std follows from them."""
