@@ -723,7 +723,8 @@ PHASES = ["frame_begin", "fk", "velocities", "contacts", "muscles", "newton_eule
           "checkpoint", "adj_seed", "adj_integrator", "adj_lambda", "adj_path_sums", "adj_contacts",
           "adj_muscles", "adj_body_terms", "adj_subtree_sums", "adj_derivatives", "adj_state", "tape_load",
           "tape_prefetch", "adj_frame", "window_end", "termination", "fc_states", "muscle_paths",
-          "muscle_accumulate", "adj_muscle_paths", "adj_muscle_derivatives", "adj_muscle_accumulate"]
+          "muscle_accumulate", "adj_muscle_paths", "adj_muscle_derivatives", "adj_muscle_accumulate",
+          "frame_obs", "frame_actor", "adj_frame_actor"]
 
 
 def phase_profile(reset=True):

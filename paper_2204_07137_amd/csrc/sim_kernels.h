@@ -91,9 +91,11 @@ __device__ __forceinline__ void frame_begin(const WinArgs& A, const Scal* __rest
   task_obs<L::kLanes>(m, E.q, E.qd, E.a, E.act, E.obs, ln);
   real* ob = A.obs + ((size_t)t * N + env) * od;
   for (int i = ln; i < od; i += L::kLanes) ob[i] = E.obs[i];
+  SIM_PHASE(E, PH_FB_OBS);
   if (A.closed_loop) {
     obs_normalize<L::kLanes>(A, m, E.obs, ln);
     mlp_forward<L::kLanes>(A.actor, E.obs, E.h0, E.h1, E.y, E.xb16, ln, E.gb, E.lnst);
+    SIM_PHASE(E, PH_FB_MLP);
     // keep the hidden activations for the adjoint's input VJP (at most two hidden layers; with
     // layer normalisation the ELU outputs and then each hidden layer's mean and inverse
     // deviation)
@@ -297,6 +299,7 @@ __device__ __forceinline__ void adjoint_frame(const WinArgs& A, const Scal* __re
     for (int i = ln; i < na; i += L::kLanes) E.y[i] = E.abar[i] * squash_grad(m, E.a[i]);
     __syncthreads();
     mlp_vjp_input<L::kLanes>(A.actor, E.h0, E.h1, E.y, E.gb, E.obs, E.xb16, ln, E.lnst);
+    SIM_PHASE(E, PH_AF_MLP);
     for (int i = ln; i < L::kMaxA; i += L::kLanes) E.abar[i] = RL(0.0);
     __syncthreads();
     obs_adjoint_scale<L::kLanes>(A, m, E.obs, ln);

@@ -130,8 +130,12 @@ enum {
   PH_FM_ACC = 33,      // forward muscles: point forces into the per-body wrench table
   PH_AM_PATH = 34,     // muscle adjoint: path geometry and tensions recomputed
   PH_AM_DERIV = 35,    // muscle adjoint: virtual velocities, tension and direction derivatives
-  PH_AM_ACC = 36       // muscle adjoint: per-body terms into the three tables
+  PH_AM_ACC = 36,      // muscle adjoint: per-body terms into the three tables
+  PH_FB_OBS = 37,      // frame start: observation and its store
+  PH_FB_MLP = 38,      // frame start: the actor MLP and the hidden activations' store
+  PH_AF_MLP = 39       // frame-level reverse: the actor's input VJP with its operand loads
 };
+static_assert(PH_AF_MLP < SIM_NPHASE, "phase ids within the profile table");
 #ifdef SIM_PHASE_PROFILE
 template <int LN>
 __device__ __forceinline__ void phase_mark(unsigned long long* P, int id);

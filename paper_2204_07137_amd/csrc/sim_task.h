@@ -122,9 +122,13 @@ __device__ __forceinline__ void load_lane_block(const real* __restrict__ p, real
   }
 }
 
+// Weight rows are requested MLP_BATCH at a time, all before the first is used: the compiler
+// otherwise waits for each row's load before requesting the next (the kernels use every
+// register), paying one memory latency per row.  The FMA order is that of a row-by-row loop.
+#define MLP_BATCH 8
+
 // Each of the environment's LN lanes owns NCH consecutive outputs (rows padded to a multiple
-// of 64 = NCH * LN), so a weight row is one coalesced vector load per lane; 16 input rows are
-// kept in flight.
+// of 64 = NCH * LN), so a weight row is one coalesced vector load per lane.
 template <int NCH, int LN>
 __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const real* __restrict__ bb,
                                               const real* in, real* dst, int ni, int no, bool hidden, int ln) {
@@ -136,8 +140,20 @@ __device__ __forceinline__ void mlp_layer_fwd(const real* __restrict__ WT, const
     acc[c] = (o < no) ? bb[o] : RL(0.0);
   }
   const real* base = WT + ln * NCH;
-#pragma unroll 16
-  for (int i = 0; i < ni; ++i) {
+  int i = 0;
+  for (; i + MLP_BATCH <= ni; i += MLP_BATCH) {
+    real w[MLP_BATCH][NCH];
+#pragma unroll
+    for (int u = 0; u < MLP_BATCH; ++u) load_lane_block<NCH>(base + (size_t)(i + u) * nop, w[u]);
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < MLP_BATCH; ++u) {
+      const real xi = in[i + u];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) acc[c] = m_fma(w[u][c], xi, acc[c]);
+    }
+  }
+  for (; i < ni; ++i) {
     const real xi = in[i];
     real w[NCH];
     load_lane_block<NCH>(base + (size_t)i * nop, w);
@@ -163,8 +179,20 @@ __device__ __forceinline__ void mlp_layer_vjp(const real* __restrict__ W, const 
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc[c] = RL(0.0);
   const real* base = W + ln * NCH;
-#pragma unroll 16
-  for (int o = 0; o < no; ++o) {
+  int o = 0;
+  for (; o + MLP_BATCH <= no; o += MLP_BATCH) {
+    real w[MLP_BATCH][NCH];
+#pragma unroll
+    for (int u = 0; u < MLP_BATCH; ++u) load_lane_block<NCH>(base + (size_t)(o + u) * nip, w[u]);
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < MLP_BATCH; ++u) {
+      const real go = g[o + u];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) acc[c] = m_fma(w[u][c], go, acc[c]);
+    }
+  }
+  for (; o < no; ++o) {
     const real go = g[o];
     real w[NCH];
     load_lane_block<NCH>(base + (size_t)o * nip, w);
