@@ -48,7 +48,29 @@ __device__ __forceinline__ void mlp_tiles_bf16(const uint16_t* __restrict__ P, c
     f32x4 acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kt = 0; kt < nkt; ++kt) {
+    // the weight tiles of two k-steps (up to eight) are requested before the first product,
+    // so the loop waits for one memory latency per two k-steps, not per tile; the products
+    // accumulate in k order as before
+    int kt = 0;
+    for (; kt + 2 <= nkt; kt += 2) {
+      bf16x8 b[2][4];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          b[q][u] = (t0 + u < nrt) ? *reinterpret_cast<const bf16x8*>(P + ((size_t)((t0 + u) * nkt + kt + q) * SIM_WAVE + ln) * 8)
+                                   : bf16x8{};
+      __asm__ volatile("" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        bf16x8 a = *reinterpret_cast<const bf16x8*>(xb + (kt + q) * 32 + lk * 8);
+        if (ln & 15) a = bf16x8{};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (t0 + u < nrt) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][u], acc[u], 0, 0, 0);
+      }
+    }
+    for (; kt < nkt; ++kt) {
       bf16x8 a = *reinterpret_cast<const bf16x8*>(xb + kt * 32 + lk * 8);
       if (ln & 15) a = bf16x8{};
 #pragma unroll
